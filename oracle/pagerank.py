@@ -1,0 +1,118 @@
+"""PageRank oracle (float64, CPU, plain numpy).
+
+TEST INFRASTRUCTURE ONLY: imported by tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the product path.
+
+The paper evaluates pull-based PageRank with floating-point scores and stops
+when the total absolute score change between the last two iterations falls
+below a threshold (section IV, evaluation setup).  It gives no formula, so the
+oracle uses the standard damped form (reading R1 of the design notes):
+
+    T(x)_v = (1 - alpha)/N + alpha * ( sum_{u -> v} x_u / outdeg(u) + D(x)/N )
+    D(x)   = sum_{u : outdeg(u) = 0} x_u          (dangling mass, spread evenly)
+
+Edges are counted with multiplicity and self-loops count in outdeg.  The
+linear part alpha*(A + (1/N) 1 delta^T) is alpha times a column-stochastic
+matrix, so T is an alpha-contraction in the L1 norm with a unique fixed point
+x* whose entries sum to 1.
+
+Every function takes the out-edge CSR graph produced by ``graphgen`` and
+expands it to an edge list itself.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+ALPHA = 0.85
+
+
+def edge_list(g):
+    """(src, dst) int64 arrays of every edge u -> v of the CSR graph."""
+    deg = np.diff(g.ptr.astype(np.int64))
+    src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    dst = g.idx.astype(np.int64)
+    return src, dst
+
+
+def out_degree(g):
+    return np.diff(g.ptr.astype(np.int64))
+
+
+def apply_T(x, src, dst, deg, alpha=ALPHA):
+    """One synchronous (Jacobi) sweep: every vertex pulls from its in-neighbours'
+    previous values (introduction: values computed in one iteration become
+    visible only at the start of the next)."""
+    n = x.shape[0]
+    x = np.asarray(x, dtype=np.float64)
+    contrib = np.zeros(n, dtype=np.float64)
+    nz = deg > 0
+    contrib[nz] = x[nz] / deg[nz]
+    pulled = np.bincount(dst, weights=contrib[src], minlength=n)
+    dangling = float(x[~nz].sum())
+    return (1.0 - alpha) / n + alpha * (pulled + dangling / n)
+
+
+def pagerank_jacobi(g, alpha=ALPHA, tol=1e-6, max_sweeps=10_000, x0=None, keep_iterates=False):
+    """Synchronous PageRank from x0 = 1/N until the L1 change of a sweep drops
+    below ``tol`` (strictly).  The confirming sweep is counted.
+
+    Returns (x, sweeps, residuals, iterates) where residuals[k] is the L1
+    change of sweep k+1 and iterates[k] the vector after sweep k+1 (only when
+    ``keep_iterates``).
+    """
+    n = g.n
+    src, dst = edge_list(g)
+    deg = out_degree(g)
+    x = np.full(n, 1.0 / n) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
+    residuals, iterates = [], []
+    sweeps = 0
+    while sweeps < max_sweeps:
+        xn = apply_T(x, src, dst, deg, alpha)
+        r = float(np.abs(xn - x).sum())
+        x = xn
+        sweeps += 1
+        residuals.append(r)
+        if keep_iterates:
+            iterates.append(x.copy())
+        if r < tol:
+            break
+    return x, sweeps, residuals, iterates
+
+
+def pagerank_fixed_point(g, alpha=ALPHA, tol=1e-12, max_sweeps=100_000):
+    """x* to within the float64 noise floor: Jacobi iteration until the L1
+    change is below ``tol`` (1e-12 by default), then one normalisation."""
+    x, _, _, _ = pagerank_jacobi(g, alpha, tol, max_sweeps)
+    return x / x.sum()
+
+
+def certificate(g, x, alpha=ALPHA):
+    """Upper bound on ||x - x*||_1 valid for any vector x:
+    ||x - x*|| <= ||T(x) - x|| / (1 - alpha), because T is an
+    alpha-contraction in L1."""
+    src, dst = edge_list(g)
+    deg = out_degree(g)
+    x = np.asarray(x, dtype=np.float64)
+    return float(np.abs(apply_T(x, src, dst, deg, alpha) - x).sum()) / (1.0 - alpha)
+
+
+def transition_matrix(g):
+    """Dense column-stochastic M with M[v, u] = (#edges u->v)/outdeg(u) and a
+    uniform column 1/N for every dangling u (tiny graphs only)."""
+    n = g.n
+    src, dst = edge_list(g)
+    deg = out_degree(g)
+    M = np.zeros((n, n), dtype=np.float64)
+    for u, v in zip(src.tolist(), dst.tolist()):
+        M[v, u] += 1.0 / deg[u]
+    for u in range(n):
+        if deg[u] == 0:
+            M[:, u] = 1.0 / n
+    return M
+
+
+def pagerank_dense(g, alpha=ALPHA):
+    """Fixed point by direct solve of (I - alpha M) x = (1 - alpha)/N 1."""
+    n = g.n
+    M = transition_matrix(g)
+    return np.linalg.solve(np.eye(n) - alpha * M, np.full(n, (1.0 - alpha) / n))

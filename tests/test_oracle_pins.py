@@ -1,0 +1,298 @@
+"""Pins of the CPU oracle against facts outside itself (no GPU).
+
+Each test compares the oracle with something it does not share code with:
+closed forms derived by hand from the fixed-point equation, an independent
+library (networkx, scipy), brute force on tiny inputs, or an invariant fixed by
+the mathematics (contraction, mass conservation, optimality certificates).
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+from oracle import pagerank as opr
+from oracle import schedule as osch
+from oracle import sssp as osp
+from tests import graphs as tg
+
+ALPHA = 0.85
+
+
+# ---------------------------------------------------------------- PageRank --
+
+@pytest.mark.parametrize("n", [1, 2, 7, 33])
+def test_pr_uniform_closed_forms(n):
+    """Directed cycle, complete digraph and the edgeless graph (all dangling)
+    have the uniform vector 1/N as fixed point."""
+    for g in (tg.cycle(n), tg.empty(n)) + ((tg.complete(n),) if n > 1 else ()):
+        x = opr.pagerank_fixed_point(g)
+        np.testing.assert_allclose(x, np.full(n, 1.0 / n), rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("n", [2, 5, 17, 200])
+def test_pr_in_star_closed_form(n):
+    """Leaves -> dangling hub.  Solving x_leaf = (1-a)/N + a x_hub/N,
+    x_hub = (1-a)/N + a((N-1) x_leaf + x_hub/N) with sum 1 gives
+    x_hub = (1 + (N-1)a) / (N + (N-1)a), x_leaf = (1 - x_hub)/(N-1)."""
+    g = tg.in_star(n)
+    x = opr.pagerank_fixed_point(g)
+    hub = (1 + (n - 1) * ALPHA) / (n + (n - 1) * ALPHA)
+    leaf = (1 - hub) / (n - 1)
+    assert abs(x[0] - hub) < 1e-11
+    np.testing.assert_allclose(x[1:], leaf, rtol=0, atol=1e-11)
+
+
+def test_pr_in_star_n5_values():
+    """Numerical values for N = 5 kept as a golden fixture."""
+    g = tg.in_star(5)
+    x = opr.pagerank_fixed_point(g)
+    vals = _golden("pagerank_closed_forms.txt")
+    assert abs(x[0] - vals["instar5_hub"]) < 5e-8
+    assert abs(x[1] - vals["instar5_leaf"]) < 5e-8
+
+
+@pytest.mark.parametrize("n", [2, 5, 64])
+def test_pr_out_star_closed_form(n):
+    """Hub -> dangling leaves.  The hub has no in-edges, so
+    x_hub = (1-a)/N + a D/N with D = 1 - x_hub, i.e. x_hub = 1/(N + a).
+    This pins the direction of the pull (in-edges, not out-edges)."""
+    g = tg.out_star(n)
+    x = opr.pagerank_fixed_point(g)
+    hub = 1.0 / (n + ALPHA)
+    assert abs(x[0] - hub) < 1e-11
+    np.testing.assert_allclose(x[1:], (1 - hub) / (n - 1), rtol=0, atol=1e-11)
+
+
+def test_pr_two_vertex_closed_form():
+    """0 -> 1 with 1 dangling: x0 = 1/(2 + a), x1 = (1 + a)/(2 + a)."""
+    g = gg.from_edges(2, [0], [1])
+    x = opr.pagerank_fixed_point(g)
+    assert abs(x[0] - 1 / (2 + ALPHA)) < 1e-11
+    assert abs(x[1] - (1 + ALPHA) / (2 + ALPHA)) < 1e-11
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_pr_dense_solve(seed):
+    """Jacobi fixed point equals the direct linear solve on tiny random
+    graphs, including self-loops, dangling-heavy and multigraph inputs."""
+    n = 5 + 9 * seed
+    graphs = [tg.random_graph(n, 3 * n, seed), tg.dangling_heavy(n, seed),
+              tg.random_graph(n, 4 * n, seed + 100, dedup=False)]
+    for g in graphs:
+        x = opr.pagerank_fixed_point(g)
+        xd = opr.pagerank_dense(g)
+        assert np.abs(x - xd).sum() < 1e-11
+        assert abs(xd.sum() - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_pr_networkx(seed):
+    """Independent implementation: networkx.pagerank (uniform teleport and
+    uniform redistribution of dangling mass by default)."""
+    nx = pytest.importorskip("networkx")
+    g = tg.random_graph(600, 2400, seed) if seed == 0 else tg.dangling_heavy(900, seed)
+    G = nx.DiGraph()
+    G.add_nodes_from(range(g.n))
+    src, dst = opr.edge_list(g)
+    G.add_edges_from(zip(src.tolist(), dst.tolist()))
+    ref = nx.pagerank(G, alpha=ALPHA, tol=1e-15, max_iter=100000)
+    ref = np.array([ref[i] for i in range(g.n)])
+    x = opr.pagerank_fixed_point(g)
+    assert np.abs(x - ref).sum() < 1e-11
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_pr_mass_and_contraction(seed):
+    """Every Jacobi iterate keeps total mass 1; T is an alpha-contraction in
+    L1; the change per sweep shrinks by at least alpha."""
+    g = tg.dangling_heavy(120, seed)
+    x, sweeps, res, its = opr.pagerank_jacobi(g, tol=1e-12, keep_iterates=True)
+    for it in its:
+        assert abs(it.sum() - 1.0) < 1e-13
+    for a, b in zip(res, res[1:]):
+        assert b <= ALPHA * a * (1 + 1e-9) + 1e-16
+    rng = np.random.default_rng(seed)
+    src, dst = opr.edge_list(g)
+    deg = opr.out_degree(g)
+    for _ in range(5):
+        u, v = rng.random(g.n), rng.random(g.n)
+        lhs = np.abs(opr.apply_T(u, src, dst, deg) - opr.apply_T(v, src, dst, deg)).sum()
+        assert lhs <= ALPHA * np.abs(u - v).sum() * (1 + 1e-12)
+
+
+def test_pr_certificate_bounds_error():
+    """||T(x) - x||/(1 - a) bounds ||x - x*|| for arbitrary perturbations."""
+    g = tg.random_graph(300, 1500, 7)
+    xs = opr.pagerank_dense(g)
+    rng = np.random.default_rng(3)
+    assert opr.certificate(g, xs) < 1e-13
+    for scale in (1e-3, 1e-6, 1e-9):
+        x = xs + scale * rng.standard_normal(g.n) / g.n
+        err = np.abs(x - xs).sum()
+        cert = opr.certificate(g, x)
+        assert err <= cert * (1 + 1e-9) + 1e-15
+        assert cert <= err * (1 + ALPHA) / (1 - ALPHA) * (1 + 1e-9) + 1e-15
+
+
+def test_pr_stopping_rule():
+    """Stops at the first sweep whose L1 change is strictly below tol, and the
+    returned count includes that sweep."""
+    g = tg.random_graph(200, 900, 4)
+    x, sweeps, res, _ = opr.pagerank_jacobi(g, tol=1e-6)
+    assert res[-1] < 1e-6 and all(r >= 1e-6 for r in res[:-1])
+    assert len(res) == sweeps
+
+
+# -------------------------------------------------------------------- SSSP --
+
+@pytest.mark.parametrize("seed", range(5))
+def test_sssp_bf_matches_dijkstra_scipy_fw(seed):
+    """Synchronous Bellman-Ford == heap Dijkstra == scipy Dijkstra ==
+    Floyd-Warshall row, with unreachable vertices."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import dijkstra as sp_dijkstra
+    n = 20 + 20 * seed
+    g = tg.random_graph(n, int(1.5 * n), seed)
+    src, dst, w = osp.edge_list(g)
+    mat = csr_matrix((w.astype(np.float64), (src, dst)), shape=(n, n))
+    fw = osp.floyd_warshall(g) if n <= 64 else None
+    for s in range(0, n, max(1, n // 5)):
+        bf, _, _ = osp.bellman_ford_sync(g, s)
+        dj = osp.dijkstra(g, s)
+        ref = sp_dijkstra(mat, directed=True, indices=s)
+        ref = np.where(np.isinf(ref), osp.INF32, ref).astype(np.uint32)
+        np.testing.assert_array_equal(bf, dj)
+        np.testing.assert_array_equal(bf, ref)
+        if fw is not None:
+            np.testing.assert_array_equal(bf, fw[s].astype(np.uint32))
+
+
+def test_sssp_certificate_accepts_and_rejects():
+    g = tg.random_graph(80, 300, 11)
+    d, _, _ = osp.bellman_ford_sync(g, 0)
+    ok, msg = osp.certificate(g, 0, d)
+    assert ok, msg
+    reach = np.flatnonzero((d != osp.INF32) & (np.arange(g.n) != 0))
+    unreach = np.flatnonzero(d == osp.INF32)
+    assert reach.size and unreach.size
+    for mutate in ("plus", "minus", "inf", "finite"):
+        e = d.astype(np.int64).copy()
+        if mutate == "plus":
+            e[reach[0]] += 1
+        elif mutate == "minus":
+            e[reach[-1]] -= 1
+        elif mutate == "inf":
+            e[reach[1]] = osp.INF32
+        else:
+            e[unreach[0]] = 5
+        ok, _ = osp.certificate(g, 0, e.astype(np.uint32))
+        assert not ok, mutate
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_sssp_sync_hop_invariant(seed):
+    """After k synchronous sweeps, d = shortest length over paths of at most k
+    edges (brute force), and the sweep count is 1 + max hop count h(v), h(v)
+    the fewest edges on a shortest path to v."""
+    g = tg.random_graph(30, 70, seed, weights=(1, 9))
+    d, sweeps, its = osp.bellman_ford_sync(g, 0, keep_iterates=True)
+    for k, it in enumerate(its, start=1):
+        np.testing.assert_array_equal(it, osp.bounded_hop_distances(g, 0, k))
+    h = np.zeros(g.n, dtype=np.int64)
+    for v in range(g.n):
+        if d[v] == osp.INF32:
+            continue
+        k = 0
+        while osp.bounded_hop_distances(g, 0, k)[v] != d[v]:
+            k += 1
+        h[v] = k
+    assert sweeps == 1 + h.max()
+
+
+@pytest.mark.parametrize("n", [1, 2, 10, 50])
+def test_sssp_path_graph(n):
+    """Path 0 -> ... -> n-1 with unit weights: distances 0..n-1; synchronous
+    Bellman-Ford needs exactly n sweeps (n-1 with changes plus the confirming
+    one); a single in-order asynchronous worker needs 2."""
+    g = gg.path_graph(n)
+    d, sweeps, _ = osp.bellman_ford_sync(g, 0)
+    np.testing.assert_array_equal(d, np.arange(n, dtype=np.uint32))
+    assert sweeps == n
+    da, sa, _ = osch.sssp(g, 0, mode=osch.ASYNC, P=1)
+    np.testing.assert_array_equal(da, d)
+    assert sa == (2 if n > 1 else 1)
+
+
+# --------------------------------------------------- emulated commit modes --
+
+@pytest.mark.parametrize("seed", range(3))
+def test_schedule_modes_same_fixed_point(seed):
+    """Every commit mode reaches the same answer (chaotic relaxation): SSSP
+    bit-exact, PageRank within 1e-9 of the dense solve."""
+    g = tg.random_graph(60, 240, seed)
+    xs = opr.pagerank_dense(g)
+    d0, _, _ = osp.bellman_ford_sync(g, 0)
+    for mode, delta, P in [(osch.SYNC, 0, 4), (osch.ASYNC, 0, 4), (osch.DELAYED, 4, 4),
+                           (osch.DELAYED, 1, 3), (osch.DELAYED, 1000, 5)]:
+        x, _, _ = osch.pagerank(g, mode, delta, P, tol=1e-12)
+        assert np.abs(x / x.sum() - xs).sum() < 1e-9
+        d, _, _ = osch.sssp(g, 0, mode, delta, P)
+        np.testing.assert_array_equal(d, d0)
+
+
+def test_schedule_sync_equals_jacobi():
+    """The emulated synchronous schedule is exactly the Jacobi oracle."""
+    g = tg.dangling_heavy(50, 2)
+    _, s1, r1 = osch.pagerank(g, osch.SYNC, 0, P=3, tol=1e-9)
+    _, s2, r2, _ = opr.pagerank_jacobi(g, tol=1e-9)
+    assert s1 == s2
+    np.testing.assert_allclose(r1, r2, rtol=1e-10, atol=1e-15)
+    d1, t1, snaps1 = osch.sssp(g, 0, osch.SYNC, 0, P=3)
+    d2, t2, its2 = osp.bellman_ford_sync(g, 0, keep_iterates=True)
+    assert t1 == t2
+    for a, b in zip(snaps1, its2):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_schedule_delta_whole_block_is_sync():
+    """Equal blocks, lock-step threads and delta = block size: nobody flushes
+    before the sweep ends, so delayed == synchronous sweep by sweep (the
+    paper's statement that delta equal to the per-thread output count gives
+    the synchronous algorithm)."""
+    g = tg.random_graph(48, 200, 5)
+    bounds = [0, 12, 24, 36, 48]
+    _, s1, snaps1 = osch.sssp(g, 0, osch.DELAYED, 12, bounds=bounds)
+    _, s2, its2 = osp.bellman_ford_sync(g, 0, keep_iterates=True)
+    assert s1 == s2
+    for a, b in zip(snaps1, its2):
+        np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_schedule_sssp_monotone(seed):
+    """P-9: in any commit mode, reads are never staler than the previous
+    sweep, so the distances after sweep k are <= the synchronous ones and the
+    asynchronous/delayed sweep count never exceeds the synchronous one."""
+    g = tg.random_graph(80, 260, seed + 20)
+    _, ss, its = osp.bellman_ford_sync(g, 0, keep_iterates=True)
+    for mode, delta, P in [(osch.ASYNC, 0, 4), (osch.DELAYED, 3, 4), (osch.DELAYED, 64, 2)]:
+        _, sm, snaps = osch.sssp(g, 0, mode, delta, P)
+        assert sm <= ss
+        for k, s in enumerate(snaps):
+            ref = its[min(k, len(its) - 1)]
+            assert (s.astype(np.int64) <= ref.astype(np.int64)).all()
+
+
+# ---------------------------------------------------------------- helpers --
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split()[:2]
+            vals[k] = float(v)
+    return vals
