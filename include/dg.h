@@ -1,0 +1,187 @@
+/*
+ * dg.h - C ABI of the delayed asynchronous graph sweep library (MI355X, gfx950).
+ *
+ * The library runs the per-iteration vertex-update sweep of two iterative
+ * graph algorithms from Blanco, McMillan and Low, "Delayed Asynchronous
+ * Iterative Graph Algorithms" (HPEC 2021):
+ *
+ *   - pull-style PageRank (section IV-A, dense updates: every vertex is
+ *     recomputed from its in-neighbours every sweep);
+ *   - pull-style Bellman-Ford single-source shortest paths with 32-bit
+ *     unsigned path lengths (section IV-D);
+ *
+ * each in three commit modes (section III and figure 1):
+ *
+ *   DG_SYNC     outputs go to a separate array that becomes the input of the
+ *               next sweep (Jacobi; one barrier per sweep, the kernel edge);
+ *   DG_ASYNC    every new value is written to the single global array as
+ *               soon as it is computed (delta = 0);
+ *   DG_DELAYED  new values are staged in a workgroup-local buffer (LDS) and
+ *               copied to the global array every d vertices of the worker's
+ *               block and when the block is done (the paper's hybrid, delta=d).
+ *
+ * Reads always come from the global array (the global-read variant of
+ * section III-C).  Work is split into contiguous vertex blocks, one per
+ * persistent workgroup ("worker"), balanced by in-edges (section III-A).
+ *
+ * Conventions for every function:
+ *   - every function returns a dg_status; nothing throws or aborts across the
+ *     ABI; on error dg_last_error() returns a message for the calling thread;
+ *   - argument validation happens on the host before any HIP call, and on a
+ *     validation error no output is touched;
+ *   - `hip_stream` is a hipStream_t (NULL = the legacy default stream); all
+ *     device work of a call is enqueued on it and the call returns after the
+ *     result is complete (the stream is synchronised);
+ *   - one graph handle may be used by one call at a time; distinct handles may
+ *     run concurrently on distinct streams.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DG_OK = 0,
+  DG_ERR_INVALID_ARGUMENT = 1, /* malformed input; nothing was changed        */
+  DG_ERR_OUT_OF_MEMORY = 2,    /* a device or host allocation failed         */
+  DG_ERR_DEVICE = 3,           /* a HIP call failed (no device, fault, ...)  */
+  DG_ERR_NOT_CONVERGED = 4,    /* max_sweeps reached; outputs and stats hold
+                                  the last iterate                            */
+  DG_ERR_UNSUPPORTED = 5       /* valid request this build cannot run        */
+} dg_status;
+
+/* Commit mode of a sweep (section III). */
+typedef enum { DG_SYNC = 0, DG_ASYNC = 1, DG_DELAYED = 2 } dg_mode;
+
+/* Layout of the adjacency handed to dg_graph_create.
+ * DG_CSR: ptr is indexed by source vertex, idx holds destinations (out-edges).
+ * DG_CSC: ptr is indexed by destination vertex, idx holds sources (in-edges). */
+typedef enum { DG_CSR = 0, DG_CSC = 1 } dg_layout;
+
+/* Storage precision of PageRank scores.  Sums over in-edges, the residual,
+ * the dangling mass and the final normalisation are float64 in both. */
+typedef enum { DG_F32 = 0, DG_F64 = 1 } dg_dtype;
+
+/* Commit interval meaning "the worker's whole block": flush only when the
+ * worker's block is done (or the staging buffer is full). */
+#define DG_D_WHOLE 0xFFFFFFFFu
+
+/* Distance of a vertex the source cannot reach. */
+#define DG_INF_DIST 0xFFFFFFFFu
+
+typedef struct dg_graph dg_graph;
+
+/* Per-call statistics. */
+typedef struct {
+  uint32_t sweeps;          /* sweeps run, including the confirming one     */
+  uint32_t workers;         /* persistent workgroups (contiguous blocks)    */
+  uint32_t tile_vertices;   /* vertices a worker computes concurrently      */
+  uint32_t commit_interval; /* effective d in vertices (0 = no staging)     */
+  double residual;          /* PageRank: L1 change of the last sweep        */
+  double seconds;           /* time to convergence: first sweep launch to
+                               the end of the sweep that met the stopping
+                               rule, measured with events on the stream     */
+  uint64_t edges_traversed; /* m * sweeps                                   */
+} dg_stats;
+
+/* Static facts about an uploaded graph. */
+typedef struct {
+  uint32_t n;          /* vertices                                         */
+  uint64_t m;          /* edges                                            */
+  uint32_t workers;    /* persistent workgroups used by the sweeps         */
+  uint32_t tiles;      /* tiles over all workers                           */
+  uint32_t max_in_degree;
+  uint32_t dangling;   /* vertices with out-degree 0                       */
+  uint32_t has_weights;
+  uint32_t compute_units;
+  uint64_t device_bytes; /* device memory held by the graph (not workspace) */
+} dg_graph_info;
+
+/* Device memory hooks.  alloc(bytes, stream, ctx) returns device memory or
+ * NULL; free(ptr, stream, ctx) releases it.  Passing NULL for both restores
+ * hipMalloc/hipFree.  The hooks apply to allocations made after the call; a
+ * graph frees its memory with the hooks that allocated it, so they must stay
+ * valid until every graph created under them is destroyed. */
+typedef void* (*dg_alloc_fn)(size_t bytes, void* hip_stream, void* ctx);
+typedef void (*dg_free_fn)(void* ptr, void* hip_stream, void* ctx);
+dg_status dg_set_allocator(dg_alloc_fn alloc, dg_free_fn free_fn, void* ctx);
+
+/* Upload a graph and build its in-edge form (pull sweeps need in-neighbours,
+ * section III-A).
+ *   n          vertices, 1 <= n <= 0xFFFFFFFE
+ *   m          edges, m < 2^32 - 4096
+ *   layout     DG_CSR or DG_CSC (see dg_layout)
+ *   ptr        host array of n+1 uint64 offsets: ptr[0] = 0, non-decreasing,
+ *              ptr[n] = m
+ *   idx        host array of m uint32 vertex ids, each < n
+ *   w          host array of m uint32 edge weights, or NULL (PageRank only).
+ *              Path lengths saturate at DG_INF_DIST.
+ * Duplicate edges are kept (PageRank counts multiplicity, SSSP takes the
+ * minimum) and self-loops count in the out-degree.  The arrays are copied:
+ * the caller keeps ownership and may free them when the call returns.  On
+ * success *out owns device memory until dg_graph_destroy.
+ * Errors: INVALID_ARGUMENT (malformed arrays, NULL pointers), OUT_OF_MEMORY,
+ * DEVICE. */
+dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr,
+                          const uint32_t* idx, const uint32_t* w, void* hip_stream,
+                          dg_graph** out);
+
+/* Release a graph and its workspace.  NULL is a no-op. */
+dg_status dg_graph_destroy(dg_graph* g);
+
+/* Fill *info with static facts about g. */
+dg_status dg_graph_info_get(const dg_graph* g, dg_graph_info* info);
+
+/* PageRank by repeated pull sweeps (sections III and IV-A).
+ *   damping     0 <= damping < 1 (0.85 in the paper's evaluation setup)
+ *   tol         stop after the first sweep whose L1 score change is < tol
+ *               (the paper's stopping rule with a threshold); tol >= 0, finite;
+ *               tol = 0 runs exactly max_sweeps sweeps
+ *   mode, d     commit mode; d >= 1 is the commit interval in vertices for
+ *               DG_DELAYED (DG_D_WHOLE = whole block) and ignored otherwise
+ *   dtype       score storage precision
+ *   max_sweeps  1 <= max_sweeps <= 1000000
+ *   out_scores  n float64 scores normalised to sum 1; device memory when
+ *               out_on_device != 0, else host memory
+ *   stats       may be NULL
+ * Scores start at 1/n; the mass of dangling vertices (out-degree 0) is spread
+ * evenly over all vertices, using the value measured in the previous sweep.
+ * Returns NOT_CONVERGED (with out_scores and stats filled) when max_sweeps
+ * sweeps ran without meeting the stopping rule. */
+dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uint32_t d,
+                      dg_dtype dtype, uint32_t max_sweeps, double* out_scores,
+                      int out_on_device, dg_stats* stats, void* hip_stream);
+
+/* Bellman-Ford single-source shortest paths by repeated pull relaxation
+ * sweeps (sections III and IV-D): d'(v) = min(d(v), min over in-edges
+ * (u,v) of d(u) + w(u,v)), stored every sweep, stopping after the first
+ * sweep in which no distance decreased.
+ *   src         source vertex, < n
+ *   mode, d     as for dg_pagerank
+ *   max_sweeps  1 <= max_sweeps <= 1000000
+ *   out_dist    n uint32 distances, DG_INF_DIST for unreachable vertices;
+ *               device memory when out_on_device != 0, else host memory
+ * Requires a graph created with weights.  Distances are exact whenever the
+ * longest shortest path is below 2^32 - 1. */
+dg_status dg_sssp(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t max_sweeps,
+                  uint32_t* out_dist, int out_on_device, dg_stats* stats, void* hip_stream);
+
+/* Static name of a status code. */
+const char* dg_status_str(dg_status s);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* dg_last_error(void);
+
+/* Library version string. */
+const char* dg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_H */

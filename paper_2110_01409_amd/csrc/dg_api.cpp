@@ -1,0 +1,625 @@
+// Host side of the C ABI declared in include/dg.h: argument validation,
+// in-edge (CSC) construction, tiling and the blocked worker partition, device
+// memory, and the sweep driver with device-side termination.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dg.h"
+#include "dg_internal.hpp"
+
+using namespace dg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+dg_status fail(dg_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+std::mutex g_alloc_mu;
+dg_alloc_fn g_alloc = nullptr;
+dg_free_fn g_free = nullptr;
+void* g_alloc_ctx = nullptr;
+
+// Sweeps queued ahead of the host's convergence check.  Each queued sweep
+// first tests on the device whether an earlier one met the stopping rule.
+constexpr uint32_t kSweepChunk = 8;
+constexpr uint32_t kMaxSweeps = 1000000;
+
+}  // namespace
+
+struct dg_graph {
+  uint32_t n = 0;
+  uint64_t m = 0;
+  bool has_w = false;
+  uint32_t P = 0, T = 0, cus = 0, max_in_deg = 0, n_dangling = 0;
+  size_t lds_per_block = 65536;
+  // allocator captured at creation
+  dg_alloc_fn alloc = nullptr;
+  dg_free_fn free_fn = nullptr;
+  void* ctx = nullptr;
+  hipStream_t create_stream = nullptr;
+  std::vector<void*> owned;
+  uint64_t graph_bytes = 0;
+  // resident graph
+  uint32_t *in_ptr = nullptr, *in_src = nullptr, *in_w = nullptr, *out_deg = nullptr;
+  uint32_t *tile_v = nullptr, *work_t = nullptr;
+  // workspace (grown on demand)
+  void* vals[3] = {nullptr, nullptr, nullptr};  // 8n bytes each
+  double* norm = nullptr;                        // kNormBlocks + 1
+  uint32_t ws_sweeps = 0;
+  double *resid = nullptr, *dang = nullptr, *part = nullptr;
+  uint32_t *count = nullptr, *changed = nullptr;
+  void* host_poll = nullptr;  // pinned [S+1] doubles
+  hipEvent_t ev_start = nullptr;
+  hipEvent_t ev_sweep[2 * kSweepChunk] = {};
+  hipEvent_t ev_copy[2] = {};
+  bool events = false;
+};
+
+namespace {
+
+void* dev_alloc(dg_graph* g, size_t bytes, hipStream_t s) {
+  if (bytes == 0) bytes = 256;
+  void* p = nullptr;
+  if (g->alloc) {
+    p = g->alloc(bytes, s, g->ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  if (p) g->owned.push_back(p);
+  return p;
+}
+
+void dev_free(dg_graph* g, void* p) {
+  if (!p) return;
+  auto it = std::find(g->owned.begin(), g->owned.end(), p);
+  if (it != g->owned.end()) g->owned.erase(it);
+  if (g->free_fn) g->free_fn(p, g->create_stream, g->ctx);
+  else (void)hipFree(p);
+}
+
+void release_all(dg_graph* g) {
+  if (g->events) {
+    (void)hipEventDestroy(g->ev_start);
+    for (auto& e : g->ev_sweep) (void)hipEventDestroy(e);
+    for (auto& e : g->ev_copy) (void)hipEventDestroy(e);
+    g->events = false;
+  }
+  if (g->host_poll) {
+    (void)hipHostFree(g->host_poll);
+    g->host_poll = nullptr;
+  }
+  std::vector<void*> all = g->owned;
+  for (void* p : all) dev_free(g, p);
+  g->owned.clear();
+}
+
+#define DG_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      (void)hipGetLastError();                                                        \
+      return fail(e_ == hipErrorOutOfMemory ? DG_ERR_OUT_OF_MEMORY : DG_ERR_DEVICE,   \
+                  "%s failed: %s", #call, hipGetErrorString(e_));                     \
+    }                                                                                 \
+  } while (0)
+
+// Tiles: consecutive vertices, at most kTileV of them and at most kTileE
+// in-edges, except that a vertex with more than kTileE in-edges is a tile of
+// its own.
+void build_tiles(const std::vector<uint32_t>& in_ptr, uint32_t n, std::vector<uint32_t>& tile_v) {
+  tile_v.clear();
+  tile_v.push_back(0);
+  uint32_t nv = 0;
+  uint64_t ne = 0;
+  for (uint32_t v = 0; v < n; ++v) {
+    const uint64_t deg = in_ptr[v + 1] - in_ptr[v];
+    if (nv > 0 && (nv == (uint32_t)kTileV || ne + deg > (uint64_t)kTileE)) {
+      tile_v.push_back(v);
+      nv = 0;
+      ne = 0;
+    }
+    ++nv;
+    ne += deg;
+  }
+  if (tile_v.back() != n) tile_v.push_back(n);
+}
+
+// Blocked partition of the tiles over P workers (section III-A: contiguous
+// blocks balanced by in-neighbours).  The cost of a tile also counts its
+// vertices and a fixed per-tile overhead, because on the GPU each vertex is
+// read and written and each tile costs a few workgroup barriers.
+void build_workers(const std::vector<uint32_t>& in_ptr, const std::vector<uint32_t>& tile_v, uint32_t P,
+                   std::vector<uint32_t>& work_t) {
+  const uint32_t T = (uint32_t)tile_v.size() - 1;
+  std::vector<double> cum(T + 1, 0.0);
+  for (uint32_t t = 0; t < T; ++t) {
+    const double e = (double)(in_ptr[tile_v[t + 1]] - in_ptr[tile_v[t]]);
+    const double v = (double)(tile_v[t + 1] - tile_v[t]);
+    cum[t + 1] = cum[t] + 256.0 + e + 4.0 * v;
+  }
+  work_t.assign(P + 1, T);
+  work_t[0] = 0;
+  for (uint32_t w = 1; w < P; ++w) {
+    const double target = cum[T] * (double)w / (double)P;
+    uint32_t t = (uint32_t)(std::lower_bound(cum.begin(), cum.end(), target) - cum.begin());
+    t = std::min(std::max(t, work_t[w - 1]), T);
+    work_t[w] = t;
+  }
+  work_t[P] = T;
+}
+
+dg_status ensure_workspace(dg_graph* g, uint32_t S, hipStream_t s) {
+  if (!g->vals[0]) {
+    for (auto& v : g->vals) {
+      v = dev_alloc(g, (size_t)g->n * 8, s);
+      if (!v) return fail(DG_ERR_OUT_OF_MEMORY, "workspace allocation of %zu bytes failed", (size_t)g->n * 8);
+    }
+    g->norm = static_cast<double*>(dev_alloc(g, (kNormBlocks + 1) * sizeof(double), s));
+    g->part = static_cast<double*>(dev_alloc(g, 2 * (size_t)g->P * sizeof(double), s));
+    if (!g->norm || !g->part) return fail(DG_ERR_OUT_OF_MEMORY, "workspace allocation failed");
+  }
+  if (!g->events) {
+    DG_HIP(hipEventCreate(&g->ev_start));
+    for (auto& e : g->ev_sweep) DG_HIP(hipEventCreate(&e));
+    for (auto& e : g->ev_copy) DG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    g->events = true;
+  }
+  if (g->ws_sweeps < S) {
+    dev_free(g, g->resid);
+    dev_free(g, g->dang);
+    dev_free(g, g->count);
+    dev_free(g, g->changed);
+    if (g->host_poll) (void)hipHostFree(g->host_poll);
+    g->host_poll = nullptr;
+    const size_t k = (size_t)S + 1;
+    g->resid = static_cast<double*>(dev_alloc(g, k * sizeof(double), s));
+    g->dang = static_cast<double*>(dev_alloc(g, k * sizeof(double), s));
+    g->count = static_cast<uint32_t*>(dev_alloc(g, k * sizeof(uint32_t), s));
+    g->changed = static_cast<uint32_t*>(dev_alloc(g, k * sizeof(uint32_t), s));
+    if (!g->resid || !g->dang || !g->count || !g->changed) {
+      g->ws_sweeps = 0;
+      return fail(DG_ERR_OUT_OF_MEMORY, "sweep state allocation failed");
+    }
+    DG_HIP(hipHostMalloc(&g->host_poll, k * sizeof(double), hipHostMallocDefault));
+    g->ws_sweeps = S;
+  }
+  return DG_OK;
+}
+
+Topology topo(const dg_graph* g) {
+  Topology t;
+  t.in_ptr = g->in_ptr;
+  t.in_src = g->in_src;
+  t.in_w = g->in_w;
+  t.out_deg = g->out_deg;
+  t.tile_v = g->tile_v;
+  t.work_t = g->work_t;
+  t.n = g->n;
+  t.P = g->P;
+  return t;
+}
+
+SweepState state(const dg_graph* g) {
+  SweepState st;
+  st.resid = g->resid;
+  st.dang = g->dang;
+  st.count = g->count;
+  st.changed = g->changed;
+  st.part = g->part;
+  return st;
+}
+
+dg_status check_mode(dg_mode mode, uint32_t d) {
+  if (mode != DG_SYNC && mode != DG_ASYNC && mode != DG_DELAYED)
+    return fail(DG_ERR_INVALID_ARGUMENT, "mode %d is not DG_SYNC, DG_ASYNC or DG_DELAYED", (int)mode);
+  if (mode == DG_DELAYED && d == 0)
+    return fail(DG_ERR_INVALID_ARGUMENT, "delayed mode needs a commit interval d >= 1");
+  return DG_OK;
+}
+
+// Staging capacity in vertices for a commit interval d: room for d values
+// plus one more tile, bounded by the LDS a workgroup may allocate.
+void staging(const dg_graph* g, uint32_t d, size_t elem, uint32_t& cap, uint32_t& d_eff) {
+  const size_t static_lds = 6 * 1024;
+  size_t max_vals = (g->lds_per_block > static_lds ? g->lds_per_block - static_lds : 0) / elem;
+  if (max_vals < 2 * (size_t)kTileV) max_vals = 2 * (size_t)kTileV;
+  const uint32_t dmax = (uint32_t)(max_vals - kTileV);
+  d_eff = d < dmax ? d : dmax;
+  cap = d_eff + kTileV;
+}
+
+// Convergence loop shared by both algorithms.  launch(k) enqueues sweep k;
+// the state entry k+1 (PageRank residual or Bellman-Ford changed flag) is
+// copied to the host after each chunk; done(entry) tells whether sweep k met
+// the stopping rule.  Two chunks are in flight so the device never waits for
+// the host.
+template <typename Launch, typename Done>
+dg_status drive(dg_graph* g, uint32_t max_sweeps, hipStream_t s, bool pr, Launch launch, Done done,
+                uint32_t& sweeps, double& seconds, bool& converged, double& last_entry) {
+  const uint32_t C = std::min(kSweepChunk, max_sweeps);
+  const size_t esz = pr ? sizeof(double) : sizeof(uint32_t);
+  void* src = pr ? (void*)g->resid : (void*)g->changed;
+  unsigned char* host = static_cast<unsigned char*>(g->host_poll);
+  DG_HIP(hipEventRecord(g->ev_start, s));
+  uint32_t next = 0;  // next sweep to enqueue
+  uint32_t chunk_idx = 0;
+  std::vector<std::pair<uint32_t, uint32_t>> inflight;  // (first sweep, count)
+  auto enqueue = [&]() -> dg_status {
+    const uint32_t k0 = next, kc = std::min(C, max_sweeps - next);
+    for (uint32_t j = 0; j < kc; ++j) {
+      hipError_t e = launch(k0 + j);
+      if (e != hipSuccess) return fail(DG_ERR_DEVICE, "sweep launch failed: %s", hipGetErrorString(e));
+      DG_HIP(hipEventRecord(g->ev_sweep[(k0 + j) % (2 * kSweepChunk)], s));
+    }
+    DG_HIP(hipMemcpyAsync(host + (size_t)(k0 + 1) * esz, static_cast<unsigned char*>(src) + (size_t)(k0 + 1) * esz,
+                          (size_t)kc * esz, hipMemcpyDeviceToHost, s));
+    DG_HIP(hipEventRecord(g->ev_copy[chunk_idx & 1], s));
+    ++chunk_idx;
+    inflight.emplace_back(k0, kc);
+    next += kc;
+    return DG_OK;
+  };
+  converged = false;
+  sweeps = 0;
+  dg_status st = enqueue();
+  if (st != DG_OK) return st;
+  if (next < max_sweeps && (st = enqueue()) != DG_OK) return st;
+  uint32_t polled = 0;
+  int found = -1;
+  while (!inflight.empty()) {
+    auto [k0, kc] = inflight.front();
+    inflight.erase(inflight.begin());
+    DG_HIP(hipEventSynchronize(g->ev_copy[polled & 1]));
+    ++polled;
+    for (uint32_t j = 0; j < kc; ++j) {
+      const unsigned char* p = host + (size_t)(k0 + j + 1) * esz;
+      if (done(p)) {
+        found = (int)(k0 + j);
+        break;
+      }
+    }
+    if (found >= 0) break;
+    if (next < max_sweeps && (st = enqueue()) != DG_OK) return st;
+  }
+  DG_HIP(hipStreamSynchronize(s));
+  const uint32_t last = found >= 0 ? (uint32_t)found : max_sweeps - 1;
+  converged = found >= 0;
+  sweeps = last + 1;
+  float ms = 0.f;
+  DG_HIP(hipEventElapsedTime(&ms, g->ev_start, g->ev_sweep[last % (2 * kSweepChunk)]));
+  seconds = ms * 1e-3;
+  if (pr) {
+    std::memcpy(&last_entry, host + (size_t)(last + 1) * esz, sizeof(double));
+  } else {
+    last_entry = 0.0;
+  }
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dg_version(void) { return "dg 0.1 (gfx950)"; }
+
+const char* dg_last_error(void) { return g_last_error.c_str(); }
+
+const char* dg_status_str(dg_status s) {
+  switch (s) {
+    case DG_OK: return "DG_OK";
+    case DG_ERR_INVALID_ARGUMENT: return "DG_ERR_INVALID_ARGUMENT";
+    case DG_ERR_OUT_OF_MEMORY: return "DG_ERR_OUT_OF_MEMORY";
+    case DG_ERR_DEVICE: return "DG_ERR_DEVICE";
+    case DG_ERR_NOT_CONVERGED: return "DG_ERR_NOT_CONVERGED";
+    case DG_ERR_UNSUPPORTED: return "DG_ERR_UNSUPPORTED";
+  }
+  return "DG_ERR_UNKNOWN";
+}
+
+dg_status dg_set_allocator(dg_alloc_fn alloc, dg_free_fn free_fn, void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(DG_ERR_INVALID_ARGUMENT, "alloc and free hooks must both be set or both be NULL");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc = alloc;
+  g_free = free_fn;
+  g_alloc_ctx = ctx;
+  return DG_OK;
+}
+
+dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
+                          const uint32_t* w, void* hip_stream, dg_graph** out) {
+  g_last_error.clear();
+  if (!out) return fail(DG_ERR_INVALID_ARGUMENT, "out is NULL");
+  if (n == 0 || n > 0xFFFFFFFEu) return fail(DG_ERR_INVALID_ARGUMENT, "n = %u outside [1, 2^32-2]", n);
+  if (m >= (uint64_t)0xFFFFFFFFu - 2 * kEdgePad) return fail(DG_ERR_INVALID_ARGUMENT, "m = %llu too large",
+                                                             (unsigned long long)m);
+  if (layout != DG_CSR && layout != DG_CSC) return fail(DG_ERR_INVALID_ARGUMENT, "unknown layout %d", (int)layout);
+  if (!ptr) return fail(DG_ERR_INVALID_ARGUMENT, "ptr is NULL");
+  if (m > 0 && !idx) return fail(DG_ERR_INVALID_ARGUMENT, "idx is NULL");
+  if (ptr[0] != 0) return fail(DG_ERR_INVALID_ARGUMENT, "ptr[0] = %llu, expected 0", (unsigned long long)ptr[0]);
+  for (uint32_t v = 0; v < n; ++v)
+    if (ptr[v + 1] < ptr[v]) return fail(DG_ERR_INVALID_ARGUMENT, "ptr decreases at %u", v);
+  if (ptr[n] != m) return fail(DG_ERR_INVALID_ARGUMENT, "ptr[n] = %llu, expected m = %llu",
+                               (unsigned long long)ptr[n], (unsigned long long)m);
+  for (uint64_t e = 0; e < m; ++e)
+    if (idx[e] >= n) return fail(DG_ERR_INVALID_ARGUMENT, "idx[%llu] = %u >= n", (unsigned long long)e, idx[e]);
+
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  dg_graph* g = new (std::nothrow) dg_graph;
+  if (!g) return fail(DG_ERR_OUT_OF_MEMORY, "host allocation failed");
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g->alloc = g_alloc;
+    g->free_fn = g_free;
+    g->ctx = g_alloc_ctx;
+  }
+  g->create_stream = s;
+  g->n = n;
+  g->m = m;
+  g->has_w = (w != nullptr);
+
+  // In-edge form (stable counting sort: in-edges of a vertex by ascending source).
+  std::vector<uint32_t> in_ptr, in_src, in_w, out_deg, tile_v, work_t;
+  try {
+    in_ptr.assign((size_t)n + 1, 0);
+    in_src.assign((size_t)m + kEdgePad, 0);
+    if (w) in_w.assign((size_t)m + kEdgePad, 0);
+    out_deg.assign(n, 0);
+    if (layout == DG_CSR) {
+      for (uint64_t e = 0; e < m; ++e) ++in_ptr[idx[e] + 1];
+      for (uint32_t v = 0; v < n; ++v) in_ptr[v + 1] += in_ptr[v];
+      std::vector<uint32_t> pos(in_ptr.begin(), in_ptr.end() - 1);
+      for (uint32_t u = 0; u < n; ++u) {
+        out_deg[u] = (uint32_t)(ptr[u + 1] - ptr[u]);
+        for (uint64_t e = ptr[u]; e < ptr[u + 1]; ++e) {
+          const uint32_t p = pos[idx[e]]++;
+          in_src[p] = u;
+          if (w) in_w[p] = w[e];
+        }
+      }
+    } else {
+      for (uint32_t v = 0; v <= n; ++v) in_ptr[v] = (uint32_t)ptr[v];
+      for (uint64_t e = 0; e < m; ++e) {
+        in_src[e] = idx[e];
+        ++out_deg[idx[e]];
+      }
+      if (w) std::copy(w, w + m, in_w.begin());
+    }
+    for (uint32_t v = 0; v < n; ++v) {
+      g->max_in_deg = std::max(g->max_in_deg, in_ptr[v + 1] - in_ptr[v]);
+      g->n_dangling += out_deg[v] == 0;
+    }
+    build_tiles(in_ptr, n, tile_v);
+  } catch (const std::bad_alloc&) {
+    delete g;
+    return fail(DG_ERR_OUT_OF_MEMORY, "host allocation failed while building the in-edge form");
+  }
+  g->T = (uint32_t)tile_v.size() - 1;
+
+  // Device sizes.  Without a device (or on error) nothing below leaks.
+  int dev = 0, cus = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he == hipSuccess) he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  int lds = 0;
+  if (he == hipSuccess) he = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (he != hipSuccess) {
+    (void)hipGetLastError();
+    delete g;
+    return fail(DG_ERR_DEVICE, "no usable HIP device: %s", hipGetErrorString(he));
+  }
+  g->cus = (uint32_t)cus;
+  g->lds_per_block = (size_t)lds;
+  uint32_t P = std::max(1u, std::min(g->cus * 8u, g->T));
+  if (P > 8) P &= ~7u;
+  g->P = P;
+  build_workers(in_ptr, tile_v, P, work_t);
+
+  struct Up {
+    uint32_t** dst;
+    const std::vector<uint32_t>* src;
+  } ups[] = {{&g->in_ptr, &in_ptr}, {&g->in_src, &in_src}, {&g->in_w, &in_w},
+             {&g->out_deg, &out_deg}, {&g->tile_v, &tile_v}, {&g->work_t, &work_t}};
+  for (auto& u : ups) {
+    if (u.src->empty()) continue;
+    const size_t bytes = u.src->size() * sizeof(uint32_t);
+    *u.dst = static_cast<uint32_t*>(dev_alloc(g, bytes, s));
+    if (!*u.dst) {
+      release_all(g);
+      delete g;
+      return fail(DG_ERR_OUT_OF_MEMORY, "device allocation of %zu bytes failed", bytes);
+    }
+    g->graph_bytes += bytes;
+    he = hipMemcpyAsync(*u.dst, u.src->data(), bytes, hipMemcpyHostToDevice, s);
+    if (he != hipSuccess) break;
+  }
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  if (he != hipSuccess) {
+    (void)hipGetLastError();
+    release_all(g);
+    delete g;
+    return fail(DG_ERR_DEVICE, "graph upload failed: %s", hipGetErrorString(he));
+  }
+  *out = g;
+  return DG_OK;
+}
+
+dg_status dg_graph_destroy(dg_graph* g) {
+  if (!g) return DG_OK;
+  (void)hipDeviceSynchronize();
+  release_all(g);
+  delete g;
+  return DG_OK;
+}
+
+dg_status dg_graph_info_get(const dg_graph* g, dg_graph_info* info) {
+  if (!g || !info) return fail(DG_ERR_INVALID_ARGUMENT, "NULL argument");
+  info->n = g->n;
+  info->m = g->m;
+  info->workers = g->P;
+  info->tiles = g->T;
+  info->max_in_degree = g->max_in_deg;
+  info->dangling = g->n_dangling;
+  info->has_weights = g->has_w ? 1u : 0u;
+  info->compute_units = g->cus;
+  info->device_bytes = g->graph_bytes;
+  return DG_OK;
+}
+
+dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uint32_t d, dg_dtype dtype,
+                      uint32_t max_sweeps, double* out_scores, int out_on_device, dg_stats* stats,
+                      void* hip_stream) {
+  g_last_error.clear();
+  if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (!(damping >= 0.0 && damping < 1.0)) return fail(DG_ERR_INVALID_ARGUMENT, "damping must be in [0, 1)");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(DG_ERR_INVALID_ARGUMENT, "tol must be finite and >= 0");
+  dg_status st = check_mode(mode, d);
+  if (st != DG_OK) return st;
+  if (dtype != DG_F32 && dtype != DG_F64) return fail(DG_ERR_INVALID_ARGUMENT, "unknown dtype %d", (int)dtype);
+  if (max_sweeps == 0 || max_sweeps > kMaxSweeps)
+    return fail(DG_ERR_INVALID_ARGUMENT, "max_sweeps must be in [1, %u]", kMaxSweeps);
+  if (!out_scores) return fail(DG_ERR_INVALID_ARGUMENT, "out_scores is NULL");
+
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if ((st = ensure_workspace(g, max_sweeps, s)) != DG_OK) return st;
+  const bool f64 = dtype == DG_F64;
+  const size_t elem = f64 ? 8 : 4;
+  uint32_t cap = 0, d_eff = 0;
+  if (mode == DG_DELAYED) staging(g, d, elem, cap, d_eff);
+  void* x = g->vals[0];
+  void* c0 = g->vals[1];
+  void* c1 = mode == DG_SYNC ? g->vals[2] : nullptr;
+  const double d0 = (double)g->n_dangling / (double)g->n;
+  SweepState sst = state(g);
+  DG_HIP(launch_pr_init(f64, x, c0, c1, g->out_deg, g->n, sst, max_sweeps, d0, s));
+
+  PrArgs a;
+  a.g = topo(g);
+  a.st = sst;
+  a.x = x;
+  a.alpha = damping;
+  a.tol = tol;
+  a.d = d_eff;
+  a.cap = cap;
+  auto launch = [&](uint32_t k) {
+    if (mode == DG_SYNC) {
+      a.cin = (k & 1) ? c1 : c0;
+      a.cout = (k & 1) ? c0 : c1;
+    } else {
+      a.cin = c0;
+      a.cout = c0;
+    }
+    a.k = k;
+    return launch_pr_sweep((int)mode, f64, a, s);
+  };
+  auto done = [&](const unsigned char* p) {
+    double r;
+    std::memcpy(&r, p, sizeof r);
+    return !(r >= tol);
+  };
+  uint32_t sweeps = 0;
+  double secs = 0.0, resid = 0.0;
+  bool conv = false;
+  if ((st = drive(g, max_sweeps, s, true, launch, done, sweeps, secs, conv, resid)) != DG_OK) return st;
+
+  double* dst = out_on_device ? out_scores : static_cast<double*>(g->vals[1]);
+  if (!out_on_device && mode != DG_SYNC) dst = static_cast<double*>(g->vals[2]);
+  DG_HIP(launch_normalize(f64, x, g->n, dst, g->norm, s));
+  if (!out_on_device) DG_HIP(hipMemcpyAsync(out_scores, dst, (size_t)g->n * 8, hipMemcpyDeviceToHost, s));
+  DG_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    stats->sweeps = sweeps;
+    stats->workers = g->P;
+    stats->tile_vertices = kTileV;
+    stats->commit_interval = mode == DG_DELAYED ? d_eff : 0;
+    stats->residual = resid;
+    stats->seconds = secs;
+    stats->edges_traversed = g->m * (uint64_t)sweeps;
+  }
+  if (!conv) return fail(DG_ERR_NOT_CONVERGED, "no convergence within %u sweeps (last change %g)", max_sweeps, resid);
+  return DG_OK;
+}
+
+dg_status dg_sssp(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t max_sweeps, uint32_t* out_dist,
+                  int out_on_device, dg_stats* stats, void* hip_stream) {
+  g_last_error.clear();
+  if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (!g->has_w) return fail(DG_ERR_INVALID_ARGUMENT, "graph was created without weights");
+  if (src >= g->n) return fail(DG_ERR_INVALID_ARGUMENT, "source %u >= n = %u", src, g->n);
+  dg_status st = check_mode(mode, d);
+  if (st != DG_OK) return st;
+  if (max_sweeps == 0 || max_sweeps > kMaxSweeps)
+    return fail(DG_ERR_INVALID_ARGUMENT, "max_sweeps must be in [1, %u]", kMaxSweeps);
+  if (!out_dist) return fail(DG_ERR_INVALID_ARGUMENT, "out_dist is NULL");
+
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if ((st = ensure_workspace(g, max_sweeps, s)) != DG_OK) return st;
+  uint32_t cap = 0, d_eff = 0;
+  if (mode == DG_DELAYED) staging(g, d, sizeof(uint32_t), cap, d_eff);
+  uint32_t* b0 = static_cast<uint32_t*>(g->vals[0]);
+  uint32_t* b1 = mode == DG_SYNC ? static_cast<uint32_t*>(g->vals[1]) : nullptr;
+  SweepState sst = state(g);
+  DG_HIP(launch_bf_init(b0, b1, g->n, src, sst, max_sweeps, s));
+
+  BfArgs a;
+  a.g = topo(g);
+  a.st = sst;
+  a.d = d_eff;
+  a.cap = cap;
+  auto launch = [&](uint32_t k) {
+    if (mode == DG_SYNC) {
+      a.din = (k & 1) ? b1 : b0;
+      a.dout = (k & 1) ? b0 : b1;
+    } else {
+      a.din = b0;
+      a.dout = b0;
+    }
+    a.k = k;
+    return launch_bf_sweep((int)mode, a, s);
+  };
+  auto done = [&](const unsigned char* p) {
+    uint32_t c;
+    std::memcpy(&c, p, sizeof c);
+    return c == 0;
+  };
+  uint32_t sweeps = 0;
+  double secs = 0.0, unused = 0.0;
+  bool conv = false;
+  if ((st = drive(g, max_sweeps, s, false, launch, done, sweeps, secs, conv, unused)) != DG_OK) return st;
+  // The last executed sweep k = sweeps-1 wrote buffer (k+1) % 2 in sync mode.
+  const uint32_t* res = (mode == DG_SYNC && (sweeps & 1)) ? b1 : b0;
+  DG_HIP(hipMemcpyAsync(out_dist, res, (size_t)g->n * sizeof(uint32_t),
+                        out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  DG_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    stats->sweeps = sweeps;
+    stats->workers = g->P;
+    stats->tile_vertices = kTileV;
+    stats->commit_interval = mode == DG_DELAYED ? d_eff : 0;
+    stats->residual = 0.0;
+    stats->seconds = secs;
+    stats->edges_traversed = g->m * (uint64_t)sweeps;
+  }
+  if (!conv) return fail(DG_ERR_NOT_CONVERGED, "no convergence within %u sweeps", max_sweeps);
+  return DG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Internal interface between the host driver (dg_api.cpp) and the gfx950
+// sweep kernels (sweep_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dg {
+
+// Workgroup shape of every sweep kernel: 4 wave64s.
+constexpr int kWG = 256;
+// Consecutive in-edges one thread reduces per chunk (two 16-byte index loads).
+constexpr int kEPT = 8;
+// Edge slots a workgroup covers per chunk.
+constexpr int kChunk = kWG * kEPT;
+// At most this many vertices per tile: one vertex per thread in the update phase.
+constexpr int kTileV = kWG;
+// Edge budget of a multi-vertex tile.  A chunk starts at the tile's first
+// edge rounded down to a multiple of 4 (16-byte aligned vector loads), so a
+// tile of at most kChunk-4 edges always fits one chunk.  A single vertex with
+// more in-edges gets a tile of its own that spans several chunks.
+constexpr int kTileE = kChunk - 4;
+// Zero padding after in_src / in_w so that the last chunk's vector loads stay
+// inside the allocation.
+constexpr uint32_t kEdgePad = kChunk + 16;
+
+constexpr uint32_t kInf = 0xFFFFFFFFu;
+
+enum Mode : int { kSync = 0, kAsync = 1, kDelayed = 2 };
+
+// Graph arrays resident in HBM (all device pointers).
+struct Topology {
+  const uint32_t* in_ptr;   // [n+1] in-edge offsets (CSC over destinations)
+  const uint32_t* in_src;   // [m + kEdgePad] source of each in-edge
+  const uint32_t* in_w;     // [m + kEdgePad] weight of each in-edge (nullable)
+  const uint32_t* out_deg;  // [n] out-degree
+  const uint32_t* tile_v;   // [T+1] first vertex of each tile
+  const uint32_t* work_t;   // [P+1] first tile of each worker
+  uint32_t n;
+  uint32_t P;               // workers = workgroups launched per sweep
+};
+
+// Per-call convergence state, indexed by sweep.  Sweep k reads entry k and
+// writes entry k+1, so a queued sweep can test on the device whether an
+// earlier one already met the stopping rule.
+struct SweepState {
+  double* resid;      // [S+1] resid[k+1] = L1 change of sweep k; resid[0] = +inf
+  double* dang;       // [S+1] dangling mass used by sweep k
+  uint32_t* count;    // [S+1] workers finished in sweep k
+  uint32_t* changed;  // [S+1] changed[k+1] != 0 iff sweep k decreased a distance
+  double* part;       // [2P] per-worker partial sums (residual, dangling mass)
+};
+
+struct PrArgs {
+  Topology g;
+  SweepState st;
+  void* x;          // [n] scores, written only by their owner
+  const void* cin;  // [n] contributions read by the sweep
+  void* cout;       // [n] contributions written (== cin unless synchronous)
+  double alpha;
+  double tol;
+  uint32_t k;       // sweep index
+  uint32_t d;       // commit interval in vertices (delayed mode)
+  uint32_t cap;     // staging capacity in vertices (delayed mode)
+};
+
+struct BfArgs {
+  Topology g;
+  SweepState st;
+  const uint32_t* din;  // [n] distances read by the sweep
+  uint32_t* dout;       // [n] distances written (== din unless synchronous)
+  uint32_t k;
+  uint32_t d;
+  uint32_t cap;
+};
+
+// Launchers (enqueue only; return the launch status).
+hipError_t launch_pr_init(bool f64, void* x, void* c0, void* c1, const uint32_t* out_deg, uint32_t n,
+                          SweepState st, uint32_t S, double d0, hipStream_t s);
+hipError_t launch_pr_sweep(int mode, bool f64, const PrArgs& a, hipStream_t s);
+hipError_t launch_bf_init(uint32_t* d0, uint32_t* d1, uint32_t n, uint32_t src, SweepState st, uint32_t S,
+                          hipStream_t s);
+hipError_t launch_bf_sweep(int mode, const BfArgs& a, hipStream_t s);
+// out[v] = x[v] / sum(x), sum in float64 with a fixed reduction order.
+hipError_t launch_normalize(bool f64, const void* x, uint32_t n, double* out, double* scratch, hipStream_t s);
+constexpr uint32_t kNormBlocks = 512;  // scratch needs kNormBlocks + 1 doubles
+
+}  // namespace dg

@@ -1,0 +1,485 @@
+// gfx950 kernels for pull-style PageRank and Bellman-Ford sweeps in the three
+// commit modes of Blanco, McMillan and Low, "Delayed Asynchronous Iterative
+// Graph Algorithms" (section III).
+//
+// Mapping (the same for both algorithms):
+//   * A sweep launches P persistent workgroups ("workers").  Worker w owns a
+//     contiguous range of tiles and so a contiguous vertex block (blocked
+//     partitioning balanced by in-edges, section III-A) and walks it in
+//     ascending vertex order.  Worker ids are spread so that each of the eight
+//     XCDs (workgroups are dispatched to XCDs round-robin) owns one contiguous
+//     eighth of the vertex range.
+//   * A tile holds <= 256 vertices and <= 2044 in-edges, or one vertex with
+//     more.  Its edges are processed in chunks of 2048 slots starting at the
+//     tile's first edge rounded down to a multiple of 4: thread t reduces the
+//     8 consecutive slots [8t, 8t+8) of the chunk, fetched with two 16-byte
+//     loads of the index (and weight) stream, then 8 independent gathers.
+//     Partial sums (or minima) per vertex go to LDS with ds_add_f64 /
+//     ds_min_u32 once per vertex boundary crossed; a single-vertex tile uses a
+//     wavefront shuffle reduction and one LDS atomic per wave instead.
+//   * In the update phase thread i of the workgroup computes vertex i of the
+//     tile and commits it according to the mode:
+//       sync     plain store into the output array (double buffer);
+//       async    agent-scope store into the single global array at once;
+//       delayed  store into an LDS staging buffer; the buffer is copied to the
+//                global array with coalesced agent-scope stores when it holds
+//                >= d values, when the next tile would overflow it, and when
+//                the worker's block is done (section III-B).
+//     Gathers in async and delayed mode are agent-scope loads so that values
+//     committed by workgroups on other XCDs are seen within the same sweep
+//     (global reads, section III-C); synchronous gathers are plain cached
+//     loads.
+//   * Each worker reduces its residual / dangling mass (PageRank) or
+//     "changed" flag (Bellman-Ford) over its block; the last worker to finish
+//     sums the per-worker partials in worker order and publishes the values the
+//     next sweep reads, so termination is decided on the device.
+#include "dg_internal.hpp"
+
+namespace dg {
+namespace {
+
+__device__ __forceinline__ uint32_t worker_id(uint32_t b, uint32_t P) {
+  // Workgroup b runs on XCD b % 8; give each XCD a contiguous slice of workers.
+  if ((P & 7u) == 0) return (b & 7u) * (P >> 3) + (b >> 3);
+  return b;
+}
+
+template <int M, typename T>
+__device__ __forceinline__ T ld_shared(const T* p) {
+  if constexpr (M == kSync) {
+    return *p;
+  } else {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void st_agent(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t u = __shfl_xor(v, o, 64);
+    v = u < v ? u : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
+  const uint32_t s = a + b;
+  return s < a ? kInf : s;  // INF + w and overflow both saturate
+}
+
+// Largest i in [0, nv) with s_ptr[i] <= e, given s_ptr[0] <= e < s_ptr[nv]:
+// the tile-local vertex that owns edge slot e.
+__device__ __forceinline__ uint32_t owner_of(const uint32_t* s_ptr, uint32_t nv, uint32_t e) {
+  uint32_t lo = 0, hi = nv;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (s_ptr[mid] <= e) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void load_idx8(const uint32_t* p, uint32_t (&u)[kEPT]) {
+  const uint4 q0 = *reinterpret_cast<const uint4*>(p);
+  const uint4 q1 = *reinterpret_cast<const uint4*>(p + 4);
+  u[0] = q0.x; u[1] = q0.y; u[2] = q0.z; u[3] = q0.w;
+  u[4] = q1.x; u[5] = q1.y; u[6] = q1.z; u[7] = q1.w;
+}
+
+// ---------------------------------------------------------------- PageRank --
+
+template <int M, typename T>
+__global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
+  __shared__ uint32_t s_ptr[kTileV + 1];
+  __shared__ double s_acc[kTileV];
+  __shared__ double s_red[2 * (kWG / 64)];
+  __shared__ int s_last;
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  T* s_stage = reinterpret_cast<T*>(s_dyn);
+
+  const uint32_t k = a.k;
+  if (!(a.st.resid[k] >= a.tol)) return;  // an earlier sweep met the stopping rule
+
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63u, wv = tid >> 6;
+  const uint32_t P = a.g.P;
+  const uint32_t w = worker_id(blockIdx.x, P);
+  const double inv_n = 1.0 / (double)a.g.n;
+  const double alpha = a.alpha;
+  const double base = (1.0 - alpha) * inv_n + alpha * a.st.dang[k] * inv_n;
+  const T* cin = static_cast<const T*>(a.cin);
+  T* cout = static_cast<T*>(a.cout);
+  T* x = static_cast<T*>(a.x);
+
+  double r_loc = 0.0, d_loc = 0.0;
+  const uint32_t t0 = a.g.work_t[w], t1 = a.g.work_t[w + 1];
+  uint32_t staged = 0;
+  uint32_t stage_v0 = a.g.tile_v[t0];
+
+  for (uint32_t t = t0; t < t1; ++t) {
+    const uint32_t v0 = a.g.tile_v[t], v1 = a.g.tile_v[t + 1], nv = v1 - v0;
+    for (uint32_t i = tid; i <= nv; i += kWG) s_ptr[i] = a.g.in_ptr[v0 + i];
+    if (tid < nv) s_acc[tid] = 0.0;
+    __syncthreads();
+    const uint32_t eb = s_ptr[0], ee = s_ptr[nv];
+    for (uint32_t cb = eb & ~3u; cb < ee; cb += kChunk) {
+      const uint32_t e0 = cb + tid * kEPT;
+      const bool active = (e0 < ee) && (e0 + kEPT > eb);
+      double val[kEPT];
+#pragma unroll
+      for (int j = 0; j < kEPT; ++j) val[j] = 0.0;
+      if (active) {
+        uint32_t u[kEPT];
+        load_idx8(a.g.in_src + e0, u);
+#pragma unroll
+        for (int j = 0; j < kEPT; ++j) {
+          const uint32_t e = e0 + j;
+          if (e >= eb && e < ee) val[j] = (double)ld_shared<M>(cin + u[j]);
+        }
+      }
+      if (nv == 1) {
+        double p = 0.0;
+#pragma unroll
+        for (int j = 0; j < kEPT; ++j) p += val[j];
+        p = wave_sum(p);
+        if (lane == 0) atomicAdd(&s_acc[0], p);
+      } else if (active) {
+        const uint32_t es = e0 > eb ? e0 : eb;
+        const uint32_t en = (e0 + kEPT < ee) ? e0 + kEPT : ee;
+        uint32_t i = owner_of(s_ptr, nv, es);
+        uint32_t bound = s_ptr[i + 1];
+        double part = 0.0;
+#pragma unroll
+        for (int j = 0; j < kEPT; ++j) {
+          const uint32_t e = e0 + j;
+          if (e >= es && e < en) {
+            if (e >= bound) {
+              atomicAdd(&s_acc[i], part);
+              part = 0.0;
+              do { ++i; bound = s_ptr[i + 1]; } while (e >= bound);
+            }
+            part += val[j];
+          }
+        }
+        atomicAdd(&s_acc[i], part);
+      }
+    }
+    __syncthreads();
+    if (tid < nv) {
+      const uint32_t v = v0 + tid;
+      const double xn = base + alpha * s_acc[tid];
+      const T xo = x[v];
+      const T xs = static_cast<T>(xn);
+      x[v] = xs;
+      const uint32_t dg = a.g.out_deg[v];
+      const T cn = dg ? static_cast<T>(xn / (double)dg) : static_cast<T>(0);
+      r_loc += fabs((double)xs - (double)xo);
+      if (dg == 0) d_loc += xn;
+      if constexpr (M == kSync) {
+        cout[v] = cn;
+      } else if constexpr (M == kAsync) {
+        st_agent(cout + v, cn);
+      } else {
+        s_stage[staged + tid] = cn;
+      }
+    }
+    if constexpr (M == kDelayed) {
+      staged += nv;
+      const bool last = (t + 1 == t1);
+      const uint32_t next_nv = last ? 0u : a.g.tile_v[t + 2] - v1;
+      if (last || staged >= a.d || staged + next_nv > a.cap) {
+        __syncthreads();
+        for (uint32_t i = tid; i < staged; i += kWG) st_agent(cout + stage_v0 + i, s_stage[i]);
+        stage_v0 += staged;
+        staged = 0;
+      }
+    }
+    __syncthreads();
+  }
+
+  // Worker partials, then the last worker folds them in worker order.
+  r_loc = wave_sum(r_loc);
+  d_loc = wave_sum(d_loc);
+  if (lane == 0) {
+    s_red[wv] = r_loc;
+    s_red[4 + wv] = d_loc;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    a.st.part[w] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    a.st.part[P + w] = s_red[4] + s_red[5] + s_red[6] + s_red[7];
+    __threadfence();
+    const uint32_t prev = atomicAdd(&a.st.count[k], 1u);
+    s_last = (prev == P - 1);
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    double r = 0.0, dd = 0.0;
+    for (uint32_t i = tid; i < P; i += kWG) {
+      r += __hip_atomic_load(a.st.part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      dd += __hip_atomic_load(a.st.part + P + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    r = wave_sum(r);
+    dd = wave_sum(dd);
+    if (lane == 0) {
+      s_red[wv] = r;
+      s_red[4 + wv] = dd;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      a.st.resid[k + 1] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+      a.st.dang[k + 1] = s_red[4] + s_red[5] + s_red[6] + s_red[7];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void pr_init_kernel(T* x, T* c0, T* c1, const uint32_t* out_deg, uint32_t n,
+                                                      SweepState st, uint32_t S, double d0) {
+  const uint32_t i = blockIdx.x * kWG + threadIdx.x;
+  const double x0 = 1.0 / (double)n;
+  if (i < n) {
+    const uint32_t dg = out_deg[i];
+    const T c = dg ? static_cast<T>(x0 / (double)dg) : static_cast<T>(0);
+    x[i] = static_cast<T>(x0);
+    c0[i] = c;
+    if (c1) c1[i] = c;
+  }
+  if (i <= S) {
+    st.resid[i] = (i == 0) ? __builtin_inf() : 0.0;
+    st.dang[i] = (i == 0) ? d0 : 0.0;
+    st.count[i] = 0;
+    st.changed[i] = (i == 0) ? 1u : 0u;
+  }
+}
+
+// ------------------------------------------------------------ Bellman-Ford --
+
+template <int M>
+__global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
+  __shared__ uint32_t s_ptr[kTileV + 1];
+  __shared__ uint32_t s_acc[kTileV];
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  uint32_t* s_stage = reinterpret_cast<uint32_t*>(s_dyn);
+
+  const uint32_t k = a.k;
+  if (a.st.changed[k] == 0) return;  // an earlier sweep made no update
+
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63u;
+  const uint32_t w = worker_id(blockIdx.x, a.g.P);
+  const uint32_t* din = a.din;
+  uint32_t* dout = a.dout;
+  const uint32_t t0 = a.g.work_t[w], t1 = a.g.work_t[w + 1];
+  uint32_t staged = 0;
+  uint32_t stage_v0 = a.g.tile_v[t0];
+  int any = 0;
+
+  for (uint32_t t = t0; t < t1; ++t) {
+    const uint32_t v0 = a.g.tile_v[t], v1 = a.g.tile_v[t + 1], nv = v1 - v0;
+    for (uint32_t i = tid; i <= nv; i += kWG) s_ptr[i] = a.g.in_ptr[v0 + i];
+    if (tid < nv) s_acc[tid] = kInf;
+    __syncthreads();
+    const uint32_t eb = s_ptr[0], ee = s_ptr[nv];
+    for (uint32_t cb = eb & ~3u; cb < ee; cb += kChunk) {
+      const uint32_t e0 = cb + tid * kEPT;
+      const bool active = (e0 < ee) && (e0 + kEPT > eb);
+      uint32_t cand[kEPT];
+#pragma unroll
+      for (int j = 0; j < kEPT; ++j) cand[j] = kInf;
+      if (active) {
+        uint32_t u[kEPT], wt[kEPT];
+        load_idx8(a.g.in_src + e0, u);
+        load_idx8(a.g.in_w + e0, wt);
+#pragma unroll
+        for (int j = 0; j < kEPT; ++j) {
+          const uint32_t e = e0 + j;
+          if (e >= eb && e < ee) cand[j] = sat_add(ld_shared<M>(din + u[j]), wt[j]);
+        }
+      }
+      if (nv == 1) {
+        uint32_t p = kInf;
+#pragma unroll
+        for (int j = 0; j < kEPT; ++j) p = cand[j] < p ? cand[j] : p;
+        p = wave_min(p);
+        if (lane == 0 && p != kInf) atomicMin(&s_acc[0], p);
+      } else if (active) {
+        const uint32_t es = e0 > eb ? e0 : eb;
+        const uint32_t en = (e0 + kEPT < ee) ? e0 + kEPT : ee;
+        uint32_t i = owner_of(s_ptr, nv, es);
+        uint32_t bound = s_ptr[i + 1];
+        uint32_t part = kInf;
+#pragma unroll
+        for (int j = 0; j < kEPT; ++j) {
+          const uint32_t e = e0 + j;
+          if (e >= es && e < en) {
+            if (e >= bound) {
+              if (part != kInf) atomicMin(&s_acc[i], part);
+              part = kInf;
+              do { ++i; bound = s_ptr[i + 1]; } while (e >= bound);
+            }
+            part = cand[j] < part ? cand[j] : part;
+          }
+        }
+        if (part != kInf) atomicMin(&s_acc[i], part);
+      }
+    }
+    __syncthreads();
+    if (tid < nv) {
+      const uint32_t v = v0 + tid;
+      const uint32_t old = ld_shared<M>(din + v);
+      const uint32_t best = s_acc[tid];
+      const uint32_t nw = best < old ? best : old;
+      any |= (nw < old);
+      if constexpr (M == kSync) {
+        dout[v] = nw;
+      } else if constexpr (M == kAsync) {
+        st_agent(dout + v, nw);
+      } else {
+        s_stage[staged + tid] = nw;
+      }
+    }
+    if constexpr (M == kDelayed) {
+      staged += nv;
+      const bool last = (t + 1 == t1);
+      const uint32_t next_nv = last ? 0u : a.g.tile_v[t + 2] - v1;
+      if (last || staged >= a.d || staged + next_nv > a.cap) {
+        __syncthreads();
+        for (uint32_t i = tid; i < staged; i += kWG) st_agent(dout + stage_v0 + i, s_stage[i]);
+        stage_v0 += staged;
+        staged = 0;
+      }
+    }
+    __syncthreads();
+  }
+  if (__syncthreads_or(any) && tid == 0) st_agent(a.st.changed + k + 1, 1u);
+}
+
+__global__ __launch_bounds__(kWG) void bf_init_kernel(uint32_t* d0, uint32_t* d1, uint32_t n, uint32_t src,
+                                                      SweepState st, uint32_t S) {
+  const uint32_t i = blockIdx.x * kWG + threadIdx.x;
+  if (i < n) {
+    const uint32_t v = (i == src) ? 0u : kInf;
+    d0[i] = v;
+    if (d1) d1[i] = v;
+  }
+  if (i <= S) {
+    st.resid[i] = 0.0;
+    st.dang[i] = 0.0;
+    st.count[i] = 0;
+    st.changed[i] = (i == 0) ? 1u : 0u;
+  }
+}
+
+// ----------------------------------------------------------- normalisation --
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void sum_blocks_kernel(const T* x, uint32_t n, double* part) {
+  __shared__ double s[kWG / 64];
+  double acc = 0.0;
+  for (uint32_t i = blockIdx.x * kWG + threadIdx.x; i < n; i += gridDim.x * kWG) acc += (double)x[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63u) == 0) s[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+}
+
+__global__ __launch_bounds__(kWG) void sum_partials_kernel(double* part, uint32_t nb) {
+  __shared__ double s[kWG / 64];
+  double acc = 0.0;
+  for (uint32_t i = threadIdx.x; i < nb; i += kWG) acc += part[i];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63u) == 0) s[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[nb] = s[0] + s[1] + s[2] + s[3];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void scale_kernel(const T* x, uint32_t n, const double* total, double* out) {
+  const uint32_t i = blockIdx.x * kWG + threadIdx.x;
+  if (i < n) out[i] = (double)x[i] / *total;
+}
+
+inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kWG - 1) / kWG); }
+
+template <int M, typename T>
+size_t pr_dyn_lds(const PrArgs& a) {
+  return M == kDelayed ? (size_t)a.cap * sizeof(T) : 0;
+}
+
+}  // namespace
+
+hipError_t launch_pr_init(bool f64, void* x, void* c0, void* c1, const uint32_t* out_deg, uint32_t n,
+                          SweepState st, uint32_t S, double d0, hipStream_t s) {
+  const uint32_t nb = blocks_for((uint64_t)(n > S + 1 ? n : S + 1));
+  if (f64) {
+    pr_init_kernel<double><<<nb, kWG, 0, s>>>(static_cast<double*>(x), static_cast<double*>(c0),
+                                              static_cast<double*>(c1), out_deg, n, st, S, d0);
+  } else {
+    pr_init_kernel<float><<<nb, kWG, 0, s>>>(static_cast<float*>(x), static_cast<float*>(c0),
+                                             static_cast<float*>(c1), out_deg, n, st, S, d0);
+  }
+  return hipGetLastError();
+}
+
+template <int M, typename T>
+static void pr_sweep_go(const PrArgs& a, hipStream_t s) {
+  pr_sweep_kernel<M, T><<<a.g.P, kWG, pr_dyn_lds<M, T>(a), s>>>(a);
+}
+
+hipError_t launch_pr_sweep(int mode, bool f64, const PrArgs& a, hipStream_t s) {
+  if (f64) {
+    if (mode == kSync) pr_sweep_go<kSync, double>(a, s);
+    else if (mode == kAsync) pr_sweep_go<kAsync, double>(a, s);
+    else pr_sweep_go<kDelayed, double>(a, s);
+  } else {
+    if (mode == kSync) pr_sweep_go<kSync, float>(a, s);
+    else if (mode == kAsync) pr_sweep_go<kAsync, float>(a, s);
+    else pr_sweep_go<kDelayed, float>(a, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bf_init(uint32_t* d0, uint32_t* d1, uint32_t n, uint32_t src, SweepState st, uint32_t S,
+                          hipStream_t s) {
+  const uint32_t nb = blocks_for((uint64_t)(n > S + 1 ? n : S + 1));
+  bf_init_kernel<<<nb, kWG, 0, s>>>(d0, d1, n, src, st, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_bf_sweep(int mode, const BfArgs& a, hipStream_t s) {
+  const size_t lds = mode == kDelayed ? (size_t)a.cap * sizeof(uint32_t) : 0;
+  if (mode == kSync) bf_sweep_kernel<kSync><<<a.g.P, kWG, 0, s>>>(a);
+  else if (mode == kAsync) bf_sweep_kernel<kAsync><<<a.g.P, kWG, 0, s>>>(a);
+  else bf_sweep_kernel<kDelayed><<<a.g.P, kWG, lds, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(bool f64, const void* x, uint32_t n, double* out, double* scratch, hipStream_t s) {
+  const uint32_t nb = kNormBlocks;
+  if (f64) {
+    sum_blocks_kernel<double><<<nb, kWG, 0, s>>>(static_cast<const double*>(x), n, scratch);
+  } else {
+    sum_blocks_kernel<float><<<nb, kWG, 0, s>>>(static_cast<const float*>(x), n, scratch);
+  }
+  sum_partials_kernel<<<1, kWG, 0, s>>>(scratch, nb);
+  if (f64) {
+    scale_kernel<double><<<blocks_for(n), kWG, 0, s>>>(static_cast<const double*>(x), n, scratch + nb, out);
+  } else {
+    scale_kernel<float><<<blocks_for(n), kWG, 0, s>>>(static_cast<const float*>(x), n, scratch + nb, out);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace dg

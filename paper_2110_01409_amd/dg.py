@@ -1,0 +1,264 @@
+"""Python binding of the C ABI in include/dg.h (argument marshalling only).
+
+The functions ``dg_graph_create``, ``dg_graph_destroy``, ``dg_graph_info_get``,
+``dg_pagerank``, ``dg_sssp``, ``dg_set_allocator``, ``dg_status_str``,
+``dg_last_error`` and ``dg_version`` are the C entry points, loaded with
+ctypes from the in-tree ``libdg.so``.  Every step of a sweep runs in the HIP
+library; PyTorch only provides device memory (its caching allocator is
+registered as the library's allocator) and the stream.
+
+``Graph`` wraps a handle with keyword defaults.  If the library is missing,
+importing this module raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdg.so")
+
+DG_OK, DG_ERR_INVALID_ARGUMENT, DG_ERR_OUT_OF_MEMORY, DG_ERR_DEVICE, DG_ERR_NOT_CONVERGED, DG_ERR_UNSUPPORTED = range(6)
+DG_SYNC, DG_ASYNC, DG_DELAYED = 0, 1, 2
+DG_CSR, DG_CSC = 0, 1
+DG_F32, DG_F64 = 0, 1
+DG_D_WHOLE = 0xFFFFFFFF
+DG_INF_DIST = 0xFFFFFFFF
+
+MODES = {"sync": DG_SYNC, "async": DG_ASYNC, "delayed": DG_DELAYED}
+DTYPES = {"f32": DG_F32, "f64": DG_F64}
+
+# Every symbol declared in include/dg.h.
+EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_info_get", "dg_pagerank",
+           "dg_sssp", "dg_status_str", "dg_last_error", "dg_version")
+
+
+class dg_stats(C.Structure):
+    _fields_ = [("sweeps", C.c_uint32), ("workers", C.c_uint32), ("tile_vertices", C.c_uint32),
+                ("commit_interval", C.c_uint32), ("residual", C.c_double), ("seconds", C.c_double),
+                ("edges_traversed", C.c_uint64)]
+
+
+class dg_graph_info(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("m", C.c_uint64), ("workers", C.c_uint32), ("tiles", C.c_uint32),
+                ("max_in_degree", C.c_uint32), ("dangling", C.c_uint32), ("has_weights", C.c_uint32),
+                ("compute_units", C.c_uint32), ("device_bytes", C.c_uint64)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class DGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{status_str(status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2110_01409_amd.build` "
+                          "(or __graft_entry__.build()) first")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "dg_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, P]),
+        "dg_graph_create": (C.c_int, [C.c_uint32, C.c_uint64, C.c_int, P, P, P, P, C.POINTER(C.c_void_p)]),
+        "dg_graph_destroy": (C.c_int, [P]),
+        "dg_graph_info_get": (C.c_int, [P, C.POINTER(dg_graph_info)]),
+        "dg_pagerank": (C.c_int, [P, C.c_double, C.c_double, C.c_int, C.c_uint32, C.c_int, C.c_uint32, P, C.c_int,
+                                  C.POINTER(dg_stats), P]),
+        "dg_sssp": (C.c_int, [P, C.c_uint32, C.c_int, C.c_uint32, C.c_uint32, P, C.c_int, C.POINTER(dg_stats), P]),
+        "dg_status_str": (C.c_char_p, [C.c_int]),
+        "dg_last_error": (C.c_char_p, []),
+        "dg_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def status_str(s: int) -> str:
+    return lib.dg_status_str(s).decode()
+
+
+def last_error() -> str:
+    return lib.dg_last_error().decode()
+
+
+def version() -> str:
+    return lib.dg_version().decode()
+
+
+# Thin same-name wrappers of the C entry points.
+def dg_set_allocator(alloc, free_fn, ctx=None):
+    return lib.dg_set_allocator(alloc, free_fn, ctx)
+
+
+def dg_graph_create(n, m, layout, ptr, idx, w, stream, out):
+    return lib.dg_graph_create(n, m, layout, ptr, idx, w, stream, out)
+
+
+def dg_graph_destroy(g):
+    return lib.dg_graph_destroy(g)
+
+
+def dg_graph_info_get(g, info):
+    return lib.dg_graph_info_get(g, info)
+
+
+def dg_pagerank(g, damping, tol, mode, d, dtype, max_sweeps, out, out_on_device, stats, stream):
+    return lib.dg_pagerank(g, damping, tol, mode, d, dtype, max_sweeps, out, out_on_device, stats, stream)
+
+
+def dg_sssp(g, src, mode, d, max_sweeps, out, out_on_device, stats, stream):
+    return lib.dg_sssp(g, src, mode, d, max_sweeps, out, out_on_device, stats, stream)
+
+
+def _check(status, allow=()):
+    if status != DG_OK and status not in allow:
+        raise DGError(status, last_error())
+    return status
+
+
+# ------------------------------------------------------ torch as allocator --
+
+_torch_hooks = None
+
+
+def use_torch_allocator():
+    """Route the library's device allocations through torch's caching
+    allocator (idempotent)."""
+    global _torch_hooks
+    if _torch_hooks is not None:
+        return
+    import torch
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            dev = torch.cuda.current_device()
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+        except Exception:  # the library reports DG_ERR_OUT_OF_MEMORY
+            return None
+
+    def _free(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    hooks = (ALLOC_FN(_alloc), FREE_FN(_free))
+    _check(lib.dg_set_allocator(hooks[0], hooks[1], None))
+    _torch_hooks = hooks
+
+
+def _stream_handle(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+@dataclasses.dataclass
+class Stats:
+    sweeps: int
+    workers: int
+    tile_vertices: int
+    commit_interval: int
+    residual: float
+    seconds: float
+    edges_traversed: int
+    converged: bool
+
+    @property
+    def gteps(self) -> float:
+        return self.edges_traversed / self.seconds / 1e9 if self.seconds > 0 else float("nan")
+
+
+def _stats(s: dg_stats, converged: bool) -> Stats:
+    return Stats(s.sweeps, s.workers, s.tile_vertices, s.commit_interval, s.residual, s.seconds,
+                 s.edges_traversed, converged)
+
+
+class Graph:
+    """A graph resident in device memory.
+
+    ``Graph(n, ptr, idx, w=None, layout="csr")`` copies host arrays (ptr
+    uint64[n+1], idx uint32[m], w uint32[m] or None) to the device and builds
+    the in-edge form.  ``Graph.from_csr(g)`` takes a ``graphgen.CSRGraph``.
+    """
+
+    def __init__(self, n, ptr, idx, w=None, layout="csr", stream=None, torch_allocator=True):
+        ptr = np.ascontiguousarray(ptr, dtype=np.uint64)
+        idx = np.ascontiguousarray(idx, dtype=np.uint32)
+        wa = None if w is None else np.ascontiguousarray(w, dtype=np.uint32)
+        if torch_allocator:
+            use_torch_allocator()
+        h = C.c_void_p()
+        lay = DG_CSR if layout == "csr" else DG_CSC
+        _check(dg_graph_create(int(n), int(idx.shape[0]), lay, _np_ptr(ptr), _np_ptr(idx),
+                               None if wa is None else _np_ptr(wa), _stream_handle(stream), C.byref(h)))
+        self._h = h
+        self.n = int(n)
+        self.m = int(idx.shape[0])
+
+    @classmethod
+    def from_csr(cls, g, **kw):
+        return cls(g.n, g.ptr, g.idx, g.w, layout="csr", **kw)
+
+    def info(self) -> dg_graph_info:
+        inf = dg_graph_info()
+        _check(dg_graph_info_get(self._h, C.byref(inf)))
+        return inf
+
+    def pagerank(self, damping=0.85, tol=1e-6, mode="delayed", d=64, dtype="f32", max_sweeps=10_000,
+                 out=None, stream=None, allow_not_converged=False):
+        """Returns (scores float64 tensor on the device, Stats)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        st = dg_stats()
+        s = _check(dg_pagerank(self._h, float(damping), float(tol), MODES[mode], int(d), DTYPES[dtype],
+                               int(max_sweeps), C.c_void_p(out.data_ptr()), 1, C.byref(st),
+                               _stream_handle(stream)),
+                   allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+        return out, _stats(st, s == DG_OK)
+
+    def sssp(self, src, mode="delayed", d=64, max_sweeps=None, out=None, stream=None, allow_not_converged=False):
+        """Returns (distances uint32 tensor on the device, Stats)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.uint32, device="cuda")
+        if max_sweeps is None:
+            max_sweeps = min(self.n + 1, 1_000_000)
+        st = dg_stats()
+        s = _check(dg_sssp(self._h, int(src), MODES[mode], int(d), int(max_sweeps), C.c_void_p(out.data_ptr()), 1,
+                           C.byref(st), _stream_handle(stream)),
+                   allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+        return out, _stats(st, s == DG_OK)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            dg_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,108 @@
+"""The C-ABI library loads, exports every symbol include/dg.h declares, and
+validates arguments on the host before any HIP call (no GPU needed)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dg.h")
+
+
+@pytest.fixture(scope="module")
+def dg():
+    from paper_2110_01409_amd import dg as _dg
+    return _dg
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(dg_[a-z_]+)\s*\(", src))
+    return {n for n in names if not n.endswith("_fn")}
+
+
+def test_exports_match_header(dg):
+    declared = _declared()
+    assert declared == set(dg.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", dg.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (dg_[a-z_]+)\b", out))
+    missing = declared - exported
+    assert not missing, missing
+    for name in declared:
+        assert hasattr(dg.lib, name)
+
+
+def test_status_strings(dg):
+    for s in range(6):
+        assert dg.status_str(s).startswith("DG_")
+    assert "gfx950" in dg.version()
+
+
+def _create(dg, n, ptr, idx, w=None, layout=None):
+    h = C.c_void_p()
+    ptr = np.ascontiguousarray(ptr, np.uint64)
+    idx = np.ascontiguousarray(idx, np.uint32)
+    wp = None if w is None else dg._np_ptr(np.ascontiguousarray(w, np.uint32))
+    s = dg.dg_graph_create(n, idx.shape[0], dg.DG_CSR if layout is None else layout, dg._np_ptr(ptr),
+                           dg._np_ptr(idx), wp, None, C.byref(h))
+    return s, h
+
+
+@pytest.mark.parametrize("case", ["n0", "ptr0", "decreasing", "ptr_end", "idx_range", "layout", "null_ptr"])
+def test_create_validation(dg, case):
+    ptr = np.array([0, 1, 3, 3], np.uint64)
+    idx = np.array([1, 0, 2], np.uint32)
+    n = 3
+    layout = None
+    if case == "n0":
+        n = 0
+    elif case == "ptr0":
+        ptr = ptr + 1
+    elif case == "decreasing":
+        ptr = np.array([0, 2, 1, 3], np.uint64)
+    elif case == "ptr_end":
+        ptr = np.array([0, 1, 2, 2], np.uint64)
+    elif case == "idx_range":
+        idx = np.array([1, 0, 3], np.uint32)
+    elif case == "layout":
+        layout = 7
+    if case == "null_ptr":
+        h = C.c_void_p()
+        s = dg.dg_graph_create(3, 3, dg.DG_CSR, None, dg._np_ptr(idx), None, None, C.byref(h))
+    else:
+        s, h = _create(dg, n, ptr, idx, layout=layout)
+    assert s == dg.DG_ERR_INVALID_ARGUMENT
+    assert dg.last_error()
+    assert not h.value
+
+
+def test_valid_graph_without_device(dg):
+    """A well-formed graph passes validation; on a machine without a GPU the
+    call then fails cleanly with DG_ERR_DEVICE (with a GPU it succeeds)."""
+    import torch
+    s, h = _create(dg, 3, [0, 1, 3, 3], [1, 0, 2], [5, 6, 7])
+    if torch.cuda.is_available():
+        assert s == dg.DG_OK
+        dg.dg_graph_destroy(h)
+    else:
+        assert s == dg.DG_ERR_DEVICE and "device" in dg.last_error()
+
+
+def test_call_validation_null_graph(dg):
+    out = np.zeros(4, np.float64)
+    st = dg.dg_stats()
+    assert dg.dg_pagerank(None, 0.85, 1e-6, 0, 1, 0, 10, dg._np_ptr(out), 0, C.byref(st), None) == \
+        dg.DG_ERR_INVALID_ARGUMENT
+    assert dg.dg_sssp(None, 0, 0, 1, 10, dg._np_ptr(out), 0, C.byref(st), None) == dg.DG_ERR_INVALID_ARGUMENT
+    assert dg.dg_graph_destroy(None) == dg.DG_OK
+    assert dg.dg_graph_info_get(None, None) == dg.DG_ERR_INVALID_ARGUMENT
+
+
+def test_allocator_hooks_must_pair(dg):
+    alloc = dg.ALLOC_FN(lambda n, s, c: None)
+    assert dg.lib.dg_set_allocator(alloc, dg.FREE_FN(), None) == dg.DG_ERR_INVALID_ARGUMENT
+    assert dg.lib.dg_set_allocator(dg.ALLOC_FN(), dg.FREE_FN(), None) == dg.DG_OK

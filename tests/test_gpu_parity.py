@@ -1,0 +1,246 @@
+"""GPU parity of the HIP sweeps against the CPU oracle (needs an MI355X).
+
+Tolerances:
+* SSSP: bit-exact in every mode (integers).
+* PageRank: L1 distance to the oracle's float64 fixed point <= 1e-6 in every
+  mode and precision.  The stopping rule bounds the change of the last sweep,
+  not the error, so parity runs stop at tol = 1e-8 (f64) / 1e-7 (f32), where
+  the synchronous error bound alpha/(1-alpha)*tol stays below 1e-6.
+* Synchronous per-sweep iterates agree with the oracle's Jacobi iterates to
+  1e-13 relative L1 (float64; only the summation order differs).
+"""
+import ctypes as C
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+from oracle import pagerank as opr
+from oracle import sssp as osp
+from tests import graphs as tg
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+MODES = [("sync", 0), ("async", 0), ("delayed", 1), ("delayed", 64), ("delayed", 1024), ("delayed", 0xFFFFFFFF)]
+PR_TOL = {"f64": 1e-8, "f32": 1e-7}
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2110_01409_amd import dg as _dg
+    return _dg
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+_cache = {}
+
+
+def _graph(name):
+    if name not in _cache:
+        if name == "rmat10":
+            g = gg.rmat(10, seed=10)
+        elif name == "rmat14":
+            g = gg.rmat(14, seed=14)
+        elif name == "banded":
+            g = gg.banded(60_000, 16, 4096, 0.01, seed=3)
+        elif name == "er":
+            g = gg.erdos_renyi(30_001, 12, seed=5)
+        elif name == "instar":
+            g = tg.in_star(9000)
+        elif name == "multi":
+            g = tg.random_graph(3001, 20_000, 7, dedup=False)
+        else:
+            raise KeyError(name)
+        _cache[name] = (g, opr.pagerank_fixed_point(g))
+    return _cache[name]
+
+
+def _sources(g, k=2):
+    return gg.pick_sources(g, k, seed=1).tolist()
+
+
+def test_rmat10_golden_sync(dg):
+    """Small R-MAT against the stored oracle values: synchronous PageRank
+    float64 within 1e-6 (and sweep count within one of the oracle's, the only
+    difference being summation order at the threshold), synchronous
+    Bellman-Ford bit-exact with the exact sweep count."""
+    with open(os.path.join(HERE, "golden", "rmat10_seed10.json")) as f:
+        gold = json.load(f)
+    g = gg.rmat(10, seed=10)
+    assert g.sha256() == gold["sha256"]
+    G = dg.Graph.from_csr(g)
+    x, st = G.pagerank(tol=1e-7, mode="sync", dtype="f64")
+    assert np.abs(_np(x) - np.array(gold["pagerank_fixed_point"])).sum() <= 1e-6
+    assert abs(st.sweeps - gold["pagerank_sync_sweeps_tol1e-7"]) <= 1
+    d, st = G.sssp(0, mode="sync")
+    np.testing.assert_array_equal(_np(d), np.array(gold["sssp_dist"], dtype=np.uint32))
+    assert st.sweeps == gold["sssp_sync_sweeps"]
+    G.close()
+
+
+@pytest.mark.parametrize("name", ["rmat10", "rmat14", "banded", "er", "instar", "multi"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_pagerank_all_modes(dg, name, dtype):
+    g, xs = _graph(name)
+    G = dg.Graph.from_csr(g)
+    for mode, d in MODES:
+        x, st = G.pagerank(tol=PR_TOL[dtype], mode=mode, d=max(d, 1), dtype=dtype, max_sweeps=2000)
+        xv = _np(x)
+        err = np.abs(xv - xs).sum()
+        assert err <= 1e-6, (name, dtype, mode, d, err, st)
+        assert abs(xv.sum() - 1.0) < 1e-12
+        assert st.converged and st.sweeps >= 1
+        print(f"{name} {dtype} {mode:7s} d={d:<10d} sweeps={st.sweeps:3d} err={err:.2e}")
+    G.close()
+
+
+@pytest.mark.parametrize("name", ["rmat10", "rmat14", "banded", "er", "instar", "multi"])
+def test_sssp_all_modes_bit_exact(dg, name):
+    g, _ = _graph(name)
+    G = dg.Graph.from_csr(g)
+    for src in _sources(g):
+        ref, ref_sweeps, _ = osp.bellman_ford_sync(g, src)
+        for mode, d in MODES:
+            dist, st = G.sssp(src, mode=mode, d=max(d, 1))
+            np.testing.assert_array_equal(_np(dist), ref, err_msg=f"{name} src={src} {mode} d={d}")
+            assert st.converged
+            if mode == "sync":
+                assert st.sweeps == ref_sweeps
+            else:
+                assert st.sweeps <= ref_sweeps  # never staler than synchronous
+    G.close()
+
+
+def test_sync_per_sweep_iterates(dg):
+    """Synchronous sweeps reproduce the oracle's Jacobi iterates one by one
+    (PageRank float64 to 1e-13 relative L1, Bellman-Ford bit-exact)."""
+    g, _ = _graph("rmat14")
+    G = dg.Graph.from_csr(g)
+    _, _, _, its = opr.pagerank_jacobi(g, tol=0.0, max_sweeps=6, keep_iterates=True)
+    for k in range(1, 7):
+        x, st = G.pagerank(tol=0.0, mode="sync", dtype="f64", max_sweeps=k, allow_not_converged=True)
+        assert st.sweeps == k and not st.converged
+        ref = its[k - 1] / its[k - 1].sum()
+        assert np.abs(_np(x) - ref).sum() <= 1e-13 * np.abs(ref).sum()
+    src = _sources(g, 1)[0]
+    _, _, bits = osp.bellman_ford_sync(g, src, keep_iterates=True)
+    for k in range(1, min(len(bits), 8) + 1):
+        d, st = G.sssp(src, mode="sync", max_sweeps=k, allow_not_converged=True)
+        np.testing.assert_array_equal(_np(d), bits[k - 1])
+    G.close()
+
+
+@pytest.mark.parametrize("n", [3000, 20_000])
+def test_path_graph_visibility(dg, n):
+    """Path 0 -> ... -> n-1: synchronous needs exactly n sweeps; asynchronous
+    and delayed commits propagate inside a sweep, so they need far fewer."""
+    g = gg.path_graph(n, weight=2)
+    G = dg.Graph.from_csr(g)
+    ref = (2 * np.arange(n)).astype(np.uint32)
+    d, st = G.sssp(0, mode="sync")
+    np.testing.assert_array_equal(_np(d), ref)
+    assert st.sweeps == n
+    for mode, dd in [("async", 1), ("delayed", 1), ("delayed", 64)]:
+        d, st = G.sssp(0, mode=mode, d=dd)
+        np.testing.assert_array_equal(_np(d), ref)
+        print(f"path{n} {mode} d={dd}: {st.sweeps} sweeps")
+        assert st.sweeps < n // 4
+    G.close()
+
+
+def test_edge_cases(dg):
+    """Single vertex, edgeless graph, self-loop only, hub beyond one chunk,
+    unreachable vertices, NOT_CONVERGED, host outputs through the raw ABI."""
+    # one vertex, no edge: score 1, distance 0
+    G = dg.Graph(1, np.array([0, 0], np.uint64), np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    for mode, d in MODES:
+        x, st = G.pagerank(mode=mode, d=max(d, 1), dtype="f64")
+        assert abs(_np(x)[0] - 1.0) < 1e-15
+        dist, _ = G.sssp(0, mode=mode, d=max(d, 1))
+        assert _np(dist)[0] == 0
+    G.close()
+    # self-loop only
+    G = dg.Graph(1, np.array([0, 1], np.uint64), np.zeros(1, np.uint32), np.array([9], np.uint32))
+    x, _ = G.pagerank(dtype="f64")
+    assert abs(_np(x)[0] - 1.0) < 1e-15
+    G.close()
+    # edgeless graph: all dangling -> uniform
+    n = 777
+    G = dg.Graph(n, np.zeros(n + 1, np.uint64), np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    for mode, d in MODES:
+        x, _ = G.pagerank(mode=mode, d=max(d, 1), dtype="f32")
+        assert np.abs(_np(x) - 1.0 / n).max() < 1e-12
+        dist, _ = G.sssp(5, mode=mode, d=max(d, 1))
+        dv = _np(dist)
+        assert dv[5] == 0 and (np.delete(dv, 5) == dg.DG_INF_DIST).all()
+    G.close()
+    # NOT_CONVERGED keeps the last iterate and stats
+    g, xs = _graph("rmat10")
+    G = dg.Graph.from_csr(g)
+    with pytest.raises(dg.DGError) as ei:
+        G.pagerank(tol=1e-12, max_sweeps=2)
+    assert ei.value.status == dg.DG_ERR_NOT_CONVERGED
+    x, st = G.pagerank(tol=1e-12, max_sweeps=2, allow_not_converged=True)
+    assert st.sweeps == 2 and not st.converged
+    # host output pointers through the raw C ABI
+    out = np.zeros(g.n, np.float64)
+    stats = dg.dg_stats()
+    s = dg.dg_pagerank(G._h, 0.85, 1e-8, dg.DG_DELAYED, 64, dg.DG_F64, 1000, dg._np_ptr(out), 0,
+                       C.byref(stats), None)
+    assert s == dg.DG_OK and np.abs(out - xs).sum() < 1e-6
+    dout = np.zeros(g.n, np.uint32)
+    s = dg.dg_sssp(G._h, 0, dg.DG_ASYNC, 1, 5000, dg._np_ptr(dout), 0, C.byref(stats), None)
+    assert s == dg.DG_OK
+    np.testing.assert_array_equal(dout, osp.bellman_ford_sync(g, 0)[0])
+    # validation on a live handle leaves outputs untouched
+    s = dg.dg_sssp(G._h, g.n, dg.DG_SYNC, 1, 10, dg._np_ptr(dout), 0, None, None)
+    assert s == dg.DG_ERR_INVALID_ARGUMENT
+    s = dg.dg_pagerank(G._h, 1.0, 1e-6, dg.DG_SYNC, 1, dg.DG_F32, 10, dg._np_ptr(out), 0, None, None)
+    assert s == dg.DG_ERR_INVALID_ARGUMENT
+    s = dg.dg_pagerank(G._h, 0.85, 1e-6, dg.DG_DELAYED, 0, dg.DG_F32, 10, dg._np_ptr(out), 0, None, None)
+    assert s == dg.DG_ERR_INVALID_ARGUMENT
+    G.close()
+    # PageRank-only graph refuses SSSP
+    Gn = dg.Graph(g.n, g.ptr, g.idx, None)
+    with pytest.raises(dg.DGError):
+        Gn.sssp(0)
+    Gn.close()
+
+
+def test_csc_input_matches_csr(dg):
+    """The same graph handed over as in-edges gives the same answers."""
+    g, xs = _graph("rmat10")
+    src = np.repeat(np.arange(g.n), np.diff(g.ptr.astype(np.int64)))
+    order = np.lexsort((src, g.idx))
+    cptr = np.zeros(g.n + 1, np.uint64)
+    np.cumsum(np.bincount(g.idx, minlength=g.n), out=cptr[1:])
+    G = dg.Graph(g.n, cptr, src[order].astype(np.uint32), g.w[order], layout="csc")
+    x, _ = G.pagerank(tol=1e-8, mode="async", dtype="f64")
+    assert np.abs(_np(x) - xs).sum() < 1e-6
+    d, _ = G.sssp(3, mode="delayed", d=64)
+    np.testing.assert_array_equal(_np(d), osp.bellman_ford_sync(g, 3)[0])
+    G.close()
+
+
+def test_repeatability_async(dg):
+    """Asynchronous results vary run to run only within tolerance (PageRank)
+    and not at all (SSSP)."""
+    g, xs = _graph("rmat14")
+    G = dg.Graph.from_csr(g)
+    src = _sources(g, 1)[0]
+    ref = osp.bellman_ford_sync(g, src)[0]
+    for _ in range(5):
+        x, _ = G.pagerank(tol=1e-7, mode="async", dtype="f32")
+        assert np.abs(_np(x) - xs).sum() <= 1e-6
+        d, _ = G.sssp(src, mode="delayed", d=1)
+        np.testing.assert_array_equal(_np(d), ref)
+    G.close()
