@@ -1,0 +1,243 @@
+"""Benchmark: GTEPS and time to convergence of delayed vs synchronous vs
+asynchronous PageRank and Bellman-Ford sweeps on one MI355X.
+
+Workload (synthetic, generated in-process from a fixed seed): R-MAT scale 22,
+edge factor 16, a/b/c/d = 0.57/0.19/0.19/0.05, ids permuted, directed,
+duplicates removed, uint32 weights uniform in [1, 255] (seed 22).  It stands in
+for the paper's Kron graph, which is not available here.
+
+One step = one PageRank (float32 scores, damping 0.85, tol 1e-6, delayed
+commits) plus one Bellman-Ford SSSP (delayed commits) from the next of 16
+sources, both run to convergence on the device-resident graph.  ``value`` is
+edges traversed (m x sweeps, summed over both) divided by the wall time of
+the timed steps.
+
+Besides the JSON line's required fields it reports, per commit mode, sweeps,
+time to convergence and GTEPS for PageRank float32 / float64 and SSSP; the
+roofline of the dominant kernel (the float32 delayed PageRank sweep) from
+event timing on the library's stream; and the CPU oracle's throughput on a
+bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = ("rmat22: R-MAT scale 22, edge factor 16, a/b/c/d .57/.19/.19/.05, ids permuted, directed, "
+            "duplicates removed, uint32 weights U[1,255], seed 22")
+KERNEL_SRC = os.path.join(ROOT, "paper_2110_01409_amd", "csrc", "sweep_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pr_sweep_f32_delayed_rmat22_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def pr_bytes_per_sweep(n, m, dtype):
+    """Algorithmic bytes of one PageRank sweep: per edge the 4-byte source
+    index and one gathered contribution; per vertex the 4-byte offset, the
+    out-degree, the old score read, the new score and contribution written."""
+    e = 4 if dtype == "f32" else 8
+    return m * (4 + e) + n * (4 + 4 + 3 * e)
+
+
+def bf_bytes_per_sweep(n, m):
+    """Per edge: 4-byte source index, 4-byte weight, 4-byte gathered distance;
+    per vertex: 4-byte offset, old distance read, new distance written."""
+    return m * 12 + n * 12
+
+
+def cpu_baseline(g, budget_s=15.0):
+    """The oracle's synchronous float64 PageRank sweep, timed on the host on
+    the same graph for as many sweeps as fit the budget."""
+    from oracle import pagerank as opr
+    src, dst = opr.edge_list(g)
+    deg = opr.out_degree(g)
+    x = np.full(g.n, 1.0 / g.n)
+    sweeps = 0
+    t0 = time.perf_counter()
+    while True:
+        x = opr.apply_T(x, src, dst, deg)
+        sweeps += 1
+        if time.perf_counter() - t0 > budget_s or sweeps >= 50:
+            break
+    dt = time.perf_counter() - t0
+    return {
+        "value": g.m * sweeps / dt / 1e9,
+        "unit": "GTEPS",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{sweeps} synchronous float64 PageRank sweeps of the numpy oracle on the same rmat22 graph "
+                  f"({dt:.1f} s; numpy gather/bincount run single-threaded)",
+        "seconds_per_sweep": dt / sweeps,
+        "host_cpus_available": len(os.sched_getaffinity(0)),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--d", type=int, default=64, help="commit interval of the headline delayed mode")
+    ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-modes", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see the sharding note in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import graphgen as gg
+    from paper_2110_01409_amd import dg
+
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    g = gg.rmat(args.scale, seed=args.scale)
+    log(f"generated rmat{args.scale}: n={g.n} m={g.m} in {time.perf_counter() - t:.1f}s")
+    sources = gg.pick_sources(g, 16, seed=args.scale).tolist()
+    t = time.perf_counter()
+    G = dg.Graph.from_csr(g)
+    info = G.info()
+    log(f"uploaded in {time.perf_counter() - t:.1f}s: workers={info.workers} tiles={info.tiles} "
+        f"max_in_degree={info.max_in_degree} dangling={info.dangling}")
+    n, m = g.n, g.m
+
+    def step(i):
+        _, sp = G.pagerank(damping=0.85, tol=1e-6, mode="delayed", d=args.d, dtype="f32")
+        _, sb = G.sssp(sources[i % len(sources)], mode="delayed", d=args.d)
+        return sp, sb
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    edges = 0
+    pr_sweeps, bf_sweeps = [], []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        sp, sb = step(i)
+        edges += sp.edges_traversed + sb.edges_traversed
+        pr_sweeps.append(sp.sweeps)
+        bf_sweeps.append(sb.sweeps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = edges / wall / 1e9
+    log(f"timed {args.steps} steps: {wall * 1e3 / args.steps:.2f} ms/step, {value:.1f} GTEPS, "
+        f"PR sweeps {pr_sweeps}, SSSP sweeps {bf_sweeps}")
+
+    # Roofline of the dominant kernel: float32 delayed PageRank sweeps, timed by
+    # the library's events on its stream over a fixed number of sweeps.
+    K = 40
+    G.pagerank(tol=0.0, mode="delayed", d=args.d, dtype="f32", max_sweeps=K, allow_not_converged=True)
+    _, rs = G.pagerank(tol=0.0, mode="delayed", d=args.d, dtype="f32", max_sweeps=K, allow_not_converged=True)
+    t_sweep = rs.seconds / rs.sweeps
+    algo = pr_bytes_per_sweep(n, m, "f32")
+    achieved = algo / t_sweep / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_sha256_16") == kernel_hash() and tr.get("n") == n and tr.get("m") == m:
+            traffic = tr.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "pr_sweep_kernel<delayed, float>", "algorithmic_bytes_per_launch": algo,
+                "avg_launch_us": round(t_sweep * 1e6, 2)}
+    log(f"roofline: {t_sweep * 1e6:.1f} us/sweep, {achieved:.0f} GB/s algorithmic = "
+        f"{100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s")
+
+    modes = {}
+    if not args.no_modes:
+        ref, _ = G.pagerank(tol=1e-10, mode="sync", dtype="f64", max_sweeps=5000)
+        table = [("sync", 0), ("async", 0), ("delayed", 1), ("delayed", 64), ("delayed", 1024),
+                 ("delayed", dg.DG_D_WHOLE)]
+        for mode, d in table:
+            key = mode if mode != "delayed" else f"delayed_d{'whole' if d == dg.DG_D_WHOLE else d}"
+            row = {}
+            for dtype in ("f32", "f64"):
+                runs = []
+                for _ in range(3):
+                    x, s = G.pagerank(tol=1e-6, mode=mode, d=max(d, 1), dtype=dtype)
+                    runs.append(s)
+                err = float((x - ref).abs().sum())
+                best = min(runs, key=lambda r: r.seconds)
+                row[f"pagerank_{dtype}"] = {
+                    "sweeps": [r.sweeps for r in runs], "t_conv_ms": round(best.seconds * 1e3, 3),
+                    "t_sweep_us": round(best.seconds / best.sweeps * 1e6, 2), "gteps": round(best.gteps, 1),
+                    "l1_vs_f64_tol1e-10": err,
+                    "hbm_frac_algorithmic": round(pr_bytes_per_sweep(n, m, dtype) * best.sweeps / best.seconds
+                                                  / 1e9 / HBM_PEAK_GBS, 4)}
+            tot_t, tot_s, sw = 0.0, 0, []
+            for src in sources:
+                _, s = G.sssp(src, mode=mode, d=max(d, 1))
+                tot_t += s.seconds
+                tot_s += s.sweeps
+                sw.append(s.sweeps)
+            row["sssp_16_sources"] = {"sweeps": sw, "t_conv_ms_total": round(tot_t * 1e3, 3),
+                                      "gteps": round(m * tot_s / tot_t / 1e9, 1),
+                                      "hbm_frac_algorithmic": round(bf_bytes_per_sweep(n, m) * tot_s / tot_t
+                                                                    / 1e9 / HBM_PEAK_GBS, 4)}
+            modes[key] = row
+            log(f"{key:16s} PR f32 {row['pagerank_f32']['sweeps']} {row['pagerank_f32']['t_conv_ms']} ms "
+                f"({row['pagerank_f32']['gteps']} GTEPS, err {row['pagerank_f32']['l1_vs_f64_tol1e-10']:.1e}) | "
+                f"PR f64 {row['pagerank_f64']['sweeps']} {row['pagerank_f64']['t_conv_ms']} ms | "
+                f"SSSP {row['sssp_16_sources']['t_conv_ms_total']} ms total, {row['sssp_16_sources']['gteps']} GTEPS")
+        sync_pr = modes["sync"]["pagerank_f32"]["t_conv_ms"]
+        sync_bf = modes["sync"]["sssp_16_sources"]["t_conv_ms_total"]
+        for key, row in modes.items():
+            row["speedup_vs_sync_pagerank_f32"] = round(sync_pr / row["pagerank_f32"]["t_conv_ms"], 3)
+            row["speedup_vs_sync_sssp"] = round(sync_bf / row["sssp_16_sources"]["t_conv_ms_total"], 3)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(g)
+        log(f"cpu baseline (oracle): {cpu['value']:.4f} GTEPS on {cpu['cores']} core(s)")
+
+    out = {
+        "metric": "GTEPS and time-to-convergence, RMAT-22 PageRank/SSSP, delayed vs sync vs async",
+        "value": round(value, 2),
+        "unit": "GTEPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 scores (f64 accumulation) + u32 distances",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "n": n, "m": m,
+                   "step": f"PageRank f32 delayed d={args.d} tol 1e-6 damping 0.85 + SSSP delayed d={args.d} "
+                           "from one of 16 sources (u32 weights)",
+                   "pagerank_sweeps": pr_sweeps, "sssp_sweeps": bf_sweeps, "workers": info.workers,
+                   "tiles": info.tiles},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "modes": modes,
+    }
+    G.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -138,7 +138,7 @@ dg_status dg_graph_destroy(dg_graph* g);
 dg_status dg_graph_info_get(const dg_graph* g, dg_graph_info* info);
 
 /* PageRank by repeated pull sweeps (sections III and IV-A).
- *   damping     0 <= damping < 1 (0.85 in the paper's evaluation setup)
+ *   damping     0 <= damping < 1 (0.85 is the customary value)
  *   tol         stop after the first sweep whose L1 score change is < tol
  *               (the paper's stopping rule with a threshold); tol >= 0, finite;
  *               tol = 0 runs exactly max_sweeps sweeps
@@ -149,8 +149,13 @@ dg_status dg_graph_info_get(const dg_graph* g, dg_graph_info* info);
  *   out_scores  n float64 scores normalised to sum 1; device memory when
  *               out_on_device != 0, else host memory
  *   stats       may be NULL
- * Scores start at 1/n; the mass of dangling vertices (out-degree 0) is spread
- * evenly over all vertices, using the value measured in the previous sweep.
+ * Scores start at 1/n.  The mass of dangling vertices (out-degree 0) is spread
+ * evenly over all vertices; a sweep spreads 1 minus the mass the non-dangling
+ * vertices held after the previous sweep, which equals the dangling mass when
+ * the scores sum to 1 (always, in synchronous mode) and also returns any mass
+ * an asynchronous sweep lost or gained.  The residual of a sweep is the sum
+ * over vertices of |new score - previous stored score|, the new score taken
+ * in float64 before rounding to the storage precision.
  * Returns NOT_CONVERGED (with out_scores and stats filled) when max_sweeps
  * sweeps ran without meeting the stopping rule. */
 dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uint32_t d,

@@ -21,9 +21,12 @@ interleaving is arbitrary, so this emulator is used for invariants that hold
 for every interleaving, never for exact sweep counts of a GPU run.
 
 PageRank publishes the contribution c_v = x_v / outdeg(v) (0 if dangling);
-the score x_v is private to its owner.  The dangling mass used in a sweep is
-the one measured in the previous sweep (reading R3 of the design notes); the
-residual of a vertex is its new score minus its previous score.
+the score x_v is private to its owner.  The mass a sweep spreads uniformly is
+measured in the previous sweep, either as the dangling mass itself
+(``spread="dangling"``) or as one minus the non-dangling mass
+(``spread="deficit"``, the form the GPU library uses); both equal the
+dangling mass whenever the scores sum to 1, so they give the same fixed
+point.  The residual of a vertex is its new score minus its previous score.
 """
 from __future__ import annotations
 
@@ -137,8 +140,11 @@ def sssp(g, source, mode=SYNC, delta=0, P=1, bounds=None, max_sweeps=None):
     return snaps[-1], sweeps, snaps
 
 
-def pagerank(g, mode=SYNC, delta=0, P=1, bounds=None, alpha=0.85, tol=1e-10, max_sweeps=10_000):
+def pagerank(g, mode=SYNC, delta=0, P=1, bounds=None, alpha=0.85, tol=1e-10, max_sweeps=10_000,
+             spread="dangling"):
     """PageRank under the emulated schedule.  Returns (x, sweeps, residuals)."""
+    if spread not in ("dangling", "deficit"):
+        raise ValueError("spread must be 'dangling' or 'deficit'")
     n = g.n
     bounds = bounds if bounds is not None else blocks_by_in_edges(g, P)
     ins, deg = _in_lists(g)
@@ -164,12 +170,15 @@ def pagerank(g, mode=SYNC, delta=0, P=1, bounds=None, alpha=0.85, tol=1e-10, max
         sweeps += 1
         r = 0.0
         D = 0.0
+        S = 0.0
         for v, xn in hist[0]:
             r += abs(xn - x[v])
             x[v] = xn
             if deg[v] == 0:
                 D += xn
-        state["D"] = D
+            else:
+                S += xn
+        state["D"] = D if spread == "dangling" else 1.0 - S
         residuals.append(r)
         if r < tol:
             break

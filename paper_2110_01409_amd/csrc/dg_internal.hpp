@@ -46,10 +46,10 @@ struct Topology {
 // earlier one already met the stopping rule.
 struct SweepState {
   double* resid;      // [S+1] resid[k+1] = L1 change of sweep k; resid[0] = +inf
-  double* dang;       // [S+1] dangling mass used by sweep k
+  double* dang;       // [S+1] mass sweep k spreads uniformly: 1 - non-dangling mass after sweep k-1
   uint32_t* count;    // [S+1] workers finished in sweep k
   uint32_t* changed;  // [S+1] changed[k+1] != 0 iff sweep k decreased a distance
-  double* part;       // [2P] per-worker partial sums (residual, dangling mass)
+  double* part;       // [2P] per-worker partial sums (residual, non-dangling mass)
 };
 
 struct PrArgs {

@@ -29,7 +29,7 @@
 //     committed by workgroups on other XCDs are seen within the same sweep
 //     (global reads, section III-C); synchronous gathers are plain cached
 //     loads.
-//   * Each worker reduces its residual / dangling mass (PageRank) or
+//   * Each worker reduces its residual / non-dangling mass (PageRank) or
 //     "changed" flag (Bellman-Ford) over its block; the last worker to finish
 //     sums the per-worker partials in worker order and publishes the values the
 //     next sweep reads, so termination is decided on the device.
@@ -116,12 +116,17 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
   const uint32_t w = worker_id(blockIdx.x, P);
   const double inv_n = 1.0 / (double)a.g.n;
   const double alpha = a.alpha;
+  // Mass spread uniformly over all vertices: one minus the mass the
+  // non-dangling vertices held after the previous sweep.  With total mass 1
+  // this is exactly the dangling mass; when an asynchronous sweep leaves the
+  // total off 1 it also returns the deficit, so the total-mass error mode
+  // decays at once instead of at rate alpha.  The fixed point is unchanged.
   const double base = (1.0 - alpha) * inv_n + alpha * a.st.dang[k] * inv_n;
   const T* cin = static_cast<const T*>(a.cin);
   T* cout = static_cast<T*>(a.cout);
   T* x = static_cast<T*>(a.x);
 
-  double r_loc = 0.0, d_loc = 0.0;
+  double r_loc = 0.0, nd_loc = 0.0;
   const uint32_t t0 = a.g.work_t[w], t1 = a.g.work_t[w + 1];
   uint32_t staged = 0;
   uint32_t stage_v0 = a.g.tile_v[t0];
@@ -179,12 +184,13 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
       const uint32_t v = v0 + tid;
       const double xn = base + alpha * s_acc[tid];
       const T xo = x[v];
-      const T xs = static_cast<T>(xn);
-      x[v] = xs;
+      x[v] = static_cast<T>(xn);
       const uint32_t dg = a.g.out_deg[v];
       const T cn = dg ? static_cast<T>(xn / (double)dg) : static_cast<T>(0);
-      r_loc += fabs((double)xs - (double)xo);
-      if (dg == 0) d_loc += xn;
+      // Change of the score: new value before rounding to storage minus the
+      // stored old value (in float64 both are the same value).
+      r_loc += fabs(xn - (double)xo);
+      if (dg != 0) nd_loc += xn;
       if constexpr (M == kSync) {
         cout[v] = cn;
       } else if constexpr (M == kAsync) {
@@ -209,10 +215,10 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
 
   // Worker partials, then the last worker folds them in worker order.
   r_loc = wave_sum(r_loc);
-  d_loc = wave_sum(d_loc);
+  nd_loc = wave_sum(nd_loc);
   if (lane == 0) {
     s_red[wv] = r_loc;
-    s_red[4 + wv] = d_loc;
+    s_red[4 + wv] = nd_loc;
   }
   __syncthreads();
   if (tid == 0) {
@@ -239,7 +245,7 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
     __syncthreads();
     if (tid == 0) {
       a.st.resid[k + 1] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
-      a.st.dang[k + 1] = s_red[4] + s_red[5] + s_red[6] + s_red[7];
+      a.st.dang[k + 1] = 1.0 - (s_red[4] + s_red[5] + s_red[6] + s_red[7]);
     }
   }
 }

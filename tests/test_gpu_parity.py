@@ -139,21 +139,61 @@ def test_sync_per_sweep_iterates(dg):
     G.close()
 
 
-@pytest.mark.parametrize("n", [3000, 20_000])
-def test_path_graph_visibility(dg, n):
-    """Path 0 -> ... -> n-1: synchronous needs exactly n sweeps; asynchronous
-    and delayed commits propagate inside a sweep, so they need far fewer."""
+def test_path_graph_sync_exact(dg):
+    """Path 0 -> ... -> n-1: synchronous needs exactly n sweeps (n-1 with
+    changes plus the confirming one); every mode is bit-exact.  A tile's
+    vertices are computed concurrently, so inside a tile even asynchronous
+    sweeps advance one hop at a time."""
+    n = 3000
     g = gg.path_graph(n, weight=2)
     G = dg.Graph.from_csr(g)
     ref = (2 * np.arange(n)).astype(np.uint32)
     d, st = G.sssp(0, mode="sync")
     np.testing.assert_array_equal(_np(d), ref)
     assert st.sweeps == n
-    for mode, dd in [("async", 1), ("delayed", 1), ("delayed", 64)]:
+    for mode, dd in [("async", 1), ("delayed", 1), ("delayed", 64), ("delayed", 0xFFFFFFFF)]:
         d, st = G.sssp(0, mode=mode, d=dd)
         np.testing.assert_array_equal(_np(d), ref)
-        print(f"path{n} {mode} d={dd}: {st.sweeps} sweeps")
-        assert st.sweeps < n // 4
+        assert st.sweeps <= n
+    G.close()
+
+
+def test_commit_visibility_tile_chain(dg):
+    """A chain whose consecutive vertices sit in consecutive tiles (vertex
+    256*i -> 256*(i+1), all other vertices isolated, so every tile holds 256
+    vertices and one chain vertex).  Each worker owns L/P consecutive tiles.
+
+    * sync: the chain advances one tile per sweep: exactly L sweeps;
+    * async and delayed with d <= 256: a value committed by tile k is read by
+      tile k+1 of the same worker in the same sweep, so a sweep advances the
+      chain through a whole worker block: about P sweeps;
+    * delayed with d = whole block: nothing is visible before the block
+      ends, so the chain again advances about one tile per sweep.
+    """
+    L = 32768
+    n = 256 * L
+    src = 256 * np.arange(L - 1, dtype=np.int64)
+    g = gg.from_edges(n, src, src + 256, w=np.ones(L - 1, np.uint32))
+    G = dg.Graph.from_csr(g)
+    info = G.info()
+    assert info.tiles == L
+    P = info.workers
+    ref = np.full(n, dg.DG_INF_DIST, np.uint32)
+    ref[256 * np.arange(L)] = np.arange(L)
+    d, st = G.sssp(0, mode="sync")
+    np.testing.assert_array_equal(_np(d), ref)
+    assert st.sweeps == L
+    res = {}
+    for mode, dd in [("async", 1), ("delayed", 1), ("delayed", 256), ("delayed", 1024), ("delayed", 0xFFFFFFFF)]:
+        d, st = G.sssp(0, mode=mode, d=dd)
+        np.testing.assert_array_equal(_np(d), ref)
+        res[(mode, dd)] = st.sweeps
+        print(f"tile chain L={L} P={P} {mode} d={dd}: {st.sweeps} sweeps")
+    assert res[("async", 1)] <= 2 * P + 2
+    assert res[("delayed", 1)] <= 2 * P + 2
+    assert res[("delayed", 256)] <= 2 * P + 2
+    assert res[("delayed", 1024)] > res[("delayed", 256)]
+    assert res[("delayed", 0xFFFFFFFF)] >= L // 4
     G.close()
 
 

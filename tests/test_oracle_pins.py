@@ -296,3 +296,18 @@ def _golden(name):
             k, v = line.split()[:2]
             vals[k] = float(v)
     return vals
+
+
+def test_schedule_deficit_spread():
+    """Spreading 1 - (non-dangling mass) instead of the dangling mass: the
+    synchronous schedule is unchanged sweep by sweep (scores always sum to 1
+    there), every mode reaches the same fixed point."""
+    g = tg.dangling_heavy(90, 4)
+    xs = opr.pagerank_dense(g)
+    _, s1, r1 = osch.pagerank(g, osch.SYNC, 0, P=3, tol=1e-10, spread="deficit")
+    _, s2, r2, _ = opr.pagerank_jacobi(g, tol=1e-10)
+    assert s1 == s2
+    np.testing.assert_allclose(r1, r2, rtol=1e-9, atol=1e-15)
+    for mode, delta in [(osch.ASYNC, 0), (osch.DELAYED, 5)]:
+        x, _, _ = osch.pagerank(g, mode, delta, P=4, tol=1e-12, spread="deficit")
+        assert np.abs(x / x.sum() - xs).sum() < 1e-9
