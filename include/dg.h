@@ -99,6 +99,8 @@ typedef struct {
   uint32_t dangling;   /* vertices with out-degree 0                       */
   uint32_t has_weights;
   uint32_t compute_units;
+  uint32_t hot_vertices; /* sources stored in the compact region            */
+  uint64_t hot_edges;    /* in-edges whose source is in the compact region  */
   uint64_t device_bytes; /* device memory held by the graph (not workspace) */
 } dg_graph_info;
 
@@ -111,6 +113,21 @@ typedef void* (*dg_alloc_fn)(size_t bytes, void* hip_stream, void* ctx);
 typedef void (*dg_free_fn)(void* ptr, void* hip_stream, void* ctx);
 dg_status dg_set_allocator(dg_alloc_fn alloc, dg_free_fn free_fn, void* ctx);
 
+/* Options of dg_graph_create (pass NULL for the defaults).
+ *   workers       persistent workgroups that own the contiguous vertex blocks;
+ *                 0 = automatic (8 per compute unit, at most one per tile)
+ *   hot_vertices  at most this many sources with the largest out-degree (and
+ *                 above-average out-degree) get their published value stored
+ *                 in a compact region after the n regular slots, so gathers
+ *                 from them hit in L2; ownership, blocks and commit points are
+ *                 unchanged, only the storage address moves.
+ *                 DG_HOT_AUTO = 524288, 0 = no compact region */
+#define DG_HOT_AUTO 0xFFFFFFFFu
+typedef struct {
+  uint32_t workers;
+  uint32_t hot_vertices;
+} dg_graph_opts;
+
 /* Upload a graph and build its in-edge form (pull sweeps need in-neighbours,
  * section III-A).
  *   n          vertices, 1 <= n <= 0xFFFFFFFE
@@ -121,6 +138,7 @@ dg_status dg_set_allocator(dg_alloc_fn alloc, dg_free_fn free_fn, void* ctx);
  *   idx        host array of m uint32 vertex ids, each < n
  *   w          host array of m uint32 edge weights, or NULL (PageRank only).
  *              Path lengths saturate at DG_INF_DIST.
+ *   opts       creation options, or NULL for the defaults
  * Duplicate edges are kept (PageRank counts multiplicity, SSSP takes the
  * minimum) and self-loops count in the out-degree.  The arrays are copied:
  * the caller keeps ownership and may free them when the call returns.  On
@@ -128,8 +146,8 @@ dg_status dg_set_allocator(dg_alloc_fn alloc, dg_free_fn free_fn, void* ctx);
  * Errors: INVALID_ARGUMENT (malformed arrays, NULL pointers), OUT_OF_MEMORY,
  * DEVICE. */
 dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr,
-                          const uint32_t* idx, const uint32_t* w, void* hip_stream,
-                          dg_graph** out);
+                          const uint32_t* idx, const uint32_t* w, const dg_graph_opts* opts,
+                          void* hip_stream, dg_graph** out);
 
 /* Release a graph and its workspace.  NULL is a no-op. */
 dg_status dg_graph_destroy(dg_graph* g);

@@ -49,6 +49,9 @@ struct dg_graph {
   uint64_t m = 0;
   bool has_w = false;
   uint32_t P = 0, T = 0, cus = 0, max_in_deg = 0, n_dangling = 0;
+  uint32_t K = 0;          // sources stored in the compact region
+  uint32_t max_block_v = 1;  // most vertices any worker owns
+  uint64_t hot_edges = 0;  // in-edges whose source is in the compact region
   size_t lds_per_block = 65536;
   // allocator captured at creation
   dg_alloc_fn alloc = nullptr;
@@ -58,10 +61,10 @@ struct dg_graph {
   std::vector<void*> owned;
   uint64_t graph_bytes = 0;
   // resident graph
-  uint32_t *in_ptr = nullptr, *in_src = nullptr, *in_w = nullptr, *out_deg = nullptr;
+  uint32_t *in_ptr = nullptr, *in_src = nullptr, *in_w = nullptr, *out_deg = nullptr, *cpos = nullptr;
   uint32_t *tile_v = nullptr, *work_t = nullptr;
   // workspace (grown on demand)
-  void* vals[3] = {nullptr, nullptr, nullptr};  // 8n bytes each
+  void* vals[3] = {nullptr, nullptr, nullptr};  // 8(n+K) bytes each
   double* norm = nullptr;                        // kNormBlocks + 1
   uint32_t ws_sweeps = 0;
   double *resid = nullptr, *dang = nullptr, *part = nullptr;
@@ -169,9 +172,10 @@ void build_workers(const std::vector<uint32_t>& in_ptr, const std::vector<uint32
 
 dg_status ensure_workspace(dg_graph* g, uint32_t S, hipStream_t s) {
   if (!g->vals[0]) {
+    const size_t bytes = ((size_t)g->n + g->K) * 8;
     for (auto& v : g->vals) {
-      v = dev_alloc(g, (size_t)g->n * 8, s);
-      if (!v) return fail(DG_ERR_OUT_OF_MEMORY, "workspace allocation of %zu bytes failed", (size_t)g->n * 8);
+      v = dev_alloc(g, bytes, s);
+      if (!v) return fail(DG_ERR_OUT_OF_MEMORY, "workspace allocation of %zu bytes failed", bytes);
     }
     g->norm = static_cast<double*>(dev_alloc(g, (kNormBlocks + 1) * sizeof(double), s));
     g->part = static_cast<double*>(dev_alloc(g, 2 * (size_t)g->P * sizeof(double), s));
@@ -211,6 +215,7 @@ Topology topo(const dg_graph* g) {
   t.in_src = g->in_src;
   t.in_w = g->in_w;
   t.out_deg = g->out_deg;
+  t.cpos = g->cpos;
   t.tile_v = g->tile_v;
   t.work_t = g->work_t;
   t.n = g->n;
@@ -236,15 +241,18 @@ dg_status check_mode(dg_mode mode, uint32_t d) {
   return DG_OK;
 }
 
-// Staging capacity in vertices for a commit interval d: room for d values
-// plus one more tile, bounded by the LDS a workgroup may allocate.
-void staging(const dg_graph* g, uint32_t d, size_t elem, uint32_t& cap, uint32_t& d_eff) {
-  const size_t static_lds = 6 * 1024;
-  size_t max_vals = (g->lds_per_block > static_lds ? g->lds_per_block - static_lds : 0) / elem;
-  if (max_vals < 2 * (size_t)kTileV) max_vals = 2 * (size_t)kTileV;
-  const uint32_t dmax = (uint32_t)(max_vals - kTileV);
-  d_eff = d < dmax ? d : dmax;
-  cap = d_eff + kTileV;
+// Staging for a commit interval d.  LDS holds d values plus one more tile
+// (each staged vertex keeps its value and the 4-byte slot it is committed
+// to) when that fits in kLdsStage bytes, which keeps eight workgroups per
+// compute unit; larger intervals stage in a global per-vertex shadow array.
+// Returns the LDS capacity (0 = global shadow) and the effective interval.
+constexpr size_t kLdsStage = 16 * 1024;
+void staging(const dg_graph* g, uint32_t d, size_t elem, uint32_t& cap, uint32_t& d_eff, bool& shadow) {
+  d_eff = std::min(d, g->max_block_v);
+  if (d_eff < 1) d_eff = 1;
+  const size_t need = ((size_t)d_eff + kTileV) * (elem + 4);
+  shadow = need > kLdsStage;
+  cap = shadow ? 0u : d_eff + kTileV;
 }
 
 // Convergence loop shared by both algorithms.  launch(k) enqueues sweep k;
@@ -346,7 +354,7 @@ dg_status dg_set_allocator(dg_alloc_fn alloc, dg_free_fn free_fn, void* ctx) {
 }
 
 dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
-                          const uint32_t* w, void* hip_stream, dg_graph** out) {
+                          const uint32_t* w, const dg_graph_opts* opts, void* hip_stream, dg_graph** out) {
   g_last_error.clear();
   if (!out) return fail(DG_ERR_INVALID_ARGUMENT, "out is NULL");
   if (n == 0 || n > 0xFFFFFFFEu) return fail(DG_ERR_INVALID_ARGUMENT, "n = %u outside [1, 2^32-2]", n);
@@ -362,6 +370,9 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
                                (unsigned long long)ptr[n], (unsigned long long)m);
   for (uint64_t e = 0; e < m; ++e)
     if (idx[e] >= n) return fail(DG_ERR_INVALID_ARGUMENT, "idx[%llu] = %u >= n", (unsigned long long)e, idx[e]);
+  const uint32_t want_workers = opts ? opts->workers : 0u;
+  uint32_t hot_max = (!opts || opts->hot_vertices == DG_HOT_AUTO) ? 524288u : opts->hot_vertices;
+  hot_max = std::min<uint32_t>(hot_max, 0xFFFFFFFEu - n);
 
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   dg_graph* g = new (std::nothrow) dg_graph;
@@ -377,31 +388,56 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
   g->m = m;
   g->has_w = (w != nullptr);
 
-  // In-edge form (stable counting sort: in-edges of a vertex by ascending source).
-  std::vector<uint32_t> in_ptr, in_src, in_w, out_deg, tile_v, work_t;
+  // In-edge form (stable counting sort: in-edges of a vertex by ascending
+  // source), with each source replaced by the slot of its published value.
+  std::vector<uint32_t> in_ptr, in_src, in_w, out_deg, cpos, tile_v, work_t;
   try {
     in_ptr.assign((size_t)n + 1, 0);
     in_src.assign((size_t)m + kEdgePad, 0);
     if (w) in_w.assign((size_t)m + kEdgePad, 0);
     out_deg.assign(n, 0);
     if (layout == DG_CSR) {
+      for (uint32_t u = 0; u < n; ++u) out_deg[u] = (uint32_t)(ptr[u + 1] - ptr[u]);
+    } else {
+      for (uint64_t e = 0; e < m; ++e) ++out_deg[idx[e]];
+    }
+    // Compact region: the sources with the largest above-average out-degree,
+    // laid out in vertex order.  Vertex order keeps each worker's hot
+    // vertices in one contiguous run of slots, so a commit dirties few cache
+    // lines of the region everybody gathers from (the reason the paper gives
+    // for blocked partitioning and line-sized buffers).
+    cpos.resize(n);
+    for (uint32_t v = 0; v < n; ++v) cpos[v] = v;
+    {
+      const double avg = (double)m / (double)n;
+      std::vector<uint32_t> cand;
+      for (uint32_t v = 0; v < n; ++v)
+        if (out_deg[v] > 1 && (double)out_deg[v] > avg) cand.push_back(v);
+      std::stable_sort(cand.begin(), cand.end(),
+                       [&](uint32_t a, uint32_t b) { return out_deg[a] > out_deg[b]; });
+      g->K = (uint32_t)std::min<size_t>(cand.size(), hot_max);
+      cand.resize(g->K);
+      std::sort(cand.begin(), cand.end());
+      for (uint32_t r = 0; r < g->K; ++r) {
+        cpos[cand[r]] = n + r;
+        g->hot_edges += out_deg[cand[r]];
+      }
+    }
+    if (layout == DG_CSR) {
       for (uint64_t e = 0; e < m; ++e) ++in_ptr[idx[e] + 1];
       for (uint32_t v = 0; v < n; ++v) in_ptr[v + 1] += in_ptr[v];
       std::vector<uint32_t> pos(in_ptr.begin(), in_ptr.end() - 1);
       for (uint32_t u = 0; u < n; ++u) {
-        out_deg[u] = (uint32_t)(ptr[u + 1] - ptr[u]);
+        const uint32_t slot = cpos[u];
         for (uint64_t e = ptr[u]; e < ptr[u + 1]; ++e) {
           const uint32_t p = pos[idx[e]]++;
-          in_src[p] = u;
+          in_src[p] = slot;
           if (w) in_w[p] = w[e];
         }
       }
     } else {
       for (uint32_t v = 0; v <= n; ++v) in_ptr[v] = (uint32_t)ptr[v];
-      for (uint64_t e = 0; e < m; ++e) {
-        in_src[e] = idx[e];
-        ++out_deg[idx[e]];
-      }
+      for (uint64_t e = 0; e < m; ++e) in_src[e] = cpos[idx[e]];
       if (w) std::copy(w, w + m, in_w.begin());
     }
     for (uint32_t v = 0; v < n; ++v) {
@@ -428,16 +464,19 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
   }
   g->cus = (uint32_t)cus;
   g->lds_per_block = (size_t)lds;
-  uint32_t P = std::max(1u, std::min(g->cus * 8u, g->T));
-  if (P > 8) P &= ~7u;
+  uint32_t P = want_workers ? want_workers : g->cus * 8u;
+  P = std::max(1u, std::min(P, g->T));
+  if (P > 8 && !want_workers) P &= ~7u;
   g->P = P;
   build_workers(in_ptr, tile_v, P, work_t);
+  for (uint32_t wk = 0; wk < P; ++wk)
+    g->max_block_v = std::max(g->max_block_v, tile_v[work_t[wk + 1]] - tile_v[work_t[wk]]);
 
   struct Up {
     uint32_t** dst;
     const std::vector<uint32_t>* src;
-  } ups[] = {{&g->in_ptr, &in_ptr}, {&g->in_src, &in_src}, {&g->in_w, &in_w},
-             {&g->out_deg, &out_deg}, {&g->tile_v, &tile_v}, {&g->work_t, &work_t}};
+  } ups[] = {{&g->in_ptr, &in_ptr}, {&g->in_src, &in_src}, {&g->in_w, &in_w}, {&g->out_deg, &out_deg},
+             {&g->cpos, &cpos}, {&g->tile_v, &tile_v}, {&g->work_t, &work_t}};
   for (auto& u : ups) {
     if (u.src->empty()) continue;
     const size_t bytes = u.src->size() * sizeof(uint32_t);
@@ -480,6 +519,8 @@ dg_status dg_graph_info_get(const dg_graph* g, dg_graph_info* info) {
   info->dangling = g->n_dangling;
   info->has_weights = g->has_w ? 1u : 0u;
   info->compute_units = g->cus;
+  info->hot_vertices = g->K;
+  info->hot_edges = g->hot_edges;
   info->device_bytes = g->graph_bytes;
   return DG_OK;
 }
@@ -503,18 +544,20 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
   const bool f64 = dtype == DG_F64;
   const size_t elem = f64 ? 8 : 4;
   uint32_t cap = 0, d_eff = 0;
-  if (mode == DG_DELAYED) staging(g, d, elem, cap, d_eff);
+  bool use_shadow = false;
+  if (mode == DG_DELAYED) staging(g, d, elem, cap, d_eff, use_shadow);
   void* x = g->vals[0];
   void* c0 = g->vals[1];
   void* c1 = mode == DG_SYNC ? g->vals[2] : nullptr;
   const double d0 = (double)g->n_dangling / (double)g->n;
   SweepState sst = state(g);
-  DG_HIP(launch_pr_init(f64, x, c0, c1, g->out_deg, g->n, sst, max_sweeps, d0, s));
+  DG_HIP(launch_pr_init(f64, x, c0, c1, g->out_deg, g->cpos, g->n, sst, max_sweeps, d0, s));
 
   PrArgs a;
   a.g = topo(g);
   a.st = sst;
   a.x = x;
+  a.shadow = use_shadow ? g->vals[2] : nullptr;
   a.alpha = damping;
   a.tol = tol;
   a.d = d_eff;
@@ -573,17 +616,19 @@ dg_status dg_sssp(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t 
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if ((st = ensure_workspace(g, max_sweeps, s)) != DG_OK) return st;
   uint32_t cap = 0, d_eff = 0;
-  if (mode == DG_DELAYED) staging(g, d, sizeof(uint32_t), cap, d_eff);
+  bool use_shadow = false;
+  if (mode == DG_DELAYED) staging(g, d, sizeof(uint32_t), cap, d_eff, use_shadow);
   uint32_t* b0 = static_cast<uint32_t*>(g->vals[0]);
   uint32_t* b1 = mode == DG_SYNC ? static_cast<uint32_t*>(g->vals[1]) : nullptr;
   SweepState sst = state(g);
-  DG_HIP(launch_bf_init(b0, b1, g->n, src, sst, max_sweeps, s));
+  DG_HIP(launch_bf_init(b0, b1, g->cpos, g->n, src, sst, max_sweeps, s));
 
   BfArgs a;
   a.g = topo(g);
   a.st = sst;
   a.d = d_eff;
   a.cap = cap;
+  a.shadow = use_shadow ? static_cast<uint32_t*>(g->vals[2]) : nullptr;
   auto launch = [&](uint32_t k) {
     if (mode == DG_SYNC) {
       a.din = (k & 1) ? b1 : b0;
@@ -606,8 +651,10 @@ dg_status dg_sssp(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t 
   if ((st = drive(g, max_sweeps, s, false, launch, done, sweeps, secs, conv, unused)) != DG_OK) return st;
   // The last executed sweep k = sweeps-1 wrote buffer (k+1) % 2 in sync mode.
   const uint32_t* res = (mode == DG_SYNC && (sweeps & 1)) ? b1 : b0;
-  DG_HIP(hipMemcpyAsync(out_dist, res, (size_t)g->n * sizeof(uint32_t),
-                        out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  uint32_t* dst = out_on_device ? out_dist : static_cast<uint32_t*>(g->vals[2]);
+  DG_HIP(launch_bf_gather(res, g->cpos, g->n, dst, s));
+  if (!out_on_device)
+    DG_HIP(hipMemcpyAsync(out_dist, dst, (size_t)g->n * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   DG_HIP(hipStreamSynchronize(s));
   if (stats) {
     stats->sweeps = sweeps;

@@ -32,9 +32,11 @@ enum Mode : int { kSync = 0, kAsync = 1, kDelayed = 2 };
 // Graph arrays resident in HBM (all device pointers).
 struct Topology {
   const uint32_t* in_ptr;   // [n+1] in-edge offsets (CSC over destinations)
-  const uint32_t* in_src;   // [m + kEdgePad] source of each in-edge
+  const uint32_t* in_src;   // [m + kEdgePad] slot (cpos) of each in-edge's source
   const uint32_t* in_w;     // [m + kEdgePad] weight of each in-edge (nullable)
   const uint32_t* out_deg;  // [n] out-degree
+  const uint32_t* cpos;     // [n] slot of each vertex's published value: v, or
+                            // n + rank for the K sources of the compact region
   const uint32_t* tile_v;   // [T+1] first vertex of each tile
   const uint32_t* work_t;   // [P+1] first tile of each worker
   uint32_t n;
@@ -60,9 +62,10 @@ struct PrArgs {
   void* cout;       // [n] contributions written (== cin unless synchronous)
   double alpha;
   double tol;
+  void* shadow;     // [n] global staging buffer indexed by vertex, or null to stage in LDS
   uint32_t k;       // sweep index
   uint32_t d;       // commit interval in vertices (delayed mode)
-  uint32_t cap;     // staging capacity in vertices (delayed mode)
+  uint32_t cap;     // LDS staging capacity in vertices (delayed mode, LDS staging)
 };
 
 struct BfArgs {
@@ -70,17 +73,20 @@ struct BfArgs {
   SweepState st;
   const uint32_t* din;  // [n] distances read by the sweep
   uint32_t* dout;       // [n] distances written (== din unless synchronous)
+  uint32_t* shadow;     // [n] global staging buffer indexed by vertex, or null to stage in LDS
   uint32_t k;
   uint32_t d;
   uint32_t cap;
 };
 
 // Launchers (enqueue only; return the launch status).
-hipError_t launch_pr_init(bool f64, void* x, void* c0, void* c1, const uint32_t* out_deg, uint32_t n,
-                          SweepState st, uint32_t S, double d0, hipStream_t s);
+hipError_t launch_pr_init(bool f64, void* x, void* c0, void* c1, const uint32_t* out_deg, const uint32_t* cpos,
+                          uint32_t n, SweepState st, uint32_t S, double d0, hipStream_t s);
 hipError_t launch_pr_sweep(int mode, bool f64, const PrArgs& a, hipStream_t s);
-hipError_t launch_bf_init(uint32_t* d0, uint32_t* d1, uint32_t n, uint32_t src, SweepState st, uint32_t S,
-                          hipStream_t s);
+hipError_t launch_bf_init(uint32_t* d0, uint32_t* d1, const uint32_t* cpos, uint32_t n, uint32_t src,
+                          SweepState st, uint32_t S, hipStream_t s);
+// out[v] = d[cpos[v]]: distances back in vertex order.
+hipError_t launch_bf_gather(const uint32_t* d, const uint32_t* cpos, uint32_t n, uint32_t* out, hipStream_t s);
 hipError_t launch_bf_sweep(int mode, const BfArgs& a, hipStream_t s);
 // out[v] = x[v] / sum(x), sum in float64 with a fixed reduction order.
 hipError_t launch_normalize(bool f64, const void* x, uint32_t n, double* out, double* scratch, hipStream_t s);

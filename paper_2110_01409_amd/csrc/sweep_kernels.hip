@@ -17,14 +17,20 @@
 //     Partial sums (or minima) per vertex go to LDS with ds_add_f64 /
 //     ds_min_u32 once per vertex boundary crossed; a single-vertex tile uses a
 //     wavefront shuffle reduction and one LDS atomic per wave instead.
+//   * Published values (PageRank contributions, distances) live in slot
+//     cpos[v]: v itself, or a slot in a compact region after the n regular
+//     ones for the sources with the largest out-degree, so that most gathers
+//     hit in L2.  The index stream already holds slots, not vertex ids.
 //   * In the update phase thread i of the workgroup computes vertex i of the
 //     tile and commits it according to the mode:
 //       sync     plain store into the output array (double buffer);
 //       async    agent-scope store into the single global array at once;
-//       delayed  store into an LDS staging buffer; the buffer is copied to the
+//       delayed  store into a staging buffer; the buffer is copied to the
 //                global array with coalesced agent-scope stores when it holds
 //                >= d values, when the next tile would overflow it, and when
-//                the worker's block is done (section III-B).
+//                the worker's block is done (section III-B).  The buffer is in
+//                LDS for small d and a global per-vertex shadow array for large
+//                d, so that big buffers do not cut occupancy.
 //     Gathers in async and delayed mode are agent-scope loads so that values
 //     committed by workgroups on other XCDs are seen within the same sweep
 //     (global reads, section III-C); synchronous gathers are plain cached
@@ -105,7 +111,8 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
   __shared__ double s_red[2 * (kWG / 64)];
   __shared__ int s_last;
   extern __shared__ __align__(16) unsigned char s_dyn[];
-  T* s_stage = reinterpret_cast<T*>(s_dyn);
+  T* s_stage = reinterpret_cast<T*>(s_dyn);                         // [cap] values
+  uint32_t* s_spos = reinterpret_cast<uint32_t*>(s_dyn + a.cap * sizeof(T));  // [cap] slots
 
   const uint32_t k = a.k;
   if (!(a.st.resid[k] >= a.tol)) return;  // an earlier sweep met the stopping rule
@@ -125,11 +132,11 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
   const T* cin = static_cast<const T*>(a.cin);
   T* cout = static_cast<T*>(a.cout);
   T* x = static_cast<T*>(a.x);
+  T* shadow = static_cast<T*>(a.shadow);
 
   double r_loc = 0.0, nd_loc = 0.0;
   const uint32_t t0 = a.g.work_t[w], t1 = a.g.work_t[w + 1];
   uint32_t staged = 0;
-  uint32_t stage_v0 = a.g.tile_v[t0];
 
   for (uint32_t t = t0; t < t1; ++t) {
     const uint32_t v0 = a.g.tile_v[t], v1 = a.g.tile_v[t + 1], nv = v1 - v0;
@@ -144,13 +151,21 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
 #pragma unroll
       for (int j = 0; j < kEPT; ++j) val[j] = 0.0;
       if (active) {
+        // Branch-free: slots outside the tile gather c[0] and are zeroed, so
+        // the eight gathers are all in flight together.
         uint32_t u[kEPT];
+        bool ok[kEPT];
         load_idx8(a.g.in_src + e0, u);
 #pragma unroll
         for (int j = 0; j < kEPT; ++j) {
-          const uint32_t e = e0 + j;
-          if (e >= eb && e < ee) val[j] = (double)ld_shared<M>(cin + u[j]);
+          ok[j] = (e0 + j >= eb) & (e0 + j < ee);
+          u[j] = ok[j] ? u[j] : 0u;
         }
+        T raw[kEPT];
+#pragma unroll
+        for (int j = 0; j < kEPT; ++j) raw[j] = ld_shared<M>(cin + u[j]);
+#pragma unroll
+        for (int j = 0; j < kEPT; ++j) val[j] = ok[j] ? (double)raw[j] : 0.0;
       }
       if (nv == 1) {
         double p = 0.0;
@@ -191,22 +206,30 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
       // stored old value (in float64 both are the same value).
       r_loc += fabs(xn - (double)xo);
       if (dg != 0) nd_loc += xn;
+      const uint32_t p = a.g.cpos[v];
       if constexpr (M == kSync) {
-        cout[v] = cn;
+        cout[p] = cn;
       } else if constexpr (M == kAsync) {
-        st_agent(cout + v, cn);
+        st_agent(cout + p, cn);
+      } else if (shadow) {
+        shadow[v] = cn;
       } else {
         s_stage[staged + tid] = cn;
+        s_spos[staged + tid] = p;
       }
     }
     if constexpr (M == kDelayed) {
       staged += nv;
       const bool last = (t + 1 == t1);
       const uint32_t next_nv = last ? 0u : a.g.tile_v[t + 2] - v1;
-      if (last || staged >= a.d || staged + next_nv > a.cap) {
+      if (last || staged >= a.d || (!shadow && staged + next_nv > a.cap)) {
         __syncthreads();
-        for (uint32_t i = tid; i < staged; i += kWG) st_agent(cout + stage_v0 + i, s_stage[i]);
-        stage_v0 += staged;
+        if (shadow) {
+          const uint32_t f0 = v1 - staged;
+          for (uint32_t i = tid; i < staged; i += kWG) st_agent(cout + a.g.cpos[f0 + i], shadow[f0 + i]);
+        } else {
+          for (uint32_t i = tid; i < staged; i += kWG) st_agent(cout + s_spos[i], s_stage[i]);
+        }
         staged = 0;
       }
     }
@@ -251,16 +274,18 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kWG) void pr_init_kernel(T* x, T* c0, T* c1, const uint32_t* out_deg, uint32_t n,
-                                                      SweepState st, uint32_t S, double d0) {
+__global__ __launch_bounds__(kWG) void pr_init_kernel(T* x, T* c0, T* c1, const uint32_t* out_deg,
+                                                      const uint32_t* cpos, uint32_t n, SweepState st, uint32_t S,
+                                                      double d0) {
   const uint32_t i = blockIdx.x * kWG + threadIdx.x;
   const double x0 = 1.0 / (double)n;
   if (i < n) {
     const uint32_t dg = out_deg[i];
     const T c = dg ? static_cast<T>(x0 / (double)dg) : static_cast<T>(0);
+    const uint32_t p = cpos[i];
     x[i] = static_cast<T>(x0);
-    c0[i] = c;
-    if (c1) c1[i] = c;
+    c0[p] = c;
+    if (c1) c1[p] = c;
   }
   if (i <= S) {
     st.resid[i] = (i == 0) ? __builtin_inf() : 0.0;
@@ -277,7 +302,8 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
   __shared__ uint32_t s_ptr[kTileV + 1];
   __shared__ uint32_t s_acc[kTileV];
   extern __shared__ __align__(16) unsigned char s_dyn[];
-  uint32_t* s_stage = reinterpret_cast<uint32_t*>(s_dyn);
+  uint32_t* s_stage = reinterpret_cast<uint32_t*>(s_dyn);       // [cap] values
+  uint32_t* s_spos = s_stage + a.cap;                           // [cap] slots
 
   const uint32_t k = a.k;
   if (a.st.changed[k] == 0) return;  // an earlier sweep made no update
@@ -289,7 +315,6 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
   uint32_t* dout = a.dout;
   const uint32_t t0 = a.g.work_t[w], t1 = a.g.work_t[w + 1];
   uint32_t staged = 0;
-  uint32_t stage_v0 = a.g.tile_v[t0];
   int any = 0;
 
   for (uint32_t t = t0; t < t1; ++t) {
@@ -306,13 +331,19 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
       for (int j = 0; j < kEPT; ++j) cand[j] = kInf;
       if (active) {
         uint32_t u[kEPT], wt[kEPT];
+        bool ok[kEPT];
         load_idx8(a.g.in_src + e0, u);
         load_idx8(a.g.in_w + e0, wt);
 #pragma unroll
         for (int j = 0; j < kEPT; ++j) {
-          const uint32_t e = e0 + j;
-          if (e >= eb && e < ee) cand[j] = sat_add(ld_shared<M>(din + u[j]), wt[j]);
+          ok[j] = (e0 + j >= eb) & (e0 + j < ee);
+          u[j] = ok[j] ? u[j] : 0u;
         }
+        uint32_t du[kEPT];
+#pragma unroll
+        for (int j = 0; j < kEPT; ++j) du[j] = ld_shared<M>(din + u[j]);
+#pragma unroll
+        for (int j = 0; j < kEPT; ++j) cand[j] = ok[j] ? sat_add(du[j], wt[j]) : kInf;
       }
       if (nv == 1) {
         uint32_t p = kInf;
@@ -343,27 +374,34 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
     }
     __syncthreads();
     if (tid < nv) {
-      const uint32_t v = v0 + tid;
-      const uint32_t old = ld_shared<M>(din + v);
+      const uint32_t p = a.g.cpos[v0 + tid];
+      const uint32_t old = ld_shared<M>(din + p);
       const uint32_t best = s_acc[tid];
       const uint32_t nw = best < old ? best : old;
       any |= (nw < old);
       if constexpr (M == kSync) {
-        dout[v] = nw;
+        dout[p] = nw;
       } else if constexpr (M == kAsync) {
-        st_agent(dout + v, nw);
+        st_agent(dout + p, nw);
+      } else if (a.shadow) {
+        a.shadow[v0 + tid] = nw;
       } else {
         s_stage[staged + tid] = nw;
+        s_spos[staged + tid] = p;
       }
     }
     if constexpr (M == kDelayed) {
       staged += nv;
       const bool last = (t + 1 == t1);
       const uint32_t next_nv = last ? 0u : a.g.tile_v[t + 2] - v1;
-      if (last || staged >= a.d || staged + next_nv > a.cap) {
+      if (last || staged >= a.d || (!a.shadow && staged + next_nv > a.cap)) {
         __syncthreads();
-        for (uint32_t i = tid; i < staged; i += kWG) st_agent(dout + stage_v0 + i, s_stage[i]);
-        stage_v0 += staged;
+        if (a.shadow) {
+          const uint32_t f0 = v1 - staged;
+          for (uint32_t i = tid; i < staged; i += kWG) st_agent(dout + a.g.cpos[f0 + i], a.shadow[f0 + i]);
+        } else {
+          for (uint32_t i = tid; i < staged; i += kWG) st_agent(dout + s_spos[i], s_stage[i]);
+        }
         staged = 0;
       }
     }
@@ -372,13 +410,14 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
   if (__syncthreads_or(any) && tid == 0) st_agent(a.st.changed + k + 1, 1u);
 }
 
-__global__ __launch_bounds__(kWG) void bf_init_kernel(uint32_t* d0, uint32_t* d1, uint32_t n, uint32_t src,
-                                                      SweepState st, uint32_t S) {
+__global__ __launch_bounds__(kWG) void bf_init_kernel(uint32_t* d0, uint32_t* d1, const uint32_t* cpos, uint32_t n,
+                                                      uint32_t src, SweepState st, uint32_t S) {
   const uint32_t i = blockIdx.x * kWG + threadIdx.x;
   if (i < n) {
     const uint32_t v = (i == src) ? 0u : kInf;
-    d0[i] = v;
-    if (d1) d1[i] = v;
+    const uint32_t p = cpos[i];
+    d0[p] = v;
+    if (d1) d1[p] = v;
   }
   if (i <= S) {
     st.resid[i] = 0.0;
@@ -386,6 +425,12 @@ __global__ __launch_bounds__(kWG) void bf_init_kernel(uint32_t* d0, uint32_t* d1
     st.count[i] = 0;
     st.changed[i] = (i == 0) ? 1u : 0u;
   }
+}
+
+__global__ __launch_bounds__(kWG) void bf_gather_kernel(const uint32_t* d, const uint32_t* cpos, uint32_t n,
+                                                        uint32_t* out) {
+  const uint32_t i = blockIdx.x * kWG + threadIdx.x;
+  if (i < n) out[i] = d[cpos[i]];
 }
 
 // ----------------------------------------------------------- normalisation --
@@ -421,20 +466,20 @@ inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kWG - 1) / kWG);
 
 template <int M, typename T>
 size_t pr_dyn_lds(const PrArgs& a) {
-  return M == kDelayed ? (size_t)a.cap * sizeof(T) : 0;
+  return M == kDelayed ? (size_t)a.cap * (sizeof(T) + sizeof(uint32_t)) : 0;
 }
 
 }  // namespace
 
-hipError_t launch_pr_init(bool f64, void* x, void* c0, void* c1, const uint32_t* out_deg, uint32_t n,
-                          SweepState st, uint32_t S, double d0, hipStream_t s) {
+hipError_t launch_pr_init(bool f64, void* x, void* c0, void* c1, const uint32_t* out_deg, const uint32_t* cpos,
+                          uint32_t n, SweepState st, uint32_t S, double d0, hipStream_t s) {
   const uint32_t nb = blocks_for((uint64_t)(n > S + 1 ? n : S + 1));
   if (f64) {
     pr_init_kernel<double><<<nb, kWG, 0, s>>>(static_cast<double*>(x), static_cast<double*>(c0),
-                                              static_cast<double*>(c1), out_deg, n, st, S, d0);
+                                              static_cast<double*>(c1), out_deg, cpos, n, st, S, d0);
   } else {
     pr_init_kernel<float><<<nb, kWG, 0, s>>>(static_cast<float*>(x), static_cast<float*>(c0),
-                                             static_cast<float*>(c1), out_deg, n, st, S, d0);
+                                             static_cast<float*>(c1), out_deg, cpos, n, st, S, d0);
   }
   return hipGetLastError();
 }
@@ -457,15 +502,20 @@ hipError_t launch_pr_sweep(int mode, bool f64, const PrArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_bf_init(uint32_t* d0, uint32_t* d1, uint32_t n, uint32_t src, SweepState st, uint32_t S,
-                          hipStream_t s) {
+hipError_t launch_bf_init(uint32_t* d0, uint32_t* d1, const uint32_t* cpos, uint32_t n, uint32_t src,
+                          SweepState st, uint32_t S, hipStream_t s) {
   const uint32_t nb = blocks_for((uint64_t)(n > S + 1 ? n : S + 1));
-  bf_init_kernel<<<nb, kWG, 0, s>>>(d0, d1, n, src, st, S);
+  bf_init_kernel<<<nb, kWG, 0, s>>>(d0, d1, cpos, n, src, st, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_bf_gather(const uint32_t* d, const uint32_t* cpos, uint32_t n, uint32_t* out, hipStream_t s) {
+  bf_gather_kernel<<<blocks_for(n), kWG, 0, s>>>(d, cpos, n, out);
   return hipGetLastError();
 }
 
 hipError_t launch_bf_sweep(int mode, const BfArgs& a, hipStream_t s) {
-  const size_t lds = mode == kDelayed ? (size_t)a.cap * sizeof(uint32_t) : 0;
+  const size_t lds = mode == kDelayed ? (size_t)a.cap * 2 * sizeof(uint32_t) : 0;
   if (mode == kSync) bf_sweep_kernel<kSync><<<a.g.P, kWG, 0, s>>>(a);
   else if (mode == kAsync) bf_sweep_kernel<kAsync><<<a.g.P, kWG, 0, s>>>(a);
   else bf_sweep_kernel<kDelayed><<<a.g.P, kWG, lds, s>>>(a);

@@ -45,7 +45,15 @@ class dg_stats(C.Structure):
 class dg_graph_info(C.Structure):
     _fields_ = [("n", C.c_uint32), ("m", C.c_uint64), ("workers", C.c_uint32), ("tiles", C.c_uint32),
                 ("max_in_degree", C.c_uint32), ("dangling", C.c_uint32), ("has_weights", C.c_uint32),
-                ("compute_units", C.c_uint32), ("device_bytes", C.c_uint64)]
+                ("compute_units", C.c_uint32), ("hot_vertices", C.c_uint32), ("hot_edges", C.c_uint64),
+                ("device_bytes", C.c_uint64)]
+
+
+class dg_graph_opts(C.Structure):
+    _fields_ = [("workers", C.c_uint32), ("hot_vertices", C.c_uint32)]
+
+
+DG_HOT_AUTO = 0xFFFFFFFF
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -66,7 +74,8 @@ def _load():
     P = C.c_void_p
     sig = {
         "dg_set_allocator": (C.c_int, [ALLOC_FN, FREE_FN, P]),
-        "dg_graph_create": (C.c_int, [C.c_uint32, C.c_uint64, C.c_int, P, P, P, P, C.POINTER(C.c_void_p)]),
+        "dg_graph_create": (C.c_int, [C.c_uint32, C.c_uint64, C.c_int, P, P, P, C.POINTER(dg_graph_opts), P,
+                                      C.POINTER(C.c_void_p)]),
         "dg_graph_destroy": (C.c_int, [P]),
         "dg_graph_info_get": (C.c_int, [P, C.POINTER(dg_graph_info)]),
         "dg_pagerank": (C.c_int, [P, C.c_double, C.c_double, C.c_int, C.c_uint32, C.c_int, C.c_uint32, P, C.c_int,
@@ -103,8 +112,8 @@ def dg_set_allocator(alloc, free_fn, ctx=None):
     return lib.dg_set_allocator(alloc, free_fn, ctx)
 
 
-def dg_graph_create(n, m, layout, ptr, idx, w, stream, out):
-    return lib.dg_graph_create(n, m, layout, ptr, idx, w, stream, out)
+def dg_graph_create(n, m, layout, ptr, idx, w, opts, stream, out):
+    return lib.dg_graph_create(n, m, layout, ptr, idx, w, opts, stream, out)
 
 
 def dg_graph_destroy(g):
@@ -197,7 +206,8 @@ class Graph:
     the in-edge form.  ``Graph.from_csr(g)`` takes a ``graphgen.CSRGraph``.
     """
 
-    def __init__(self, n, ptr, idx, w=None, layout="csr", stream=None, torch_allocator=True):
+    def __init__(self, n, ptr, idx, w=None, layout="csr", stream=None, torch_allocator=True, workers=0,
+                 hot_vertices=DG_HOT_AUTO):
         ptr = np.ascontiguousarray(ptr, dtype=np.uint64)
         idx = np.ascontiguousarray(idx, dtype=np.uint32)
         wa = None if w is None else np.ascontiguousarray(w, dtype=np.uint32)
@@ -205,8 +215,10 @@ class Graph:
             use_torch_allocator()
         h = C.c_void_p()
         lay = DG_CSR if layout == "csr" else DG_CSC
+        opts = dg_graph_opts(int(workers), int(hot_vertices))
         _check(dg_graph_create(int(n), int(idx.shape[0]), lay, _np_ptr(ptr), _np_ptr(idx),
-                               None if wa is None else _np_ptr(wa), _stream_handle(stream), C.byref(h)))
+                               None if wa is None else _np_ptr(wa), C.byref(opts), _stream_handle(stream),
+                               C.byref(h)))
         self._h = h
         self.n = int(n)
         self.m = int(idx.shape[0])

@@ -48,7 +48,7 @@ def _create(dg, n, ptr, idx, w=None, layout=None):
     idx = np.ascontiguousarray(idx, np.uint32)
     wp = None if w is None else dg._np_ptr(np.ascontiguousarray(w, np.uint32))
     s = dg.dg_graph_create(n, idx.shape[0], dg.DG_CSR if layout is None else layout, dg._np_ptr(ptr),
-                           dg._np_ptr(idx), wp, None, C.byref(h))
+                           dg._np_ptr(idx), wp, None, None, C.byref(h))
     return s, h
 
 
@@ -72,7 +72,7 @@ def test_create_validation(dg, case):
         layout = 7
     if case == "null_ptr":
         h = C.c_void_p()
-        s = dg.dg_graph_create(3, 3, dg.DG_CSR, None, dg._np_ptr(idx), None, None, C.byref(h))
+        s = dg.dg_graph_create(3, 3, dg.DG_CSR, None, dg._np_ptr(idx), None, None, None, C.byref(h))
     else:
         s, h = _create(dg, n, ptr, idx, layout=layout)
     assert s == dg.DG_ERR_INVALID_ARGUMENT

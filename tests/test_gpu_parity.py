@@ -284,3 +284,27 @@ def test_repeatability_async(dg):
         d, _ = G.sssp(src, mode="delayed", d=1)
         np.testing.assert_array_equal(_np(d), ref)
     G.close()
+
+
+@pytest.mark.parametrize("hot,workers", [(0, 0), (1000, 0), (0xFFFFFFFF, 3), (0xFFFFFFFF, 17), (50, 1)])
+def test_options_hot_region_and_workers(dg, hot, workers):
+    """The compact hot region and the worker count change only where values
+    are stored and who computes them: results stay bit-exact (SSSP) and within
+    tolerance (PageRank), in every mode."""
+    g, xs = _graph("rmat14")
+    G = dg.Graph.from_csr(g, hot_vertices=hot, workers=workers)
+    info = G.info()
+    if hot == 0:
+        assert info.hot_vertices == 0 and info.hot_edges == 0
+    else:
+        assert 0 < info.hot_vertices <= hot
+    if workers:
+        assert info.workers == workers
+    src = _sources(g, 1)[0]
+    ref = osp.bellman_ford_sync(g, src)[0]
+    for mode, d in MODES:
+        x, _ = G.pagerank(tol=1e-8, mode=mode, d=max(d, 1), dtype="f64")
+        assert np.abs(_np(x) - xs).sum() <= 1e-6
+        dist, _ = G.sssp(src, mode=mode, d=max(d, 1))
+        np.testing.assert_array_equal(_np(dist), ref)
+    G.close()
