@@ -115,7 +115,7 @@ dg_status dg_set_allocator(dg_alloc_fn alloc, dg_free_fn free_fn, void* ctx);
 
 /* Options of dg_graph_create (pass NULL for the defaults).
  *   workers       persistent workgroups that own the contiguous vertex blocks;
- *                 0 = automatic (8 per compute unit, at most one per tile)
+ *                 0 = automatic (5 per compute unit, at most one per tile)
  *   hot_vertices  at most this many sources with the largest out-degree (and
  *                 above-average out-degree) get their published value stored
  *                 in a compact region after the n regular slots, so gathers

@@ -79,6 +79,22 @@ __device__ __forceinline__ uint32_t wave_min(uint32_t v) {
   return v;
 }
 
+// Workgroup barrier for LDS traffic only.  __syncthreads() also issues a
+// workgroup release fence, which on this target waits for every outstanding
+// global load (vmcnt(0)) and so drains the prefetches and gathers in flight.
+// Tile-local hand-offs go through LDS, so waiting for LDS operations
+// (lgkmcnt(0)) before the barrier is enough; global loads stay in flight.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Read-only tables indexed by workgroup-uniform values (tile and worker
+// bounds, in-edge offsets at tile ends) are read through the constant
+// address space so they become scalar loads, which do not sit in the
+// in-order vector-load counter in front of the gathers.
+typedef const __attribute__((address_space(4))) uint32_t* const_u32p;
+__device__ __forceinline__ const_u32p as_const(const uint32_t* p) { return (const_u32p)(p); }
+
 __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
   const uint32_t s = a + b;
   return s < a ? kInf : s;  // INF + w and overflow both saturate
@@ -135,14 +151,35 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
   T* shadow = static_cast<T*>(a.shadow);
 
   double r_loc = 0.0, nd_loc = 0.0;
-  const uint32_t t0 = a.g.work_t[w], t1 = a.g.work_t[w + 1];
+  const const_u32p tile_v = as_const(a.g.tile_v);
+  const uint32_t t0 = as_const(a.g.work_t)[w], t1 = as_const(a.g.work_t)[w + 1];
+  const uint32_t n = a.g.n;
   uint32_t staged = 0;
 
+  // Offsets of the first tile; later tiles' offsets are prefetched into
+  // registers while the previous tile's gathers are in flight.
+  uint32_t v0 = tile_v[t0];
+  if (t0 < t1) {
+    const uint32_t nv0 = tile_v[t0 + 1] - v0;
+    if (tid <= nv0) s_ptr[tid] = a.g.in_ptr[v0 + tid];
+    if (tid == 0 && nv0 == kTileV) s_ptr[kTileV] = a.g.in_ptr[v0 + kTileV];
+  }
   for (uint32_t t = t0; t < t1; ++t) {
-    const uint32_t v0 = a.g.tile_v[t], v1 = a.g.tile_v[t + 1], nv = v1 - v0;
-    for (uint32_t i = tid; i <= nv; i += kWG) s_ptr[i] = a.g.in_ptr[v0 + i];
+    const uint32_t v1 = tile_v[t + 1], nv = v1 - v0;
+    const bool more = t + 1 < t1;
+    const uint32_t nvn = more ? tile_v[t + 2] - v1 : 0u;
+    // Per-vertex inputs of the update phase and the next tile's offsets,
+    // issued before the gathers without branches (indices clamped into
+    // range, results used only where valid), so that nothing waits on them
+    // until the update phase.
+    const uint32_t vi = min(v0 + tid, n - 1);
+    const T xo = x[vi];
+    const uint32_t dg = a.g.out_deg[vi];
+    const uint32_t p = a.g.cpos[vi];
+    const uint32_t nxt = a.g.in_ptr[min(v1 + tid, n)];
+    const uint32_t nxt_end = as_const(a.g.in_ptr)[v1 + nvn];
     if (tid < nv) s_acc[tid] = 0.0;
-    __syncthreads();
+    lds_barrier();
     const uint32_t eb = s_ptr[0], ee = s_ptr[nv];
     for (uint32_t cb = eb & ~3u; cb < ee; cb += kChunk) {
       const uint32_t e0 = cb + tid * kEPT;
@@ -168,11 +205,11 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
         for (int j = 0; j < kEPT; ++j) val[j] = ok[j] ? (double)raw[j] : 0.0;
       }
       if (nv == 1) {
-        double p = 0.0;
+        double q = 0.0;
 #pragma unroll
-        for (int j = 0; j < kEPT; ++j) p += val[j];
-        p = wave_sum(p);
-        if (lane == 0) atomicAdd(&s_acc[0], p);
+        for (int j = 0; j < kEPT; ++j) q += val[j];
+        q = wave_sum(q);
+        if (lane == 0) atomicAdd(&s_acc[0], q);
       } else if (active) {
         const uint32_t es = e0 > eb ? e0 : eb;
         const uint32_t en = (e0 + kEPT < ee) ? e0 + kEPT : ee;
@@ -194,19 +231,16 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
         atomicAdd(&s_acc[i], part);
       }
     }
-    __syncthreads();
+    lds_barrier();
     if (tid < nv) {
       const uint32_t v = v0 + tid;
       const double xn = base + alpha * s_acc[tid];
-      const T xo = x[v];
       x[v] = static_cast<T>(xn);
-      const uint32_t dg = a.g.out_deg[v];
       const T cn = dg ? static_cast<T>(xn / (double)dg) : static_cast<T>(0);
       // Change of the score: new value before rounding to storage minus the
       // stored old value (in float64 both are the same value).
       r_loc += fabs(xn - (double)xo);
       if (dg != 0) nd_loc += xn;
-      const uint32_t p = a.g.cpos[v];
       if constexpr (M == kSync) {
         cout[p] = cn;
       } else if constexpr (M == kAsync) {
@@ -220,10 +254,8 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
     }
     if constexpr (M == kDelayed) {
       staged += nv;
-      const bool last = (t + 1 == t1);
-      const uint32_t next_nv = last ? 0u : a.g.tile_v[t + 2] - v1;
-      if (last || staged >= a.d || (!shadow && staged + next_nv > a.cap)) {
-        __syncthreads();
+      if (!more || staged >= a.d || (!shadow && staged + nvn > a.cap)) {
+        if (shadow) __syncthreads(); else lds_barrier();
         if (shadow) {
           const uint32_t f0 = v1 - staged;
           for (uint32_t i = tid; i < staged; i += kWG) st_agent(cout + a.g.cpos[f0 + i], shadow[f0 + i]);
@@ -233,7 +265,12 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
         staged = 0;
       }
     }
-    __syncthreads();
+    lds_barrier();
+    if (more) {
+      if (tid < nvn) s_ptr[tid] = nxt;
+      if (tid == 0) s_ptr[nvn] = nxt_end;
+    }
+    v0 = v1;
   }
 
   // Worker partials, then the last worker folds them in worker order.
@@ -313,15 +350,27 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
   const uint32_t w = worker_id(blockIdx.x, a.g.P);
   const uint32_t* din = a.din;
   uint32_t* dout = a.dout;
-  const uint32_t t0 = a.g.work_t[w], t1 = a.g.work_t[w + 1];
+  const const_u32p tile_v = as_const(a.g.tile_v);
+  const uint32_t t0 = as_const(a.g.work_t)[w], t1 = as_const(a.g.work_t)[w + 1];
+  const uint32_t n = a.g.n;
   uint32_t staged = 0;
   int any = 0;
 
+  uint32_t v0 = tile_v[t0];
+  if (t0 < t1) {
+    const uint32_t nv0 = tile_v[t0 + 1] - v0;
+    if (tid <= nv0) s_ptr[tid] = a.g.in_ptr[v0 + tid];
+    if (tid == 0 && nv0 == kTileV) s_ptr[kTileV] = a.g.in_ptr[v0 + kTileV];
+  }
   for (uint32_t t = t0; t < t1; ++t) {
-    const uint32_t v0 = a.g.tile_v[t], v1 = a.g.tile_v[t + 1], nv = v1 - v0;
-    for (uint32_t i = tid; i <= nv; i += kWG) s_ptr[i] = a.g.in_ptr[v0 + i];
+    const uint32_t v1 = tile_v[t + 1], nv = v1 - v0;
+    const bool more = t + 1 < t1;
+    const uint32_t nvn = more ? tile_v[t + 2] - v1 : 0u;
+    const uint32_t p = a.g.cpos[min(v0 + tid, n - 1)];
+    const uint32_t nxt = a.g.in_ptr[min(v1 + tid, n)];
+    const uint32_t nxt_end = as_const(a.g.in_ptr)[v1 + nvn];
     if (tid < nv) s_acc[tid] = kInf;
-    __syncthreads();
+    lds_barrier();
     const uint32_t eb = s_ptr[0], ee = s_ptr[nv];
     for (uint32_t cb = eb & ~3u; cb < ee; cb += kChunk) {
       const uint32_t e0 = cb + tid * kEPT;
@@ -346,11 +395,11 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
         for (int j = 0; j < kEPT; ++j) cand[j] = ok[j] ? sat_add(du[j], wt[j]) : kInf;
       }
       if (nv == 1) {
-        uint32_t p = kInf;
+        uint32_t q = kInf;
 #pragma unroll
-        for (int j = 0; j < kEPT; ++j) p = cand[j] < p ? cand[j] : p;
-        p = wave_min(p);
-        if (lane == 0 && p != kInf) atomicMin(&s_acc[0], p);
+        for (int j = 0; j < kEPT; ++j) q = cand[j] < q ? cand[j] : q;
+        q = wave_min(q);
+        if (lane == 0 && q != kInf) atomicMin(&s_acc[0], q);
       } else if (active) {
         const uint32_t es = e0 > eb ? e0 : eb;
         const uint32_t en = (e0 + kEPT < ee) ? e0 + kEPT : ee;
@@ -372,9 +421,8 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
         if (part != kInf) atomicMin(&s_acc[i], part);
       }
     }
-    __syncthreads();
+    lds_barrier();
     if (tid < nv) {
-      const uint32_t p = a.g.cpos[v0 + tid];
       const uint32_t old = ld_shared<M>(din + p);
       const uint32_t best = s_acc[tid];
       const uint32_t nw = best < old ? best : old;
@@ -392,10 +440,8 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
     }
     if constexpr (M == kDelayed) {
       staged += nv;
-      const bool last = (t + 1 == t1);
-      const uint32_t next_nv = last ? 0u : a.g.tile_v[t + 2] - v1;
-      if (last || staged >= a.d || (!a.shadow && staged + next_nv > a.cap)) {
-        __syncthreads();
+      if (!more || staged >= a.d || (!a.shadow && staged + nvn > a.cap)) {
+        if (a.shadow) __syncthreads(); else lds_barrier();
         if (a.shadow) {
           const uint32_t f0 = v1 - staged;
           for (uint32_t i = tid; i < staged; i += kWG) st_agent(dout + a.g.cpos[f0 + i], a.shadow[f0 + i]);
@@ -405,7 +451,12 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
         staged = 0;
       }
     }
-    __syncthreads();
+    lds_barrier();
+    if (more) {
+      if (tid < nvn) s_ptr[tid] = nxt;
+      if (tid == 0) s_ptr[nvn] = nxt_end;
+    }
+    v0 = v1;
   }
   if (__syncthreads_or(any) && tid == 0) st_agent(a.st.changed + k + 1, 1u);
 }
