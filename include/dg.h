@@ -130,7 +130,8 @@ typedef struct {
 
 /* Upload a graph and build its in-edge form (pull sweeps need in-neighbours,
  * section III-A).
- *   n          vertices, 1 <= n <= 0xFFFFFFFE
+ *   n          vertices, 1 <= n; n plus the compact-region slots must stay
+ *              below 2^29 (DG_ERR_UNSUPPORTED otherwise)
  *   m          edges, m < 2^32 - 4096
  *   layout     DG_CSR or DG_CSC (see dg_layout)
  *   ptr        host array of n+1 uint64 offsets: ptr[0] = 0, non-decreasing,

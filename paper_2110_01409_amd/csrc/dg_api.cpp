@@ -222,6 +222,7 @@ Topology topo(const dg_graph* g) {
   t.tile_v = g->tile_v;
   t.work_t = g->work_t;
   t.n = g->n;
+  t.K = g->K;
   t.P = g->P;
   return t;
 }
@@ -453,6 +454,13 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
     return fail(DG_ERR_OUT_OF_MEMORY, "host allocation failed while building the in-edge form");
   }
   g->T = (uint32_t)tile_v.size() - 1;
+  // Gathers address the value array through a buffer resource with a 32-bit
+  // byte range: (n + K) float64 slots must stay below 4 GiB.
+  if (((uint64_t)n + g->K) * 8u >= (1ull << 32)) {
+    delete g;
+    return fail(DG_ERR_UNSUPPORTED, "n + hot slots = %llu exceeds the 2^29 value slots a sweep can address",
+                (unsigned long long)n + g->K);
+  }
 
   // Device sizes.  Without a device (or on error) nothing below leaks.
   int dev = 0, cus = 0;

@@ -40,6 +40,7 @@ struct Topology {
   const uint32_t* tile_v;   // [T+1] first vertex of each tile
   const uint32_t* work_t;   // [P+1] first tile of each worker
   uint32_t n;
+  uint32_t K;               // slots of the compact region after the n regular ones
   uint32_t P;               // workers = workgroups launched per sweep
 };
 

@@ -111,12 +111,43 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t* s_ptr, uint32_t nv,
   return lo;
 }
 
-__device__ __forceinline__ void load_idx8(const uint32_t* p, uint32_t (&u)[kEPT]) {
-  const uint4 q0 = *reinterpret_cast<const uint4*>(p);
-  const uint4 q1 = *reinterpret_cast<const uint4*>(p + 4);
+// Buffer resources (raw, stride 0).  A lane whose byte offset lies outside
+// [0, bytes) reads 0 and makes no memory access, which masks lanes without
+// branches.  dword3 is the raw-buffer format word for this target.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+constexpr uint32_t kOut = 0xFFFFFFFFu;  // an offset that is always out of range
+__device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// Eight consecutive 4-byte words of the in-edge stream for one thread.  The
+// window [nb, lim) is rounded up to whole 16-byte groups so that each
+// 16-byte load is entirely inside or outside it.
+__device__ __forceinline__ void load_win8(const uint32_t* stream, uint32_t nb, uint32_t lim, uint32_t tid,
+                                          uint32_t (&u)[kEPT]) {
+  const uint32_t end = (lim + 3u) & ~3u;
+  const rsrc_t r = make_rsrc(stream + nb, end > nb ? (end - nb) * 4u : 0u);
+  const v4u q0 = __builtin_amdgcn_raw_buffer_load_b128(r, tid * 32u, 0, 0);
+  const v4u q1 = __builtin_amdgcn_raw_buffer_load_b128(r, tid * 32u + 16u, 0, 0);
   u[0] = q0.x; u[1] = q0.y; u[2] = q0.z; u[3] = q0.w;
   u[4] = q1.x; u[5] = q1.y; u[6] = q1.z; u[7] = q1.w;
 }
+
+// Gather of a published value; out-of-range offsets read 0.  Asynchronous
+// and delayed sweeps read with the agent-scope coherence bit (sc1), the
+// same access an agent-scope relaxed atomic load makes.
+template <int M, typename T>
+__device__ __forceinline__ T gather(rsrc_t r, uint32_t off) {
+  constexpr int pol = (M == kSync) ? 0 : 16;
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, pol));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, pol));
+  }
+}
+
 
 // ---------------------------------------------------------------- PageRank --
 
@@ -149,6 +180,7 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
   T* cout = static_cast<T*>(a.cout);
   T* x = static_cast<T*>(a.x);
   T* shadow = static_cast<T*>(a.shadow);
+  const rsrc_t rc = make_rsrc(cin, (a.g.n + a.g.K) * (uint32_t)sizeof(T));
 
   double r_loc = 0.0, nd_loc = 0.0;
   const const_u32p tile_v = as_const(a.g.tile_v);
@@ -159,51 +191,69 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
   // Offsets of the first tile; later tiles' offsets are prefetched into
   // registers while the previous tile's gathers are in flight.
   uint32_t v0 = tile_v[t0];
+  // Indices of the next chunk to gather.  They are always loaded one chunk
+  // ahead (software pipelining): while a chunk's gathers are in flight the
+  // following chunk's indices, of this tile or of the worker's next tile,
+  // are already on their way.
+  uint32_t u[kEPT];
+  // Per-vertex inputs of a tile's update phase (old score, out-degree, slot)
+  // and the next tile's offsets are loaded during the previous tile's last
+  // chunk, next to the index prefetch, with branch-free clamped loads.
+  T xo_n = static_cast<T>(0);
+  uint32_t dg_n = 0, p_n = 0, nxt = 0, nxt_end = 0;
   if (t0 < t1) {
     const uint32_t nv0 = tile_v[t0 + 1] - v0;
     if (tid <= nv0) s_ptr[tid] = a.g.in_ptr[v0 + tid];
     if (tid == 0 && nv0 == kTileV) s_ptr[kTileV] = a.g.in_ptr[v0 + kTileV];
+    const uint32_t b0 = as_const(a.g.in_ptr)[v0] & ~3u;
+    load_win8(a.g.in_src, b0, as_const(a.g.in_ptr)[tile_v[t0 + 1]], tid, u);
+    const uint32_t vi = min(v0 + tid, n - 1);
+    xo_n = x[vi];
+    dg_n = a.g.out_deg[vi];
+    p_n = a.g.cpos[vi];
   }
   for (uint32_t t = t0; t < t1; ++t) {
     const uint32_t v1 = tile_v[t + 1], nv = v1 - v0;
     const bool more = t + 1 < t1;
     const uint32_t nvn = more ? tile_v[t + 2] - v1 : 0u;
-    // Per-vertex inputs of the update phase and the next tile's offsets,
-    // issued before the gathers without branches (indices clamped into
-    // range, results used only where valid), so that nothing waits on them
-    // until the update phase.
-    const uint32_t vi = min(v0 + tid, n - 1);
-    const T xo = x[vi];
-    const uint32_t dg = a.g.out_deg[vi];
-    const uint32_t p = a.g.cpos[vi];
-    const uint32_t nxt = a.g.in_ptr[min(v1 + tid, n)];
-    const uint32_t nxt_end = as_const(a.g.in_ptr)[v1 + nvn];
+    const T xo = xo_n;
+    const uint32_t dg = dg_n, p = p_n;
+    const uint32_t ee_next = as_const(a.g.in_ptr)[v1 + nvn];  // last edge of the next tile
+    // Loads for the next tile; issued right after the index prefetch of
+    // this tile's last chunk (or here when the tile has no edges).
+    auto prefetch_next = [&]() {
+      const uint32_t vi = min(v1 + tid, n - 1);
+      xo_n = x[vi];
+      dg_n = a.g.out_deg[vi];
+      p_n = a.g.cpos[vi];
+      nxt = a.g.in_ptr[min(v1 + tid, n)];
+      nxt_end = ee_next;
+    };
     if (tid < nv) s_acc[tid] = 0.0;
     lds_barrier();
     const uint32_t eb = s_ptr[0], ee = s_ptr[nv];
     for (uint32_t cb = eb & ~3u; cb < ee; cb += kChunk) {
       const uint32_t e0 = cb + tid * kEPT;
       const bool active = (e0 < ee) && (e0 + kEPT > eb);
+      // Branch-free: slots outside the tile gather c[0] and are zeroed, so
+      // the eight gathers are all in flight together.
+      T raw[kEPT];
+#pragma unroll
+      for (int j = 0; j < kEPT; ++j) {
+        const bool ok = (e0 + j >= eb) & (e0 + j < ee);
+        raw[j] = gather<M, T>(rc, ok ? u[j] * (uint32_t)sizeof(T) : kOut);
+      }
+      // Prefetch the next chunk's indices: the next chunk of this tile, else
+      // the first chunk of the next tile (its window starts at this tile's
+      // last edge rounded down), else nothing.
+      const bool last = cb + kChunk >= ee;
+      const uint32_t nb = !last ? cb + kChunk : (more ? (ee & ~3u) : cb);
+      const uint32_t lim = !last ? ee : (more ? ee_next : cb);
+      load_win8(a.g.in_src, nb, lim, tid, u);
+      if (last) prefetch_next();
       double val[kEPT];
 #pragma unroll
-      for (int j = 0; j < kEPT; ++j) val[j] = 0.0;
-      if (active) {
-        // Branch-free: slots outside the tile gather c[0] and are zeroed, so
-        // the eight gathers are all in flight together.
-        uint32_t u[kEPT];
-        bool ok[kEPT];
-        load_idx8(a.g.in_src + e0, u);
-#pragma unroll
-        for (int j = 0; j < kEPT; ++j) {
-          ok[j] = (e0 + j >= eb) & (e0 + j < ee);
-          u[j] = ok[j] ? u[j] : 0u;
-        }
-        T raw[kEPT];
-#pragma unroll
-        for (int j = 0; j < kEPT; ++j) raw[j] = ld_shared<M>(cin + u[j]);
-#pragma unroll
-        for (int j = 0; j < kEPT; ++j) val[j] = ok[j] ? (double)raw[j] : 0.0;
-      }
+      for (int j = 0; j < kEPT; ++j) val[j] = (double)raw[j];
       if (nv == 1) {
         double q = 0.0;
 #pragma unroll
@@ -230,6 +280,11 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
         }
         atomicAdd(&s_acc[i], part);
       }
+    }
+    if (eb >= ee) {
+      // A tile without in-edges ran no chunk: fetch the next tile's window here.
+      if (more) load_win8(a.g.in_src, ee & ~3u, ee_next, tid, u);
+      prefetch_next();
     }
     lds_barrier();
     if (tid < nv) {
@@ -350,6 +405,7 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
   const uint32_t w = worker_id(blockIdx.x, a.g.P);
   const uint32_t* din = a.din;
   uint32_t* dout = a.dout;
+  const rsrc_t rd = make_rsrc(din, (a.g.n + a.g.K) * 4u);
   const const_u32p tile_v = as_const(a.g.tile_v);
   const uint32_t t0 = as_const(a.g.work_t)[w], t1 = as_const(a.g.work_t)[w + 1];
   const uint32_t n = a.g.n;
@@ -357,43 +413,52 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
   int any = 0;
 
   uint32_t v0 = tile_v[t0];
+  uint32_t u[kEPT], wt[kEPT];  // next chunk's indices and weights, loaded one chunk ahead
+  uint32_t p_n = 0, nxt = 0, nxt_end = 0;
   if (t0 < t1) {
     const uint32_t nv0 = tile_v[t0 + 1] - v0;
     if (tid <= nv0) s_ptr[tid] = a.g.in_ptr[v0 + tid];
     if (tid == 0 && nv0 == kTileV) s_ptr[kTileV] = a.g.in_ptr[v0 + kTileV];
+    const uint32_t b0 = as_const(a.g.in_ptr)[v0] & ~3u;
+    const uint32_t l0 = as_const(a.g.in_ptr)[tile_v[t0 + 1]];
+    load_win8(a.g.in_src, b0, l0, tid, u);
+    load_win8(a.g.in_w, b0, l0, tid, wt);
+    p_n = a.g.cpos[min(v0 + tid, n - 1)];
   }
   for (uint32_t t = t0; t < t1; ++t) {
     const uint32_t v1 = tile_v[t + 1], nv = v1 - v0;
     const bool more = t + 1 < t1;
     const uint32_t nvn = more ? tile_v[t + 2] - v1 : 0u;
-    const uint32_t p = a.g.cpos[min(v0 + tid, n - 1)];
-    const uint32_t nxt = a.g.in_ptr[min(v1 + tid, n)];
-    const uint32_t nxt_end = as_const(a.g.in_ptr)[v1 + nvn];
+    const uint32_t p = p_n;
+    const uint32_t ee_next = as_const(a.g.in_ptr)[v1 + nvn];
+    auto prefetch_next = [&]() {
+      p_n = a.g.cpos[min(v1 + tid, n - 1)];
+      nxt = a.g.in_ptr[min(v1 + tid, n)];
+      nxt_end = ee_next;
+    };
     if (tid < nv) s_acc[tid] = kInf;
     lds_barrier();
     const uint32_t eb = s_ptr[0], ee = s_ptr[nv];
     for (uint32_t cb = eb & ~3u; cb < ee; cb += kChunk) {
       const uint32_t e0 = cb + tid * kEPT;
       const bool active = (e0 < ee) && (e0 + kEPT > eb);
+      bool ok[kEPT];
+      uint32_t du[kEPT], wc[kEPT];
+#pragma unroll
+      for (int j = 0; j < kEPT; ++j) {
+        ok[j] = (e0 + j >= eb) & (e0 + j < ee);
+        du[j] = gather<M, uint32_t>(rd, ok[j] ? u[j] * 4u : kOut);
+        wc[j] = wt[j];
+      }
+      const bool last = cb + kChunk >= ee;
+      const uint32_t nb = !last ? cb + kChunk : (more ? (ee & ~3u) : cb);
+      const uint32_t lim = !last ? ee : (more ? ee_next : cb);
+      load_win8(a.g.in_src, nb, lim, tid, u);
+      load_win8(a.g.in_w, nb, lim, tid, wt);
+      if (last) prefetch_next();
       uint32_t cand[kEPT];
 #pragma unroll
-      for (int j = 0; j < kEPT; ++j) cand[j] = kInf;
-      if (active) {
-        uint32_t u[kEPT], wt[kEPT];
-        bool ok[kEPT];
-        load_idx8(a.g.in_src + e0, u);
-        load_idx8(a.g.in_w + e0, wt);
-#pragma unroll
-        for (int j = 0; j < kEPT; ++j) {
-          ok[j] = (e0 + j >= eb) & (e0 + j < ee);
-          u[j] = ok[j] ? u[j] : 0u;
-        }
-        uint32_t du[kEPT];
-#pragma unroll
-        for (int j = 0; j < kEPT; ++j) du[j] = ld_shared<M>(din + u[j]);
-#pragma unroll
-        for (int j = 0; j < kEPT; ++j) cand[j] = ok[j] ? sat_add(du[j], wt[j]) : kInf;
-      }
+      for (int j = 0; j < kEPT; ++j) cand[j] = ok[j] ? sat_add(du[j], wc[j]) : kInf;
       if (nv == 1) {
         uint32_t q = kInf;
 #pragma unroll
@@ -420,6 +485,13 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
         }
         if (part != kInf) atomicMin(&s_acc[i], part);
       }
+    }
+    if (eb >= ee) {
+      if (more) {
+        load_win8(a.g.in_src, ee & ~3u, ee_next, tid, u);
+        load_win8(a.g.in_w, ee & ~3u, ee_next, tid, wt);
+      }
+      prefetch_next();
     }
     lds_barrier();
     if (tid < nv) {
