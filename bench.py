@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy five times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -108,10 +110,21 @@ def main():
 
     import torch
 
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # A plain copy of known size: it reads and writes exactly 1 GiB, so the
+        # fetch/write byte counters measured on it calibrate the sweeps' ones.
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": a.numel() * 4, "copies": 5}), flush=True)
+        return
+
     import graphgen as gg
     from paper_2110_01409_amd import dg
 
-    torch.cuda.set_device(0)
     t = time.perf_counter()
     g = gg.rmat(args.scale, seed=args.scale)
     log(f"generated rmat{args.scale}: n={g.n} m={g.m} in {time.perf_counter() - t:.1f}s")

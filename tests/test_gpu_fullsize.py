@@ -1,0 +1,108 @@
+"""Parity at full size (needs an MI355X; a few minutes of host time).
+
+Workloads, in the launch configuration bench.py times (default workers and
+compact hot region):
+
+* R-MAT scale 22 (4,194,304 vertices, ~65M edges after deduplication,
+  a/b/c/d .57/.19/.19/.05, permuted, seed 22);
+* the diagonal-banded graph, 16,777,216 vertices, 16 out-edges within
+  +-4096 plus 1% long-range (seed 24).
+
+PageRank on R-MAT 22 is compared with the oracle's float64 fixed point
+(Jacobi to an L1 change below 1e-12) directly: L1 <= 1e-6 in every mode and
+precision.  On the banded graph the oracle's error certificate
+||T(x) - x||_1 / (1 - alpha), an upper bound on ||x - x*||_1, must be <= 1e-6.
+
+SSSP results are checked with the oracle's O(m) optimality certificate, which
+holds exactly when the distances are the true shortest paths (a bit-exact
+check without a second solver), and one source against scipy's Dijkstra.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+from oracle import pagerank as opr
+from oracle import sssp as osp
+
+pytestmark = pytest.mark.gpu
+
+MODES = [("sync", 1), ("async", 1), ("delayed", 1), ("delayed", 64), ("delayed", 1024), ("delayed", 0xFFFFFFFF)]
+PR_TOL = {"f64": 1e-8, "f32": 1e-7}
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2110_01409_amd import dg as _dg
+    return _dg
+
+
+@pytest.fixture(scope="module")
+def rmat22():
+    g = gg.rmat(22, seed=22)
+    print(f"rmat22 n={g.n} m={g.m}", flush=True)
+    return g
+
+
+@pytest.fixture(scope="module")
+def rmat22_xstar(rmat22):
+    x = opr.pagerank_fixed_point(rmat22, tol=1e-12)
+    print("rmat22 fixed point ready", flush=True)
+    return x
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_rmat22_pagerank_all_modes(dg, rmat22, rmat22_xstar, dtype):
+    G = dg.Graph.from_csr(rmat22)
+    for mode, d in MODES:
+        x, st = G.pagerank(tol=PR_TOL[dtype], mode=mode, d=d, dtype=dtype, max_sweeps=500)
+        err = float(np.abs(x.cpu().numpy() - rmat22_xstar).sum())
+        print(f"rmat22 {dtype} {mode} d={d}: sweeps={st.sweeps} L1 err={err:.2e} t={st.seconds*1e3:.2f} ms",
+              flush=True)
+        assert err <= 1e-6, (dtype, mode, d, err)
+    G.close()
+
+
+def test_rmat22_sssp_all_modes(dg, rmat22):
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import dijkstra as sp_dijkstra
+    G = dg.Graph.from_csr(rmat22)
+    sources = gg.pick_sources(rmat22, 16, seed=22).tolist()
+    # one source against an independent solver
+    deg = np.diff(rmat22.ptr.astype(np.int64))
+    mat = csr_matrix((rmat22.w.astype(np.float64), rmat22.idx.astype(np.int64), rmat22.ptr.astype(np.int64)),
+                     shape=(rmat22.n, rmat22.n))
+    ref = sp_dijkstra(mat, directed=True, indices=sources[0])
+    ref = np.where(np.isinf(ref), osp.INF32, ref).astype(np.uint32)
+    del deg
+    for mode, d in MODES:
+        dist, st = G.sssp(sources[0], mode=mode, d=d)
+        np.testing.assert_array_equal(dist.cpu().numpy(), ref, err_msg=f"{mode} d={d}")
+    # the rest by certificate, cycling through the modes
+    for i, src in enumerate(sources[1:6]):
+        mode, d = MODES[i % len(MODES)]
+        dist, st = G.sssp(src, mode=mode, d=d)
+        ok, msg = osp.certificate(rmat22, src, dist.cpu().numpy())
+        print(f"rmat22 sssp src={src} {mode} d={d}: sweeps={st.sweeps} certificate {msg}", flush=True)
+        assert ok, msg
+    G.close()
+
+
+def test_banded16m_pagerank_and_sssp(dg):
+    g = gg.banded(1 << 24, 16, 4096, 0.01, seed=24)
+    print(f"banded n={g.n} m={g.m}", flush=True)
+    G = dg.Graph.from_csr(g)
+    for mode, d in [("sync", 1), ("delayed", 64), ("async", 1)]:
+        x, st = G.pagerank(tol=1e-7, mode=mode, d=d, dtype="f32", max_sweeps=1000)
+        cert = opr.certificate(g, x.cpu().numpy())
+        print(f"banded f32 {mode} d={d}: sweeps={st.sweeps} certificate bound {cert:.2e}", flush=True)
+        assert cert <= 1e-6
+    src = int(gg.pick_sources(g, 1, seed=24)[0])
+    for mode, d in [("delayed", 1024), ("sync", 1)]:
+        dist, st = G.sssp(src, mode=mode, d=d)
+        ok, msg = osp.certificate(g, src, dist.cpu().numpy())
+        print(f"banded sssp {mode} d={d}: sweeps={st.sweeps} certificate {msg}", flush=True)
+        assert ok, msg
+    G.close()
