@@ -116,3 +116,72 @@ def pagerank_dense(g, alpha=ALPHA):
     n = g.n
     M = transition_matrix(g)
     return np.linalg.solve(np.eye(n) - alpha * M, np.full(n, (1.0 - alpha) / n))
+
+
+# ------------------------------------------------- personalised PageRank --
+#
+# Personalised PageRank with a one-hot restart vector e_s (batched queries of
+# the sweep library): teleport and dangling mass both go to the restart vertex
+# s, so the linear part stays alpha times a column-stochastic matrix:
+#
+#     P_s(x)_v = (1 - alpha) [v = s] + alpha ( sum_{u -> v} x_u / outdeg(u) + D(x) [v = s] )
+
+
+def apply_ppr(x, src, dst, deg, s, alpha=ALPHA):
+    """One synchronous personalised-PageRank sweep with restart vertex s."""
+    n = x.shape[0]
+    x = np.asarray(x, dtype=np.float64)
+    contrib = np.zeros(n, dtype=np.float64)
+    nz = deg > 0
+    contrib[nz] = x[nz] / deg[nz]
+    out = alpha * np.bincount(dst, weights=contrib[src], minlength=n)
+    out[s] += (1.0 - alpha) + alpha * float(x[~nz].sum())
+    return out
+
+
+def ppr_jacobi(g, s, alpha=ALPHA, tol=1e-12, max_sweeps=100_000):
+    """Synchronous personalised PageRank from x0 = e_s until the L1 change of
+    a sweep drops below tol.  Returns (x, sweeps)."""
+    src, dst = edge_list(g)
+    deg = out_degree(g)
+    x = np.zeros(g.n)
+    x[s] = 1.0
+    sweeps = 0
+    while sweeps < max_sweeps:
+        xn = apply_ppr(x, src, dst, deg, s, alpha)
+        r = float(np.abs(xn - x).sum())
+        x = xn
+        sweeps += 1
+        if r < tol:
+            break
+    return x, sweeps
+
+
+def ppr_fixed_point(g, s, alpha=ALPHA, tol=1e-12):
+    x, _ = ppr_jacobi(g, s, alpha, tol)
+    return x / x.sum()
+
+
+def ppr_dense(g, s, alpha=ALPHA):
+    """Direct solve of (I - alpha M_s) x = (1 - alpha) e_s, where M_s has the
+    column of each dangling vertex equal to e_s (tiny graphs)."""
+    n = g.n
+    src, dst = edge_list(g)
+    deg = out_degree(g)
+    M = np.zeros((n, n))
+    for u, v in zip(src.tolist(), dst.tolist()):
+        M[v, u] += 1.0 / deg[u]
+    for u in range(n):
+        if deg[u] == 0:
+            M[s, u] = 1.0
+    rhs = np.zeros(n)
+    rhs[s] = 1.0 - alpha
+    return np.linalg.solve(np.eye(n) - alpha * M, rhs)
+
+
+def ppr_certificate(g, x, s, alpha=ALPHA):
+    """Upper bound on ||x - x*_s||_1: ||P_s(x) - x||_1 / (1 - alpha)."""
+    src, dst = edge_list(g)
+    deg = out_degree(g)
+    x = np.asarray(x, dtype=np.float64)
+    return float(np.abs(apply_ppr(x, src, dst, deg, s, alpha) - x).sum()) / (1.0 - alpha)

@@ -311,3 +311,48 @@ def test_schedule_deficit_spread():
     for mode, delta in [(osch.ASYNC, 0), (osch.DELAYED, 5)]:
         x, _, _ = osch.pagerank(g, mode, delta, P=4, tol=1e-12, spread="deficit")
         assert np.abs(x / x.sum() - xs).sum() < 1e-9
+
+
+# ------------------------------------------------ personalised PageRank ----
+
+@pytest.mark.parametrize("n", [3, 8, 21])
+def test_ppr_cycle_closed_form(n):
+    """Directed cycle, restart at s: mass decays by alpha per hop, so
+    x_{s+k} = (1 - a) a^k / (1 - a^n)."""
+    g = tg.cycle(n)
+    for s in (0, n // 2):
+        x = opr.ppr_fixed_point(g, s)
+        k = (np.arange(n) - s) % n
+        ref = (1 - ALPHA) * ALPHA ** k / (1 - ALPHA ** n)
+        np.testing.assert_allclose(x, ref, rtol=0, atol=1e-11)
+
+
+def test_ppr_out_star_closed_form():
+    """Hub 0 -> dangling leaves, restart at the hub: dangling mass returns to
+    the hub, x_hub = (1 - a) + a (1 - x_hub) -> x_hub = 1/(1 + a), and the
+    leaves share the rest equally."""
+    n = 9
+    g = tg.out_star(n)
+    x = opr.ppr_fixed_point(g, 0)
+    assert abs(x[0] - 1 / (1 + ALPHA)) < 1e-11
+    np.testing.assert_allclose(x[1:], (1 - 1 / (1 + ALPHA)) / (n - 1), rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_ppr_dense_and_networkx(seed):
+    """Jacobi fixed point == direct solve == networkx with personalization
+    and dangling distribution both e_s (an independent implementation)."""
+    nx = pytest.importorskip("networkx")
+    g = tg.dangling_heavy(40 + 10 * seed, seed) if seed % 2 else tg.random_graph(50, 160, seed)
+    s = int(gg.pick_sources(g, 1, seed=seed)[0])
+    x = opr.ppr_fixed_point(g, s)
+    assert np.abs(x - opr.ppr_dense(g, s)).sum() < 1e-10
+    G = nx.DiGraph()
+    G.add_nodes_from(range(g.n))
+    src, dst = opr.edge_list(g)
+    G.add_edges_from(zip(src.tolist(), dst.tolist()))
+    e = {v: (1.0 if v == s else 0.0) for v in range(g.n)}
+    ref = nx.pagerank(G, alpha=ALPHA, personalization=e, dangling=e, tol=1e-15, max_iter=100000)
+    ref = np.array([ref[i] for i in range(g.n)])
+    assert np.abs(x - ref).sum() < 1e-10
+    assert opr.ppr_certificate(g, x, s) < 1e-9
