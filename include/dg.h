@@ -195,6 +195,44 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
 dg_status dg_sssp(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t max_sweeps,
                   uint32_t* out_dist, int out_on_device, dg_stats* stats, void* hip_stream);
 
+/* Batched queries (forms beyond the paper's single query: many sources swept
+ * together on one graph).  Queries are grouped 64 to a batch and every
+ * batch of a call runs in the same sweep launches; values are stored
+ * vertex-major so one gather serves the 64 queries of a batch.  Each batch
+ * stops when all its queries met the stopping rule; the call returns when
+ * every batch has.  Commit modes and d are as for the single-query calls.
+ *   sources     host array of k vertex ids (< n); k >= 1
+ *   max_sweeps  1 <= max_sweeps <= 100000
+ *   stats       sweeps = sweeps until every batch converged;
+ *               edges_traversed = m * sum over queries of their batch's sweeps
+ *
+ * dg_sssp_batch: Bellman-Ford from each source (as dg_sssp).
+ *   out_dist    k rows of n uint32: row q holds the distances from sources[q]
+ *
+ * dg_ppr_batch: personalised PageRank with a one-hot restart vector per
+ * query: x = (1 - damping) e_s + damping (A x + D(x) e_s), where D(x) is the
+ * mass on dangling vertices, i.e. teleport and dangling mass both return to
+ * the restart vertex s = sources[q].  Scores are stored in float32 or
+ * float64 (dtype) with float64 sums, residuals and normalisation.  After
+ * every sweep each query's vector is rescaled to mass 1 (a per-query factor,
+ * no extra pass over memory): the fixed point has mass 1, and the rescale
+ * removes the mass error that Gauss-Seidel-ordered sweeps accumulate.  Each
+ * query stops at the first sweep whose L1 change for that query is < tol and
+ * its row is the iterate of that sweep (later sweeps of its batch leave it
+ * untouched), so a row does not depend on the other queries of the call in
+ * synchronous mode.  Float32 storage has a noise floor of about 1e-7 (the L1
+ * change of a sweep cannot settle much below the rounding of a vector of
+ * mass 1); ask for tol >= 2e-7 with DG_F32 or use DG_F64.
+ *   damping     0 <= damping < 1
+ *   dtype       DG_F32 or DG_F64
+ *   out_scores  k rows of n float64, each normalised to sum 1 */
+dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mode mode, uint32_t d,
+                        uint32_t max_sweeps, uint32_t* out_dist, int out_on_device, dg_stats* stats,
+                        void* hip_stream);
+dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double damping, double tol,
+                       dg_mode mode, uint32_t d, dg_dtype dtype, uint32_t max_sweeps, double* out_scores,
+                       int out_on_device, dg_stats* stats, void* hip_stream);
+
 /* Static name of a status code. */
 const char* dg_status_str(dg_status s);
 

@@ -1,0 +1,486 @@
+// Batched queries: many SSSP sources, or many personalised-PageRank restart
+// vertices, swept together on one graph in one launch.
+//
+// Queries are grouped in batches of 64: the 64 lanes of a wavefront are the
+// 64 queries of a batch, and values are stored vertex-major, [slot][64], so
+// a gather of a source's values for the whole batch is one coalesced
+// 256-byte row.  The in-edge index and weight streams are read once per
+// batch instead of once per query.  Batches are the y dimension of the
+// launch; a batch whose queries have all met the stopping rule exits at once.
+//
+// Work mapping: the same persistent workers and tiles as the single-query
+// sweeps (contiguous vertex blocks, ascending order).  Within a tile the four
+// wavefronts of the workgroup take vertices round-robin; a single-vertex tile
+// (a hub) is split over the four wavefronts and combined in LDS.  For each
+// vertex a wavefront reads 64 in-edges with one coalesced load, broadcasts
+// each edge's source slot and weight with readlane, and keeps eight row
+// gathers in flight.
+//
+// Commit modes are those of the single-query sweeps: synchronous (double
+// buffer), asynchronous (agent-scope store per vertex), delayed (staged in a
+// per-batch shadow array, committed every d vertices and at the block end).
+#include "dg_internal.hpp"
+
+namespace dg {
+namespace {
+
+constexpr uint32_t kQ = 64;  // queries per batch
+
+__device__ __forceinline__ uint32_t worker_of(uint32_t b, uint32_t P) {
+  if ((P & 7u) == 0) return (b & 7u) * (P >> 3) + (b >> 3);
+  return b;
+}
+
+template <int M, typename T>
+__device__ __forceinline__ T ld_q(const T* p) {
+  if constexpr (M == kSync) return *p;
+  else return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_q(T* p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t sat_add_q(uint32_t a, uint32_t b) {
+  const uint32_t s = a + b;
+  return s < a ? kInf : s;
+}
+
+__device__ __forceinline__ uint32_t bcast(uint32_t v, uint32_t j) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)j);
+}
+
+typedef const __attribute__((address_space(4))) uint32_t* cu32p;
+__device__ __forceinline__ cu32p cst(const uint32_t* p) { return (cu32p)(p); }
+
+// min over in-edges [e0, e1) of d[src] + w, taking every `step`-th group of
+// 64 edges starting at group `first`.  Lane q handles query q.
+template <int M>
+__device__ __forceinline__ uint32_t relax_edges(const uint32_t* __restrict__ in_src, const uint32_t* __restrict__ in_w,
+                                                const uint32_t* d, uint32_t e0, uint32_t e1, uint32_t first,
+                                                uint32_t step, uint32_t lane) {
+  uint32_t acc = kInf;
+  for (uint32_t e = e0 + first * 64u; e < e1; e += 64u * step) {
+    const uint32_t cnt = min(64u, e1 - e);
+    const uint32_t idx = lane < cnt ? in_src[e + lane] : 0u;
+    const uint32_t wt = lane < cnt ? in_w[e + lane] : 0u;
+    uint32_t j = 0;
+    for (; j + 8 <= cnt; j += 8) {
+      uint32_t val[8];
+#pragma unroll
+      for (uint32_t q = 0; q < 8; ++q) val[q] = ld_q<M>(d + (size_t)bcast(idx, j + q) * kQ + lane);
+#pragma unroll
+      for (uint32_t q = 0; q < 8; ++q) {
+        const uint32_t c = sat_add_q(val[q], bcast(wt, j + q));
+        acc = c < acc ? c : acc;
+      }
+    }
+    for (; j < cnt; ++j) {
+      const uint32_t c = sat_add_q(ld_q<M>(d + (size_t)bcast(idx, j) * kQ + lane), bcast(wt, j));
+      acc = c < acc ? c : acc;
+    }
+  }
+  return acc;
+}
+
+// sum over in-edges [e0, e1) of c[src] (float64), same access pattern.
+template <int M, typename T>
+__device__ __forceinline__ double pull_edges(const uint32_t* __restrict__ in_src, const T* c, uint32_t e0, uint32_t e1,
+                                             uint32_t first, uint32_t step, uint32_t lane) {
+  double acc = 0.0;
+  for (uint32_t e = e0 + first * 64u; e < e1; e += 64u * step) {
+    const uint32_t cnt = min(64u, e1 - e);
+    const uint32_t idx = lane < cnt ? in_src[e + lane] : 0u;
+    uint32_t j = 0;
+    for (; j + 8 <= cnt; j += 8) {
+      T val[8];
+#pragma unroll
+      for (uint32_t q = 0; q < 8; ++q) val[q] = ld_q<M>(c + (size_t)bcast(idx, j + q) * kQ + lane);
+#pragma unroll
+      for (uint32_t q = 0; q < 8; ++q) acc += (double)val[q];
+    }
+    for (; j < cnt; ++j) acc += (double)ld_q<M>(c + (size_t)bcast(idx, j) * kQ + lane);
+  }
+  return acc;
+}
+
+// ------------------------------------------------------ multi-source SSSP --
+
+template <int M>
+__global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
+  __shared__ uint32_t s_hub[kWG / 64][kQ];
+  __shared__ int s_any;
+  const uint32_t b = blockIdx.y, NB = a.NB, k = a.k;
+  if (a.changed[k * NB + b] == 0) return;  // this batch already converged
+
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+  const uint32_t w = worker_of(blockIdx.x, a.g.P);
+  const size_t stride = (size_t)(a.g.n + a.g.K) * kQ;
+  const uint32_t* din = a.din + b * stride;
+  uint32_t* dout = a.dout + b * stride;
+  uint32_t* shadow = a.shadow ? a.shadow + (size_t)b * a.g.n * kQ : nullptr;
+  const cu32p tile_v = cst(a.g.tile_v);
+  const cu32p in_ptr = cst(a.g.in_ptr);
+  const uint32_t t0 = cst(a.g.work_t)[w], t1 = cst(a.g.work_t)[w + 1];
+  if (tid == 0) s_any = 0;
+  __syncthreads();
+  uint32_t any = 0, staged = 0;
+
+  for (uint32_t t = t0; t < t1; ++t) {
+    const uint32_t v0 = tile_v[t], v1 = tile_v[t + 1], nv = v1 - v0;
+    if (nv == 1) {
+      // Hub: the four wavefronts split its in-edges, wavefront 0 commits.
+      const uint32_t e0 = in_ptr[v0], e1 = in_ptr[v1];
+      s_hub[wv][lane] = relax_edges<M>(a.g.in_src, a.g.in_w, din, e0, e1, wv, kWG / 64, lane);
+      __syncthreads();
+      if (wv == 0) {
+        uint32_t acc = s_hub[0][lane];
+        for (uint32_t i = 1; i < kWG / 64; ++i) acc = s_hub[i][lane] < acc ? s_hub[i][lane] : acc;
+        const uint32_t p = a.g.cpos[v0];
+        const uint32_t old = ld_q<M>(din + (size_t)p * kQ + lane);
+        const uint32_t nw = acc < old ? acc : old;
+        any |= nw < old;
+        if constexpr (M == kSync) dout[(size_t)p * kQ + lane] = nw;
+        else if constexpr (M == kAsync) st_q(dout + (size_t)p * kQ + lane, nw);
+        else shadow[(size_t)v0 * kQ + lane] = nw;
+      }
+      __syncthreads();
+    } else {
+      for (uint32_t v = v0 + wv; v < v1; v += kWG / 64) {
+        const uint32_t acc = relax_edges<M>(a.g.in_src, a.g.in_w, din, in_ptr[v], in_ptr[v + 1], 0, 1, lane);
+        const uint32_t p = a.g.cpos[v];
+        const uint32_t old = ld_q<M>(din + (size_t)p * kQ + lane);
+        const uint32_t nw = acc < old ? acc : old;
+        any |= nw < old;
+        if constexpr (M == kSync) dout[(size_t)p * kQ + lane] = nw;
+        else if constexpr (M == kAsync) st_q(dout + (size_t)p * kQ + lane, nw);
+        else shadow[(size_t)v * kQ + lane] = nw;
+      }
+    }
+    if constexpr (M == kDelayed) {
+      staged += nv;
+      if (t + 1 == t1 || staged >= a.d) {
+        __syncthreads();  // the shadow rows of the whole buffer are written
+        for (uint32_t v = v1 - staged + wv; v < v1; v += kWG / 64)
+          st_q(dout + (size_t)a.g.cpos[v] * kQ + lane, shadow[(size_t)v * kQ + lane]);
+        staged = 0;
+      }
+    }
+  }
+  if (any) s_any = 1;  // benign race: every writer stores 1
+  __syncthreads();
+  if (tid == 0 && s_any) st_q(a.changed + (k + 1) * NB + b, 1u);
+}
+
+__global__ __launch_bounds__(kWG) void mbf_init_kernel(uint32_t* d0, uint32_t* d1, const uint32_t* cpos,
+                                                       const uint32_t* src, uint32_t nq, uint32_t n, uint32_t K,
+                                                       uint32_t NB) {
+  // one thread per (vertex, query) of every batch
+  const size_t i = (size_t)blockIdx.x * kWG + threadIdx.x;
+  const size_t per_batch = (size_t)n * kQ;
+  if (i >= per_batch * NB) return;
+  const uint32_t b = (uint32_t)(i / per_batch);
+  const uint32_t v = (uint32_t)((i % per_batch) / kQ), q = (uint32_t)(i % kQ);
+  const uint32_t qi = b * kQ + q;
+  const uint32_t val = (qi < nq && src[qi] == v) ? 0u : kInf;
+  const size_t off = (size_t)b * (n + K) * kQ + (size_t)cpos[v] * kQ + q;
+  d0[off] = val;
+  if (d1) d1[off] = val;
+}
+
+// out[q][v] = d[cpos[v]][q] for the nq queries; a 64x64 tile per block
+// through LDS so both the read and the write are coalesced.
+__global__ __launch_bounds__(kWG) void mbf_out_kernel(const uint32_t* d, const uint32_t* cpos, uint32_t n, uint32_t K,
+                                                      uint32_t nq, uint32_t* out) {
+  __shared__ uint32_t s[64][65];
+  const uint32_t b = blockIdx.y, vb = blockIdx.x * 64;
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t* db = d + (size_t)b * (n + K) * kQ;
+  for (uint32_t r = wv; r < 64; r += kWG / 64) {
+    const uint32_t v = vb + r;
+    s[r][lane] = v < n ? db[(size_t)cpos[v] * kQ + lane] : 0u;
+  }
+  __syncthreads();
+  for (uint32_t r = wv; r < 64; r += kWG / 64) {
+    const uint32_t qi = b * kQ + r, v = vb + lane;
+    if (qi < nq && v < n) out[(size_t)qi * n + v] = s[lane][r];
+  }
+}
+
+// --------------------------------------------- multi personalised PageRank --
+//
+// Each query's scores are stored scaled: stored = true value * S, with one
+// float64 factor S per query for the whole sweep.  After a sweep its total
+// mass M is known and the true vector is rescaled by 1/M, which costs no pass
+// over memory: S becomes S * M and the stored values are reinterpreted.  The
+// fixed point has mass 1, so the rescale changes no fixed point; it removes
+// the slowly decaying mass error that Gauss-Seidel-ordered (asynchronous and
+// delayed) sweeps create, which synchronous sweeps do not have because they
+// conserve mass exactly.
+
+template <int M, typename T>
+__global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
+  __shared__ double s_hub[kWG / 64][kQ];
+  __shared__ double s_red[3][kWG / 64][kQ];
+  __shared__ int s_last;
+  const uint32_t b = blockIdx.y, NB = a.NB, k = a.k;
+  if (!(a.resid[k * NB + b] >= a.tol)) return;  // this batch already converged
+
+  const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+  const uint32_t P = a.g.P;
+  const uint32_t w = worker_of(blockIdx.x, P);
+  const size_t stride = (size_t)(a.g.n + a.g.K) * kQ;
+  const T* cin = static_cast<const T*>(a.cin) + b * stride;
+  T* cout = static_cast<T*>(a.cout) + b * stride;
+  T* x = static_cast<T*>(a.x) + (size_t)b * a.g.n * kQ;
+  T* shadow = a.shadow ? static_cast<T*>(a.shadow) + (size_t)b * a.g.n * kQ : nullptr;
+  const uint32_t qi = b * kQ + lane;
+  const uint32_t src = qi < a.nq ? a.src[qi] : kInf;
+  // A query that met the stopping rule in an earlier sweep (and every padding
+  // lane) is frozen: its lane still walks the edges with the others but
+  // writes nothing, so its result is the iterate of the sweep that stopped it.
+  const bool live = a.qdone[(size_t)b * kQ + lane] == 0;
+  const double alpha = a.alpha;
+  const size_t ring = ((size_t)(k & 1u) * NB + b) * kQ + lane;
+  const double S = a.scale[ring], invS = 1.0 / S;
+  const double D = a.dang[ring];
+  const double restart = (1.0 - alpha) + alpha * D;
+  const cu32p tile_v = cst(a.g.tile_v);
+  const cu32p in_ptr = cst(a.g.in_ptr);
+  const uint32_t t0 = cst(a.g.work_t)[w], t1 = cst(a.g.work_t)[w + 1];
+  double r_loc = 0.0, dm_loc = 0.0, m_loc = 0.0;
+  uint32_t staged = 0;
+
+  auto update = [&](uint32_t v, double acc) {
+    if (!live) return;
+    const double xn = alpha * acc * invS + (v == src ? restart : 0.0);
+    const double xo = (double)x[(size_t)v * kQ + lane] * invS;
+    x[(size_t)v * kQ + lane] = (T)(xn * S);
+    const uint32_t dg = a.g.out_deg[v];
+    const T cn = dg ? (T)(xn * S / (double)dg) : (T)0;
+    r_loc += fabs(xn - xo);
+    m_loc += xn;
+    if (dg == 0) dm_loc += xn;
+    const uint32_t p = a.g.cpos[v];
+    if constexpr (M == kSync) cout[(size_t)p * kQ + lane] = cn;
+    else if constexpr (M == kAsync) st_q(cout + (size_t)p * kQ + lane, cn);
+    else shadow[(size_t)v * kQ + lane] = cn;
+  };
+
+  for (uint32_t t = t0; t < t1; ++t) {
+    const uint32_t v0 = tile_v[t], v1 = tile_v[t + 1], nv = v1 - v0;
+    if (nv == 1) {
+      const uint32_t e0 = in_ptr[v0], e1 = in_ptr[v1];
+      s_hub[wv][lane] = pull_edges<M, T>(a.g.in_src, cin, e0, e1, wv, kWG / 64, lane);
+      __syncthreads();
+      if (wv == 0) update(v0, s_hub[0][lane] + s_hub[1][lane] + s_hub[2][lane] + s_hub[3][lane]);
+      __syncthreads();
+    } else {
+      for (uint32_t v = v0 + wv; v < v1; v += kWG / 64)
+        update(v, pull_edges<M, T>(a.g.in_src, cin, in_ptr[v], in_ptr[v + 1], 0, 1, lane));
+    }
+    if constexpr (M == kDelayed) {
+      staged += nv;
+      if (t + 1 == t1 || staged >= a.d) {
+        __syncthreads();
+        if (live)
+          for (uint32_t v = v1 - staged + wv; v < v1; v += kWG / 64)
+            st_q(cout + (size_t)a.g.cpos[v] * kQ + lane, shadow[(size_t)v * kQ + lane]);
+        staged = 0;
+      }
+    }
+  }
+
+  // Per-query partials of this worker, then the last worker of the batch
+  // folds them in worker order.
+  s_red[0][wv][lane] = r_loc;
+  s_red[1][wv][lane] = dm_loc;
+  s_red[2][wv][lane] = m_loc;
+  __syncthreads();
+  double* part = a.part + ((size_t)w * NB + b) * 3 * kQ;
+  if (wv == 0) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      part[j * kQ + lane] = s_red[j][0][lane] + s_red[j][1][lane] + s_red[j][2][lane] + s_red[j][3][lane];
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) s_last = (atomicAdd(a.count + k * NB + b, 1u) == P - 1);
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  if (wv == 0) {
+    double r = 0.0, dm = 0.0, ms = 0.0;
+    for (uint32_t i = 0; i < P; ++i) {
+      const double* pp = a.part + ((size_t)i * NB + b) * 3 * kQ;
+      r += __hip_atomic_load(pp + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      dm += __hip_atomic_load(pp + kQ + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ms += __hip_atomic_load(pp + 2 * kQ + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // A live query's mass is at least 1 - alpha > 0 (the restart term).
+    const size_t next = ((size_t)((k + 1) & 1u) * NB + b) * kQ + lane;
+    // The dangling mass itself, not the deficit 1 - (non-dangling mass): with
+    // a one-hot restart the deficit would put a negative rank-one term on a
+    // single row, and asynchronous sweeps of that operator can diverge.
+    a.dang[next] = live ? dm / ms : D;
+    a.scale[next] = live ? S * ms : S;
+    if (live && !(r >= a.tol)) a.qdone[(size_t)b * kQ + lane] = k + 1;
+    // batch residual: the largest change among the queries still live
+    double m = live ? r : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double u = __shfl_xor(m, o, 64);
+      m = u > m ? u : m;
+    }
+    if (lane == 0) a.resid[(k + 1) * NB + b] = m;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void mppr_init_kernel(T* x, T* c0, T* c1, const uint32_t* out_deg,
+                                                        const uint32_t* cpos, const uint32_t* src, uint32_t nq,
+                                                        uint32_t n, uint32_t K, uint32_t NB, double* dang) {
+  const size_t i = (size_t)blockIdx.x * kWG + threadIdx.x;
+  const size_t per_batch = (size_t)n * kQ;
+  if (i >= per_batch * NB) return;
+  const uint32_t b = (uint32_t)(i / per_batch);
+  const uint32_t v = (uint32_t)((i % per_batch) / kQ), q = (uint32_t)(i % kQ);
+  const uint32_t qi = b * kQ + q;
+  const bool at_src = qi < nq && src[qi] == v;
+  const uint32_t dg = out_deg[v];
+  x[(size_t)b * n * kQ + (size_t)v * kQ + q] = at_src ? (T)1 : (T)0;
+  const T c = (at_src && dg) ? (T)(1.0 / (double)dg) : (T)0;
+  const size_t off = (size_t)b * (n + K) * kQ + (size_t)cpos[v] * kQ + q;
+  c0[off] = c;
+  if (c1) c1[off] = c;
+  if (at_src) dang[(size_t)b * kQ + q] = dg ? 0.0 : 1.0;  // dangling mass of x0 = e_s
+}
+
+// Per-query sums of the stored scores in a fixed order, so that a row's
+// normalisation does not depend on scheduling: kSumBlocks partials per batch
+// (waves combined in LDS in wave order), then one fold in block order.
+constexpr uint32_t kSumBlocks = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void mppr_sum_kernel(const T* x, uint32_t n, double* qpart) {
+  __shared__ double s[kWG / 64][kQ];
+  const uint32_t b = blockIdx.y, lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const T* xb = x + (size_t)b * n * kQ;
+  double acc = 0.0;
+  for (uint32_t v = blockIdx.x * (kWG / 64) + wv; v < n; v += kSumBlocks * (kWG / 64)) acc += (double)xb[(size_t)v * kQ + lane];
+  s[wv][lane] = acc;
+  __syncthreads();
+  if (wv == 0) qpart[((size_t)b * kSumBlocks + blockIdx.x) * kQ + lane] = s[0][lane] + s[1][lane] + s[2][lane] + s[3][lane];
+}
+
+__global__ __launch_bounds__(kQ) void mppr_fold_kernel(const double* qpart, double* qsum) {
+  const uint32_t b = blockIdx.x, lane = threadIdx.x;
+  double acc = 0.0;
+  for (uint32_t i = 0; i < kSumBlocks; ++i) acc += qpart[((size_t)b * kSumBlocks + i) * kQ + lane];
+  qsum[(size_t)b * kQ + lane] = acc;
+}
+
+// row q of the output = stored scores of query q / their sum (the storage
+// scale cancels)
+template <typename T>
+__global__ __launch_bounds__(kWG) void mppr_out_kernel(const T* x, const double* qsum, uint32_t n, uint32_t nq,
+                                                       double* out) {
+  __shared__ double s[64][65];
+  const uint32_t b = blockIdx.y, vb = blockIdx.x * 64;
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const T* xb = x + (size_t)b * n * kQ;
+  for (uint32_t r = wv; r < 64; r += kWG / 64) {
+    const uint32_t v = vb + r;
+    s[r][lane] = v < n ? (double)xb[(size_t)v * kQ + lane] : 0.0;
+  }
+  __syncthreads();
+  for (uint32_t r = wv; r < 64; r += kWG / 64) {
+    const uint32_t qi = b * kQ + r, v = vb + lane;
+    if (qi < nq && v < n) out[(size_t)qi * n + v] = s[lane][r] / qsum[(size_t)b * kQ + r];
+  }
+}
+
+__global__ __launch_bounds__(kWG) void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
+  const size_t i = (size_t)blockIdx.x * kWG + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(kWG) void fill_f64_kernel(double* p, size_t n, double v) {
+  const size_t i = (size_t)blockIdx.x * kWG + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline uint32_t nblocks(size_t n) { return (uint32_t)((n + kWG - 1) / kWG); }
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s) {
+  if (n) fill_u32_kernel<<<nblocks(n), kWG, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s) {
+  if (n) fill_f64_kernel<<<nblocks(n), kWG, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_mbf_init(uint32_t* d0, uint32_t* d1, const uint32_t* cpos, const uint32_t* src, uint32_t nq,
+                           uint32_t n, uint32_t K, uint32_t NB, hipStream_t s) {
+  mbf_init_kernel<<<nblocks((size_t)n * kQ * NB), kWG, 0, s>>>(d0, d1, cpos, src, nq, n, K, NB);
+  return hipGetLastError();
+}
+
+hipError_t launch_mbf_sweep(int mode, const MbfArgs& a, hipStream_t s) {
+  const dim3 grid(a.g.P, a.NB);
+  if (mode == kSync) mbf_sweep_kernel<kSync><<<grid, kWG, 0, s>>>(a);
+  else if (mode == kAsync) mbf_sweep_kernel<kAsync><<<grid, kWG, 0, s>>>(a);
+  else mbf_sweep_kernel<kDelayed><<<grid, kWG, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mbf_out(const uint32_t* d, const uint32_t* cpos, uint32_t n, uint32_t K, uint32_t nq, uint32_t NB,
+                          uint32_t* out, hipStream_t s) {
+  mbf_out_kernel<<<dim3((n + 63) / 64, NB), kWG, 0, s>>>(d, cpos, n, K, nq, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mppr_init(bool f64, void* x, void* c0, void* c1, const uint32_t* out_deg, const uint32_t* cpos,
+                            const uint32_t* src, uint32_t nq, uint32_t n, uint32_t K, uint32_t NB, double* dang,
+                            hipStream_t s) {
+  const uint32_t nb = nblocks((size_t)n * kQ * NB);
+  if (f64)
+    mppr_init_kernel<double><<<nb, kWG, 0, s>>>(static_cast<double*>(x), static_cast<double*>(c0),
+                                                static_cast<double*>(c1), out_deg, cpos, src, nq, n, K, NB, dang);
+  else
+    mppr_init_kernel<float><<<nb, kWG, 0, s>>>(static_cast<float*>(x), static_cast<float*>(c0),
+                                               static_cast<float*>(c1), out_deg, cpos, src, nq, n, K, NB, dang);
+  return hipGetLastError();
+}
+
+template <typename T>
+static void mppr_sweep_dispatch(int mode, const MpprArgs& a, hipStream_t s) {
+  const dim3 grid(a.g.P, a.NB);
+  if (mode == kSync) mppr_sweep_kernel<kSync, T><<<grid, kWG, 0, s>>>(a);
+  else if (mode == kAsync) mppr_sweep_kernel<kAsync, T><<<grid, kWG, 0, s>>>(a);
+  else mppr_sweep_kernel<kDelayed, T><<<grid, kWG, 0, s>>>(a);
+}
+
+hipError_t launch_mppr_sweep(int mode, bool f64, const MpprArgs& a, hipStream_t s) {
+  if (f64) mppr_sweep_dispatch<double>(mode, a, s);
+  else mppr_sweep_dispatch<float>(mode, a, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_mppr_out(bool f64, const void* x, double* qpart, double* qsum, uint32_t n, uint32_t nq, uint32_t NB,
+                           double* out, hipStream_t s) {
+  const dim3 gs(kSumBlocks, NB), go((n + 63) / 64, NB);
+  if (f64) mppr_sum_kernel<double><<<gs, kWG, 0, s>>>(static_cast<const double*>(x), n, qpart);
+  else mppr_sum_kernel<float><<<gs, kWG, 0, s>>>(static_cast<const float*>(x), n, qpart);
+  mppr_fold_kernel<<<NB, kQ, 0, s>>>(qpart, qsum);
+  if (f64) mppr_out_kernel<double><<<go, kWG, 0, s>>>(static_cast<const double*>(x), qsum, n, nq, out);
+  else mppr_out_kernel<float><<<go, kWG, 0, s>>>(static_cast<const float*>(x), qsum, n, nq, out);
+  return hipGetLastError();
+}
+
+}  // namespace dg

@@ -259,18 +259,16 @@ void staging(const dg_graph* g, uint32_t d, size_t elem, uint32_t& cap, uint32_t
   cap = shadow ? 0u : d_eff + kTileV;
 }
 
-// Convergence loop shared by both algorithms.  launch(k) enqueues sweep k;
-// the state entry k+1 (PageRank residual or Bellman-Ford changed flag) is
-// copied to the host after each chunk; done(entry) tells whether sweep k met
-// the stopping rule.  Two chunks are in flight so the device never waits for
-// the host.
+// Convergence loop shared by every entry point.  launch(k) enqueues sweep k;
+// after each chunk the E state entries (esz bytes each) that sweep k writes
+// at index (k+1)*E are copied to the pinned buffer `host`; done(entries, k)
+// tells whether sweep k met the stopping rule.  Two chunks are in flight so
+// the device never waits for the host.
 template <typename Launch, typename Done>
-dg_status drive(dg_graph* g, uint32_t max_sweeps, hipStream_t s, bool pr, Launch launch, Done done,
-                uint32_t& sweeps, double& seconds, bool& converged, double& last_entry) {
+dg_status drive(dg_graph* g, uint32_t max_sweeps, hipStream_t s, const void* state, size_t esz, uint32_t E,
+                unsigned char* host, Launch launch, Done done, uint32_t& sweeps, double& seconds, bool& converged) {
   const uint32_t C = std::min(kSweepChunk, max_sweeps);
-  const size_t esz = pr ? sizeof(double) : sizeof(uint32_t);
-  void* src = pr ? (void*)g->resid : (void*)g->changed;
-  unsigned char* host = static_cast<unsigned char*>(g->host_poll);
+  const size_t row = esz * E;
   DG_HIP(hipEventRecord(g->ev_start, s));
   uint32_t next = 0;  // next sweep to enqueue
   uint32_t chunk_idx = 0;
@@ -282,8 +280,8 @@ dg_status drive(dg_graph* g, uint32_t max_sweeps, hipStream_t s, bool pr, Launch
       if (e != hipSuccess) return fail(DG_ERR_DEVICE, "sweep launch failed: %s", hipGetErrorString(e));
       DG_HIP(hipEventRecord(g->ev_sweep[(k0 + j) % (2 * kSweepChunk)], s));
     }
-    DG_HIP(hipMemcpyAsync(host + (size_t)(k0 + 1) * esz, static_cast<unsigned char*>(src) + (size_t)(k0 + 1) * esz,
-                          (size_t)kc * esz, hipMemcpyDeviceToHost, s));
+    DG_HIP(hipMemcpyAsync(host + (size_t)(k0 + 1) * row, static_cast<const unsigned char*>(state) + (size_t)(k0 + 1) * row,
+                          (size_t)kc * row, hipMemcpyDeviceToHost, s));
     DG_HIP(hipEventRecord(g->ev_copy[chunk_idx & 1], s));
     ++chunk_idx;
     inflight.emplace_back(k0, kc);
@@ -303,8 +301,7 @@ dg_status drive(dg_graph* g, uint32_t max_sweeps, hipStream_t s, bool pr, Launch
     DG_HIP(hipEventSynchronize(g->ev_copy[polled & 1]));
     ++polled;
     for (uint32_t j = 0; j < kc; ++j) {
-      const unsigned char* p = host + (size_t)(k0 + j + 1) * esz;
-      if (done(p)) {
+      if (done(host + (size_t)(k0 + j + 1) * row, k0 + j)) {
         found = (int)(k0 + j);
         break;
       }
@@ -319,13 +316,32 @@ dg_status drive(dg_graph* g, uint32_t max_sweeps, hipStream_t s, bool pr, Launch
   float ms = 0.f;
   DG_HIP(hipEventElapsedTime(&ms, g->ev_start, g->ev_sweep[last % (2 * kSweepChunk)]));
   seconds = ms * 1e-3;
-  if (pr) {
-    std::memcpy(&last_entry, host + (size_t)(last + 1) * esz, sizeof(double));
-  } else {
-    last_entry = 0.0;
-  }
   return DG_OK;
 }
+
+// Pinned host buffer for the batched entry points' state polls.
+struct PinnedBuf {
+  void* p = nullptr;
+  ~PinnedBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+// Device allocations of one batched call, released when the call returns.
+struct CallAllocs {
+  dg_graph* g;
+  std::vector<void*> ptrs;
+  explicit CallAllocs(dg_graph* gg) : g(gg) {}
+  void* get(size_t bytes, hipStream_t s) {
+    void* p = dev_alloc(g, bytes, s);
+    if (p) ptrs.push_back(p);
+    return p;
+  }
+  ~CallAllocs() {
+    if (!ptrs.empty()) (void)hipDeviceSynchronize();
+    for (void* p : ptrs) dev_free(g, p);
+  }
+};
 
 }  // namespace
 
@@ -584,7 +600,7 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
     a.k = k;
     return launch_pr_sweep((int)mode, f64, a, s);
   };
-  auto done = [&](const unsigned char* p) {
+  auto done = [&](const unsigned char* p, uint32_t) {
     double r;
     std::memcpy(&r, p, sizeof r);
     return !(r >= tol);
@@ -592,7 +608,10 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
   uint32_t sweeps = 0;
   double secs = 0.0, resid = 0.0;
   bool conv = false;
-  if ((st = drive(g, max_sweeps, s, true, launch, done, sweeps, secs, conv, resid)) != DG_OK) return st;
+  unsigned char* poll = static_cast<unsigned char*>(g->host_poll);
+  if ((st = drive(g, max_sweeps, s, g->resid, sizeof(double), 1, poll, launch, done, sweeps, secs, conv)) != DG_OK)
+    return st;
+  std::memcpy(&resid, poll + (size_t)sweeps * sizeof(double), sizeof(double));
 
   double* dst = out_on_device ? out_scores : static_cast<double*>(g->vals[1]);
   if (!out_on_device && mode != DG_SYNC) dst = static_cast<double*>(g->vals[2]);
@@ -651,15 +670,17 @@ dg_status dg_sssp(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t 
     a.k = k;
     return launch_bf_sweep((int)mode, a, s);
   };
-  auto done = [&](const unsigned char* p) {
+  auto done = [&](const unsigned char* p, uint32_t) {
     uint32_t c;
     std::memcpy(&c, p, sizeof c);
     return c == 0;
   };
   uint32_t sweeps = 0;
-  double secs = 0.0, unused = 0.0;
+  double secs = 0.0;
   bool conv = false;
-  if ((st = drive(g, max_sweeps, s, false, launch, done, sweeps, secs, conv, unused)) != DG_OK) return st;
+  unsigned char* poll = static_cast<unsigned char*>(g->host_poll);
+  if ((st = drive(g, max_sweeps, s, g->changed, sizeof(uint32_t), 1, poll, launch, done, sweeps, secs, conv)) != DG_OK)
+    return st;
   // The last executed sweep k = sweeps-1 wrote buffer (k+1) % 2 in sync mode.
   const uint32_t* res = (mode == DG_SYNC && (sweeps & 1)) ? b1 : b0;
   uint32_t* dst = out_on_device ? out_dist : static_cast<uint32_t*>(g->vals[2]);
@@ -675,6 +696,242 @@ dg_status dg_sssp(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t 
     stats->residual = 0.0;
     stats->seconds = secs;
     stats->edges_traversed = g->m * (uint64_t)sweeps;
+  }
+  if (!conv) return fail(DG_ERR_NOT_CONVERGED, "no convergence within %u sweeps", max_sweeps);
+  return DG_OK;
+}
+
+// ----------------------------------------------------------- batched --
+
+namespace {
+constexpr uint32_t kBatchQ = 64;
+constexpr uint32_t kMaxBatchSweeps = 100000;
+
+dg_status check_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mode mode, uint32_t d,
+                      uint32_t max_sweeps, const void* out) {
+  if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (!sources || k == 0) return fail(DG_ERR_INVALID_ARGUMENT, "need k >= 1 sources");
+  for (uint32_t i = 0; i < k; ++i)
+    if (sources[i] >= g->n) return fail(DG_ERR_INVALID_ARGUMENT, "sources[%u] = %u >= n", i, sources[i]);
+  dg_status st = check_mode(mode, d);
+  if (st != DG_OK) return st;
+  if (max_sweeps == 0 || max_sweeps > kMaxBatchSweeps)
+    return fail(DG_ERR_INVALID_ARGUMENT, "max_sweeps must be in [1, %u] for batched queries", kMaxBatchSweeps);
+  if (!out) return fail(DG_ERR_INVALID_ARGUMENT, "output is NULL");
+  const uint64_t NB = (k + kBatchQ - 1) / kBatchQ;
+  if ((uint64_t)(g->n + g->K) * kBatchQ * 4u * NB >= (1ull << 40))
+    return fail(DG_ERR_UNSUPPORTED, "batched values would exceed 1 TiB");
+  return DG_OK;
+}
+}  // namespace
+
+dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mode mode, uint32_t d,
+                        uint32_t max_sweeps, uint32_t* out_dist, int out_on_device, dg_stats* stats,
+                        void* hip_stream) {
+  g_last_error.clear();
+  dg_status st = check_batch(g, sources, k, mode, d, max_sweeps, out_dist);
+  if (st != DG_OK) return st;
+  if (!g->has_w) return fail(DG_ERR_INVALID_ARGUMENT, "graph was created without weights");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if ((st = ensure_workspace(g, 1, s)) != DG_OK) return st;
+  const uint32_t NB = (k + kBatchQ - 1) / kBatchQ;
+  const size_t vals = (size_t)NB * (g->n + g->K) * kBatchQ;
+  CallAllocs al(g);
+  uint32_t* srcd = static_cast<uint32_t*>(al.get((size_t)k * 4, s));
+  uint32_t* b0 = static_cast<uint32_t*>(al.get(vals * 4, s));
+  uint32_t* b1 = mode == DG_SYNC ? static_cast<uint32_t*>(al.get(vals * 4, s)) : nullptr;
+  uint32_t* sh = mode == DG_DELAYED ? static_cast<uint32_t*>(al.get((size_t)NB * g->n * kBatchQ * 4, s)) : nullptr;
+  uint32_t* changed = static_cast<uint32_t*>(al.get(((size_t)max_sweeps + 1) * NB * 4, s));
+  uint32_t* outd = out_on_device ? out_dist : static_cast<uint32_t*>(al.get((size_t)k * g->n * 4, s));
+  if (!srcd || !b0 || (mode == DG_SYNC && !b1) || (mode == DG_DELAYED && !sh) || !changed || !outd)
+    return fail(DG_ERR_OUT_OF_MEMORY, "batched SSSP workspace allocation failed");
+  PinnedBuf poll;
+  DG_HIP(hipHostMalloc(&poll.p, ((size_t)max_sweeps + 1) * NB * 4, hipHostMallocDefault));
+  DG_HIP(hipMemcpyAsync(srcd, sources, (size_t)k * 4, hipMemcpyHostToDevice, s));
+  DG_HIP(launch_fill_u32(changed, ((size_t)max_sweeps + 1) * NB, 0u, s));
+  DG_HIP(launch_fill_u32(changed, NB, 1u, s));
+  DG_HIP(launch_mbf_init(b0, b1, g->cpos, srcd, k, g->n, g->K, NB, s));
+  MbfArgs a;
+  a.g = topo(g);
+  a.changed = changed;
+  a.shadow = sh;
+  a.d = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_v)) : 0u;
+  a.NB = NB;
+  auto launch = [&](uint32_t kk) {
+    if (mode == DG_SYNC) {
+      a.din = (kk & 1) ? b1 : b0;
+      a.dout = (kk & 1) ? b0 : b1;
+    } else {
+      a.din = b0;
+      a.dout = b0;
+    }
+    a.k = kk;
+    return launch_mbf_sweep((int)mode, a, s);
+  };
+  std::vector<uint32_t> bsweeps(NB, 0);
+  auto done = [&](const unsigned char* p, uint32_t kk) {
+    bool all = true;
+    for (uint32_t b = 0; b < NB; ++b) {
+      uint32_t c;
+      std::memcpy(&c, p + 4 * b, 4);
+      if (c == 0 && bsweeps[b] == 0) bsweeps[b] = kk + 1;
+      all = all && c == 0;
+    }
+    return all;
+  };
+  uint32_t sweeps = 0;
+  double secs = 0.0;
+  bool conv = false;
+  if ((st = drive(g, max_sweeps, s, changed, 4, NB, static_cast<unsigned char*>(poll.p), launch, done, sweeps, secs,
+                  conv)) != DG_OK)
+    return st;
+  // The buffer sweep `sweeps-1` wrote holds every batch's final distances:
+  // converged batches skip later sweeps, and sync sweeps alternate buffers.
+  const uint32_t* res = (mode == DG_SYNC && (sweeps & 1)) ? b1 : b0;
+  if (mode == DG_SYNC) {
+    // A batch that converged earlier stopped writing: its last write went to
+    // the buffer of its own final sweep.  Copy those rows into `res`.
+    for (uint32_t b = 0; b < NB; ++b) {
+      const uint32_t sb = bsweeps[b] ? bsweeps[b] : sweeps;
+      const uint32_t* own = (sb & 1) ? b1 : b0;
+      if (own != res) {
+        const size_t off = (size_t)b * (g->n + g->K) * kBatchQ;
+        DG_HIP(hipMemcpyAsync(const_cast<uint32_t*>(res) + off, own + off, (size_t)(g->n + g->K) * kBatchQ * 4,
+                              hipMemcpyDeviceToDevice, s));
+      }
+    }
+  }
+  DG_HIP(launch_mbf_out(res, g->cpos, g->n, g->K, k, NB, outd, s));
+  if (!out_on_device) DG_HIP(hipMemcpyAsync(out_dist, outd, (size_t)k * g->n * 4, hipMemcpyDeviceToHost, s));
+  DG_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    uint64_t qe = 0;
+    for (uint32_t b = 0; b < NB; ++b) {
+      const uint32_t nq = std::min(kBatchQ, k - b * kBatchQ);
+      qe += (uint64_t)(bsweeps[b] ? bsweeps[b] : sweeps) * nq;
+    }
+    stats->sweeps = sweeps;
+    stats->workers = g->P;
+    stats->tile_vertices = kTileV;
+    stats->commit_interval = mode == DG_DELAYED ? a.d : 0;
+    stats->residual = 0.0;
+    stats->seconds = secs;
+    stats->edges_traversed = g->m * qe;
+  }
+  if (!conv) return fail(DG_ERR_NOT_CONVERGED, "no convergence within %u sweeps", max_sweeps);
+  return DG_OK;
+}
+
+dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double damping, double tol, dg_mode mode,
+                       uint32_t d, dg_dtype dtype, uint32_t max_sweeps, double* out_scores, int out_on_device,
+                       dg_stats* stats, void* hip_stream) {
+  g_last_error.clear();
+  dg_status st = check_batch(g, sources, k, mode, d, max_sweeps, out_scores);
+  if (st != DG_OK) return st;
+  if (!(damping >= 0.0 && damping < 1.0)) return fail(DG_ERR_INVALID_ARGUMENT, "damping must be in [0, 1)");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(DG_ERR_INVALID_ARGUMENT, "tol must be finite and >= 0");
+  if (dtype != DG_F32 && dtype != DG_F64) return fail(DG_ERR_INVALID_ARGUMENT, "dtype must be DG_F32 or DG_F64");
+  const bool f64 = dtype == DG_F64;
+  const size_t esz = f64 ? 8 : 4;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if ((st = ensure_workspace(g, 1, s)) != DG_OK) return st;
+  const uint32_t NB = (k + kBatchQ - 1) / kBatchQ;
+  const size_t vals = (size_t)NB * (g->n + g->K) * kBatchQ;
+  const size_t xs = (size_t)NB * g->n * kBatchQ;
+  CallAllocs al(g);
+  uint32_t* srcd = static_cast<uint32_t*>(al.get((size_t)k * 4, s));
+  void* x = al.get(xs * esz, s);
+  void* c0 = al.get(vals * esz, s);
+  void* c1 = mode == DG_SYNC ? al.get(vals * esz, s) : nullptr;
+  void* sh = mode == DG_DELAYED ? al.get(xs * esz, s) : nullptr;
+  double* resid = static_cast<double*>(al.get(((size_t)max_sweeps + 1) * NB * 8, s));
+  uint32_t* count = static_cast<uint32_t*>(al.get(((size_t)max_sweeps + 1) * NB * 4, s));
+  double* dang = static_cast<double*>(al.get((size_t)2 * NB * kBatchQ * 8, s));
+  double* scale = static_cast<double*>(al.get((size_t)2 * NB * kBatchQ * 8, s));
+  uint32_t* qdone = static_cast<uint32_t*>(al.get((size_t)NB * kBatchQ * 4, s));
+  double* part = static_cast<double*>(al.get((size_t)g->P * NB * 3 * kBatchQ * 8, s));
+  double* qsum = static_cast<double*>(al.get((size_t)NB * kBatchQ * 8, s));
+  double* qpart = static_cast<double*>(al.get((size_t)NB * 256 * kBatchQ * 8, s));
+  double* outd = out_on_device ? out_scores : static_cast<double*>(al.get((size_t)k * g->n * 8, s));
+  if (!srcd || !x || !c0 || (mode == DG_SYNC && !c1) || (mode == DG_DELAYED && !sh) || !resid || !count || !dang ||
+      !scale || !qdone || !part || !qsum || !qpart || !outd)
+    return fail(DG_ERR_OUT_OF_MEMORY, "batched PageRank workspace allocation failed");
+  PinnedBuf poll;
+  DG_HIP(hipHostMalloc(&poll.p, ((size_t)max_sweeps + 1) * NB * 8, hipHostMallocDefault));
+  DG_HIP(hipMemcpyAsync(srcd, sources, (size_t)k * 4, hipMemcpyHostToDevice, s));
+  DG_HIP(launch_fill_f64(resid, ((size_t)max_sweeps + 1) * NB, 0.0, s));
+  DG_HIP(launch_fill_f64(resid, NB, __builtin_inf(), s));
+  DG_HIP(launch_fill_u32(count, ((size_t)max_sweeps + 1) * NB, 0u, s));
+  DG_HIP(launch_fill_f64(dang, (size_t)2 * NB * kBatchQ, 0.0, s));
+  DG_HIP(launch_fill_f64(scale, (size_t)2 * NB * kBatchQ, 1.0, s));
+  // padding lanes of the last batch start frozen
+  DG_HIP(launch_fill_u32(qdone, (size_t)k, 0u, s));
+  if ((size_t)NB * kBatchQ > k) DG_HIP(launch_fill_u32(qdone + k, (size_t)NB * kBatchQ - k, 1u, s));
+  DG_HIP(launch_mppr_init(f64, x, c0, c1, g->out_deg, g->cpos, srcd, k, g->n, g->K, NB, dang, s));
+  MpprArgs a;
+  a.g = topo(g);
+  a.x = x;
+  a.shadow = sh;
+  a.src = srcd;
+  a.resid = resid;
+  a.dang = dang;
+  a.scale = scale;
+  a.qdone = qdone;
+  a.count = count;
+  a.part = part;
+  a.alpha = damping;
+  a.tol = tol;
+  a.nq = k;
+  a.d = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_v)) : 0u;
+  a.NB = NB;
+  auto launch = [&](uint32_t kk) {
+    if (mode == DG_SYNC) {
+      a.cin = (kk & 1) ? c1 : c0;
+      a.cout = (kk & 1) ? c0 : c1;
+    } else {
+      a.cin = c0;
+      a.cout = c0;
+    }
+    a.k = kk;
+    return launch_mppr_sweep((int)mode, f64, a, s);
+  };
+  std::vector<uint32_t> bsweeps(NB, 0);
+  double last_r = 0.0;
+  auto done = [&](const unsigned char* p, uint32_t kk) {
+    bool all = true;
+    last_r = 0.0;
+    for (uint32_t b = 0; b < NB; ++b) {
+      double r;
+      std::memcpy(&r, p + 8 * b, 8);
+      const bool ok = !(r >= tol);
+      if (ok && bsweeps[b] == 0) bsweeps[b] = kk + 1;
+      if (!ok) last_r = std::max(last_r, r);
+      all = all && ok;
+    }
+    return all;
+  };
+  uint32_t sweeps = 0;
+  double secs = 0.0;
+  bool conv = false;
+  if ((st = drive(g, max_sweeps, s, resid, 8, NB, static_cast<unsigned char*>(poll.p), launch, done, sweeps, secs,
+                  conv)) != DG_OK)
+    return st;
+  DG_HIP(launch_mppr_out(f64, x, qpart, qsum, g->n, k, NB, outd, s));
+  if (!out_on_device) DG_HIP(hipMemcpyAsync(out_scores, outd, (size_t)k * g->n * 8, hipMemcpyDeviceToHost, s));
+  DG_HIP(hipStreamSynchronize(s));
+  if (stats) {
+    uint64_t qe = 0;
+    for (uint32_t b = 0; b < NB; ++b) {
+      const uint32_t nq = std::min(kBatchQ, k - b * kBatchQ);
+      qe += (uint64_t)(bsweeps[b] ? bsweeps[b] : sweeps) * nq;
+    }
+    stats->sweeps = sweeps;
+    stats->workers = g->P;
+    stats->tile_vertices = kTileV;
+    stats->commit_interval = mode == DG_DELAYED ? a.d : 0;
+    stats->residual = last_r;
+    stats->seconds = secs;
+    stats->edges_traversed = g->m * qe;
   }
   if (!conv) return fail(DG_ERR_NOT_CONVERGED, "no convergence within %u sweeps", max_sweeps);
   return DG_OK;

@@ -80,6 +80,48 @@ struct BfArgs {
   uint32_t cap;
 };
 
+// Batched queries (64 per batch, vertex-major [slot][64] values).
+struct MbfArgs {
+  Topology g;
+  const uint32_t* din;  // [NB][n+K][64] distances read
+  uint32_t* dout;       // [NB][n+K][64] distances written (== din unless synchronous)
+  uint32_t* shadow;     // [NB][n][64] delayed-mode staging, else null
+  uint32_t* changed;    // [(S+1)][NB] changed[(k+1)NB+b] != 0 iff sweep k changed batch b
+  uint32_t k, d, NB;
+};
+
+struct MpprArgs {
+  Topology g;
+  const void* cin;      // [NB][n+K][64] contributions read (float or double)
+  void* cout;           // [NB][n+K][64] contributions written
+  void* x;              // [NB][n][64] scores
+  void* shadow;         // [NB][n][64] delayed-mode staging, else null
+  const uint32_t* src;  // [nq] restart vertex of each query
+  double* resid;        // [(S+1)][NB] largest per-query L1 change of sweep k-1; entry 0 = +inf
+  double* dang;         // [2][NB][64] dangling mass (true scale) returned to the restart vertex, by sweep parity
+  double* scale;        // [2][NB][64] storage scale of each query's values, by sweep parity
+  uint32_t* qdone;      // [NB][64] 0 while a query runs, else the sweep count that stopped it
+  uint32_t* count;      // [(S+1)][NB] workers finished
+  double* part;         // [P][NB][3][64] per-worker partials (change, dangling mass, total mass)
+  double alpha, tol;
+  uint32_t nq, k, d, NB;
+};
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, size_t n, double v, hipStream_t s);
+hipError_t launch_mbf_init(uint32_t* d0, uint32_t* d1, const uint32_t* cpos, const uint32_t* src, uint32_t nq,
+                           uint32_t n, uint32_t K, uint32_t NB, hipStream_t s);
+hipError_t launch_mbf_sweep(int mode, const MbfArgs& a, hipStream_t s);
+hipError_t launch_mbf_out(const uint32_t* d, const uint32_t* cpos, uint32_t n, uint32_t K, uint32_t nq, uint32_t NB,
+                          uint32_t* out, hipStream_t s);
+hipError_t launch_mppr_init(bool f64, void* x, void* c0, void* c1, const uint32_t* out_deg, const uint32_t* cpos,
+                            const uint32_t* src, uint32_t nq, uint32_t n, uint32_t K, uint32_t NB, double* dang,
+                            hipStream_t s);
+hipError_t launch_mppr_sweep(int mode, bool f64, const MpprArgs& a, hipStream_t s);
+// qpart: [NB][256][64] float64 scratch; qsum: [NB][64]
+hipError_t launch_mppr_out(bool f64, const void* x, double* qpart, double* qsum, uint32_t n, uint32_t nq, uint32_t NB,
+                           double* out, hipStream_t s);
+
 // Launchers (enqueue only; return the launch status).
 hipError_t launch_pr_init(bool f64, void* x, void* c0, void* c1, const uint32_t* out_deg, const uint32_t* cpos,
                           uint32_t n, SweepState st, uint32_t S, double d0, hipStream_t s);

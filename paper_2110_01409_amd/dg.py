@@ -33,7 +33,7 @@ DTYPES = {"f32": DG_F32, "f64": DG_F64}
 
 # Every symbol declared in include/dg.h.
 EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_info_get", "dg_pagerank",
-           "dg_sssp", "dg_status_str", "dg_last_error", "dg_version")
+           "dg_sssp", "dg_sssp_batch", "dg_ppr_batch", "dg_status_str", "dg_last_error", "dg_version")
 
 
 class dg_stats(C.Structure):
@@ -81,6 +81,10 @@ def _load():
         "dg_pagerank": (C.c_int, [P, C.c_double, C.c_double, C.c_int, C.c_uint32, C.c_int, C.c_uint32, P, C.c_int,
                                   C.POINTER(dg_stats), P]),
         "dg_sssp": (C.c_int, [P, C.c_uint32, C.c_int, C.c_uint32, C.c_uint32, P, C.c_int, C.POINTER(dg_stats), P]),
+        "dg_sssp_batch": (C.c_int, [P, P, C.c_uint32, C.c_int, C.c_uint32, C.c_uint32, P, C.c_int,
+                                    C.POINTER(dg_stats), P]),
+        "dg_ppr_batch": (C.c_int, [P, P, C.c_uint32, C.c_double, C.c_double, C.c_int, C.c_uint32, C.c_int, C.c_uint32, P,
+                                   C.c_int, C.POINTER(dg_stats), P]),
         "dg_status_str": (C.c_char_p, [C.c_int]),
         "dg_last_error": (C.c_char_p, []),
         "dg_version": (C.c_char_p, []),
@@ -130,6 +134,15 @@ def dg_pagerank(g, damping, tol, mode, d, dtype, max_sweeps, out, out_on_device,
 
 def dg_sssp(g, src, mode, d, max_sweeps, out, out_on_device, stats, stream):
     return lib.dg_sssp(g, src, mode, d, max_sweeps, out, out_on_device, stats, stream)
+
+
+def dg_sssp_batch(g, sources, k, mode, d, max_sweeps, out, out_on_device, stats, stream):
+    return lib.dg_sssp_batch(g, sources, k, mode, d, max_sweeps, out, out_on_device, stats, stream)
+
+
+def dg_ppr_batch(g, sources, k, damping, tol, mode, d, dtype, max_sweeps, out, out_on_device, stats, stream):
+    return lib.dg_ppr_batch(g, sources, k, damping, tol, mode, d, dtype, max_sweeps, out, out_on_device, stats,
+                            stream)
 
 
 def _check(status, allow=()):
@@ -255,6 +268,37 @@ class Graph:
         st = dg_stats()
         s = _check(dg_sssp(self._h, int(src), MODES[mode], int(d), int(max_sweeps), C.c_void_p(out.data_ptr()), 1,
                            C.byref(st), _stream_handle(stream)),
+                   allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+        return out, _stats(st, s == DG_OK)
+
+    def sssp_batch(self, sources, mode="delayed", d=64, max_sweeps=None, out=None, stream=None,
+                   allow_not_converged=False):
+        """Distances from every source: uint32 tensor [k, n] on the device, Stats."""
+        import torch
+        src = np.ascontiguousarray(sources, dtype=np.uint32)
+        k = int(src.shape[0])
+        if out is None:
+            out = torch.empty((k, self.n), dtype=torch.uint32, device="cuda")
+        if max_sweeps is None:
+            max_sweeps = min(self.n + 1, 100_000)
+        st = dg_stats()
+        s = _check(dg_sssp_batch(self._h, _np_ptr(src), k, MODES[mode], int(d), int(max_sweeps),
+                                 C.c_void_p(out.data_ptr()), 1, C.byref(st), _stream_handle(stream)),
+                   allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+        return out, _stats(st, s == DG_OK)
+
+    def ppr_batch(self, sources, damping=0.85, tol=1e-6, mode="delayed", d=64, dtype="f32", max_sweeps=10_000,
+                  out=None, stream=None, allow_not_converged=False):
+        """Personalised PageRank per restart vertex: float64 tensor [k, n], Stats."""
+        import torch
+        src = np.ascontiguousarray(sources, dtype=np.uint32)
+        k = int(src.shape[0])
+        if out is None:
+            out = torch.empty((k, self.n), dtype=torch.float64, device="cuda")
+        st = dg_stats()
+        s = _check(dg_ppr_batch(self._h, _np_ptr(src), k, float(damping), float(tol), MODES[mode], int(d),
+                                DTYPES[dtype], int(max_sweeps), C.c_void_p(out.data_ptr()), 1, C.byref(st),
+                                _stream_handle(stream)),
                    allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
         return out, _stats(st, s == DG_OK)
 

@@ -1,0 +1,132 @@
+"""GPU parity of the batched entry points (64 queries per batch).
+
+* dg_sssp_batch: every row bit-exact against the oracle's Bellman-Ford from
+  that source, in every mode, with several batches and a ragged last batch.
+* dg_ppr_batch: every row within L1 1e-6 of the oracle's personalised
+  PageRank fixed point (float64, change < 1e-12), with float64 storage
+  stopping at tol 1e-9 (then the contraction bound alone guarantees
+  alpha/(1-alpha) * 1e-9 < 1e-8) and float32 storage stopping at tol 2e-7,
+  above its rounding floor of about 1e-7.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+from oracle import pagerank as opr
+from oracle import sssp as osp
+from tests import graphs as tg
+
+pytestmark = pytest.mark.gpu
+
+MODES = [("sync", 1), ("async", 1), ("delayed", 1), ("delayed", 64), ("delayed", 1024), ("delayed", 0xFFFFFFFF)]
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2110_01409_amd import dg as _dg
+    return _dg
+
+
+@pytest.mark.parametrize("name", ["rmat13", "instar", "banded"])
+def test_sssp_batch_all_modes(dg, name):
+    if name == "rmat13":
+        g = gg.rmat(13, seed=13)
+    elif name == "instar":
+        g = tg.in_star(5000)  # one hub beyond a chunk: the four-wavefront split
+    else:
+        g = gg.banded(20_000, 16, 512, 0.01, seed=4)
+    k = 70  # two batches, the second ragged
+    rng = np.random.default_rng(1)
+    sources = rng.integers(0, g.n, size=k).astype(np.uint32)
+    sources[5] = sources[6]  # a duplicate query
+    refs = {int(s): osp.bellman_ford_sync(g, int(s))[0] for s in set(sources.tolist())}
+    G = dg.Graph.from_csr(g)
+    for mode, d in MODES:
+        out, st = G.sssp_batch(sources, mode=mode, d=d)
+        got = out.cpu().numpy()
+        for q, s in enumerate(sources.tolist()):
+            np.testing.assert_array_equal(got[q], refs[s], err_msg=f"{name} {mode} d={d} query {q} src {s}")
+        assert st.converged
+        print(f"{name} sssp_batch {mode} d={d}: sweeps={st.sweeps} t={st.seconds*1e3:.2f} ms", flush=True)
+    # batched rows equal the single-query entry point
+    for s in sources[:3].tolist():
+        one, _ = G.sssp(s, mode="sync")
+        np.testing.assert_array_equal(one.cpu().numpy(), refs[s])
+    G.close()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-9), ("f32", 2e-7)])
+@pytest.mark.parametrize("name", ["rmat12", "dangling", "instar"])
+def test_ppr_batch_all_modes(dg, name, dtype, tol):
+    if name == "rmat12":
+        g = gg.rmat(12, seed=12)
+    elif name == "dangling":
+        g = tg.dangling_heavy(3000, 5)
+    else:
+        g = tg.in_star(5000)
+    k = 67
+    rng = np.random.default_rng(2)
+    sources = rng.integers(0, g.n, size=k).astype(np.uint32)
+    deg = np.diff(g.ptr.astype(np.int64))
+    sources[0] = int(np.flatnonzero(deg == 0)[0])  # a dangling restart vertex
+    refs = {int(s): opr.ppr_fixed_point(g, int(s)) for s in set(sources.tolist())}
+    G = dg.Graph.from_csr(g)
+    for mode, d in MODES:
+        out, st = G.ppr_batch(sources, tol=tol, mode=mode, d=d, dtype=dtype, max_sweeps=5000)
+        got = out.cpu().numpy()
+        errs = [np.abs(got[q] - refs[s]).sum() for q, s in enumerate(sources.tolist())]
+        print(f"{name} ppr_batch {dtype} {mode} d={d}: sweeps={st.sweeps} max L1 err={max(errs):.2e}", flush=True)
+        assert max(errs) <= (1e-8 if dtype == "f64" else 1e-6), (mode, d, max(errs))
+        assert np.abs(got.sum(axis=1) - 1.0).max() < 1e-9
+        assert st.converged
+    G.close()
+
+
+def test_ppr_batch_row_independent_of_mix(dg):
+    """Synchronous sweeps are lane-local and each query stops on its own
+    change, so a row is the same bit for bit alone and in a mixed batch."""
+    g = gg.rmat(12, seed=7)
+    rng = np.random.default_rng(5)
+    sources = rng.integers(0, g.n, size=100).astype(np.uint32)
+    G = dg.Graph.from_csr(g)
+    for dtype, tol in (("f32", 2e-7), ("f64", 1e-9)):
+        mix, _ = G.ppr_batch(sources, tol=tol, mode="sync", dtype=dtype)
+        for q in (0, 37, 99):
+            one, _ = G.ppr_batch(sources[q:q + 1], tol=tol, mode="sync", dtype=dtype)
+            np.testing.assert_array_equal(mix[q].cpu().numpy(), one[0].cpu().numpy(), err_msg=f"{dtype} query {q}")
+    G.close()
+
+
+def test_batch_validation(dg):
+    g = gg.rmat(10, seed=10)
+    G = dg.Graph.from_csr(g)
+    out = np.zeros(4 * g.n, np.uint32)
+    st = dg.dg_stats()
+    src = np.array([0, 1, g.n, 2], np.uint32)
+    assert dg.dg_sssp_batch(G._h, dg._np_ptr(src), 4, dg.DG_SYNC, 1, 100, dg._np_ptr(out), 0, C.byref(st),
+                            None) == dg.DG_ERR_INVALID_ARGUMENT
+    src = np.array([0], np.uint32)
+    assert dg.dg_sssp_batch(G._h, dg._np_ptr(src), 0, dg.DG_SYNC, 1, 100, dg._np_ptr(out), 0, C.byref(st),
+                            None) == dg.DG_ERR_INVALID_ARGUMENT
+    outf = np.zeros(g.n, np.float64)
+    assert dg.dg_ppr_batch(G._h, dg._np_ptr(src), 1, 1.5, 1e-6, dg.DG_SYNC, 1, dg.DG_F32, 100, dg._np_ptr(outf), 0,
+                           C.byref(st), None) == dg.DG_ERR_INVALID_ARGUMENT
+    assert dg.dg_ppr_batch(G._h, dg._np_ptr(src), 1, 0.85, 1e-6, dg.DG_SYNC, 1, 7, 100, dg._np_ptr(outf), 0,
+                           C.byref(st), None) == dg.DG_ERR_INVALID_ARGUMENT
+    # host outputs through the raw ABI
+    s2 = np.array([3, 7], np.uint32)
+    out2 = np.zeros(2 * g.n, np.uint32)
+    assert dg.dg_sssp_batch(G._h, dg._np_ptr(s2), 2, dg.DG_DELAYED, 64, 2000, dg._np_ptr(out2), 0, C.byref(st),
+                            None) == dg.DG_OK
+    np.testing.assert_array_equal(out2[:g.n], osp.bellman_ford_sync(g, 3)[0])
+    np.testing.assert_array_equal(out2[g.n:], osp.bellman_ford_sync(g, 7)[0])
+    outp = np.zeros(2 * g.n, np.float64)
+    assert dg.dg_ppr_batch(G._h, dg._np_ptr(s2), 2, 0.85, 1e-9, dg.DG_ASYNC, 1, dg.DG_F64, 5000, dg._np_ptr(outp),
+                           0, C.byref(st), None) == dg.DG_OK
+    assert np.abs(outp[:g.n] - opr.ppr_fixed_point(g, 3)).sum() < 1e-6
+    G.close()
