@@ -220,9 +220,10 @@ dg_status dg_sssp(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t 
  * query stops at the first sweep whose L1 change for that query is < tol and
  * its row is the iterate of that sweep (later sweeps of its batch leave it
  * untouched), so a row does not depend on the other queries of the call in
- * synchronous mode.  Float32 storage has a noise floor of about 1e-7 (the L1
- * change of a sweep cannot settle much below the rounding of a vector of
- * mass 1); ask for tol >= 2e-7 with DG_F32 or use DG_F64.
+ * synchronous mode.  Float32 storage has a noise floor: the L1 change of a
+ * sweep cannot settle much below the rounding of a vector of mass 1, about
+ * 1e-7 with synchronous commits and 1e-7 to 3e-7 with asynchronous ones;
+ * ask for tol >= 5e-7 with DG_F32, or use DG_F64.
  *   damping     0 <= damping < 1
  *   dtype       DG_F32 or DG_F64
  *   out_scores  k rows of n float64, each normalised to sum 1 */

@@ -5,8 +5,10 @@
 * dg_ppr_batch: every row within L1 1e-6 of the oracle's personalised
   PageRank fixed point (float64, change < 1e-12), with float64 storage
   stopping at tol 1e-9 (then the contraction bound alone guarantees
-  alpha/(1-alpha) * 1e-9 < 1e-8) and float32 storage stopping at tol 2e-7,
-  above its rounding floor of about 1e-7.
+  alpha/(1-alpha) * 1e-9 < 1e-8) and float32 storage stopping at tol 5e-7,
+  above its rounding floor (about 1e-7 synchronous, 1-3e-7 under
+  asynchronous commits, where each sweep reads a timing-dependent mix of
+  values that differ by rounding).
 """
 import ctypes as C
 
@@ -60,7 +62,7 @@ def test_sssp_batch_all_modes(dg, name):
     G.close()
 
 
-@pytest.mark.parametrize("dtype,tol", [("f64", 1e-9), ("f32", 2e-7)])
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-9), ("f32", 5e-7)])
 @pytest.mark.parametrize("name", ["rmat12", "dangling", "instar"])
 def test_ppr_batch_all_modes(dg, name, dtype, tol):
     if name == "rmat12":
@@ -94,7 +96,7 @@ def test_ppr_batch_row_independent_of_mix(dg):
     rng = np.random.default_rng(5)
     sources = rng.integers(0, g.n, size=100).astype(np.uint32)
     G = dg.Graph.from_csr(g)
-    for dtype, tol in (("f32", 2e-7), ("f64", 1e-9)):
+    for dtype, tol in (("f32", 5e-7), ("f64", 1e-9)):
         mix, _ = G.ppr_batch(sources, tol=tol, mode="sync", dtype=dtype)
         for q in (0, 37, 99):
             one, _ = G.ppr_batch(sources[q:q + 1], tol=tol, mode="sync", dtype=dtype)
