@@ -15,8 +15,9 @@ the timed steps.
 Besides the JSON line's required fields it reports, per commit mode, sweeps,
 time to convergence and GTEPS for PageRank float32 / float64 and SSSP; the
 roofline of the dominant kernel (the float32 delayed PageRank sweep) from
-event timing on the library's stream; and the CPU oracle's throughput on a
-bounded sample of the same workload.
+event timing on the library's stream; batched multi-source SSSP and
+personalised PageRank (256 queries) against one query at a time; and the CPU
+oracle's throughput on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -100,6 +101,8 @@ def main():
     ap.add_argument("--scale", type=int, default=22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-queries", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy five times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -221,6 +224,45 @@ def main():
             row["speedup_vs_sync_pagerank_f32"] = round(sync_pr / row["pagerank_f32"]["t_conv_ms"], 3)
             row["speedup_vs_sync_sssp"] = round(sync_bf / row["sssp_16_sources"]["t_conv_ms_total"], 3)
 
+    batched = {}
+    if not args.no_batched:
+        # Many queries on the same resident graph: batched launches against the
+        # single-query entry point called once per source, same stopping rule.
+        bsrc = gg.pick_sources(g, args.batch_queries, seed=args.scale + 1)
+        for mode in ("sync", "async", "delayed"):
+            G.sssp_batch(bsrc[:64], mode=mode, d=args.d)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out_b, sb = G.sssp_batch(bsrc, mode=mode, d=args.d)
+            torch.cuda.synchronize()
+            tb = time.perf_counter() - t
+            t = time.perf_counter()
+            e1, equal = 0, True
+            for q, src in enumerate(bsrc.tolist()):
+                o1, s1 = G.sssp(src, mode=mode, d=args.d)
+                e1 += s1.edges_traversed
+                if q % 64 == 0:
+                    equal = equal and bool((o1 == out_b[q]).all())
+            torch.cuda.synchronize()
+            t1 = time.perf_counter() - t
+            G.ppr_batch(bsrc[:64], tol=1e-6, mode=mode, d=args.d)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, sp = G.ppr_batch(bsrc, tol=1e-6, mode=mode, d=args.d, dtype="f32")
+            torch.cuda.synchronize()
+            tp = time.perf_counter() - t
+            batched[mode] = {
+                "sssp": {"queries": len(bsrc), "batched_ms": round(tb * 1e3, 2), "batched_sweeps": sb.sweeps,
+                         "batched_gteps": round(sb.edges_traversed / tb / 1e9, 1),
+                         "one_at_a_time_ms": round(t1 * 1e3, 2), "one_at_a_time_gteps": round(e1 / t1 / 1e9, 1),
+                         "speedup": round(t1 / tb, 2), "rows_equal_sampled": equal},
+                "ppr_f32_tol1e-6": {"queries": len(bsrc), "batched_ms": round(tp * 1e3, 2),
+                                    "batched_sweeps": sp.sweeps,
+                                    "batched_gteps": round(sp.edges_traversed / tp / 1e9, 1)}}
+            log(f"batched {mode}: SSSP x{len(bsrc)} {tb * 1e3:.1f} ms vs one-at-a-time {t1 * 1e3:.1f} ms "
+                f"({t1 / tb:.1f}x, rows equal {equal}); PPR x{len(bsrc)} {tp * 1e3:.1f} ms "
+                f"({sp.edges_traversed / tp / 1e9:.0f} GTEPS)")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(g)
@@ -247,6 +289,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "modes": modes,
+        "batched": batched,
     }
     G.close()
     print(json.dumps(out), flush=True)

@@ -14,11 +14,24 @@
 #include <vector>
 
 #include "dg.h"
+#include "dg_host.hpp"
 #include "dg_internal.hpp"
 
 using namespace dg;
+using dg::host::fail;
+using dg::host::g_last_error;
 
 namespace {
+
+std::mutex g_alloc_mu;
+dg_alloc_fn g_alloc = nullptr;
+dg_free_fn g_free = nullptr;
+void* g_alloc_ctx = nullptr;
+
+}  // namespace
+
+namespace dg {
+namespace host {
 
 thread_local std::string g_last_error;
 
@@ -32,10 +45,37 @@ dg_status fail(dg_status s, const char* fmt, ...) {
   return s;
 }
 
-std::mutex g_alloc_mu;
-dg_alloc_fn g_alloc = nullptr;
-dg_free_fn g_free = nullptr;
-void* g_alloc_ctx = nullptr;
+void current_allocator(dg_alloc_fn& alloc, dg_free_fn& free_fn, void*& ctx) {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  alloc = g_alloc;
+  free_fn = g_free;
+  ctx = g_alloc_ctx;
+}
+
+void build_tiles(const std::vector<uint32_t>& in_ptr, uint32_t n, std::vector<uint32_t>& tile_v) {
+  tile_v.clear();
+  tile_v.push_back(0);
+  uint32_t nv = 0;
+  uint64_t ne = 0;
+  for (uint32_t v = 0; v < n; ++v) {
+    const uint64_t deg = in_ptr[v + 1] - in_ptr[v];
+    if (nv > 0 && (nv == (uint32_t)kTileV || ne + deg > (uint64_t)kTileE)) {
+      tile_v.push_back(v);
+      nv = 0;
+      ne = 0;
+    }
+    ++nv;
+    ne += deg;
+  }
+  if (tile_v.back() != n) tile_v.push_back(n);
+}
+
+}  // namespace host
+}  // namespace dg
+
+using dg::host::build_tiles;
+
+namespace {
 
 // Sweeps queued ahead of the host's convergence check.  Each queued sweep
 // first tests on the device whether an earlier one met the stopping rule.
@@ -116,37 +156,6 @@ void release_all(dg_graph* g) {
   std::vector<void*> all = g->owned;
   for (void* p : all) dev_free(g, p);
   g->owned.clear();
-}
-
-#define DG_HIP(call)                                                                  \
-  do {                                                                                \
-    hipError_t e_ = (call);                                                           \
-    if (e_ != hipSuccess) {                                                           \
-      (void)hipGetLastError();                                                        \
-      return fail(e_ == hipErrorOutOfMemory ? DG_ERR_OUT_OF_MEMORY : DG_ERR_DEVICE,   \
-                  "%s failed: %s", #call, hipGetErrorString(e_));                     \
-    }                                                                                 \
-  } while (0)
-
-// Tiles: consecutive vertices, at most kTileV of them and at most kTileE
-// in-edges, except that a vertex with more than kTileE in-edges is a tile of
-// its own.
-void build_tiles(const std::vector<uint32_t>& in_ptr, uint32_t n, std::vector<uint32_t>& tile_v) {
-  tile_v.clear();
-  tile_v.push_back(0);
-  uint32_t nv = 0;
-  uint64_t ne = 0;
-  for (uint32_t v = 0; v < n; ++v) {
-    const uint64_t deg = in_ptr[v + 1] - in_ptr[v];
-    if (nv > 0 && (nv == (uint32_t)kTileV || ne + deg > (uint64_t)kTileE)) {
-      tile_v.push_back(v);
-      nv = 0;
-      ne = 0;
-    }
-    ++nv;
-    ne += deg;
-  }
-  if (tile_v.back() != n) tile_v.push_back(n);
 }
 
 // Blocked partition of the tiles over P workers (section III-A: contiguous

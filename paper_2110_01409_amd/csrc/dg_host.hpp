@@ -1,0 +1,40 @@
+// Host-side helpers shared by the translation units of the C ABI
+// (dg_api.cpp: single graphs and batched queries; dg_set.cpp: graph sets).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dg.h"
+
+namespace dg {
+namespace host {
+
+// Message of the last error on the calling thread (dg_last_error).
+extern thread_local std::string g_last_error;
+
+// Records a printf-style message and returns s.
+dg_status fail(dg_status s, const char* fmt, ...);
+
+// Allocation hooks installed by dg_set_allocator (both null: hipMalloc/hipFree).
+void current_allocator(dg_alloc_fn& alloc, dg_free_fn& free_fn, void*& ctx);
+
+// Tiles of consecutive vertices: at most kTileV vertices and kTileE in-edges,
+// except that a vertex with more in-edges is a tile of its own.
+void build_tiles(const std::vector<uint32_t>& in_ptr, uint32_t n, std::vector<uint32_t>& tile_v);
+
+}  // namespace host
+}  // namespace dg
+
+#define DG_HIP(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      (void)hipGetLastError();                                                                \
+      return ::dg::host::fail(e_ == hipErrorOutOfMemory ? DG_ERR_OUT_OF_MEMORY : DG_ERR_DEVICE, \
+                              "%s failed: %s", #call, hipGetErrorString(e_));                 \
+    }                                                                                         \
+  } while (0)

@@ -1,13 +1,12 @@
 """Python binding of the C ABI in include/dg.h (argument marshalling only).
 
-The functions ``dg_graph_create``, ``dg_graph_destroy``, ``dg_graph_info_get``,
-``dg_pagerank``, ``dg_sssp``, ``dg_set_allocator``, ``dg_status_str``,
-``dg_last_error`` and ``dg_version`` are the C entry points, loaded with
-ctypes from the in-tree ``libdg.so``.  Every step of a sweep runs in the HIP
+The ``dg_*`` functions are the C entry points (every symbol of the header,
+listed in ``EXPORTS``), loaded with ctypes from the in-tree ``libdg.so``.  Every step of a sweep runs in the HIP
 library; PyTorch only provides device memory (its caching allocator is
 registered as the library's allocator) and the stream.
 
-``Graph`` wraps a handle with keyword defaults.  If the library is missing,
+``Graph`` wraps a graph handle and ``GraphSet`` a set handle, with keyword
+defaults.  If the library is missing,
 importing this module raises: there is no CPU fallback.
 """
 from __future__ import annotations
@@ -33,7 +32,9 @@ DTYPES = {"f32": DG_F32, "f64": DG_F64}
 
 # Every symbol declared in include/dg.h.
 EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_info_get", "dg_pagerank",
-           "dg_sssp", "dg_sssp_batch", "dg_ppr_batch", "dg_status_str", "dg_last_error", "dg_version")
+           "dg_sssp", "dg_sssp_batch", "dg_ppr_batch", "dg_set_create", "dg_set_destroy", "dg_set_info_get",
+           "dg_set_pagerank", "dg_set_sssp", "dg_status_str", "dg_last_error", "dg_version")
+DG_SET_EAGER = 1
 
 
 class dg_stats(C.Structure):
@@ -54,6 +55,20 @@ class dg_graph_opts(C.Structure):
 
 
 DG_HOT_AUTO = 0xFFFFFFFF
+
+
+class dg_graph_desc(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("m", C.c_uint64), ("ptr", C.c_void_p), ("idx", C.c_void_p),
+                ("w", C.c_void_p)]
+
+
+class dg_set_opts(C.Structure):
+    _fields_ = [("workers", C.c_uint32)]
+
+
+class dg_set_info(C.Structure):
+    _fields_ = [("graphs", C.c_uint32), ("n", C.c_uint64), ("m", C.c_uint64), ("tiles", C.c_uint32),
+                ("workers", C.c_uint32), ("has_weights", C.c_uint32), ("device_bytes", C.c_uint64)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
@@ -85,6 +100,13 @@ def _load():
                                     C.POINTER(dg_stats), P]),
         "dg_ppr_batch": (C.c_int, [P, P, C.c_uint32, C.c_double, C.c_double, C.c_int, C.c_uint32, C.c_int, C.c_uint32, P,
                                    C.c_int, C.POINTER(dg_stats), P]),
+        "dg_set_create": (C.c_int, [C.c_uint32, P, C.POINTER(dg_set_opts), P, C.POINTER(C.c_void_p)]),
+        "dg_set_destroy": (C.c_int, [P]),
+        "dg_set_info_get": (C.c_int, [P, C.POINTER(dg_set_info)]),
+        "dg_set_pagerank": (C.c_int, [P, C.c_double, C.c_double, C.c_int, C.c_uint32, C.c_int, C.c_uint32,
+                                      C.c_uint32, P, C.c_int, P, C.POINTER(dg_stats), P]),
+        "dg_set_sssp": (C.c_int, [P, P, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, P, C.c_int, P,
+                                  C.POINTER(dg_stats), P]),
         "dg_status_str": (C.c_char_p, [C.c_int]),
         "dg_last_error": (C.c_char_p, []),
         "dg_version": (C.c_char_p, []),
@@ -143,6 +165,28 @@ def dg_sssp_batch(g, sources, k, mode, d, max_sweeps, out, out_on_device, stats,
 def dg_ppr_batch(g, sources, k, damping, tol, mode, d, dtype, max_sweeps, out, out_on_device, stats, stream):
     return lib.dg_ppr_batch(g, sources, k, damping, tol, mode, d, dtype, max_sweeps, out, out_on_device, stats,
                             stream)
+
+
+def dg_set_create(count, graphs, opts, stream, out):
+    return lib.dg_set_create(count, graphs, opts, stream, out)
+
+
+def dg_set_destroy(s):
+    return lib.dg_set_destroy(s)
+
+
+def dg_set_info_get(s, info):
+    return lib.dg_set_info_get(s, info)
+
+
+def dg_set_pagerank(s, damping, tol, mode, d, dtype, max_sweeps, flags, out, out_on_device, out_sweeps, stats,
+                    stream):
+    return lib.dg_set_pagerank(s, damping, tol, mode, d, dtype, max_sweeps, flags, out, out_on_device, out_sweeps,
+                               stats, stream)
+
+
+def dg_set_sssp(s, sources, mode, d, max_sweeps, flags, out, out_on_device, out_sweeps, stats, stream):
+    return lib.dg_set_sssp(s, sources, mode, d, max_sweeps, flags, out, out_on_device, out_sweeps, stats, stream)
 
 
 def _check(status, allow=()):
@@ -318,3 +362,83 @@ class Graph:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class GraphSet:
+    """Many graphs resident together and swept in one launch per sweep.
+
+    ``GraphSet(graphs)`` takes ``graphgen.CSRGraph`` objects (all weighted or
+    all unweighted).  Results are flat tensors over the union of the graphs'
+    vertices; ``offsets[i]`` is graph i's first vertex and ``split(t)`` cuts
+    a result into per-graph views.
+    """
+
+    def __init__(self, graphs, workers=0, stream=None, torch_allocator=True):
+        if torch_allocator:
+            use_torch_allocator()
+        self._keep = []
+        descs = (dg_graph_desc * len(graphs))()
+        for i, g in enumerate(graphs):
+            ptr = np.ascontiguousarray(g.ptr, dtype=np.uint64)
+            idx = np.ascontiguousarray(g.idx, dtype=np.uint32)
+            w = None if g.w is None else np.ascontiguousarray(g.w, dtype=np.uint32)
+            self._keep.append((ptr, idx, w))
+            descs[i] = dg_graph_desc(int(g.n), int(idx.shape[0]), ptr.ctypes.data, idx.ctypes.data,
+                                     None if w is None else w.ctypes.data)
+        h = C.c_void_p()
+        opts = dg_set_opts(int(workers))
+        _check(dg_set_create(len(graphs), descs, C.byref(opts), _stream_handle(stream), C.byref(h)))
+        self._keep = None  # the library copied the arrays
+        self._h = h
+        self.sizes = [int(g.n) for g in graphs]
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        self.n = int(self.offsets[-1])
+
+    def info(self) -> dg_set_info:
+        i = dg_set_info()
+        _check(dg_set_info_get(self._h, C.byref(i)))
+        return i
+
+    def split(self, t):
+        return [t[self.offsets[i]:self.offsets[i + 1]] for i in range(len(self.sizes))]
+
+    def pagerank(self, damping=0.85, tol=1e-6, mode="delayed", d=64, dtype="f32", max_sweeps=10_000, eager=False,
+                 stream=None, allow_not_converged=False):
+        """Per-graph PageRank: (float64 tensor [n], per-graph sweeps, Stats)."""
+        import torch
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        sw = np.zeros(len(self.sizes), np.uint32)
+        st = dg_stats()
+        s = _check(dg_set_pagerank(self._h, float(damping), float(tol), MODES[mode], int(d), DTYPES[dtype],
+                                   int(max_sweeps), DG_SET_EAGER if eager else 0, C.c_void_p(out.data_ptr()), 1,
+                                   _np_ptr(sw), C.byref(st), _stream_handle(stream)),
+                   allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+        return out, sw, _stats(st, s == DG_OK)
+
+    def sssp(self, sources, mode="delayed", d=64, max_sweeps=None, eager=False, stream=None,
+             allow_not_converged=False):
+        """Per-graph Bellman-Ford from sources[i] (local ids): (uint32 tensor
+        [n] of distances, per-graph sweeps, Stats)."""
+        import torch
+        src = np.ascontiguousarray(sources, dtype=np.uint32)
+        if max_sweeps is None:
+            max_sweeps = min(max(self.sizes) + 1, 1_000_000)
+        out = torch.empty(self.n, dtype=torch.uint32, device="cuda")
+        sw = np.zeros(len(self.sizes), np.uint32)
+        st = dg_stats()
+        s = _check(dg_set_sssp(self._h, _np_ptr(src), MODES[mode], int(d), int(max_sweeps),
+                               DG_SET_EAGER if eager else 0, C.c_void_p(out.data_ptr()), 1, _np_ptr(sw),
+                               C.byref(st), _stream_handle(stream)),
+                   allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+        return out, sw, _stats(st, s == DG_OK)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            dg_set_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -106,3 +106,63 @@ def test_allocator_hooks_must_pair(dg):
     alloc = dg.ALLOC_FN(lambda n, s, c: None)
     assert dg.lib.dg_set_allocator(alloc, dg.FREE_FN(), None) == dg.DG_ERR_INVALID_ARGUMENT
     assert dg.lib.dg_set_allocator(dg.ALLOC_FN(), dg.FREE_FN(), None) == dg.DG_OK
+
+
+def _descs(dg, graphs):
+    keep, arr = [], (dg.dg_graph_desc * max(1, len(graphs)))()
+    for i, (n, ptr, idx, w) in enumerate(graphs):
+        ptr = np.ascontiguousarray(ptr, np.uint64)
+        idx = np.ascontiguousarray(idx, np.uint32)
+        w = None if w is None else np.ascontiguousarray(w, np.uint32)
+        keep.append((ptr, idx, w))
+        arr[i] = dg.dg_graph_desc(n, idx.shape[0], ptr.ctypes.data, idx.ctypes.data,
+                                  None if w is None else w.ctypes.data)
+    return arr, keep
+
+
+GOOD = (3, [0, 1, 3, 3], [1, 0, 2], [5, 6, 7])
+
+
+@pytest.mark.parametrize("case", ["empty", "n0", "ptr_end", "idx_range", "mixed_weights", "decreasing"])
+def test_set_create_validation(dg, case):
+    graphs = [GOOD, GOOD]
+    if case == "n0":
+        graphs = [GOOD, (0, [0], [], None)]
+    elif case == "ptr_end":
+        graphs = [GOOD, (3, [0, 1, 2, 2], [1, 0, 2], [1, 1, 1])]
+    elif case == "idx_range":
+        graphs = [GOOD, (3, [0, 1, 3, 3], [1, 0, 3], [1, 1, 1])]
+    elif case == "mixed_weights":
+        graphs = [GOOD, (3, [0, 1, 3, 3], [1, 0, 2], None)]
+    elif case == "decreasing":
+        graphs = [GOOD, (3, [0, 2, 1, 3], [1, 0, 2], [1, 1, 1])]
+    arr, keep = _descs(dg, graphs)
+    h = C.c_void_p()
+    s = dg.dg_set_create(0 if case == "empty" else len(graphs), arr, None, None, C.byref(h))
+    assert s == dg.DG_ERR_INVALID_ARGUMENT, dg.last_error()
+    assert dg.last_error()
+    assert not h.value
+
+
+def test_set_valid_without_device(dg):
+    import torch
+    arr, keep = _descs(dg, [GOOD, (1, [0, 0], [], [])])
+    h = C.c_void_p()
+    s = dg.dg_set_create(2, arr, None, None, C.byref(h))
+    if torch.cuda.is_available():
+        assert s == dg.DG_OK
+        dg.dg_set_destroy(h)
+    else:
+        assert s == dg.DG_ERR_DEVICE and "device" in dg.last_error()
+
+
+def test_set_call_validation_null(dg):
+    out = np.zeros(4, np.float64)
+    st = dg.dg_stats()
+    assert dg.dg_set_pagerank(None, 0.85, 1e-6, 0, 1, 0, 10, 0, dg._np_ptr(out), 0, None, C.byref(st), None) == \
+        dg.DG_ERR_INVALID_ARGUMENT
+    src = np.zeros(1, np.uint32)
+    assert dg.dg_set_sssp(None, dg._np_ptr(src), 0, 1, 10, 0, dg._np_ptr(out), 0, None, C.byref(st), None) == \
+        dg.DG_ERR_INVALID_ARGUMENT
+    assert dg.dg_set_destroy(None) == dg.DG_OK
+    assert dg.dg_set_info_get(None, None) == dg.DG_ERR_INVALID_ARGUMENT
