@@ -102,6 +102,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-topology", action="store_true")
     ap.add_argument("--batch-queries", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy five times (reference for HBM byte counters)")
@@ -263,6 +264,46 @@ def main():
                 f"({t1 / tb:.1f}x, rows equal {equal}); PPR x{len(bsrc)} {tp * 1e3:.1f} ms "
                 f"({sp.edges_traversed / tp / 1e9:.0f} GTEPS)")
 
+    topology = {}
+    if not args.no_topology:
+        # Access matrices (reads by worker group of values owned by group) of the
+        # workload and of a banded graph of the same size, next to each graph's
+        # gain from delaying commits over committing at once.
+        def mode_times(GG, srcs):
+            out = {}
+            for mode, d in (("async", 0), ("delayed", 64), ("delayed", 1024), ("delayed", dg.DG_D_WHOLE)):
+                key = mode if mode == "async" else f"delayed_d{'whole' if d == dg.DG_D_WHOLE else d}"
+                pr = min(GG.pagerank(tol=1e-6, mode=mode, d=max(d, 1), dtype="f32")[1].seconds for _ in range(3))
+                bf = sum(GG.sssp(int(x), mode=mode, d=max(d, 1))[1].seconds for x in srcs)
+                out[key] = {"pagerank_f32_ms": round(pr * 1e3, 3), "sssp_ms": round(bf * 1e3, 3)}
+            best_pr = min(v["pagerank_f32_ms"] for k, v in out.items() if k != "async")
+            best_bf = min(v["sssp_ms"] for k, v in out.items() if k != "async")
+            out["delay_gain_pagerank"] = round(out["async"]["pagerank_f32_ms"] / best_pr, 3)
+            out["delay_gain_sssp"] = round(out["async"]["sssp_ms"] / best_bf, 3)
+            return out
+
+        def access(GG):
+            res = {}
+            for groups in (8, 32):
+                _, st = GG.access_matrix(groups)
+                res[f"groups{groups}"] = {"diagonal_share": round(st.diagonal_share, 4),
+                                          "uniform_diagonal": round(st.uniform_diagonal, 4),
+                                          "lift": round(st.diagonal_share / max(st.uniform_diagonal, 1e-12), 2)}
+            res["self_share"] = round(st.self_share, 4)
+            return res
+
+        topology[f"rmat{args.scale}"] = {"access": access(G), "modes": mode_times(G, sources[:4])}
+        gb = gg.banded(n, 16, 4096, 0.01, seed=args.scale)
+        GB = dg.Graph.from_csr(gb)
+        topology[gb.name] = {"n": gb.n, "m": gb.m, "access": access(GB),
+                             "modes": mode_times(GB, gg.pick_sources(gb, 4, seed=1).tolist())}
+        GB.close()
+        del gb
+        for k, v in topology.items():
+            log(f"topology {k}: diagonal share (32 groups) {v['access']['groups32']['diagonal_share']} "
+                f"(lift {v['access']['groups32']['lift']}), self share {v['access']['self_share']}; "
+                f"delay gain PR {v['modes']['delay_gain_pagerank']}x, SSSP {v['modes']['delay_gain_sssp']}x")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(g)
@@ -290,6 +331,7 @@ def main():
         "cpu_baseline": cpu,
         "modes": modes,
         "batched": batched,
+        "topology": topology,
     }
     G.close()
     print(json.dumps(out), flush=True)

@@ -234,6 +234,37 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
                        dg_mode mode, uint32_t d, dg_dtype dtype, uint32_t max_sweeps, double* out_scores,
                        int out_on_device, dg_stats* stats, void* hip_stream);
 
+/* The static blocked partition (section III-A) of a graph: worker w owns
+ * vertices [out_first_vertex[w], out_first_vertex[w+1]).
+ *   out_first_vertex  host array of workers + 1 entries (dg_graph_info) */
+dg_status dg_graph_partition(const dg_graph* g, uint32_t* out_first_vertex, void* hip_stream);
+
+/* Topology instrumentation (section IV, effects of graph topology, Fig. 5):
+ * the access matrix of one pull sweep under the graph's static blocked
+ * partition.  Each in-edge u -> v is a read, by the worker owning v, of the
+ * value the worker owning u writes; workers are coarsened into `groups`
+ * groups of consecutive workers (8 groups = one per XCD), giving a coarsened
+ * adjacency matrix.  The paper finds that delaying commits pays little when
+ * reads cluster on the diagonal (a worker mostly reads what it writes itself)
+ * and pays when they are spread.
+ *   groups      1 <= groups <= min(64, workers)
+ *   out_counts  host array of groups*groups (row: reading group, column:
+ *               owning group), or NULL
+ *   stats       totals and shares, or NULL (not both NULL) */
+typedef struct {
+  uint64_t reads;           /* in-edges: the gathers of one sweep */
+  uint64_t same_worker;     /* reads of a value the reading worker writes itself */
+  uint64_t diagonal;        /* reads within the reading group (matrix diagonal) */
+  uint32_t groups;
+  uint32_t workers;
+  double self_share;        /* same_worker / reads */
+  double diagonal_share;    /* diagonal / reads */
+  double uniform_diagonal;  /* diagonal share expected if reads ignored the reader:
+                               sum over groups of row share x column share */
+} dg_access_stats;
+dg_status dg_access_matrix(dg_graph* g, uint32_t groups, uint64_t* out_counts, dg_access_stats* stats,
+                           void* hip_stream);
+
 /* Graph sets (a form beyond the paper's single graph: many graphs, of uneven
  * sizes, resident together and swept in one launch per sweep).  The graphs
  * are stored as one union graph; tiles never span two graphs and workgroups

@@ -561,6 +561,62 @@ dg_status dg_graph_info_get(const dg_graph* g, dg_graph_info* info) {
   return DG_OK;
 }
 
+dg_status dg_graph_partition(const dg_graph* g, uint32_t* out_first_vertex, void* hip_stream) {
+  g_last_error.clear();
+  if (!g || !out_first_vertex) return fail(DG_ERR_INVALID_ARGUMENT, "NULL argument");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  std::vector<uint32_t> wt(g->P + 1), tv((size_t)g->T + 1);
+  DG_HIP(hipMemcpyAsync(wt.data(), g->work_t, wt.size() * 4, hipMemcpyDeviceToHost, s));
+  DG_HIP(hipMemcpyAsync(tv.data(), g->tile_v, tv.size() * 4, hipMemcpyDeviceToHost, s));
+  DG_HIP(hipStreamSynchronize(s));
+  for (uint32_t w = 0; w <= g->P; ++w) out_first_vertex[w] = tv[wt[w]];
+  return DG_OK;
+}
+
+dg_status dg_access_matrix(dg_graph* g, uint32_t groups, uint64_t* out_counts, dg_access_stats* stats,
+                           void* hip_stream) {
+  g_last_error.clear();
+  if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (groups < 1 || groups > 64 || groups > g->P)
+    return fail(DG_ERR_INVALID_ARGUMENT, "groups = %u outside [1, min(64, workers = %u)]", groups, g->P);
+  if (!out_counts && !stats) return fail(DG_ERR_INVALID_ARGUMENT, "nothing to return");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  CallAllocs al(g);
+  uint32_t* vw = static_cast<uint32_t*>(al.get((size_t)g->n * 4, s));
+  uint32_t* inv = static_cast<uint32_t*>(al.get((size_t)std::max(g->K, 1u) * 4, s));
+  unsigned long long* cnt = static_cast<unsigned long long*>(al.get(((size_t)groups * groups + 1) * 8, s));
+  if (!vw || !inv || !cnt) return fail(DG_ERR_OUT_OF_MEMORY, "access matrix workspace allocation failed");
+  DG_HIP(hipMemsetAsync(cnt, 0, ((size_t)groups * groups + 1) * 8, s));
+  DG_HIP(launch_access_matrix(topo(g), vw, inv, groups, cnt, cnt + (size_t)groups * groups, s));
+  std::vector<unsigned long long> h((size_t)groups * groups + 1);
+  DG_HIP(hipMemcpyAsync(h.data(), cnt, h.size() * 8, hipMemcpyDeviceToHost, s));
+  DG_HIP(hipStreamSynchronize(s));
+  uint64_t total = 0, diag = 0;
+  std::vector<double> row(groups, 0.0), col(groups, 0.0);
+  for (uint32_t r = 0; r < groups; ++r)
+    for (uint32_t c = 0; c < groups; ++c) {
+      const uint64_t x = h[(size_t)r * groups + c];
+      total += x;
+      if (r == c) diag += x;
+      row[r] += (double)x;
+      col[c] += (double)x;
+      if (out_counts) out_counts[(size_t)r * groups + c] = x;
+    }
+  if (stats) {
+    stats->reads = total;
+    stats->same_worker = h.back();
+    stats->diagonal = diag;
+    stats->groups = groups;
+    stats->workers = g->P;
+    stats->self_share = total ? (double)h.back() / (double)total : 0.0;
+    stats->diagonal_share = total ? (double)diag / (double)total : 0.0;
+    double u = 0.0;
+    for (uint32_t r = 0; r < groups; ++r) u += row[r] * col[r];
+    stats->uniform_diagonal = total ? u / ((double)total * (double)total) : 0.0;
+  }
+  return DG_OK;
+}
+
 dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uint32_t d, dg_dtype dtype,
                       uint32_t max_sweeps, double* out_scores, int out_on_device, dg_stats* stats,
                       void* hip_stream) {

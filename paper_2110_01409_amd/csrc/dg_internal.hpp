@@ -199,4 +199,10 @@ hipError_t launch_set_bf_sweep(int mode, const SetBfArgs& a, hipStream_t s);
 // last_k: index of the last sweep run (buffer choice for graphs that did not converge)
 hipError_t launch_set_bf_out(int mode, const SetBfArgs& a, uint32_t last_k, uint32_t* out, hipStream_t s);
 
+// Access matrix of one pull sweep: counts[r * B + c] += reads by worker group r
+// of values written by group c; *self += reads of a value the reader writes.
+// vw: [n] scratch (worker of each vertex), inv: [K] scratch (vertex of each hot slot).
+hipError_t launch_access_matrix(const Topology& g, uint32_t* vw, uint32_t* inv, uint32_t B,
+                                unsigned long long* counts, unsigned long long* self, hipStream_t s);
+
 }  // namespace dg

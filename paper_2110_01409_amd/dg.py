@@ -33,7 +33,8 @@ DTYPES = {"f32": DG_F32, "f64": DG_F64}
 # Every symbol declared in include/dg.h.
 EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_info_get", "dg_pagerank",
            "dg_sssp", "dg_sssp_batch", "dg_ppr_batch", "dg_set_create", "dg_set_destroy", "dg_set_info_get",
-           "dg_set_pagerank", "dg_set_sssp", "dg_status_str", "dg_last_error", "dg_version")
+           "dg_set_pagerank", "dg_set_sssp", "dg_graph_partition", "dg_access_matrix", "dg_status_str",
+           "dg_last_error", "dg_version")
 DG_SET_EAGER = 1
 
 
@@ -60,6 +61,12 @@ DG_HOT_AUTO = 0xFFFFFFFF
 class dg_graph_desc(C.Structure):
     _fields_ = [("n", C.c_uint32), ("m", C.c_uint64), ("ptr", C.c_void_p), ("idx", C.c_void_p),
                 ("w", C.c_void_p)]
+
+
+class dg_access_stats(C.Structure):
+    _fields_ = [("reads", C.c_uint64), ("same_worker", C.c_uint64), ("diagonal", C.c_uint64),
+                ("groups", C.c_uint32), ("workers", C.c_uint32), ("self_share", C.c_double),
+                ("diagonal_share", C.c_double), ("uniform_diagonal", C.c_double)]
 
 
 class dg_set_opts(C.Structure):
@@ -107,6 +114,8 @@ def _load():
                                       C.c_uint32, P, C.c_int, P, C.POINTER(dg_stats), P]),
         "dg_set_sssp": (C.c_int, [P, P, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, P, C.c_int, P,
                                   C.POINTER(dg_stats), P]),
+        "dg_graph_partition": (C.c_int, [P, P, P]),
+        "dg_access_matrix": (C.c_int, [P, C.c_uint32, P, C.POINTER(dg_access_stats), P]),
         "dg_status_str": (C.c_char_p, [C.c_int]),
         "dg_last_error": (C.c_char_p, []),
         "dg_version": (C.c_char_p, []),
@@ -187,6 +196,14 @@ def dg_set_pagerank(s, damping, tol, mode, d, dtype, max_sweeps, flags, out, out
 
 def dg_set_sssp(s, sources, mode, d, max_sweeps, flags, out, out_on_device, out_sweeps, stats, stream):
     return lib.dg_set_sssp(s, sources, mode, d, max_sweeps, flags, out, out_on_device, out_sweeps, stats, stream)
+
+
+def dg_graph_partition(g, out_first_vertex, stream):
+    return lib.dg_graph_partition(g, out_first_vertex, stream)
+
+
+def dg_access_matrix(g, groups, out_counts, stats, stream):
+    return lib.dg_access_matrix(g, groups, out_counts, stats, stream)
 
 
 def _check(status, allow=()):
@@ -345,6 +362,20 @@ class Graph:
                                 _stream_handle(stream)),
                    allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
         return out, _stats(st, s == DG_OK)
+
+    def partition(self, stream=None):
+        """First vertex of each worker's block: uint32 array [workers + 1]."""
+        out = np.zeros(self.info().workers + 1, np.uint32)
+        _check(dg_graph_partition(self._h, _np_ptr(out), _stream_handle(stream)))
+        return out
+
+    def access_matrix(self, groups=32, stream=None):
+        """Reads of one pull sweep by reading worker group (rows) into values
+        owned by group (columns): (uint64 array [groups, groups], dg_access_stats)."""
+        out = np.zeros((groups, groups), np.uint64)
+        st = dg_access_stats()
+        _check(dg_access_matrix(self._h, int(groups), _np_ptr(out), C.byref(st), _stream_handle(stream)))
+        return out, st
 
     def close(self):
         if getattr(self, "_h", None):

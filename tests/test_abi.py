@@ -166,3 +166,10 @@ def test_set_call_validation_null(dg):
         dg.DG_ERR_INVALID_ARGUMENT
     assert dg.dg_set_destroy(None) == dg.DG_OK
     assert dg.dg_set_info_get(None, None) == dg.DG_ERR_INVALID_ARGUMENT
+
+
+def test_topology_call_validation_null(dg):
+    st = dg.dg_access_stats()
+    assert dg.dg_access_matrix(None, 8, None, C.byref(st), None) == dg.DG_ERR_INVALID_ARGUMENT
+    out = np.zeros(4, np.uint32)
+    assert dg.dg_graph_partition(None, dg._np_ptr(out), None) == dg.DG_ERR_INVALID_ARGUMENT

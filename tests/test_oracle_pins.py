@@ -356,3 +356,41 @@ def test_ppr_dense_and_networkx(seed):
     ref = np.array([ref[i] for i in range(g.n)])
     assert np.abs(x - ref).sum() < 1e-10
     assert opr.ppr_certificate(g, x, s) < 1e-9
+
+
+# ------------------------------------------------------------ access matrix --
+
+def test_access_matrix_matches_loops_and_invariants():
+    from oracle import topology as otop
+    g = gg.rmat(7, seed=3)
+    first = [0, 10, 40, 41, 90, g.n]  # uneven blocks, one of a single vertex
+    for groups in (1, 2, 5):
+        a, sa = otop.access_matrix(g, first, groups)
+        b, sb = otop.access_matrix_loops(g, first, groups)
+        np.testing.assert_array_equal(a, b)
+        assert sa == sb
+        assert a.sum() == g.m  # every edge is one read
+    one, _ = otop.access_matrix(g, first, 1)
+    assert one[0, 0] == g.m
+
+
+def test_access_matrix_special_cases():
+    from oracle import topology as otop
+    n = 12
+    # only self-loops: every read is the reader's own value
+    g = gg.from_edges(n, np.arange(n), np.arange(n), name="loops")
+    c, same = otop.access_matrix(g, [0, 4, 8, 12], 3)
+    assert same == n and np.trace(c) == n
+    # edges only from block 0 into block 2: all reads by worker 2 of worker 0's values
+    g = gg.from_edges(n, np.array([0, 1, 2, 3]), np.array([8, 9, 10, 11]), name="cross")
+    c, same = otop.access_matrix(g, [0, 4, 8, 12], 3)
+    assert same == 0 and c[2, 0] == 4 and c.sum() == 4
+    d, u = otop.shares(c)
+    assert d == 0.0 and u == 0.0  # row 2 and column 0 never meet on the diagonal
+    # complete graph without self-loops, blocks of 4: 4*3 reads inside a block,
+    # 4*4 from each other block; the uniform expectation is 1/3
+    g = tg.complete(12)
+    c, _ = otop.access_matrix(g, [0, 4, 8, 12], 3)
+    np.testing.assert_array_equal(c, np.full((3, 3), 16) - 4 * np.eye(3, dtype=np.int64))
+    d, u = otop.shares(c)
+    assert abs(d - 36 / 132) < 1e-15 and abs(u - 1 / 3) < 1e-15
