@@ -103,6 +103,7 @@ def main():
     ap.add_argument("--no-modes", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-topology", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--batch-queries", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy five times (reference for HBM byte counters)")
@@ -304,6 +305,29 @@ def main():
                 f"(lift {v['access']['groups32']['lift']}), self share {v['access']['self_share']}; "
                 f"delay gain PR {v['modes']['delay_gain_pagerank']}x, SSSP {v['modes']['delay_gain_sssp']}x")
 
+    tuning = {}
+    if not args.no_tune:
+        # Autotuner: partition size and commit mode/interval chosen by the
+        # sweep-time x sweep-count model, against the default configuration.
+        dg.tune_cache_clear()
+        for algo, kw in (("pagerank", {"dtype": "f32", "tol": 1e-6}), ("sssp", {"src": int(sources[0])})):
+            t0 = time.perf_counter()
+            t = G.tune(algo, use_cache=False, **kw)
+            t["tuning_wall_s"] = round(time.perf_counter() - t0, 3)
+            G.repartition(0)
+            if algo == "pagerank":
+                dflt = min(G.pagerank(tol=1e-6, mode="delayed", d=args.d, dtype="f32")[1].seconds for _ in range(3))
+            else:
+                dflt = min(G.sssp(int(sources[0]), mode="delayed", d=args.d)[1].seconds for _ in range(3))
+            t["default_seconds"] = dflt
+            t["default"] = f"delayed d={args.d}, {info.workers} workers"
+            t["speedup_vs_default"] = round(dflt / t["seconds"], 3)
+            t.pop("graph_hash")
+            tuning[algo] = t
+            log(f"tuned {algo}: {t['mode']} d={t['d']} workers={t['workers']} -> {t['seconds'] * 1e3:.3f} ms "
+                f"(model {t['predicted_seconds'] * 1e3:.3f} ms; default {dflt * 1e3:.3f} ms; "
+                f"{t['candidates']} candidates in {t['tuning_wall_s']} s)")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(g)
@@ -332,6 +356,7 @@ def main():
         "modes": modes,
         "batched": batched,
         "topology": topology,
+        "tuning": tuning,
     }
     G.close()
     print(json.dumps(out), flush=True)

@@ -239,6 +239,52 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
  *   out_first_vertex  host array of workers + 1 entries (dg_graph_info) */
 dg_status dg_graph_partition(const dg_graph* g, uint32_t* out_first_vertex, void* hip_stream);
 
+/* Re-partitions a resident graph over `workers` workers (0 = the default,
+ * 5 per compute unit rounded down to a multiple of 8), without re-uploading
+ * it.  The blocked partition is rebuilt as at creation (section III-A).
+ * Must not overlap a sweep call on the same graph. */
+dg_status dg_graph_repartition(dg_graph* g, uint32_t workers, void* hip_stream);
+
+/* Autotuner (a form beyond the paper, which leaves the choice of delta to
+ * future work and shows that it depends on topology, thread count and update
+ * density: sections IV and V).  Chooses the partition size and the commit mode and interval
+ * for one algorithm on one graph by a sweep-time x sweep-count model:
+ *   1. a full run of every candidate (sync, async, delayed with d in
+ *      {16, 64, 256, 1024, 4096, whole}) at the current partition gives its
+ *      sweep count;
+ *   2. for every partition size (2, 3, 4, 5, 6, 8 workers per compute unit,
+ *      rounded down to a multiple of 8), a 6-sweep probe of every candidate
+ *      gives its time per sweep (best of two);
+ *   3. the candidate with the least predicted time to convergence is run
+ *      twice more to measure it.
+ * The graph is left partitioned with the chosen number of workers (unless
+ * DG_TUNE_KEEP_WORKERS).  Results are cached in-process by the graph's
+ * 64-bit content hash, the algorithm, dtype, tol and source; a cached entry
+ * is returned at once (from_cache = 1) unless DG_TUNE_NO_CACHE.
+ *   algo   DG_ALGO_PAGERANK (damping 0.85, tol > 0, dtype) or DG_ALGO_SSSP
+ *          (source src; tol and dtype ignored) */
+typedef enum { DG_ALGO_PAGERANK = 0, DG_ALGO_SSSP = 1 } dg_algo;
+#define DG_TUNE_NO_CACHE 1u
+#define DG_TUNE_KEEP_WORKERS 2u
+typedef struct {
+  uint32_t workers;          /* chosen partition size (now the graph's) */
+  dg_mode mode;              /* chosen commit mode */
+  uint32_t d;                /* chosen commit interval (delayed) */
+  uint32_t sweeps;           /* sweeps of the measuring run */
+  double seconds;            /* time to convergence of the measuring run */
+  double predicted_seconds;  /* the model's estimate for the choice */
+  uint32_t candidates;       /* (partition, mode, d) triples evaluated */
+  uint32_t from_cache;
+  uint64_t graph_hash;       /* content hash of the graph */
+} dg_tuning;
+dg_status dg_tune(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, uint32_t src, uint32_t flags,
+                  dg_tuning* out, void* hip_stream);
+/* The in-process cache of tuning results: cleared, written to and merged
+ * from a text file (one result per line, comments start with '#'). */
+dg_status dg_tune_cache_clear(void);
+dg_status dg_tune_cache_save(const char* path);
+dg_status dg_tune_cache_load(const char* path);
+
 /* Topology instrumentation (section IV, effects of graph topology, Fig. 5):
  * the access matrix of one pull sweep under the graph's static blocked
  * partition.  Each in-edge u -> v is a read, by the worker owning v, of the

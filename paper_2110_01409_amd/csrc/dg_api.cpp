@@ -94,6 +94,8 @@ struct dg_graph {
   uint32_t P = 0, T = 0, cus = 0, max_in_deg = 0, n_dangling = 0;
   uint32_t K = 0;          // sources stored in the compact region
   uint32_t max_block_v = 1;  // most vertices any worker owns
+  std::vector<uint32_t> tile_v_h, tile_e0_h;  // host copies: first vertex / first in-edge of each tile
+  uint64_t hash = 0;                         // content hash of the in-edge form (tuning cache key)
   uint64_t hot_edges = 0;  // in-edges whose source is in the compact region
   size_t lds_per_block = 65536;
   // allocator captured at creation
@@ -162,12 +164,12 @@ void release_all(dg_graph* g) {
 // blocks balanced by in-neighbours).  The cost of a tile also counts its
 // vertices and a fixed per-tile overhead, because on the GPU each vertex is
 // read and written and each tile costs a few workgroup barriers.
-void build_workers(const std::vector<uint32_t>& in_ptr, const std::vector<uint32_t>& tile_v, uint32_t P,
+void build_workers(const std::vector<uint32_t>& tile_v, const std::vector<uint32_t>& tile_e0, uint32_t P,
                    std::vector<uint32_t>& work_t) {
   const uint32_t T = (uint32_t)tile_v.size() - 1;
   std::vector<double> cum(T + 1, 0.0);
   for (uint32_t t = 0; t < T; ++t) {
-    const double e = (double)(in_ptr[tile_v[t + 1]] - in_ptr[tile_v[t]]);
+    const double e = (double)(tile_e0[t + 1] - tile_e0[t]);
     const double v = (double)(tile_v[t + 1] - tile_v[t]);
     cum[t + 1] = cum[t] + 256.0 + e + 4.0 * v;
   }
@@ -180,6 +182,16 @@ void build_workers(const std::vector<uint32_t>& in_ptr, const std::vector<uint32
     work_t[w] = t;
   }
   work_t[P] = T;
+}
+
+// 64-bit FNV-1a over 8-byte words (the tail zero-padded) of a uint32 array,
+// continuing from h.
+uint64_t hash_words(uint64_t h, const uint32_t* p, size_t n) {
+  const uint64_t prime = 0x100000001b3ull;
+  size_t i = 0;
+  for (; i + 2 <= n; i += 2) h = (h ^ ((uint64_t)p[i] | ((uint64_t)p[i + 1] << 32))) * prime;
+  if (i < n) h = (h ^ (uint64_t)p[i]) * prime;
+  return (h ^ (uint64_t)n) * prime;
 }
 
 dg_status ensure_workspace(dg_graph* g, uint32_t S, hipStream_t s) {
@@ -354,6 +366,48 @@ struct CallAllocs {
 
 }  // namespace
 
+namespace {
+
+// Tuning results cached in-process by (graph content, algorithm, dtype,
+// tolerance, source).
+struct TuneEntry {
+  uint64_t hash;
+  int algo, dtype;
+  double tol;
+  uint32_t src;
+  dg_tuning t;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune_cache;
+
+bool tune_find(uint64_t hash, int algo, int dtype, double tol, uint32_t src, dg_tuning& out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const auto& e : g_tune_cache)
+    if (e.hash == hash && e.algo == algo && e.dtype == dtype && e.tol == tol && e.src == src) {
+      out = e.t;
+      return true;
+    }
+  return false;
+}
+
+void tune_put(const TuneEntry& n) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& e : g_tune_cache)
+    if (e.hash == n.hash && e.algo == n.algo && e.dtype == n.dtype && e.tol == n.tol && e.src == n.src) {
+      e = n;
+      return;
+    }
+  g_tune_cache.push_back(n);
+}
+
+uint32_t default_workers(const dg_graph* g, uint32_t per_cu) {
+  uint32_t P = std::max(1u, std::min(g->cus * per_cu, g->T));
+  if (P > 8) P &= ~7u;
+  return P;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* dg_version(void) { return "dg 0.1 (gfx950)"; }
@@ -474,6 +528,14 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
       g->n_dangling += out_deg[v] == 0;
     }
     build_tiles(in_ptr, n, tile_v);
+    g->tile_v_h = tile_v;
+    g->tile_e0_h.resize(tile_v.size());
+    for (size_t t = 0; t < tile_v.size(); ++t) g->tile_e0_h[t] = in_ptr[tile_v[t]];
+    uint64_t h = 0xcbf29ce484222325ull;
+    h = hash_words(h, in_ptr.data(), in_ptr.size());
+    h = hash_words(h, in_src.data(), (size_t)m);
+    if (w) h = hash_words(h, in_w.data(), (size_t)m);
+    g->hash = hash_words(h, out_deg.data(), out_deg.size());
   } catch (const std::bad_alloc&) {
     delete g;
     return fail(DG_ERR_OUT_OF_MEMORY, "host allocation failed while building the in-edge form");
@@ -504,7 +566,7 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
   P = std::max(1u, std::min(P, g->T));
   if (P > 8 && !want_workers) P &= ~7u;
   g->P = P;
-  build_workers(in_ptr, tile_v, P, work_t);
+  build_workers(g->tile_v_h, g->tile_e0_h, P, work_t);
   for (uint32_t wk = 0; wk < P; ++wk)
     g->max_block_v = std::max(g->max_block_v, tile_v[work_t[wk + 1]] - tile_v[work_t[wk]]);
 
@@ -999,6 +1061,200 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
     stats->edges_traversed = g->m * qe;
   }
   if (!conv) return fail(DG_ERR_NOT_CONVERGED, "no convergence within %u sweeps", max_sweeps);
+  return DG_OK;
+}
+
+dg_status dg_graph_repartition(dg_graph* g, uint32_t workers, void* hip_stream) {
+  g_last_error.clear();
+  if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
+  const uint32_t P = workers ? std::max(1u, std::min(workers, g->T)) : default_workers(g, kWorkersPerCU);
+  if (P == g->P) return DG_OK;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  std::vector<uint32_t> work_t;
+  build_workers(g->tile_v_h, g->tile_e0_h, P, work_t);
+  uint32_t mbv = 1;
+  for (uint32_t w = 0; w < P; ++w) mbv = std::max(mbv, g->tile_v_h[work_t[w + 1]] - g->tile_v_h[work_t[w]]);
+  DG_HIP(hipStreamSynchronize(s));
+  uint32_t* wt = static_cast<uint32_t*>(dev_alloc(g, (size_t)(P + 1) * 4, s));
+  double* part = g->part ? static_cast<double*>(dev_alloc(g, 2 * (size_t)P * sizeof(double), s)) : nullptr;
+  if (!wt || (g->part && !part)) {
+    dev_free(g, wt);
+    dev_free(g, part);
+    return fail(DG_ERR_OUT_OF_MEMORY, "repartition allocation failed");
+  }
+  DG_HIP(hipMemcpyAsync(wt, work_t.data(), (size_t)(P + 1) * 4, hipMemcpyHostToDevice, s));
+  DG_HIP(hipStreamSynchronize(s));
+  dev_free(g, g->work_t);
+  g->work_t = wt;
+  if (g->part) {
+    dev_free(g, g->part);
+    g->part = part;
+  }
+  g->P = P;
+  g->max_block_v = mbv;
+  return DG_OK;
+}
+
+dg_status dg_tune(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, uint32_t src, uint32_t flags,
+                  dg_tuning* out, void* hip_stream) {
+  g_last_error.clear();
+  if (!g || !out) return fail(DG_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (algo != DG_ALGO_PAGERANK && algo != DG_ALGO_SSSP) return fail(DG_ERR_INVALID_ARGUMENT, "unknown algorithm");
+  if (flags & ~(uint32_t)(DG_TUNE_NO_CACHE | DG_TUNE_KEEP_WORKERS))
+    return fail(DG_ERR_INVALID_ARGUMENT, "unknown flags 0x%x", flags);
+  if (algo == DG_ALGO_PAGERANK) {
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(DG_ERR_INVALID_ARGUMENT, "tol must be finite and > 0");
+    if (dtype != DG_F32 && dtype != DG_F64) return fail(DG_ERR_INVALID_ARGUMENT, "dtype must be DG_F32 or DG_F64");
+    src = 0;
+  } else {
+    if (src >= g->n) return fail(DG_ERR_INVALID_ARGUMENT, "source %u >= n", src);
+    if (!g->has_w) return fail(DG_ERR_INVALID_ARGUMENT, "the graph was created without weights");
+    dtype = DG_F32;
+    tol = 0.0;
+  }
+  const bool keep = (flags & DG_TUNE_KEEP_WORKERS) != 0;
+  dg_tuning cached;
+  if (!(flags & DG_TUNE_NO_CACHE) && tune_find(g->hash, (int)algo, (int)dtype, tol, src, cached)) {
+    if (!keep) {
+      dg_status st = dg_graph_repartition(g, cached.workers, hip_stream);
+      if (st != DG_OK) return st;
+    }
+    *out = cached;
+    out->from_cache = 1;
+    out->workers = g->P;
+    return DG_OK;
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  CallAllocs al(g);
+  void* scratch = al.get((size_t)g->n * 8, s);
+  if (!scratch) return fail(DG_ERR_OUT_OF_MEMORY, "tuning scratch allocation failed");
+  const uint32_t full = algo == DG_ALGO_PAGERANK ? 10000u : std::min<uint32_t>(g->n + 1, kMaxSweeps);
+  // one run: status DG_OK or DG_ERR_NOT_CONVERGED (probes) fill st
+  auto run = [&](dg_mode mode, uint32_t d, double tl, uint32_t ms, dg_stats& st) -> dg_status {
+    dg_status r = algo == DG_ALGO_PAGERANK
+                      ? dg_pagerank(g, 0.85, tl, mode, d, dtype, ms, static_cast<double*>(scratch), 1, &st, hip_stream)
+                      : dg_sssp(g, src, mode, d, ms, static_cast<uint32_t*>(scratch), 1, &st, hip_stream);
+    if (r == DG_ERR_NOT_CONVERGED) r = DG_OK;
+    return r;
+  };
+  struct Cand {
+    dg_mode mode;
+    uint32_t d;
+    uint32_t sweeps;
+  };
+  std::vector<Cand> cands = {{DG_SYNC, 1, 0},      {DG_ASYNC, 1, 0},     {DG_DELAYED, 16, 0},
+                             {DG_DELAYED, 64, 0},  {DG_DELAYED, 256, 0}, {DG_DELAYED, 1024, 0},
+                             {DG_DELAYED, 4096, 0}, {DG_DELAYED, DG_D_WHOLE, 0}};
+  // Sweep counts: a full run of each candidate at the current partition.
+  dg_status st;
+  for (auto& c : cands) {
+    dg_stats x{};
+    if ((st = run(c.mode, c.d, tol, full, x)) != DG_OK) return st;
+    c.sweeps = x.sweeps;
+  }
+  // Time per sweep: short fixed-length probes (tol 0 for PageRank) for every
+  // partition size, best of two.
+  std::vector<uint32_t> Ps;
+  if (keep) {
+    Ps.push_back(g->P);
+  } else {
+    for (uint32_t per_cu : {2u, 3u, 4u, 5u, 6u, 8u}) {
+      const uint32_t P = default_workers(g, per_cu);
+      if (std::find(Ps.begin(), Ps.end(), P) == Ps.end()) Ps.push_back(P);
+    }
+  }
+  const uint32_t probe = 6;
+  double best = 1e300;
+  uint32_t bestP = g->P, bestc = 0, evaluated = 0;
+  for (uint32_t P : Ps) {
+    if ((st = dg_graph_repartition(g, P, hip_stream)) != DG_OK) return st;
+    for (uint32_t i = 0; i < cands.size(); ++i) {
+      double ts = 1e300;
+      for (int rep = 0; rep < 2; ++rep) {
+        dg_stats x{};
+        if ((st = run(cands[i].mode, cands[i].d, algo == DG_ALGO_PAGERANK ? 0.0 : tol, probe, x)) != DG_OK)
+          return st;
+        if (x.sweeps) ts = std::min(ts, x.seconds / x.sweeps);
+      }
+      const double pred = ts * cands[i].sweeps;
+      ++evaluated;
+      if (pred < best) {
+        best = pred;
+        bestP = P;
+        bestc = i;
+      }
+    }
+  }
+  if ((st = dg_graph_repartition(g, bestP, hip_stream)) != DG_OK) return st;
+  dg_stats v1{}, v2{};
+  if ((st = run(cands[bestc].mode, cands[bestc].d, tol, full, v1)) != DG_OK) return st;
+  if ((st = run(cands[bestc].mode, cands[bestc].d, tol, full, v2)) != DG_OK) return st;
+  dg_tuning t{};
+  t.workers = g->P;
+  t.mode = cands[bestc].mode;
+  t.d = cands[bestc].d;
+  t.sweeps = v2.sweeps;
+  t.seconds = std::min(v1.seconds, v2.seconds);
+  t.predicted_seconds = best;
+  t.candidates = evaluated;
+  t.from_cache = 0;
+  t.graph_hash = g->hash;
+  tune_put(TuneEntry{g->hash, (int)algo, (int)dtype, tol, src, t});
+  *out = t;
+  return DG_OK;
+}
+
+dg_status dg_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache.clear();
+  return DG_OK;
+}
+
+dg_status dg_tune_cache_save(const char* path) {
+  g_last_error.clear();
+  if (!path) return fail(DG_ERR_INVALID_ARGUMENT, "path is NULL");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(DG_ERR_INVALID_ARGUMENT, "cannot open %s for writing", path);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::fprintf(f, "# dg tuning cache: hash algo dtype tol src workers mode d sweeps seconds\n");
+  for (const auto& e : g_tune_cache)
+    std::fprintf(f, "%016llx %d %d %.17g %u %u %d %u %u %.9g\n", (unsigned long long)e.hash, e.algo, e.dtype, e.tol,
+                 e.src, e.t.workers, (int)e.t.mode, e.t.d, e.t.sweeps, e.t.seconds);
+  const bool ok = std::fclose(f) == 0;
+  return ok ? DG_OK : fail(DG_ERR_INVALID_ARGUMENT, "writing %s failed", path);
+}
+
+dg_status dg_tune_cache_load(const char* path) {
+  g_last_error.clear();
+  if (!path) return fail(DG_ERR_INVALID_ARGUMENT, "path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(DG_ERR_INVALID_ARGUMENT, "cannot open %s", path);
+  char line[512];
+  uint32_t bad = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    unsigned long long h = 0;
+    int algo = 0, dtype = 0, mode = 0;
+    double tol = 0.0, secs = 0.0;
+    unsigned src = 0, workers = 0, d = 0, sweeps = 0;
+    if (std::sscanf(line, "%llx %d %d %lg %u %u %d %u %u %lg", &h, &algo, &dtype, &tol, &src, &workers, &mode, &d,
+                    &sweeps, &secs) != 10 ||
+        (algo != DG_ALGO_PAGERANK && algo != DG_ALGO_SSSP) || mode < DG_SYNC || mode > DG_DELAYED || workers == 0 ||
+        (mode == DG_DELAYED && d == 0)) {
+      ++bad;
+      continue;
+    }
+    dg_tuning t{};
+    t.workers = workers;
+    t.mode = (dg_mode)mode;
+    t.d = d;
+    t.sweeps = sweeps;
+    t.seconds = secs;
+    t.graph_hash = h;
+    tune_put(TuneEntry{(uint64_t)h, algo, dtype, tol, src, t});
+  }
+  std::fclose(f);
+  if (bad) return fail(DG_ERR_INVALID_ARGUMENT, "%u malformed line(s) in %s skipped", bad, path);
   return DG_OK;
 }
 

@@ -33,8 +33,12 @@ DTYPES = {"f32": DG_F32, "f64": DG_F64}
 # Every symbol declared in include/dg.h.
 EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_info_get", "dg_pagerank",
            "dg_sssp", "dg_sssp_batch", "dg_ppr_batch", "dg_set_create", "dg_set_destroy", "dg_set_info_get",
-           "dg_set_pagerank", "dg_set_sssp", "dg_graph_partition", "dg_access_matrix", "dg_status_str",
+           "dg_set_pagerank", "dg_set_sssp", "dg_graph_partition", "dg_access_matrix", "dg_graph_repartition",
+           "dg_tune", "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_status_str",
            "dg_last_error", "dg_version")
+DG_ALGO_PAGERANK, DG_ALGO_SSSP = 0, 1
+DG_TUNE_NO_CACHE, DG_TUNE_KEEP_WORKERS = 1, 2
+MODE_NAMES = {0: "sync", 1: "async", 2: "delayed"}
 DG_SET_EAGER = 1
 
 
@@ -67,6 +71,12 @@ class dg_access_stats(C.Structure):
     _fields_ = [("reads", C.c_uint64), ("same_worker", C.c_uint64), ("diagonal", C.c_uint64),
                 ("groups", C.c_uint32), ("workers", C.c_uint32), ("self_share", C.c_double),
                 ("diagonal_share", C.c_double), ("uniform_diagonal", C.c_double)]
+
+
+class dg_tuning(C.Structure):
+    _fields_ = [("workers", C.c_uint32), ("mode", C.c_int), ("d", C.c_uint32), ("sweeps", C.c_uint32),
+                ("seconds", C.c_double), ("predicted_seconds", C.c_double), ("candidates", C.c_uint32),
+                ("from_cache", C.c_uint32), ("graph_hash", C.c_uint64)]
 
 
 class dg_set_opts(C.Structure):
@@ -116,6 +126,11 @@ def _load():
                                   C.POINTER(dg_stats), P]),
         "dg_graph_partition": (C.c_int, [P, P, P]),
         "dg_access_matrix": (C.c_int, [P, C.c_uint32, P, C.POINTER(dg_access_stats), P]),
+        "dg_graph_repartition": (C.c_int, [P, C.c_uint32, P]),
+        "dg_tune": (C.c_int, [P, C.c_int, C.c_int, C.c_double, C.c_uint32, C.c_uint32, C.POINTER(dg_tuning), P]),
+        "dg_tune_cache_clear": (C.c_int, []),
+        "dg_tune_cache_save": (C.c_int, [C.c_char_p]),
+        "dg_tune_cache_load": (C.c_int, [C.c_char_p]),
         "dg_status_str": (C.c_char_p, [C.c_int]),
         "dg_last_error": (C.c_char_p, []),
         "dg_version": (C.c_char_p, []),
@@ -204,6 +219,38 @@ def dg_graph_partition(g, out_first_vertex, stream):
 
 def dg_access_matrix(g, groups, out_counts, stats, stream):
     return lib.dg_access_matrix(g, groups, out_counts, stats, stream)
+
+
+def dg_graph_repartition(g, workers, stream):
+    return lib.dg_graph_repartition(g, workers, stream)
+
+
+def dg_tune(g, algo, dtype, tol, src, flags, out, stream):
+    return lib.dg_tune(g, algo, dtype, tol, src, flags, out, stream)
+
+
+def dg_tune_cache_clear():
+    return lib.dg_tune_cache_clear()
+
+
+def dg_tune_cache_save(path):
+    return lib.dg_tune_cache_save(path)
+
+
+def dg_tune_cache_load(path):
+    return lib.dg_tune_cache_load(path)
+
+
+def tune_cache_save(path):
+    _check(dg_tune_cache_save(os.fsencode(path)))
+
+
+def tune_cache_load(path):
+    _check(dg_tune_cache_load(os.fsencode(path)))
+
+
+def tune_cache_clear():
+    _check(dg_tune_cache_clear())
 
 
 def _check(status, allow=()):
@@ -362,6 +409,21 @@ class Graph:
                                 _stream_handle(stream)),
                    allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
         return out, _stats(st, s == DG_OK)
+
+    def repartition(self, workers=0, stream=None):
+        """Rebuild the blocked partition over `workers` workers (0 = default)."""
+        _check(dg_graph_repartition(self._h, int(workers), _stream_handle(stream)))
+
+    def tune(self, algo="pagerank", dtype="f32", tol=1e-6, src=0, use_cache=True, keep_workers=False, stream=None):
+        """Choose workers, mode and d (the graph keeps the chosen partition).
+        Returns a dict with the choice and its measured time."""
+        t = dg_tuning()
+        flags = (0 if use_cache else DG_TUNE_NO_CACHE) | (DG_TUNE_KEEP_WORKERS if keep_workers else 0)
+        _check(dg_tune(self._h, DG_ALGO_PAGERANK if algo == "pagerank" else DG_ALGO_SSSP, DTYPES[dtype],
+                       float(tol), int(src), flags, C.byref(t), _stream_handle(stream)))
+        return {"workers": t.workers, "mode": MODE_NAMES[t.mode], "d": t.d, "sweeps": t.sweeps,
+                "seconds": t.seconds, "predicted_seconds": t.predicted_seconds, "candidates": t.candidates,
+                "from_cache": bool(t.from_cache), "graph_hash": t.graph_hash}
 
     def partition(self, stream=None):
         """First vertex of each worker's block: uint32 array [workers + 1]."""

@@ -173,3 +173,32 @@ def test_topology_call_validation_null(dg):
     assert dg.dg_access_matrix(None, 8, None, C.byref(st), None) == dg.DG_ERR_INVALID_ARGUMENT
     out = np.zeros(4, np.uint32)
     assert dg.dg_graph_partition(None, dg._np_ptr(out), None) == dg.DG_ERR_INVALID_ARGUMENT
+
+
+def test_tune_call_validation_null(dg):
+    t = dg.dg_tuning()
+    assert dg.dg_tune(None, 0, 0, 1e-6, 0, 0, C.byref(t), None) == dg.DG_ERR_INVALID_ARGUMENT
+    assert dg.dg_graph_repartition(None, 8, None) == dg.DG_ERR_INVALID_ARGUMENT
+
+
+def test_tune_cache_roundtrip(dg, tmp_path):
+    """The tuning cache is host-only: save, clear and load a file, with a
+    malformed line reported and skipped."""
+    p = tmp_path / "tune.txt"
+    dg.tune_cache_clear()
+    dg.tune_cache_save(p)
+    assert p.read_text().startswith("#")
+    p.write_text("# comment\n"
+                 "00000000deadbeef 0 0 1e-06 0 640 2 64 13 0.0065\n"
+                 "not a valid line\n")
+    assert dg.dg_tune_cache_load(os.fsencode(str(p))) == dg.DG_ERR_INVALID_ARGUMENT
+    assert "1 malformed" in dg.last_error()
+    q = tmp_path / "again.txt"
+    dg.tune_cache_save(q)
+    lines = [ln for ln in q.read_text().splitlines() if not ln.startswith("#")]
+    assert len(lines) == 1 and lines[0].split()[:8] == ["00000000deadbeef", "0", "0", "9.9999999999999995e-07",
+                                                        "0", "640", "2", "64"]
+    dg.tune_cache_clear()
+    dg.tune_cache_save(q)
+    assert [ln for ln in q.read_text().splitlines() if not ln.startswith("#")] == []
+    assert dg.dg_tune_cache_load(b"/nonexistent/dir/x") == dg.DG_ERR_INVALID_ARGUMENT
