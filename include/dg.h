@@ -382,6 +382,60 @@ dg_status dg_set_sssp(dg_set* s, const uint32_t* sources, dg_mode mode, uint32_t
                       uint32_t flags, uint32_t* out_dist, int out_on_device, uint32_t* out_sweeps,
                       dg_stats* stats, void* hip_stream);
 
+/* Serving loop (a form beyond the paper: many independent queries arriving
+ * over time on resident graphs).  The server keeps a queue per (graph, query
+ * kind) and pools of 64-lane batches swept by the batched kernels
+ * (dg_sssp_batch / dg_ppr_batch semantics per lane).  Batching is
+ * continuous: at every sweep boundary queued requests take free lanes of the
+ * running batches (their lanes are initialised while the other lanes keep
+ * their state), finished lanes hand over their rows and become free, and a
+ * pool grows by one batch when it has no free lane and the state budget
+ * allows.  A request's result is therefore the same as the batched call's for
+ * its source: bit-identical for SSSP in every mode and, in synchronous mode,
+ * for PPR as well.
+ * The graphs must outlive the server; one server is driven by one thread. */
+typedef struct dg_server dg_server;
+typedef enum { DG_QUERY_SSSP = 0, DG_QUERY_PPR = 1 } dg_query;
+typedef struct {
+  uint64_t hbm_budget;   /* bytes of batch state over all pools; 0 = no limit */
+  uint32_t max_batches;  /* batches per (graph, kind); 0 = no limit but the budget */
+  dg_mode mode;          /* commit mode of every sweep */
+  uint32_t d;            /* commit interval (delayed) */
+  double damping;        /* PPR: 0 <= damping < 1 */
+  double tol;            /* PPR: per-query stopping tolerance (L1 change), > 0 */
+  dg_dtype dtype;        /* PPR storage */
+} dg_server_opts;
+typedef struct {
+  uint32_t graph;
+  dg_query kind;
+  uint32_t source;
+  uint32_t sweeps;       /* sweeps from admission to the stopping one */
+  uint32_t state;        /* 0 queued, 1 running, 2 finished, 3 fetched */
+  uint64_t submit_step, admit_step, finish_step;
+} dg_request_info;
+typedef struct {
+  uint32_t queued, running, finished;  /* finished = results not yet fetched */
+  uint32_t batches;
+  uint64_t state_bytes;
+  uint64_t steps;
+} dg_server_status;
+/* graphs: `count` resident graphs (not owned).  Work runs on hip_stream. */
+dg_status dg_server_create(dg_graph* const* graphs, uint32_t count, const dg_server_opts* opts, void* hip_stream,
+                           dg_server** out);
+dg_status dg_server_destroy(dg_server* s);
+/* Queues a query: SSSP from `source` (the graph needs weights) or PPR with
+ * restart vertex `source`.  Ids start at 1. */
+dg_status dg_server_submit(dg_server* s, uint32_t graph, dg_query kind, uint32_t source, uint64_t* out_id);
+/* One step: admission, one sweep of every pool with running queries,
+ * retirement.  Writes up to `cap` ids of requests finished so far and not yet
+ * reported to out_finished (the rest are reported by later steps). */
+dg_status dg_server_step(dg_server* s, uint64_t* out_finished, uint32_t cap, uint32_t* out_count);
+/* Request status (info) and, when out != NULL, its result: n uint32
+ * distances (SSSP) or n float64 scores summing to 1 (PPR), device memory
+ * when out_on_device != 0.  Fetching releases the result. */
+dg_status dg_server_fetch(dg_server* s, uint64_t id, void* out, int out_on_device, dg_request_info* info);
+dg_status dg_server_status_get(const dg_server* s, dg_server_status* status);
+
 /* Static name of a status code. */
 const char* dg_status_str(dg_status s);
 

@@ -111,8 +111,10 @@ template <int M>
 __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
   __shared__ uint32_t s_hub[kWG / 64][kQ];
   __shared__ int s_any;
+  __shared__ uint32_t s_lane[kQ];
   const uint32_t b = blockIdx.y, NB = a.NB, k = a.k;
-  if (a.changed[k * NB + b] == 0) return;  // this batch already converged
+  // batch already converged (call mode) or without running queries (serving)
+  if (a.bactive ? a.bactive[b] == 0 : a.changed[k * NB + b] == 0) return;
 
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
   const uint32_t w = worker_of(blockIdx.x, a.g.P);
@@ -124,6 +126,7 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
   const cu32p in_ptr = cst(a.g.in_ptr);
   const uint32_t t0 = cst(a.g.work_t)[w], t1 = cst(a.g.work_t)[w + 1];
   if (tid == 0) s_any = 0;
+  if (tid < kQ) s_lane[tid] = 0;
   __syncthreads();
   uint32_t any = 0, staged = 0;
 
@@ -167,6 +170,13 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
         staged = 0;
       }
     }
+  }
+  if (a.lchg) {
+    // serving: which queries (lanes) changed anywhere in this sweep
+    if (any) atomicOr(&s_lane[lane], 1u);
+    __syncthreads();
+    if (tid < kQ && s_lane[tid]) atomicOr(a.lchg + (size_t)b * kQ + tid, 1u);
+    return;
   }
   if (any) s_any = 1;  // benign race: every writer stores 1
   __syncthreads();
@@ -225,7 +235,8 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
   __shared__ double s_red[3][kWG / 64][kQ];
   __shared__ int s_last;
   const uint32_t b = blockIdx.y, NB = a.NB, k = a.k;
-  if (!(a.resid[k * NB + b] >= a.tol)) return;  // this batch already converged
+  // batch already converged (call mode) or without running queries (serving)
+  if (a.bactive ? a.bactive[b] == 0 : !(a.resid[k * NB + b] >= a.tol)) return;
 
   const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
   const uint32_t P = a.g.P;
@@ -306,7 +317,9 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
   }
   __threadfence();
   __syncthreads();
-  if (tid == 0) s_last = (atomicAdd(a.count + k * NB + b, 1u) == P - 1);
+  // worker counter: per sweep (call mode) or a two-slot ring (serving)
+  uint32_t* cnt = a.count + (size_t)(a.bactive ? (k & 1u) : k) * NB + b;
+  if (tid == 0) s_last = (atomicAdd(cnt, 1u) == P - 1);
   __syncthreads();
   if (!s_last) return;
   __threadfence();
@@ -333,7 +346,12 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
       const double u = __shfl_xor(m, o, 64);
       m = u > m ? u : m;
     }
-    if (lane == 0) a.resid[(k + 1) * NB + b] = m;
+    if (a.bactive) {
+      // serving: clear the ring slot the next sweep counts in
+      if (lane == 0) a.count[(size_t)((k + 1) & 1u) * NB + b] = 0;
+    } else if (lane == 0) {
+      a.resid[(k + 1) * NB + b] = m;
+    }
   }
 }
 
@@ -399,6 +417,102 @@ __global__ __launch_bounds__(kWG) void mppr_out_kernel(const T* x, const double*
     const uint32_t qi = b * kQ + r, v = vb + lane;
     if (qi < nq && v < n) out[(size_t)qi * n + v] = s[lane][r] / qsum[(size_t)b * kQ + r];
   }
+}
+
+// ------------------------------------------------ serving: lane set-up --
+//
+// lane_src[b * 64 + q] is the source (restart vertex) of a query admitted
+// into lane q of batch b at this sweep boundary, or kInf for lanes left as
+// they are; grid.y walks the list of batches that admit anything.
+
+__global__ __launch_bounds__(kWG) void mbf_lane_init_kernel(uint32_t* d0, uint32_t* d1, const uint32_t* cpos,
+                                                            uint32_t n, uint32_t K, const uint32_t* lane_src,
+                                                            const uint32_t* blist) {
+  const size_t i = (size_t)blockIdx.x * kWG + threadIdx.x;
+  if (i >= (size_t)n * kQ) return;
+  const uint32_t b = blist[blockIdx.y];
+  const uint32_t v = (uint32_t)(i / kQ), q = (uint32_t)(i % kQ);
+  const uint32_t s = lane_src[(size_t)b * kQ + q];
+  if (s == kInf) return;
+  const size_t off = (size_t)b * (n + K) * kQ + (size_t)cpos[v] * kQ + q;
+  const uint32_t val = s == v ? 0u : kInf;
+  d0[off] = val;
+  if (d1) d1[off] = val;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void mppr_lane_init_kernel(T* x, T* c0, T* c1, const uint32_t* out_deg,
+                                                             const uint32_t* cpos, uint32_t n, uint32_t K,
+                                                             const uint32_t* lane_src, const uint32_t* blist) {
+  const size_t i = (size_t)blockIdx.x * kWG + threadIdx.x;
+  if (i >= (size_t)n * kQ) return;
+  const uint32_t b = blist[blockIdx.y];
+  const uint32_t v = (uint32_t)(i / kQ), q = (uint32_t)(i % kQ);
+  const uint32_t s = lane_src[(size_t)b * kQ + q];
+  if (s == kInf) return;
+  const bool at = s == v;
+  const uint32_t dg = out_deg[v];
+  x[(size_t)b * n * kQ + (size_t)v * kQ + q] = at ? (T)1 : (T)0;
+  const T c = (at && dg) ? (T)(1.0 / (double)dg) : (T)0;
+  const size_t off = (size_t)b * (n + K) * kQ + (size_t)cpos[v] * kQ + q;
+  c0[off] = c;
+  if (c1) c1[off] = c;
+}
+
+// Per-lane scalars of admitted PPR queries: restart vertex, unit scale and
+// the dangling mass of x0 = e_s in both ring slots, running.
+__global__ __launch_bounds__(kWG) void mppr_lane_scalars_kernel(const uint32_t* lane_src, const uint32_t* out_deg,
+                                                                uint32_t NB, uint32_t* src, double* dang,
+                                                                double* scale, uint32_t* qdone) {
+  const uint32_t i = blockIdx.x * kWG + threadIdx.x;
+  if (i >= NB * kQ) return;
+  const uint32_t s = lane_src[i];
+  if (s == kInf) return;
+  src[i] = s;
+  const double d0 = out_deg[s] ? 0.0 : 1.0;
+  dang[i] = d0;
+  dang[(size_t)NB * kQ + i] = d0;
+  scale[i] = 1.0;
+  scale[(size_t)NB * kQ + i] = 1.0;
+  qdone[i] = 0;
+}
+
+// Row of one finished query: distances in vertex order.
+__global__ __launch_bounds__(kWG) void mbf_lane_out_kernel(const uint32_t* d, const uint32_t* cpos, uint32_t n,
+                                                           uint32_t K, uint32_t b, uint32_t q, uint32_t* out) {
+  const uint32_t v = blockIdx.x * kWG + threadIdx.x;
+  if (v >= n) return;
+  out[v] = d[(size_t)b * (n + K) * kQ + (size_t)cpos[v] * kQ + q];
+}
+
+// Row of one finished PPR query normalised to sum 1: kSumBlocks partial sums
+// in a fixed order, then every block folds them in block order and scales.
+template <typename T>
+__global__ __launch_bounds__(kWG) void mppr_lane_sum_kernel(const T* x, uint32_t n, uint32_t b, uint32_t q,
+                                                            double* qpart) {
+  __shared__ double s[kWG / 64];
+  const T* xb = x + (size_t)b * n * kQ;
+  double acc = 0.0;
+  for (uint32_t v = blockIdx.x * kWG + threadIdx.x; v < n; v += kSumBlocks * kWG) acc += (double)xb[(size_t)v * kQ + q];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63u) == 0) s[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) qpart[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void mppr_lane_out_kernel(const T* x, uint32_t n, uint32_t b, uint32_t q,
+                                                            const double* qpart, double* out) {
+  __shared__ double s_sum;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (uint32_t i = 0; i < kSumBlocks; ++i) t += qpart[i];
+    s_sum = t;
+  }
+  __syncthreads();
+  const uint32_t v = blockIdx.x * kWG + threadIdx.x;
+  if (v >= n) return;
+  out[v] = (double)x[(size_t)b * n * kQ + (size_t)v * kQ + q] / s_sum;
 }
 
 __global__ __launch_bounds__(kWG) void fill_u32_kernel(uint32_t* p, size_t n, uint32_t v) {
@@ -480,6 +594,46 @@ hipError_t launch_mppr_out(bool f64, const void* x, double* qpart, double* qsum,
   mppr_fold_kernel<<<NB, kQ, 0, s>>>(qpart, qsum);
   if (f64) mppr_out_kernel<double><<<go, kWG, 0, s>>>(static_cast<const double*>(x), qsum, n, nq, out);
   else mppr_out_kernel<float><<<go, kWG, 0, s>>>(static_cast<const float*>(x), qsum, n, nq, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mbf_lane_init(uint32_t* d0, uint32_t* d1, const uint32_t* cpos, uint32_t n, uint32_t K,
+                                const uint32_t* lane_src, const uint32_t* blist, uint32_t nb, hipStream_t s) {
+  if (nb) mbf_lane_init_kernel<<<dim3(nblocks((size_t)n * kQ), nb), kWG, 0, s>>>(d0, d1, cpos, n, K, lane_src, blist);
+  return hipGetLastError();
+}
+
+hipError_t launch_mppr_lane_init(bool f64, void* x, void* c0, void* c1, const uint32_t* out_deg, const uint32_t* cpos,
+                                 uint32_t n, uint32_t K, uint32_t NB, const uint32_t* lane_src, const uint32_t* blist,
+                                 uint32_t nb, uint32_t* src, double* dang, double* scale, uint32_t* qdone,
+                                 hipStream_t s) {
+  if (!nb) return hipSuccess;
+  const dim3 grid(nblocks((size_t)n * kQ), nb);
+  if (f64)
+    mppr_lane_init_kernel<double><<<grid, kWG, 0, s>>>(static_cast<double*>(x), static_cast<double*>(c0),
+                                                       static_cast<double*>(c1), out_deg, cpos, n, K, lane_src, blist);
+  else
+    mppr_lane_init_kernel<float><<<grid, kWG, 0, s>>>(static_cast<float*>(x), static_cast<float*>(c0),
+                                                      static_cast<float*>(c1), out_deg, cpos, n, K, lane_src, blist);
+  mppr_lane_scalars_kernel<<<nblocks((size_t)NB * kQ), kWG, 0, s>>>(lane_src, out_deg, NB, src, dang, scale, qdone);
+  return hipGetLastError();
+}
+
+hipError_t launch_mbf_lane_out(const uint32_t* d, const uint32_t* cpos, uint32_t n, uint32_t K, uint32_t b, uint32_t q,
+                               uint32_t* out, hipStream_t s) {
+  mbf_lane_out_kernel<<<nblocks(n), kWG, 0, s>>>(d, cpos, n, K, b, q, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mppr_lane_out(bool f64, const void* x, uint32_t n, uint32_t b, uint32_t q, double* qpart,
+                                double* out, hipStream_t s) {
+  if (f64) {
+    mppr_lane_sum_kernel<double><<<kSumBlocks, kWG, 0, s>>>(static_cast<const double*>(x), n, b, q, qpart);
+    mppr_lane_out_kernel<double><<<nblocks(n), kWG, 0, s>>>(static_cast<const double*>(x), n, b, q, qpart, out);
+  } else {
+    mppr_lane_sum_kernel<float><<<kSumBlocks, kWG, 0, s>>>(static_cast<const float*>(x), n, b, q, qpart);
+    mppr_lane_out_kernel<float><<<nblocks(n), kWG, 0, s>>>(static_cast<const float*>(x), n, b, q, qpart, out);
+  }
   return hipGetLastError();
 }
 

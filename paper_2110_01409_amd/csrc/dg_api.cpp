@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "dg.h"
+#include "dg_graph.hpp"
 #include "dg_host.hpp"
 #include "dg_internal.hpp"
 
@@ -75,53 +76,12 @@ void build_tiles(const std::vector<uint32_t>& in_ptr, uint32_t n, std::vector<ui
 
 using dg::host::build_tiles;
 
-namespace {
+using dg::host::kMaxSweeps;
+using dg::host::kSweepChunk;
+using dg::host::kWorkersPerCU;
 
-// Sweeps queued ahead of the host's convergence check.  Each queued sweep
-// first tests on the device whether an earlier one met the stopping rule.
-constexpr uint32_t kSweepChunk = 8;
-constexpr uint32_t kMaxSweeps = 1000000;
-// Default persistent workgroups per compute unit.  Five measured faster than
-// eight on RMAT and banded graphs (fewer concurrent gather streams per CU).
-constexpr uint32_t kWorkersPerCU = 5;
-
-}  // namespace
-
-struct dg_graph {
-  uint32_t n = 0;
-  uint64_t m = 0;
-  bool has_w = false;
-  uint32_t P = 0, T = 0, cus = 0, max_in_deg = 0, n_dangling = 0;
-  uint32_t K = 0;          // sources stored in the compact region
-  uint32_t max_block_v = 1;  // most vertices any worker owns
-  std::vector<uint32_t> tile_v_h, tile_e0_h;  // host copies: first vertex / first in-edge of each tile
-  uint64_t hash = 0;                         // content hash of the in-edge form (tuning cache key)
-  uint64_t hot_edges = 0;  // in-edges whose source is in the compact region
-  size_t lds_per_block = 65536;
-  // allocator captured at creation
-  dg_alloc_fn alloc = nullptr;
-  dg_free_fn free_fn = nullptr;
-  void* ctx = nullptr;
-  hipStream_t create_stream = nullptr;
-  std::vector<void*> owned;
-  uint64_t graph_bytes = 0;
-  // resident graph
-  uint32_t *in_ptr = nullptr, *in_src = nullptr, *in_w = nullptr, *out_deg = nullptr, *cpos = nullptr;
-  uint32_t *tile_v = nullptr, *work_t = nullptr;
-  // workspace (grown on demand)
-  void* vals[3] = {nullptr, nullptr, nullptr};  // 8(n+K) bytes each
-  double* norm = nullptr;                        // kNormBlocks + 1
-  uint32_t ws_sweeps = 0;
-  double *resid = nullptr, *dang = nullptr, *part = nullptr;
-  uint32_t *count = nullptr, *changed = nullptr;
-  void* host_poll = nullptr;  // pinned [S+1] doubles
-  hipEvent_t ev_start = nullptr;
-  hipEvent_t ev_sweep[2 * kSweepChunk] = {};
-  hipEvent_t ev_copy[2] = {};
-  bool events = false;
-};
-
-namespace {
+namespace dg {
+namespace host {
 
 void* dev_alloc(dg_graph* g, size_t bytes, hipStream_t s) {
   if (bytes == 0) bytes = 256;
@@ -143,6 +103,36 @@ void dev_free(dg_graph* g, void* p) {
   if (g->free_fn) g->free_fn(p, g->create_stream, g->ctx);
   else (void)hipFree(p);
 }
+
+}  // namespace host
+}  // namespace dg
+
+namespace dg {
+namespace host {
+
+Topology topo(const dg_graph* g) {
+  Topology t;
+  t.in_ptr = g->in_ptr;
+  t.in_src = g->in_src;
+  t.in_w = g->in_w;
+  t.out_deg = g->out_deg;
+  t.cpos = g->cpos;
+  t.tile_v = g->tile_v;
+  t.work_t = g->work_t;
+  t.n = g->n;
+  t.K = g->K;
+  t.P = g->P;
+  return t;
+}
+
+}  // namespace host
+}  // namespace dg
+
+using dg::host::dev_alloc;
+using dg::host::dev_free;
+using dg::host::topo;
+
+namespace {
 
 void release_all(dg_graph* g) {
   if (g->events) {
@@ -233,20 +223,6 @@ dg_status ensure_workspace(dg_graph* g, uint32_t S, hipStream_t s) {
   return DG_OK;
 }
 
-Topology topo(const dg_graph* g) {
-  Topology t;
-  t.in_ptr = g->in_ptr;
-  t.in_src = g->in_src;
-  t.in_w = g->in_w;
-  t.out_deg = g->out_deg;
-  t.cpos = g->cpos;
-  t.tile_v = g->tile_v;
-  t.work_t = g->work_t;
-  t.n = g->n;
-  t.K = g->K;
-  t.P = g->P;
-  return t;
-}
 
 SweepState state(const dg_graph* g) {
   SweepState st;
@@ -879,6 +855,7 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
   DG_HIP(launch_fill_u32(changed, NB, 1u, s));
   DG_HIP(launch_mbf_init(b0, b1, g->cpos, srcd, k, g->n, g->K, NB, s));
   MbfArgs a;
+  std::memset(&a, 0, sizeof a);  // call mode: no serving fields
   a.g = topo(g);
   a.changed = changed;
   a.shadow = sh;
@@ -996,6 +973,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   if ((size_t)NB * kBatchQ > k) DG_HIP(launch_fill_u32(qdone + k, (size_t)NB * kBatchQ - k, 1u, s));
   DG_HIP(launch_mppr_init(f64, x, c0, c1, g->out_deg, g->cpos, srcd, k, g->n, g->K, NB, dang, s));
   MpprArgs a;
+  std::memset(&a, 0, sizeof a);  // call mode: no serving fields
   a.g = topo(g);
   a.x = x;
   a.shadow = sh;

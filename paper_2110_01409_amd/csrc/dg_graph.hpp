@@ -1,0 +1,73 @@
+// The resident graph object behind dg_graph*, shared by the host translation
+// units (dg_api.cpp: single graphs, batched queries, tuning; dg_server.cpp:
+// the serving loop).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "dg.h"
+#include "dg_internal.hpp"
+
+namespace dg {
+namespace host {
+
+// Sweeps queued ahead of the host's convergence check.  Each queued sweep
+// first tests on the device whether an earlier one met the stopping rule.
+constexpr uint32_t kSweepChunk = 8;
+constexpr uint32_t kMaxSweeps = 1000000;
+// Default persistent workgroups per compute unit.  Five measured faster than
+// eight on RMAT and banded graphs (fewer concurrent gather streams per CU).
+constexpr uint32_t kWorkersPerCU = 5;
+
+}  // namespace host
+}  // namespace dg
+
+struct dg_graph {
+  uint32_t n = 0;
+  uint64_t m = 0;
+  bool has_w = false;
+  uint32_t P = 0, T = 0, cus = 0, max_in_deg = 0, n_dangling = 0;
+  uint32_t K = 0;          // sources stored in the compact region
+  uint32_t max_block_v = 1;  // most vertices any worker owns
+  std::vector<uint32_t> tile_v_h, tile_e0_h;  // host copies: first vertex / first in-edge of each tile
+  uint64_t hash = 0;                         // content hash of the in-edge form (tuning cache key)
+  uint64_t hot_edges = 0;  // in-edges whose source is in the compact region
+  size_t lds_per_block = 65536;
+  // allocator captured at creation
+  dg_alloc_fn alloc = nullptr;
+  dg_free_fn free_fn = nullptr;
+  void* ctx = nullptr;
+  hipStream_t create_stream = nullptr;
+  std::vector<void*> owned;
+  uint64_t graph_bytes = 0;
+  // resident graph
+  uint32_t *in_ptr = nullptr, *in_src = nullptr, *in_w = nullptr, *out_deg = nullptr, *cpos = nullptr;
+  uint32_t *tile_v = nullptr, *work_t = nullptr;
+  // workspace (grown on demand)
+  void* vals[3] = {nullptr, nullptr, nullptr};  // 8(n+K) bytes each
+  double* norm = nullptr;                        // kNormBlocks + 1
+  uint32_t ws_sweeps = 0;
+  double *resid = nullptr, *dang = nullptr, *part = nullptr;
+  uint32_t *count = nullptr, *changed = nullptr;
+  void* host_poll = nullptr;  // pinned [S+1] doubles
+  hipEvent_t ev_start = nullptr;
+  hipEvent_t ev_sweep[2 * dg::host::kSweepChunk] = {};
+  hipEvent_t ev_copy[2] = {};
+  bool events = false;
+};
+
+namespace dg {
+namespace host {
+
+// Device allocations through the graph's allocator hooks (tracked, freed with
+// the graph).
+void* dev_alloc(dg_graph* g, size_t bytes, hipStream_t s);
+void dev_free(dg_graph* g, void* p);
+// Device arrays of the resident graph as passed to the kernels.
+Topology topo(const dg_graph* g);
+
+}  // namespace host
+}  // namespace dg

@@ -86,7 +86,9 @@ struct MbfArgs {
   const uint32_t* din;  // [NB][n+K][64] distances read
   uint32_t* dout;       // [NB][n+K][64] distances written (== din unless synchronous)
   uint32_t* shadow;     // [NB][n][64] delayed-mode staging, else null
-  uint32_t* changed;    // [(S+1)][NB] changed[(k+1)NB+b] != 0 iff sweep k changed batch b
+  uint32_t* changed;    // [(S+1)][NB] changed[(k+1)NB+b] != 0 iff sweep k changed batch b (call mode)
+  uint32_t* lchg;       // serving: [NB][64] set to nonzero for every query that changed in the sweep, else null
+  const uint32_t* bactive;  // serving: [NB] nonzero for batches with running queries, else null
   uint32_t k, d, NB;
 };
 
@@ -101,6 +103,8 @@ struct MpprArgs {
   double* dang;         // [2][NB][64] dangling mass (true scale) returned to the restart vertex, by sweep parity
   double* scale;        // [2][NB][64] storage scale of each query's values, by sweep parity
   uint32_t* qdone;      // [NB][64] 0 while a query runs, else the sweep count that stopped it
+  const uint32_t* bactive;  // serving: [NB] nonzero for batches with running queries (count is then a
+                            // [2][NB] ring and resid is unused), else null
   uint32_t* count;      // [(S+1)][NB] workers finished
   double* part;         // [P][NB][3][64] per-worker partials (change, dangling mass, total mass)
   double alpha, tol;
@@ -204,5 +208,20 @@ hipError_t launch_set_bf_out(int mode, const SetBfArgs& a, uint32_t last_k, uint
 // vw: [n] scratch (worker of each vertex), inv: [K] scratch (vertex of each hot slot).
 hipError_t launch_access_matrix(const Topology& g, uint32_t* vw, uint32_t* inv, uint32_t B,
                                 unsigned long long* counts, unsigned long long* self, hipStream_t s);
+
+// Serving (continuous batching): lanes admitted at a sweep boundary, rows of
+// finished lanes.  lane_src: [NB][64] source per admitted lane, kInf elsewhere;
+// blist: the nb batches that admit anything.
+hipError_t launch_mbf_lane_init(uint32_t* d0, uint32_t* d1, const uint32_t* cpos, uint32_t n, uint32_t K,
+                                const uint32_t* lane_src, const uint32_t* blist, uint32_t nb, hipStream_t s);
+hipError_t launch_mppr_lane_init(bool f64, void* x, void* c0, void* c1, const uint32_t* out_deg, const uint32_t* cpos,
+                                 uint32_t n, uint32_t K, uint32_t NB, const uint32_t* lane_src, const uint32_t* blist,
+                                 uint32_t nb, uint32_t* src, double* dang, double* scale, uint32_t* qdone,
+                                 hipStream_t s);
+hipError_t launch_mbf_lane_out(const uint32_t* d, const uint32_t* cpos, uint32_t n, uint32_t K, uint32_t b, uint32_t q,
+                               uint32_t* out, hipStream_t s);
+// qpart: [256] float64 scratch
+hipError_t launch_mppr_lane_out(bool f64, const void* x, uint32_t n, uint32_t b, uint32_t q, double* qpart,
+                                double* out, hipStream_t s);
 
 }  // namespace dg

@@ -34,8 +34,11 @@ DTYPES = {"f32": DG_F32, "f64": DG_F64}
 EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_info_get", "dg_pagerank",
            "dg_sssp", "dg_sssp_batch", "dg_ppr_batch", "dg_set_create", "dg_set_destroy", "dg_set_info_get",
            "dg_set_pagerank", "dg_set_sssp", "dg_graph_partition", "dg_access_matrix", "dg_graph_repartition",
-           "dg_tune", "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_status_str",
-           "dg_last_error", "dg_version")
+           "dg_tune", "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_server_create",
+           "dg_server_destroy", "dg_server_submit", "dg_server_step", "dg_server_fetch", "dg_server_status_get",
+           "dg_status_str", "dg_last_error", "dg_version")
+DG_QUERY_SSSP, DG_QUERY_PPR = 0, 1
+QUERIES = {"sssp": DG_QUERY_SSSP, "ppr": DG_QUERY_PPR}
 DG_ALGO_PAGERANK, DG_ALGO_SSSP = 0, 1
 DG_TUNE_NO_CACHE, DG_TUNE_KEEP_WORKERS = 1, 2
 MODE_NAMES = {0: "sync", 1: "async", 2: "delayed"}
@@ -77,6 +80,22 @@ class dg_tuning(C.Structure):
     _fields_ = [("workers", C.c_uint32), ("mode", C.c_int), ("d", C.c_uint32), ("sweeps", C.c_uint32),
                 ("seconds", C.c_double), ("predicted_seconds", C.c_double), ("candidates", C.c_uint32),
                 ("from_cache", C.c_uint32), ("graph_hash", C.c_uint64)]
+
+
+class dg_server_opts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_uint64), ("max_batches", C.c_uint32), ("mode", C.c_int), ("d", C.c_uint32),
+                ("damping", C.c_double), ("tol", C.c_double), ("dtype", C.c_int)]
+
+
+class dg_request_info(C.Structure):
+    _fields_ = [("graph", C.c_uint32), ("kind", C.c_int), ("source", C.c_uint32), ("sweeps", C.c_uint32),
+                ("state", C.c_uint32), ("submit_step", C.c_uint64), ("admit_step", C.c_uint64),
+                ("finish_step", C.c_uint64)]
+
+
+class dg_server_status(C.Structure):
+    _fields_ = [("queued", C.c_uint32), ("running", C.c_uint32), ("finished", C.c_uint32), ("batches", C.c_uint32),
+                ("state_bytes", C.c_uint64), ("steps", C.c_uint64)]
 
 
 class dg_set_opts(C.Structure):
@@ -131,6 +150,12 @@ def _load():
         "dg_tune_cache_clear": (C.c_int, []),
         "dg_tune_cache_save": (C.c_int, [C.c_char_p]),
         "dg_tune_cache_load": (C.c_int, [C.c_char_p]),
+        "dg_server_create": (C.c_int, [P, C.c_uint32, C.POINTER(dg_server_opts), P, C.POINTER(C.c_void_p)]),
+        "dg_server_destroy": (C.c_int, [P]),
+        "dg_server_submit": (C.c_int, [P, C.c_uint32, C.c_int, C.c_uint32, C.POINTER(C.c_uint64)]),
+        "dg_server_step": (C.c_int, [P, P, C.c_uint32, C.POINTER(C.c_uint32)]),
+        "dg_server_fetch": (C.c_int, [P, C.c_uint64, P, C.c_int, C.POINTER(dg_request_info)]),
+        "dg_server_status_get": (C.c_int, [P, C.POINTER(dg_server_status)]),
         "dg_status_str": (C.c_char_p, [C.c_int]),
         "dg_last_error": (C.c_char_p, []),
         "dg_version": (C.c_char_p, []),
@@ -239,6 +264,30 @@ def dg_tune_cache_save(path):
 
 def dg_tune_cache_load(path):
     return lib.dg_tune_cache_load(path)
+
+
+def dg_server_create(graphs, count, opts, stream, out):
+    return lib.dg_server_create(graphs, count, opts, stream, out)
+
+
+def dg_server_destroy(srv):
+    return lib.dg_server_destroy(srv)
+
+
+def dg_server_submit(srv, graph, kind, source, out_id):
+    return lib.dg_server_submit(srv, graph, kind, source, out_id)
+
+
+def dg_server_step(srv, out_finished, cap, out_count):
+    return lib.dg_server_step(srv, out_finished, cap, out_count)
+
+
+def dg_server_fetch(srv, rid, out, out_on_device, info):
+    return lib.dg_server_fetch(srv, rid, out, out_on_device, info)
+
+
+def dg_server_status_get(srv, status):
+    return lib.dg_server_status_get(srv, status)
 
 
 def tune_cache_save(path):
@@ -528,6 +577,70 @@ class GraphSet:
     def close(self):
         if getattr(self, "_h", None):
             dg_set_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop over resident ``Graph`` objects (continuous batching).
+
+    ``submit(graph, kind, source)`` queues a query ("sssp" or "ppr") and
+    returns its id; ``step()`` runs one sweep boundary and returns the ids
+    finished so far; ``fetch(id)`` returns the result tensor (uint32
+    distances or float64 scores) and the request's info.
+    """
+
+    def __init__(self, graphs, mode="async", d=64, damping=0.85, tol=1e-6, dtype="f32", hbm_budget=0,
+                 max_batches=0, stream=None):
+        self._graphs = list(graphs)  # keep them alive
+        arr = (C.c_void_p * len(self._graphs))(*[g._h.value for g in self._graphs])
+        opts = dg_server_opts(int(hbm_budget), int(max_batches), MODES[mode], int(d), float(damping), float(tol),
+                              DTYPES[dtype])
+        h = C.c_void_p()
+        _check(dg_server_create(arr, len(self._graphs), C.byref(opts), _stream_handle(stream), C.byref(h)))
+        self._h = h
+        self._buf = np.zeros(4096, np.uint64)
+
+    def submit(self, graph, kind, source):
+        rid = C.c_uint64()
+        _check(dg_server_submit(self._h, int(graph), QUERIES[kind], int(source), C.byref(rid)))
+        return int(rid.value)
+
+    def step(self):
+        cnt = C.c_uint32()
+        _check(dg_server_step(self._h, _np_ptr(self._buf), self._buf.shape[0], C.byref(cnt)))
+        return self._buf[:cnt.value].astype(np.int64).tolist()
+
+    def info(self, rid):
+        info = dg_request_info()
+        _check(dg_server_fetch(self._h, int(rid), None, 0, C.byref(info)))
+        return {"graph": info.graph, "kind": "sssp" if info.kind == DG_QUERY_SSSP else "ppr", "source": info.source,
+                "sweeps": info.sweeps, "state": info.state, "submit_step": info.submit_step,
+                "admit_step": info.admit_step, "finish_step": info.finish_step}
+
+    def fetch(self, rid):
+        import torch
+        inf = self.info(rid)
+        n = self._graphs[inf["graph"]].n
+        out = torch.empty(n, dtype=torch.uint32 if inf["kind"] == "sssp" else torch.float64, device="cuda")
+        info = dg_request_info()
+        _check(dg_server_fetch(self._h, int(rid), C.c_void_p(out.data_ptr()), 1, C.byref(info)))
+        return out, inf
+
+    def status(self):
+        st = dg_server_status()
+        _check(dg_server_status_get(self._h, C.byref(st)))
+        return {"queued": st.queued, "running": st.running, "finished": st.finished, "batches": st.batches,
+                "state_bytes": st.state_bytes, "steps": st.steps}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            dg_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

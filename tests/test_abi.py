@@ -202,3 +202,15 @@ def test_tune_cache_roundtrip(dg, tmp_path):
     dg.tune_cache_save(q)
     assert [ln for ln in q.read_text().splitlines() if not ln.startswith("#")] == []
     assert dg.dg_tune_cache_load(b"/nonexistent/dir/x") == dg.DG_ERR_INVALID_ARGUMENT
+
+
+def test_server_call_validation_null(dg):
+    h = C.c_void_p()
+    opts = dg.dg_server_opts(0, 0, dg.DG_ASYNC, 64, 0.85, 1e-6, dg.DG_F32)
+    assert dg.dg_server_create(None, 1, C.byref(opts), None, C.byref(h)) == dg.DG_ERR_INVALID_ARGUMENT
+    rid = C.c_uint64()
+    assert dg.dg_server_submit(None, 0, 0, 0, C.byref(rid)) == dg.DG_ERR_INVALID_ARGUMENT
+    cnt = C.c_uint32()
+    assert dg.dg_server_step(None, None, 0, C.byref(cnt)) == dg.DG_ERR_INVALID_ARGUMENT
+    assert dg.dg_server_fetch(None, 1, None, 0, None) == dg.DG_ERR_INVALID_ARGUMENT
+    assert dg.dg_server_destroy(None) == dg.DG_OK
