@@ -92,6 +92,86 @@ def cpu_baseline(g, budget_s=15.0):
     }
 
 
+def serve_bench(dg, gg, G22, g22, args):
+    """Serving loop under load: 8 resident R-MAT graphs (scales 16-21 plus the
+    workload graph), requests half SSSP from a random source and half PPR
+    (float32, tol 1e-6) on a random graph.  The peak rate is measured with
+    every request queued at once; then Poisson arrivals at 25/50/75/90% of
+    it, with latency from arrival to the step that retires the request."""
+    import torch
+    scales = [16, 17, 18, 19, 20, 21, 21]
+    graphs, handles = [], []
+    for i, sc in enumerate(scales):
+        gi = gg.rmat(sc, seed=100 + i)
+        graphs.append(gi)
+        handles.append(dg.Graph.from_csr(gi))
+    graphs.append(g22)
+    handles.append(G22)
+    rng = np.random.default_rng(7)
+    R = args.serve_requests
+
+    def make(count):
+        out = []
+        for _ in range(count):
+            gi = int(rng.integers(0, len(graphs)))
+            out.append((gi, "sssp" if rng.random() < 0.5 else "ppr", int(rng.integers(0, graphs[gi].n))))
+        return out
+
+    buf = torch.empty(max(x.n for x in graphs), dtype=torch.float64, device="cuda")
+
+    def run(reqs, arrivals):
+        srv = dg.Server(handles, mode="async", tol=1e-6, dtype="f32")
+        t0 = time.perf_counter()
+        i, pend, lat, fin_t, steps = 0, {}, [], [], 0
+        while len(lat) < len(reqs):
+            now = time.perf_counter() - t0
+            while i < len(reqs) and arrivals[i] <= now:
+                pend[srv.submit(*reqs[i])] = arrivals[i]
+                i += 1
+            if not pend:
+                continue  # idle until the next arrival
+            fin = srv.step()
+            steps += 1
+            now = time.perf_counter() - t0
+            for rid in fin:
+                lat.append(now - pend.pop(rid))
+                fin_t.append(now)
+                srv.fetch(rid, out=buf)
+        wall = time.perf_counter() - t0
+        st = srv.status()
+        srv.close()
+        lat = np.array(lat)
+        # throughput while requests arrive (the drain after the last arrival
+        # excluded); with every request queued at once, over the whole run
+        span = float(arrivals[-1])
+        qps = (np.sum(np.array(fin_t) <= span) / span) if span > 0 else len(reqs) / wall
+        return {"requests": len(reqs), "wall_s": round(wall, 3), "achieved_qps": round(float(qps), 1),
+                "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2), "steps": steps,
+                "batches_peak": st["batches"], "state_gb": round(st["state_bytes"] / 2**30, 2)}
+
+    reqs = make(R)
+    run(reqs[:64], np.zeros(64))  # warm-up
+    peak = run(reqs, np.zeros(R))
+    qps = peak["achieved_qps"]
+    levels = []
+    for load in (0.25, 0.5, 0.75, 0.9):
+        reqs = make(R)
+        arrivals = np.cumsum(rng.exponential(1.0 / (load * qps), size=R))
+        r = run(reqs, arrivals)
+        r["load"] = load
+        r["offered_qps"] = round(load * qps, 1)
+        levels.append(r)
+        log(f"serving at {int(load * 100)}% of peak ({load * qps:.0f} QPS): achieved {r['achieved_qps']} QPS, "
+            f"p50 {r['p50_ms']} ms, p99 {r['p99_ms']} ms")
+    for h in handles[:-1]:
+        h.close()
+    log(f"serving peak (all {R} queued at once): {qps} QPS, p50 {peak['p50_ms']} ms, p99 {peak['p99_ms']} ms")
+    return {"graphs": [f"rmat{s}" for s in scales] + [f"rmat{args.scale}"],
+            "mix": "1/2 SSSP (random source), 1/2 PPR (float32, tol 1e-6), uniform over graphs; async commits",
+            "peak": peak, "levels": levels}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +184,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-topology", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2048)
     ap.add_argument("--batch-queries", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy five times (reference for HBM byte counters)")
@@ -328,6 +410,10 @@ def main():
                 f"(model {t['predicted_seconds'] * 1e3:.3f} ms; default {dflt * 1e3:.3f} ms; "
                 f"{t['candidates']} candidates in {t['tuning_wall_s']} s)")
 
+    serving = {}
+    if not args.no_serve:
+        serving = serve_bench(dg, gg, G, g, args)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(g)
@@ -357,6 +443,7 @@ def main():
         "batched": batched,
         "topology": topology,
         "tuning": tuning,
+        "serving": serving,
     }
     G.close()
     print(json.dumps(out), flush=True)

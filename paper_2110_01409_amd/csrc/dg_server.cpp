@@ -1,10 +1,12 @@
 // Host side of the serving loop (dg_server_*): resident graphs, a queue of
 // requests per (graph, query kind), and continuous batching.  Each pool of a
 // (graph, kind) owns batches of 64 lanes swept by the batched kernels in
-// serving mode; at every sweep boundary queued requests take free lanes (a
-// lane is initialised for its source while the others keep running),
-// finished lanes hand their row to the request and become free, and a pool
-// grows by one batch when it has no free lane and the state budget allows.
+// serving mode; at every sweep boundary of the pool queued requests take free
+// lanes (a lane is initialised for its source while the others keep
+// running), finished lanes hand their row to the request and become free, and
+// the pool grows by one batch when it has no free lane and the state budget
+// allows.  Pools run on streams of their own and advance independently, so a
+// small graph's queries are not paced by a large graph's sweeps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,6 +48,11 @@ struct Pool {
   // both kinds
   uint32_t *bactive = nullptr, *lane_src = nullptr, *blist = nullptr;
   uint32_t* flags_h = nullptr;  // pinned [NB * 64] readback
+  hipStream_t st = nullptr;     // the pool's stream
+  hipEvent_t ev = nullptr;      // recorded after a sweep's readback
+  bool inflight = false;        // a sweep was launched and not yet retired
+  uint64_t launched_at = 0;     // launch order (the oldest is waited for)
+  double* qpart = nullptr;      // [256] normalisation partials (PPR)
   std::vector<int64_t> lane_req;  // request id in each lane, -1 if free
   std::vector<uint32_t> lane_k0;  // pool sweep count when the lane was admitted
   std::deque<uint64_t> queue;
@@ -70,8 +77,7 @@ struct dg_server {
   std::vector<Pool> pools;  // index 2 * graph + kind
   std::vector<Req> reqs;    // index id - 1
   std::deque<uint64_t> finished;
-  uint64_t steps = 0, state_bytes = 0;
-  double* qpart = nullptr;  // [256] normalisation partials
+  uint64_t steps = 0, state_bytes = 0, launches = 0;
 };
 
 namespace {
@@ -95,14 +101,20 @@ void free_pool(Pool& p) {
     dev_free(p.g, q);
   if (p.flags_h) (void)hipHostFree(p.flags_h);
   p.flags_h = nullptr;
+  dev_free(p.g, p.qpart);
+  p.qpart = nullptr;
+  if (p.ev) (void)hipEventDestroy(p.ev);
+  if (p.st) (void)hipStreamDestroy(p.st);
+  p.ev = nullptr;
+  p.st = nullptr;
 }
 
 // Moves old [NB] x stride bytes into the front of a new [NB+1] x stride array.
 template <typename T>
 dg_status regrow(dg_server* s, Pool& p, T*& arr, size_t stride_bytes, bool copy) {
-  T* na = static_cast<T*>(dev_alloc(p.g, (size_t)(p.NB + 1) * stride_bytes, s->s));
+  T* na = static_cast<T*>(dev_alloc(p.g, (size_t)(p.NB + 1) * stride_bytes, p.st));
   if (!na) return fail(DG_ERR_OUT_OF_MEMORY, "serving state allocation failed");
-  if (arr && copy && p.NB) DG_HIP(hipMemcpyAsync(na, arr, (size_t)p.NB * stride_bytes, hipMemcpyDeviceToDevice, s->s));
+  if (arr && copy && p.NB) DG_HIP(hipMemcpyAsync(na, arr, (size_t)p.NB * stride_bytes, hipMemcpyDeviceToDevice, p.st));
   dev_free(p.g, arr);
   arr = na;
   return DG_OK;
@@ -112,14 +124,14 @@ dg_status regrow(dg_server* s, Pool& p, T*& arr, size_t stride_bytes, bool copy)
 template <typename T>
 dg_status regrow_ring(dg_server* s, Pool& p, T*& arr, size_t stride_bytes) {
   const size_t NB = p.NB, NB1 = p.NB + 1;
-  T* na = static_cast<T*>(dev_alloc(p.g, 2 * NB1 * stride_bytes, s->s));
+  T* na = static_cast<T*>(dev_alloc(p.g, 2 * NB1 * stride_bytes, p.st));
   if (!na) return fail(DG_ERR_OUT_OF_MEMORY, "serving state allocation failed");
   if (arr && NB) {
     auto* src = reinterpret_cast<unsigned char*>(arr);
     auto* dst = reinterpret_cast<unsigned char*>(na);
-    DG_HIP(hipMemcpyAsync(dst, src, NB * stride_bytes, hipMemcpyDeviceToDevice, s->s));
+    DG_HIP(hipMemcpyAsync(dst, src, NB * stride_bytes, hipMemcpyDeviceToDevice, p.st));
     DG_HIP(hipMemcpyAsync(dst + NB1 * stride_bytes, src + NB * stride_bytes, NB * stride_bytes,
-                          hipMemcpyDeviceToDevice, s->s));
+                          hipMemcpyDeviceToDevice, p.st));
   }
   dev_free(p.g, arr);
   arr = na;
@@ -133,6 +145,12 @@ dg_status grow(dg_server* s, Pool& p) {
   const bool sync = s->o.mode == DG_SYNC, del = s->o.mode == DG_DELAYED;
   const uint32_t NB1 = p.NB + 1;
   dg_status st;
+  if (!p.st) {
+    DG_HIP(hipStreamCreateWithFlags(&p.st, hipStreamNonBlocking));
+    DG_HIP(hipEventCreateWithFlags(&p.ev, hipEventDisableTiming));
+    p.qpart = static_cast<double*>(dev_alloc(g, 256 * 8, p.st));
+    if (!p.qpart) return fail(DG_ERR_OUT_OF_MEMORY, "serving state allocation failed");
+  }
   if (p.kind == DG_QUERY_SSSP) {
     if ((st = regrow(s, p, p.b0, slots * kLanes * 4, true)) != DG_OK) return st;
     if (sync && (st = regrow(s, p, p.b1, slots * kLanes * 4, true)) != DG_OK) return st;
@@ -150,22 +168,22 @@ dg_status grow(dg_server* s, Pool& p) {
     if ((st = regrow_ring(s, p, p.scale, kLanes * 8)) != DG_OK) return st;
     if ((st = regrow_ring(s, p, p.count, 4)) != DG_OK) return st;
     dev_free(g, p.part);
-    p.part = static_cast<double*>(dev_alloc(g, (size_t)g->P * NB1 * 3 * kLanes * 8, s->s));
+    p.part = static_cast<double*>(dev_alloc(g, (size_t)g->P * NB1 * 3 * kLanes * 8, p.st));
     if (!p.part) return fail(DG_ERR_OUT_OF_MEMORY, "serving state allocation failed");
     // the new batch's lanes are frozen and unassigned
-    DG_HIP(launch_fill_u32(p.qdone + (size_t)p.NB * kLanes, kLanes, 1u, s->s));
-    DG_HIP(launch_fill_u32(p.src + (size_t)p.NB * kLanes, kLanes, kInf, s->s));
-    DG_HIP(launch_fill_f64(p.scale + (size_t)p.NB * kLanes, kLanes, 1.0, s->s));
-    DG_HIP(launch_fill_f64(p.scale + (size_t)(2 * NB1 - 1) * kLanes, kLanes, 1.0, s->s));
-    DG_HIP(launch_fill_f64(p.dang + (size_t)p.NB * kLanes, kLanes, 0.0, s->s));
-    DG_HIP(launch_fill_f64(p.dang + (size_t)(2 * NB1 - 1) * kLanes, kLanes, 0.0, s->s));
+    DG_HIP(launch_fill_u32(p.qdone + (size_t)p.NB * kLanes, kLanes, 1u, p.st));
+    DG_HIP(launch_fill_u32(p.src + (size_t)p.NB * kLanes, kLanes, kInf, p.st));
+    DG_HIP(launch_fill_f64(p.scale + (size_t)p.NB * kLanes, kLanes, 1.0, p.st));
+    DG_HIP(launch_fill_f64(p.scale + (size_t)(2 * NB1 - 1) * kLanes, kLanes, 1.0, p.st));
+    DG_HIP(launch_fill_f64(p.dang + (size_t)p.NB * kLanes, kLanes, 0.0, p.st));
+    DG_HIP(launch_fill_f64(p.dang + (size_t)(2 * NB1 - 1) * kLanes, kLanes, 0.0, p.st));
   }
   dev_free(g, p.bactive);
   dev_free(g, p.lane_src);
   dev_free(g, p.blist);
-  p.bactive = static_cast<uint32_t*>(dev_alloc(g, (size_t)NB1 * 4, s->s));
-  p.lane_src = static_cast<uint32_t*>(dev_alloc(g, (size_t)NB1 * kLanes * 4, s->s));
-  p.blist = static_cast<uint32_t*>(dev_alloc(g, (size_t)NB1 * 4, s->s));
+  p.bactive = static_cast<uint32_t*>(dev_alloc(g, (size_t)NB1 * 4, p.st));
+  p.lane_src = static_cast<uint32_t*>(dev_alloc(g, (size_t)NB1 * kLanes * 4, p.st));
+  p.blist = static_cast<uint32_t*>(dev_alloc(g, (size_t)NB1 * 4, p.st));
   if (!p.bactive || !p.lane_src || !p.blist) return fail(DG_ERR_OUT_OF_MEMORY, "serving state allocation failed");
   if (p.flags_h) (void)hipHostFree(p.flags_h);
   p.flags_h = nullptr;
@@ -215,7 +233,7 @@ dg_status pool_sweep(dg_server* s, Pool& p, bool& ran) {
   for (size_t i = 0; i < p.lane_req.size(); ++i)
     if (p.lane_req[i] >= 0) active[i / kLanes] = 1, any = true;
   if (!any) return DG_OK;
-  hipStream_t q = s->s;
+  hipStream_t q = p.st;
   const Topology t = topo(g);
   if (!blist.empty()) {
     lane_src.resize((size_t)p.NB * kLanes, kNone);
@@ -284,13 +302,13 @@ dg_status pool_retire(dg_server* s, Pool& p) {
     const uint64_t id = (uint64_t)p.lane_req[i];
     Req& r = s->reqs[id - 1];
     const uint32_t b = (uint32_t)(i / kLanes), lane = (uint32_t)(i % kLanes);
-    r.result = dev_alloc(g, (size_t)g->n * (p.kind == DG_QUERY_SSSP ? 4 : 8), s->s);
+    r.result = dev_alloc(g, (size_t)g->n * (p.kind == DG_QUERY_SSSP ? 4 : 8), p.st);
     if (!r.result) return fail(DG_ERR_OUT_OF_MEMORY, "result allocation failed");
     if (p.kind == DG_QUERY_SSSP) {
       // no distance changed in the last sweep, so both buffers hold the result
-      DG_HIP(launch_mbf_lane_out(p.b0, g->cpos, g->n, g->K, b, lane, static_cast<uint32_t*>(r.result), s->s));
+      DG_HIP(launch_mbf_lane_out(p.b0, g->cpos, g->n, g->K, b, lane, static_cast<uint32_t*>(r.result), p.st));
     } else {
-      DG_HIP(launch_mppr_lane_out(f64(s), p.x, g->n, b, lane, s->qpart, static_cast<double*>(r.result), s->s));
+      DG_HIP(launch_mppr_lane_out(f64(s), p.x, g->n, b, lane, p.qpart, static_cast<double*>(r.result), p.st));
     }
     r.state = 2;
     r.finish_step = s->steps;
@@ -330,22 +348,17 @@ dg_status dg_server_create(dg_graph* const* graphs, uint32_t count, const dg_ser
       p.kind = kind;
       p.per_batch = batch_bytes(s, graphs[i], kind);
     }
-  s->qpart = static_cast<double*>(dev_alloc(graphs[0], 256 * 8, s->s));
-  if (!s->qpart) {
-    delete s;
-    return fail(DG_ERR_OUT_OF_MEMORY, "server allocation failed");
-  }
   *out = s;
   return DG_OK;
 }
 
 dg_status dg_server_destroy(dg_server* s) {
   if (!s) return DG_OK;
-  (void)hipStreamSynchronize(s->s);
+  for (auto& p : s->pools)
+    if (p.st) (void)hipStreamSynchronize(p.st);
   for (auto& r : s->reqs)
     if (r.result) dev_free(s->graphs[r.graph], r.result);
   for (auto& p : s->pools) free_pool(p);
-  dev_free(s->graphs[0], s->qpart);
   delete s;
   return DG_OK;
 }
@@ -377,20 +390,58 @@ dg_status dg_server_step(dg_server* s, uint64_t* out_finished, uint32_t cap, uin
   g_last_error.clear();
   if (!s || !out_count || (cap && !out_finished)) return fail(DG_ERR_INVALID_ARGUMENT, "NULL argument");
   ++s->steps;
-  std::vector<char> ran(s->pools.size(), 0);
-  for (size_t i = 0; i < s->pools.size(); ++i) {
-    bool r = false;
-    dg_status st = pool_sweep(s, s->pools[i], r);
+  // A pool whose sweep has finished retires its finished lanes; the rows are
+  // complete when the extraction on its stream is.
+  auto retire = [&](Pool& p) -> dg_status {
+    dg_status st = pool_retire(s, p);
     if (st != DG_OK) return st;
-    ran[i] = r;
+    DG_HIP(hipStreamSynchronize(p.st));
+    p.inflight = false;
+    return DG_OK;
+  };
+  bool retired = false;
+  for (auto& p : s->pools) {
+    if (!p.inflight) continue;
+    const hipError_t q = hipEventQuery(p.ev);
+    if (q == hipErrorNotReady) {
+      (void)hipGetLastError();  // not an error: keep it out of later launch checks
+      continue;
+    }
+    DG_HIP(q);
+    dg_status st = retire(p);
+    if (st != DG_OK) return st;
+    retired = true;
   }
-  DG_HIP(hipStreamSynchronize(s->s));
-  for (size_t i = 0; i < s->pools.size(); ++i) {
-    if (!ran[i]) continue;
-    dg_status st = pool_retire(s, s->pools[i]);
+  // Every idle pool with work admits queued requests and starts its next sweep.
+  auto launch = [&](Pool& p) -> dg_status {
+    bool ran = false;
+    dg_status st = pool_sweep(s, p, ran);
+    if (st != DG_OK) return st;
+    if (ran) {
+      DG_HIP(hipEventRecord(p.ev, p.st));
+      p.inflight = true;
+      p.launched_at = ++s->launches;
+    }
+    return DG_OK;
+  };
+  for (auto& p : s->pools) {
+    if (p.inflight) continue;
+    dg_status st = launch(p);
     if (st != DG_OK) return st;
   }
-  DG_HIP(hipStreamSynchronize(s->s));
+  // Nothing retired in this call: wait for the oldest sweep, retire it and
+  // start its pool's next one, so every call makes progress.
+  if (!retired) {
+    Pool* oldest = nullptr;
+    for (auto& p : s->pools)
+      if (p.inflight && (!oldest || p.launched_at < oldest->launched_at)) oldest = &p;
+    if (oldest) {
+      DG_HIP(hipEventSynchronize(oldest->ev));
+      dg_status st = retire(*oldest);
+      if (st == DG_OK) st = launch(*oldest);
+      if (st != DG_OK) return st;
+    }
+  }
   uint32_t c = 0;
   while (c < cap && !s->finished.empty()) {
     out_finished[c++] = s->finished.front();

@@ -623,11 +623,16 @@ class Server:
                 "sweeps": info.sweeps, "state": info.state, "submit_step": info.submit_step,
                 "admit_step": info.admit_step, "finish_step": info.finish_step}
 
-    def fetch(self, rid):
+    def fetch(self, rid, out=None):
+        """Result of a finished request (into `out`, a device tensor of at
+        least n elements of the result's size, if given) and its info."""
         import torch
         inf = self.info(rid)
         n = self._graphs[inf["graph"]].n
-        out = torch.empty(n, dtype=torch.uint32 if inf["kind"] == "sssp" else torch.float64, device="cuda")
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint32 if inf["kind"] == "sssp" else torch.float64, device="cuda")
+        elif out.numel() * out.element_size() < n * (4 if inf["kind"] == "sssp" else 8) or not out.is_cuda:
+            raise ValueError("out is too small or not on the device")
         info = dg_request_info()
         _check(dg_server_fetch(self._h, int(rid), C.c_void_p(out.data_ptr()), 1, C.byref(info)))
         return out, inf
