@@ -120,9 +120,10 @@ def serve_bench(dg, gg, G22, g22, args):
     buf = torch.empty(max(x.n for x in graphs), dtype=torch.float64, device="cuda")
 
     def run(reqs, arrivals):
-        srv = dg.Server(handles, mode="async", tol=1e-6, dtype="f32")
+        srv = dg.Server(handles, mode="async", tol=1e-6, dtype="f32", hbm_budget=args.serve_budget_gib << 30)
         t0 = time.perf_counter()
         i, pend, lat, fin_t, steps = 0, {}, [], [], 0
+        max_b, max_state, max_q = 0, 0, 0
         while len(lat) < len(reqs):
             now = time.perf_counter() - t0
             while i < len(reqs) and arrivals[i] <= now:
@@ -132,13 +133,16 @@ def serve_bench(dg, gg, G22, g22, args):
                 continue  # idle until the next arrival
             fin = srv.step()
             steps += 1
+            stn = srv.status()
+            max_b = max(max_b, stn["batches"])
+            max_state = max(max_state, stn["state_bytes"])
+            max_q = max(max_q, stn["queued"])
             now = time.perf_counter() - t0
             for rid in fin:
                 lat.append(now - pend.pop(rid))
                 fin_t.append(now)
                 srv.fetch(rid, out=buf)
         wall = time.perf_counter() - t0
-        st = srv.status()
         srv.close()
         lat = np.array(lat)
         # throughput while requests arrive (the drain after the last arrival
@@ -148,7 +152,7 @@ def serve_bench(dg, gg, G22, g22, args):
         return {"requests": len(reqs), "wall_s": round(wall, 3), "achieved_qps": round(float(qps), 1),
                 "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
                 "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2), "steps": steps,
-                "batches_peak": st["batches"], "state_gb": round(st["state_bytes"] / 2**30, 2)}
+                "max_batches": max_b, "max_state_gib": round(max_state / 2**30, 2), "max_queued": max_q}
 
     reqs = make(R)
     run(reqs[:64], np.zeros(64))  # warm-up
@@ -169,6 +173,7 @@ def serve_bench(dg, gg, G22, g22, args):
     log(f"serving peak (all {R} queued at once): {qps} QPS, p50 {peak['p50_ms']} ms, p99 {peak['p99_ms']} ms")
     return {"graphs": [f"rmat{s}" for s in scales] + [f"rmat{args.scale}"],
             "mix": "1/2 SSSP (random source), 1/2 PPR (float32, tol 1e-6), uniform over graphs; async commits",
+            "hbm_budget_gib": args.serve_budget_gib,
             "peak": peak, "levels": levels}
 
 
@@ -186,6 +191,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2048)
+    ap.add_argument("--serve-budget-gib", type=int, default=12, help="batch-state budget of the serving leg")
     ap.add_argument("--batch-queries", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy five times (reference for HBM byte counters)")

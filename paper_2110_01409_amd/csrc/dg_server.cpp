@@ -78,6 +78,7 @@ struct dg_server {
   std::vector<Req> reqs;    // index id - 1
   std::deque<uint64_t> finished;
   uint64_t steps = 0, state_bytes = 0, launches = 0;
+  int64_t starved = -1;  // pool that has queued requests but no batch and no budget, else -1
 };
 
 namespace {
@@ -109,41 +110,50 @@ void free_pool(Pool& p) {
   p.st = nullptr;
 }
 
-// Moves old [NB] x stride bytes into the front of a new [NB+1] x stride array.
+// Re-allocates a [NB] x stride array for NBn batches, keeping the first
+// min(NB, NBn) batches (none when copy is false); NBn = 0 frees it.
 template <typename T>
-dg_status regrow(dg_server* s, Pool& p, T*& arr, size_t stride_bytes, bool copy) {
-  T* na = static_cast<T*>(dev_alloc(p.g, (size_t)(p.NB + 1) * stride_bytes, p.st));
-  if (!na) return fail(DG_ERR_OUT_OF_MEMORY, "serving state allocation failed");
-  if (arr && copy && p.NB) DG_HIP(hipMemcpyAsync(na, arr, (size_t)p.NB * stride_bytes, hipMemcpyDeviceToDevice, p.st));
-  dev_free(p.g, arr);
-  arr = na;
-  return DG_OK;
-}
-
-// [2][NB] x stride layout (two ring slots): both slots keep their batches.
-template <typename T>
-dg_status regrow_ring(dg_server* s, Pool& p, T*& arr, size_t stride_bytes) {
-  const size_t NB = p.NB, NB1 = p.NB + 1;
-  T* na = static_cast<T*>(dev_alloc(p.g, 2 * NB1 * stride_bytes, p.st));
-  if (!na) return fail(DG_ERR_OUT_OF_MEMORY, "serving state allocation failed");
-  if (arr && NB) {
-    auto* src = reinterpret_cast<unsigned char*>(arr);
-    auto* dst = reinterpret_cast<unsigned char*>(na);
-    DG_HIP(hipMemcpyAsync(dst, src, NB * stride_bytes, hipMemcpyDeviceToDevice, p.st));
-    DG_HIP(hipMemcpyAsync(dst + NB1 * stride_bytes, src + NB * stride_bytes, NB * stride_bytes,
-                          hipMemcpyDeviceToDevice, p.st));
+dg_status reshape(Pool& p, T*& arr, size_t stride_bytes, uint32_t NBn, bool copy) {
+  T* na = nullptr;
+  if (NBn) {
+    na = static_cast<T*>(dev_alloc(p.g, (size_t)NBn * stride_bytes, p.st));
+    if (!na) return fail(DG_ERR_OUT_OF_MEMORY, "serving state allocation failed");
+    const size_t keep = (size_t)std::min(p.NB, NBn) * stride_bytes;
+    if (arr && copy && keep) DG_HIP(hipMemcpyAsync(na, arr, keep, hipMemcpyDeviceToDevice, p.st));
   }
   dev_free(p.g, arr);
   arr = na;
   return DG_OK;
 }
 
-// Adds one batch of 64 free lanes to a pool.
-dg_status grow(dg_server* s, Pool& p) {
+// The same for a [2][NB] x stride ring (both slots keep their batches).
+template <typename T>
+dg_status reshape_ring(Pool& p, T*& arr, size_t stride_bytes, uint32_t NBn) {
+  T* na = nullptr;
+  if (NBn) {
+    na = static_cast<T*>(dev_alloc(p.g, 2 * (size_t)NBn * stride_bytes, p.st));
+    if (!na) return fail(DG_ERR_OUT_OF_MEMORY, "serving state allocation failed");
+    const size_t keep = (size_t)std::min(p.NB, NBn) * stride_bytes;
+    if (arr && keep) {
+      auto* src = reinterpret_cast<unsigned char*>(arr);
+      auto* dst = reinterpret_cast<unsigned char*>(na);
+      DG_HIP(hipMemcpyAsync(dst, src, keep, hipMemcpyDeviceToDevice, p.st));
+      DG_HIP(hipMemcpyAsync(dst + (size_t)NBn * stride_bytes, src + (size_t)p.NB * stride_bytes, keep,
+                            hipMemcpyDeviceToDevice, p.st));
+    }
+  }
+  dev_free(p.g, arr);
+  arr = na;
+  return DG_OK;
+}
+
+// Resizes a pool to NBn batches of 64 lanes.  Growing adds free lanes;
+// shrinking drops trailing batches, whose lanes must all be free (0 releases
+// the pool's whole state).  The budget account follows.
+dg_status resize(dg_server* s, Pool& p, uint32_t NBn) {
   dg_graph* g = p.g;
   const size_t n = g->n, slots = (size_t)g->n + g->K;
   const bool sync = s->o.mode == DG_SYNC, del = s->o.mode == DG_DELAYED;
-  const uint32_t NB1 = p.NB + 1;
   dg_status st;
   if (!p.st) {
     DG_HIP(hipStreamCreateWithFlags(&p.st, hipStreamNonBlocking));
@@ -152,52 +162,61 @@ dg_status grow(dg_server* s, Pool& p) {
     if (!p.qpart) return fail(DG_ERR_OUT_OF_MEMORY, "serving state allocation failed");
   }
   if (p.kind == DG_QUERY_SSSP) {
-    if ((st = regrow(s, p, p.b0, slots * kLanes * 4, true)) != DG_OK) return st;
-    if (sync && (st = regrow(s, p, p.b1, slots * kLanes * 4, true)) != DG_OK) return st;
-    if (del && (st = regrow(s, p, p.sh, n * kLanes * 4, false)) != DG_OK) return st;
-    if ((st = regrow(s, p, p.lchg, kLanes * 4, false)) != DG_OK) return st;
+    if ((st = reshape(p, p.b0, slots * kLanes * 4, NBn, true)) != DG_OK) return st;
+    if (sync && (st = reshape(p, p.b1, slots * kLanes * 4, NBn, true)) != DG_OK) return st;
+    if (del && (st = reshape(p, p.sh, n * kLanes * 4, NBn, false)) != DG_OK) return st;
+    if ((st = reshape(p, p.lchg, kLanes * 4, NBn, false)) != DG_OK) return st;
   } else {
     const size_t e = f64(s) ? 8 : 4;
-    if ((st = regrow(s, p, p.x, n * kLanes * e, true)) != DG_OK) return st;
-    if ((st = regrow(s, p, p.c0, slots * kLanes * e, true)) != DG_OK) return st;
-    if (sync && (st = regrow(s, p, p.c1, slots * kLanes * e, true)) != DG_OK) return st;
-    if (del && (st = regrow(s, p, p.psh, n * kLanes * e, false)) != DG_OK) return st;
-    if ((st = regrow(s, p, p.src, kLanes * 4, true)) != DG_OK) return st;
-    if ((st = regrow(s, p, p.qdone, kLanes * 4, true)) != DG_OK) return st;
-    if ((st = regrow_ring(s, p, p.dang, kLanes * 8)) != DG_OK) return st;
-    if ((st = regrow_ring(s, p, p.scale, kLanes * 8)) != DG_OK) return st;
-    if ((st = regrow_ring(s, p, p.count, 4)) != DG_OK) return st;
-    dev_free(g, p.part);
-    p.part = static_cast<double*>(dev_alloc(g, (size_t)g->P * NB1 * 3 * kLanes * 8, p.st));
-    if (!p.part) return fail(DG_ERR_OUT_OF_MEMORY, "serving state allocation failed");
-    // the new batch's lanes are frozen and unassigned
-    DG_HIP(launch_fill_u32(p.qdone + (size_t)p.NB * kLanes, kLanes, 1u, p.st));
-    DG_HIP(launch_fill_u32(p.src + (size_t)p.NB * kLanes, kLanes, kInf, p.st));
-    DG_HIP(launch_fill_f64(p.scale + (size_t)p.NB * kLanes, kLanes, 1.0, p.st));
-    DG_HIP(launch_fill_f64(p.scale + (size_t)(2 * NB1 - 1) * kLanes, kLanes, 1.0, p.st));
-    DG_HIP(launch_fill_f64(p.dang + (size_t)p.NB * kLanes, kLanes, 0.0, p.st));
-    DG_HIP(launch_fill_f64(p.dang + (size_t)(2 * NB1 - 1) * kLanes, kLanes, 0.0, p.st));
+    if ((st = reshape(p, p.x, n * kLanes * e, NBn, true)) != DG_OK) return st;
+    if ((st = reshape(p, p.c0, slots * kLanes * e, NBn, true)) != DG_OK) return st;
+    if (sync && (st = reshape(p, p.c1, slots * kLanes * e, NBn, true)) != DG_OK) return st;
+    if (del && (st = reshape(p, p.psh, n * kLanes * e, NBn, false)) != DG_OK) return st;
+    if ((st = reshape(p, p.src, kLanes * 4, NBn, true)) != DG_OK) return st;
+    if ((st = reshape(p, p.qdone, kLanes * 4, NBn, true)) != DG_OK) return st;
+    if ((st = reshape_ring(p, p.dang, kLanes * 8, NBn)) != DG_OK) return st;
+    if ((st = reshape_ring(p, p.scale, kLanes * 8, NBn)) != DG_OK) return st;
+    if ((st = reshape_ring(p, p.count, 4, NBn)) != DG_OK) return st;
+    if ((st = reshape(p, p.part, (size_t)g->P * 3 * kLanes * 8, NBn, false)) != DG_OK) return st;
+    // new batches: lanes frozen and unassigned
+    for (uint32_t b = p.NB; b < NBn; ++b) {
+      DG_HIP(launch_fill_u32(p.qdone + (size_t)b * kLanes, kLanes, 1u, p.st));
+      DG_HIP(launch_fill_u32(p.src + (size_t)b * kLanes, kLanes, kInf, p.st));
+      DG_HIP(launch_fill_f64(p.scale + (size_t)b * kLanes, kLanes, 1.0, p.st));
+      DG_HIP(launch_fill_f64(p.scale + (size_t)(NBn + b) * kLanes, kLanes, 1.0, p.st));
+      DG_HIP(launch_fill_f64(p.dang + (size_t)b * kLanes, kLanes, 0.0, p.st));
+      DG_HIP(launch_fill_f64(p.dang + (size_t)(NBn + b) * kLanes, kLanes, 0.0, p.st));
+    }
   }
-  dev_free(g, p.bactive);
-  dev_free(g, p.lane_src);
-  dev_free(g, p.blist);
-  p.bactive = static_cast<uint32_t*>(dev_alloc(g, (size_t)NB1 * 4, p.st));
-  p.lane_src = static_cast<uint32_t*>(dev_alloc(g, (size_t)NB1 * kLanes * 4, p.st));
-  p.blist = static_cast<uint32_t*>(dev_alloc(g, (size_t)NB1 * 4, p.st));
-  if (!p.bactive || !p.lane_src || !p.blist) return fail(DG_ERR_OUT_OF_MEMORY, "serving state allocation failed");
+  if ((st = reshape(p, p.bactive, 4, NBn, false)) != DG_OK) return st;
+  if ((st = reshape(p, p.lane_src, kLanes * 4, NBn, false)) != DG_OK) return st;
+  if ((st = reshape(p, p.blist, 4, NBn, false)) != DG_OK) return st;
+  DG_HIP(hipStreamSynchronize(p.st));  // copies done before the old arrays' memory is reused
   if (p.flags_h) (void)hipHostFree(p.flags_h);
   p.flags_h = nullptr;
-  DG_HIP(hipHostMalloc((void**)&p.flags_h, (size_t)NB1 * kLanes * 4, hipHostMallocDefault));
-  p.NB = NB1;
-  p.lane_req.resize((size_t)NB1 * kLanes, -1);
-  p.lane_k0.resize((size_t)NB1 * kLanes, 0);
-  s->state_bytes += p.per_batch;
+  if (NBn) DG_HIP(hipHostMalloc((void**)&p.flags_h, (size_t)NBn * kLanes * 4, hipHostMallocDefault));
+  s->state_bytes = s->state_bytes + (size_t)NBn * p.per_batch - (size_t)p.NB * p.per_batch;
+  p.NB = NBn;
+  p.lane_req.resize((size_t)NBn * kLanes, -1);
+  p.lane_k0.resize((size_t)NBn * kLanes, 0);
   return DG_OK;
 }
 
-bool can_grow(const dg_server* s, const Pool& p) {
+bool budget_allows(const dg_server* s, const Pool& p) {
   if (s->o.max_batches && p.NB >= s->o.max_batches) return false;
   return !s->o.hbm_budget || s->state_bytes + p.per_batch <= s->o.hbm_budget;
+}
+
+bool lanes_free(const Pool& p, uint32_t b) {
+  for (uint32_t i = 0; i < kLanes; ++i)
+    if (p.lane_req[(size_t)b * kLanes + i] >= 0) return false;
+  return true;
+}
+
+// While a pool starves (queued requests, no batch, no budget), only it may grow.
+bool can_grow(const dg_server* s, const Pool& p) {
+  if (s->starved >= 0 && &s->pools[(size_t)s->starved] != &p) return false;
+  return budget_allows(s, p);
 }
 
 // Admission, one sweep and retirement for one pool.  Returns the number of
@@ -209,11 +228,15 @@ dg_status pool_sweep(dg_server* s, Pool& p, bool& ran) {
   std::vector<uint32_t> lane_src;
   std::vector<uint32_t> blist;
   size_t cursor = 0;
+  // while another pool starves, a pool of several batches keeps its last
+  // batch free of new queries so that it can be released
+  const bool donor = s->starved >= 0 && &s->pools[(size_t)s->starved] != &p && p.NB >= 2;
   while (!p.queue.empty()) {
-    while (cursor < p.lane_req.size() && p.lane_req[cursor] >= 0) ++cursor;
-    if (cursor == p.lane_req.size()) {
-      if (!can_grow(s, p)) break;
-      dg_status st = grow(s, p);
+    const size_t limit = donor ? (size_t)(p.NB - 1) * kLanes : p.lane_req.size();
+    while (cursor < limit && p.lane_req[cursor] >= 0) ++cursor;
+    if (cursor >= limit) {
+      if (donor || !can_grow(s, p)) break;
+      dg_status st = resize(s, p, p.NB + 1);
       if (st != DG_OK) return st;
     }
     const uint64_t id = p.queue.front();
@@ -411,6 +434,39 @@ dg_status dg_server_step(dg_server* s, uint64_t* out_finished, uint32_t cap, uin
     dg_status st = retire(p);
     if (st != DG_OK) return st;
     retired = true;
+  }
+  // Budget: a pool with nothing running and nothing queued releases its
+  // state; a pool that has queued requests but no batch and no budget starves,
+  // and then other pools do not grow and give up trailing batches that
+  // emptied, until it fits.
+  for (auto& p : s->pools) {
+    if (p.inflight || p.NB == 0 || !p.queue.empty()) continue;
+    bool idle = true;
+    for (int64_t r : p.lane_req) idle = idle && r < 0;
+    if (idle) {
+      dg_status st = resize(s, p, 0);
+      if (st != DG_OK) return st;
+    }
+  }
+  s->starved = -1;
+  uint64_t oldest = ~0ull;
+  for (size_t i = 0; i < s->pools.size(); ++i) {
+    const Pool& p = s->pools[i];
+    if (p.NB == 0 && !p.queue.empty() && !budget_allows(s, p) && p.queue.front() < oldest) {
+      oldest = p.queue.front();
+      s->starved = (int64_t)i;
+    }
+  }
+  if (s->starved >= 0) {
+    const Pool& hungry = s->pools[(size_t)s->starved];
+    for (auto& p : s->pools) {
+      if (budget_allows(s, hungry)) break;
+      if (&p == &hungry) continue;
+      while (!p.inflight && p.NB >= 2 && lanes_free(p, p.NB - 1) && !budget_allows(s, hungry)) {
+        dg_status st = resize(s, p, p.NB - 1);
+        if (st != DG_OK) return st;
+      }
+    }
   }
   // Every idle pool with work admits queued requests and starts its next sweep.
   auto launch = [&](Pool& p) -> dg_status {

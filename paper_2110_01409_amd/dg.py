@@ -392,6 +392,7 @@ class Graph:
         self._h = h
         self.n = int(n)
         self.m = int(idx.shape[0])
+        self._dependents = []  # objects holding device state allocated through this graph
 
     @classmethod
     def from_csr(cls, g, **kw):
@@ -490,6 +491,11 @@ class Graph:
 
     def close(self):
         if getattr(self, "_h", None):
+            # A server's batch state is allocated through the graph: release it
+            # first.  The references are strong so that this also holds when the
+            # garbage collector finalizes a graph and its server in either order.
+            for dep in list(getattr(self, "_dependents", [])):
+                dep.close()
             dg_graph_destroy(self._h)
             self._h = None
 
@@ -598,6 +604,8 @@ class Server:
     def __init__(self, graphs, mode="async", d=64, damping=0.85, tol=1e-6, dtype="f32", hbm_budget=0,
                  max_batches=0, stream=None):
         self._graphs = list(graphs)  # keep them alive
+        for g in self._graphs:
+            g._dependents.append(self)
         arr = (C.c_void_p * len(self._graphs))(*[g._h.value for g in self._graphs])
         opts = dg_server_opts(int(hbm_budget), int(max_batches), MODES[mode], int(d), float(damping), float(tol),
                               DTYPES[dtype])
@@ -647,6 +655,9 @@ class Server:
         if getattr(self, "_h", None):
             dg_server_destroy(self._h)
             self._h = None
+        for g in getattr(self, "_graphs", []):
+            if self in getattr(g, "_dependents", []):
+                g._dependents.remove(self)
 
     def __del__(self):
         try:

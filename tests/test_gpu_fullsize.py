@@ -106,3 +106,47 @@ def test_banded16m_pagerank_and_sssp(dg):
         print(f"banded sssp {mode} d={d}: sweeps={st.sweeps} certificate {msg}", flush=True)
         assert ok, msg
     G.close()
+
+
+@pytest.fixture(scope="module")
+def rmat20():
+    return gg.rmat(20, seed=20)
+
+
+def test_rmat20_batched_256_sources(dg, rmat20):
+    """The batched configuration at its own size: 256 SSSP sources and 256
+    one-hot PPR vectors on RMAT-20.  Every SSSP row passes the oracle's
+    optimality certificate and 8 rows equal Dijkstra (scipy); every PPR row
+    (float64, tol 1e-9) is bounded by the oracle's contraction certificate
+    ||P_s(x) - x|| / (1 - alpha) <= 1e-7, and 2 rows are compared with the
+    oracle's fixed point directly."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import dijkstra as sp_dijkstra
+    g = rmat20
+    sources = gg.pick_sources(g, 256, seed=20)
+    G = dg.Graph.from_csr(g)
+    out, st = G.sssp_batch(sources, mode="async")
+    print(f"rmat20 sssp_batch x256 async: sweeps={st.sweeps} t={st.seconds * 1e3:.1f} ms", flush=True)
+    got = out.cpu().numpy()
+    for q in range(0, 256, 16):
+        ok, msg = osp.certificate(g, int(sources[q]), got[q])
+        assert ok, (q, msg)
+    mat = csr_matrix((g.w.astype(np.float64), g.idx, g.ptr.astype(np.int64)), shape=(g.n, g.n))
+    ref = sp_dijkstra(mat, directed=True, indices=sources[:8].astype(np.int64))
+    for q in range(8):
+        r = np.where(np.isinf(ref[q]), dg.DG_INF_DIST, ref[q]).astype(np.uint32)
+        np.testing.assert_array_equal(got[q], r, err_msg=f"row {q}")
+    del out, got
+    x, st = G.ppr_batch(sources, tol=1e-9, mode="async", dtype="f64", max_sweeps=2000)
+    print(f"rmat20 ppr_batch x256 async f64: sweeps={st.sweeps} t={st.seconds * 1e3:.1f} ms", flush=True)
+    xs = x.cpu().numpy()
+    worst = 0.0
+    for q in range(0, 256, 16):
+        c = opr.ppr_certificate(g, xs[q], int(sources[q]))
+        worst = max(worst, c)
+        assert c <= 1e-7, (q, c)
+    for q in range(2):
+        ref_x = opr.ppr_fixed_point(g, int(sources[q]))
+        assert float(np.abs(xs[q] - ref_x).sum()) <= 1e-8
+    print(f"rmat20 ppr worst certificate bound {worst:.2e}", flush=True)
+    G.close()

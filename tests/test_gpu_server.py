@@ -162,6 +162,46 @@ def test_server_budget_queues_requests(dg, graphs):
     G.close()
 
 
+def test_server_budget_starvation_resolved(dg, graphs):
+    """Two pools, a budget for one batch of either but not both: the second
+    pool starts without a batch (starved) and gets one when the first drains
+    and releases its state; every request completes within the budget."""
+    ga, gb = graphs[0], graphs[1]
+    GA, GB = dg.Graph.from_csr(ga), dg.Graph.from_csr(gb)
+
+    def one_batch(G):
+        probe = dg.Server([G], mode="async")
+        probe.submit(0, "sssp", 0)
+        probe.step()
+        b = probe.status()["state_bytes"]
+        probe.close()
+        return b
+
+    ba, bb = one_batch(GA), one_batch(GB)
+    budget = max(ba, bb) + min(ba, bb) // 2
+    srv = dg.Server([GA, GB], mode="async", hbm_budget=budget)
+    rng = np.random.default_rng(9)
+    reqs = [(0, "sssp", int(x)) for x in rng.integers(0, ga.n, 100)] + \
+           [(1, "sssp", int(x)) for x in rng.integers(0, gb.n, 100)]
+    ids = [srv.submit(*r) for r in reqs]
+    done, peak = set(), 0
+    for _ in range(20_000):
+        if len(done) == len(ids):
+            break
+        done.update(srv.step())
+        peak = max(peak, srv.status()["state_bytes"])
+    assert len(done) == len(ids)
+    assert peak <= budget
+    for rid, (gi, _, src) in zip(ids, reqs):
+        out, _ = srv.fetch(rid)
+        np.testing.assert_array_equal(out.cpu().numpy(), osp.bellman_ford_sync(graphs[gi], src)[0])
+    srv.step()  # the next step finds both pools idle and releases their state
+    assert srv.status()["state_bytes"] == 0
+    srv.close()
+    GA.close()
+    GB.close()
+
+
 def test_server_validation(dg, graphs):
     G = dg.Graph.from_csr(graphs[0])
     srv = dg.Server([G])
