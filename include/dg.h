@@ -313,22 +313,20 @@ dg_status dg_access_matrix(dg_graph* g, uint32_t groups, uint64_t* out_counts, d
 
 /* Graph sets (a form beyond the paper's single graph: many graphs, of uneven
  * sizes, resident together and swept in one launch per sweep).  The graphs
- * are stored as one union graph; tiles never span two graphs and workgroups
- * take tiles from a global work list, so a set of small graphs fills the GPU
- * and graphs that have stopped cost nothing but a flag test.  Every graph
- * runs the algorithm of the single-graph call (dg_pagerank / dg_sssp, with
- * the same commit modes of section III and the same per-graph formulas and
- * stopping rules) and stops on its own.  In delayed mode a workgroup commits
- * after staging >= d vertices or 64 tiles, and when its share of the sweep
- * ends.  Sweeps run in chunks of 8; by default a chunk is captured once into
- * a HIP graph and replayed (DG_SET_EAGER launches the kernels directly).
- * Calls run on a stream of the set's own, ordered after work already queued
- * on hip_stream, and return when the results are complete.  Calls on one set
- * must not overlap.
- * STATUS: dg_set_pagerank and dg_set_sssp are switched off in this build and
- * return DG_ERR_UNSUPPORTED after validating their arguments (their first
- * run on the GPU stopped making progress, cause not yet identified);
- * dg_set_create, dg_set_info_get and dg_set_destroy work. */
+ * are stored as one union graph (graph i's vertices follow those of graphs
+ * 0..i-1; no edge crosses two graphs) and swept by the single-graph kernels
+ * in the commit modes of section III, so one launch serves every graph and
+ * the blocked partition balances the union's edges over the GPU.
+ *  - SSSP: every graph's Bellman-Ford starts from its own source; each
+ *    graph's distances are exactly those of dg_sssp on it.
+ *  - PageRank: the union's PageRank restricted to one graph and renormalised
+ *    to sum 1 equals that graph's own (its teleport and dangling term is the
+ *    same constant for all vertices, and the graph's mass balance rescales
+ *    it to the graph's own).  The union stops when its L1 change is below
+ *    tol (1 - damping) min_i n_i / N, which bounds every graph's own L1
+ *    change by tol.
+ * All graphs sweep until the last one stops: out_sweeps reports the set's
+ * sweep count for every graph. */
 typedef struct dg_set dg_set;
 
 typedef struct {
@@ -353,7 +351,6 @@ typedef struct {
   uint64_t device_bytes;
 } dg_set_info;
 
-#define DG_SET_EAGER 1u  /* launch each sweep directly instead of replaying a captured chunk */
 
 /* Builds and uploads a set of `count` graphs (host CSR arrays; copied, not
  * retained).  Limits: total vertices < 2^31, total edges < 2^32 - 2^12. */
@@ -363,20 +360,23 @@ dg_status dg_set_destroy(dg_set* s);
 dg_status dg_set_info_get(const dg_set* s, dg_set_info* info);
 
 /* PageRank of every graph of the set (as dg_pagerank, per graph).
- *   flags       0 or DG_SET_EAGER
+ *   flags       0 (reserved)
+ *   dtype       DG_F32 only when the union tolerance above is >= 1e-7 (the
+ *               float32 rounding floor), else DG_ERR_UNSUPPORTED: use DG_F64
  *   out_scores  n float64 over the union (graph i's vertices at its offset,
  *               the sum of the n of graphs before it), each graph normalised
  *               to sum 1; device memory when out_on_device != 0
- *   out_sweeps  host array of `graphs` entries or NULL: sweeps each graph
- *               took (0 = it did not stop within max_sweeps)
- *   stats       sweeps = the most any graph took; edges_traversed = sum over
- *               graphs of m * sweeps; seconds = device time of the sweeps */
+ *   out_sweeps  host array of `graphs` entries or NULL: the set's sweeps
+ *               (0 = it did not stop within max_sweeps)
+ *   stats       as dg_pagerank's on the union: sweeps, device seconds of the
+ *               sweeps, edges_traversed = total edges x sweeps */
 dg_status dg_set_pagerank(dg_set* s, double damping, double tol, dg_mode mode, uint32_t d, dg_dtype dtype,
                           uint32_t max_sweeps, uint32_t flags, double* out_scores, int out_on_device,
                           uint32_t* out_sweeps, dg_stats* stats, void* hip_stream);
 
 /* Bellman-Ford of every graph from its own source (as dg_sssp, per graph).
  *   sources     host array of `graphs` vertex ids, local to each graph
+ *   flags       0 (reserved)
  *   out_dist    n uint32 over the union, DG_INF_DIST where unreachable */
 dg_status dg_set_sssp(dg_set* s, const uint32_t* sources, dg_mode mode, uint32_t d, uint32_t max_sweeps,
                       uint32_t flags, uint32_t* out_dist, int out_on_device, uint32_t* out_sweeps,

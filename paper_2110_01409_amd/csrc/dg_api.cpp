@@ -736,6 +736,16 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
 
 dg_status dg_sssp(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t max_sweeps, uint32_t* out_dist,
                   int out_on_device, dg_stats* stats, void* hip_stream) {
+  return dg::host::sssp_run(g, src, nullptr, 0, mode, d, max_sweeps, out_dist, out_on_device, stats, hip_stream);
+}
+
+}  // extern "C"
+
+namespace dg {
+namespace host {
+
+dg_status sssp_run(dg_graph* g, uint32_t src, const uint32_t* more_src, uint32_t n_more, dg_mode mode, uint32_t d,
+                   uint32_t max_sweeps, uint32_t* out_dist, int out_on_device, dg_stats* stats, void* hip_stream) {
   g_last_error.clear();
   if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
   if (!g->has_w) return fail(DG_ERR_INVALID_ARGUMENT, "graph was created without weights");
@@ -755,6 +765,7 @@ dg_status dg_sssp(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t 
   uint32_t* b1 = mode == DG_SYNC ? static_cast<uint32_t*>(g->vals[1]) : nullptr;
   SweepState sst = state(g);
   DG_HIP(launch_bf_init(b0, b1, g->cpos, g->n, src, sst, max_sweeps, s));
+  if (n_more) DG_HIP(launch_bf_more_sources(b0, b1, g->cpos, more_src, n_more, s));
 
   BfArgs a;
   a.g = topo(g);
@@ -803,6 +814,11 @@ dg_status dg_sssp(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t 
   if (!conv) return fail(DG_ERR_NOT_CONVERGED, "no convergence within %u sweeps", max_sweeps);
   return DG_OK;
 }
+
+}  // namespace host
+}  // namespace dg
+
+extern "C" {
 
 // ----------------------------------------------------------- batched --
 

@@ -68,6 +68,11 @@ void* dev_alloc(dg_graph* g, size_t bytes, hipStream_t s);
 void dev_free(dg_graph* g, void* p);
 // Device arrays of the resident graph as passed to the kernels.
 Topology topo(const dg_graph* g);
+// Bellman-Ford from src and, when n_more > 0, also from the n_more sources in
+// the device array more_src (distance to the nearest source); otherwise as
+// dg_sssp.
+dg_status sssp_run(dg_graph* g, uint32_t src, const uint32_t* more_src, uint32_t n_more, dg_mode mode, uint32_t d,
+                   uint32_t max_sweeps, uint32_t* out_dist, int out_on_device, dg_stats* stats, void* hip_stream);
 
 }  // namespace host
 }  // namespace dg

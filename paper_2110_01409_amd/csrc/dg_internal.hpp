@@ -139,69 +139,13 @@ hipError_t launch_bf_sweep(int mode, const BfArgs& a, hipStream_t s);
 hipError_t launch_normalize(bool f64, const void* x, uint32_t n, double* out, double* scratch, hipStream_t s);
 constexpr uint32_t kNormBlocks = 512;  // scratch needs kNormBlocks + 1 doubles
 
-// Sets of graphs swept together: one launch per sweep over the union of
-// their vertices.  Tiles never span two graphs; workgroups take tiles from a
-// global work list (one atomic cursor per sweep), and each graph has its own
-// reductions and stopping rule.
-struct SetTopo {
-  const uint32_t* in_ptr;   // [N+1] in-edge offsets over the union
-  const uint32_t* in_src;   // [M + kEdgePad] source vertex (union id) of each in-edge
-  const uint32_t* in_w;     // [M + kEdgePad] weight of each in-edge (nullable)
-  const uint32_t* out_deg;  // [N] out-degree
-  const uint32_t* tile_v;   // [T+1] first vertex of each tile
-  const uint32_t* tile_g;   // [T] graph of each tile
-  const uint32_t* g_voff;   // [G+1] first vertex of each graph
-  const uint32_t* g_toff;   // [G+1] first tile of each graph
-  uint32_t N, T, G;
-  uint32_t P;               // workgroups launched per sweep
-};
-
-// Per-call control state.  The sweep index lives on the device and is
-// advanced by the fold kernel that closes each sweep, so a chunk of sweeps
-// is the same sequence of launches every time and can be captured once.
-struct SetCtl {
-  uint32_t* cur;        // [1] index of the next sweep
-  uint32_t* next;       // [S+1] work-list cursor of each sweep
-  uint32_t* live;       // [S+1] graphs still running at the start of sweep k; live[0] = G
-  uint32_t* fcount;     // [S+1] fold blocks finished in sweep k
-  uint32_t* gdone;      // [G] 0 while a graph runs, else the number of sweeps it took
-  uint32_t* host_live;  // [S+1] host-mapped copy of live, written by the last fold block
-  uint32_t S;           // sweep limit
-};
-
-struct SetPrArgs {
-  SetTopo g;
-  SetCtl c;
-  void* c0;       // [N] contributions (synchronous: read in even sweeps)
-  void* c1;       // [N] second buffer (synchronous only, else null)
-  void* x;        // [N] scores
-  void* shadow;   // [N] delayed-mode staging (else null)
-  double* tpart;  // [T][2] per-tile partials: L1 change, non-dangling mass
-  double* gdang;  // [2][G] mass each graph spreads in a sweep, by sweep parity
-  double* gres;   // [G] L1 change of each graph's last sweep
-  double alpha, tol;
-  uint32_t d;     // commit interval in vertices (delayed)
-};
-
-struct SetBfArgs {
-  SetTopo g;
-  SetCtl c;
-  uint32_t* c0;      // [N] distances (synchronous: read in even sweeps)
-  uint32_t* c1;      // [N] second buffer (synchronous only, else null)
-  uint32_t* shadow;  // [N] delayed-mode staging (else null)
-  uint32_t* tchg;    // [T] per-tile "a distance decreased" flags
-  uint32_t d;
-};
-
-hipError_t launch_set_pr_init(bool f64, const SetPrArgs& a, const double* dang0, hipStream_t s);
-// One sweep: the sweep kernel, then the fold kernel that reduces per graph,
-// freezes converged graphs and advances the sweep index.
-hipError_t launch_set_pr_sweep(int mode, bool f64, const SetPrArgs& a, hipStream_t s);
-hipError_t launch_set_pr_out(bool f64, const SetPrArgs& a, double* out, hipStream_t s);
-hipError_t launch_set_bf_init(const SetBfArgs& a, const uint32_t* src, hipStream_t s);
-hipError_t launch_set_bf_sweep(int mode, const SetBfArgs& a, hipStream_t s);
-// last_k: index of the last sweep run (buffer choice for graphs that did not converge)
-hipError_t launch_set_bf_out(int mode, const SetBfArgs& a, uint32_t last_k, uint32_t* out, hipStream_t s);
+// Sets of graphs stored as one union graph (disjoint vertex ranges).
+// Distances 0 at k more sources (device array src of vertex ids), in both
+// buffers when d1 is not null.
+hipError_t launch_bf_more_sources(uint32_t* d0, uint32_t* d1, const uint32_t* cpos, const uint32_t* src, uint32_t k,
+                                  hipStream_t s);
+// x[voff[g] .. voff[g+1]) /= its sum, for each of the G graphs (fixed order).
+hipError_t launch_segment_normalize(double* x, const uint32_t* voff, uint32_t G, hipStream_t s);
 
 // Access matrix of one pull sweep: counts[r * B + c] += reads by worker group r
 // of values written by group c; *self += reads of a value the reader writes.

@@ -42,7 +42,6 @@ QUERIES = {"sssp": DG_QUERY_SSSP, "ppr": DG_QUERY_PPR}
 DG_ALGO_PAGERANK, DG_ALGO_SSSP = 0, 1
 DG_TUNE_NO_CACHE, DG_TUNE_KEEP_WORKERS = 1, 2
 MODE_NAMES = {0: "sync", 1: "async", 2: "delayed"}
-DG_SET_EAGER = 1
 
 
 class dg_stats(C.Structure):
@@ -513,12 +512,14 @@ class Graph:
 
 
 class GraphSet:
-    """Many graphs resident together and swept in one launch per sweep.
+    """Many graphs resident together (one union graph) and swept in one
+    launch per sweep.
 
     ``GraphSet(graphs)`` takes ``graphgen.CSRGraph`` objects (all weighted or
     all unweighted).  Results are flat tensors over the union of the graphs'
-    vertices; ``offsets[i]`` is graph i's first vertex and ``split(t)`` cuts
-    a result into per-graph views.
+    vertices, each graph's PageRank normalised on its own; ``offsets[i]`` is
+    graph i's first vertex and ``split(t)`` cuts a result into per-graph
+    views.
     """
 
     def __init__(self, graphs, workers=0, stream=None, torch_allocator=True):
@@ -550,32 +551,31 @@ class GraphSet:
     def split(self, t):
         return [t[self.offsets[i]:self.offsets[i + 1]] for i in range(len(self.sizes))]
 
-    def pagerank(self, damping=0.85, tol=1e-6, mode="delayed", d=64, dtype="f32", max_sweeps=10_000, eager=False,
-                 stream=None, allow_not_converged=False):
+    def pagerank(self, damping=0.85, tol=1e-6, mode="delayed", d=64, dtype="f64", max_sweeps=10_000, stream=None,
+                 allow_not_converged=False):
         """Per-graph PageRank: (float64 tensor [n], per-graph sweeps, Stats)."""
         import torch
         out = torch.empty(self.n, dtype=torch.float64, device="cuda")
         sw = np.zeros(len(self.sizes), np.uint32)
         st = dg_stats()
         s = _check(dg_set_pagerank(self._h, float(damping), float(tol), MODES[mode], int(d), DTYPES[dtype],
-                                   int(max_sweeps), DG_SET_EAGER if eager else 0, C.c_void_p(out.data_ptr()), 1,
+                                   int(max_sweeps), 0, C.c_void_p(out.data_ptr()), 1,
                                    _np_ptr(sw), C.byref(st), _stream_handle(stream)),
                    allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
         return out, sw, _stats(st, s == DG_OK)
 
-    def sssp(self, sources, mode="delayed", d=64, max_sweeps=None, eager=False, stream=None,
-             allow_not_converged=False):
+    def sssp(self, sources, mode="delayed", d=64, max_sweeps=None, stream=None, allow_not_converged=False):
         """Per-graph Bellman-Ford from sources[i] (local ids): (uint32 tensor
         [n] of distances, per-graph sweeps, Stats)."""
         import torch
         src = np.ascontiguousarray(sources, dtype=np.uint32)
         if max_sweeps is None:
-            max_sweeps = min(max(self.sizes) + 1, 1_000_000)
+            max_sweeps = min(self.n + 1, 1_000_000)
         out = torch.empty(self.n, dtype=torch.uint32, device="cuda")
         sw = np.zeros(len(self.sizes), np.uint32)
         st = dg_stats()
         s = _check(dg_set_sssp(self._h, _np_ptr(src), MODES[mode], int(d), int(max_sweeps),
-                               DG_SET_EAGER if eager else 0, C.c_void_p(out.data_ptr()), 1, _np_ptr(sw),
+                               0, C.c_void_p(out.data_ptr()), 1, _np_ptr(sw),
                                C.byref(st), _stream_handle(stream)),
                    allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
         return out, sw, _stats(st, s == DG_OK)

@@ -1,0 +1,122 @@
+"""GPU parity of graph sets stored as one union graph (many uneven graphs
+swept together, one launch per sweep).
+
+* dg_set_sssp: each graph's distances bit-exact against the oracle's
+  Bellman-Ford from that graph's source, in every mode.
+* dg_set_pagerank: each graph's scores (renormalised on its own) within L1
+  1e-6 of the oracle's fixed point for that graph alone, float64 storage,
+  every mode; the union's stopping rule bounds each graph's own change by
+  tol.  Float32 is refused when the union tolerance falls under its floor.
+* 64 uneven graphs (R-MAT and G(n, m)) in one set.
+"""
+import numpy as np
+import pytest
+
+import graphgen as gg
+from oracle import pagerank as opr
+from oracle import sssp as osp
+from tests import graphs as tg
+from tests.test_gpu_set import uneven_graphs
+
+pytestmark = pytest.mark.gpu
+
+MODES = [("sync", 1), ("async", 1), ("delayed", 1), ("delayed", 64), ("delayed", 1024), ("delayed", 0xFFFFFFFF)]
+
+
+@pytest.fixture(scope="module")
+def dg():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2110_01409_amd import dg as _dg
+    return _dg
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    return uneven_graphs()
+
+
+@pytest.fixture(scope="module")
+def uset(dg, graphs):
+    S = dg.GraphSet(graphs)
+    yield S
+    S.close()
+
+
+def test_union_sssp_all_modes(dg, uset, graphs):
+    rng = np.random.default_rng(11)
+    sources = np.array([int(rng.integers(0, g.n)) for g in graphs], np.uint32)
+    refs = [osp.bellman_ford_sync(g, int(s))[0] for g, s in zip(graphs, sources)]
+    for mode, d in MODES:
+        out, sw, st = uset.sssp(sources, mode=mode, d=d)
+        parts = uset.split(out.cpu().numpy())
+        for g, part, ref in zip(graphs, parts, refs):
+            np.testing.assert_array_equal(part, ref, err_msg=f"{g.name} {mode} d={d}")
+        assert st.converged and (sw == st.sweeps).all()
+        print(f"union sssp {mode} d={d}: sweeps {st.sweeps} t={st.seconds * 1e3:.2f} ms", flush=True)
+
+
+def test_union_pagerank_all_modes_f64(dg, uset, graphs):
+    refs = [opr.pagerank_fixed_point(g) for g in graphs]
+    for mode, d in MODES:
+        out, sw, st = uset.pagerank(tol=1e-8, mode=mode, d=d, dtype="f64", max_sweeps=20_000)
+        parts = uset.split(out.cpu().numpy())
+        errs = [float(np.abs(p - r).sum()) for p, r in zip(parts, refs)]
+        worst = int(np.argmax(errs))
+        print(f"union pagerank f64 {mode} d={d}: sweeps {st.sweeps} max L1 err {errs[worst]:.2e} "
+              f"({graphs[worst].name})", flush=True)
+        assert errs[worst] <= 1e-6, (mode, d, graphs[worst].name, errs[worst])
+        for p in parts:
+            assert abs(p.sum() - 1.0) < 1e-12
+        assert st.converged
+
+
+def test_union_pagerank_f32(dg, graphs):
+    # 1 vertex next to 20000: the union tolerance is far below the float32 floor
+    S = dg.GraphSet(graphs)
+    with pytest.raises(dg.DGError) as e:
+        S.pagerank(tol=1e-6, dtype="f32")
+    assert e.value.status == dg.DG_ERR_UNSUPPORTED
+    S.close()
+    # two graphs of equal size: tol 4e-6 gives a union tolerance of 3e-7
+    pair = [gg.rmat(12, seed=31), gg.rmat(12, seed=32)]
+    S = dg.GraphSet(pair)
+    out, sw, st = S.pagerank(tol=4e-6, mode="delayed", d=64, dtype="f32")
+    for p, g in zip(S.split(out.cpu().numpy()), pair):
+        err = float(np.abs(p - opr.pagerank_fixed_point(g)).sum())
+        assert err <= 1.1 * 0.85 / 0.15 * 4e-6, (g.name, err)
+    S.close()
+
+
+def test_union_64_uneven_graphs(dg):
+    """64 graphs: R-MAT scales 8-13 mixed with G(n, m) of average degree
+    8-32, one launch per sweep for all of them."""
+    rng = np.random.default_rng(64)
+    graphs = []
+    for i in range(64):
+        if i % 2 == 0:
+            graphs.append(gg.rmat(int(rng.integers(8, 14)), seed=200 + i))
+        else:
+            graphs.append(gg.erdos_renyi(int(rng.integers(500, 5000)), float(rng.integers(8, 33)), seed=200 + i))
+    S = dg.GraphSet(graphs)
+    assert S.info().graphs == 64
+    sources = np.array([int(rng.integers(0, g.n)) for g in graphs], np.uint32)
+    out, sw, st = S.sssp(sources, mode="async")
+    print(f"64-graph union sssp async: sweeps {st.sweeps} t={st.seconds * 1e3:.2f} ms", flush=True)
+    for part, g, s in zip(S.split(out.cpu().numpy()), graphs, sources.tolist()):
+        np.testing.assert_array_equal(part, osp.bellman_ford_sync(g, s)[0], err_msg=g.name)
+    out, sw, st = S.pagerank(tol=1e-8, mode="delayed", d=64, dtype="f64")
+    print(f"64-graph union pagerank f64 delayed: sweeps {st.sweeps} t={st.seconds * 1e3:.2f} ms", flush=True)
+    for part, g in zip(S.split(out.cpu().numpy()), graphs):
+        assert float(np.abs(part - opr.pagerank_fixed_point(g)).sum()) <= 1e-6, g.name
+    S.close()
+
+
+def test_union_validation(dg, graphs):
+    S = dg.GraphSet(graphs[:3])
+    with pytest.raises(dg.DGError):
+        S.sssp(np.array([0, 0, graphs[2].n], np.uint32))  # source outside its graph
+    with pytest.raises(dg.DGError):
+        S.pagerank(damping=1.0)
+    S.close()
