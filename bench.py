@@ -92,6 +92,45 @@ def cpu_baseline(g, budget_s=15.0):
     }
 
 
+def set_bench(dg, gg):
+    """64 graphs of uneven size (R-MAT scales 12-18 mixed with G(n, m) of
+    average degree 8-32) as one set: SSSP (async, random source per graph)
+    and PageRank (float64, tol 1e-6 per graph) in one launch per sweep,
+    against each graph run on its own through the single-graph calls."""
+    rng = np.random.default_rng(3)
+    graphs = []
+    for i in range(64):
+        if i % 2 == 0:
+            graphs.append(gg.rmat(int(rng.integers(12, 19)), seed=300 + i))
+        else:
+            graphs.append(gg.erdos_renyi(int(rng.integers(4096, 262145)), float(rng.integers(8, 33)), seed=300 + i))
+    sources = np.array([int(rng.integers(0, x.n)) for x in graphs], np.uint32)
+    S = dg.GraphSet(graphs)
+    S.sssp(sources, mode="async")
+    t_sssp = min(S.sssp(sources, mode="async")[2].seconds for _ in range(3))
+    _, _, sp = S.pagerank(tol=1e-6, mode="delayed", d=64, dtype="f64")
+    t_pr = min(S.pagerank(tol=1e-6, mode="delayed", d=64, dtype="f64")[2].seconds for _ in range(3))
+    info = S.info()
+    S.close()
+    alone_sssp, alone_pr = 0.0, 0.0
+    for x, src in zip(graphs, sources.tolist()):
+        G1 = dg.Graph.from_csr(x)
+        G1.sssp(src, mode="async")
+        alone_sssp += min(G1.sssp(src, mode="async")[1].seconds for _ in range(2))
+        alone_pr += min(G1.pagerank(tol=1e-6, mode="delayed", d=64, dtype="f64")[1].seconds for _ in range(2))
+        G1.close()
+    res = {"graphs": 64, "n": int(info.n), "m": int(info.m),
+           "mix": "32 R-MAT (scales 12-18) + 32 G(n, m) (n 4096-262144, avg degree 8-32)",
+           "sssp_async": {"set_ms": round(t_sssp * 1e3, 3), "one_graph_at_a_time_ms": round(alone_sssp * 1e3, 3),
+                          "speedup": round(alone_sssp / t_sssp, 2)},
+           "pagerank_f64_delayed_d64_tol1e-6": {"set_ms": round(t_pr * 1e3, 3), "set_sweeps": sp.sweeps,
+                                               "one_graph_at_a_time_ms": round(alone_pr * 1e3, 3),
+                                               "speedup": round(alone_pr / t_pr, 2)}}
+    log(f"graph set (64 graphs, n={info.n}, m={info.m}): SSSP {t_sssp * 1e3:.2f} ms vs {alone_sssp * 1e3:.2f} ms "
+        f"one at a time; PageRank f64 {t_pr * 1e3:.2f} ms ({sp.sweeps} sweeps) vs {alone_pr * 1e3:.2f} ms")
+    return res
+
+
 def serve_bench(dg, gg, G22, g22, args):
     """Serving loop under load: 8 resident R-MAT graphs (scales 16-21 plus the
     workload graph), requests half SSSP from a random source and half PPR
@@ -190,6 +229,7 @@ def main():
     ap.add_argument("--no-topology", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-set", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2048)
     ap.add_argument("--serve-budget-gib", type=int, default=12, help="batch-state budget of the serving leg")
     ap.add_argument("--batch-queries", type=int, default=256)
@@ -416,6 +456,10 @@ def main():
                 f"(model {t['predicted_seconds'] * 1e3:.3f} ms; default {dflt * 1e3:.3f} ms; "
                 f"{t['candidates']} candidates in {t['tuning_wall_s']} s)")
 
+    graph_set = {}
+    if not args.no_set:
+        graph_set = set_bench(dg, gg)
+
     serving = {}
     if not args.no_serve:
         serving = serve_bench(dg, gg, G, g, args)
@@ -449,6 +493,7 @@ def main():
         "batched": batched,
         "topology": topology,
         "tuning": tuning,
+        "graph_set": graph_set,
         "serving": serving,
     }
     G.close()
