@@ -411,6 +411,19 @@ def main():
             out["delay_gain_sssp"] = round(out["async"]["sssp_ms"] / best_bf, 3)
             return out
 
+        def local_reads(GG, srcs):
+            # ablation: delayed commits of the whole block with and without
+            # reads of the worker's own staged values
+            out = {}
+            for mode in ("delayed", "delayed_local"):
+                runs = [GG.pagerank(tol=1e-6, mode=mode, d=dg.DG_D_WHOLE, dtype="f32")[1] for _ in range(3)]
+                best = min(runs, key=lambda r: r.seconds)
+                bf = [GG.sssp(int(x), mode=mode, d=dg.DG_D_WHOLE)[1] for x in srcs]
+                out[mode] = {"pagerank_f32_ms": round(best.seconds * 1e3, 3), "pagerank_sweeps": best.sweeps,
+                             "sssp_ms": round(sum(r.seconds for r in bf) * 1e3, 3),
+                             "sssp_sweeps": [r.sweeps for r in bf]}
+            return out
+
         def access(GG):
             res = {}
             for groups in (8, 32):
@@ -421,17 +434,20 @@ def main():
             res["self_share"] = round(st.self_share, 4)
             return res
 
-        topology[f"rmat{args.scale}"] = {"access": access(G), "modes": mode_times(G, sources[:4])}
+        topology[f"rmat{args.scale}"] = {"access": access(G), "modes": mode_times(G, sources[:4]),
+                                          "local_reads_d_whole": local_reads(G, sources[:4])}
         gb = gg.banded(n, 16, 4096, 0.01, seed=args.scale)
         GB = dg.Graph.from_csr(gb)
         topology[gb.name] = {"n": gb.n, "m": gb.m, "access": access(GB),
-                             "modes": mode_times(GB, gg.pick_sources(gb, 4, seed=1).tolist())}
+                             "modes": mode_times(GB, gg.pick_sources(gb, 4, seed=1).tolist()),
+                             "local_reads_d_whole": local_reads(GB, gg.pick_sources(gb, 4, seed=1).tolist())}
         GB.close()
         del gb
         for k, v in topology.items():
             log(f"topology {k}: diagonal share (32 groups) {v['access']['groups32']['diagonal_share']} "
                 f"(lift {v['access']['groups32']['lift']}), self share {v['access']['self_share']}; "
-                f"delay gain PR {v['modes']['delay_gain_pagerank']}x, SSSP {v['modes']['delay_gain_sssp']}x")
+                f"delay gain PR {v['modes']['delay_gain_pagerank']}x, SSSP {v['modes']['delay_gain_sssp']}x; "
+                f"local reads (d whole): {v['local_reads_d_whole']}")
 
     tuning = {}
     if not args.no_tune:

@@ -20,9 +20,17 @@
  *               copied to the global array every d vertices of the worker's
  *               block and when the block is done (the paper's hybrid, delta=d).
  *
- * Reads always come from the global array (the global-read variant of
- * section III-C).  Work is split into contiguous vertex blocks, one per
- * persistent workgroup ("worker"), balanced by in-edges (section III-A).
+ *   DG_DELAYED_LOCAL  DG_DELAYED, and a worker reads the values of its own
+ *               vertices from its staging buffer (newest, maybe not yet
+ *               committed) instead of the global array: the local-read
+ *               variant of section III-C, here as an ablation.  Staging is
+ *               the per-vertex shadow array; sources in the compact region
+ *               of high-out-degree vertices are read from the global array.
+ *               dg_pagerank and dg_sssp only.
+ *
+ * Other reads come from the global array (the global-read variant of section
+ * III-C).  Work is split into contiguous vertex blocks, one per persistent
+ * workgroup ("worker"), balanced by in-edges (section III-A).
  *
  * Conventions for every function:
  *   - every function returns a dg_status; nothing throws or aborts across the
@@ -56,7 +64,7 @@ typedef enum {
 } dg_status;
 
 /* Commit mode of a sweep (section III). */
-typedef enum { DG_SYNC = 0, DG_ASYNC = 1, DG_DELAYED = 2 } dg_mode;
+typedef enum { DG_SYNC = 0, DG_ASYNC = 1, DG_DELAYED = 2, DG_DELAYED_LOCAL = 3 } dg_mode;
 
 /* Layout of the adjacency handed to dg_graph_create.
  * DG_CSR: ptr is indexed by source vertex, idx holds destinations (out-edges).

@@ -234,10 +234,14 @@ SweepState state(const dg_graph* g) {
   return st;
 }
 
-dg_status check_mode(dg_mode mode, uint32_t d) {
-  if (mode != DG_SYNC && mode != DG_ASYNC && mode != DG_DELAYED)
-    return fail(DG_ERR_INVALID_ARGUMENT, "mode %d is not DG_SYNC, DG_ASYNC or DG_DELAYED", (int)mode);
-  if (mode == DG_DELAYED && d == 0)
+// local: whether the caller supports DG_DELAYED_LOCAL (single-query sweeps).
+dg_status check_mode(dg_mode mode, uint32_t d, bool local = false) {
+  if (mode == DG_DELAYED_LOCAL && !local)
+    return fail(DG_ERR_INVALID_ARGUMENT, "DG_DELAYED_LOCAL is supported by dg_pagerank and dg_sssp only");
+  if (mode != DG_SYNC && mode != DG_ASYNC && mode != DG_DELAYED && mode != DG_DELAYED_LOCAL)
+    return fail(DG_ERR_INVALID_ARGUMENT, "mode %d is not DG_SYNC, DG_ASYNC, DG_DELAYED or DG_DELAYED_LOCAL",
+                (int)mode);
+  if ((mode == DG_DELAYED || mode == DG_DELAYED_LOCAL) && d == 0)
     return fail(DG_ERR_INVALID_ARGUMENT, "delayed mode needs a commit interval d >= 1");
   return DG_OK;
 }
@@ -662,7 +666,7 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
   if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
   if (!(damping >= 0.0 && damping < 1.0)) return fail(DG_ERR_INVALID_ARGUMENT, "damping must be in [0, 1)");
   if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(DG_ERR_INVALID_ARGUMENT, "tol must be finite and >= 0");
-  dg_status st = check_mode(mode, d);
+  dg_status st = check_mode(mode, d, true);
   if (st != DG_OK) return st;
   if (dtype != DG_F32 && dtype != DG_F64) return fail(DG_ERR_INVALID_ARGUMENT, "unknown dtype %d", (int)dtype);
   if (max_sweeps == 0 || max_sweeps > kMaxSweeps)
@@ -675,13 +679,19 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
   const size_t elem = f64 ? 8 : 4;
   uint32_t cap = 0, d_eff = 0;
   bool use_shadow = false;
-  if (mode == DG_DELAYED) staging(g, d, elem, cap, d_eff, use_shadow);
+  const bool delayed = mode == DG_DELAYED || mode == DG_DELAYED_LOCAL;
+  if (delayed) staging(g, d, elem, cap, d_eff, use_shadow);
+  if (mode == DG_DELAYED_LOCAL) {
+    use_shadow = true;  // local reads look the worker's staged values up by vertex
+    cap = 0;
+  }
   void* x = g->vals[0];
   void* c0 = g->vals[1];
   void* c1 = mode == DG_SYNC ? g->vals[2] : nullptr;
   const double d0 = (double)g->n_dangling / (double)g->n;
   SweepState sst = state(g);
   DG_HIP(launch_pr_init(f64, x, c0, c1, g->out_deg, g->cpos, g->n, sst, max_sweeps, d0, s));
+  if (mode == DG_DELAYED_LOCAL) DG_HIP(launch_by_vertex(f64, c0, g->cpos, g->n, g->vals[2], s));
 
   PrArgs a;
   a.g = topo(g);
@@ -725,7 +735,7 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
     stats->sweeps = sweeps;
     stats->workers = g->P;
     stats->tile_vertices = kTileV;
-    stats->commit_interval = mode == DG_DELAYED ? d_eff : 0;
+    stats->commit_interval = delayed ? d_eff : 0;
     stats->residual = resid;
     stats->seconds = secs;
     stats->edges_traversed = g->m * (uint64_t)sweeps;
@@ -750,7 +760,7 @@ dg_status sssp_run(dg_graph* g, uint32_t src, const uint32_t* more_src, uint32_t
   if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
   if (!g->has_w) return fail(DG_ERR_INVALID_ARGUMENT, "graph was created without weights");
   if (src >= g->n) return fail(DG_ERR_INVALID_ARGUMENT, "source %u >= n = %u", src, g->n);
-  dg_status st = check_mode(mode, d);
+  dg_status st = check_mode(mode, d, true);
   if (st != DG_OK) return st;
   if (max_sweeps == 0 || max_sweeps > kMaxSweeps)
     return fail(DG_ERR_INVALID_ARGUMENT, "max_sweeps must be in [1, %u]", kMaxSweeps);
@@ -760,12 +770,19 @@ dg_status sssp_run(dg_graph* g, uint32_t src, const uint32_t* more_src, uint32_t
   if ((st = ensure_workspace(g, max_sweeps, s)) != DG_OK) return st;
   uint32_t cap = 0, d_eff = 0;
   bool use_shadow = false;
-  if (mode == DG_DELAYED) staging(g, d, sizeof(uint32_t), cap, d_eff, use_shadow);
+  const bool delayed = mode == DG_DELAYED || mode == DG_DELAYED_LOCAL;
+  if (delayed) staging(g, d, sizeof(uint32_t), cap, d_eff, use_shadow);
+  if (mode == DG_DELAYED_LOCAL) {
+    use_shadow = true;  // local reads look the worker's staged values up by vertex
+    cap = 0;
+  }
   uint32_t* b0 = static_cast<uint32_t*>(g->vals[0]);
   uint32_t* b1 = mode == DG_SYNC ? static_cast<uint32_t*>(g->vals[1]) : nullptr;
   SweepState sst = state(g);
   DG_HIP(launch_bf_init(b0, b1, g->cpos, g->n, src, sst, max_sweeps, s));
   if (n_more) DG_HIP(launch_bf_more_sources(b0, b1, g->cpos, more_src, n_more, s));
+  if (mode == DG_DELAYED_LOCAL)
+    DG_HIP(launch_bf_gather(b0, g->cpos, g->n, static_cast<uint32_t*>(g->vals[2]), s));
 
   BfArgs a;
   a.g = topo(g);
@@ -806,7 +823,7 @@ dg_status sssp_run(dg_graph* g, uint32_t src, const uint32_t* more_src, uint32_t
     stats->sweeps = sweeps;
     stats->workers = g->P;
     stats->tile_vertices = kTileV;
-    stats->commit_interval = mode == DG_DELAYED ? d_eff : 0;
+    stats->commit_interval = delayed ? d_eff : 0;
     stats->residual = 0.0;
     stats->seconds = secs;
     stats->edges_traversed = g->m * (uint64_t)sweeps;

@@ -27,7 +27,9 @@ constexpr uint32_t kEdgePad = kChunk + 16;
 
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 
-enum Mode : int { kSync = 0, kAsync = 1, kDelayed = 2 };
+// Commit modes; kDelayedLocal is delayed commits with local reads of a
+// worker's own staged values (single-query sweeps only).
+enum Mode : int { kSync = 0, kAsync = 1, kDelayed = 2, kDelayedLocal = 3 };
 
 // Graph arrays resident in HBM (all device pointers).
 struct Topology {
@@ -135,6 +137,8 @@ hipError_t launch_bf_init(uint32_t* d0, uint32_t* d1, const uint32_t* cpos, uint
 // out[v] = d[cpos[v]]: distances back in vertex order.
 hipError_t launch_bf_gather(const uint32_t* d, const uint32_t* cpos, uint32_t n, uint32_t* out, hipStream_t s);
 hipError_t launch_bf_sweep(int mode, const BfArgs& a, hipStream_t s);
+// out[v] = c[cpos[v]] for v < n (float or double): values in vertex order.
+hipError_t launch_by_vertex(bool f64, const void* c, const uint32_t* cpos, uint32_t n, void* out, hipStream_t s);
 // out[v] = x[v] / sum(x), sum in float64 with a fixed reduction order.
 hipError_t launch_normalize(bool f64, const void* x, uint32_t n, double* out, double* scratch, hipStream_t s);
 constexpr uint32_t kNormBlocks = 512;  // scratch needs kNormBlocks + 1 doubles

@@ -151,7 +151,14 @@ __device__ __forceinline__ T gather(rsrc_t r, uint32_t off) {
 
 // ---------------------------------------------------------------- PageRank --
 
-template <int M, typename T>
+// LOCAL (delayed mode with the per-vertex shadow only): a gather whose source
+// is one of this worker's own vertices reads the worker's staged value from
+// the shadow instead of the committed array (the local-read variant of
+// section III-C).  The shadow holds the newest value of every vertex of the
+// block: this sweep's for vertices already updated, else the one committed at
+// the end of the previous sweep.  Sources in the compact region are read from
+// the committed array.
+template <int M, typename T, bool LOCAL = false>
 __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
   __shared__ uint32_t s_ptr[kTileV + 1];
   __shared__ double s_acc[kTileV];
@@ -187,6 +194,7 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
   const uint32_t t0 = as_const(a.g.work_t)[w], t1 = as_const(a.g.work_t)[w + 1];
   const uint32_t n = a.g.n;
   uint32_t staged = 0;
+  const uint32_t bv0 = tile_v[t0], bv1 = tile_v[t1];  // this worker's vertex block
 
   // Offsets of the first tile; later tiles' offsets are prefetched into
   // registers while the previous tile's gathers are in flight.
@@ -241,7 +249,13 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
 #pragma unroll
       for (int j = 0; j < kEPT; ++j) {
         const bool ok = (e0 + j >= eb) & (e0 + j < ee);
-        raw[j] = gather<M, T>(rc, ok ? u[j] * (uint32_t)sizeof(T) : kOut);
+        if constexpr (LOCAL) {
+          const bool loc = ok & (u[j] >= bv0) & (u[j] < bv1);
+          raw[j] = gather<M, T>(rc, (ok & !loc) ? u[j] * (uint32_t)sizeof(T) : kOut);
+          if (loc) raw[j] = shadow[u[j]];
+        } else {
+          raw[j] = gather<M, T>(rc, ok ? u[j] * (uint32_t)sizeof(T) : kOut);
+        }
       }
       // Prefetch the next chunk's indices: the next chunk of this tile, else
       // the first chunk of the next tile (its window starts at this tile's
@@ -320,7 +334,9 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
         staged = 0;
       }
     }
-    lds_barrier();
+    // Local reads of the next tile must see this tile's shadow stores, which
+    // needs the full barrier (it waits for outstanding global stores).
+    if constexpr (LOCAL) __syncthreads(); else lds_barrier();
     if (more) {
       if (tid < nvn) s_ptr[tid] = nxt;
       if (tid == 0) s_ptr[nvn] = nxt_end;
@@ -389,7 +405,9 @@ __global__ __launch_bounds__(kWG) void pr_init_kernel(T* x, T* c0, T* c1, const 
 
 // ------------------------------------------------------------ Bellman-Ford --
 
-template <int M>
+// LOCAL: as for pr_sweep_kernel, reads of this worker's own vertices come
+// from its shadow (delayed mode with the per-vertex shadow only).
+template <int M, bool LOCAL = false>
 __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
   __shared__ uint32_t s_ptr[kTileV + 1];
   __shared__ uint32_t s_acc[kTileV];
@@ -411,6 +429,7 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
   const uint32_t n = a.g.n;
   uint32_t staged = 0;
   int any = 0;
+  const uint32_t bv0 = tile_v[t0], bv1 = tile_v[t1];  // this worker's vertex block
 
   uint32_t v0 = tile_v[t0];
   uint32_t u[kEPT], wt[kEPT];  // next chunk's indices and weights, loaded one chunk ahead
@@ -447,7 +466,13 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
 #pragma unroll
       for (int j = 0; j < kEPT; ++j) {
         ok[j] = (e0 + j >= eb) & (e0 + j < ee);
-        du[j] = gather<M, uint32_t>(rd, ok[j] ? u[j] * 4u : kOut);
+        if constexpr (LOCAL) {
+          const bool loc = ok[j] & (u[j] >= bv0) & (u[j] < bv1);
+          du[j] = gather<M, uint32_t>(rd, (ok[j] & !loc) ? u[j] * 4u : kOut);
+          if (loc) du[j] = a.shadow[u[j]];
+        } else {
+          du[j] = gather<M, uint32_t>(rd, ok[j] ? u[j] * 4u : kOut);
+        }
         wc[j] = wt[j];
       }
       const bool last = cb + kChunk >= ee;
@@ -523,7 +548,7 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
         staged = 0;
       }
     }
-    lds_barrier();
+    if constexpr (LOCAL) __syncthreads(); else lds_barrier();
     if (more) {
       if (tid < nvn) s_ptr[tid] = nxt;
       if (tid == 0) s_ptr[nvn] = nxt_end;
@@ -585,6 +610,14 @@ __global__ __launch_bounds__(kWG) void scale_kernel(const T* x, uint32_t n, cons
   if (i < n) out[i] = (double)x[i] / *total;
 }
 
+// out[v] = c[cpos[v]]: committed values in vertex order (the local-read
+// variant starts its shadow from them).
+template <typename T>
+__global__ __launch_bounds__(kWG) void by_vertex_kernel(const T* c, const uint32_t* cpos, uint32_t n, T* out) {
+  const uint32_t v = blockIdx.x * kWG + threadIdx.x;
+  if (v < n) out[v] = c[cpos[v]];
+}
+
 inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kWG - 1) / kWG); }
 
 template <int M, typename T>
@@ -607,21 +640,33 @@ hipError_t launch_pr_init(bool f64, void* x, void* c0, void* c1, const uint32_t*
   return hipGetLastError();
 }
 
-template <int M, typename T>
+template <int M, typename T, bool LOCAL = false>
 static void pr_sweep_go(const PrArgs& a, hipStream_t s) {
-  pr_sweep_kernel<M, T><<<a.g.P, kWG, pr_dyn_lds<M, T>(a), s>>>(a);
+  pr_sweep_kernel<M, T, LOCAL><<<a.g.P, kWG, pr_dyn_lds<M, T>(a), s>>>(a);
 }
 
 hipError_t launch_pr_sweep(int mode, bool f64, const PrArgs& a, hipStream_t s) {
   if (f64) {
     if (mode == kSync) pr_sweep_go<kSync, double>(a, s);
     else if (mode == kAsync) pr_sweep_go<kAsync, double>(a, s);
+    else if (mode == kDelayedLocal) pr_sweep_go<kDelayed, double, true>(a, s);
     else pr_sweep_go<kDelayed, double>(a, s);
   } else {
     if (mode == kSync) pr_sweep_go<kSync, float>(a, s);
     else if (mode == kAsync) pr_sweep_go<kAsync, float>(a, s);
+    else if (mode == kDelayedLocal) pr_sweep_go<kDelayed, float, true>(a, s);
     else pr_sweep_go<kDelayed, float>(a, s);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_by_vertex(bool f64, const void* c, const uint32_t* cpos, uint32_t n, void* out, hipStream_t s) {
+  if (f64)
+    by_vertex_kernel<double><<<blocks_for(n), kWG, 0, s>>>(static_cast<const double*>(c), cpos, n,
+                                                          static_cast<double*>(out));
+  else
+    by_vertex_kernel<float><<<blocks_for(n), kWG, 0, s>>>(static_cast<const float*>(c), cpos, n,
+                                                         static_cast<float*>(out));
   return hipGetLastError();
 }
 
@@ -638,9 +683,10 @@ hipError_t launch_bf_gather(const uint32_t* d, const uint32_t* cpos, uint32_t n,
 }
 
 hipError_t launch_bf_sweep(int mode, const BfArgs& a, hipStream_t s) {
-  const size_t lds = mode == kDelayed ? (size_t)a.cap * 2 * sizeof(uint32_t) : 0;
+  const size_t lds = (mode == kDelayed || mode == kDelayedLocal) ? (size_t)a.cap * 2 * sizeof(uint32_t) : 0;
   if (mode == kSync) bf_sweep_kernel<kSync><<<a.g.P, kWG, 0, s>>>(a);
   else if (mode == kAsync) bf_sweep_kernel<kAsync><<<a.g.P, kWG, 0, s>>>(a);
+  else if (mode == kDelayedLocal) bf_sweep_kernel<kDelayed, true><<<a.g.P, kWG, lds, s>>>(a);
   else bf_sweep_kernel<kDelayed><<<a.g.P, kWG, lds, s>>>(a);
   return hipGetLastError();
 }

@@ -21,13 +21,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdg.so")
 
 DG_OK, DG_ERR_INVALID_ARGUMENT, DG_ERR_OUT_OF_MEMORY, DG_ERR_DEVICE, DG_ERR_NOT_CONVERGED, DG_ERR_UNSUPPORTED = range(6)
-DG_SYNC, DG_ASYNC, DG_DELAYED = 0, 1, 2
+DG_SYNC, DG_ASYNC, DG_DELAYED, DG_DELAYED_LOCAL = 0, 1, 2, 3
 DG_CSR, DG_CSC = 0, 1
 DG_F32, DG_F64 = 0, 1
 DG_D_WHOLE = 0xFFFFFFFF
 DG_INF_DIST = 0xFFFFFFFF
 
-MODES = {"sync": DG_SYNC, "async": DG_ASYNC, "delayed": DG_DELAYED}
+MODES = {"sync": DG_SYNC, "async": DG_ASYNC, "delayed": DG_DELAYED, "delayed_local": DG_DELAYED_LOCAL}
 DTYPES = {"f32": DG_F32, "f64": DG_F64}
 
 # Every symbol declared in include/dg.h.

@@ -24,7 +24,8 @@ from tests import graphs as tg
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-MODES = [("sync", 0), ("async", 0), ("delayed", 1), ("delayed", 64), ("delayed", 1024), ("delayed", 0xFFFFFFFF)]
+MODES = [("sync", 0), ("async", 0), ("delayed", 1), ("delayed", 64), ("delayed", 1024), ("delayed", 0xFFFFFFFF),
+         ("delayed_local", 64), ("delayed_local", 0xFFFFFFFF)]
 PR_TOL = {"f64": 1e-8, "f32": 1e-7}
 
 
