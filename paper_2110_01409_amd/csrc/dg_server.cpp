@@ -228,9 +228,11 @@ dg_status pool_sweep(dg_server* s, Pool& p, bool& ran) {
   std::vector<uint32_t> lane_src;
   std::vector<uint32_t> blist;
   size_t cursor = 0;
-  // while another pool starves, a pool of several batches keeps its last
-  // batch free of new queries so that it can be released
-  const bool donor = s->starved >= 0 && &s->pools[(size_t)s->starved] != &p && p.NB >= 2;
+  // while another pool starves, every other pool keeps its last batch free
+  // of new queries so that it can be released (a pool of one batch then
+  // drains and, if requests still wait, starves in turn: the pool of the
+  // oldest waiting request is served first)
+  const bool donor = s->starved >= 0 && &s->pools[(size_t)s->starved] != &p && p.NB >= 1;
   while (!p.queue.empty()) {
     const size_t limit = donor ? (size_t)(p.NB - 1) * kLanes : p.lane_req.size();
     while (cursor < limit && p.lane_req[cursor] >= 0) ++cursor;
@@ -438,7 +440,7 @@ dg_status dg_server_step(dg_server* s, uint64_t* out_finished, uint32_t cap, uin
   // Budget: a pool with nothing running and nothing queued releases its
   // state; a pool that has queued requests but no batch and no budget starves,
   // and then other pools do not grow and give up trailing batches that
-  // emptied, until it fits.
+  // emptied (their last one included), until it fits.
   for (auto& p : s->pools) {
     if (p.inflight || p.NB == 0 || !p.queue.empty()) continue;
     bool idle = true;
@@ -462,7 +464,7 @@ dg_status dg_server_step(dg_server* s, uint64_t* out_finished, uint32_t cap, uin
     for (auto& p : s->pools) {
       if (budget_allows(s, hungry)) break;
       if (&p == &hungry) continue;
-      while (!p.inflight && p.NB >= 2 && lanes_free(p, p.NB - 1) && !budget_allows(s, hungry)) {
+      while (!p.inflight && p.NB >= 1 && lanes_free(p, p.NB - 1) && !budget_allows(s, hungry)) {
         dg_status st = resize(s, p, p.NB - 1);
         if (st != DG_OK) return st;
       }

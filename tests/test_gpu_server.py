@@ -202,6 +202,62 @@ def test_server_budget_starvation_resolved(dg, graphs):
     GB.close()
 
 
+def test_server_budget_starvation_under_steady_arrivals(dg, graphs):
+    """As above, but requests keep arriving on the first pool every step, so
+    it never drains by itself: the starved pool must still be served (the
+    first pool stops admitting into its one batch, drains and releases it),
+    and then the pools take turns until every request is done."""
+    ga, gb = graphs[0], graphs[1]
+    GA, GB = dg.Graph.from_csr(ga), dg.Graph.from_csr(gb)
+
+    def one_batch(G):
+        probe = dg.Server([G], mode="async")
+        probe.submit(0, "sssp", 0)
+        probe.step()
+        b = probe.status()["state_bytes"]
+        probe.close()
+        return b
+
+    ba, bb = one_batch(GA), one_batch(GB)
+    budget = max(ba, bb) + min(ba, bb) // 2
+    srv = dg.Server([GA, GB], mode="async", hbm_budget=budget)
+    rng = np.random.default_rng(11)
+    reqs, ids = [], []
+
+    def submit(gi):
+        src = int(rng.integers(0, graphs[gi].n))
+        reqs.append((gi, src))
+        ids.append(srv.submit(gi, "sssp", src))
+
+    for _ in range(64):
+        submit(0)
+    done = set(srv.step())  # pool A takes the budget (queries may already finish)
+    b_ids = set()
+    for _ in range(10):
+        submit(1)
+        b_ids.add(ids[-1])
+    peak, steps_to_b = 0, None
+    for step in range(20_000):
+        if step < 400:
+            submit(0)  # steady arrivals on A
+        elif len(done) == len(ids):
+            break
+        done.update(srv.step())
+        peak = max(peak, srv.status()["state_bytes"])
+        if steps_to_b is None and b_ids <= done:
+            steps_to_b = step
+    print("B served after", steps_to_b, "steps; total", len(ids), flush=True)
+    assert steps_to_b is not None and steps_to_b < 400
+    assert len(done) == len(ids) and peak <= budget
+    for rid, (gi, src) in zip(ids, reqs):
+        if rid in b_ids or rid % 37 == 0:
+            out, _ = srv.fetch(rid)
+            np.testing.assert_array_equal(out.cpu().numpy(), osp.bellman_ford_sync(graphs[gi], src)[0])
+    srv.close()
+    GA.close()
+    GB.close()
+
+
 def test_server_validation(dg, graphs):
     G = dg.Graph.from_csr(graphs[0])
     srv = dg.Server([G])
