@@ -109,6 +109,8 @@ typedef struct {
   uint32_t compute_units;
   uint32_t hot_vertices; /* sources stored in the compact region            */
   uint64_t hot_edges;    /* in-edges whose source is in the compact region  */
+  uint32_t resident_vertices; /* leading compact-region sources in the LDS table */
+  uint64_t resident_edges;    /* in-edges whose source is in the table          */
   uint64_t device_bytes; /* device memory held by the graph (not workspace) */
 } dg_graph_info;
 
@@ -129,11 +131,29 @@ dg_status dg_set_allocator(dg_alloc_fn alloc, dg_free_fn free_fn, void* ctx);
  *                 in a compact region after the n regular slots, so gathers
  *                 from them hit in L2; ownership, blocks and commit points are
  *                 unchanged, only the storage address moves.
- *                 DG_HOT_AUTO = 524288, 0 = no compact region */
+ *                 DG_HOT_AUTO = 524288, 0 = no compact region
+ *   resident_vertices
+ *                 at most this many of the compact region's sources, those
+ *                 with the largest out-degree, are also read from a copy in
+ *                 each workgroup's LDS (the resident table) instead of being
+ *                 gathered; at most 6144 (a float64 sweep uses the first
+ *                 3072).  DG_RESIDENT_AUTO = 6144 if those cover at least 1/16
+ *                 of the in-edges, else 0; 0 = no table.  A read of a
+ *                 resident source returns, in
+ *                   DG_SYNC     the value of the previous sweep, exactly as a
+ *                               gather would;
+ *                   DG_ASYNC, DG_DELAYED, DG_DELAYED_LOCAL
+ *                               a value read from the global array at most
+ *                               three tiles of the reader earlier (the table
+ *                               is refreshed a third at a time after each
+ *                               tile), instead of at the moment of the read.
+ *                 Results converge to the same fixed point / distances. */
 #define DG_HOT_AUTO 0xFFFFFFFFu
+#define DG_RESIDENT_AUTO 0xFFFFFFFFu
 typedef struct {
   uint32_t workers;
   uint32_t hot_vertices;
+  uint32_t resident_vertices;
 } dg_graph_opts;
 
 /* Upload a graph and build its in-edge form (pull sweeps need in-neighbours,

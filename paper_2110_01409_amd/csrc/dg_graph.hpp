@@ -35,6 +35,8 @@ struct dg_graph {
   std::vector<uint32_t> tile_v_h, tile_e0_h;  // host copies: first vertex / first in-edge of each tile
   uint64_t hash = 0;                         // content hash of the in-edge form (tuning cache key)
   uint64_t hot_edges = 0;  // in-edges whose source is in the compact region
+  uint32_t R = 0;          // leading compact-region slots kept in the sweeps' LDS table
+  uint64_t res_edges = 0;  // in-edges whose source is one of them
   size_t lds_per_block = 65536;
   // allocator captured at creation
   dg_alloc_fn alloc = nullptr;

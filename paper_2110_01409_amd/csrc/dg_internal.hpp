@@ -27,6 +27,14 @@ constexpr uint32_t kEdgePad = kChunk + 16;
 
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 
+// LDS of a sweep workgroup: five workgroups share a compute unit's 160 KB.
+constexpr uint32_t kLdsBudget = 32 * 1024;
+// Resident table: LDS copy of the first slots of the compact region (the
+// sources with the largest out-degree), read instead of gathering them.
+constexpr uint32_t kResBytes = 24 * 1024;
+// Bytes of the table refreshed at once (8 registers per thread).
+constexpr uint32_t kResSegBytes = kWG * 8 * 4;
+
 // Commit modes; kDelayedLocal is delayed commits with local reads of a
 // worker's own staged values (single-query sweeps only).
 enum Mode : int { kSync = 0, kAsync = 1, kDelayed = 2, kDelayedLocal = 3 };
@@ -69,6 +77,11 @@ struct PrArgs {
   uint32_t k;       // sweep index
   uint32_t d;       // commit interval in vertices (delayed mode)
   uint32_t cap;     // LDS staging capacity in vertices (delayed mode, LDS staging)
+  // Slots n .. n+res-1 are read from the workgroup's LDS table (0 = none).
+  // The table is filled at the start of the sweep; an asynchronous sweep
+  // refreshes one segment of it after every tile, a delayed sweep after
+  // every tile that ends with a commit.
+  uint32_t res;
 };
 
 struct BfArgs {
@@ -80,6 +93,7 @@ struct BfArgs {
   uint32_t k;
   uint32_t d;
   uint32_t cap;
+  uint32_t res;  // as PrArgs::res
 };
 
 // Batched queries (64 per batch, vertex-major [slot][64] values).

@@ -126,6 +126,7 @@ dg_status dg_set_create(uint32_t count, const dg_graph_desc* graphs, const dg_se
   dg_graph_opts go;
   go.workers = opts ? opts->workers : 0u;
   go.hot_vertices = DG_HOT_AUTO;
+  go.resident_vertices = DG_RESIDENT_AUTO;
   dg_status st = dg_graph_create((uint32_t)N, M, DG_CSR, ptr.data(), M ? idx.data() : nullptr,
                                  weighted == 1 ? w.data() : nullptr, &go, hip_stream, &s->g);
   if (st != DG_OK) {

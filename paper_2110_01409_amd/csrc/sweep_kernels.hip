@@ -149,6 +149,55 @@ __device__ __forceinline__ T gather(rsrc_t r, uint32_t off) {
 }
 
 
+// Resident table.  The first `res` slots of the compact region hold the
+// published values of the sources with the largest out-degree; each
+// workgroup keeps a copy of them in LDS, after its staging buffer, and reads
+// a gather of slot n+i from entry i.  Gathers cost L2 requests, which bound
+// the sweep; an LDS read costs none.  The copy is filled at the start of the
+// sweep (exact for a synchronous sweep, whose input does not change during
+// the sweep).  Asynchronous and delayed sweeps refresh one segment of
+// kResSegBytes after every tile, so no entry is older than
+// ceil(res / segment) tiles of the reader (3 at the default size): the
+// segment's loads are issued after the barrier that ends a tile's gathers
+// (the chunk registers are free then) and written to LDS after the barrier
+// that ends the tile, before the barrier that starts the next tile's gathers.
+__host__ __device__ constexpr uint32_t res_offset(uint32_t cap, uint32_t elem) {
+  return (cap * (elem + 4u) + 15u) & ~15u;
+}
+
+template <int M, typename T>
+struct ResTable {
+  static constexpr uint32_t kPer = kResSegBytes / (kWG * sizeof(T));  // values per thread per segment
+  static constexpr uint32_t kSeg = kPer * kWG;                         // values per segment
+  T* lds;
+  uint32_t res, n, next = 0;  // next: first value of the segment to refresh
+  T r[kPer];
+  __device__ __forceinline__ void issue(rsrc_t rc, uint32_t tid) {
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+      const uint32_t i = next + j * kWG + tid;
+      r[j] = gather<M, T>(rc, i < res ? (n + i) * (uint32_t)sizeof(T) : kOut);
+    }
+  }
+  __device__ __forceinline__ void commit(uint32_t tid) {
+#pragma unroll
+    for (uint32_t j = 0; j < kPer; ++j) {
+      const uint32_t i = next + j * kWG + tid;
+      if (i < res) lds[i] = r[j];
+    }
+    next += kSeg;
+    if (next >= res) next = 0;
+  }
+  // Whole table, at the start of the sweep (published by the first tile's barrier).
+  __device__ __forceinline__ void fill(rsrc_t rc, uint32_t tid) {
+    for (next = 0; next < res;) {
+      issue(rc, tid);
+      commit(tid);
+      if (next == 0) break;
+    }
+  }
+};
+
 // ---------------------------------------------------------------- PageRank --
 
 // LOCAL (delayed mode with the per-vertex shadow only): a gather whose source
@@ -188,6 +237,11 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
   T* x = static_cast<T*>(a.x);
   T* shadow = static_cast<T*>(a.shadow);
   const rsrc_t rc = make_rsrc(cin, (a.g.n + a.g.K) * (uint32_t)sizeof(T));
+  ResTable<M, T> rt;
+  rt.lds = reinterpret_cast<T*>(s_dyn + res_offset(M == kDelayed ? a.cap : 0u, sizeof(T)));
+  rt.res = a.res;
+  rt.n = a.g.n;
+  if (rt.res) rt.fill(rc, tid);
 
   double r_loc = 0.0, nd_loc = 0.0;
   const const_u32p tile_v = as_const(a.g.tile_v);
@@ -237,6 +291,10 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
       nxt = a.g.in_ptr[min(v1 + tid, n)];
       nxt_end = ee_next;
     };
+    // Delayed mode: this tile ends with a commit of the staged values.
+    const bool flush = M == kDelayed && (!more || staged + nv >= a.d || (!shadow && staged + nv + nvn > a.cap));
+    // Refresh a segment of the resident table for the next tile.
+    const bool refresh = M != kSync && rt.res && more;
     if (tid < nv) s_acc[tid] = 0.0;
     lds_barrier();
     const uint32_t eb = s_ptr[0], ee = s_ptr[nv];
@@ -249,13 +307,16 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
 #pragma unroll
       for (int j = 0; j < kEPT; ++j) {
         const bool ok = (e0 + j >= eb) & (e0 + j < ee);
+        const uint32_t ri = u[j] - n;  // resident index (wraps for regular slots)
+        const bool inres = ok & (ri < rt.res);
         if constexpr (LOCAL) {
           const bool loc = ok & (u[j] >= bv0) & (u[j] < bv1);
-          raw[j] = gather<M, T>(rc, (ok & !loc) ? u[j] * (uint32_t)sizeof(T) : kOut);
+          raw[j] = gather<M, T>(rc, (ok & !loc & !inres) ? u[j] * (uint32_t)sizeof(T) : kOut);
           if (loc) raw[j] = shadow[u[j]];
         } else {
-          raw[j] = gather<M, T>(rc, ok ? u[j] * (uint32_t)sizeof(T) : kOut);
+          raw[j] = gather<M, T>(rc, (ok & !inres) ? u[j] * (uint32_t)sizeof(T) : kOut);
         }
+        if (inres) raw[j] = rt.lds[ri];
       }
       // Prefetch the next chunk's indices: the next chunk of this tile, else
       // the first chunk of the next tile (its window starts at this tile's
@@ -301,6 +362,7 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
       prefetch_next();
     }
     lds_barrier();
+    if (refresh) rt.issue(rc, tid);
     if (tid < nv) {
       const uint32_t v = v0 + tid;
       const double xn = base + alpha * s_acc[tid];
@@ -323,7 +385,7 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
     }
     if constexpr (M == kDelayed) {
       staged += nv;
-      if (!more || staged >= a.d || (!shadow && staged + nvn > a.cap)) {
+      if (flush) {
         if (shadow) __syncthreads(); else lds_barrier();
         if (shadow) {
           const uint32_t f0 = v1 - staged;
@@ -337,6 +399,7 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
     // Local reads of the next tile must see this tile's shadow stores, which
     // needs the full barrier (it waits for outstanding global stores).
     if constexpr (LOCAL) __syncthreads(); else lds_barrier();
+    if (refresh) rt.commit(tid);  // every wave is past this tile's gathers
     if (more) {
       if (tid < nvn) s_ptr[tid] = nxt;
       if (tid == 0) s_ptr[nvn] = nxt_end;
@@ -429,6 +492,11 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
   const uint32_t n = a.g.n;
   uint32_t staged = 0;
   int any = 0;
+  ResTable<M, uint32_t> rt;
+  rt.lds = reinterpret_cast<uint32_t*>(s_dyn + res_offset(M == kDelayed ? a.cap : 0u, 4u));
+  rt.res = a.res;
+  rt.n = n;
+  if (rt.res) rt.fill(rd, tid);
   const uint32_t bv0 = tile_v[t0], bv1 = tile_v[t1];  // this worker's vertex block
 
   uint32_t v0 = tile_v[t0];
@@ -455,6 +523,8 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
       nxt = a.g.in_ptr[min(v1 + tid, n)];
       nxt_end = ee_next;
     };
+    const bool flush = M == kDelayed && (!more || staged + nv >= a.d || (!a.shadow && staged + nv + nvn > a.cap));
+    const bool refresh = M != kSync && rt.res && more;
     if (tid < nv) s_acc[tid] = kInf;
     lds_barrier();
     const uint32_t eb = s_ptr[0], ee = s_ptr[nv];
@@ -466,13 +536,16 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
 #pragma unroll
       for (int j = 0; j < kEPT; ++j) {
         ok[j] = (e0 + j >= eb) & (e0 + j < ee);
+        const uint32_t ri = u[j] - n;
+        const bool inres = ok[j] & (ri < rt.res);
         if constexpr (LOCAL) {
           const bool loc = ok[j] & (u[j] >= bv0) & (u[j] < bv1);
-          du[j] = gather<M, uint32_t>(rd, (ok[j] & !loc) ? u[j] * 4u : kOut);
+          du[j] = gather<M, uint32_t>(rd, (ok[j] & !loc & !inres) ? u[j] * 4u : kOut);
           if (loc) du[j] = a.shadow[u[j]];
         } else {
-          du[j] = gather<M, uint32_t>(rd, ok[j] ? u[j] * 4u : kOut);
+          du[j] = gather<M, uint32_t>(rd, (ok[j] & !inres) ? u[j] * 4u : kOut);
         }
+        if (inres) du[j] = rt.lds[ri];
         wc[j] = wt[j];
       }
       const bool last = cb + kChunk >= ee;
@@ -519,6 +592,7 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
       prefetch_next();
     }
     lds_barrier();
+    if (refresh) rt.issue(rd, tid);
     if (tid < nv) {
       const uint32_t old = ld_shared<M>(din + p);
       const uint32_t best = s_acc[tid];
@@ -537,7 +611,7 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
     }
     if constexpr (M == kDelayed) {
       staged += nv;
-      if (!more || staged >= a.d || (!a.shadow && staged + nvn > a.cap)) {
+      if (flush) {
         if (a.shadow) __syncthreads(); else lds_barrier();
         if (a.shadow) {
           const uint32_t f0 = v1 - staged;
@@ -549,6 +623,7 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
       }
     }
     if constexpr (LOCAL) __syncthreads(); else lds_barrier();
+    if (refresh) rt.commit(tid);
     if (more) {
       if (tid < nvn) s_ptr[tid] = nxt;
       if (tid == 0) s_ptr[nvn] = nxt_end;
@@ -622,7 +697,7 @@ inline uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + kWG - 1) / kWG);
 
 template <int M, typename T>
 size_t pr_dyn_lds(const PrArgs& a) {
-  return M == kDelayed ? (size_t)a.cap * (sizeof(T) + sizeof(uint32_t)) : 0;
+  return (size_t)res_offset(M == kDelayed ? a.cap : 0u, sizeof(T)) + (size_t)a.res * sizeof(T);
 }
 
 }  // namespace
@@ -683,9 +758,10 @@ hipError_t launch_bf_gather(const uint32_t* d, const uint32_t* cpos, uint32_t n,
 }
 
 hipError_t launch_bf_sweep(int mode, const BfArgs& a, hipStream_t s) {
-  const size_t lds = (mode == kDelayed || mode == kDelayedLocal) ? (size_t)a.cap * 2 * sizeof(uint32_t) : 0;
-  if (mode == kSync) bf_sweep_kernel<kSync><<<a.g.P, kWG, 0, s>>>(a);
-  else if (mode == kAsync) bf_sweep_kernel<kAsync><<<a.g.P, kWG, 0, s>>>(a);
+  const size_t lds = (size_t)res_offset(mode == kDelayed || mode == kDelayedLocal ? a.cap : 0u, 4u) +
+                     (size_t)a.res * sizeof(uint32_t);
+  if (mode == kSync) bf_sweep_kernel<kSync><<<a.g.P, kWG, lds, s>>>(a);
+  else if (mode == kAsync) bf_sweep_kernel<kAsync><<<a.g.P, kWG, lds, s>>>(a);
   else if (mode == kDelayedLocal) bf_sweep_kernel<kDelayed, true><<<a.g.P, kWG, lds, s>>>(a);
   else bf_sweep_kernel<kDelayed><<<a.g.P, kWG, lds, s>>>(a);
   return hipGetLastError();

@@ -54,14 +54,15 @@ class dg_graph_info(C.Structure):
     _fields_ = [("n", C.c_uint32), ("m", C.c_uint64), ("workers", C.c_uint32), ("tiles", C.c_uint32),
                 ("max_in_degree", C.c_uint32), ("dangling", C.c_uint32), ("has_weights", C.c_uint32),
                 ("compute_units", C.c_uint32), ("hot_vertices", C.c_uint32), ("hot_edges", C.c_uint64),
-                ("device_bytes", C.c_uint64)]
+                ("resident_vertices", C.c_uint32), ("resident_edges", C.c_uint64), ("device_bytes", C.c_uint64)]
 
 
 class dg_graph_opts(C.Structure):
-    _fields_ = [("workers", C.c_uint32), ("hot_vertices", C.c_uint32)]
+    _fields_ = [("workers", C.c_uint32), ("hot_vertices", C.c_uint32), ("resident_vertices", C.c_uint32)]
 
 
 DG_HOT_AUTO = 0xFFFFFFFF
+DG_RESIDENT_AUTO = 0xFFFFFFFF
 
 
 class dg_graph_desc(C.Structure):
@@ -376,7 +377,7 @@ class Graph:
     """
 
     def __init__(self, n, ptr, idx, w=None, layout="csr", stream=None, torch_allocator=True, workers=0,
-                 hot_vertices=DG_HOT_AUTO):
+                 hot_vertices=DG_HOT_AUTO, resident_vertices=DG_RESIDENT_AUTO):
         ptr = np.ascontiguousarray(ptr, dtype=np.uint64)
         idx = np.ascontiguousarray(idx, dtype=np.uint32)
         wa = None if w is None else np.ascontiguousarray(w, dtype=np.uint32)
@@ -384,7 +385,7 @@ class Graph:
             use_torch_allocator()
         h = C.c_void_p()
         lay = DG_CSR if layout == "csr" else DG_CSC
-        opts = dg_graph_opts(int(workers), int(hot_vertices))
+        opts = dg_graph_opts(int(workers), int(hot_vertices), int(resident_vertices))
         _check(dg_graph_create(int(n), int(idx.shape[0]), lay, _np_ptr(ptr), _np_ptr(idx),
                                None if wa is None else _np_ptr(wa), C.byref(opts), _stream_handle(stream),
                                C.byref(h)))

@@ -309,3 +309,75 @@ def test_options_hot_region_and_workers(dg, hot, workers):
         dist, _ = G.sssp(src, mode=mode, d=max(d, 1))
         np.testing.assert_array_equal(_np(dist), ref)
     G.close()
+
+
+def _resident_reference(g, res_opt=0xFFFFFFFF, hot_cap=524288):
+    """Compact region and resident table by their definition: candidates are
+    sources with out-degree above 1 and above the average, the region takes
+    the largest hot_cap of them, the table the largest min(res_opt, 6144) of
+    those; the automatic size (res_opt = all ones) keeps the table only if
+    its sources cover at least 1/16 of the edges."""
+    od = np.diff(g.ptr.astype(np.int64))
+    cand = np.nonzero((od > 1) & (od > g.m / g.n))[0]
+    top = cand[np.argsort(-od[cand], kind="stable")][:hot_cap]
+    r = min(top.size, res_opt, 6144)
+    cover = int(od[top[:r]].sum())
+    if res_opt == 0xFFFFFFFF and cover * 16 < g.m:
+        r, cover = 0, 0
+    return top.size, int(od[top].sum()), r, cover
+
+
+@pytest.mark.parametrize("name,res", [("rmat14", 0xFFFFFFFF), ("er", 0xFFFFFFFF), ("rmat14", 100),
+                                      ("banded", 0xFFFFFFFF)])
+def test_resident_table_sync_same_values(dg, name, res):
+    """Synchronous sweeps read the resident table where they would gather the
+    same values (the table is filled from the sweep's unchanging input).
+    SSSP is bit-identical with and without it; PageRank agrees up to the
+    order in which LDS atomics add a vertex's partial sums (which varies
+    from run to run as well)."""
+    g, xs = _graph(name)
+    A = dg.Graph.from_csr(g, resident_vertices=res)
+    B = dg.Graph.from_csr(g, resident_vertices=0)
+    ia, ib = A.info(), B.info()
+    K, hot_e, R, res_e = _resident_reference(g, res)
+    assert (ia.hot_vertices, ia.hot_edges) == (K, hot_e) == (ib.hot_vertices, ib.hot_edges)
+    assert (ia.resident_vertices, ia.resident_edges) == (R, res_e)
+    assert (ib.resident_vertices, ib.resident_edges) == (0, 0)
+    assert R > 0
+    for dtype, tol, same in (("f32", 1e-7, 1e-6), ("f64", 1e-10, 1e-12)):
+        xa, sa = A.pagerank(tol=tol, mode="sync", dtype=dtype)
+        xb, sb = B.pagerank(tol=tol, mode="sync", dtype=dtype)
+        assert abs(sa.sweeps - sb.sweeps) <= 1
+        bound = same if sa.sweeps == sb.sweeps else 10 * tol / (1 - 0.85)  # one sweep more: within the stop rule
+        assert np.abs(_np(xa) - _np(xb)).sum() <= bound, dtype
+        assert np.abs(_np(xa) - xs).sum() <= 1e-6
+    for src in _sources(g, 2):
+        da, sa = A.sssp(src, mode="sync")
+        db, sb = B.sssp(src, mode="sync")
+        assert sa.sweeps == sb.sweeps
+        np.testing.assert_array_equal(_np(da), _np(db))
+        np.testing.assert_array_equal(_np(da), osp.bellman_ford_sync(g, src)[0])
+    A.close()
+    B.close()
+
+
+@pytest.mark.parametrize("res", [1, 100, 2049, 0xFFFFFFFF])
+def test_resident_table_async_delayed_local(dg, res):
+    """Asynchronous and delayed sweeps refresh the table a segment at a time
+    after every tile: table sizes below, at and across a segment boundary,
+    every commit interval, and the local-read variant, all converge to the
+    oracle's fixed point (PageRank) and its exact distances (SSSP)."""
+    g, xs = _graph("rmat14")
+    G = dg.Graph.from_csr(g, resident_vertices=res)
+    assert G.info().resident_vertices == _resident_reference(g, res)[2] > 0
+    src = _sources(g, 1)[0]
+    ref = osp.bellman_ford_sync(g, src)[0]
+    for mode, ds in (("async", (1,)), ("delayed", (1, 64, 1024, 0xFFFFFFFF)),
+                     ("delayed_local", (64, 0xFFFFFFFF))):
+        for d in ds:
+            for dtype, tol in (("f32", 1e-7), ("f64", 1e-9)):
+                x, _ = G.pagerank(tol=tol, mode=mode, d=d, dtype=dtype)
+                assert np.abs(_np(x) - xs).sum() <= 1e-6, (mode, d, dtype)
+            dist, _ = G.sssp(src, mode=mode, d=d)
+            np.testing.assert_array_equal(_np(dist), ref, err_msg=f"{mode} d={d}")
+    G.close()
