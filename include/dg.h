@@ -111,6 +111,8 @@ typedef struct {
   uint64_t hot_edges;    /* in-edges whose source is in the compact region  */
   uint32_t resident_vertices; /* leading compact-region sources in the LDS table */
   uint64_t resident_edges;    /* in-edges whose source is in the table          */
+  uint32_t weight_bytes;      /* bytes per stored weight: 1 when every weight is
+                                 <= 255, 4 otherwise, 0 without weights        */
   uint64_t device_bytes; /* device memory held by the graph (not workspace) */
 } dg_graph_info;
 
@@ -166,7 +168,9 @@ typedef struct {
  *              ptr[n] = m
  *   idx        host array of m uint32 vertex ids, each < n
  *   w          host array of m uint32 edge weights, or NULL (PageRank only).
- *              Path lengths saturate at DG_INF_DIST.
+ *              Path lengths saturate at DG_INF_DIST.  When every weight is
+ *              <= 255 the device keeps them as bytes (dg_graph_info.
+ *              weight_bytes), which shortens the sweeps' weight stream.
  *   opts       creation options, or NULL for the defaults
  * Duplicate edges are kept (PageRank counts multiplicity, SSSP takes the
  * minimum) and self-loops count in the out-degree.  The arrays are copied:

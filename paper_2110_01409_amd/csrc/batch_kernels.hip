@@ -58,13 +58,13 @@ __device__ __forceinline__ cu32p cst(const uint32_t* p) { return (cu32p)(p); }
 // 64 edges starting at group `first`.  Lane q handles query q.
 template <int M>
 __device__ __forceinline__ uint32_t relax_edges(const uint32_t* __restrict__ in_src, const uint32_t* __restrict__ in_w,
-                                                const uint32_t* d, uint32_t e0, uint32_t e1, uint32_t first,
-                                                uint32_t step, uint32_t lane) {
+                                                const uint8_t* __restrict__ in_w8, const uint32_t* d, uint32_t e0,
+                                                uint32_t e1, uint32_t first, uint32_t step, uint32_t lane) {
   uint32_t acc = kInf;
   for (uint32_t e = e0 + first * 64u; e < e1; e += 64u * step) {
     const uint32_t cnt = min(64u, e1 - e);
     const uint32_t idx = lane < cnt ? in_src[e + lane] : 0u;
-    const uint32_t wt = lane < cnt ? in_w[e + lane] : 0u;
+    const uint32_t wt = lane < cnt ? (in_w8 ? (uint32_t)in_w8[e + lane] : in_w[e + lane]) : 0u;
     uint32_t j = 0;
     for (; j + 8 <= cnt; j += 8) {
       uint32_t val[8];
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
     if (nv == 1) {
       // Hub: the four wavefronts split its in-edges, wavefront 0 commits.
       const uint32_t e0 = in_ptr[v0], e1 = in_ptr[v1];
-      s_hub[wv][lane] = relax_edges<M>(a.g.in_src, a.g.in_w, din, e0, e1, wv, kWG / 64, lane);
+      s_hub[wv][lane] = relax_edges<M>(a.g.in_src, a.g.in_w, a.g.in_w8, din, e0, e1, wv, kWG / 64, lane);
       __syncthreads();
       if (wv == 0) {
         uint32_t acc = s_hub[0][lane];
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
       __syncthreads();
     } else {
       for (uint32_t v = v0 + wv; v < v1; v += kWG / 64) {
-        const uint32_t acc = relax_edges<M>(a.g.in_src, a.g.in_w, din, in_ptr[v], in_ptr[v + 1], 0, 1, lane);
+        const uint32_t acc = relax_edges<M>(a.g.in_src, a.g.in_w, a.g.in_w8, din, in_ptr[v], in_ptr[v + 1], 0, 1, lane);
         const uint32_t p = a.g.cpos[v];
         const uint32_t old = ld_q<M>(din + (size_t)p * kQ + lane);
         const uint32_t nw = acc < old ? acc : old;

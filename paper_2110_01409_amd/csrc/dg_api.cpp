@@ -115,6 +115,7 @@ Topology topo(const dg_graph* g) {
   t.in_ptr = g->in_ptr;
   t.in_src = g->in_src;
   t.in_w = g->in_w;
+  t.in_w8 = g->in_w8;
   t.out_deg = g->out_deg;
   t.cpos = g->cpos;
   t.tile_v = g->tile_v;
@@ -466,7 +467,7 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
 
   // In-edge form (stable counting sort: in-edges of a vertex by ascending
   // source), with each source replaced by the slot of its published value.
-  std::vector<uint32_t> in_ptr, in_src, in_w, out_deg, cpos, tile_v, work_t;
+  std::vector<uint32_t> in_ptr, in_src, in_w, w8pack, out_deg, cpos, tile_v, work_t;
   try {
     in_ptr.assign((size_t)n + 1, 0);
     in_src.assign((size_t)m + kEdgePad, 0);
@@ -546,6 +547,13 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
     h = hash_words(h, in_src.data(), (size_t)m);
     if (w) h = hash_words(h, in_w.data(), (size_t)m);
     g->hash = hash_words(h, out_deg.data(), out_deg.size());
+    // Weights that all fit a byte are stored as bytes (packed four to a
+    // word here): a quarter of the weight stream's bytes per sweep.
+    if (w && std::all_of(w, w + m, [](uint32_t x) { return x <= 255u; })) {
+      w8pack.assign(((size_t)m + kEdgePad + 16 + 3) / 4, 0u);
+      for (uint64_t e = 0; e < m; ++e) w8pack[e >> 2] |= in_w[e] << (8 * (e & 3));
+      std::vector<uint32_t>().swap(in_w);
+    }
   } catch (const std::bad_alloc&) {
     delete g;
     return fail(DG_ERR_OUT_OF_MEMORY, "host allocation failed while building the in-edge form");
@@ -580,11 +588,12 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
   for (uint32_t wk = 0; wk < P; ++wk)
     g->max_block_v = std::max(g->max_block_v, tile_v[work_t[wk + 1]] - tile_v[work_t[wk]]);
 
+  uint32_t* w8_words = nullptr;
   struct Up {
     uint32_t** dst;
     const std::vector<uint32_t>* src;
-  } ups[] = {{&g->in_ptr, &in_ptr}, {&g->in_src, &in_src}, {&g->in_w, &in_w}, {&g->out_deg, &out_deg},
-             {&g->cpos, &cpos}, {&g->tile_v, &tile_v}, {&g->work_t, &work_t}};
+  } ups[] = {{&g->in_ptr, &in_ptr}, {&g->in_src, &in_src}, {&g->in_w, &in_w}, {&w8_words, &w8pack},
+             {&g->out_deg, &out_deg}, {&g->cpos, &cpos}, {&g->tile_v, &tile_v}, {&g->work_t, &work_t}};
   for (auto& u : ups) {
     if (u.src->empty()) continue;
     const size_t bytes = u.src->size() * sizeof(uint32_t);
@@ -598,6 +607,7 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
     he = hipMemcpyAsync(*u.dst, u.src->data(), bytes, hipMemcpyHostToDevice, s);
     if (he != hipSuccess) break;
   }
+  g->in_w8 = reinterpret_cast<uint8_t*>(w8_words);
   if (he == hipSuccess) he = hipStreamSynchronize(s);
   if (he != hipSuccess) {
     (void)hipGetLastError();
@@ -631,6 +641,7 @@ dg_status dg_graph_info_get(const dg_graph* g, dg_graph_info* info) {
   info->hot_edges = g->hot_edges;
   info->resident_vertices = g->R;
   info->resident_edges = g->res_edges;
+  info->weight_bytes = g->in_w8 ? 1u : (g->in_w ? 4u : 0u);
   info->device_bytes = g->graph_bytes;
   return DG_OK;
 }

@@ -47,6 +47,7 @@ struct dg_graph {
   uint64_t graph_bytes = 0;
   // resident graph
   uint32_t *in_ptr = nullptr, *in_src = nullptr, *in_w = nullptr, *out_deg = nullptr, *cpos = nullptr;
+  uint8_t* in_w8 = nullptr;  // weights as bytes when all are <= 255 (then in_w is null)
   uint32_t *tile_v = nullptr, *work_t = nullptr;
   // workspace (grown on demand)
   void* vals[3] = {nullptr, nullptr, nullptr};  // 8(n+K) bytes each

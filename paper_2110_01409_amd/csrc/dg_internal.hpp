@@ -43,7 +43,8 @@ enum Mode : int { kSync = 0, kAsync = 1, kDelayed = 2, kDelayedLocal = 3 };
 struct Topology {
   const uint32_t* in_ptr;   // [n+1] in-edge offsets (CSC over destinations)
   const uint32_t* in_src;   // [m + kEdgePad] slot (cpos) of each in-edge's source
-  const uint32_t* in_w;     // [m + kEdgePad] weight of each in-edge (nullable)
+  const uint32_t* in_w;     // [m + kEdgePad] weight of each in-edge, when stored as uint32 (else null)
+  const uint8_t* in_w8;     // [m + kEdgePad + 16] the same as bytes, when every weight is <= 255 (else null)
   const uint32_t* out_deg;  // [n] out-degree
   const uint32_t* cpos;     // [n] slot of each vertex's published value: v, or
                             // n + rank for the K sources of the compact region

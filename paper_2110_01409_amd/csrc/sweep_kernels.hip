@@ -135,6 +135,27 @@ __device__ __forceinline__ void load_win8(const uint32_t* stream, uint32_t nb, u
   u[4] = q1.x; u[5] = q1.y; u[6] = q1.z; u[7] = q1.w;
 }
 
+// The same for a stream of one-byte weights: eight bytes per thread, one
+// 8-byte load (4-byte aligned, as buffer loads need), widened to uint32.
+__device__ __forceinline__ void load_win8_u8(const uint8_t* stream, uint32_t nb, uint32_t lim, uint32_t tid,
+                                             uint32_t (&u)[kEPT]) {
+  const uint32_t end = (lim + 7u) & ~7u;
+  const rsrc_t r = make_rsrc(stream + nb, end > nb ? end - nb : 0u);
+  const v2u q = __builtin_amdgcn_raw_buffer_load_b64(r, tid * 8u, 0, 0);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    u[j] = (q.x >> (8 * j)) & 255u;
+    u[4 + j] = (q.y >> (8 * j)) & 255u;
+  }
+}
+
+// Weights of the next chunk, from whichever stream the graph keeps.
+__device__ __forceinline__ void load_weights(const Topology& g, uint32_t nb, uint32_t lim, uint32_t tid,
+                                             uint32_t (&u)[kEPT]) {
+  if (g.in_w8) load_win8_u8(g.in_w8, nb, lim, tid, u);
+  else load_win8(g.in_w, nb, lim, tid, u);
+}
+
 // Gather of a published value; out-of-range offsets read 0.  Asynchronous
 // and delayed sweeps read with the agent-scope coherence bit (sc1), the
 // same access an agent-scope relaxed atomic load makes.
@@ -509,7 +530,7 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
     const uint32_t b0 = as_const(a.g.in_ptr)[v0] & ~3u;
     const uint32_t l0 = as_const(a.g.in_ptr)[tile_v[t0 + 1]];
     load_win8(a.g.in_src, b0, l0, tid, u);
-    load_win8(a.g.in_w, b0, l0, tid, wt);
+    load_weights(a.g, b0, l0, tid, wt);
     p_n = a.g.cpos[min(v0 + tid, n - 1)];
   }
   for (uint32_t t = t0; t < t1; ++t) {
@@ -552,7 +573,7 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
       const uint32_t nb = !last ? cb + kChunk : (more ? (ee & ~3u) : cb);
       const uint32_t lim = !last ? ee : (more ? ee_next : cb);
       load_win8(a.g.in_src, nb, lim, tid, u);
-      load_win8(a.g.in_w, nb, lim, tid, wt);
+      load_weights(a.g, nb, lim, tid, wt);
       if (last) prefetch_next();
       uint32_t cand[kEPT];
 #pragma unroll
@@ -587,7 +608,7 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
     if (eb >= ee) {
       if (more) {
         load_win8(a.g.in_src, ee & ~3u, ee_next, tid, u);
-        load_win8(a.g.in_w, ee & ~3u, ee_next, tid, wt);
+        load_weights(a.g, ee & ~3u, ee_next, tid, wt);
       }
       prefetch_next();
     }

@@ -54,7 +54,8 @@ class dg_graph_info(C.Structure):
     _fields_ = [("n", C.c_uint32), ("m", C.c_uint64), ("workers", C.c_uint32), ("tiles", C.c_uint32),
                 ("max_in_degree", C.c_uint32), ("dangling", C.c_uint32), ("has_weights", C.c_uint32),
                 ("compute_units", C.c_uint32), ("hot_vertices", C.c_uint32), ("hot_edges", C.c_uint64),
-                ("resident_vertices", C.c_uint32), ("resident_edges", C.c_uint64), ("device_bytes", C.c_uint64)]
+                ("resident_vertices", C.c_uint32), ("resident_edges", C.c_uint64), ("weight_bytes", C.c_uint32),
+                ("device_bytes", C.c_uint64)]
 
 
 class dg_graph_opts(C.Structure):

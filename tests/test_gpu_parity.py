@@ -381,3 +381,31 @@ def test_resident_table_async_delayed_local(dg, res):
             dist, _ = G.sssp(src, mode=mode, d=d)
             np.testing.assert_array_equal(_np(dist), ref, err_msg=f"{mode} d={d}")
     G.close()
+
+
+@pytest.mark.parametrize("wmax,wbytes", [(255, 1), (256, 4), (1 << 24, 4)])
+def test_weight_storage(dg, wmax, wbytes):
+    """Weights that all fit a byte are kept as bytes, others as uint32; both
+    streams give the oracle's exact distances in every mode, single-source
+    and batched.  The byte case includes the largest byte value; the
+    uint32 cases include a weight of 256 (the boundary) and weights up to
+    2^24 (long paths that saturate nothing)."""
+    import dataclasses
+    g0, _ = _graph("rmat14")
+    rng = np.random.default_rng(wmax)
+    w = rng.integers(1, wmax + 1, size=g0.m, dtype=np.uint64).astype(np.uint32)
+    w[rng.integers(0, g0.m)] = wmax  # the largest weight occurs
+    g = dataclasses.replace(g0, w=w, name=f"rmat14_w{wmax}")
+    G = dg.Graph.from_csr(g)
+    assert G.info().weight_bytes == wbytes
+    srcs = _sources(g, 3)
+    refs = [osp.bellman_ford_sync(g, s)[0] for s in srcs]
+    for mode, d in MODES:
+        for s, ref in zip(srcs, refs):
+            dist, _ = G.sssp(s, mode=mode, d=max(d, 1))
+            np.testing.assert_array_equal(_np(dist), ref, err_msg=f"{mode} d={d} w<={wmax}")
+        if mode != "delayed_local":
+            out, _ = G.sssp_batch(srcs, mode=mode, d=max(d, 1))
+            for i, ref in enumerate(refs):
+                np.testing.assert_array_equal(_np(out[i]), ref, err_msg=f"batch {mode} d={d} w<={wmax}")
+    G.close()
