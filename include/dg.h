@@ -188,6 +188,47 @@ dg_status dg_graph_destroy(dg_graph* g);
 /* Fill *info with static facts about g. */
 dg_status dg_graph_info_get(const dg_graph* g, dg_graph_info* info);
 
+/* Layout plans: the host-side part of dg_graph_create, without a device.
+ * dg_plan_create validates the arrays exactly as dg_graph_create does and
+ * builds what it would upload for a device of `compute_units` compute units
+ * (>= 1): the in-edge form with source slots (section III-A: pull sweeps read
+ * in-neighbours), the compact region and its resident table, the tiles, and
+ * the blocked worker partition balanced by in-edges (section III-A).  For
+ * inspecting a layout before uploading it, and for testing it on machines
+ * without a GPU.  Arguments and errors as dg_graph_create, except DEVICE,
+ * which cannot occur; *out is owned by the caller until dg_plan_destroy. */
+typedef struct dg_plan dg_plan;
+typedef struct {
+  uint32_t n;
+  uint64_t m;
+  uint32_t workers;           /* worker blocks                                  */
+  uint32_t tiles;
+  uint32_t max_in_degree;
+  uint32_t dangling;
+  uint32_t hot_vertices;      /* K: sources in the compact region               */
+  uint64_t hot_edges;
+  uint32_t resident_vertices; /* R: leading compact-region slots in the table   */
+  uint64_t resident_edges;
+  uint32_t weight_bytes;      /* 1, 4, or 0 without weights                     */
+  uint64_t content_hash;      /* hash of the in-edge form (the tuning cache key) */
+} dg_plan_info;
+dg_status dg_plan_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
+                         const uint32_t* w, const dg_graph_opts* opts, uint32_t compute_units, dg_plan** out);
+dg_status dg_plan_info_get(const dg_plan* p, dg_plan_info* info);
+/* Copies the plan into caller arrays; any pointer may be NULL to skip it.
+ *   in_ptr [n+1]    in-edge offsets
+ *   in_src [m]      slot of each in-edge's source: the vertex itself, or
+ *                   n + rank for the K compact-region sources (the first R
+ *                   of them are the resident table)
+ *   in_w   [m]      the weight of each in-edge, widened to uint32
+ *                   (INVALID_ARGUMENT if the graph has none)
+ *   cpos   [n]      slot of each vertex's published value
+ *   tile_v [tiles+1]  first vertex of each tile
+ *   work_t [workers+1] first tile of each worker */
+dg_status dg_plan_arrays(const dg_plan* p, uint32_t* in_ptr, uint32_t* in_src, uint32_t* in_w, uint32_t* cpos,
+                         uint32_t* tile_v, uint32_t* work_t);
+dg_status dg_plan_destroy(dg_plan* p);
+
 /* PageRank by repeated pull sweeps (sections III and IV-A).
  *   damping     0 <= damping < 1 (0.85 is the customary value)
  *   tol         stop after the first sweep whose L1 score change is < tol

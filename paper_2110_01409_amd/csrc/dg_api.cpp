@@ -17,6 +17,7 @@
 #include "dg_graph.hpp"
 #include "dg_host.hpp"
 #include "dg_internal.hpp"
+#include "dg_plan.hpp"
 
 using namespace dg;
 using dg::host::fail;
@@ -53,32 +54,18 @@ void current_allocator(dg_alloc_fn& alloc, dg_free_fn& free_fn, void*& ctx) {
   ctx = g_alloc_ctx;
 }
 
-void build_tiles(const std::vector<uint32_t>& in_ptr, uint32_t n, std::vector<uint32_t>& tile_v) {
-  tile_v.clear();
-  tile_v.push_back(0);
-  uint32_t nv = 0;
-  uint64_t ne = 0;
-  for (uint32_t v = 0; v < n; ++v) {
-    const uint64_t deg = in_ptr[v + 1] - in_ptr[v];
-    if (nv > 0 && (nv == (uint32_t)kTileV || ne + deg > (uint64_t)kTileE)) {
-      tile_v.push_back(v);
-      nv = 0;
-      ne = 0;
-    }
-    ++nv;
-    ne += deg;
-  }
-  if (tile_v.back() != n) tile_v.push_back(n);
-}
-
 }  // namespace host
 }  // namespace dg
 
-using dg::host::build_tiles;
 
 using dg::host::kMaxSweeps;
 using dg::host::kSweepChunk;
 using dg::host::kWorkersPerCU;
+using dg::host::build_layout;
+using dg::host::build_workers;
+using dg::host::plan_workers;
+using dg::host::Layout;
+using dg::host::validate_graph;
 
 namespace dg {
 namespace host {
@@ -155,36 +142,6 @@ void release_all(dg_graph* g) {
 // blocks balanced by in-neighbours).  The cost of a tile also counts its
 // vertices and a fixed per-tile overhead, because on the GPU each vertex is
 // read and written and each tile costs a few workgroup barriers.
-void build_workers(const std::vector<uint32_t>& tile_v, const std::vector<uint32_t>& tile_e0, uint32_t P,
-                   std::vector<uint32_t>& work_t) {
-  const uint32_t T = (uint32_t)tile_v.size() - 1;
-  std::vector<double> cum(T + 1, 0.0);
-  for (uint32_t t = 0; t < T; ++t) {
-    const double e = (double)(tile_e0[t + 1] - tile_e0[t]);
-    const double v = (double)(tile_v[t + 1] - tile_v[t]);
-    cum[t + 1] = cum[t] + 256.0 + e + 4.0 * v;
-  }
-  work_t.assign(P + 1, T);
-  work_t[0] = 0;
-  for (uint32_t w = 1; w < P; ++w) {
-    const double target = cum[T] * (double)w / (double)P;
-    uint32_t t = (uint32_t)(std::lower_bound(cum.begin(), cum.end(), target) - cum.begin());
-    t = std::min(std::max(t, work_t[w - 1]), T);
-    work_t[w] = t;
-  }
-  work_t[P] = T;
-}
-
-// 64-bit FNV-1a over 8-byte words (the tail zero-padded) of a uint32 array,
-// continuing from h.
-uint64_t hash_words(uint64_t h, const uint32_t* p, size_t n) {
-  const uint64_t prime = 0x100000001b3ull;
-  size_t i = 0;
-  for (; i + 2 <= n; i += 2) h = (h ^ ((uint64_t)p[i] | ((uint64_t)p[i + 1] << 32))) * prime;
-  if (i < n) h = (h ^ (uint64_t)p[i]) * prime;
-  return (h ^ (uint64_t)n) * prime;
-}
-
 dg_status ensure_workspace(dg_graph* g, uint32_t S, hipStream_t s) {
   if (!g->vals[0]) {
     const size_t bytes = ((size_t)g->n + g->K) * 8;
@@ -432,24 +389,8 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
                           const uint32_t* w, const dg_graph_opts* opts, void* hip_stream, dg_graph** out) {
   g_last_error.clear();
   if (!out) return fail(DG_ERR_INVALID_ARGUMENT, "out is NULL");
-  if (n == 0 || n > 0xFFFFFFFEu) return fail(DG_ERR_INVALID_ARGUMENT, "n = %u outside [1, 2^32-2]", n);
-  if (m >= (uint64_t)0xFFFFFFFFu - 2 * kEdgePad) return fail(DG_ERR_INVALID_ARGUMENT, "m = %llu too large",
-                                                             (unsigned long long)m);
-  if (layout != DG_CSR && layout != DG_CSC) return fail(DG_ERR_INVALID_ARGUMENT, "unknown layout %d", (int)layout);
-  if (!ptr) return fail(DG_ERR_INVALID_ARGUMENT, "ptr is NULL");
-  if (m > 0 && !idx) return fail(DG_ERR_INVALID_ARGUMENT, "idx is NULL");
-  if (ptr[0] != 0) return fail(DG_ERR_INVALID_ARGUMENT, "ptr[0] = %llu, expected 0", (unsigned long long)ptr[0]);
-  for (uint32_t v = 0; v < n; ++v)
-    if (ptr[v + 1] < ptr[v]) return fail(DG_ERR_INVALID_ARGUMENT, "ptr decreases at %u", v);
-  if (ptr[n] != m) return fail(DG_ERR_INVALID_ARGUMENT, "ptr[n] = %llu, expected m = %llu",
-                               (unsigned long long)ptr[n], (unsigned long long)m);
-  for (uint64_t e = 0; e < m; ++e)
-    if (idx[e] >= n) return fail(DG_ERR_INVALID_ARGUMENT, "idx[%llu] = %u >= n", (unsigned long long)e, idx[e]);
-  const uint32_t want_workers = opts ? opts->workers : 0u;
-  uint32_t hot_max = (!opts || opts->hot_vertices == DG_HOT_AUTO) ? 524288u : opts->hot_vertices;
-  hot_max = std::min<uint32_t>(hot_max, 0xFFFFFFFEu - n);
-  const bool res_auto = !opts || opts->resident_vertices == DG_RESIDENT_AUTO;
-  const uint32_t res_max = std::min<uint32_t>(res_auto ? kResBytes / 4u : opts->resident_vertices, kResBytes / 4u);
+  dg_status st = validate_graph(n, m, layout, ptr, idx);
+  if (st != DG_OK) return st;
 
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   dg_graph* g = new (std::nothrow) dg_graph;
@@ -465,107 +406,23 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
   g->m = m;
   g->has_w = (w != nullptr);
 
-  // In-edge form (stable counting sort: in-edges of a vertex by ascending
-  // source), with each source replaced by the slot of its published value.
-  std::vector<uint32_t> in_ptr, in_src, in_w, w8pack, out_deg, cpos, tile_v, work_t;
-  try {
-    in_ptr.assign((size_t)n + 1, 0);
-    in_src.assign((size_t)m + kEdgePad, 0);
-    if (w) in_w.assign((size_t)m + kEdgePad, 0);
-    out_deg.assign(n, 0);
-    if (layout == DG_CSR) {
-      for (uint32_t u = 0; u < n; ++u) out_deg[u] = (uint32_t)(ptr[u + 1] - ptr[u]);
-    } else {
-      for (uint64_t e = 0; e < m; ++e) ++out_deg[idx[e]];
-    }
-    // Compact region: the sources with the largest above-average out-degree,
-    // in three runs, each in vertex order: the R/2 largest, the next R/2
-    // (together the sweeps' LDS-resident table of R slots, of which a
-    // float64 sweep keeps the first half), then the rest.  Vertex order keeps
-    // each worker's hot vertices in a few contiguous runs of slots, so a
-    // commit dirties few cache lines of the region everybody gathers from
-    // (the reason the paper gives for blocked partitioning and line-sized
-    // buffers); ordering the table by degree instead made asynchronous
-    // sweeps 12% slower on R-MAT.
-    cpos.resize(n);
-    for (uint32_t v = 0; v < n; ++v) cpos[v] = v;
-    {
-      const double avg = (double)m / (double)n;
-      std::vector<uint32_t> cand;
-      for (uint32_t v = 0; v < n; ++v)
-        if (out_deg[v] > 1 && (double)out_deg[v] > avg) cand.push_back(v);
-      std::stable_sort(cand.begin(), cand.end(),
-                       [&](uint32_t a, uint32_t b) { return out_deg[a] > out_deg[b]; });
-      g->K = (uint32_t)std::min<size_t>(cand.size(), hot_max);
-      cand.resize(g->K);
-      g->R = std::min(g->K, res_max);
-      // Automatic size: no table (and no reordering) unless it covers at
-      // least 1/16 of the in-edges; below that its refreshes cost more than
-      // the gathers it saves.
-      if (res_auto) {
-        uint64_t cover = 0;
-        for (uint32_t r = 0; r < g->R; ++r) cover += out_deg[cand[r]];
-        if (cover * 16 < m) g->R = 0;
-      }
-      const uint32_t half = (g->R + 1) / 2;
-      std::sort(cand.begin(), cand.begin() + half);
-      std::sort(cand.begin() + half, cand.begin() + g->R);
-      std::sort(cand.begin() + g->R, cand.end());
-      for (uint32_t r = 0; r < g->K; ++r) {
-        cpos[cand[r]] = n + r;
-        g->hot_edges += out_deg[cand[r]];
-        if (r < g->R) g->res_edges += out_deg[cand[r]];
-      }
-    }
-    if (layout == DG_CSR) {
-      for (uint64_t e = 0; e < m; ++e) ++in_ptr[idx[e] + 1];
-      for (uint32_t v = 0; v < n; ++v) in_ptr[v + 1] += in_ptr[v];
-      std::vector<uint32_t> pos(in_ptr.begin(), in_ptr.end() - 1);
-      for (uint32_t u = 0; u < n; ++u) {
-        const uint32_t slot = cpos[u];
-        for (uint64_t e = ptr[u]; e < ptr[u + 1]; ++e) {
-          const uint32_t p = pos[idx[e]]++;
-          in_src[p] = slot;
-          if (w) in_w[p] = w[e];
-        }
-      }
-    } else {
-      for (uint32_t v = 0; v <= n; ++v) in_ptr[v] = (uint32_t)ptr[v];
-      for (uint64_t e = 0; e < m; ++e) in_src[e] = cpos[idx[e]];
-      if (w) std::copy(w, w + m, in_w.begin());
-    }
-    for (uint32_t v = 0; v < n; ++v) {
-      g->max_in_deg = std::max(g->max_in_deg, in_ptr[v + 1] - in_ptr[v]);
-      g->n_dangling += out_deg[v] == 0;
-    }
-    build_tiles(in_ptr, n, tile_v);
-    g->tile_v_h = tile_v;
-    g->tile_e0_h.resize(tile_v.size());
-    for (size_t t = 0; t < tile_v.size(); ++t) g->tile_e0_h[t] = in_ptr[tile_v[t]];
-    uint64_t h = 0xcbf29ce484222325ull;
-    h = hash_words(h, in_ptr.data(), in_ptr.size());
-    h = hash_words(h, in_src.data(), (size_t)m);
-    if (w) h = hash_words(h, in_w.data(), (size_t)m);
-    g->hash = hash_words(h, out_deg.data(), out_deg.size());
-    // Weights that all fit a byte are stored as bytes (packed four to a
-    // word here): a quarter of the weight stream's bytes per sweep.
-    if (w && std::all_of(w, w + m, [](uint32_t x) { return x <= 255u; })) {
-      w8pack.assign(((size_t)m + kEdgePad + 16 + 3) / 4, 0u);
-      for (uint64_t e = 0; e < m; ++e) w8pack[e >> 2] |= in_w[e] << (8 * (e & 3));
-      std::vector<uint32_t>().swap(in_w);
-    }
-  } catch (const std::bad_alloc&) {
+  // The layout every sweep reads (the same construction dg_plan_create
+  // returns without a device).
+  Layout L;
+  if ((st = build_layout(n, m, layout, ptr, idx, w, opts, L)) != DG_OK) {
     delete g;
-    return fail(DG_ERR_OUT_OF_MEMORY, "host allocation failed while building the in-edge form");
+    return st;
   }
-  g->T = (uint32_t)tile_v.size() - 1;
-  // Gathers address the value array through a buffer resource with a 32-bit
-  // byte range: (n + K) float64 slots must stay below 4 GiB.
-  if (((uint64_t)n + g->K) * 8u >= (1ull << 32)) {
-    delete g;
-    return fail(DG_ERR_UNSUPPORTED, "n + hot slots = %llu exceeds the 2^29 value slots a sweep can address",
-                (unsigned long long)n + g->K);
-  }
+  g->K = L.K;
+  g->R = L.R;
+  g->hot_edges = L.hot_edges;
+  g->res_edges = L.res_edges;
+  g->max_in_deg = L.max_in_deg;
+  g->n_dangling = L.n_dangling;
+  g->hash = L.hash;
+  g->T = L.T();
+  g->tile_v_h = L.tile_v;
+  g->tile_e0_h = L.tile_e0;
 
   // Device sizes.  Without a device (or on error) nothing below leaks.
   int dev = 0, cus = 0;
@@ -580,20 +437,19 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
   }
   g->cus = (uint32_t)cus;
   g->lds_per_block = (size_t)lds;
-  uint32_t P = want_workers ? want_workers : g->cus * kWorkersPerCU;
-  P = std::max(1u, std::min(P, g->T));
-  if (P > 8 && !want_workers) P &= ~7u;
+  const uint32_t P = plan_workers(L, opts ? opts->workers : 0u, g->cus);
   g->P = P;
-  build_workers(g->tile_v_h, g->tile_e0_h, P, work_t);
+  std::vector<uint32_t> work_t;
+  build_workers(L.tile_v, L.tile_e0, P, work_t);
   for (uint32_t wk = 0; wk < P; ++wk)
-    g->max_block_v = std::max(g->max_block_v, tile_v[work_t[wk + 1]] - tile_v[work_t[wk]]);
+    g->max_block_v = std::max(g->max_block_v, L.tile_v[work_t[wk + 1]] - L.tile_v[work_t[wk]]);
 
   uint32_t* w8_words = nullptr;
   struct Up {
     uint32_t** dst;
     const std::vector<uint32_t>* src;
-  } ups[] = {{&g->in_ptr, &in_ptr}, {&g->in_src, &in_src}, {&g->in_w, &in_w}, {&w8_words, &w8pack},
-             {&g->out_deg, &out_deg}, {&g->cpos, &cpos}, {&g->tile_v, &tile_v}, {&g->work_t, &work_t}};
+  } ups[] = {{&g->in_ptr, &L.in_ptr}, {&g->in_src, &L.in_src}, {&g->in_w, &L.in_w}, {&w8_words, &L.w8pack},
+             {&g->out_deg, &L.out_deg}, {&g->cpos, &L.cpos}, {&g->tile_v, &L.tile_v}, {&g->work_t, &work_t}};
   for (auto& u : ups) {
     if (u.src->empty()) continue;
     const size_t bytes = u.src->size() * sizeof(uint32_t);

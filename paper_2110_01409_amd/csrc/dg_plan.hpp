@@ -1,0 +1,58 @@
+// Host-only construction of a graph's device layout: the in-edge form, the
+// compact region and its resident table, the tiles and the worker
+// partition.  dg_graph_create uploads exactly what build_layout and
+// build_partition produce; dg_plan_* expose the same result without a
+// device.  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "dg.h"
+
+namespace dg {
+namespace host {
+
+struct Layout {
+  uint32_t n = 0;
+  uint64_t m = 0;
+  bool has_w = false;
+  uint32_t K = 0;             // compact-region slots
+  uint32_t R = 0;             // leading compact-region slots in the resident table
+  uint64_t hot_edges = 0;     // in-edges whose source is in the compact region
+  uint64_t res_edges = 0;     // in-edges whose source is in the resident table
+  uint32_t max_in_deg = 0, n_dangling = 0;
+  uint64_t hash = 0;          // content hash of the in-edge form (FNV-1a)
+  std::vector<uint32_t> in_ptr;   // [n+1]
+  std::vector<uint32_t> in_src;   // [m + kEdgePad] slot of each in-edge's source
+  std::vector<uint32_t> in_w;     // [m + kEdgePad] uint32 weights, empty when packed or unweighted
+  std::vector<uint32_t> w8pack;   // bytes of the weights packed four to a word, when all are <= 255
+  std::vector<uint32_t> out_deg;  // [n]
+  std::vector<uint32_t> cpos;     // [n] slot of each vertex's published value
+  std::vector<uint32_t> tile_v;   // [T+1] first vertex of each tile
+  std::vector<uint32_t> tile_e0;  // [T+1] first in-edge of each tile
+  uint32_t T() const { return (uint32_t)tile_v.size() - 1; }
+};
+
+// Checks the arrays of dg_graph_create (the checks its documentation lists).
+dg_status validate_graph(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx);
+
+// Builds everything but the worker partition from validated arrays.
+// Returns DG_ERR_OUT_OF_MEMORY on host allocation failure and
+// DG_ERR_UNSUPPORTED when n plus the compact region exceeds the slots a
+// sweep can address.
+dg_status build_layout(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
+                       const uint32_t* w, const dg_graph_opts* opts, Layout& L);
+
+// Worker count for a device of `cus` compute units: opts->workers if set,
+// else 5 per compute unit rounded down to a multiple of 8; never more than
+// the tiles.
+uint32_t plan_workers(const Layout& L, uint32_t want_workers, uint32_t cus);
+
+// Contiguous tile ranges of P workers balanced by 256 + in-edges + 4 x
+// vertices per tile; work_t[P+1].
+void build_workers(const std::vector<uint32_t>& tile_v, const std::vector<uint32_t>& tile_e0, uint32_t P,
+                   std::vector<uint32_t>& work_t);
+
+}  // namespace host
+}  // namespace dg

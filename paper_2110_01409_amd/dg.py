@@ -36,7 +36,8 @@ EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_
            "dg_set_pagerank", "dg_set_sssp", "dg_graph_partition", "dg_access_matrix", "dg_graph_repartition",
            "dg_tune", "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_server_create",
            "dg_server_destroy", "dg_server_submit", "dg_server_step", "dg_server_fetch", "dg_server_status_get",
-           "dg_status_str", "dg_last_error", "dg_version")
+           "dg_plan_create", "dg_plan_info_get", "dg_plan_arrays", "dg_plan_destroy", "dg_status_str",
+           "dg_last_error", "dg_version")
 DG_QUERY_SSSP, DG_QUERY_PPR = 0, 1
 QUERIES = {"sssp": DG_QUERY_SSSP, "ppr": DG_QUERY_PPR}
 DG_ALGO_PAGERANK, DG_ALGO_SSSP = 0, 1
@@ -56,6 +57,13 @@ class dg_graph_info(C.Structure):
                 ("compute_units", C.c_uint32), ("hot_vertices", C.c_uint32), ("hot_edges", C.c_uint64),
                 ("resident_vertices", C.c_uint32), ("resident_edges", C.c_uint64), ("weight_bytes", C.c_uint32),
                 ("device_bytes", C.c_uint64)]
+
+
+class dg_plan_info(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("m", C.c_uint64), ("workers", C.c_uint32), ("tiles", C.c_uint32),
+                ("max_in_degree", C.c_uint32), ("dangling", C.c_uint32), ("hot_vertices", C.c_uint32),
+                ("hot_edges", C.c_uint64), ("resident_vertices", C.c_uint32), ("resident_edges", C.c_uint64),
+                ("weight_bytes", C.c_uint32), ("content_hash", C.c_uint64)]
 
 
 class dg_graph_opts(C.Structure):
@@ -122,6 +130,12 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2110_01409_amd.build` "
                           "(or __graft_entry__.build()) first")
+    # PyTorch first: the library then binds to the HIP runtime PyTorch loaded
+    # (its libamdhip64 satisfies the library's dependency), so device
+    # pointers and streams from torch are valid in the library.  Loaded the
+    # other way round, the process holds two HIP runtimes and the library
+    # finds no device.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P = C.c_void_p
     sig = {
@@ -129,6 +143,11 @@ def _load():
         "dg_graph_create": (C.c_int, [C.c_uint32, C.c_uint64, C.c_int, P, P, P, C.POINTER(dg_graph_opts), P,
                                       C.POINTER(C.c_void_p)]),
         "dg_graph_destroy": (C.c_int, [P]),
+        "dg_plan_create": (C.c_int, [C.c_uint32, C.c_uint64, C.c_int, P, P, P, C.POINTER(dg_graph_opts), C.c_uint32,
+                                     C.POINTER(C.c_void_p)]),
+        "dg_plan_info_get": (C.c_int, [P, C.POINTER(dg_plan_info)]),
+        "dg_plan_arrays": (C.c_int, [P, P, P, P, P, P, P]),
+        "dg_plan_destroy": (C.c_int, [P]),
         "dg_graph_info_get": (C.c_int, [P, C.POINTER(dg_graph_info)]),
         "dg_pagerank": (C.c_int, [P, C.c_double, C.c_double, C.c_int, C.c_uint32, C.c_int, C.c_uint32, P, C.c_int,
                                   C.POINTER(dg_stats), P]),
@@ -194,6 +213,22 @@ def dg_graph_create(n, m, layout, ptr, idx, w, opts, stream, out):
 
 def dg_graph_destroy(g):
     return lib.dg_graph_destroy(g)
+
+
+def dg_plan_create(n, m, layout, ptr, idx, w, opts, compute_units, out):
+    return lib.dg_plan_create(n, m, layout, ptr, idx, w, opts, compute_units, out)
+
+
+def dg_plan_info_get(p, info):
+    return lib.dg_plan_info_get(p, info)
+
+
+def dg_plan_arrays(p, in_ptr, in_src, in_w, cpos, tile_v, work_t):
+    return lib.dg_plan_arrays(p, in_ptr, in_src, in_w, cpos, tile_v, work_t)
+
+
+def dg_plan_destroy(p):
+    return lib.dg_plan_destroy(p)
 
 
 def dg_graph_info_get(g, info):
@@ -312,6 +347,34 @@ def _check(status, allow=()):
 # ------------------------------------------------------ torch as allocator --
 
 _torch_hooks = None
+
+
+def plan(n, ptr, idx, w=None, layout="csr", compute_units=256, workers=0, hot_vertices=DG_HOT_AUTO,
+         resident_vertices=DG_RESIDENT_AUTO):
+    """The layout dg_graph_create would upload, built on the host only
+    (dg_plan_*): a dict of the plan's facts and its arrays as numpy arrays
+    (in_ptr, in_src, in_w or None, cpos, tile_v, work_t)."""
+    ptr = np.ascontiguousarray(ptr, dtype=np.uint64)
+    idx = np.ascontiguousarray(idx, dtype=np.uint32)
+    wa = None if w is None else np.ascontiguousarray(w, dtype=np.uint32)
+    opts = dg_graph_opts(int(workers), int(hot_vertices), int(resident_vertices))
+    h = C.c_void_p()
+    _check(dg_plan_create(int(n), int(idx.shape[0]), DG_CSR if layout == "csr" else DG_CSC, _np_ptr(ptr),
+                          _np_ptr(idx), None if wa is None else _np_ptr(wa), C.byref(opts), int(compute_units),
+                          C.byref(h)))
+    try:
+        info = dg_plan_info()
+        _check(dg_plan_info_get(h, C.byref(info)))
+        out = {f: getattr(info, f) for f, _ in dg_plan_info._fields_}
+        arr = {"in_ptr": np.empty(info.n + 1, np.uint32), "in_src": np.empty(info.m, np.uint32),
+               "in_w": np.empty(info.m, np.uint32) if wa is not None else None,
+               "cpos": np.empty(info.n, np.uint32), "tile_v": np.empty(info.tiles + 1, np.uint32),
+               "work_t": np.empty(info.workers + 1, np.uint32)}
+        _check(dg_plan_arrays(h, *[None if a is None else _np_ptr(a) for a in arr.values()]))
+        out.update(arr)
+        return out
+    finally:
+        dg_plan_destroy(h)
 
 
 def use_torch_allocator():
