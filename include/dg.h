@@ -432,15 +432,19 @@ dg_status dg_set_create(uint32_t count, const dg_graph_desc* graphs, const dg_se
 dg_status dg_set_destroy(dg_set* s);
 dg_status dg_set_info_get(const dg_set* s, dg_set_info* info);
 
-/* PageRank of every graph of the set (as dg_pagerank, per graph).
+/* PageRank of every graph of the set (as dg_pagerank, per graph).  All
+ * graphs are swept together; every graph's own L1 change of normalised
+ * scores is measured each sweep, and the set stops at the first sweep after
+ * which every graph has met tol (the single-graph rule, graph by graph).
  *   flags       0 (reserved)
- *   dtype       DG_F32 only when the union tolerance above is >= 1e-7 (the
- *               float32 rounding floor), else DG_ERR_UNSUPPORTED: use DG_F64
+ *   dtype       DG_F32 only for tol >= 1e-7 (the float32 rounding floor) or
+ *               tol = 0, else DG_ERR_UNSUPPORTED: use DG_F64
  *   out_scores  n float64 over the union (graph i's vertices at its offset,
  *               the sum of the n of graphs before it), each graph normalised
  *               to sum 1; device memory when out_on_device != 0
- *   out_sweeps  host array of `graphs` entries or NULL: the set's sweeps
- *               (0 = it did not stop within max_sweeps)
+ *   out_sweeps  host array of `graphs` entries or NULL: for each graph the
+ *               first sweep after which its change was below tol (0 = none
+ *               within max_sweeps)
  *   stats       as dg_pagerank's on the union: sweeps, device seconds of the
  *               sweeps, edges_traversed = total edges x sweeps */
 dg_status dg_set_pagerank(dg_set* s, double damping, double tol, dg_mode mode, uint32_t d, dg_dtype dtype,

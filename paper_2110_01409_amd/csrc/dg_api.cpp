@@ -63,6 +63,7 @@ using dg::host::kSweepChunk;
 using dg::host::kWorkersPerCU;
 using dg::host::build_layout;
 using dg::host::build_workers;
+using dg::host::build_workers_seg;
 using dg::host::plan_workers;
 using dg::host::Layout;
 using dg::host::validate_graph;
@@ -138,10 +139,6 @@ void release_all(dg_graph* g) {
   g->owned.clear();
 }
 
-// Blocked partition of the tiles over P workers (section III-A: contiguous
-// blocks balanced by in-neighbours).  The cost of a tile also counts its
-// vertices and a fixed per-tile overhead, because on the GPU each vertex is
-// read and written and each tile costs a few workgroup barriers.
 dg_status ensure_workspace(dg_graph* g, uint32_t S, hipStream_t s) {
   if (!g->vals[0]) {
     const size_t bytes = ((size_t)g->n + g->K) * 8;
@@ -150,7 +147,7 @@ dg_status ensure_workspace(dg_graph* g, uint32_t S, hipStream_t s) {
       if (!v) return fail(DG_ERR_OUT_OF_MEMORY, "workspace allocation of %zu bytes failed", bytes);
     }
     g->norm = static_cast<double*>(dev_alloc(g, (kNormBlocks + 1) * sizeof(double), s));
-    g->part = static_cast<double*>(dev_alloc(g, 2 * (size_t)g->P * sizeof(double), s));
+    g->part = static_cast<double*>(dev_alloc(g, 3 * (size_t)g->P * sizeof(double), s));
     if (!g->norm || !g->part) return fail(DG_ERR_OUT_OF_MEMORY, "workspace allocation failed");
   }
   if (!g->events) {
@@ -388,6 +385,17 @@ dg_status dg_set_allocator(dg_alloc_fn alloc, dg_free_fn free_fn, void* ctx) {
 dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
                           const uint32_t* w, const dg_graph_opts* opts, void* hip_stream, dg_graph** out) {
   g_last_error.clear();
+  return dg::host::graph_create(n, m, layout, ptr, idx, w, opts, nullptr, hip_stream, out);
+}
+
+}  // extern "C"
+
+namespace dg {
+namespace host {
+
+dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
+                       const uint32_t* w, const dg_graph_opts* opts, const std::vector<uint32_t>* seg_v,
+                       void* hip_stream, dg_graph** out) {
   if (!out) return fail(DG_ERR_INVALID_ARGUMENT, "out is NULL");
   dg_status st = validate_graph(n, m, layout, ptr, idx);
   if (st != DG_OK) return st;
@@ -409,7 +417,7 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
   // The layout every sweep reads (the same construction dg_plan_create
   // returns without a device).
   Layout L;
-  if ((st = build_layout(n, m, layout, ptr, idx, w, opts, L)) != DG_OK) {
+  if ((st = build_layout(n, m, layout, ptr, idx, w, opts, L, seg_v)) != DG_OK) {
     delete g;
     return st;
   }
@@ -437,10 +445,20 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
   }
   g->cus = (uint32_t)cus;
   g->lds_per_block = (size_t)lds;
-  const uint32_t P = plan_workers(L, opts ? opts->workers : 0u, g->cus);
-  g->P = P;
+  uint32_t P = plan_workers(L, opts ? opts->workers : 0u, g->cus);
   std::vector<uint32_t> work_t;
-  build_workers(L.tile_v, L.tile_e0, P, work_t);
+  if (seg_v) {
+    g->G = (uint32_t)seg_v->size() - 1;
+    g->seg_v = *seg_v;
+    build_workers_seg(L.tile_v, L.tile_e0, *seg_v, std::max(P, g->G), work_t, g->wseg_h);
+    P = g->wseg_h.back();
+    g->wgraph_h.resize(P);
+    for (uint32_t gi = 0; gi < g->G; ++gi)
+      for (uint32_t wk = g->wseg_h[gi]; wk < g->wseg_h[gi + 1]; ++wk) g->wgraph_h[wk] = gi;
+  } else {
+    build_workers(L.tile_v, L.tile_e0, P, work_t);
+  }
+  g->P = P;
   for (uint32_t wk = 0; wk < P; ++wk)
     g->max_block_v = std::max(g->max_block_v, L.tile_v[work_t[wk + 1]] - L.tile_v[work_t[wk]]);
 
@@ -449,7 +467,8 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
     uint32_t** dst;
     const std::vector<uint32_t>* src;
   } ups[] = {{&g->in_ptr, &L.in_ptr}, {&g->in_src, &L.in_src}, {&g->in_w, &L.in_w}, {&w8_words, &L.w8pack},
-             {&g->out_deg, &L.out_deg}, {&g->cpos, &L.cpos}, {&g->tile_v, &L.tile_v}, {&g->work_t, &work_t}};
+             {&g->out_deg, &L.out_deg}, {&g->cpos, &L.cpos}, {&g->tile_v, &L.tile_v}, {&g->work_t, &work_t},
+             {&g->wseg, &g->wseg_h}, {&g->wgraph, &g->wgraph_h}};
   for (auto& u : ups) {
     if (u.src->empty()) continue;
     const size_t bytes = u.src->size() * sizeof(uint32_t);
@@ -471,9 +490,22 @@ dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64
     delete g;
     return fail(DG_ERR_DEVICE, "graph upload failed: %s", hipGetErrorString(he));
   }
+  if (g->G) {
+    g->gsweeps = static_cast<uint32_t*>(dev_alloc(g, (size_t)g->G * sizeof(uint32_t), s));
+    if (!g->gsweeps) {
+      release_all(g);
+      delete g;
+      return fail(DG_ERR_OUT_OF_MEMORY, "device allocation failed");
+    }
+  }
   *out = g;
   return DG_OK;
 }
+
+}  // namespace host
+}  // namespace dg
+
+extern "C" {
 
 dg_status dg_graph_destroy(dg_graph* g) {
   if (!g) return DG_OK;
@@ -603,6 +635,11 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
   a.d = d_eff;
   a.cap = cap;
   a.res = nres;
+  a.wseg = g->G ? g->wseg : nullptr;
+  a.wgraph = g->wgraph;
+  a.G = g->G;
+  a.gsweeps = g->gsweeps;
+  if (g->G) DG_HIP(launch_fill_u32(g->gsweeps, g->G, 0u, s));
   auto launch = [&](uint32_t k) {
     if (mode == DG_SYNC) {
       a.cin = (k & 1) ? c1 : c0;
@@ -981,6 +1018,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
 dg_status dg_graph_repartition(dg_graph* g, uint32_t workers, void* hip_stream) {
   g_last_error.clear();
   if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (g->G) return fail(DG_ERR_UNSUPPORTED, "a set's union graph keeps its per-graph worker blocks");
   const uint32_t P = workers ? std::max(1u, std::min(workers, g->T)) : default_workers(g, kWorkersPerCU);
   if (P == g->P) return DG_OK;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -990,7 +1028,7 @@ dg_status dg_graph_repartition(dg_graph* g, uint32_t workers, void* hip_stream) 
   for (uint32_t w = 0; w < P; ++w) mbv = std::max(mbv, g->tile_v_h[work_t[w + 1]] - g->tile_v_h[work_t[w]]);
   DG_HIP(hipStreamSynchronize(s));
   uint32_t* wt = static_cast<uint32_t*>(dev_alloc(g, (size_t)(P + 1) * 4, s));
-  double* part = g->part ? static_cast<double*>(dev_alloc(g, 2 * (size_t)P * sizeof(double), s)) : nullptr;
+  double* part = g->part ? static_cast<double*>(dev_alloc(g, 3 * (size_t)P * sizeof(double), s)) : nullptr;
   if (!wt || (g->part && !part)) {
     dev_free(g, wt);
     dev_free(g, part);

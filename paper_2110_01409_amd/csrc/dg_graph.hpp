@@ -34,6 +34,15 @@ struct dg_graph {
   uint32_t max_block_v = 1;  // most vertices any worker owns
   std::vector<uint32_t> tile_v_h, tile_e0_h;  // host copies: first vertex / first in-edge of each tile
   uint64_t hash = 0;                         // content hash of the in-edge form (tuning cache key)
+  // Graph sets: the union of G graphs, with worker blocks aligned to graph
+  // boundaries (graph i's workers are wseg[i] .. wseg[i+1]-1); G = 0 otherwise.
+  uint32_t G = 0;
+  std::vector<uint32_t> seg_v;  // [G+1] first vertex of each graph (host)
+  std::vector<uint32_t> wseg_h; // [G+1] first worker of each graph (host)
+  uint32_t* wseg = nullptr;     // device copy of wseg_h
+  std::vector<uint32_t> wgraph_h;  // [P] graph of each worker (host)
+  uint32_t* wgraph = nullptr;      // device copy of wgraph_h
+  uint32_t* gsweeps = nullptr;  // [G] first sweep that took each graph below tol
   uint64_t hot_edges = 0;  // in-edges whose source is in the compact region
   uint32_t R = 0;          // leading compact-region slots kept in the sweeps' LDS table
   uint64_t res_edges = 0;  // in-edges whose source is one of them
@@ -71,6 +80,12 @@ void* dev_alloc(dg_graph* g, size_t bytes, hipStream_t s);
 void dev_free(dg_graph* g, void* p);
 // Device arrays of the resident graph as passed to the kernels.
 Topology topo(const dg_graph* g);
+// dg_graph_create for the union graph of a set: seg_v[G+1] are the first
+// vertices of the G graphs.  Tiles never cross a graph boundary and every
+// graph gets its own worker blocks (at least one).
+dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
+                       const uint32_t* w, const dg_graph_opts* opts, const std::vector<uint32_t>* seg_v,
+                       void* hip_stream, dg_graph** out);
 // Bellman-Ford from src and, when n_more > 0, also from the n_more sources in
 // the device array more_src (distance to the nearest source); otherwise as
 // dg_sssp.

@@ -23,8 +23,10 @@ dg_status fail(dg_status s, const char* fmt, ...);
 void current_allocator(dg_alloc_fn& alloc, dg_free_fn& free_fn, void*& ctx);
 
 // Tiles of consecutive vertices: at most kTileV vertices and kTileE in-edges,
-// except that a vertex with more in-edges is a tile of its own.
-void build_tiles(const std::vector<uint32_t>& in_ptr, uint32_t n, std::vector<uint32_t>& tile_v);
+// except that a vertex with more in-edges is a tile of its own; a tile also
+// ends before every vertex listed in seg_v (the graphs of a set).
+void build_tiles(const std::vector<uint32_t>& in_ptr, uint32_t n, std::vector<uint32_t>& tile_v,
+                 const std::vector<uint32_t>* seg_v = nullptr);
 
 }  // namespace host
 }  // namespace dg

@@ -63,7 +63,7 @@ struct SweepState {
   double* dang;       // [S+1] mass sweep k spreads uniformly: 1 - non-dangling mass after sweep k-1
   uint32_t* count;    // [S+1] workers finished in sweep k
   uint32_t* changed;  // [S+1] changed[k+1] != 0 iff sweep k decreased a distance
-  double* part;       // [2P] per-worker partial sums (residual, non-dangling mass)
+  double* part;       // [3P] per-worker partial sums (residual, non-dangling mass, total mass)
 };
 
 struct PrArgs {
@@ -78,6 +78,17 @@ struct PrArgs {
   uint32_t k;       // sweep index
   uint32_t d;       // commit interval in vertices (delayed mode)
   uint32_t cap;     // LDS staging capacity in vertices (delayed mode, LDS staging)
+  // Graph sets (the union of G graphs, worker blocks aligned to graph
+  // boundaries): graph i's workers are wseg[i] .. wseg[i+1]-1.  The stopping
+  // value of a sweep is then the largest per-graph L1 change divided by that
+  // graph's mass, and gsweeps[i] records the first sweep that took graph i
+  // below tol (0 until then).  wseg is null for a single graph.
+  // A worker whose graph has already met tol skips its block and keeps its
+  // mass partials of the sweep that converged (its values stay as they were).
+  const uint32_t* wseg;
+  const uint32_t* wgraph;  // [P] graph of each worker
+  uint32_t G;
+  uint32_t* gsweeps;
   // Slots n .. n+res-1 are read from the workgroup's LDS table (0 = none).
   // The table is filled at the start of the sweep; an asynchronous sweep
   // refreshes one segment of it after every tile, a delayed sweep after

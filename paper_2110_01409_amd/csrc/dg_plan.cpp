@@ -26,14 +26,23 @@ uint64_t hash_words(uint64_t h, const uint32_t* p, size_t n) {
 
 }  // namespace
 
-void build_tiles(const std::vector<uint32_t>& in_ptr, uint32_t n, std::vector<uint32_t>& tile_v) {
+void build_tiles(const std::vector<uint32_t>& in_ptr, uint32_t n, std::vector<uint32_t>& tile_v,
+                 const std::vector<uint32_t>* seg_v) {
   tile_v.clear();
   tile_v.push_back(0);
   uint32_t nv = 0;
   uint64_t ne = 0;
+  size_t next_seg = 1;  // index into seg_v of the next graph boundary
   for (uint32_t v = 0; v < n; ++v) {
     const uint64_t deg = in_ptr[v + 1] - in_ptr[v];
-    if (nv > 0 && (nv == (uint32_t)kTileV || ne + deg > (uint64_t)kTileE)) {
+    bool boundary = false;
+    if (seg_v) {
+      while (next_seg < seg_v->size() && (*seg_v)[next_seg] <= v) {
+        boundary |= (*seg_v)[next_seg] == v;
+        ++next_seg;
+      }
+    }
+    if (nv > 0 && (boundary || nv == (uint32_t)kTileV || ne + deg > (uint64_t)kTileE)) {
       tile_v.push_back(v);
       nv = 0;
       ne = 0;
@@ -64,6 +73,47 @@ void build_workers(const std::vector<uint32_t>& tile_v, const std::vector<uint32
   work_t[P] = T;
 }
 
+void build_workers_seg(const std::vector<uint32_t>& tile_v, const std::vector<uint32_t>& tile_e0,
+                       const std::vector<uint32_t>& seg_v, uint32_t P, std::vector<uint32_t>& work_t,
+                       std::vector<uint32_t>& wseg) {
+  const uint32_t G = (uint32_t)seg_v.size() - 1;
+  // first tile of each graph (tiles never cross a graph boundary)
+  std::vector<uint32_t> gt(G + 1);
+  for (uint32_t i = 0; i <= G; ++i)
+    gt[i] = (uint32_t)(std::lower_bound(tile_v.begin(), tile_v.end(), seg_v[i]) - tile_v.begin());
+  std::vector<double> cost(G, 0.0);
+  double total = 0.0;
+  for (uint32_t i = 0; i < G; ++i) {
+    for (uint32_t t = gt[i]; t < gt[i + 1]; ++t)
+      cost[i] += 256.0 + (double)(tile_e0[t + 1] - tile_e0[t]) + 4.0 * (double)(tile_v[t + 1] - tile_v[t]);
+    total += cost[i];
+  }
+  // one worker each, the rest by largest remaining cost per worker
+  std::vector<uint32_t> pw(G, 1u);
+  for (uint32_t extra = P - G, i = 0; extra > 0; --extra) {
+    uint32_t best = 0;
+    double bq = -1.0;
+    for (i = 0; i < G; ++i) {
+      if (pw[i] >= gt[i + 1] - gt[i]) continue;  // no more workers than tiles
+      const double q = cost[i] / (double)pw[i];
+      if (q > bq) bq = q, best = i;
+    }
+    if (bq < 0.0) break;
+    ++pw[best];
+  }
+  wseg.assign(G + 1, 0);
+  work_t.clear();
+  work_t.push_back(0);
+  for (uint32_t i = 0; i < G; ++i) {
+    wseg[i + 1] = wseg[i] + pw[i];
+    std::vector<uint32_t> tv(tile_v.begin() + gt[i], tile_v.begin() + gt[i + 1] + 1);
+    std::vector<uint32_t> te(tile_e0.begin() + gt[i], tile_e0.begin() + gt[i + 1] + 1);
+    std::vector<uint32_t> wt;
+    build_workers(tv, te, pw[i], wt);
+    for (uint32_t k = 1; k <= pw[i]; ++k) work_t.push_back(gt[i] + wt[k]);
+  }
+}
+
 dg_status validate_graph(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx) {
   if (n == 0 || n > 0xFFFFFFFEu) return fail(DG_ERR_INVALID_ARGUMENT, "n = %u outside [1, 2^32-2]", n);
   if (m >= (uint64_t)0xFFFFFFFFu - 2 * kEdgePad)
@@ -83,7 +133,8 @@ dg_status validate_graph(uint32_t n, uint64_t m, dg_layout layout, const uint64_
 }
 
 dg_status build_layout(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
-                       const uint32_t* w, const dg_graph_opts* opts, Layout& L) {
+                       const uint32_t* w, const dg_graph_opts* opts, Layout& L,
+                       const std::vector<uint32_t>* seg_v) {
   uint32_t hot_max = (!opts || opts->hot_vertices == DG_HOT_AUTO) ? 524288u : opts->hot_vertices;
   hot_max = std::min<uint32_t>(hot_max, 0xFFFFFFFEu - n);
   const bool res_auto = !opts || opts->resident_vertices == DG_RESIDENT_AUTO;
@@ -164,7 +215,7 @@ dg_status build_layout(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
       L.max_in_deg = std::max(L.max_in_deg, L.in_ptr[v + 1] - L.in_ptr[v]);
       L.n_dangling += L.out_deg[v] == 0;
     }
-    build_tiles(L.in_ptr, n, L.tile_v);
+    build_tiles(L.in_ptr, n, L.tile_v, seg_v);
     L.tile_e0.resize(L.tile_v.size());
     for (size_t t = 0; t < L.tile_v.size(); ++t) L.tile_e0[t] = L.in_ptr[L.tile_v[t]];
     uint64_t h = 0xcbf29ce484222325ull;

@@ -41,8 +41,11 @@ dg_status validate_graph(uint32_t n, uint64_t m, dg_layout layout, const uint64_
 // Returns DG_ERR_OUT_OF_MEMORY on host allocation failure and
 // DG_ERR_UNSUPPORTED when n plus the compact region exceeds the slots a
 // sweep can address.
+// seg_v (optional, [G+1]): first vertices of the graphs of a set; no tile
+// crosses one of them.
 dg_status build_layout(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
-                       const uint32_t* w, const dg_graph_opts* opts, Layout& L);
+                       const uint32_t* w, const dg_graph_opts* opts, Layout& L,
+                       const std::vector<uint32_t>* seg_v = nullptr);
 
 // Worker count for a device of `cus` compute units: opts->workers if set,
 // else 5 per compute unit rounded down to a multiple of 8; never more than
@@ -53,6 +56,13 @@ uint32_t plan_workers(const Layout& L, uint32_t want_workers, uint32_t cus);
 // vertices per tile; work_t[P+1].
 void build_workers(const std::vector<uint32_t>& tile_v, const std::vector<uint32_t>& tile_e0, uint32_t P,
                    std::vector<uint32_t>& work_t);
+
+// The same for a set: P >= G workers, each graph gets at least one and
+// otherwise workers in proportion to its cost, and its tiles are split
+// among them as above.  Returns wseg[G+1], the first worker of each graph.
+void build_workers_seg(const std::vector<uint32_t>& tile_v, const std::vector<uint32_t>& tile_e0,
+                       const std::vector<uint32_t>& seg_v, uint32_t P, std::vector<uint32_t>& work_t,
+                       std::vector<uint32_t>& wseg);
 
 }  // namespace host
 }  // namespace dg

@@ -10,10 +10,11 @@
 // x_v = alpha * (pulled) + c with the same constant c = ((1 - alpha) + alpha
 // D) / N for every vertex, and g's mass balance M_g (1 - alpha) + alpha D_g =
 // n_g ((1 - alpha) + alpha D) / N makes x / M_g solve g's own equation
-// x_v = alpha * (pulled) + ((1 - alpha) + alpha D_g / M_g) / n_g.  Since
-// M_g >= (1 - alpha) n_g / N, stopping the union when its L1 change is below
-// tol (1 - alpha) min_g n_g / N bounds every graph's own (normalised) L1
-// change by tol.
+// x_v = alpha * (pulled) + ((1 - alpha) + alpha D_g / M_g) / n_g.  Worker
+// blocks never cross a graph boundary, so the sweep kernel sums each graph's
+// L1 change and mass separately: a sweep's stopping value is the largest
+// change over M_g, i.e. the largest change of a graph's normalised scores,
+// and the set stops when every graph has met the single-graph rule.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -59,6 +60,14 @@ dg_status set_check_mode(dg_mode mode, uint32_t d, uint32_t max_sweeps) {
 void per_graph(const dg_set* s, const dg_stats& st, bool conv, uint32_t* out_sweeps) {
   if (!out_sweeps) return;
   for (uint32_t i = 0; i < s->G; ++i) out_sweeps[i] = conv ? st.sweeps : 0u;
+}
+
+// PageRank: the first sweep that took each graph below tol (0: never).
+dg_status per_graph_pagerank(const dg_set* s, uint32_t* out_sweeps, hipStream_t q) {
+  if (!out_sweeps) return DG_OK;
+  DG_HIP(hipMemcpyAsync(out_sweeps, s->g->gsweeps, (size_t)s->G * 4, hipMemcpyDeviceToHost, q));
+  DG_HIP(hipStreamSynchronize(q));
+  return DG_OK;
 }
 
 }  // namespace
@@ -127,8 +136,8 @@ dg_status dg_set_create(uint32_t count, const dg_graph_desc* graphs, const dg_se
   go.workers = opts ? opts->workers : 0u;
   go.hot_vertices = DG_HOT_AUTO;
   go.resident_vertices = DG_RESIDENT_AUTO;
-  dg_status st = dg_graph_create((uint32_t)N, M, DG_CSR, ptr.data(), M ? idx.data() : nullptr,
-                                 weighted == 1 ? w.data() : nullptr, &go, hip_stream, &s->g);
+  dg_status st = dg::host::graph_create((uint32_t)N, M, DG_CSR, ptr.data(), M ? idx.data() : nullptr,
+                                        weighted == 1 ? w.data() : nullptr, &go, &s->voff, hip_stream, &s->g);
   if (st != DG_OK) {
     delete s;
     return st;
@@ -186,11 +195,9 @@ dg_status dg_set_pagerank(dg_set* s, double damping, double tol, dg_mode mode, u
   dg_status st = set_check_mode(mode, d, max_sweeps);
   if (st != DG_OK) return st;
   const uint32_t N = s->voff.back();
-  const double tol_union = tol * (1.0 - damping) * (double)s->n_min / (double)N;
-  if (dtype == DG_F32 && tol > 0.0 && tol_union < kF32Floor)
-    return fail(DG_ERR_UNSUPPORTED,
-                "float32 cannot reach the union tolerance %.3g that bounds each graph's change by %.3g; use DG_F64",
-                tol_union, tol);
+  if (dtype == DG_F32 && tol > 0.0 && tol < kF32Floor)
+    return fail(DG_ERR_UNSUPPORTED, "float32 scores cannot settle below an L1 change of %.0e (tol %.3g); use DG_F64",
+                kF32Floor, tol);
   hipStream_t q = static_cast<hipStream_t>(hip_stream);
   double* outd = out_scores;
   if (!out_on_device) {
@@ -198,7 +205,7 @@ dg_status dg_set_pagerank(dg_set* s, double damping, double tol, dg_mode mode, u
     if (!outd) return fail(DG_ERR_OUT_OF_MEMORY, "output staging allocation failed");
   }
   dg_stats x{};
-  const dg_status run = dg_pagerank(s->g, damping, tol_union, mode, d, dtype, max_sweeps, outd, 1, &x, hip_stream);
+  const dg_status run = dg_pagerank(s->g, damping, tol, mode, d, dtype, max_sweeps, outd, 1, &x, hip_stream);
   hipError_t he = hipSuccess;
   if (run == DG_OK || run == DG_ERR_NOT_CONVERGED) {
     he = launch_segment_normalize(outd, s->voff_d, s->G, q);
@@ -212,7 +219,8 @@ dg_status dg_set_pagerank(dg_set* s, double damping, double tol, dg_mode mode, u
     (void)hipGetLastError();
     return fail(DG_ERR_DEVICE, "set normalisation failed: %s", hipGetErrorString(he));
   }
-  per_graph(s, x, run == DG_OK, out_sweeps);
+  const dg_status ps = per_graph_pagerank(s, out_sweeps, q);
+  if (ps != DG_OK) return ps;
   if (stats) *stats = x;
   if (run != DG_OK) return fail(run, "the set did not converge within %u sweeps", max_sweeps);
   return DG_OK;

@@ -232,7 +232,7 @@ template <int M, typename T, bool LOCAL = false>
 __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
   __shared__ uint32_t s_ptr[kTileV + 1];
   __shared__ double s_acc[kTileV];
-  __shared__ double s_red[2 * (kWG / 64)];
+  __shared__ double s_red[3 * (kWG / 64)];
   __shared__ int s_last;
   extern __shared__ __align__(16) unsigned char s_dyn[];
   T* s_stage = reinterpret_cast<T*>(s_dyn);                         // [cap] values
@@ -262,11 +262,13 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
   rt.lds = reinterpret_cast<T*>(s_dyn + res_offset(M == kDelayed ? a.cap : 0u, sizeof(T)));
   rt.res = a.res;
   rt.n = a.g.n;
-  if (rt.res) rt.fill(rc, tid);
+  // Graph sets: a worker of a graph that already met tol has nothing to do.
+  const bool frozen = a.wseg && a.gsweeps[a.wgraph[w]] != 0;
+  if (rt.res && !frozen) rt.fill(rc, tid);
 
-  double r_loc = 0.0, nd_loc = 0.0;
+  double r_loc = 0.0, nd_loc = 0.0, m_loc = 0.0;
   const const_u32p tile_v = as_const(a.g.tile_v);
-  const uint32_t t0 = as_const(a.g.work_t)[w], t1 = as_const(a.g.work_t)[w + 1];
+  const uint32_t t0 = as_const(a.g.work_t)[w], t1 = frozen ? t0 : as_const(a.g.work_t)[w + 1];
   const uint32_t n = a.g.n;
   uint32_t staged = 0;
   const uint32_t bv0 = tile_v[t0], bv1 = tile_v[t1];  // this worker's vertex block
@@ -393,6 +395,7 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
       // stored old value (in float64 both are the same value).
       r_loc += fabs(xn - (double)xo);
       if (dg != 0) nd_loc += xn;
+      m_loc += xn;
       if constexpr (M == kSync) {
         cout[p] = cn;
       } else if constexpr (M == kAsync) {
@@ -431,14 +434,19 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
   // Worker partials, then the last worker folds them in worker order.
   r_loc = wave_sum(r_loc);
   nd_loc = wave_sum(nd_loc);
+  m_loc = wave_sum(m_loc);
   if (lane == 0) {
     s_red[wv] = r_loc;
     s_red[4 + wv] = nd_loc;
+    s_red[8 + wv] = m_loc;
   }
   __syncthreads();
   if (tid == 0) {
     a.st.part[w] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
-    a.st.part[P + w] = s_red[4] + s_red[5] + s_red[6] + s_red[7];
+    if (!frozen) {
+      a.st.part[P + w] = s_red[4] + s_red[5] + s_red[6] + s_red[7];
+      a.st.part[2 * P + w] = s_red[8] + s_red[9] + s_red[10] + s_red[11];
+    }
     __threadfence();
     const uint32_t prev = atomicAdd(&a.st.count[k], 1u);
     s_last = (prev == P - 1);
@@ -446,12 +454,36 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
   __syncthreads();
   if (s_last) {
     __threadfence();
+    auto part = [&](uint32_t i) {
+      return __hip_atomic_load(a.st.part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
     double r = 0.0, dd = 0.0;
-    for (uint32_t i = tid; i < P; i += kWG) {
-      r += __hip_atomic_load(a.st.part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      dd += __hip_atomic_load(a.st.part + P + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!a.wseg) {
+      for (uint32_t i = tid; i < P; i += kWG) r += part(i);
+    } else {
+      // Graph sets: each graph's change relative to its own mass (its L1
+      // change once normalised); the sweep's value is the largest of them.
+      for (uint32_t gi = tid; gi < a.G; gi += kWG) {
+        double rg = 0.0, mg = 0.0;
+        for (uint32_t i = a.wseg[gi]; i < a.wseg[gi + 1]; ++i) {
+          rg += part(i);
+          mg += part(2 * P + i);
+        }
+        const double q = rg / mg;
+        r = q > r ? q : r;
+        if (q < a.tol && a.gsweeps[gi] == 0) a.gsweeps[gi] = k + 1;
+      }
     }
-    r = wave_sum(r);
+    for (uint32_t i = tid; i < P; i += kWG) dd += part(P + i);
+    if (!a.wseg) {
+      r = wave_sum(r);
+    } else {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double t = __shfl_xor(r, o, 64);
+        r = t > r ? t : r;
+      }
+    }
     dd = wave_sum(dd);
     if (lane == 0) {
       s_red[wv] = r;
@@ -459,7 +491,8 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
     }
     __syncthreads();
     if (tid == 0) {
-      a.st.resid[k + 1] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+      a.st.resid[k + 1] = !a.wseg ? s_red[0] + s_red[1] + s_red[2] + s_red[3]
+                                  : fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3]));
       a.st.dang[k + 1] = 1.0 - (s_red[4] + s_red[5] + s_red[6] + s_red[7]);
     }
   }
