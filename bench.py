@@ -500,7 +500,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "n": n, "m": m,
                    "step": f"PageRank f32 delayed d={args.d} tol 1e-6 damping 0.85 + SSSP delayed d={args.d} "
-                           "from one of 16 sources (u32 weights)",
+                           "from one of 16 sources (weights in [1, 255], stored as bytes)",
                    "pagerank_sweeps": pr_sweeps, "sssp_sweeps": bf_sweeps, "workers": info.workers,
                    "tiles": info.tiles},
         "roofline": roofline,
