@@ -452,9 +452,14 @@ dg_status dg_set_pagerank(dg_set* s, double damping, double tol, dg_mode mode, u
                           uint32_t* out_sweeps, dg_stats* stats, void* hip_stream);
 
 /* Bellman-Ford of every graph from its own source (as dg_sssp, per graph).
+ * All graphs are swept together; a graph whose sweep changed no distance is
+ * final (no edge crosses two graphs) and is not swept again.
  *   sources     host array of `graphs` vertex ids, local to each graph
  *   flags       0 (reserved)
- *   out_dist    n uint32 over the union, DG_INF_DIST where unreachable */
+ *   out_dist    n uint32 over the union, DG_INF_DIST where unreachable
+ *   out_sweeps  host array of `graphs` entries or NULL: for each graph the
+ *               first sweep in which it changed no distance (0 = none within
+ *               max_sweeps) */
 dg_status dg_set_sssp(dg_set* s, const uint32_t* sources, dg_mode mode, uint32_t d, uint32_t max_sweeps,
                       uint32_t flags, uint32_t* out_dist, int out_on_device, uint32_t* out_sweeps,
                       dg_stats* stats, void* hip_stream);

@@ -730,6 +730,11 @@ dg_status sssp_run(dg_graph* g, uint32_t src, const uint32_t* more_src, uint32_t
   a.cap = cap;
   a.res = nres;
   a.shadow = use_shadow ? static_cast<uint32_t*>(g->vals[2]) : nullptr;
+  a.wseg = g->G ? g->wseg : nullptr;
+  a.wgraph = g->wgraph;
+  a.G = g->G;
+  a.gsweeps = g->gsweeps;
+  if (g->G) DG_HIP(launch_fill_u32(g->gsweeps, g->G, 0u, s));
   auto launch = [&](uint32_t k) {
     if (mode == DG_SYNC) {
       a.din = (k & 1) ? b1 : b0;

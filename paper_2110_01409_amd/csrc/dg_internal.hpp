@@ -106,6 +106,13 @@ struct BfArgs {
   uint32_t d;
   uint32_t cap;
   uint32_t res;  // as PrArgs::res
+  // Graph sets, as in PrArgs: gsweeps[i] records the first sweep in which
+  // graph i changed no distance (its distances are final then: no edge
+  // crosses two graphs), and its workers skip their blocks from then on.
+  const uint32_t* wseg;
+  const uint32_t* wgraph;
+  uint32_t G;
+  uint32_t* gsweeps;
 };
 
 // Batched queries (64 per batch, vertex-major [slot][64] values).

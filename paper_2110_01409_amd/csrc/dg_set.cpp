@@ -57,13 +57,9 @@ dg_status set_check_mode(dg_mode mode, uint32_t d, uint32_t max_sweeps) {
   return DG_OK;
 }
 
-void per_graph(const dg_set* s, const dg_stats& st, bool conv, uint32_t* out_sweeps) {
-  if (!out_sweeps) return;
-  for (uint32_t i = 0; i < s->G; ++i) out_sweeps[i] = conv ? st.sweeps : 0u;
-}
-
-// PageRank: the first sweep that took each graph below tol (0: never).
-dg_status per_graph_pagerank(const dg_set* s, uint32_t* out_sweeps, hipStream_t q) {
+// The first sweep that took each graph below tol (PageRank) or in which it
+// changed no distance (Bellman-Ford); 0: none within max_sweeps.
+dg_status per_graph_sweeps(const dg_set* s, uint32_t* out_sweeps, hipStream_t q) {
   if (!out_sweeps) return DG_OK;
   DG_HIP(hipMemcpyAsync(out_sweeps, s->g->gsweeps, (size_t)s->G * 4, hipMemcpyDeviceToHost, q));
   DG_HIP(hipStreamSynchronize(q));
@@ -219,7 +215,7 @@ dg_status dg_set_pagerank(dg_set* s, double damping, double tol, dg_mode mode, u
     (void)hipGetLastError();
     return fail(DG_ERR_DEVICE, "set normalisation failed: %s", hipGetErrorString(he));
   }
-  const dg_status ps = per_graph_pagerank(s, out_sweeps, q);
+  const dg_status ps = per_graph_sweeps(s, out_sweeps, q);
   if (ps != DG_OK) return ps;
   if (stats) *stats = x;
   if (run != DG_OK) return fail(run, "the set did not converge within %u sweeps", max_sweeps);
@@ -246,7 +242,8 @@ dg_status dg_set_sssp(dg_set* s, const uint32_t* sources, dg_mode mode, uint32_t
   st = dg::host::sssp_run(s->g, usrc[0], s->src_d, s->G - 1, mode, d, max_sweeps, out_dist, out_on_device, &x,
                           hip_stream);
   if (st != DG_OK && st != DG_ERR_NOT_CONVERGED) return st;
-  per_graph(s, x, st == DG_OK, out_sweeps);
+  const dg_status ps = per_graph_sweeps(s, out_sweeps, q);
+  if (ps != DG_OK) return ps;
   if (stats) *stats = x;
   return st;
 }

@@ -465,9 +465,20 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
       // change once normalised); the sweep's value is the largest of them.
       for (uint32_t gi = tid; gi < a.G; gi += kWG) {
         double rg = 0.0, mg = 0.0;
-        for (uint32_t i = a.wseg[gi]; i < a.wseg[gi + 1]; ++i) {
-          rg += part(i);
-          mg += part(2 * P + i);
+        const uint32_t i1 = a.wseg[gi + 1];
+        for (uint32_t i = a.wseg[gi]; i < i1; i += 8) {
+          // eight loads in flight, then the sums in worker order
+          double vr[8], vm[8];
+#pragma unroll
+          for (uint32_t j = 0; j < 8; ++j) {
+            vr[j] = i + j < i1 ? part(i + j) : 0.0;
+            vm[j] = i + j < i1 ? part(2 * P + i + j) : 0.0;
+          }
+#pragma unroll
+          for (uint32_t j = 0; j < 8; ++j) {
+            rg += vr[j];
+            mg += vm[j];
+          }
         }
         const double q = rg / mg;
         r = q > r ? q : r;
@@ -542,7 +553,9 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
   uint32_t* dout = a.dout;
   const rsrc_t rd = make_rsrc(din, (a.g.n + a.g.K) * 4u);
   const const_u32p tile_v = as_const(a.g.tile_v);
-  const uint32_t t0 = as_const(a.g.work_t)[w], t1 = as_const(a.g.work_t)[w + 1];
+  // Graph sets: a worker of a graph that already settled has nothing to do.
+  const bool frozen = a.wseg && a.gsweeps[a.wgraph[w]] != 0;
+  const uint32_t t0 = as_const(a.g.work_t)[w], t1 = frozen ? t0 : as_const(a.g.work_t)[w + 1];
   const uint32_t n = a.g.n;
   uint32_t staged = 0;
   int any = 0;
@@ -550,7 +563,7 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
   rt.lds = reinterpret_cast<uint32_t*>(s_dyn + res_offset(M == kDelayed ? a.cap : 0u, 4u));
   rt.res = a.res;
   rt.n = n;
-  if (rt.res) rt.fill(rd, tid);
+  if (rt.res && !frozen) rt.fill(rd, tid);
   const uint32_t bv0 = tile_v[t0], bv1 = tile_v[t1];  // this worker's vertex block
 
   uint32_t v0 = tile_v[t0];
@@ -684,7 +697,39 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
     }
     v0 = v1;
   }
-  if (__syncthreads_or(any) && tid == 0) st_agent(a.st.changed + k + 1, 1u);
+  const int anyb = __syncthreads_or(any);
+  if (!a.wseg) {
+    if (anyb && tid == 0) st_agent(a.st.changed + k + 1, 1u);
+    return;
+  }
+  // Graph sets: per-worker change flags; the last worker folds them per
+  // graph, records the graphs that settled, and flags the sweep if any
+  // graph changed.
+  __shared__ int s_last;
+  if (tid == 0) {
+    a.st.part[w] = anyb ? 1.0 : 0.0;
+    __threadfence();
+    s_last = atomicAdd(&a.st.count[k], 1u) == a.g.P - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  int ch_any = 0;
+  for (uint32_t gi = tid; gi < a.G; gi += kWG) {
+    int ch = 0;
+    const uint32_t i1 = a.wseg[gi + 1];
+    for (uint32_t i = a.wseg[gi]; i < i1; i += 8) {
+      double v[8];  // eight loads in flight
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j)
+        v[j] = i + j < i1 ? __hip_atomic_load(a.st.part + i + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+#pragma unroll
+      for (uint32_t j = 0; j < 8; ++j) ch |= v[j] != 0.0;
+    }
+    if (!ch && a.gsweeps[gi] == 0) a.gsweeps[gi] = k + 1;
+    ch_any |= ch;
+  }
+  if (__syncthreads_or(ch_any) && tid == 0) st_agent(a.st.changed + k + 1, 1u);
 }
 
 __global__ __launch_bounds__(kWG) void bf_init_kernel(uint32_t* d0, uint32_t* d1, const uint32_t* cpos, uint32_t n,
