@@ -132,3 +132,32 @@ def test_union_validation(dg, graphs):
     with pytest.raises(dg.DGError):
         S.pagerank(damping=1.0)
     S.close()
+
+
+def test_union_more_graphs_than_workers(dg):
+    """2000 tiny graphs (1 to 6 vertices, some edgeless): more graphs than the
+    default 1280 workers, so every graph still gets a worker of its own.
+    SSSP bit-exact with the oracle's per-graph sweep counts in synchronous
+    mode; PageRank within the stopping rule's bound for every graph."""
+    rng = np.random.default_rng(2000)
+    graphs = []
+    for i in range(2000):
+        n = int(rng.integers(1, 7))
+        m = int(rng.integers(0, 3 * n + 1))
+        graphs.append(tg.random_graph(n, m, 3000 + i, dedup=False))
+    S = dg.GraphSet(graphs)
+    info = S.info()
+    assert info.graphs == 2000 and info.workers >= 2000
+    sources = np.array([int(rng.integers(0, g.n)) for g in graphs], np.uint32)
+    refs = [osp.bellman_ford_sync(g, int(s))[:2] for g, s in zip(graphs, sources)]
+    for mode, d in (("sync", 1), ("async", 1), ("delayed", 64)):
+        out, sw, st = S.sssp(sources, mode=mode, d=d)
+        for part, (ref, _) in zip(S.split(out.cpu().numpy()), refs):
+            np.testing.assert_array_equal(part, ref)
+        if mode == "sync":
+            np.testing.assert_array_equal(sw, [r[1] for r in refs])
+    out, sw, st = S.pagerank(tol=1e-9, mode="delayed", d=64, dtype="f64")
+    for part, g in zip(S.split(out.cpu().numpy()), graphs):
+        assert float(np.abs(part - opr.pagerank_fixed_point(g)).sum()) <= 1e-8, g.name
+    assert (sw >= 1).all() and sw.max() == st.sweeps
+    S.close()
