@@ -128,7 +128,7 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
   if (tid == 0) s_any = 0;
   if (tid < kQ) s_lane[tid] = 0;
   __syncthreads();
-  uint32_t any = 0, staged = 0;
+  uint32_t any = 0, staged = 0, t_first = t0;  // t_first: first tile staged since the last commit
 
   for (uint32_t t = t0; t < t1; ++t) {
     const uint32_t v0 = tile_v[t], v1 = tile_v[t + 1], nv = v1 - v0;
@@ -164,10 +164,17 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
     if constexpr (M == kDelayed) {
       staged += nv;
       if (t + 1 == t1 || staged >= a.d) {
-        __syncthreads();  // the shadow rows of the whole buffer are written
-        for (uint32_t v = v1 - staged + wv; v < v1; v += kWG / 64)
-          st_q(dout + (size_t)a.g.cpos[v] * kQ + lane, shadow[(size_t)v * kQ + lane]);
+        // Each wavefront commits the rows it staged itself (a tile's vertex v
+        // is wavefront (v - v0) % 4's, a hub wavefront 0's): its own stores
+        // precede its loads, so no workgroup barrier is needed.
+        for (uint32_t tt = t_first; tt <= t; ++tt) {
+          const uint32_t a0 = tile_v[tt], a1 = tile_v[tt + 1];
+          const uint32_t first = a1 - a0 == 1 ? (wv == 0 ? a0 : a1) : a0 + wv;
+          for (uint32_t v = first; v < a1; v += kWG / 64)
+            st_q(dout + (size_t)a.g.cpos[v] * kQ + lane, shadow[(size_t)v * kQ + lane]);
+        }
         staged = 0;
+        t_first = t + 1;
       }
     }
   }
@@ -261,7 +268,7 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
   const cu32p in_ptr = cst(a.g.in_ptr);
   const uint32_t t0 = cst(a.g.work_t)[w], t1 = cst(a.g.work_t)[w + 1];
   double r_loc = 0.0, dm_loc = 0.0, m_loc = 0.0;
-  uint32_t staged = 0;
+  uint32_t staged = 0, t_first = t0;  // t_first: first tile staged since the last commit
 
   auto update = [&](uint32_t v, double acc) {
     if (!live) return;
@@ -294,11 +301,17 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
     if constexpr (M == kDelayed) {
       staged += nv;
       if (t + 1 == t1 || staged >= a.d) {
-        __syncthreads();
-        if (live)
-          for (uint32_t v = v1 - staged + wv; v < v1; v += kWG / 64)
-            st_q(cout + (size_t)a.g.cpos[v] * kQ + lane, shadow[(size_t)v * kQ + lane]);
+        // each wavefront commits the rows it staged itself (as in the SSSP kernel)
+        if (live) {
+          for (uint32_t tt = t_first; tt <= t; ++tt) {
+            const uint32_t a0 = tile_v[tt], a1 = tile_v[tt + 1];
+            const uint32_t first = a1 - a0 == 1 ? (wv == 0 ? a0 : a1) : a0 + wv;
+            for (uint32_t v = first; v < a1; v += kWG / 64)
+              st_q(cout + (size_t)a.g.cpos[v] * kQ + lane, shadow[(size_t)v * kQ + lane]);
+          }
+        }
         staged = 0;
+        t_first = t + 1;
       }
     }
   }
