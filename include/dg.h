@@ -411,7 +411,10 @@ typedef struct {
 } dg_graph_desc;
 
 typedef struct {
-  uint32_t workers;  /* workgroups per sweep; 0 = 5 per compute unit */
+  uint32_t workers;  /* workgroups per sweep; 0 = 5 per compute unit.  Every
+                        graph gets at least one worker of its own (so a set
+                        of more graphs than this uses one per graph), the
+                        rest go to graphs in proportion to their edges. */
 } dg_set_opts;
 
 typedef struct {
@@ -426,7 +429,8 @@ typedef struct {
 
 
 /* Builds and uploads a set of `count` graphs (host CSR arrays; copied, not
- * retained).  Limits: total vertices < 2^31, total edges < 2^32 - 2^12. */
+ * retained) as one union graph whose tiles and worker blocks never cross a
+ * graph boundary.  Limits: total vertices < 2^31, total edges < 2^32 - 2^12. */
 dg_status dg_set_create(uint32_t count, const dg_graph_desc* graphs, const dg_set_opts* opts, void* hip_stream,
                         dg_set** out);
 dg_status dg_set_destroy(dg_set* s);
