@@ -414,7 +414,8 @@ typedef struct {
   uint32_t workers;  /* workgroups per sweep; 0 = 5 per compute unit.  Every
                         graph gets at least one worker of its own (so a set
                         of more graphs than this uses one per graph), the
-                        rest go to graphs in proportion to their edges. */
+                        rest go to graphs by their sweep cost (in-edges plus
+                        per-vertex and per-tile terms). */
 } dg_set_opts;
 
 typedef struct {
