@@ -138,16 +138,16 @@ dg_status dg_set_allocator(dg_alloc_fn alloc, dg_free_fn free_fn, void* ctx);
  *                 at most this many of the compact region's sources, those
  *                 with the largest out-degree, are also read from a copy in
  *                 each workgroup's LDS (the resident table) instead of being
- *                 gathered; at most 6144 (a float64 sweep uses the first
- *                 3072).  DG_RESIDENT_AUTO = 6144 if those cover at least 1/16
- *                 of the in-edges, else 0; 0 = no table.  A read of a
+ *                 gathered; at most 32768 (a float64 sweep uses the first
+ *                 16384).  DG_RESIDENT_AUTO = 32768 if those cover at least
+ *                 1/16 of the in-edges, else 0; 0 = no table.  A read of a
  *                 resident source returns, in
  *                   DG_SYNC     the value of the previous sweep, exactly as a
  *                               gather would;
  *                   DG_ASYNC, DG_DELAYED, DG_DELAYED_LOCAL
  *                               a value read from the global array at most
- *                               three tiles of the reader earlier (the table
- *                               is refreshed a third at a time after each
+ *                               four tiles of the reader earlier (the table
+ *                               is refreshed a quarter at a time after each
  *                               tile), instead of at the moment of the read.
  *                 Results converge to the same fixed point / distances. */
 #define DG_HOT_AUTO 0xFFFFFFFFu

@@ -61,6 +61,8 @@ void current_allocator(dg_alloc_fn& alloc, dg_free_fn& free_fn, void*& ctx) {
 using dg::host::kMaxSweeps;
 using dg::host::kSweepChunk;
 using dg::host::kWorkersPerCU;
+using dg::host::kBatchWorkersPerCU;
+using dg::host::topo_batch;
 using dg::host::build_layout;
 using dg::host::build_workers;
 using dg::host::build_workers_seg;
@@ -111,6 +113,13 @@ Topology topo(const dg_graph* g) {
   t.n = g->n;
   t.K = g->K;
   t.P = g->P;
+  return t;
+}
+
+Topology topo_batch(const dg_graph* g) {
+  Topology t = topo(g);
+  t.work_t = g->work_tb;
+  t.P = g->Pb;
   return t;
 }
 
@@ -210,12 +219,12 @@ uint32_t resident(const dg_graph* g, size_t elem) {
 // Staging for a commit interval d.  LDS holds d values plus one more tile
 // (each staged vertex keeps its value and the 4-byte slot it is committed
 // to) when that fits next to the resident table (res values) and the
-// kernel's static LDS in kLdsBudget, which keeps five workgroups per compute
-// unit, and in at most 16 KB; larger intervals stage in a global per-vertex
-// shadow array.  Returns the LDS capacity (0 = global shadow) and the
+// kernel's static LDS in kLdsBudget (the compute unit's LDS, which one sweep
+// workgroup fills), and in at most 16 KB; larger intervals stage in a global
+// per-vertex shadow array.  Returns the LDS capacity (0 = global shadow) and the
 // effective interval.
 constexpr size_t kLdsStage = 16 * 1024;
-constexpr size_t kStaticLds = 4 * 1024;  // bound on the sweep kernels' static LDS
+constexpr size_t kStaticLds = 14 * 1024;  // bound on the sweep kernels' static LDS
 void staging(const dg_graph* g, uint32_t d, size_t elem, uint32_t res, uint32_t& cap, uint32_t& d_eff,
              bool& shadow) {
   d_eff = std::min(d, g->max_block_v);
@@ -445,7 +454,7 @@ dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
   }
   g->cus = (uint32_t)cus;
   g->lds_per_block = (size_t)lds;
-  uint32_t P = plan_workers(L, opts ? opts->workers : 0u, g->cus);
+  uint32_t P = plan_workers(L, opts ? opts->workers : 0u, g->cus, kWorkersPerCU);
   std::vector<uint32_t> work_t;
   if (seg_v) {
     g->G = (uint32_t)seg_v->size() - 1;
@@ -461,6 +470,11 @@ dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
   g->P = P;
   for (uint32_t wk = 0; wk < P; ++wk)
     g->max_block_v = std::max(g->max_block_v, L.tile_v[work_t[wk + 1]] - L.tile_v[work_t[wk]]);
+  std::vector<uint32_t> work_tb;
+  g->Pb = plan_workers(L, 0u, g->cus, kBatchWorkersPerCU);
+  build_workers(L.tile_v, L.tile_e0, g->Pb, work_tb);
+  for (uint32_t wk = 0; wk < g->Pb; ++wk)
+    g->max_block_vb = std::max(g->max_block_vb, L.tile_v[work_tb[wk + 1]] - L.tile_v[work_tb[wk]]);
 
   uint32_t* w8_words = nullptr;
   struct Up {
@@ -468,7 +482,7 @@ dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
     const std::vector<uint32_t>* src;
   } ups[] = {{&g->in_ptr, &L.in_ptr}, {&g->in_src, &L.in_src}, {&g->in_w, &L.in_w}, {&w8_words, &L.w8pack},
              {&g->out_deg, &L.out_deg}, {&g->cpos, &L.cpos}, {&g->tile_v, &L.tile_v}, {&g->work_t, &work_t},
-             {&g->wseg, &g->wseg_h}, {&g->wgraph, &g->wgraph_h}};
+             {&g->wseg, &g->wseg_h}, {&g->wgraph, &g->wgraph_h}, {&g->work_tb, &work_tb}};
   for (auto& u : ups) {
     if (u.src->empty()) continue;
     const size_t bytes = u.src->size() * sizeof(uint32_t);
@@ -834,10 +848,10 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
   DG_HIP(launch_mbf_init(b0, b1, g->cpos, srcd, k, g->n, g->K, NB, s));
   MbfArgs a;
   std::memset(&a, 0, sizeof a);  // call mode: no serving fields
-  a.g = topo(g);
+  a.g = topo_batch(g);
   a.changed = changed;
   a.shadow = sh;
-  a.d = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_v)) : 0u;
+  a.d = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_vb)) : 0u;
   a.NB = NB;
   auto launch = [&](uint32_t kk) {
     if (mode == DG_SYNC) {
@@ -893,7 +907,7 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
       qe += (uint64_t)(bsweeps[b] ? bsweeps[b] : sweeps) * nq;
     }
     stats->sweeps = sweeps;
-    stats->workers = g->P;
+    stats->workers = g->Pb;
     stats->tile_vertices = kTileV;
     stats->commit_interval = mode == DG_DELAYED ? a.d : 0;
     stats->residual = 0.0;
@@ -931,7 +945,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   double* dang = static_cast<double*>(al.get((size_t)2 * NB * kBatchQ * 8, s));
   double* scale = static_cast<double*>(al.get((size_t)2 * NB * kBatchQ * 8, s));
   uint32_t* qdone = static_cast<uint32_t*>(al.get((size_t)NB * kBatchQ * 4, s));
-  double* part = static_cast<double*>(al.get((size_t)g->P * NB * 3 * kBatchQ * 8, s));
+  double* part = static_cast<double*>(al.get((size_t)g->Pb * NB * 3 * kBatchQ * 8, s));
   double* qsum = static_cast<double*>(al.get((size_t)NB * kBatchQ * 8, s));
   double* qpart = static_cast<double*>(al.get((size_t)NB * 256 * kBatchQ * 8, s));
   double* outd = out_on_device ? out_scores : static_cast<double*>(al.get((size_t)k * g->n * 8, s));
@@ -952,7 +966,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   DG_HIP(launch_mppr_init(f64, x, c0, c1, g->out_deg, g->cpos, srcd, k, g->n, g->K, NB, dang, s));
   MpprArgs a;
   std::memset(&a, 0, sizeof a);  // call mode: no serving fields
-  a.g = topo(g);
+  a.g = topo_batch(g);
   a.x = x;
   a.shadow = sh;
   a.src = srcd;
@@ -965,7 +979,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   a.alpha = damping;
   a.tol = tol;
   a.nq = k;
-  a.d = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_v)) : 0u;
+  a.d = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_vb)) : 0u;
   a.NB = NB;
   auto launch = [&](uint32_t kk) {
     if (mode == DG_SYNC) {
@@ -1009,7 +1023,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
       qe += (uint64_t)(bsweeps[b] ? bsweeps[b] : sweeps) * nq;
     }
     stats->sweeps = sweeps;
-    stats->workers = g->P;
+    stats->workers = g->Pb;
     stats->tile_vertices = kTileV;
     stats->commit_interval = mode == DG_DELAYED ? a.d : 0;
     stats->residual = last_r;
@@ -1115,7 +1129,7 @@ dg_status dg_tune(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, uint32_
   if (keep) {
     Ps.push_back(g->P);
   } else {
-    for (uint32_t per_cu : {2u, 3u, 4u, 5u, 6u, 8u}) {
+    for (uint32_t per_cu : {1u, 2u, 3u, 4u}) {
       const uint32_t P = default_workers(g, per_cu);
       if (std::find(Ps.begin(), Ps.end(), P) == Ps.end()) Ps.push_back(P);
     }

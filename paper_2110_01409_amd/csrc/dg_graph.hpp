@@ -18,9 +18,12 @@ namespace host {
 // first tests on the device whether an earlier one met the stopping rule.
 constexpr uint32_t kSweepChunk = 8;
 constexpr uint32_t kMaxSweeps = 1000000;
-// Default persistent workgroups per compute unit.  Five measured faster than
-// eight on RMAT and banded graphs (fewer concurrent gather streams per CU).
-constexpr uint32_t kWorkersPerCU = 5;
+// Default persistent workgroups per compute unit of the single-query sweeps:
+// one 1024-thread workgroup, whose LDS holds the resident table.
+constexpr uint32_t kWorkersPerCU = 1;
+// The same for the batched kernels (256 threads, no table).  Five measured
+// faster than eight on RMAT and banded graphs.
+constexpr uint32_t kBatchWorkersPerCU = 5;
 
 }  // namespace host
 }  // namespace dg
@@ -32,6 +35,9 @@ struct dg_graph {
   uint32_t P = 0, T = 0, cus = 0, max_in_deg = 0, n_dangling = 0;
   uint32_t K = 0;          // sources stored in the compact region
   uint32_t max_block_v = 1;  // most vertices any worker owns
+  // Partition of the same tiles for the batched kernels (dg_sssp_batch,
+  // dg_ppr_batch, the server): Pb workers, most vertices per block.
+  uint32_t Pb = 0, max_block_vb = 1;
   std::vector<uint32_t> tile_v_h, tile_e0_h;  // host copies: first vertex / first in-edge of each tile
   uint64_t hash = 0;                         // content hash of the in-edge form (tuning cache key)
   // Graph sets: the union of G graphs, with worker blocks aligned to graph
@@ -58,6 +64,7 @@ struct dg_graph {
   uint32_t *in_ptr = nullptr, *in_src = nullptr, *in_w = nullptr, *out_deg = nullptr, *cpos = nullptr;
   uint8_t* in_w8 = nullptr;  // weights as bytes when all are <= 255 (then in_w is null)
   uint32_t *tile_v = nullptr, *work_t = nullptr;
+  uint32_t* work_tb = nullptr;  // [Pb+1] first tile of each batched worker
   // workspace (grown on demand)
   void* vals[3] = {nullptr, nullptr, nullptr};  // 8(n+K) bytes each
   double* norm = nullptr;                        // kNormBlocks + 1
@@ -78,8 +85,10 @@ namespace host {
 // the graph).
 void* dev_alloc(dg_graph* g, size_t bytes, hipStream_t s);
 void dev_free(dg_graph* g, void* p);
-// Device arrays of the resident graph as passed to the kernels.
+// Device arrays of the resident graph as passed to the single-query sweep
+// kernels (P workers), and to the batched kernels (Pb workers).
 Topology topo(const dg_graph* g);
+Topology topo_batch(const dg_graph* g);
 // dg_graph_create for the union graph of a set: seg_v[G+1] are the first
 // vertices of the G graphs.  Tiles never cross a graph boundary and every
 // graph gets its own worker blocks (at least one).

@@ -8,14 +8,18 @@
 
 namespace dg {
 
-// Workgroup shape of every sweep kernel: 4 wave64s.
+// Workgroup of the streaming, batched, set and instrumentation kernels: 4 wave64s.
 constexpr int kWG = 256;
+// Workgroup of the single-query sweep kernels: 16 wave64s, one workgroup per
+// compute unit, so that one LDS copy of the hottest sources (the resident
+// table) can take most of the unit's 160 KB.
+constexpr int kSweepWG = 1024;
 // Consecutive in-edges one thread reduces per chunk (two 16-byte index loads).
 constexpr int kEPT = 8;
-// Edge slots a workgroup covers per chunk.
-constexpr int kChunk = kWG * kEPT;
+// Edge slots a sweep workgroup covers per chunk.
+constexpr int kChunk = kSweepWG * kEPT;
 // At most this many vertices per tile: one vertex per thread in the update phase.
-constexpr int kTileV = kWG;
+constexpr int kTileV = kSweepWG;
 // Edge budget of a multi-vertex tile.  A chunk starts at the tile's first
 // edge rounded down to a multiple of 4 (16-byte aligned vector loads), so a
 // tile of at most kChunk-4 edges always fits one chunk.  A single vertex with
@@ -27,13 +31,16 @@ constexpr uint32_t kEdgePad = kChunk + 16;
 
 constexpr uint32_t kInf = 0xFFFFFFFFu;
 
-// LDS of a sweep workgroup: five workgroups share a compute unit's 160 KB.
-constexpr uint32_t kLdsBudget = 32 * 1024;
+// LDS of a sweep workgroup: the whole compute unit's 160 KB.
+constexpr uint32_t kLdsBudget = 160 * 1024;
 // Resident table: LDS copy of the first slots of the compact region (the
 // sources with the largest out-degree), read instead of gathering them.
-constexpr uint32_t kResBytes = 24 * 1024;
+constexpr uint32_t kResBytes = 128 * 1024;
 // Bytes of the table refreshed at once (8 registers per thread).
-constexpr uint32_t kResSegBytes = kWG * 8 * 4;
+constexpr uint32_t kResSegBytes = kSweepWG * 8 * 4;
+// Dynamic LDS a sweep kernel may request (the rest of 160 KB after its
+// static LDS, which stays under 14 KB).
+constexpr uint32_t kSweepDynLds = 146 * 1024;
 
 // Commit modes; kDelayedLocal is delayed commits with local reads of a
 // worker's own staged values (single-query sweeps only).

@@ -242,8 +242,8 @@ dg_status build_layout(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
   return DG_OK;
 }
 
-uint32_t plan_workers(const Layout& L, uint32_t want_workers, uint32_t cus) {
-  uint32_t P = want_workers ? want_workers : cus * kWorkersPerCU;
+uint32_t plan_workers(const Layout& L, uint32_t want_workers, uint32_t cus, uint32_t per_cu) {
+  uint32_t P = want_workers ? want_workers : cus * per_cu;
   P = std::max(1u, std::min(P, L.T()));
   if (P > 8 && !want_workers) P &= ~7u;
   return P;
@@ -276,7 +276,7 @@ dg_status dg_plan_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_
     delete p;
     return st;
   }
-  p->P = dg::host::plan_workers(p->L, opts ? opts->workers : 0u, compute_units);
+  p->P = dg::host::plan_workers(p->L, opts ? opts->workers : 0u, compute_units, dg::host::kWorkersPerCU);
   try {
     dg::host::build_workers(p->L.tile_v, p->L.tile_e0, p->P, p->work_t);
   } catch (const std::bad_alloc&) {

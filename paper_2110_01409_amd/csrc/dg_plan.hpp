@@ -47,10 +47,10 @@ dg_status build_layout(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
                        const uint32_t* w, const dg_graph_opts* opts, Layout& L,
                        const std::vector<uint32_t>* seg_v = nullptr);
 
-// Worker count for a device of `cus` compute units: opts->workers if set,
-// else 5 per compute unit rounded down to a multiple of 8; never more than
-// the tiles.
-uint32_t plan_workers(const Layout& L, uint32_t want_workers, uint32_t cus);
+// Worker count for a device of `cus` compute units: want_workers if set,
+// else per_cu per compute unit rounded down to a multiple of 8; never more
+// than the tiles.
+uint32_t plan_workers(const Layout& L, uint32_t want_workers, uint32_t cus, uint32_t per_cu);
 
 // Contiguous tile ranges of P workers balanced by 256 + in-edges + 4 x
 // vertices per tile; work_t[P+1].

@@ -27,6 +27,7 @@ using dg::host::dev_free;
 using dg::host::fail;
 using dg::host::g_last_error;
 using dg::host::topo;
+using dg::host::topo_batch;
 
 namespace {
 
@@ -92,7 +93,7 @@ size_t batch_bytes(const dg_server* s, const dg_graph* g, int kind) {
     return (slots * (sync ? 2 : 1) + (del ? n : 0)) * kLanes * 4 + kLanes * 8 + 16;
   const size_t e = f64(s) ? 8 : 4;
   return (n + slots * (sync ? 2 : 1) + (del ? n : 0)) * kLanes * e + kLanes * (4 + 4 + 4 * 8 + 4) +
-         (size_t)g->P * 3 * kLanes * 8 + 16;
+         (size_t)g->Pb * 3 * kLanes * 8 + 16;
 }
 
 void free_pool(Pool& p) {
@@ -177,7 +178,7 @@ dg_status resize(dg_server* s, Pool& p, uint32_t NBn) {
     if ((st = reshape_ring(p, p.dang, kLanes * 8, NBn)) != DG_OK) return st;
     if ((st = reshape_ring(p, p.scale, kLanes * 8, NBn)) != DG_OK) return st;
     if ((st = reshape_ring(p, p.count, 4, NBn)) != DG_OK) return st;
-    if ((st = reshape(p, p.part, (size_t)g->P * 3 * kLanes * 8, NBn, false)) != DG_OK) return st;
+    if ((st = reshape(p, p.part, (size_t)g->Pb * 3 * kLanes * 8, NBn, false)) != DG_OK) return st;
     // new batches: lanes frozen and unassigned
     for (uint32_t b = p.NB; b < NBn; ++b) {
       DG_HIP(launch_fill_u32(p.qdone + (size_t)b * kLanes, kLanes, 1u, p.st));
@@ -259,7 +260,7 @@ dg_status pool_sweep(dg_server* s, Pool& p, bool& ran) {
     if (p.lane_req[i] >= 0) active[i / kLanes] = 1, any = true;
   if (!any) return DG_OK;
   hipStream_t q = p.st;
-  const Topology t = topo(g);
+  const Topology t = topo_batch(g);
   if (!blist.empty()) {
     lane_src.resize((size_t)p.NB * kLanes, kNone);
     DG_HIP(hipMemcpyAsync(p.lane_src, lane_src.data(), lane_src.size() * 4, hipMemcpyHostToDevice, q));
@@ -283,7 +284,7 @@ dg_status pool_sweep(dg_server* s, Pool& p, bool& ran) {
     a.lchg = p.lchg;
     a.bactive = p.bactive;
     a.k = p.k;
-    a.d = s->o.mode == DG_DELAYED ? std::max(1u, std::min(s->o.d, g->max_block_v)) : 0u;
+    a.d = s->o.mode == DG_DELAYED ? std::max(1u, std::min(s->o.d, g->max_block_vb)) : 0u;
     a.NB = p.NB;
     DG_HIP(launch_mbf_sweep((int)s->o.mode, a, q));
     DG_HIP(hipMemcpyAsync(p.flags_h, p.lchg, (size_t)p.NB * kLanes * 4, hipMemcpyDeviceToHost, q));
@@ -307,7 +308,7 @@ dg_status pool_sweep(dg_server* s, Pool& p, bool& ran) {
     a.tol = s->o.tol;
     a.nq = p.NB * kLanes;
     a.k = p.k;
-    a.d = s->o.mode == DG_DELAYED ? std::max(1u, std::min(s->o.d, g->max_block_v)) : 0u;
+    a.d = s->o.mode == DG_DELAYED ? std::max(1u, std::min(s->o.d, g->max_block_vb)) : 0u;
     a.NB = p.NB;
     DG_HIP(launch_mppr_sweep((int)s->o.mode, f64(s), a, q));
     DG_HIP(hipMemcpyAsync(p.flags_h, p.qdone, (size_t)p.NB * kLanes * 4, hipMemcpyDeviceToHost, q));

@@ -188,22 +188,22 @@ __host__ __device__ constexpr uint32_t res_offset(uint32_t cap, uint32_t elem) {
 
 template <int M, typename T>
 struct ResTable {
-  static constexpr uint32_t kPer = kResSegBytes / (kWG * sizeof(T));  // values per thread per segment
-  static constexpr uint32_t kSeg = kPer * kWG;                         // values per segment
+  static constexpr uint32_t kPer = kResSegBytes / (kSweepWG * sizeof(T));  // values per thread per segment
+  static constexpr uint32_t kSeg = kPer * kSweepWG;                         // values per segment
   T* lds;
   uint32_t res, n, next = 0;  // next: first value of the segment to refresh
   T r[kPer];
   __device__ __forceinline__ void issue(rsrc_t rc, uint32_t tid) {
 #pragma unroll
     for (uint32_t j = 0; j < kPer; ++j) {
-      const uint32_t i = next + j * kWG + tid;
+      const uint32_t i = next + j * kSweepWG + tid;
       r[j] = gather<M, T>(rc, i < res ? (n + i) * (uint32_t)sizeof(T) : kOut);
     }
   }
   __device__ __forceinline__ void commit(uint32_t tid) {
 #pragma unroll
     for (uint32_t j = 0; j < kPer; ++j) {
-      const uint32_t i = next + j * kWG + tid;
+      const uint32_t i = next + j * kSweepWG + tid;
       if (i < res) lds[i] = r[j];
     }
     next += kSeg;
@@ -229,10 +229,10 @@ struct ResTable {
 // the end of the previous sweep.  Sources in the compact region are read from
 // the committed array.
 template <int M, typename T, bool LOCAL = false>
-__global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
+__global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
   __shared__ uint32_t s_ptr[kTileV + 1];
   __shared__ double s_acc[kTileV];
-  __shared__ double s_red[3 * (kWG / 64)];
+  __shared__ double s_red[3 * (kSweepWG / 64)];
   __shared__ int s_last;
   extern __shared__ __align__(16) unsigned char s_dyn[];
   T* s_stage = reinterpret_cast<T*>(s_dyn);                         // [cap] values
@@ -413,9 +413,9 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
         if (shadow) __syncthreads(); else lds_barrier();
         if (shadow) {
           const uint32_t f0 = v1 - staged;
-          for (uint32_t i = tid; i < staged; i += kWG) st_agent(cout + a.g.cpos[f0 + i], shadow[f0 + i]);
+          for (uint32_t i = tid; i < staged; i += kSweepWG) st_agent(cout + a.g.cpos[f0 + i], shadow[f0 + i]);
         } else {
-          for (uint32_t i = tid; i < staged; i += kWG) st_agent(cout + s_spos[i], s_stage[i]);
+          for (uint32_t i = tid; i < staged; i += kSweepWG) st_agent(cout + s_spos[i], s_stage[i]);
         }
         staged = 0;
       }
@@ -435,17 +435,24 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
   r_loc = wave_sum(r_loc);
   nd_loc = wave_sum(nd_loc);
   m_loc = wave_sum(m_loc);
+  constexpr uint32_t NW = kSweepWG / 64;  // wavefronts per workgroup
   if (lane == 0) {
     s_red[wv] = r_loc;
-    s_red[4 + wv] = nd_loc;
-    s_red[8 + wv] = m_loc;
+    s_red[NW + wv] = nd_loc;
+    s_red[2 * NW + wv] = m_loc;
   }
   __syncthreads();
   if (tid == 0) {
-    a.st.part[w] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    double r_w = 0.0, nd_w = 0.0, m_w = 0.0;  // in wavefront order
+    for (uint32_t i = 0; i < NW; ++i) {
+      r_w += s_red[i];
+      nd_w += s_red[NW + i];
+      m_w += s_red[2 * NW + i];
+    }
+    a.st.part[w] = r_w;
     if (!frozen) {
-      a.st.part[P + w] = s_red[4] + s_red[5] + s_red[6] + s_red[7];
-      a.st.part[2 * P + w] = s_red[8] + s_red[9] + s_red[10] + s_red[11];
+      a.st.part[P + w] = nd_w;
+      a.st.part[2 * P + w] = m_w;
     }
     __threadfence();
     const uint32_t prev = atomicAdd(&a.st.count[k], 1u);
@@ -459,11 +466,11 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
     };
     double r = 0.0, dd = 0.0;
     if (!a.wseg) {
-      for (uint32_t i = tid; i < P; i += kWG) r += part(i);
+      for (uint32_t i = tid; i < P; i += kSweepWG) r += part(i);
     } else {
       // Graph sets: each graph's change relative to its own mass (its L1
       // change once normalised); the sweep's value is the largest of them.
-      for (uint32_t gi = tid; gi < a.G; gi += kWG) {
+      for (uint32_t gi = tid; gi < a.G; gi += kSweepWG) {
         double rg = 0.0, mg = 0.0;
         const uint32_t i1 = a.wseg[gi + 1];
         for (uint32_t i = a.wseg[gi]; i < i1; i += 8) {
@@ -485,7 +492,7 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
         if (q < a.tol && a.gsweeps[gi] == 0) a.gsweeps[gi] = k + 1;
       }
     }
-    for (uint32_t i = tid; i < P; i += kWG) dd += part(P + i);
+    for (uint32_t i = tid; i < P; i += kSweepWG) dd += part(P + i);
     if (!a.wseg) {
       r = wave_sum(r);
     } else {
@@ -498,13 +505,18 @@ __global__ __launch_bounds__(kWG) void pr_sweep_kernel(PrArgs a) {
     dd = wave_sum(dd);
     if (lane == 0) {
       s_red[wv] = r;
-      s_red[4 + wv] = dd;
+      s_red[NW + wv] = dd;
     }
     __syncthreads();
     if (tid == 0) {
-      a.st.resid[k + 1] = !a.wseg ? s_red[0] + s_red[1] + s_red[2] + s_red[3]
-                                  : fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3]));
-      a.st.dang[k + 1] = 1.0 - (s_red[4] + s_red[5] + s_red[6] + s_red[7]);
+      double r_all = 0.0, r_max = 0.0, d_all = 0.0;
+      for (uint32_t i = 0; i < NW; ++i) {
+        r_all += s_red[i];
+        r_max = fmax(r_max, s_red[i]);
+        d_all += s_red[NW + i];
+      }
+      a.st.resid[k + 1] = !a.wseg ? r_all : r_max;
+      a.st.dang[k + 1] = 1.0 - d_all;
     }
   }
 }
@@ -536,7 +548,7 @@ __global__ __launch_bounds__(kWG) void pr_init_kernel(T* x, T* c0, T* c1, const 
 // LOCAL: as for pr_sweep_kernel, reads of this worker's own vertices come
 // from its shadow (delayed mode with the per-vertex shadow only).
 template <int M, bool LOCAL = false>
-__global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
+__global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
   __shared__ uint32_t s_ptr[kTileV + 1];
   __shared__ uint32_t s_acc[kTileV];
   extern __shared__ __align__(16) unsigned char s_dyn[];
@@ -682,9 +694,9 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
         if (a.shadow) __syncthreads(); else lds_barrier();
         if (a.shadow) {
           const uint32_t f0 = v1 - staged;
-          for (uint32_t i = tid; i < staged; i += kWG) st_agent(dout + a.g.cpos[f0 + i], a.shadow[f0 + i]);
+          for (uint32_t i = tid; i < staged; i += kSweepWG) st_agent(dout + a.g.cpos[f0 + i], a.shadow[f0 + i]);
         } else {
-          for (uint32_t i = tid; i < staged; i += kWG) st_agent(dout + s_spos[i], s_stage[i]);
+          for (uint32_t i = tid; i < staged; i += kSweepWG) st_agent(dout + s_spos[i], s_stage[i]);
         }
         staged = 0;
       }
@@ -715,7 +727,7 @@ __global__ __launch_bounds__(kWG) void bf_sweep_kernel(BfArgs a) {
   if (!s_last) return;
   __threadfence();
   int ch_any = 0;
-  for (uint32_t gi = tid; gi < a.G; gi += kWG) {
+  for (uint32_t gi = tid; gi < a.G; gi += kSweepWG) {
     int ch = 0;
     const uint32_t i1 = a.wseg[gi + 1];
     for (uint32_t i = a.wseg[gi]; i < i1; i += 8) {
@@ -814,9 +826,21 @@ hipError_t launch_pr_init(bool f64, void* x, void* c0, void* c1, const uint32_t*
   return hipGetLastError();
 }
 
+// The sweep kernels take more dynamic LDS than the default 64 KB limit.
+template <typename K>
+static void allow_dyn_lds(K kernel) {
+  static bool done = false;  // once per kernel instance
+  if (!done) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)kSweepDynLds);
+    done = true;
+  }
+}
+
 template <int M, typename T, bool LOCAL = false>
 static void pr_sweep_go(const PrArgs& a, hipStream_t s) {
-  pr_sweep_kernel<M, T, LOCAL><<<a.g.P, kWG, pr_dyn_lds<M, T>(a), s>>>(a);
+  allow_dyn_lds(pr_sweep_kernel<M, T, LOCAL>);
+  pr_sweep_kernel<M, T, LOCAL><<<a.g.P, kSweepWG, pr_dyn_lds<M, T>(a), s>>>(a);
 }
 
 hipError_t launch_pr_sweep(int mode, bool f64, const PrArgs& a, hipStream_t s) {
@@ -859,10 +883,19 @@ hipError_t launch_bf_gather(const uint32_t* d, const uint32_t* cpos, uint32_t n,
 hipError_t launch_bf_sweep(int mode, const BfArgs& a, hipStream_t s) {
   const size_t lds = (size_t)res_offset(mode == kDelayed || mode == kDelayedLocal ? a.cap : 0u, 4u) +
                      (size_t)a.res * sizeof(uint32_t);
-  if (mode == kSync) bf_sweep_kernel<kSync><<<a.g.P, kWG, lds, s>>>(a);
-  else if (mode == kAsync) bf_sweep_kernel<kAsync><<<a.g.P, kWG, lds, s>>>(a);
-  else if (mode == kDelayedLocal) bf_sweep_kernel<kDelayed, true><<<a.g.P, kWG, lds, s>>>(a);
-  else bf_sweep_kernel<kDelayed><<<a.g.P, kWG, lds, s>>>(a);
+  if (mode == kSync) {
+    allow_dyn_lds(bf_sweep_kernel<kSync>);
+    bf_sweep_kernel<kSync><<<a.g.P, kSweepWG, lds, s>>>(a);
+  } else if (mode == kAsync) {
+    allow_dyn_lds(bf_sweep_kernel<kAsync>);
+    bf_sweep_kernel<kAsync><<<a.g.P, kSweepWG, lds, s>>>(a);
+  } else if (mode == kDelayedLocal) {
+    allow_dyn_lds(bf_sweep_kernel<kDelayed, true>);
+    bf_sweep_kernel<kDelayed, true><<<a.g.P, kSweepWG, lds, s>>>(a);
+  } else {
+    allow_dyn_lds(bf_sweep_kernel<kDelayed>);
+    bf_sweep_kernel<kDelayed><<<a.g.P, kSweepWG, lds, s>>>(a);
+  }
   return hipGetLastError();
 }
 

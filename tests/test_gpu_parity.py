@@ -51,6 +51,8 @@ def _graph(name):
             g = gg.rmat(10, seed=10)
         elif name == "rmat14":
             g = gg.rmat(14, seed=14)
+        elif name == "rmat16":
+            g = gg.rmat(16, seed=16)
         elif name == "banded":
             g = gg.banded(60_000, 16, 4096, 0.01, seed=3)
         elif name == "er":
@@ -161,39 +163,42 @@ def test_path_graph_sync_exact(dg):
 
 def test_commit_visibility_tile_chain(dg):
     """A chain whose consecutive vertices sit in consecutive tiles (vertex
-    256*i -> 256*(i+1), all other vertices isolated, so every tile holds 256
-    vertices and one chain vertex).  Each worker owns L/P consecutive tiles.
+    TILE*i -> TILE*(i+1), all other vertices isolated, so every tile holds
+    TILE = 1024 vertices, the sweep workgroup's size, and one chain vertex).
+    Each worker owns L/P consecutive tiles.
 
     * sync: the chain advances one tile per sweep: exactly L sweeps;
-    * async and delayed with d <= 256: a value committed by tile k is read by
-      tile k+1 of the same worker in the same sweep, so a sweep advances the
-      chain through a whole worker block: about P sweeps;
+    * async and delayed with d <= TILE: a value committed by tile k is read
+      by tile k+1 of the same worker in the same sweep, so a sweep advances
+      the chain through a whole worker block: about P sweeps;
+    * delayed with d = 4 tiles: commits every fourth tile, more sweeps;
     * delayed with d = whole block: nothing is visible before the block
       ends, so the chain again advances about one tile per sweep.
     """
-    L = 32768
-    n = 256 * L
-    src = 256 * np.arange(L - 1, dtype=np.int64)
-    g = gg.from_edges(n, src, src + 256, w=np.ones(L - 1, np.uint32))
+    TILE = 1024
+    L = 8192
+    n = TILE * L
+    src = TILE * np.arange(L - 1, dtype=np.int64)
+    g = gg.from_edges(n, src, src + TILE, w=np.ones(L - 1, np.uint32))
     G = dg.Graph.from_csr(g)
     info = G.info()
     assert info.tiles == L
     P = info.workers
     ref = np.full(n, dg.DG_INF_DIST, np.uint32)
-    ref[256 * np.arange(L)] = np.arange(L)
+    ref[TILE * np.arange(L)] = np.arange(L)
     d, st = G.sssp(0, mode="sync")
     np.testing.assert_array_equal(_np(d), ref)
-    assert st.sweeps == L
+    assert st.sweeps == L and st.tile_vertices == TILE
     res = {}
-    for mode, dd in [("async", 1), ("delayed", 1), ("delayed", 256), ("delayed", 1024), ("delayed", 0xFFFFFFFF)]:
+    for mode, dd in [("async", 1), ("delayed", 1), ("delayed", TILE), ("delayed", 4 * TILE), ("delayed", 0xFFFFFFFF)]:
         d, st = G.sssp(0, mode=mode, d=dd)
         np.testing.assert_array_equal(_np(d), ref)
         res[(mode, dd)] = st.sweeps
         print(f"tile chain L={L} P={P} {mode} d={dd}: {st.sweeps} sweeps")
     assert res[("async", 1)] <= 2 * P + 2
     assert res[("delayed", 1)] <= 2 * P + 2
-    assert res[("delayed", 256)] <= 2 * P + 2
-    assert res[("delayed", 1024)] > res[("delayed", 256)]
+    assert res[("delayed", TILE)] <= 2 * P + 2
+    assert res[("delayed", 4 * TILE)] > res[("delayed", TILE)]
     assert res[("delayed", 0xFFFFFFFF)] >= L // 4
     G.close()
 
@@ -314,13 +319,13 @@ def test_options_hot_region_and_workers(dg, hot, workers):
 def _resident_reference(g, res_opt=0xFFFFFFFF, hot_cap=524288):
     """Compact region and resident table by their definition: candidates are
     sources with out-degree above 1 and above the average, the region takes
-    the largest hot_cap of them, the table the largest min(res_opt, 6144) of
+    the largest hot_cap of them, the table the largest min(res_opt, 32768) of
     those; the automatic size (res_opt = all ones) keeps the table only if
     its sources cover at least 1/16 of the edges."""
     od = np.diff(g.ptr.astype(np.int64))
     cand = np.nonzero((od > 1) & (od > g.m / g.n))[0]
     top = cand[np.argsort(-od[cand], kind="stable")][:hot_cap]
-    r = min(top.size, res_opt, 6144)
+    r = min(top.size, res_opt, 32768)
     cover = int(od[top[:r]].sum())
     if res_opt == 0xFFFFFFFF and cover * 16 < g.m:
         r, cover = 0, 0
@@ -361,13 +366,13 @@ def test_resident_table_sync_same_values(dg, name, res):
     B.close()
 
 
-@pytest.mark.parametrize("res", [1, 100, 2049, 0xFFFFFFFF])
+@pytest.mark.parametrize("res", [1, 100, 8193, 0xFFFFFFFF])
 def test_resident_table_async_delayed_local(dg, res):
     """Asynchronous and delayed sweeps refresh the table a segment at a time
     after every tile: table sizes below, at and across a segment boundary,
     every commit interval, and the local-read variant, all converge to the
     oracle's fixed point (PageRank) and its exact distances (SSSP)."""
-    g, xs = _graph("rmat14")
+    g, xs = _graph("rmat16")
     G = dg.Graph.from_csr(g, resident_vertices=res)
     assert G.info().resident_vertices == _resident_reference(g, res)[2] > 0
     src = _sources(g, 1)[0]

@@ -8,7 +8,7 @@ with numpy:
   vertex id), the resident table as its first R slots in two vertex-ordered
   halves, the rest in vertex order; the automatic table only when its
   sources cover 1/16 of the edges;
-* tiles: greedy runs of at most 256 vertices and 2044 in-edges, a larger
+* tiles: greedy runs of at most 1024 vertices and 8188 in-edges, a larger
   vertex alone;
 * the blocked partition (section III-A: contiguous blocks balanced by
   in-edges): P contiguous tile ranges split at the cost quantiles;
@@ -32,7 +32,8 @@ def dg():
 
 
 AUTO = 0xFFFFFFFF
-TILE_V, TILE_E = 256, 2044
+TILE_V, TILE_E = 1024, 8188
+PER_CU = 1  # sweep workgroups per compute unit
 
 
 def _ref_cpos(g, hot=AUTO, res=AUTO):
@@ -42,7 +43,7 @@ def _ref_cpos(g, hot=AUTO, res=AUTO):
     top = cand[np.argsort(-od[cand], kind="stable")]
     top = top[: (524288 if hot == AUTO else hot)]
     K = top.size
-    R = min(K, 6144 if res == AUTO else min(res, 6144))
+    R = min(K, 32768 if res == AUTO else min(res, 32768))
     if res == AUTO and od[top[:R]].sum() * 16 < m:
         R = 0
     half = (R + 1) // 2
@@ -130,7 +131,7 @@ def test_tiles_and_partition(dg, graph):
         ne = np.diff(p["in_ptr"].astype(np.int64)[tile_v])
         assert (nv >= 1).all() and (nv <= TILE_V).all()
         assert ((ne <= TILE_E) | (nv == 1)).all()  # a larger vertex is a tile of its own
-        P = workers if workers else cus * 5
+        P = workers if workers else cus * PER_CU
         P = max(1, min(P, T))
         if P > 8 and not workers:
             P &= ~7
@@ -145,18 +146,18 @@ def test_tiles_and_partition(dg, graph):
 
 
 @pytest.mark.parametrize("hot,res", [(0, AUTO), (50, AUTO), (1000, 100), (AUTO, 0), (AUTO, 1), (AUTO, 2049),
-                                     (AUTO, 100_000)])
+                                     (AUTO, 8193), (AUTO, 100_000)])
 def test_region_options(dg, hot, res):
     g = gg.rmat(14, seed=14)
     p = dg.plan(g.n, g.ptr, g.idx, g.w, hot_vertices=hot, resident_vertices=res)
     cpos, K, hot_e, R, res_e = _ref_cpos(g, hot, res)
     np.testing.assert_array_equal(p["cpos"], cpos)
     assert (p["hot_vertices"], p["hot_edges"], p["resident_vertices"], p["resident_edges"]) == (K, hot_e, R, res_e)
-    assert R <= min(K, 6144)
+    assert R <= min(K, 32768)
 
 
 def test_resident_table_automatic_threshold(dg):
-    """Banded graphs of even degree: the 6144 largest sources cover too few
+    """Banded graphs of even degree: the 32768 largest sources cover too few
     edges at 4M vertices, so the automatic size keeps no table; an explicit
     size keeps one."""
     g = gg.banded(1 << 20, 16, 4096, 0.01, seed=2)
@@ -208,9 +209,9 @@ def test_edge_cases(dg):
     p = dg.plan(1, np.zeros(2, np.uint64), np.zeros(0, np.uint32))
     assert (p["tiles"], p["workers"], p["hot_vertices"], p["dangling"]) == (1, 1, 0, 1)
     np.testing.assert_array_equal(p["tile_v"], [0, 1])
-    # many vertices, no edges: full tiles of 256
-    p = dg.plan(1000, np.zeros(1001, np.uint64), np.zeros(0, np.uint32))
-    np.testing.assert_array_equal(p["tile_v"], [0, 256, 512, 768, 1000])
+    # many vertices, no edges: full tiles of 1024
+    p = dg.plan(3000, np.zeros(3001, np.uint64), np.zeros(0, np.uint32))
+    np.testing.assert_array_equal(p["tile_v"], [0, 1024, 2048, 3000])
     # one hub with far more than a tile's in-edges is a tile of its own
     g = tg.in_star(9000)
     p = dg.plan(g.n, g.ptr, g.idx, g.w)
