@@ -126,8 +126,11 @@ typedef void (*dg_free_fn)(void* ptr, void* hip_stream, void* ctx);
 dg_status dg_set_allocator(dg_alloc_fn alloc, dg_free_fn free_fn, void* ctx);
 
 /* Options of dg_graph_create (pass NULL for the defaults).
- *   workers       persistent workgroups that own the contiguous vertex blocks;
- *                 0 = automatic (5 per compute unit, at most one per tile)
+ *   workers       persistent workgroups that own the contiguous vertex blocks
+ *                 of the single-query sweeps; 0 = automatic (one 1024-thread
+ *                 workgroup per compute unit, at most one per tile).  The
+ *                 batched calls use a partition of their own (five 256-thread
+ *                 workgroups per compute unit).
  *   hot_vertices  at most this many sources with the largest out-degree (and
  *                 above-average out-degree) get their published value stored
  *                 in a compact region after the n regular slots, so gathers
@@ -312,9 +315,10 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
  *   out_first_vertex  host array of workers + 1 entries (dg_graph_info) */
 dg_status dg_graph_partition(const dg_graph* g, uint32_t* out_first_vertex, void* hip_stream);
 
-/* Re-partitions a resident graph over `workers` workers (0 = the default,
- * 5 per compute unit rounded down to a multiple of 8), without re-uploading
- * it.  The blocked partition is rebuilt as at creation (section III-A).
+/* Re-partitions the single-query sweeps of a resident graph over `workers`
+ * workers (0 = the default, one per compute unit rounded down to a multiple
+ * of 8), without re-uploading it.  The blocked partition is rebuilt as at
+ * creation (section III-A); more workers than compute units run in turn.
  * Must not overlap a sweep call on the same graph. */
 dg_status dg_graph_repartition(dg_graph* g, uint32_t workers, void* hip_stream);
 

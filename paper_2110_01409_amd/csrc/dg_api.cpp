@@ -62,6 +62,7 @@ using dg::host::kMaxSweeps;
 using dg::host::kSweepChunk;
 using dg::host::kWorkersPerCU;
 using dg::host::kBatchWorkersPerCU;
+using dg::host::kSetWorkersPerCU;
 using dg::host::topo_batch;
 using dg::host::build_layout;
 using dg::host::build_workers;
@@ -454,7 +455,7 @@ dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
   }
   g->cus = (uint32_t)cus;
   g->lds_per_block = (size_t)lds;
-  uint32_t P = plan_workers(L, opts ? opts->workers : 0u, g->cus, kWorkersPerCU);
+  uint32_t P = plan_workers(L, opts ? opts->workers : 0u, g->cus, seg_v ? kSetWorkersPerCU : kWorkersPerCU);
   std::vector<uint32_t> work_t;
   if (seg_v) {
     g->G = (uint32_t)seg_v->size() - 1;

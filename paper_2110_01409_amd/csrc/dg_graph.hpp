@@ -24,6 +24,11 @@ constexpr uint32_t kWorkersPerCU = 1;
 // The same for the batched kernels (256 threads, no table).  Five measured
 // faster than eight on RMAT and banded graphs.
 constexpr uint32_t kBatchWorkersPerCU = 5;
+// The same for the union graph of a set: smaller blocks, several sweep
+// workgroups per compute unit in turn, so that the last graphs to converge
+// (the others' workers exit at once) still spread over the whole GPU.
+// Three to five measured best on a 64-graph set.
+constexpr uint32_t kSetWorkersPerCU = 5;
 
 }  // namespace host
 }  // namespace dg
