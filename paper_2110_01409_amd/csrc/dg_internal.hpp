@@ -14,8 +14,10 @@ constexpr int kWG = 256;
 // compute unit, so that one LDS copy of the hottest sources (the resident
 // table) can take most of the unit's 160 KB.
 constexpr int kSweepWG = 1024;
-// Consecutive in-edges one thread reduces per chunk (two 16-byte index loads).
-constexpr int kEPT = 8;
+// Consecutive in-edges one thread reduces per chunk (four 16-byte index loads).
+// Sixteen measured 7% faster per sweep than eight with one sweep workgroup
+// per compute unit: twice the loads in flight per thread, half the tiles.
+constexpr int kEPT = 16;
 // Edge slots a sweep workgroup covers per chunk.
 constexpr int kChunk = kSweepWG * kEPT;
 // At most this many vertices per tile: one vertex per thread in the update phase.

@@ -82,12 +82,9 @@ void build_workers_seg(const std::vector<uint32_t>& tile_v, const std::vector<ui
   for (uint32_t i = 0; i <= G; ++i)
     gt[i] = (uint32_t)(std::lower_bound(tile_v.begin(), tile_v.end(), seg_v[i]) - tile_v.begin());
   std::vector<double> cost(G, 0.0);
-  double total = 0.0;
-  for (uint32_t i = 0; i < G; ++i) {
+  for (uint32_t i = 0; i < G; ++i)
     for (uint32_t t = gt[i]; t < gt[i + 1]; ++t)
       cost[i] += 256.0 + (double)(tile_e0[t + 1] - tile_e0[t]) + 4.0 * (double)(tile_v[t + 1] - tile_v[t]);
-    total += cost[i];
-  }
   // one worker each, the rest by largest remaining cost per worker
   std::vector<uint32_t> pw(G, 1u);
   for (uint32_t extra = P - G, i = 0; extra > 0; --extra) {

@@ -9,11 +9,13 @@
 //     ascending vertex order.  Worker ids are spread so that each of the eight
 //     XCDs (workgroups are dispatched to XCDs round-robin) owns one contiguous
 //     eighth of the vertex range.
-//   * A tile holds <= 256 vertices and <= 2044 in-edges, or one vertex with
-//     more.  Its edges are processed in chunks of 2048 slots starting at the
-//     tile's first edge rounded down to a multiple of 4: thread t reduces the
-//     8 consecutive slots [8t, 8t+8) of the chunk, fetched with two 16-byte
-//     loads of the index (and weight) stream, then 8 independent gathers.
+//   * A worker is one 1024-thread workgroup.  A tile holds <= 1024 vertices
+//     and <= 16380 in-edges, or one vertex with more.  Its edges are
+//     processed in chunks of 16384 slots starting at the tile's first edge
+//     rounded down to a multiple of 4: thread t reduces the 16 consecutive
+//     slots [16t, 16t+16) of the chunk, fetched with four 16-byte loads of the
+//     index stream (and one or four of the weight stream), then 16
+//     independent gathers.
 //     Partial sums (or minima) per vertex go to LDS with ds_add_f64 /
 //     ds_min_u32 once per vertex boundary crossed; a single-vertex tile uses a
 //     wavefront shuffle reduction and one LDS atomic per wave instead.
@@ -122,38 +124,45 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
-// Eight consecutive 4-byte words of the in-edge stream for one thread.  The
-// window [nb, lim) is rounded up to whole 16-byte groups so that each
-// 16-byte load is entirely inside or outside it.
-__device__ __forceinline__ void load_win8(const uint32_t* stream, uint32_t nb, uint32_t lim, uint32_t tid,
-                                          uint32_t (&u)[kEPT]) {
+// kEPT consecutive 4-byte words of the in-edge stream for one thread, in
+// 16-byte loads.  The window [nb, lim) is rounded up to whole 16-byte groups
+// so that each load is entirely inside or outside it.
+__device__ __forceinline__ void load_win(const uint32_t* stream, uint32_t nb, uint32_t lim, uint32_t tid,
+                                         uint32_t (&u)[kEPT]) {
   const uint32_t end = (lim + 3u) & ~3u;
   const rsrc_t r = make_rsrc(stream + nb, end > nb ? (end - nb) * 4u : 0u);
-  const v4u q0 = __builtin_amdgcn_raw_buffer_load_b128(r, tid * 32u, 0, 0);
-  const v4u q1 = __builtin_amdgcn_raw_buffer_load_b128(r, tid * 32u + 16u, 0, 0);
-  u[0] = q0.x; u[1] = q0.y; u[2] = q0.z; u[3] = q0.w;
-  u[4] = q1.x; u[5] = q1.y; u[6] = q1.z; u[7] = q1.w;
+#pragma unroll
+  for (int q = 0; q < kEPT / 4; ++q) {
+    const v4u v = __builtin_amdgcn_raw_buffer_load_b128(r, tid * (4u * kEPT) + 16u * q, 0, 0);
+    u[4 * q] = v.x;
+    u[4 * q + 1] = v.y;
+    u[4 * q + 2] = v.z;
+    u[4 * q + 3] = v.w;
+  }
 }
 
-// The same for a stream of one-byte weights: eight bytes per thread, one
-// 8-byte load (4-byte aligned, as buffer loads need), widened to uint32.
-__device__ __forceinline__ void load_win8_u8(const uint8_t* stream, uint32_t nb, uint32_t lim, uint32_t tid,
-                                             uint32_t (&u)[kEPT]) {
-  const uint32_t end = (lim + 7u) & ~7u;
+// The same for a stream of one-byte weights: kEPT = 16 bytes per thread, one
+// 16-byte load (4-byte aligned, as buffer loads need), widened to uint32.
+static_assert(kEPT == 16, "load_win_u8 reads 16 one-byte weights per thread");
+__device__ __forceinline__ void load_win_u8(const uint8_t* stream, uint32_t nb, uint32_t lim, uint32_t tid,
+                                            uint32_t (&u)[kEPT]) {
+  const uint32_t end = (lim + 15u) & ~15u;
   const rsrc_t r = make_rsrc(stream + nb, end > nb ? end - nb : 0u);
-  const v2u q = __builtin_amdgcn_raw_buffer_load_b64(r, tid * 8u, 0, 0);
+  const v4u q = __builtin_amdgcn_raw_buffer_load_b128(r, tid * 16u, 0, 0);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     u[j] = (q.x >> (8 * j)) & 255u;
     u[4 + j] = (q.y >> (8 * j)) & 255u;
+    u[8 + j] = (q.z >> (8 * j)) & 255u;
+    u[12 + j] = (q.w >> (8 * j)) & 255u;
   }
 }
 
 // Weights of the next chunk, from whichever stream the graph keeps.
 __device__ __forceinline__ void load_weights(const Topology& g, uint32_t nb, uint32_t lim, uint32_t tid,
                                              uint32_t (&u)[kEPT]) {
-  if (g.in_w8) load_win8_u8(g.in_w8, nb, lim, tid, u);
-  else load_win8(g.in_w, nb, lim, tid, u);
+  if (g.in_w8) load_win_u8(g.in_w8, nb, lim, tid, u);
+  else load_win(g.in_w, nb, lim, tid, u);
 }
 
 // Gather of a published value; out-of-range offsets read 0.  Asynchronous
@@ -291,7 +300,7 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
     if (tid <= nv0) s_ptr[tid] = a.g.in_ptr[v0 + tid];
     if (tid == 0 && nv0 == kTileV) s_ptr[kTileV] = a.g.in_ptr[v0 + kTileV];
     const uint32_t b0 = as_const(a.g.in_ptr)[v0] & ~3u;
-    load_win8(a.g.in_src, b0, as_const(a.g.in_ptr)[tile_v[t0 + 1]], tid, u);
+    load_win(a.g.in_src, b0, as_const(a.g.in_ptr)[tile_v[t0 + 1]], tid, u);
     const uint32_t vi = min(v0 + tid, n - 1);
     xo_n = x[vi];
     dg_n = a.g.out_deg[vi];
@@ -347,7 +356,7 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
       const bool last = cb + kChunk >= ee;
       const uint32_t nb = !last ? cb + kChunk : (more ? (ee & ~3u) : cb);
       const uint32_t lim = !last ? ee : (more ? ee_next : cb);
-      load_win8(a.g.in_src, nb, lim, tid, u);
+      load_win(a.g.in_src, nb, lim, tid, u);
       if (last) prefetch_next();
       double val[kEPT];
 #pragma unroll
@@ -381,7 +390,7 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
     }
     if (eb >= ee) {
       // A tile without in-edges ran no chunk: fetch the next tile's window here.
-      if (more) load_win8(a.g.in_src, ee & ~3u, ee_next, tid, u);
+      if (more) load_win(a.g.in_src, ee & ~3u, ee_next, tid, u);
       prefetch_next();
     }
     lds_barrier();
@@ -587,7 +596,7 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
     if (tid == 0 && nv0 == kTileV) s_ptr[kTileV] = a.g.in_ptr[v0 + kTileV];
     const uint32_t b0 = as_const(a.g.in_ptr)[v0] & ~3u;
     const uint32_t l0 = as_const(a.g.in_ptr)[tile_v[t0 + 1]];
-    load_win8(a.g.in_src, b0, l0, tid, u);
+    load_win(a.g.in_src, b0, l0, tid, u);
     load_weights(a.g, b0, l0, tid, wt);
     p_n = a.g.cpos[min(v0 + tid, n - 1)];
   }
@@ -630,7 +639,7 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
       const bool last = cb + kChunk >= ee;
       const uint32_t nb = !last ? cb + kChunk : (more ? (ee & ~3u) : cb);
       const uint32_t lim = !last ? ee : (more ? ee_next : cb);
-      load_win8(a.g.in_src, nb, lim, tid, u);
+      load_win(a.g.in_src, nb, lim, tid, u);
       load_weights(a.g, nb, lim, tid, wt);
       if (last) prefetch_next();
       uint32_t cand[kEPT];
@@ -665,7 +674,7 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
     }
     if (eb >= ee) {
       if (more) {
-        load_win8(a.g.in_src, ee & ~3u, ee_next, tid, u);
+        load_win(a.g.in_src, ee & ~3u, ee_next, tid, u);
         load_weights(a.g, ee & ~3u, ee_next, tid, wt);
       }
       prefetch_next();

@@ -39,7 +39,7 @@ def test_sssp_batch_all_modes(dg, name):
     if name == "rmat13":
         g = gg.rmat(13, seed=13)
     elif name == "instar":
-        g = tg.in_star(9000)  # one hub beyond a tile (8188 in-edges): the wavefront split
+        g = tg.in_star(20_000)  # one hub beyond a tile (16380 in-edges): the wavefront split
     else:
         g = gg.banded(20_000, 16, 512, 0.01, seed=4)
     k = 70  # two batches, the second ragged
@@ -70,7 +70,7 @@ def test_ppr_batch_all_modes(dg, name, dtype, tol):
     elif name == "dangling":
         g = tg.dangling_heavy(3000, 5)
     else:
-        g = tg.in_star(9000)
+        g = tg.in_star(20_000)
     k = 67
     rng = np.random.default_rng(2)
     sources = rng.integers(0, g.n, size=k).astype(np.uint32)

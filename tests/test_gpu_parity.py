@@ -58,7 +58,7 @@ def _graph(name):
         elif name == "er":
             g = gg.erdos_renyi(30_001, 12, seed=5)
         elif name == "instar":
-            g = tg.in_star(9000)
+            g = tg.in_star(20_000)
         elif name == "multi":
             g = tg.random_graph(3001, 20_000, 7, dedup=False)
         else:

@@ -48,7 +48,7 @@ def uneven_graphs():
     """Sizes from 1 to 20000 vertices, a hub beyond one tile, dangling-heavy,
     edgeless, long paths (many sweeps) and dense ones (few)."""
     return [
-        gg.rmat(10, seed=1), gg.rmat(12, seed=2), gg.erdos_renyi(3000, 8, seed=3), tg.in_star(9000),
+        gg.rmat(10, seed=1), gg.rmat(12, seed=2), gg.erdos_renyi(3000, 8, seed=3), tg.in_star(20_000),
         tg.dangling_heavy(2000, 4), gg.path_graph(300, weight=7), tg.cycle(50), tg.complete(20), tg.empty(7),
         tg.two_scc(400, 5), gg.banded(20_000, 8, 256, 0.01, seed=5), gg.rmat(8, seed=9),
         gg.from_edges(1, np.zeros(0, np.int64), np.zeros(0, np.int64), weight_seed=1, name="single"),

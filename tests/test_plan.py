@@ -8,7 +8,7 @@ with numpy:
   vertex id), the resident table as its first R slots in two vertex-ordered
   halves, the rest in vertex order; the automatic table only when its
   sources cover 1/16 of the edges;
-* tiles: greedy runs of at most 1024 vertices and 8188 in-edges, a larger
+* tiles: greedy runs of at most 1024 vertices and 16380 in-edges, a larger
   vertex alone;
 * the blocked partition (section III-A: contiguous blocks balanced by
   in-edges): P contiguous tile ranges split at the cost quantiles;
@@ -32,7 +32,7 @@ def dg():
 
 
 AUTO = 0xFFFFFFFF
-TILE_V, TILE_E = 1024, 8188
+TILE_V, TILE_E = 1024, 16380
 PER_CU = 1  # sweep workgroups per compute unit
 
 
@@ -85,7 +85,7 @@ GRAPHS = {
     "rmat12": lambda: gg.rmat(12, seed=3),
     "rmat14": lambda: gg.rmat(14, seed=14),
     "banded": lambda: gg.banded(20_000, 8, 512, 0.01, seed=22),
-    "instar": lambda: tg.in_star(9000),
+    "instar": lambda: tg.in_star(20_000),
     "dangling": lambda: tg.dangling_heavy(3000, 23),
     "multi": lambda: tg.random_graph(3001, 20_000, 7, dedup=False),
 }
@@ -213,7 +213,7 @@ def test_edge_cases(dg):
     p = dg.plan(3000, np.zeros(3001, np.uint64), np.zeros(0, np.uint32))
     np.testing.assert_array_equal(p["tile_v"], [0, 1024, 2048, 3000])
     # one hub with far more than a tile's in-edges is a tile of its own
-    g = tg.in_star(9000)
+    g = tg.in_star(20_000)
     p = dg.plan(g.n, g.ptr, g.idx, g.w)
     deg = np.diff(p["in_ptr"].astype(np.int64))
     hub = int(np.argmax(deg))
