@@ -19,6 +19,7 @@
 // Commit modes are those of the single-query sweeps: synchronous (double
 // buffer), asynchronous (agent-scope store per vertex), delayed (staged in a
 // per-batch shadow array, committed every d vertices and at the block end).
+#include "dg_device.hpp"
 #include "dg_internal.hpp"
 
 namespace dg {
@@ -187,7 +188,10 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
   }
   if (any) s_any = 1;  // benign race: every writer stores 1
   __syncthreads();
-  if (tid == 0 && s_any) st_q(a.changed + (k + 1) * NB + b, 1u);
+  if (tid == 0 && s_any) {
+    st_q(a.changed + (k + 1) * NB + b, 1u);
+    if (a.hchanged) st_host(a.hchanged + (k + 1) * NB + b, 1u);
+  }
 }
 
 __global__ __launch_bounds__(kWG) void mbf_init_kernel(uint32_t* d0, uint32_t* d1, const uint32_t* cpos,
@@ -364,6 +368,7 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
       if (lane == 0) a.count[(size_t)((k + 1) & 1u) * NB + b] = 0;
     } else if (lane == 0) {
       a.resid[(k + 1) * NB + b] = m;
+      if (a.hresid) st_host(a.hresid + (k + 1) * NB + b, m);
     }
   }
 }

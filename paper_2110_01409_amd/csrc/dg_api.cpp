@@ -59,7 +59,9 @@ void current_allocator(dg_alloc_fn& alloc, dg_free_fn& free_fn, void*& ctx) {
 
 
 using dg::host::kMaxSweeps;
-using dg::host::kSweepChunk;
+using dg::host::kEventRing;
+using dg::host::kHostReactUs;
+using dg::host::kMaxLookahead;
 using dg::host::kWorkersPerCU;
 using dg::host::kBatchWorkersPerCU;
 using dg::host::kSetWorkersPerCU;
@@ -137,7 +139,6 @@ void release_all(dg_graph* g) {
   if (g->events) {
     (void)hipEventDestroy(g->ev_start);
     for (auto& e : g->ev_sweep) (void)hipEventDestroy(e);
-    for (auto& e : g->ev_copy) (void)hipEventDestroy(e);
     g->events = false;
   }
   if (g->host_poll) {
@@ -147,6 +148,20 @@ void release_all(dg_graph* g) {
   std::vector<void*> all = g->owned;
   for (void* p : all) dev_free(g, p);
   g->owned.clear();
+}
+
+// Pinned host memory, mapped into the device's address space and coherent,
+// that kernels write with system-scope stores and the host reads once the
+// writing sweep's event has completed.
+hipError_t alloc_mapped(void** host, void** dev, size_t bytes) {
+  hipError_t e = hipHostMalloc(host, bytes, hipHostMallocMapped | hipHostMallocCoherent);
+  if (e != hipSuccess) return e;
+  e = hipHostGetDevicePointer(dev, *host, 0);
+  if (e != hipSuccess) {
+    (void)hipHostFree(*host);
+    *host = nullptr;
+  }
+  return e;
 }
 
 dg_status ensure_workspace(dg_graph* g, uint32_t S, hipStream_t s) {
@@ -163,7 +178,6 @@ dg_status ensure_workspace(dg_graph* g, uint32_t S, hipStream_t s) {
   if (!g->events) {
     DG_HIP(hipEventCreate(&g->ev_start));
     for (auto& e : g->ev_sweep) DG_HIP(hipEventCreate(&e));
-    for (auto& e : g->ev_copy) DG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     g->events = true;
   }
   if (g->ws_sweeps < S) {
@@ -173,6 +187,7 @@ dg_status ensure_workspace(dg_graph* g, uint32_t S, hipStream_t s) {
     dev_free(g, g->changed);
     if (g->host_poll) (void)hipHostFree(g->host_poll);
     g->host_poll = nullptr;
+    g->host_poll_dev = nullptr;
     const size_t k = (size_t)S + 1;
     g->resid = static_cast<double*>(dev_alloc(g, k * sizeof(double), s));
     g->dang = static_cast<double*>(dev_alloc(g, k * sizeof(double), s));
@@ -182,7 +197,7 @@ dg_status ensure_workspace(dg_graph* g, uint32_t S, hipStream_t s) {
       g->ws_sweeps = 0;
       return fail(DG_ERR_OUT_OF_MEMORY, "sweep state allocation failed");
     }
-    DG_HIP(hipHostMalloc(&g->host_poll, k * sizeof(double), hipHostMallocDefault));
+    DG_HIP(alloc_mapped(&g->host_poll, &g->host_poll_dev, k * sizeof(double)));
     g->ws_sweeps = S;
   }
   return DG_OK;
@@ -192,6 +207,8 @@ dg_status ensure_workspace(dg_graph* g, uint32_t S, hipStream_t s) {
 SweepState state(const dg_graph* g) {
   SweepState st;
   st.resid = g->resid;
+  st.hresid = static_cast<double*>(g->host_poll_dev);
+  st.hchanged = static_cast<uint32_t*>(g->host_poll_dev);
   st.dang = g->dang;
   st.count = g->count;
   st.changed = g->changed;
@@ -236,62 +253,61 @@ void staging(const dg_graph* g, uint32_t d, size_t elem, uint32_t res, uint32_t&
   cap = shadow ? 0u : d_eff + kTileV;
 }
 
-// Convergence loop shared by every entry point.  launch(k) enqueues sweep k;
-// after each chunk the E state entries (esz bytes each) that sweep k writes
-// at index (k+1)*E are copied to the pinned buffer `host`; done(entries, k)
-// tells whether sweep k met the stopping rule.  Two chunks are in flight so
-// the device never waits for the host.
+// Convergence loop shared by every entry point.  launch(k) enqueues sweep k,
+// which writes the E stopping values of its row k+1 to the device state and,
+// with system-scope stores, to the same row (`row` bytes) of the mapped host
+// buffer `host`; rows are zeroed here before their sweep is enqueued, so a
+// value a sweep does not write reads as 0, as on the device.  done(row, k)
+// tells whether sweep k met the stopping rule.  The host waits for each
+// sweep's event in turn and keeps up to `lookahead` sweeps queued beyond it,
+// enough to cover its own reaction time at the measured sweep time, so the
+// device does not wait for the host and at most that many sweeps are queued
+// after the converging one (each exits at once on the device's own check).
 template <typename Launch, typename Done>
-dg_status drive(dg_graph* g, uint32_t max_sweeps, hipStream_t s, const void* state, size_t esz, uint32_t E,
-                unsigned char* host, Launch launch, Done done, uint32_t& sweeps, double& seconds, bool& converged) {
-  const uint32_t C = std::min(kSweepChunk, max_sweeps);
-  const size_t row = esz * E;
+dg_status drive(dg_graph* g, uint32_t max_sweeps, hipStream_t s, size_t row, unsigned char* host, Launch launch,
+                Done done, uint32_t& sweeps, double& seconds, bool& converged) {
+  static_assert(kMaxLookahead + 1 < kEventRing, "a queued sweep's event slot must not be reused before it is read");
   DG_HIP(hipEventRecord(g->ev_start, s));
+  uint32_t look = std::max(1u, std::min(g->lookahead, kMaxLookahead));
   uint32_t next = 0;  // next sweep to enqueue
-  uint32_t chunk_idx = 0;
-  std::vector<std::pair<uint32_t, uint32_t>> inflight;  // (first sweep, count)
   auto enqueue = [&]() -> dg_status {
-    const uint32_t k0 = next, kc = std::min(C, max_sweeps - next);
-    for (uint32_t j = 0; j < kc; ++j) {
-      hipError_t e = launch(k0 + j);
-      if (e != hipSuccess) return fail(DG_ERR_DEVICE, "sweep launch failed: %s", hipGetErrorString(e));
-      DG_HIP(hipEventRecord(g->ev_sweep[(k0 + j) % (2 * kSweepChunk)], s));
-    }
-    DG_HIP(hipMemcpyAsync(host + (size_t)(k0 + 1) * row, static_cast<const unsigned char*>(state) + (size_t)(k0 + 1) * row,
-                          (size_t)kc * row, hipMemcpyDeviceToHost, s));
-    DG_HIP(hipEventRecord(g->ev_copy[chunk_idx & 1], s));
-    ++chunk_idx;
-    inflight.emplace_back(k0, kc);
-    next += kc;
+    std::memset(host + (size_t)(next + 1) * row, 0, row);
+    const hipError_t e = launch(next);
+    if (e != hipSuccess) return fail(DG_ERR_DEVICE, "sweep launch failed: %s", hipGetErrorString(e));
+    DG_HIP(hipEventRecord(g->ev_sweep[next % kEventRing], s));
+    ++next;
     return DG_OK;
   };
   converged = false;
   sweeps = 0;
-  dg_status st = enqueue();
-  if (st != DG_OK) return st;
-  if (next < max_sweeps && (st = enqueue()) != DG_OK) return st;
-  uint32_t polled = 0;
+  dg_status st = DG_OK;
+  while (next < max_sweeps && next < 1 + look)
+    if ((st = enqueue()) != DG_OK) return st;
   int found = -1;
-  while (!inflight.empty()) {
-    auto [k0, kc] = inflight.front();
-    inflight.erase(inflight.begin());
-    DG_HIP(hipEventSynchronize(g->ev_copy[polled & 1]));
-    ++polled;
-    for (uint32_t j = 0; j < kc; ++j) {
-      if (done(host + (size_t)(k0 + j + 1) * row, k0 + j)) {
-        found = (int)(k0 + j);
-        break;
-      }
+  for (uint32_t k = 0; k < next; ++k) {
+    DG_HIP(hipEventSynchronize(g->ev_sweep[k % kEventRing]));
+    if (k == 0) {
+      // The first sweep's time (from the stream reaching it) sets how far
+      // ahead to queue, here and in the graph's next call.
+      float ms = 0.f;
+      DG_HIP(hipEventElapsedTime(&ms, g->ev_start, g->ev_sweep[0]));
+      const double us = std::max(1.0, (double)ms * 1e3);
+      look = (uint32_t)std::min<double>(kMaxLookahead, std::max(2.0, std::ceil(kHostReactUs / us) + 1.0));
+      g->lookahead = look;
     }
-    if (found >= 0) break;
-    if (next < max_sweeps && (st = enqueue()) != DG_OK) return st;
+    if (done(host + (size_t)(k + 1) * row, k)) {
+      found = (int)k;
+      break;
+    }
+    while (next < max_sweeps && next < k + 2 + look)
+      if ((st = enqueue()) != DG_OK) return st;
   }
   DG_HIP(hipStreamSynchronize(s));
   const uint32_t last = found >= 0 ? (uint32_t)found : max_sweeps - 1;
   converged = found >= 0;
   sweeps = last + 1;
   float ms = 0.f;
-  DG_HIP(hipEventElapsedTime(&ms, g->ev_start, g->ev_sweep[last % (2 * kSweepChunk)]));
+  DG_HIP(hipEventElapsedTime(&ms, g->ev_start, g->ev_sweep[last % kEventRing]));
   seconds = ms * 1e-3;
   return DG_OK;
 }
@@ -299,6 +315,7 @@ dg_status drive(dg_graph* g, uint32_t max_sweeps, hipStream_t s, const void* sta
 // Pinned host buffer for the batched entry points' state polls.
 struct PinnedBuf {
   void* p = nullptr;
+  void* dev = nullptr;  // device address of p
   ~PinnedBuf() {
     if (p) (void)hipHostFree(p);
   }
@@ -675,7 +692,7 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
   double secs = 0.0, resid = 0.0;
   bool conv = false;
   unsigned char* poll = static_cast<unsigned char*>(g->host_poll);
-  if ((st = drive(g, max_sweeps, s, g->resid, sizeof(double), 1, poll, launch, done, sweeps, secs, conv)) != DG_OK)
+  if ((st = drive(g, max_sweeps, s, sizeof(double), poll, launch, done, sweeps, secs, conv)) != DG_OK)
     return st;
   std::memcpy(&resid, poll + (size_t)sweeps * sizeof(double), sizeof(double));
 
@@ -770,7 +787,7 @@ dg_status sssp_run(dg_graph* g, uint32_t src, const uint32_t* more_src, uint32_t
   double secs = 0.0;
   bool conv = false;
   unsigned char* poll = static_cast<unsigned char*>(g->host_poll);
-  if ((st = drive(g, max_sweeps, s, g->changed, sizeof(uint32_t), 1, poll, launch, done, sweeps, secs, conv)) != DG_OK)
+  if ((st = drive(g, max_sweeps, s, sizeof(uint32_t), poll, launch, done, sweeps, secs, conv)) != DG_OK)
     return st;
   // The last executed sweep k = sweeps-1 wrote buffer (k+1) % 2 in sync mode.
   const uint32_t* res = (mode == DG_SYNC && (sweeps & 1)) ? b1 : b0;
@@ -842,7 +859,7 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
   if (!srcd || !b0 || (mode == DG_SYNC && !b1) || (mode == DG_DELAYED && !sh) || !changed || !outd)
     return fail(DG_ERR_OUT_OF_MEMORY, "batched SSSP workspace allocation failed");
   PinnedBuf poll;
-  DG_HIP(hipHostMalloc(&poll.p, ((size_t)max_sweeps + 1) * NB * 4, hipHostMallocDefault));
+  DG_HIP(alloc_mapped(&poll.p, &poll.dev, ((size_t)max_sweeps + 1) * NB * 4));
   DG_HIP(hipMemcpyAsync(srcd, sources, (size_t)k * 4, hipMemcpyHostToDevice, s));
   DG_HIP(launch_fill_u32(changed, ((size_t)max_sweeps + 1) * NB, 0u, s));
   DG_HIP(launch_fill_u32(changed, NB, 1u, s));
@@ -851,6 +868,7 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
   std::memset(&a, 0, sizeof a);  // call mode: no serving fields
   a.g = topo_batch(g);
   a.changed = changed;
+  a.hchanged = static_cast<uint32_t*>(poll.dev);
   a.shadow = sh;
   a.d = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_vb)) : 0u;
   a.NB = NB;
@@ -879,7 +897,7 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
   uint32_t sweeps = 0;
   double secs = 0.0;
   bool conv = false;
-  if ((st = drive(g, max_sweeps, s, changed, 4, NB, static_cast<unsigned char*>(poll.p), launch, done, sweeps, secs,
+  if ((st = drive(g, max_sweeps, s, (size_t)NB * 4, static_cast<unsigned char*>(poll.p), launch, done, sweeps, secs,
                   conv)) != DG_OK)
     return st;
   // The buffer sweep `sweeps-1` wrote holds every batch's final distances:
@@ -954,7 +972,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
       !scale || !qdone || !part || !qsum || !qpart || !outd)
     return fail(DG_ERR_OUT_OF_MEMORY, "batched PageRank workspace allocation failed");
   PinnedBuf poll;
-  DG_HIP(hipHostMalloc(&poll.p, ((size_t)max_sweeps + 1) * NB * 8, hipHostMallocDefault));
+  DG_HIP(alloc_mapped(&poll.p, &poll.dev, ((size_t)max_sweeps + 1) * NB * 8));
   DG_HIP(hipMemcpyAsync(srcd, sources, (size_t)k * 4, hipMemcpyHostToDevice, s));
   DG_HIP(launch_fill_f64(resid, ((size_t)max_sweeps + 1) * NB, 0.0, s));
   DG_HIP(launch_fill_f64(resid, NB, __builtin_inf(), s));
@@ -972,6 +990,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   a.shadow = sh;
   a.src = srcd;
   a.resid = resid;
+  a.hresid = static_cast<double*>(poll.dev);
   a.dang = dang;
   a.scale = scale;
   a.qdone = qdone;
@@ -1011,7 +1030,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   uint32_t sweeps = 0;
   double secs = 0.0;
   bool conv = false;
-  if ((st = drive(g, max_sweeps, s, resid, 8, NB, static_cast<unsigned char*>(poll.p), launch, done, sweeps, secs,
+  if ((st = drive(g, max_sweeps, s, (size_t)NB * 8, static_cast<unsigned char*>(poll.p), launch, done, sweeps, secs,
                   conv)) != DG_OK)
     return st;
   DG_HIP(launch_mppr_out(f64, x, qpart, qsum, g->n, k, NB, outd, s));

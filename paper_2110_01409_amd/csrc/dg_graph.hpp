@@ -14,9 +14,14 @@
 namespace dg {
 namespace host {
 
-// Sweeps queued ahead of the host's convergence check.  Each queued sweep
-// first tests on the device whether an earlier one met the stopping rule.
-constexpr uint32_t kSweepChunk = 8;
+// Sweeps the host keeps queued beyond the one whose result it waits for: at
+// most kMaxLookahead, and enough to cover about kHostReactUs of the host's
+// reaction time at the call's measured sweep time.  Each queued sweep first
+// tests on the device whether an earlier one met the stopping rule.
+constexpr uint32_t kMaxLookahead = 8;
+constexpr double kHostReactUs = 150.0;
+// Per-sweep completion events, reused round-robin (more than the lookahead).
+constexpr uint32_t kEventRing = 16;
 constexpr uint32_t kMaxSweeps = 1000000;
 // Default persistent workgroups per compute unit of the single-query sweeps:
 // one 1024-thread workgroup, whose LDS holds the resident table.
@@ -76,10 +81,11 @@ struct dg_graph {
   uint32_t ws_sweeps = 0;
   double *resid = nullptr, *dang = nullptr, *part = nullptr;
   uint32_t *count = nullptr, *changed = nullptr;
-  void* host_poll = nullptr;  // pinned [S+1] doubles
+  void* host_poll = nullptr;      // mapped pinned [S+1] doubles: the sweeps' stopping values
+  void* host_poll_dev = nullptr;  // its device address
+  uint32_t lookahead = 4;         // sweeps queued ahead, from the last call's sweep time
   hipEvent_t ev_start = nullptr;
-  hipEvent_t ev_sweep[2 * dg::host::kSweepChunk] = {};
-  hipEvent_t ev_copy[2] = {};
+  hipEvent_t ev_sweep[dg::host::kEventRing] = {};
   bool events = false;
 };
 

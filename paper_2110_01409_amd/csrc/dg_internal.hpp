@@ -73,6 +73,10 @@ struct SweepState {
   uint32_t* count;    // [S+1] workers finished in sweep k
   uint32_t* changed;  // [S+1] changed[k+1] != 0 iff sweep k decreased a distance
   double* part;       // [3P] per-worker partial sums (residual, non-dangling mass, total mass)
+  // Mapped host mirrors of resid and changed (device addresses of pinned
+  // host memory the host polls; same row indices), or null.
+  double* hresid = nullptr;
+  uint32_t* hchanged = nullptr;
 };
 
 struct PrArgs {
@@ -133,6 +137,7 @@ struct MbfArgs {
   uint32_t* changed;    // [(S+1)][NB] changed[(k+1)NB+b] != 0 iff sweep k changed batch b (call mode)
   uint32_t* lchg;       // serving: [NB][64] set to nonzero for every query that changed in the sweep, else null
   const uint32_t* bactive;  // serving: [NB] nonzero for batches with running queries, else null
+  uint32_t* hchanged = nullptr;  // mapped host mirror of changed (call mode), or null
   uint32_t k, d, NB;
 };
 
@@ -151,6 +156,7 @@ struct MpprArgs {
                             // [2][NB] ring and resid is unused), else null
   uint32_t* count;      // [(S+1)][NB] workers finished
   double* part;         // [P][NB][3][64] per-worker partials (change, dangling mass, total mass)
+  double* hresid = nullptr;  // mapped host mirror of resid (call mode), or null
   double alpha, tol;
   uint32_t nq, k, d, NB;
 };

@@ -40,7 +40,9 @@
 //   * Each worker reduces its residual / non-dangling mass (PageRank) or
 //     "changed" flag (Bellman-Ford) over its block; the last worker to finish
 //     sums the per-worker partials in worker order and publishes the values the
-//     next sweep reads, so termination is decided on the device.
+//     next sweep reads, so termination is decided on the device.  The stopping
+//     value is also stored into mapped host memory, which the host polls.
+#include "dg_device.hpp"
 #include "dg_internal.hpp"
 
 namespace dg {
@@ -524,8 +526,10 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
         r_max = fmax(r_max, s_red[i]);
         d_all += s_red[NW + i];
       }
-      a.st.resid[k + 1] = !a.wseg ? r_all : r_max;
+      const double r_k = !a.wseg ? r_all : r_max;
+      a.st.resid[k + 1] = r_k;
       a.st.dang[k + 1] = 1.0 - d_all;
+      if (a.st.hresid) st_host(a.st.hresid + k + 1, r_k);
     }
   }
 }
@@ -720,7 +724,10 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
   }
   const int anyb = __syncthreads_or(any);
   if (!a.wseg) {
-    if (anyb && tid == 0) st_agent(a.st.changed + k + 1, 1u);
+    if (anyb && tid == 0) {
+      st_agent(a.st.changed + k + 1, 1u);
+      if (a.st.hchanged) st_host(a.st.hchanged + k + 1, 1u);
+    }
     return;
   }
   // Graph sets: per-worker change flags; the last worker folds them per
@@ -750,7 +757,10 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
     if (!ch && a.gsweeps[gi] == 0) a.gsweeps[gi] = k + 1;
     ch_any |= ch;
   }
-  if (__syncthreads_or(ch_any) && tid == 0) st_agent(a.st.changed + k + 1, 1u);
+  if (__syncthreads_or(ch_any) && tid == 0) {
+    st_agent(a.st.changed + k + 1, 1u);
+    if (a.st.hchanged) st_host(a.st.hchanged + k + 1, 1u);
+  }
 }
 
 __global__ __launch_bounds__(kWG) void bf_init_kernel(uint32_t* d0, uint32_t* d1, const uint32_t* cpos, uint32_t n,
