@@ -114,6 +114,7 @@ typedef struct {
   uint32_t weight_bytes;      /* bytes per stored weight: 1 when every weight is
                                  <= 255, 4 otherwise, 0 without weights        */
   uint64_t device_bytes; /* device memory held by the graph (not workspace) */
+  uint32_t sweep_variant; /* DG_SWEEP_WIDE, _WIDE_INFLIGHT or _NARROW          */
 } dg_graph_info;
 
 /* Device memory hooks.  alloc(bytes, stream, ctx) returns device memory or
@@ -152,13 +153,34 @@ dg_status dg_set_allocator(dg_alloc_fn alloc, dg_free_fn free_fn, void* ctx);
  *                               four tiles of the reader earlier (the table
  *                               is refreshed a quarter at a time after each
  *                               tile), instead of at the moment of the read.
- *                 Results converge to the same fixed point / distances. */
+ *                 Results converge to the same fixed point / distances.
+ *   sweep_variant how the single-query sweep kernels spread a tile's in-edges
+ *                 over a workgroup's threads (all compute the same values):
+ *                   DG_SWEEP_WIDE       16 in-edges per thread, tiles of at
+ *                                       most 16380 in-edges; the gathers of a
+ *                                       wave are paced by its resident-table
+ *                                       reads (best with many tiles per worker)
+ *                   DG_SWEEP_WIDE_INFLIGHT
+ *                                       the same tiles, all of a thread's
+ *                                       gathers in flight at once
+ *                   DG_SWEEP_NARROW     8 per thread, tiles of at most 8188
+ *                                       in-edges, all gathers in flight (best
+ *                                       for small graphs)
+ *                 DG_SWEEP_AUTO (0): NARROW if the wide tiles number fewer
+ *                 than 2 per default worker, else WIDE_INFLIGHT up to 8 per
+ *                 default worker, else WIDE.  The choice is reported in
+ *                 dg_graph_info.sweep_variant. */
 #define DG_HOT_AUTO 0xFFFFFFFFu
 #define DG_RESIDENT_AUTO 0xFFFFFFFFu
+#define DG_SWEEP_AUTO 0u
+#define DG_SWEEP_WIDE 1u
+#define DG_SWEEP_WIDE_INFLIGHT 2u
+#define DG_SWEEP_NARROW 3u
 typedef struct {
   uint32_t workers;
   uint32_t hot_vertices;
   uint32_t resident_vertices;
+  uint32_t sweep_variant;
 } dg_graph_opts;
 
 /* Upload a graph and build its in-edge form (pull sweeps need in-neighbours,
@@ -214,6 +236,7 @@ typedef struct {
   uint64_t resident_edges;
   uint32_t weight_bytes;      /* 1, 4, or 0 without weights                     */
   uint64_t content_hash;      /* hash of the in-edge form (the tuning cache key) */
+  uint32_t sweep_variant;     /* DG_SWEEP_WIDE, _WIDE_INFLIGHT or _NARROW        */
 } dg_plan_info;
 dg_status dg_plan_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
                          const uint32_t* w, const dg_graph_opts* opts, uint32_t compute_units, dg_plan** out);

@@ -116,6 +116,7 @@ Topology topo(const dg_graph* g) {
   t.n = g->n;
   t.K = g->K;
   t.P = g->P;
+  t.variant = g->variant;
   return t;
 }
 
@@ -441,24 +442,6 @@ dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
   g->m = m;
   g->has_w = (w != nullptr);
 
-  // The layout every sweep reads (the same construction dg_plan_create
-  // returns without a device).
-  Layout L;
-  if ((st = build_layout(n, m, layout, ptr, idx, w, opts, L, seg_v)) != DG_OK) {
-    delete g;
-    return st;
-  }
-  g->K = L.K;
-  g->R = L.R;
-  g->hot_edges = L.hot_edges;
-  g->res_edges = L.res_edges;
-  g->max_in_deg = L.max_in_deg;
-  g->n_dangling = L.n_dangling;
-  g->hash = L.hash;
-  g->T = L.T();
-  g->tile_v_h = L.tile_v;
-  g->tile_e0_h = L.tile_e0;
-
   // Device sizes.  Without a device (or on error) nothing below leaks.
   int dev = 0, cus = 0;
   hipError_t he = hipGetDevice(&dev);
@@ -472,7 +455,28 @@ dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
   }
   g->cus = (uint32_t)cus;
   g->lds_per_block = (size_t)lds;
-  uint32_t P = plan_workers(L, opts ? opts->workers : 0u, g->cus, seg_v ? kSetWorkersPerCU : kWorkersPerCU);
+
+  // The layout every sweep reads (the same construction dg_plan_create
+  // returns without a device).
+  const uint32_t per_cu = seg_v ? kSetWorkersPerCU : kWorkersPerCU;
+  Layout L;
+  if ((st = build_layout(n, m, layout, ptr, idx, w, opts, opts && opts->workers ? opts->workers : g->cus * per_cu, L,
+                         seg_v)) != DG_OK) {
+    delete g;
+    return st;
+  }
+  g->K = L.K;
+  g->R = L.R;
+  g->hot_edges = L.hot_edges;
+  g->res_edges = L.res_edges;
+  g->max_in_deg = L.max_in_deg;
+  g->n_dangling = L.n_dangling;
+  g->hash = L.hash;
+  g->T = L.T();
+  g->variant = L.variant;
+  g->tile_v_h = L.tile_v;
+  g->tile_e0_h = L.tile_e0;
+  uint32_t P = plan_workers(L, opts ? opts->workers : 0u, g->cus, per_cu);
   std::vector<uint32_t> work_t;
   if (seg_v) {
     g->G = (uint32_t)seg_v->size() - 1;
@@ -563,6 +567,7 @@ dg_status dg_graph_info_get(const dg_graph* g, dg_graph_info* info) {
   info->resident_edges = g->res_edges;
   info->weight_bytes = g->in_w8 ? 1u : (g->in_w ? 4u : 0u);
   info->device_bytes = g->graph_bytes;
+  info->sweep_variant = g->variant;
   return DG_OK;
 }
 

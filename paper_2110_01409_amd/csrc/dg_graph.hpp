@@ -34,6 +34,14 @@ constexpr uint32_t kBatchWorkersPerCU = 5;
 // (the others' workers exit at once) still spread over the whole GPU.
 // Three to five measured best on a 64-graph set.
 constexpr uint32_t kSetWorkersPerCU = 5;
+// Automatic sweep variant: narrow below kNarrowBelow wide tiles per worker,
+// wide with all gathers in flight up to kInFlightUpTo, wide beyond.
+// Measured per float32 PageRank sweep on R-MAT with 256 workers: narrow
+// wins up to scale 18 (27.5 against 34.8 us at scale 16, synchronous),
+// all-in-flight at scale 20 (80 against 96 us), the paced wide variant at
+// scale 22 (4680 tiles).
+constexpr uint64_t kNarrowBelow = 2;
+constexpr uint64_t kInFlightUpTo = 8;
 
 }  // namespace host
 }  // namespace dg
@@ -43,6 +51,7 @@ struct dg_graph {
   uint64_t m = 0;
   bool has_w = false;
   uint32_t P = 0, T = 0, cus = 0, max_in_deg = 0, n_dangling = 0;
+  uint32_t variant = 0;  // SweepVariant of the single-query sweeps
   uint32_t K = 0;          // sources stored in the compact region
   uint32_t max_block_v = 1;  // most vertices any worker owns
   // Partition of the same tiles for the batched kernels (dg_sssp_batch,

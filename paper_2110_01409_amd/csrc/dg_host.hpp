@@ -22,11 +22,11 @@ dg_status fail(dg_status s, const char* fmt, ...);
 // Allocation hooks installed by dg_set_allocator (both null: hipMalloc/hipFree).
 void current_allocator(dg_alloc_fn& alloc, dg_free_fn& free_fn, void*& ctx);
 
-// Tiles of consecutive vertices: at most kTileV vertices and kTileE in-edges,
+// Tiles of consecutive vertices: at most kTileV vertices and max_e in-edges,
 // except that a vertex with more in-edges is a tile of its own; a tile also
 // ends before every vertex listed in seg_v (the graphs of a set).
 void build_tiles(const std::vector<uint32_t>& in_ptr, uint32_t n, std::vector<uint32_t>& tile_v,
-                 const std::vector<uint32_t>* seg_v = nullptr);
+                 const std::vector<uint32_t>* seg_v, uint32_t max_e);
 
 }  // namespace host
 }  // namespace dg

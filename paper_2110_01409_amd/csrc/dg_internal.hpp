@@ -14,10 +14,27 @@ constexpr int kWG = 256;
 // compute unit, so that one LDS copy of the hottest sources (the resident
 // table) can take most of the unit's 160 KB.
 constexpr int kSweepWG = 1024;
-// Consecutive in-edges one thread reduces per chunk (four 16-byte index loads).
-// Sixteen measured 7% faster per sweep than eight with one sweep workgroup
-// per compute unit: twice the loads in flight per thread, half the tiles.
+// Consecutive in-edges one thread reduces per chunk in the wide sweep
+// variants (four 16-byte index loads); the narrow variant takes half.
 constexpr int kEPT = 16;
+constexpr int kEPTNarrow = 8;
+
+// Sweep kernel variants, chosen per graph when it is created (the values
+// are those of dg_graph_opts.sweep_variant):
+//   kWide          16 in-edges per thread; a resident-table slot is read
+//                  from LDS right after its gather is issued, which makes the
+//                  wave wait for its outstanding loads and so paces its
+//                  gathers.  Fastest on graphs with many tiles per worker,
+//                  where the gathers of all workers saturate the memory path.
+//   kWideInFlight  16 per thread; all of a chunk's gathers are issued before
+//                  the table is read.  Fastest at a few tiles per worker.
+//   kNarrow        8 per thread (tiles of at most kTileENarrow in-edges),
+//                  all gathers in flight: more, shorter tiles for graphs too
+//                  small to give every worker two wide tiles, whose sweeps
+//                  are bound by a tile's latency.
+enum SweepVariant : uint32_t { kWide = 1, kWideInFlight = 2, kNarrow = 3 };
+__host__ __device__ constexpr int ept_of(int v) { return v == kNarrow ? kEPTNarrow : kEPT; }
+__host__ __device__ constexpr bool all_in_flight(int v) { return v != kWide; }
 // Edge slots a sweep workgroup covers per chunk.
 constexpr int kChunk = kSweepWG * kEPT;
 // At most this many vertices per tile: one vertex per thread in the update phase.
@@ -27,6 +44,7 @@ constexpr int kTileV = kSweepWG;
 // tile of at most kChunk-4 edges always fits one chunk.  A single vertex with
 // more in-edges gets a tile of its own that spans several chunks.
 constexpr int kTileE = kChunk - 4;
+constexpr int kTileENarrow = kSweepWG * kEPTNarrow - 4;
 // Zero padding after in_src / in_w so that the last chunk's vector loads stay
 // inside the allocation.
 constexpr uint32_t kEdgePad = kChunk + 16;
@@ -62,6 +80,7 @@ struct Topology {
   uint32_t n;
   uint32_t K;               // slots of the compact region after the n regular ones
   uint32_t P;               // workers = workgroups launched per sweep
+  uint32_t variant;         // SweepVariant of the single-query sweeps
 };
 
 // Per-call convergence state, indexed by sweep.  Sweep k reads entry k and

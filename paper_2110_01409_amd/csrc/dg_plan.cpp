@@ -27,7 +27,7 @@ uint64_t hash_words(uint64_t h, const uint32_t* p, size_t n) {
 }  // namespace
 
 void build_tiles(const std::vector<uint32_t>& in_ptr, uint32_t n, std::vector<uint32_t>& tile_v,
-                 const std::vector<uint32_t>* seg_v) {
+                 const std::vector<uint32_t>* seg_v, uint32_t max_e) {
   tile_v.clear();
   tile_v.push_back(0);
   uint32_t nv = 0;
@@ -42,7 +42,7 @@ void build_tiles(const std::vector<uint32_t>& in_ptr, uint32_t n, std::vector<ui
         ++next_seg;
       }
     }
-    if (nv > 0 && (boundary || nv == (uint32_t)kTileV || ne + deg > (uint64_t)kTileE)) {
+    if (nv > 0 && (boundary || nv == (uint32_t)kTileV || ne + deg > (uint64_t)max_e)) {
       tile_v.push_back(v);
       nv = 0;
       ne = 0;
@@ -130,8 +130,10 @@ dg_status validate_graph(uint32_t n, uint64_t m, dg_layout layout, const uint64_
 }
 
 dg_status build_layout(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
-                       const uint32_t* w, const dg_graph_opts* opts, Layout& L,
+                       const uint32_t* w, const dg_graph_opts* opts, uint32_t workers, Layout& L,
                        const std::vector<uint32_t>* seg_v) {
+  const uint32_t variant = opts ? opts->sweep_variant : DG_SWEEP_AUTO;
+  if (variant > DG_SWEEP_NARROW) return fail(DG_ERR_INVALID_ARGUMENT, "unknown sweep_variant %u", variant);
   uint32_t hot_max = (!opts || opts->hot_vertices == DG_HOT_AUTO) ? 524288u : opts->hot_vertices;
   hot_max = std::min<uint32_t>(hot_max, 0xFFFFFFFEu - n);
   const bool res_auto = !opts || opts->resident_vertices == DG_RESIDENT_AUTO;
@@ -212,7 +214,15 @@ dg_status build_layout(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
       L.max_in_deg = std::max(L.max_in_deg, L.in_ptr[v + 1] - L.in_ptr[v]);
       L.n_dangling += L.out_deg[v] == 0;
     }
-    build_tiles(L.in_ptr, n, L.tile_v, seg_v);
+    // Sweep variant (SweepVariant): the wide tiles, or the narrow ones when
+    // the wide give fewer than kNarrowBelow tiles per worker.
+    build_tiles(L.in_ptr, n, L.tile_v, seg_v, (uint32_t)kTileE);
+    const uint64_t T = L.tile_v.size() - 1, P = std::max(1u, workers);
+    L.variant = variant != DG_SWEEP_AUTO ? variant
+                : T < kNarrowBelow * P       ? (uint32_t)kNarrow
+                : T <= kInFlightUpTo * P     ? (uint32_t)kWideInFlight
+                                             : (uint32_t)kWide;
+    if (L.variant == kNarrow) build_tiles(L.in_ptr, n, L.tile_v, seg_v, (uint32_t)kTileENarrow);
     L.tile_e0.resize(L.tile_v.size());
     for (size_t t = 0; t < L.tile_v.size(); ++t) L.tile_e0[t] = L.in_ptr[L.tile_v[t]];
     uint64_t h = 0xcbf29ce484222325ull;
@@ -269,7 +279,8 @@ dg_status dg_plan_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_
   if (st != DG_OK) return st;
   dg_plan* p = new (std::nothrow) dg_plan;
   if (!p) return fail(DG_ERR_OUT_OF_MEMORY, "host allocation failed");
-  if ((st = dg::host::build_layout(n, m, layout, ptr, idx, w, opts, p->L)) != DG_OK) {
+  const uint32_t workers = opts && opts->workers ? opts->workers : compute_units * dg::host::kWorkersPerCU;
+  if ((st = dg::host::build_layout(n, m, layout, ptr, idx, w, opts, workers, p->L)) != DG_OK) {
     delete p;
     return st;
   }
@@ -299,6 +310,7 @@ dg_status dg_plan_info_get(const dg_plan* p, dg_plan_info* info) {
   info->resident_edges = L.res_edges;
   info->weight_bytes = !L.has_w ? 0u : (L.w8pack.empty() ? 4u : 1u);
   info->content_hash = L.hash;
+  info->sweep_variant = L.variant;
   return DG_OK;
 }
 

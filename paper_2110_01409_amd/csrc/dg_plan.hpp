@@ -31,6 +31,7 @@ struct Layout {
   std::vector<uint32_t> cpos;     // [n] slot of each vertex's published value
   std::vector<uint32_t> tile_v;   // [T+1] first vertex of each tile
   std::vector<uint32_t> tile_e0;  // [T+1] first in-edge of each tile
+  uint32_t variant = 0;           // SweepVariant of the single-query sweeps
   uint32_t T() const { return (uint32_t)tile_v.size() - 1; }
 };
 
@@ -38,13 +39,15 @@ struct Layout {
 dg_status validate_graph(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx);
 
 // Builds everything but the worker partition from validated arrays.
+// `workers` is the partition's worker count, which the automatic sweep
+// variant is chosen for.
 // Returns DG_ERR_OUT_OF_MEMORY on host allocation failure and
 // DG_ERR_UNSUPPORTED when n plus the compact region exceeds the slots a
 // sweep can address.
 // seg_v (optional, [G+1]): first vertices of the graphs of a set; no tile
 // crosses one of them.
 dg_status build_layout(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
-                       const uint32_t* w, const dg_graph_opts* opts, Layout& L,
+                       const uint32_t* w, const dg_graph_opts* opts, uint32_t workers, Layout& L,
                        const std::vector<uint32_t>* seg_v = nullptr);
 
 // Worker count for a device of `cus` compute units: want_workers if set,

@@ -128,10 +128,11 @@ dg_status dg_set_create(uint32_t count, const dg_graph_desc* graphs, const dg_se
     delete s;
     return fail(DG_ERR_OUT_OF_MEMORY, "host allocation failed while building the set");
   }
-  dg_graph_opts go;
+  dg_graph_opts go{};
   go.workers = opts ? opts->workers : 0u;
   go.hot_vertices = DG_HOT_AUTO;
   go.resident_vertices = DG_RESIDENT_AUTO;
+  go.sweep_variant = DG_SWEEP_AUTO;
   dg_status st = dg::host::graph_create((uint32_t)N, M, DG_CSR, ptr.data(), M ? idx.data() : nullptr,
                                         weighted == 1 ? w.data() : nullptr, &go, &s->voff, hip_stream, &s->g);
   if (st != DG_OK) {

@@ -10,12 +10,13 @@
 //     XCDs (workgroups are dispatched to XCDs round-robin) owns one contiguous
 //     eighth of the vertex range.
 //   * A worker is one 1024-thread workgroup.  A tile holds <= 1024 vertices
-//     and <= 16380 in-edges, or one vertex with more.  Its edges are
-//     processed in chunks of 16384 slots starting at the tile's first edge
-//     rounded down to a multiple of 4: thread t reduces the 16 consecutive
-//     slots [16t, 16t+16) of the chunk, fetched with four 16-byte loads of the
-//     index stream (and one or four of the weight stream), then 16
-//     independent gathers.
+//     and <= 1024 * EPT - 4 in-edges, or one vertex with more, where EPT is
+//     16 (wide variants) or 8 (narrow variant), chosen per graph.  Its edges
+//     are processed in chunks of 1024 * EPT slots starting at the tile's
+//     first edge rounded down to a multiple of 4: thread t reduces the EPT
+//     consecutive slots [EPT t, EPT t + EPT) of the chunk, fetched with
+//     16-byte loads of the index stream (and one load of byte weights),
+//     then EPT independent gathers.
 //     Partial sums (or minima) per vertex go to LDS with ds_add_f64 /
 //     ds_min_u32 once per vertex boundary crossed; a single-vertex tile uses a
 //     wavefront shuffle reduction and one LDS atomic per wave instead.
@@ -126,16 +127,17 @@ __device__ __forceinline__ rsrc_t make_rsrc(const void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
-// kEPT consecutive 4-byte words of the in-edge stream for one thread, in
+// EPT consecutive 4-byte words of the in-edge stream for one thread, in
 // 16-byte loads.  The window [nb, lim) is rounded up to whole 16-byte groups
 // so that each load is entirely inside or outside it.
+template <int EPT>
 __device__ __forceinline__ void load_win(const uint32_t* stream, uint32_t nb, uint32_t lim, uint32_t tid,
-                                         uint32_t (&u)[kEPT]) {
+                                         uint32_t (&u)[EPT]) {
   const uint32_t end = (lim + 3u) & ~3u;
   const rsrc_t r = make_rsrc(stream + nb, end > nb ? (end - nb) * 4u : 0u);
 #pragma unroll
-  for (int q = 0; q < kEPT / 4; ++q) {
-    const v4u v = __builtin_amdgcn_raw_buffer_load_b128(r, tid * (4u * kEPT) + 16u * q, 0, 0);
+  for (int q = 0; q < EPT / 4; ++q) {
+    const v4u v = __builtin_amdgcn_raw_buffer_load_b128(r, tid * (4u * EPT) + 16u * q, 0, 0);
     u[4 * q] = v.x;
     u[4 * q + 1] = v.y;
     u[4 * q + 2] = v.z;
@@ -143,28 +145,39 @@ __device__ __forceinline__ void load_win(const uint32_t* stream, uint32_t nb, ui
   }
 }
 
-// The same for a stream of one-byte weights: kEPT = 16 bytes per thread, one
-// 16-byte load (4-byte aligned, as buffer loads need), widened to uint32.
-static_assert(kEPT == 16, "load_win_u8 reads 16 one-byte weights per thread");
+// The same for a stream of one-byte weights: EPT bytes per thread in one
+// load (4-byte aligned, as buffer loads need), widened to uint32.
+template <int EPT>
 __device__ __forceinline__ void load_win_u8(const uint8_t* stream, uint32_t nb, uint32_t lim, uint32_t tid,
-                                            uint32_t (&u)[kEPT]) {
-  const uint32_t end = (lim + 15u) & ~15u;
+                                            uint32_t (&u)[EPT]) {
+  static_assert(EPT == 8 || EPT == 16, "one 8- or 16-byte load per thread");
+  const uint32_t end = (lim + (EPT - 1)) & ~(uint32_t)(EPT - 1);
   const rsrc_t r = make_rsrc(stream + nb, end > nb ? end - nb : 0u);
-  const v4u q = __builtin_amdgcn_raw_buffer_load_b128(r, tid * 16u, 0, 0);
+  if constexpr (EPT == 16) {
+    const v4u q = __builtin_amdgcn_raw_buffer_load_b128(r, tid * 16u, 0, 0);
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    u[j] = (q.x >> (8 * j)) & 255u;
-    u[4 + j] = (q.y >> (8 * j)) & 255u;
-    u[8 + j] = (q.z >> (8 * j)) & 255u;
-    u[12 + j] = (q.w >> (8 * j)) & 255u;
+    for (int j = 0; j < 4; ++j) {
+      u[j] = (q.x >> (8 * j)) & 255u;
+      u[4 + j] = (q.y >> (8 * j)) & 255u;
+      u[8 + j] = (q.z >> (8 * j)) & 255u;
+      u[12 + j] = (q.w >> (8 * j)) & 255u;
+    }
+  } else {
+    const v2u q = __builtin_amdgcn_raw_buffer_load_b64(r, tid * 8u, 0, 0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      u[j] = (q.x >> (8 * j)) & 255u;
+      u[4 + j] = (q.y >> (8 * j)) & 255u;
+    }
   }
 }
 
 // Weights of the next chunk, from whichever stream the graph keeps.
+template <int EPT>
 __device__ __forceinline__ void load_weights(const Topology& g, uint32_t nb, uint32_t lim, uint32_t tid,
-                                             uint32_t (&u)[kEPT]) {
-  if (g.in_w8) load_win_u8(g.in_w8, nb, lim, tid, u);
-  else load_win(g.in_w, nb, lim, tid, u);
+                                             uint32_t (&u)[EPT]) {
+  if (g.in_w8) load_win_u8<EPT>(g.in_w8, nb, lim, tid, u);
+  else load_win<EPT>(g.in_w, nb, lim, tid, u);
 }
 
 // Gather of a published value; out-of-range offsets read 0.  Asynchronous
@@ -189,7 +202,7 @@ __device__ __forceinline__ T gather(rsrc_t r, uint32_t off) {
 // sweep (exact for a synchronous sweep, whose input does not change during
 // the sweep).  Asynchronous and delayed sweeps refresh one segment of
 // kResSegBytes after every tile, so no entry is older than
-// ceil(res / segment) tiles of the reader (3 at the default size): the
+// ceil(res / segment) tiles of the reader (4 at the default size): the
 // segment's loads are issued after the barrier that ends a tile's gathers
 // (the chunk registers are free then) and written to LDS after the barrier
 // that ends the tile, before the barrier that starts the next tile's gathers.
@@ -239,8 +252,10 @@ struct ResTable {
 // block: this sweep's for vertices already updated, else the one committed at
 // the end of the previous sweep.  Sources in the compact region are read from
 // the committed array.
-template <int M, typename T, bool LOCAL = false>
+template <int M, typename T, bool LOCAL, int V>
 __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
+  constexpr int EPT = ept_of(V);
+  constexpr uint32_t CH = kSweepWG * EPT;  // edge slots per chunk
   __shared__ uint32_t s_ptr[kTileV + 1];
   __shared__ double s_acc[kTileV];
   __shared__ double s_red[3 * (kSweepWG / 64)];
@@ -291,7 +306,7 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
   // ahead (software pipelining): while a chunk's gathers are in flight the
   // following chunk's indices, of this tile or of the worker's next tile,
   // are already on their way.
-  uint32_t u[kEPT];
+  uint32_t u[EPT];
   // Per-vertex inputs of a tile's update phase (old score, out-degree, slot)
   // and the next tile's offsets are loaded during the previous tile's last
   // chunk, next to the index prefetch, with branch-free clamped loads.
@@ -302,7 +317,7 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
     if (tid <= nv0) s_ptr[tid] = a.g.in_ptr[v0 + tid];
     if (tid == 0 && nv0 == kTileV) s_ptr[kTileV] = a.g.in_ptr[v0 + kTileV];
     const uint32_t b0 = as_const(a.g.in_ptr)[v0] & ~3u;
-    load_win(a.g.in_src, b0, as_const(a.g.in_ptr)[tile_v[t0 + 1]], tid, u);
+    load_win<EPT>(a.g.in_src, b0, as_const(a.g.in_ptr)[tile_v[t0 + 1]], tid, u);
     const uint32_t vi = min(v0 + tid, n - 1);
     xo_n = x[vi];
     dg_n = a.g.out_deg[vi];
@@ -332,14 +347,18 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
     if (tid < nv) s_acc[tid] = 0.0;
     lds_barrier();
     const uint32_t eb = s_ptr[0], ee = s_ptr[nv];
-    for (uint32_t cb = eb & ~3u; cb < ee; cb += kChunk) {
-      const uint32_t e0 = cb + tid * kEPT;
-      const bool active = (e0 < ee) && (e0 + kEPT > eb);
-      // Branch-free: slots outside the tile gather c[0] and are zeroed, so
-      // the eight gathers are all in flight together.
-      T raw[kEPT];
+    for (uint32_t cb = eb & ~3u; cb < ee; cb += CH) {
+      const uint32_t e0 = cb + tid * EPT;
+      const bool active = (e0 < ee) && (e0 + EPT > eb);
+      // Branch-free: slots outside the tile, and slots in the resident table,
+      // read 0 without a memory access.  A table slot's value comes from LDS
+      // into the same register: in the wide variant right after its gather is
+      // issued (the LDS read then waits for the loads before it, which paces
+      // the wave's gathers), else once all of the chunk's gathers are in
+      // flight (see SweepVariant).
+      T raw[EPT];
 #pragma unroll
-      for (int j = 0; j < kEPT; ++j) {
+      for (int j = 0; j < EPT; ++j) {
         const bool ok = (e0 + j >= eb) & (e0 + j < ee);
         const uint32_t ri = u[j] - n;  // resident index (wraps for regular slots)
         const bool inres = ok & (ri < rt.res);
@@ -350,33 +369,46 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
         } else {
           raw[j] = gather<M, T>(rc, (ok & !inres) ? u[j] * (uint32_t)sizeof(T) : kOut);
         }
-        if (inres) raw[j] = rt.lds[ri];
+        if constexpr (!all_in_flight(V)) {
+          if (inres) raw[j] = rt.lds[ri];
+        }
+      }
+      if constexpr (all_in_flight(V)) {
+        if (rt.res) {
+#pragma unroll
+          for (int j = 0; j < EPT; ++j) {
+            const uint32_t ri = u[j] - n;
+            const bool inres = (e0 + j >= eb) & (e0 + j < ee) & (ri < rt.res);
+            const T r = rt.lds[inres ? ri : 0u];
+            raw[j] = inres ? r : raw[j];
+          }
+        }
       }
       // Prefetch the next chunk's indices: the next chunk of this tile, else
       // the first chunk of the next tile (its window starts at this tile's
       // last edge rounded down), else nothing.
-      const bool last = cb + kChunk >= ee;
-      const uint32_t nb = !last ? cb + kChunk : (more ? (ee & ~3u) : cb);
+      const bool last = cb + CH >= ee;
+      const uint32_t nb = !last ? cb + CH : (more ? (ee & ~3u) : cb);
       const uint32_t lim = !last ? ee : (more ? ee_next : cb);
-      load_win(a.g.in_src, nb, lim, tid, u);
+      load_win<EPT>(a.g.in_src, nb, lim, tid, u);
       if (last) prefetch_next();
-      double val[kEPT];
+      double val[EPT];
 #pragma unroll
-      for (int j = 0; j < kEPT; ++j) val[j] = (double)raw[j];
+      for (int j = 0; j < EPT; ++j) val[j] = (double)raw[j];
       if (nv == 1) {
         double q = 0.0;
 #pragma unroll
-        for (int j = 0; j < kEPT; ++j) q += val[j];
+        for (int j = 0; j < EPT; ++j) q += val[j];
         q = wave_sum(q);
         if (lane == 0) atomicAdd(&s_acc[0], q);
       } else if (active) {
         const uint32_t es = e0 > eb ? e0 : eb;
-        const uint32_t en = (e0 + kEPT < ee) ? e0 + kEPT : ee;
+        const uint32_t en = (e0 + EPT < ee) ? e0 + EPT : ee;
         uint32_t i = owner_of(s_ptr, nv, es);
         uint32_t bound = s_ptr[i + 1];
         double part = 0.0;
 #pragma unroll
-        for (int j = 0; j < kEPT; ++j) {
+        for (int j = 0; j < EPT; ++j) {
           const uint32_t e = e0 + j;
           if (e >= es && e < en) {
             if (e >= bound) {
@@ -392,7 +424,7 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
     }
     if (eb >= ee) {
       // A tile without in-edges ran no chunk: fetch the next tile's window here.
-      if (more) load_win(a.g.in_src, ee & ~3u, ee_next, tid, u);
+      if (more) load_win<EPT>(a.g.in_src, ee & ~3u, ee_next, tid, u);
       prefetch_next();
     }
     lds_barrier();
@@ -560,8 +592,10 @@ __global__ __launch_bounds__(kWG) void pr_init_kernel(T* x, T* c0, T* c1, const 
 
 // LOCAL: as for pr_sweep_kernel, reads of this worker's own vertices come
 // from its shadow (delayed mode with the per-vertex shadow only).
-template <int M, bool LOCAL = false>
+template <int M, bool LOCAL, int V>
 __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
+  constexpr int EPT = ept_of(V);
+  constexpr uint32_t CH = kSweepWG * EPT;  // edge slots per chunk
   __shared__ uint32_t s_ptr[kTileV + 1];
   __shared__ uint32_t s_acc[kTileV];
   extern __shared__ __align__(16) unsigned char s_dyn[];
@@ -592,7 +626,7 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
   const uint32_t bv0 = tile_v[t0], bv1 = tile_v[t1];  // this worker's vertex block
 
   uint32_t v0 = tile_v[t0];
-  uint32_t u[kEPT], wt[kEPT];  // next chunk's indices and weights, loaded one chunk ahead
+  uint32_t u[EPT], wt[EPT];  // next chunk's indices and weights, loaded one chunk ahead
   uint32_t p_n = 0, nxt = 0, nxt_end = 0;
   if (t0 < t1) {
     const uint32_t nv0 = tile_v[t0 + 1] - v0;
@@ -600,8 +634,8 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
     if (tid == 0 && nv0 == kTileV) s_ptr[kTileV] = a.g.in_ptr[v0 + kTileV];
     const uint32_t b0 = as_const(a.g.in_ptr)[v0] & ~3u;
     const uint32_t l0 = as_const(a.g.in_ptr)[tile_v[t0 + 1]];
-    load_win(a.g.in_src, b0, l0, tid, u);
-    load_weights(a.g, b0, l0, tid, wt);
+    load_win<EPT>(a.g.in_src, b0, l0, tid, u);
+    load_weights<EPT>(a.g, b0, l0, tid, wt);
     p_n = a.g.cpos[min(v0 + tid, n - 1)];
   }
   for (uint32_t t = t0; t < t1; ++t) {
@@ -620,13 +654,13 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
     if (tid < nv) s_acc[tid] = kInf;
     lds_barrier();
     const uint32_t eb = s_ptr[0], ee = s_ptr[nv];
-    for (uint32_t cb = eb & ~3u; cb < ee; cb += kChunk) {
-      const uint32_t e0 = cb + tid * kEPT;
-      const bool active = (e0 < ee) && (e0 + kEPT > eb);
-      bool ok[kEPT];
-      uint32_t du[kEPT], wc[kEPT];
+    for (uint32_t cb = eb & ~3u; cb < ee; cb += CH) {
+      const uint32_t e0 = cb + tid * EPT;
+      const bool active = (e0 < ee) && (e0 + EPT > eb);
+      bool ok[EPT];
+      uint32_t du[EPT], wc[EPT];
 #pragma unroll
-      for (int j = 0; j < kEPT; ++j) {
+      for (int j = 0; j < EPT; ++j) {
         ok[j] = (e0 + j >= eb) & (e0 + j < ee);
         const uint32_t ri = u[j] - n;
         const bool inres = ok[j] & (ri < rt.res);
@@ -637,32 +671,45 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
         } else {
           du[j] = gather<M, uint32_t>(rd, (ok[j] & !inres) ? u[j] * 4u : kOut);
         }
-        if (inres) du[j] = rt.lds[ri];
+        if constexpr (!all_in_flight(V)) {
+          if (inres) du[j] = rt.lds[ri];
+        }
         wc[j] = wt[j];
       }
-      const bool last = cb + kChunk >= ee;
-      const uint32_t nb = !last ? cb + kChunk : (more ? (ee & ~3u) : cb);
-      const uint32_t lim = !last ? ee : (more ? ee_next : cb);
-      load_win(a.g.in_src, nb, lim, tid, u);
-      load_weights(a.g, nb, lim, tid, wt);
-      if (last) prefetch_next();
-      uint32_t cand[kEPT];
+      if constexpr (all_in_flight(V)) {
+        if (rt.res) {
 #pragma unroll
-      for (int j = 0; j < kEPT; ++j) cand[j] = ok[j] ? sat_add(du[j], wc[j]) : kInf;
+          for (int j = 0; j < EPT; ++j) {
+            const uint32_t ri = u[j] - n;
+            const bool inres = ok[j] & (ri < rt.res);
+            const uint32_t r = rt.lds[inres ? ri : 0u];
+            du[j] = inres ? r : du[j];
+          }
+        }
+      }
+      const bool last = cb + CH >= ee;
+      const uint32_t nb = !last ? cb + CH : (more ? (ee & ~3u) : cb);
+      const uint32_t lim = !last ? ee : (more ? ee_next : cb);
+      load_win<EPT>(a.g.in_src, nb, lim, tid, u);
+      load_weights<EPT>(a.g, nb, lim, tid, wt);
+      if (last) prefetch_next();
+      uint32_t cand[EPT];
+#pragma unroll
+      for (int j = 0; j < EPT; ++j) cand[j] = ok[j] ? sat_add(du[j], wc[j]) : kInf;
       if (nv == 1) {
         uint32_t q = kInf;
 #pragma unroll
-        for (int j = 0; j < kEPT; ++j) q = cand[j] < q ? cand[j] : q;
+        for (int j = 0; j < EPT; ++j) q = cand[j] < q ? cand[j] : q;
         q = wave_min(q);
         if (lane == 0 && q != kInf) atomicMin(&s_acc[0], q);
       } else if (active) {
         const uint32_t es = e0 > eb ? e0 : eb;
-        const uint32_t en = (e0 + kEPT < ee) ? e0 + kEPT : ee;
+        const uint32_t en = (e0 + EPT < ee) ? e0 + EPT : ee;
         uint32_t i = owner_of(s_ptr, nv, es);
         uint32_t bound = s_ptr[i + 1];
         uint32_t part = kInf;
 #pragma unroll
-        for (int j = 0; j < kEPT; ++j) {
+        for (int j = 0; j < EPT; ++j) {
           const uint32_t e = e0 + j;
           if (e >= es && e < en) {
             if (e >= bound) {
@@ -678,8 +725,8 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
     }
     if (eb >= ee) {
       if (more) {
-        load_win(a.g.in_src, ee & ~3u, ee_next, tid, u);
-        load_weights(a.g, ee & ~3u, ee_next, tid, wt);
+        load_win<EPT>(a.g.in_src, ee & ~3u, ee_next, tid, u);
+        load_weights<EPT>(a.g, ee & ~3u, ee_next, tid, wt);
       }
       prefetch_next();
     }
@@ -845,34 +892,42 @@ hipError_t launch_pr_init(bool f64, void* x, void* c0, void* c1, const uint32_t*
   return hipGetLastError();
 }
 
-// The sweep kernels take more dynamic LDS than the default 64 KB limit.
-template <typename K>
-static void allow_dyn_lds(K kernel) {
-  static bool done = false;  // once per kernel instance
-  if (!done) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+// The sweep kernels take more dynamic LDS than the default 64 KB limit; the
+// attribute is set once per kernel instance.
+template <auto Kernel>
+static void allow_dyn_lds() {
+  static const bool done = [] {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(Kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)kSweepDynLds);
-    done = true;
-  }
+    return true;
+  }();
+  (void)done;
 }
 
-template <int M, typename T, bool LOCAL = false>
+template <int M, typename T, bool LOCAL, int V>
 static void pr_sweep_go(const PrArgs& a, hipStream_t s) {
-  allow_dyn_lds(pr_sweep_kernel<M, T, LOCAL>);
-  pr_sweep_kernel<M, T, LOCAL><<<a.g.P, kSweepWG, pr_dyn_lds<M, T>(a), s>>>(a);
+  allow_dyn_lds<pr_sweep_kernel<M, T, LOCAL, V>>();
+  pr_sweep_kernel<M, T, LOCAL, V><<<a.g.P, kSweepWG, pr_dyn_lds<M, T>(a), s>>>(a);
+}
+
+template <int M, typename T, bool LOCAL>
+static void pr_sweep_variant(const PrArgs& a, hipStream_t s) {
+  if (a.g.variant == kNarrow) pr_sweep_go<M, T, LOCAL, kNarrow>(a, s);
+  else if (a.g.variant == kWideInFlight) pr_sweep_go<M, T, LOCAL, kWideInFlight>(a, s);
+  else pr_sweep_go<M, T, LOCAL, kWide>(a, s);
 }
 
 hipError_t launch_pr_sweep(int mode, bool f64, const PrArgs& a, hipStream_t s) {
   if (f64) {
-    if (mode == kSync) pr_sweep_go<kSync, double>(a, s);
-    else if (mode == kAsync) pr_sweep_go<kAsync, double>(a, s);
-    else if (mode == kDelayedLocal) pr_sweep_go<kDelayed, double, true>(a, s);
-    else pr_sweep_go<kDelayed, double>(a, s);
+    if (mode == kSync) pr_sweep_variant<kSync, double, false>(a, s);
+    else if (mode == kAsync) pr_sweep_variant<kAsync, double, false>(a, s);
+    else if (mode == kDelayedLocal) pr_sweep_variant<kDelayed, double, true>(a, s);
+    else pr_sweep_variant<kDelayed, double, false>(a, s);
   } else {
-    if (mode == kSync) pr_sweep_go<kSync, float>(a, s);
-    else if (mode == kAsync) pr_sweep_go<kAsync, float>(a, s);
-    else if (mode == kDelayedLocal) pr_sweep_go<kDelayed, float, true>(a, s);
-    else pr_sweep_go<kDelayed, float>(a, s);
+    if (mode == kSync) pr_sweep_variant<kSync, float, false>(a, s);
+    else if (mode == kAsync) pr_sweep_variant<kAsync, float, false>(a, s);
+    else if (mode == kDelayedLocal) pr_sweep_variant<kDelayed, float, true>(a, s);
+    else pr_sweep_variant<kDelayed, float, false>(a, s);
   }
   return hipGetLastError();
 }
@@ -899,22 +954,26 @@ hipError_t launch_bf_gather(const uint32_t* d, const uint32_t* cpos, uint32_t n,
   return hipGetLastError();
 }
 
+template <int M, bool LOCAL, int V>
+static void bf_sweep_go(const BfArgs& a, size_t lds, hipStream_t s) {
+  allow_dyn_lds<bf_sweep_kernel<M, LOCAL, V>>();
+  bf_sweep_kernel<M, LOCAL, V><<<a.g.P, kSweepWG, lds, s>>>(a);
+}
+
+template <int M, bool LOCAL>
+static void bf_sweep_variant(const BfArgs& a, size_t lds, hipStream_t s) {
+  if (a.g.variant == kNarrow) bf_sweep_go<M, LOCAL, kNarrow>(a, lds, s);
+  else if (a.g.variant == kWideInFlight) bf_sweep_go<M, LOCAL, kWideInFlight>(a, lds, s);
+  else bf_sweep_go<M, LOCAL, kWide>(a, lds, s);
+}
+
 hipError_t launch_bf_sweep(int mode, const BfArgs& a, hipStream_t s) {
   const size_t lds = (size_t)res_offset(mode == kDelayed || mode == kDelayedLocal ? a.cap : 0u, 4u) +
                      (size_t)a.res * sizeof(uint32_t);
-  if (mode == kSync) {
-    allow_dyn_lds(bf_sweep_kernel<kSync>);
-    bf_sweep_kernel<kSync><<<a.g.P, kSweepWG, lds, s>>>(a);
-  } else if (mode == kAsync) {
-    allow_dyn_lds(bf_sweep_kernel<kAsync>);
-    bf_sweep_kernel<kAsync><<<a.g.P, kSweepWG, lds, s>>>(a);
-  } else if (mode == kDelayedLocal) {
-    allow_dyn_lds(bf_sweep_kernel<kDelayed, true>);
-    bf_sweep_kernel<kDelayed, true><<<a.g.P, kSweepWG, lds, s>>>(a);
-  } else {
-    allow_dyn_lds(bf_sweep_kernel<kDelayed>);
-    bf_sweep_kernel<kDelayed><<<a.g.P, kSweepWG, lds, s>>>(a);
-  }
+  if (mode == kSync) bf_sweep_variant<kSync, false>(a, lds, s);
+  else if (mode == kAsync) bf_sweep_variant<kAsync, false>(a, lds, s);
+  else if (mode == kDelayedLocal) bf_sweep_variant<kDelayed, true>(a, lds, s);
+  else bf_sweep_variant<kDelayed, false>(a, lds, s);
   return hipGetLastError();
 }
 

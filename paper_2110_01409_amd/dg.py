@@ -56,22 +56,26 @@ class dg_graph_info(C.Structure):
                 ("max_in_degree", C.c_uint32), ("dangling", C.c_uint32), ("has_weights", C.c_uint32),
                 ("compute_units", C.c_uint32), ("hot_vertices", C.c_uint32), ("hot_edges", C.c_uint64),
                 ("resident_vertices", C.c_uint32), ("resident_edges", C.c_uint64), ("weight_bytes", C.c_uint32),
-                ("device_bytes", C.c_uint64)]
+                ("device_bytes", C.c_uint64), ("sweep_variant", C.c_uint32)]
 
 
 class dg_plan_info(C.Structure):
     _fields_ = [("n", C.c_uint32), ("m", C.c_uint64), ("workers", C.c_uint32), ("tiles", C.c_uint32),
                 ("max_in_degree", C.c_uint32), ("dangling", C.c_uint32), ("hot_vertices", C.c_uint32),
                 ("hot_edges", C.c_uint64), ("resident_vertices", C.c_uint32), ("resident_edges", C.c_uint64),
-                ("weight_bytes", C.c_uint32), ("content_hash", C.c_uint64)]
+                ("weight_bytes", C.c_uint32), ("content_hash", C.c_uint64), ("sweep_variant", C.c_uint32)]
 
 
 class dg_graph_opts(C.Structure):
-    _fields_ = [("workers", C.c_uint32), ("hot_vertices", C.c_uint32), ("resident_vertices", C.c_uint32)]
+    _fields_ = [("workers", C.c_uint32), ("hot_vertices", C.c_uint32), ("resident_vertices", C.c_uint32),
+                ("sweep_variant", C.c_uint32)]
 
 
 DG_HOT_AUTO = 0xFFFFFFFF
 DG_RESIDENT_AUTO = 0xFFFFFFFF
+DG_SWEEP_AUTO, DG_SWEEP_WIDE, DG_SWEEP_WIDE_INFLIGHT, DG_SWEEP_NARROW = 0, 1, 2, 3
+SWEEP_VARIANTS = {"auto": DG_SWEEP_AUTO, "wide": DG_SWEEP_WIDE, "wide_inflight": DG_SWEEP_WIDE_INFLIGHT,
+                  "narrow": DG_SWEEP_NARROW}
 
 
 class dg_graph_desc(C.Structure):
@@ -350,14 +354,14 @@ _torch_hooks = None
 
 
 def plan(n, ptr, idx, w=None, layout="csr", compute_units=256, workers=0, hot_vertices=DG_HOT_AUTO,
-         resident_vertices=DG_RESIDENT_AUTO):
+         resident_vertices=DG_RESIDENT_AUTO, sweep_variant="auto"):
     """The layout dg_graph_create would upload, built on the host only
     (dg_plan_*): a dict of the plan's facts and its arrays as numpy arrays
     (in_ptr, in_src, in_w or None, cpos, tile_v, work_t)."""
     ptr = np.ascontiguousarray(ptr, dtype=np.uint64)
     idx = np.ascontiguousarray(idx, dtype=np.uint32)
     wa = None if w is None else np.ascontiguousarray(w, dtype=np.uint32)
-    opts = dg_graph_opts(int(workers), int(hot_vertices), int(resident_vertices))
+    opts = dg_graph_opts(int(workers), int(hot_vertices), int(resident_vertices), SWEEP_VARIANTS[sweep_variant])
     h = C.c_void_p()
     _check(dg_plan_create(int(n), int(idx.shape[0]), DG_CSR if layout == "csr" else DG_CSC, _np_ptr(ptr),
                           _np_ptr(idx), None if wa is None else _np_ptr(wa), C.byref(opts), int(compute_units),
@@ -441,7 +445,7 @@ class Graph:
     """
 
     def __init__(self, n, ptr, idx, w=None, layout="csr", stream=None, torch_allocator=True, workers=0,
-                 hot_vertices=DG_HOT_AUTO, resident_vertices=DG_RESIDENT_AUTO):
+                 hot_vertices=DG_HOT_AUTO, resident_vertices=DG_RESIDENT_AUTO, sweep_variant="auto"):
         ptr = np.ascontiguousarray(ptr, dtype=np.uint64)
         idx = np.ascontiguousarray(idx, dtype=np.uint32)
         wa = None if w is None else np.ascontiguousarray(w, dtype=np.uint32)
@@ -449,7 +453,7 @@ class Graph:
             use_torch_allocator()
         h = C.c_void_p()
         lay = DG_CSR if layout == "csr" else DG_CSC
-        opts = dg_graph_opts(int(workers), int(hot_vertices), int(resident_vertices))
+        opts = dg_graph_opts(int(workers), int(hot_vertices), int(resident_vertices), SWEEP_VARIANTS[sweep_variant])
         _check(dg_graph_create(int(n), int(idx.shape[0]), lay, _np_ptr(ptr), _np_ptr(idx),
                                None if wa is None else _np_ptr(wa), C.byref(opts), _stream_handle(stream),
                                C.byref(h)))

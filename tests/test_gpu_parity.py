@@ -123,6 +123,30 @@ def test_sssp_all_modes_bit_exact(dg, name):
     G.close()
 
 
+@pytest.mark.parametrize("variant", ["wide", "wide_inflight", "narrow"])
+@pytest.mark.parametrize("name", ["rmat14", "banded", "instar"])
+def test_sweep_variants(dg, name, variant):
+    """Every sweep variant, forced on graphs with a resident table (rmat14),
+    without one (banded) and with a hub tile (instar): PageRank within 1e-6
+    of the oracle in every mode and precision, SSSP bit-exact in every mode
+    with the oracle's synchronous sweep count."""
+    g, xs = _graph(name)
+    G = dg.Graph.from_csr(g, sweep_variant=variant)
+    assert G.info().sweep_variant == dg.SWEEP_VARIANTS[variant]
+    for dtype in ("f64", "f32"):
+        for mode, d in MODES:
+            x, st = G.pagerank(tol=PR_TOL[dtype], mode=mode, d=max(d, 1), dtype=dtype, max_sweeps=2000)
+            err = np.abs(_np(x) - xs).sum()
+            assert err <= 1e-6 and st.converged, (name, variant, dtype, mode, d, err, st)
+    src = _sources(g, 1)[0]
+    ref, ref_sweeps, _ = osp.bellman_ford_sync(g, src)
+    for mode, d in MODES:
+        dist, st = G.sssp(src, mode=mode, d=max(d, 1))
+        np.testing.assert_array_equal(_np(dist), ref, err_msg=f"{name} {variant} {mode} d={d}")
+        assert st.converged and (st.sweeps == ref_sweeps if mode == "sync" else st.sweeps <= ref_sweeps)
+    G.close()
+
+
 def test_sync_per_sweep_iterates(dg):
     """Synchronous sweeps reproduce the oracle's Jacobi iterates one by one
     (PageRank float64 to 1e-13 relative L1, Bellman-Ford bit-exact)."""

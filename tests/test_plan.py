@@ -9,7 +9,9 @@ with numpy:
   halves, the rest in vertex order; the automatic table only when its
   sources cover 1/16 of the edges;
 * tiles: greedy runs of at most 1024 vertices and 16380 in-edges, a larger
-  vertex alone;
+  vertex alone; 8188 in-edges (the narrow sweep variant) when the wide
+  tiles number fewer than 2 per worker; the automatic variant by tiles per
+  worker (narrow < 2 <= wide with all gathers in flight <= 8 < wide);
 * the blocked partition (section III-A: contiguous blocks balanced by
   in-edges): P contiguous tile ranges split at the cost quantiles;
 * byte weights exactly when every weight fits a byte;
@@ -32,8 +34,9 @@ def dg():
 
 
 AUTO = 0xFFFFFFFF
-TILE_V, TILE_E = 1024, 16380
+TILE_V, TILE_E, TILE_E_NARROW = 1024, 16380, 8188
 PER_CU = 1  # sweep workgroups per compute unit
+WIDE, WIDE_INFLIGHT, NARROW = 1, 2, 3
 
 
 def _ref_cpos(g, hot=AUTO, res=AUTO):
@@ -53,11 +56,11 @@ def _ref_cpos(g, hot=AUTO, res=AUTO):
     return cpos, K, int(od[top].sum()), R, int(od[top[:R]].sum())
 
 
-def _ref_tiles(in_ptr):
+def _greedy_tiles(in_ptr, max_e):
     deg = np.diff(in_ptr.astype(np.int64))
     tiles, nv, ne = [0], 0, 0
     for v, d in enumerate(deg):
-        if nv > 0 and (nv == TILE_V or ne + d > TILE_E):
+        if nv > 0 and (nv == TILE_V or ne + d > max_e):
             tiles.append(v)
             nv, ne = 0, 0
         nv += 1
@@ -65,6 +68,15 @@ def _ref_tiles(in_ptr):
     if tiles[-1] != deg.size:
         tiles.append(deg.size)
     return np.array(tiles, dtype=np.int64)
+
+
+def _ref_tiles(in_ptr, workers, variant=0):
+    """(tile_v, sweep variant) for a partition of `workers` workers."""
+    wide = _greedy_tiles(in_ptr, TILE_E)
+    T = wide.size - 1
+    if variant == 0:
+        variant = NARROW if T < 2 * workers else WIDE_INFLIGHT if T <= 8 * workers else WIDE
+    return (_greedy_tiles(in_ptr, TILE_E_NARROW) if variant == NARROW else wide), variant
 
 
 def _ref_workers(tile_v, in_ptr, P):
@@ -124,13 +136,16 @@ def test_tiles_and_partition(dg, graph):
     for cus, workers in ((256, 0), (4, 0), (1, 0), (256, 3), (256, 100_000)):
         p = dg.plan(g.n, g.ptr, g.idx, g.w, compute_units=cus, workers=workers)
         tile_v = p["tile_v"].astype(np.int64)
-        np.testing.assert_array_equal(tile_v, _ref_tiles(p["in_ptr"]))
+        ref, variant = _ref_tiles(p["in_ptr"], workers if workers else cus * PER_CU)
+        np.testing.assert_array_equal(tile_v, ref)
+        assert p["sweep_variant"] == variant
         T = tile_v.size - 1
         assert p["tiles"] == T
         nv = np.diff(tile_v)
         ne = np.diff(p["in_ptr"].astype(np.int64)[tile_v])
+        max_e = TILE_E_NARROW if variant == NARROW else TILE_E
         assert (nv >= 1).all() and (nv <= TILE_V).all()
-        assert ((ne <= TILE_E) | (nv == 1)).all()  # a larger vertex is a tile of its own
+        assert ((ne <= max_e) | (nv == 1)).all()  # a larger vertex is a tile of its own
         P = workers if workers else cus * PER_CU
         P = max(1, min(P, T))
         if P > 8 and not workers:
@@ -222,6 +237,28 @@ def test_edge_cases(dg):
     assert p["tile_v"][t] == hub and p["tile_v"][t + 1] == hub + 1
 
 
+@pytest.mark.parametrize("variant", ["wide", "wide_inflight", "narrow"])
+def test_forced_sweep_variant(dg, variant):
+    g = gg.rmat(14, seed=14)
+    code = {"wide": WIDE, "wide_inflight": WIDE_INFLIGHT, "narrow": NARROW}[variant]
+    p = dg.plan(g.n, g.ptr, g.idx, g.w, sweep_variant=variant)
+    ref, v = _ref_tiles(p["in_ptr"], 256 * PER_CU, code)
+    assert p["sweep_variant"] == v == code
+    np.testing.assert_array_equal(p["tile_v"], ref)
+
+
+def test_automatic_sweep_variant_by_size(dg):
+    """Small graphs take the narrow tiles, mid-size ones the wide tiles with
+    all gathers in flight, large ones the paced wide variant."""
+    small = gg.rmat(12, seed=3)
+    assert dg.plan(small.n, small.ptr, small.idx, small.w)["sweep_variant"] == NARROW
+    mid = gg.banded(1 << 20, 16, 4096, 0.01, seed=2)  # 16.8M in-edges: about 4 wide tiles per worker
+    p = dg.plan(mid.n, mid.ptr, mid.idx, None)
+    assert 2 * 256 <= p["tiles"] <= 8 * 256 and p["sweep_variant"] == WIDE_INFLIGHT
+    # the same graph on 64 compute units has 16 wide tiles per worker
+    assert dg.plan(mid.n, mid.ptr, mid.idx, None, compute_units=64)["sweep_variant"] == WIDE
+
+
 def test_validation(dg):
     P = dg.DG_ERR_INVALID_ARGUMENT
     ptr = np.array([0, 1, 2], np.uint64)
@@ -244,6 +281,10 @@ def test_validation(dg):
     h = dg.C.c_void_p()
     assert dg.dg_plan_create(2, 2, 7, dg._np_ptr(ptr), dg._np_ptr(idx), None, None, 1, dg.C.byref(h)) == P
     assert dg.dg_plan_create(2, 2, 0, dg._np_ptr(ptr), dg._np_ptr(idx), None, None, 1, None) == P
+    # an unknown sweep variant
+    bad = dg.dg_graph_opts(0, dg.DG_HOT_AUTO, dg.DG_RESIDENT_AUTO, 4)
+    assert dg.dg_plan_create(2, 2, 0, dg._np_ptr(ptr), dg._np_ptr(idx), None, dg.C.byref(bad), 1, dg.C.byref(h)) == P
+    assert "sweep_variant" in dg.last_error()
     assert dg.dg_plan_info_get(None, None) == P
     assert dg.dg_plan_arrays(None, None, None, None, None, None, None) == P
     assert dg.dg_plan_destroy(None) == dg.DG_OK
