@@ -465,9 +465,12 @@ dg_status dg_set_destroy(dg_set* s);
 dg_status dg_set_info_get(const dg_set* s, dg_set_info* info);
 
 /* PageRank of every graph of the set (as dg_pagerank, per graph).  All
- * graphs are swept together; every graph's own L1 change of normalised
- * scores is measured each sweep, and the set stops at the first sweep after
- * which every graph has met tol (the single-graph rule, graph by graph).
+ * graphs are swept together; each graph's dangling mass is spread over its
+ * own vertices only, so a graph iterates as it would alone (synchronous
+ * sweeps give each graph's own Jacobi iterates).  Every graph's own L1
+ * change of normalised scores is measured each sweep, and the set stops at
+ * the first sweep after which every graph has met tol (the single-graph
+ * rule, graph by graph); graphs that met it earlier are no longer swept.
  *   flags       0 (reserved)
  *   dtype       DG_F32 only for tol >= 1e-7 (the float32 rounding floor) or
  *               tol = 0, else DG_ERR_UNSUPPORTED: use DG_F64

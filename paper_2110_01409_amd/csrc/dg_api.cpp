@@ -504,7 +504,8 @@ dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
     const std::vector<uint32_t>* src;
   } ups[] = {{&g->in_ptr, &L.in_ptr}, {&g->in_src, &L.in_src}, {&g->in_w, &L.in_w}, {&w8_words, &L.w8pack},
              {&g->out_deg, &L.out_deg}, {&g->cpos, &L.cpos}, {&g->tile_v, &L.tile_v}, {&g->work_t, &work_t},
-             {&g->wseg, &g->wseg_h}, {&g->wgraph, &g->wgraph_h}, {&g->work_tb, &work_tb}};
+             {&g->wseg, &g->wseg_h}, {&g->wgraph, &g->wgraph_h}, {&g->work_tb, &work_tb},
+             {&g->segv_d, &g->seg_v}};
   for (auto& u : ups) {
     if (u.src->empty()) continue;
     const size_t bytes = u.src->size() * sizeof(uint32_t);
@@ -528,10 +529,18 @@ dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
   }
   if (g->G) {
     g->gsweeps = static_cast<uint32_t*>(dev_alloc(g, (size_t)g->G * sizeof(uint32_t), s));
-    if (!g->gsweeps) {
+    g->gdang = static_cast<double*>(dev_alloc(g, (size_t)2 * g->G * sizeof(double), s));
+    if (!g->gsweeps || !g->gdang) {
       release_all(g);
       delete g;
       return fail(DG_ERR_OUT_OF_MEMORY, "device allocation failed");
+    }
+    // Dangling mass of each graph at x = 1/n (the union's first iterate).
+    g->gdang0.assign(g->G, 0.0);
+    for (uint32_t gi = 0; gi < g->G; ++gi) {
+      uint32_t nd = 0;
+      for (uint32_t v = g->seg_v[gi]; v < g->seg_v[gi + 1]; ++v) nd += L.out_deg[v] == 0;
+      g->gdang0[gi] = (double)nd / (double)n;
     }
   }
   *out = g;
@@ -676,7 +685,12 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
   a.wgraph = g->wgraph;
   a.G = g->G;
   a.gsweeps = g->gsweeps;
-  if (g->G) DG_HIP(launch_fill_u32(g->gsweeps, g->G, 0u, s));
+  a.voff = g->segv_d;
+  a.gdang = g->gdang;
+  if (g->G) {
+    DG_HIP(launch_fill_u32(g->gsweeps, g->G, 0u, s));
+    DG_HIP(hipMemcpyAsync(g->gdang, g->gdang0.data(), (size_t)g->G * sizeof(double), hipMemcpyHostToDevice, s));
+  }
   auto launch = [&](uint32_t k) {
     if (mode == DG_SYNC) {
       a.cin = (k & 1) ? c1 : c0;

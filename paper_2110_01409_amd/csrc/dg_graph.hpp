@@ -68,6 +68,9 @@ struct dg_graph {
   std::vector<uint32_t> wgraph_h;  // [P] graph of each worker (host)
   uint32_t* wgraph = nullptr;      // device copy of wgraph_h
   uint32_t* gsweeps = nullptr;  // [G] first sweep that took each graph below tol
+  uint32_t* segv_d = nullptr;   // device copy of seg_v
+  double* gdang = nullptr;      // [2][G] per-graph dangling deficits (PrArgs::gdang)
+  std::vector<double> gdang0;   // [G] each graph's dangling share of the union before sweep 0
   uint64_t hot_edges = 0;  // in-edges whose source is in the compact region
   uint32_t R = 0;          // leading compact-region slots kept in the sweeps' LDS table
   uint64_t res_edges = 0;  // in-edges whose source is one of them

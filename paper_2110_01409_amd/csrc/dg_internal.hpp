@@ -121,6 +121,13 @@ struct PrArgs {
   const uint32_t* wgraph;  // [P] graph of each worker
   uint32_t G;
   uint32_t* gsweeps;
+  // Graph sets: each graph keeps its own mass (its share n_i/n of the
+  // union's): its dangling deficit gdang[(k & 1) G + i] = n_i/n minus its
+  // non-dangling mass after sweep k-1 is spread over its own n_i vertices,
+  // so every graph iterates as it would alone (scaled by n_i/n).
+  // voff[G+1] are the graphs' first vertices.
+  const uint32_t* voff;
+  double* gdang;  // [2][G]
   // Slots n .. n+res-1 are read from the workgroup's LDS table (0 = none).
   // The table is filled at the start of the sweep; an asynchronous sweep
   // refreshes one segment of it after every tile, a delayed sweep after

@@ -278,7 +278,11 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
   // this is exactly the dangling mass; when an asynchronous sweep leaves the
   // total off 1 it also returns the deficit, so the total-mass error mode
   // decays at once instead of at rate alpha.  The fixed point is unchanged.
-  const double base = (1.0 - alpha) * inv_n + alpha * a.st.dang[k] * inv_n;
+  double base = (1.0 - alpha) * inv_n + alpha * a.st.dang[k] * inv_n;
+  if (a.wseg) {  // graph sets: the graph's own deficit over its own vertices
+    const uint32_t gi = a.wgraph[w];
+    base = (1.0 - alpha) * inv_n + alpha * a.gdang[(k & 1u) * a.G + gi] / (double)(a.voff[gi + 1] - a.voff[gi]);
+  }
   const T* cin = static_cast<const T*>(a.cin);
   T* cout = static_cast<T*>(a.cout);
   T* x = static_cast<T*>(a.x);
@@ -514,25 +518,28 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
       // Graph sets: each graph's change relative to its own mass (its L1
       // change once normalised); the sweep's value is the largest of them.
       for (uint32_t gi = tid; gi < a.G; gi += kSweepWG) {
-        double rg = 0.0, mg = 0.0;
+        double rg = 0.0, ng = 0.0, mg = 0.0;
         const uint32_t i1 = a.wseg[gi + 1];
         for (uint32_t i = a.wseg[gi]; i < i1; i += 8) {
           // eight loads in flight, then the sums in worker order
-          double vr[8], vm[8];
+          double vr[8], vn[8], vm[8];
 #pragma unroll
           for (uint32_t j = 0; j < 8; ++j) {
             vr[j] = i + j < i1 ? part(i + j) : 0.0;
+            vn[j] = i + j < i1 ? part(P + i + j) : 0.0;
             vm[j] = i + j < i1 ? part(2 * P + i + j) : 0.0;
           }
 #pragma unroll
           for (uint32_t j = 0; j < 8; ++j) {
             rg += vr[j];
+            ng += vn[j];
             mg += vm[j];
           }
         }
         const double q = rg / mg;
         r = q > r ? q : r;
         if (q < a.tol && a.gsweeps[gi] == 0) a.gsweeps[gi] = k + 1;
+        a.gdang[((k + 1) & 1u) * a.G + gi] = (double)(a.voff[gi + 1] - a.voff[gi]) * inv_n - ng;
       }
     }
     for (uint32_t i = tid; i < P; i += kSweepWG) dd += part(P + i);

@@ -6,7 +6,7 @@ swept together, one launch per sweep).
   own sweep count (equal to the oracle's in synchronous mode).
 * dg_set_pagerank: each graph's scores (renormalised on its own) within L1
   1e-6 of the oracle's fixed point for that graph alone, float64 storage,
-  every mode.  The set stops when every graph's own normalised change is
+  every mode; synchronous sweeps reproduce each graph's own Jacobi sweeps.  The set stops when every graph's own normalised change is
   below tol, and reports for each graph the first sweep that took it there.
   Float32 is refused below its floor (tol < 1e-7) and accepted above it.
 * 64 uneven graphs (R-MAT and G(n, m)) in one set.
@@ -80,6 +80,20 @@ def test_union_pagerank_all_modes_f64(dg, uset, graphs):
         assert st.converged
         # per-graph stop: every graph met the rule, the last one at the set's final sweep
         assert (sw >= 1).all() and (sw <= st.sweeps).all() and sw.max() == st.sweeps, sw
+
+
+def test_union_pagerank_sync_is_each_graph_alone(dg, uset, graphs):
+    """Each graph keeps its own mass in the set (its dangling deficit is
+    spread over its own vertices), so synchronous set sweeps are each graph's
+    own Jacobi iterates, scaled: per-graph sweep counts equal the oracle's
+    for the graph alone, within one for rounding at the threshold."""
+    tol = 1e-8
+    out, sw, st = uset.pagerank(tol=tol, mode="sync", dtype="f64", max_sweeps=20_000)
+    assert st.converged
+    for g, s_g, part in zip(graphs, sw.tolist(), uset.split(out.cpu().numpy())):
+        x_ref, ref_sweeps, _, _ = opr.pagerank_jacobi(g, tol=tol)
+        assert abs(s_g - ref_sweeps) <= 1, (g.name, s_g, ref_sweeps)
+        assert float(np.abs(part - x_ref / x_ref.sum()).sum()) <= 1e-9, g.name
 
 
 def test_union_pagerank_f32(dg, graphs):
