@@ -46,6 +46,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+VARIANT_NAMES = {1: "wide", 2: "wide, all gathers in flight", 3: "narrow"}
+
+
 def kernel_hash():
     with open(KERNEL_SRC, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -307,7 +310,8 @@ def main():
             traffic = tr.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "pr_sweep_kernel<delayed, float>", "algorithmic_bytes_per_launch": algo,
+                "kernel": f"pr_sweep_kernel<delayed, float, {VARIANT_NAMES.get(G.info().sweep_variant, '?')}>",
+                "algorithmic_bytes_per_launch": algo,
                 "avg_launch_us": round(t_sweep * 1e6, 2)}
     log(f"roofline: {t_sweep * 1e6:.1f} us/sweep, {achieved:.0f} GB/s algorithmic = "
         f"{100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s")
