@@ -43,6 +43,36 @@ __device__ __forceinline__ void st_q(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Delayed commits staged in registers: each wavefront keeps up to kStageRows
+// rows it computed (its lane's value in a register; the vertex's slot, the
+// same in every lane, in the wavefront's own LDS array, which it reads back
+// in order, so no barrier is needed) and commits them, as coalesced 64-lane
+// rows, once `per` rows are staged and at the end of its block.  Used
+// instead of the global shadow when d <= kStageRows * waves per workgroup,
+// so that a commit every d vertices of the worker costs no extra row
+// traffic.  Batched SSSP only: the PPR kernel's extra registers cost it more
+// occupancy than the shadow's row traffic (measured 17 against 15.3 ms per
+// batch-sweep on RMAT-22).
+template <typename T>
+struct RegStage {
+  T val[kStageRows];
+  uint32_t* slot;    // [kStageRows] in LDS, this wavefront's
+  uint32_t cnt = 0;  // the same in every lane
+  __device__ __forceinline__ void flush(T* out, uint32_t lane) {
+#pragma unroll
+    for (uint32_t r = 0; r < kStageRows; ++r)
+      if (r < cnt) st_q(out + (size_t)slot[r] * kQ + lane, val[r]);
+    cnt = 0;
+  }
+  __device__ __forceinline__ void push(uint32_t p, T v, uint32_t per, T* out, uint32_t lane) {
+#pragma unroll
+    for (uint32_t r = 0; r < kStageRows; ++r)
+      if (r == cnt) val[r] = v;
+    if (lane == 0) slot[cnt] = p;
+    if (++cnt >= per) flush(out, lane);
+  }
+};
+
 __device__ __forceinline__ uint32_t sat_add_q(uint32_t a, uint32_t b) {
   const uint32_t s = a + b;
   return s < a ? kInf : s;
@@ -113,6 +143,7 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
   __shared__ uint32_t s_hub[kWG / 64][kQ];
   __shared__ int s_any;
   __shared__ uint32_t s_lane[kQ];
+  __shared__ uint32_t s_slot[kWG / 64][kStageRows];
   const uint32_t b = blockIdx.y, NB = a.NB, k = a.k;
   // batch already converged (call mode) or without running queries (serving)
   if (a.bactive ? a.bactive[b] == 0 : a.changed[k * NB + b] == 0) return;
@@ -130,6 +161,11 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
   if (tid < kQ) s_lane[tid] = 0;
   __syncthreads();
   uint32_t any = 0, staged = 0, t_first = t0;  // t_first: first tile staged since the last commit
+  // Delayed mode without a shadow: stage in registers, commit every per rows.
+  const bool regs = M == kDelayed && shadow == nullptr;
+  const uint32_t per = (a.d + kWG / 64 - 1) / (kWG / 64);
+  RegStage<uint32_t> rs;
+  rs.slot = s_slot[wv];
 
   for (uint32_t t = t0; t < t1; ++t) {
     const uint32_t v0 = tile_v[t], v1 = tile_v[t + 1], nv = v1 - v0;
@@ -147,6 +183,7 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
         any |= nw < old;
         if constexpr (M == kSync) dout[(size_t)p * kQ + lane] = nw;
         else if constexpr (M == kAsync) st_q(dout + (size_t)p * kQ + lane, nw);
+        else if (regs) rs.push(p, nw, per, dout, lane);
         else shadow[(size_t)v0 * kQ + lane] = nw;
       }
       __syncthreads();
@@ -159,10 +196,13 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
         any |= nw < old;
         if constexpr (M == kSync) dout[(size_t)p * kQ + lane] = nw;
         else if constexpr (M == kAsync) st_q(dout + (size_t)p * kQ + lane, nw);
+        else if (regs) rs.push(p, nw, per, dout, lane);
         else shadow[(size_t)v * kQ + lane] = nw;
       }
     }
-    if constexpr (M == kDelayed) {
+    if (regs) {
+      if (t + 1 == t1) rs.flush(dout, lane);  // the end of the block
+    } else if constexpr (M == kDelayed) {
       staged += nv;
       if (t + 1 == t1 || staged >= a.d) {
         // Each wavefront commits the rows it staged itself (a tile's vertex v

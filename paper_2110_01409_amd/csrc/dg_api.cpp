@@ -872,10 +872,13 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
   uint32_t* srcd = static_cast<uint32_t*>(al.get((size_t)k * 4, s));
   uint32_t* b0 = static_cast<uint32_t*>(al.get(vals * 4, s));
   uint32_t* b1 = mode == DG_SYNC ? static_cast<uint32_t*>(al.get(vals * 4, s)) : nullptr;
-  uint32_t* sh = mode == DG_DELAYED ? static_cast<uint32_t*>(al.get((size_t)NB * g->n * kBatchQ * 4, s)) : nullptr;
+  // Delayed commits stage in registers up to kRegStageMaxD, beyond in a shadow.
+  const uint32_t d_eff = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_vb)) : 0u;
+  const bool need_sh = mode == DG_DELAYED && d_eff > kRegStageMaxD;
+  uint32_t* sh = need_sh ? static_cast<uint32_t*>(al.get((size_t)NB * g->n * kBatchQ * 4, s)) : nullptr;
   uint32_t* changed = static_cast<uint32_t*>(al.get(((size_t)max_sweeps + 1) * NB * 4, s));
   uint32_t* outd = out_on_device ? out_dist : static_cast<uint32_t*>(al.get((size_t)k * g->n * 4, s));
-  if (!srcd || !b0 || (mode == DG_SYNC && !b1) || (mode == DG_DELAYED && !sh) || !changed || !outd)
+  if (!srcd || !b0 || (mode == DG_SYNC && !b1) || (need_sh && !sh) || !changed || !outd)
     return fail(DG_ERR_OUT_OF_MEMORY, "batched SSSP workspace allocation failed");
   PinnedBuf poll;
   DG_HIP(alloc_mapped(&poll.p, &poll.dev, ((size_t)max_sweeps + 1) * NB * 4));
@@ -889,7 +892,7 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
   a.changed = changed;
   a.hchanged = static_cast<uint32_t*>(poll.dev);
   a.shadow = sh;
-  a.d = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_vb)) : 0u;
+  a.d = d_eff;
   a.NB = NB;
   auto launch = [&](uint32_t kk) {
     if (mode == DG_SYNC) {
@@ -977,7 +980,9 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   void* x = al.get(xs * esz, s);
   void* c0 = al.get(vals * esz, s);
   void* c1 = mode == DG_SYNC ? al.get(vals * esz, s) : nullptr;
-  void* sh = mode == DG_DELAYED ? al.get(xs * esz, s) : nullptr;
+  const uint32_t d_eff = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_vb)) : 0u;
+  const bool need_sh = mode == DG_DELAYED;
+  void* sh = need_sh ? al.get(xs * esz, s) : nullptr;
   double* resid = static_cast<double*>(al.get(((size_t)max_sweeps + 1) * NB * 8, s));
   uint32_t* count = static_cast<uint32_t*>(al.get(((size_t)max_sweeps + 1) * NB * 4, s));
   double* dang = static_cast<double*>(al.get((size_t)2 * NB * kBatchQ * 8, s));
@@ -987,7 +992,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   double* qsum = static_cast<double*>(al.get((size_t)NB * kBatchQ * 8, s));
   double* qpart = static_cast<double*>(al.get((size_t)NB * 256 * kBatchQ * 8, s));
   double* outd = out_on_device ? out_scores : static_cast<double*>(al.get((size_t)k * g->n * 8, s));
-  if (!srcd || !x || !c0 || (mode == DG_SYNC && !c1) || (mode == DG_DELAYED && !sh) || !resid || !count || !dang ||
+  if (!srcd || !x || !c0 || (mode == DG_SYNC && !c1) || (need_sh && !sh) || !resid || !count || !dang ||
       !scale || !qdone || !part || !qsum || !qpart || !outd)
     return fail(DG_ERR_OUT_OF_MEMORY, "batched PageRank workspace allocation failed");
   PinnedBuf poll;
@@ -1018,7 +1023,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   a.alpha = damping;
   a.tol = tol;
   a.nq = k;
-  a.d = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_vb)) : 0u;
+  a.d = d_eff;
   a.NB = NB;
   auto launch = [&](uint32_t kk) {
     if (mode == DG_SYNC) {

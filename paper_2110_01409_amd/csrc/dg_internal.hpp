@@ -154,6 +154,12 @@ struct BfArgs {
   uint32_t* gsweeps;
 };
 
+// Batched queries: rows a wavefront stages in registers in delayed mode, and
+// the largest commit interval staged that way (four wavefronts per
+// workgroup); larger intervals stage in a global shadow array.
+constexpr uint32_t kStageRows = 16;
+constexpr uint32_t kRegStageMaxD = kStageRows * (kWG / 64);
+
 // Batched queries (64 per batch, vertex-major [slot][64] values).
 struct MbfArgs {
   Topology g;
