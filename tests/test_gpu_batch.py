@@ -48,7 +48,9 @@ def test_sssp_batch_all_modes(dg, name):
     sources[5] = sources[6]  # a duplicate query
     refs = {int(s): osp.bellman_ford_sync(g, int(s))[0] for s in set(sources.tolist())}
     G = dg.Graph.from_csr(g)
-    for mode, d in MODES:
+    # d <= 64 stages in registers (16 rows per wavefront, a commit every
+    # ceil(d/4) of its vertices), d > 64 in the shadow array
+    for mode, d in MODES + [("delayed", 16), ("delayed", 63), ("delayed", 65)]:
         out, st = G.sssp_batch(sources, mode=mode, d=d)
         got = out.cpu().numpy()
         for q, s in enumerate(sources.tolist()):
