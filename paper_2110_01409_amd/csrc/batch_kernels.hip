@@ -8,8 +8,9 @@
 // batch instead of once per query.  Batches are the y dimension of the
 // launch; a batch whose queries have all met the stopping rule exits at once.
 //
-// Work mapping: the same persistent workers and tiles as the single-query
-// sweeps (contiguous vertex blocks, ascending order).  Within a tile the four
+// Work mapping: the tiles of the single-query sweeps, in contiguous blocks of
+// a partition of their own (five 256-thread workgroups per compute unit),
+// each walked in ascending order.  Within a tile the four
 // wavefronts of the workgroup take vertices round-robin; a single-vertex tile
 // (a hub) is split over the four wavefronts and combined in LDS.  For each
 // vertex a wavefront reads 64 in-edges with one coalesced load, broadcasts
@@ -17,8 +18,11 @@
 // gathers in flight.
 //
 // Commit modes are those of the single-query sweeps: synchronous (double
-// buffer), asynchronous (agent-scope store per vertex), delayed (staged in a
-// per-batch shadow array, committed every d vertices and at the block end).
+// buffer), asynchronous (agent-scope store per vertex), delayed (SSSP with
+// d <= kRegStageMaxD: staged in registers and committed every d vertices of
+// the worker; otherwise staged in a per-batch shadow array and committed at
+// the end of the first tile that brings the staged count to d; always also
+// at the end of the block).
 #include "dg_device.hpp"
 #include "dg_internal.hpp"
 
