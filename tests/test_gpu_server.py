@@ -110,7 +110,7 @@ def test_server_mix_sync_f64_and_alone(dg, graphs):
         g.close()
 
 
-@pytest.mark.parametrize("mode,d", [("async", 1), ("delayed", 64)])
+@pytest.mark.parametrize("mode,d", [("async", 1), ("delayed", 64), ("delayed", 256)])
 def test_server_mix_modes_f32(dg, graphs, mode, d):
     G = [dg.Graph.from_csr(g) for g in graphs]
     srv = dg.Server(G, mode=mode, d=d, dtype="f32", tol=5e-7)
