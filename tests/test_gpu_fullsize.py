@@ -150,3 +150,25 @@ def test_rmat20_batched_256_sources(dg, rmat20):
         assert float(np.abs(xs[q] - ref_x).sum()) <= 1e-8
     print(f"rmat20 ppr worst certificate bound {worst:.2e}", flush=True)
     G.close()
+
+
+def test_rmat20_single_query_inflight_variant(dg, rmat20):
+    """RMAT-20 at its own size picks the wide sweep variant with all gathers
+    in flight (about 4 wide tiles per worker): PageRank within L1 1e-6 of the
+    oracle's fixed point in every mode (float32), SSSP by the optimality
+    certificate in every mode."""
+    g = rmat20
+    G = dg.Graph.from_csr(g)
+    assert G.info().sweep_variant == dg.DG_SWEEP_WIDE_INFLIGHT
+    xs = opr.pagerank_fixed_point(g, tol=1e-12)
+    for mode, d in MODES:
+        x, st = G.pagerank(tol=PR_TOL["f32"], mode=mode, d=d, dtype="f32", max_sweeps=500)
+        err = float(np.abs(x.cpu().numpy() - xs).sum())
+        print(f"rmat20 f32 {mode} d={d}: sweeps={st.sweeps} L1 err={err:.2e}", flush=True)
+        assert err <= 1e-6, (mode, d, err)
+    src = int(gg.pick_sources(g, 1, seed=21)[0])
+    for mode, d in MODES:
+        dist, st = G.sssp(src, mode=mode, d=d)
+        ok, msg = osp.certificate(g, src, dist.cpu().numpy())
+        assert ok, (mode, d, msg)
+    G.close()
