@@ -442,6 +442,10 @@ class Graph:
     ``Graph(n, ptr, idx, w=None, layout="csr")`` copies host arrays (ptr
     uint64[n+1], idx uint32[m], w uint32[m] or None) to the device and builds
     the in-edge form.  ``Graph.from_csr(g)`` takes a ``graphgen.CSRGraph``.
+    The keyword options are those of dg_graph_opts: ``workers``,
+    ``hot_vertices``, ``resident_vertices`` and ``sweep_variant`` ("auto",
+    "wide", "wide_inflight" or "narrow"); ``info().sweep_variant`` reports
+    the variant in use.
     """
 
     def __init__(self, n, ptr, idx, w=None, layout="csr", stream=None, torch_allocator=True, workers=0,
