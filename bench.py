@@ -62,10 +62,11 @@ def pr_bytes_per_sweep(n, m, dtype):
     return m * (4 + e) + n * (4 + 4 + 3 * e)
 
 
-def bf_bytes_per_sweep(n, m):
-    """Per edge: 4-byte source index, 4-byte weight, 4-byte gathered distance;
-    per vertex: 4-byte offset, old distance read, new distance written."""
-    return m * 12 + n * 12
+def bf_bytes_per_sweep(n, m, weight_bytes=4):
+    """Per edge: 4-byte source index, the stored weight (1 byte when every
+    weight fits a byte, else 4), 4-byte gathered distance; per vertex: 4-byte
+    offset, old distance read, new distance written."""
+    return m * (8 + weight_bytes) + n * 12
 
 
 def cpu_baseline(g, budget_s=15.0):
@@ -343,10 +344,10 @@ def main():
                 tot_t += s.seconds
                 tot_s += s.sweeps
                 sw.append(s.sweeps)
+            bf_bytes = bf_bytes_per_sweep(n, m, G.info().weight_bytes)
             row["sssp_16_sources"] = {"sweeps": sw, "t_conv_ms_total": round(tot_t * 1e3, 3),
                                       "gteps": round(m * tot_s / tot_t / 1e9, 1),
-                                      "hbm_frac_algorithmic": round(bf_bytes_per_sweep(n, m) * tot_s / tot_t
-                                                                    / 1e9 / HBM_PEAK_GBS, 4)}
+                                      "hbm_frac_algorithmic": round(bf_bytes * tot_s / tot_t / 1e9 / HBM_PEAK_GBS, 4)}
             modes[key] = row
             log(f"{key:16s} PR f32 {row['pagerank_f32']['sweeps']} {row['pagerank_f32']['t_conv_ms']} ms "
                 f"({row['pagerank_f32']['gteps']} GTEPS, err {row['pagerank_f32']['l1_vs_f64_tol1e-10']:.1e}) | "
