@@ -241,8 +241,8 @@ def main():
                     help="only run a plain 1 GiB device copy five times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(see the sharding note in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures exactly one GPU: the library has no multi-GPU path "
+              "(the sweeps would shard as a 1-D vertex partition; not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
