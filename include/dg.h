@@ -60,7 +60,7 @@ typedef enum {
   DG_ERR_DEVICE = 3,           /* a HIP call failed (no device, fault, ...)  */
   DG_ERR_NOT_CONVERGED = 4,    /* max_sweeps reached; outputs and stats hold
                                   the last iterate                            */
-  DG_ERR_UNSUPPORTED = 5       /* valid request this build cannot run        */
+  DG_ERR_UNSUPPORTED = 5       /* valid request the library cannot run       */
 } dg_status;
 
 /* Commit mode of a sweep (section III). */
