@@ -79,6 +79,33 @@ def pagerank_jacobi(g, alpha=ALPHA, tol=1e-6, max_sweeps=10_000, x0=None, keep_i
     return x, sweeps, residuals, iterates
 
 
+def union_jacobi_sweep(graphs, xs, alpha=ALPHA, per_graph=True):
+    """One synchronous sweep of a set of graphs stored as one union of
+    N = sum n_i vertices (the paper treats one graph; sets are an extension,
+    reading R28 of the design notes).  ``xs[i]`` is graph i's part of the
+    union vector.  Teleport is (1 - alpha)/N everywhere.  The dangling mass
+    is spread either over the graph's own vertices (per_graph: D_i / n_i,
+    so graph i keeps the mass n_i/N it starts with) or, as in a single graph
+    of N vertices, over the whole union (D / N with D = sum_i D_i)."""
+    N = sum(g.n for g in graphs)
+    parts, dang = [], []
+    for g, x in zip(graphs, xs):
+        src, dst = edge_list(g)
+        deg = out_degree(g)
+        x = np.asarray(x, dtype=np.float64)
+        contrib = np.zeros(g.n, dtype=np.float64)
+        nz = deg > 0
+        contrib[nz] = x[nz] / deg[nz]
+        parts.append(np.bincount(dst, weights=contrib[src], minlength=g.n))
+        dang.append(float(x[~nz].sum()))
+    D = sum(dang)
+    out = []
+    for g, pulled, d_i in zip(graphs, parts, dang):
+        spread = d_i / g.n if per_graph else D / N
+        out.append((1.0 - alpha) / N + alpha * (pulled + spread))
+    return out
+
+
 def pagerank_fixed_point(g, alpha=ALPHA, tol=1e-12, max_sweeps=100_000):
     """x* to within the float64 noise floor: Jacobi iteration until the L1
     change is below ``tol`` (1e-12 by default), then one normalisation."""

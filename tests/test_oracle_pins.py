@@ -142,6 +142,32 @@ def test_pr_stopping_rule():
     assert len(res) == sweeps
 
 
+def test_pr_union_per_graph_mass_is_each_graph_alone():
+    """Reading R28 (graph sets).  With each graph's dangling mass spread over
+    its own vertices, the union's synchronous iterates restricted to graph i
+    are graph i's own Jacobi iterates times n_i/N, for every sweep; spreading
+    one dangling mass over the whole union instead moves mass between the
+    graphs (their shares drift from n_i/N), although after normalising each
+    graph both forms reach the same fixed points."""
+    graphs = [tg.dangling_heavy(40, 2), gg.rmat(6, seed=3), tg.in_star(30), tg.complete(7)]
+    N = sum(g.n for g in graphs)
+    alone = [opr.pagerank_jacobi(g, tol=0.0, max_sweeps=12, keep_iterates=True)[3] for g in graphs]
+    xs = [np.full(g.n, 1.0 / N) for g in graphs]
+    ys = [x.copy() for x in xs]
+    drift = 0.0
+    for k in range(12):
+        xs = opr.union_jacobi_sweep(graphs, xs, per_graph=True)
+        ys = opr.union_jacobi_sweep(graphs, ys, per_graph=False)
+        for g, x, y, it in zip(graphs, xs, ys, alone):
+            np.testing.assert_allclose(x, it[k] * g.n / N, rtol=1e-12, atol=0.0)
+            drift = max(drift, abs(y.sum() - g.n / N))
+    assert drift > 1e-3  # the global spread does move mass between graphs
+    for _ in range(400):
+        ys = opr.union_jacobi_sweep(graphs, ys, per_graph=False)
+    for g, y in zip(graphs, ys):
+        np.testing.assert_allclose(y / y.sum(), opr.pagerank_fixed_point(g), rtol=0.0, atol=1e-10)
+
+
 # -------------------------------------------------------------------- SSSP --
 
 @pytest.mark.parametrize("seed", range(5))
