@@ -127,3 +127,101 @@ def test_sssp_extra_sweep_caught(monkeypatch):
 
     monkeypatch.setattr(osp, "bellman_ford_sync", short)
     assert not _sssp_pins_hold()
+
+
+# ------------------------------------------------ error certificates --
+#
+# The certificates ||T(x) - x|| / (1 - alpha) decide the pass/fail of results
+# that have no stored fixed point (large batched and served personalised
+# PageRank rows), so each plausible mistake in them must break a pin.
+
+
+def _cert_pins_hold(cert_fn, fixed_point, graphs):
+    """The pins of test_oracle_pins: certificate ~ 0 at the fixed point from a
+    dense solve, err <= cert <= (1 + a)/(1 - a) err around it, and exactness
+    on a rescaled fixed point."""
+    ok = True
+    rng = np.random.default_rng(9)
+    for g, s in graphs:
+        xs = fixed_point(g, s)
+        ok &= cert_fn(g, xs, s) < 1e-13
+        n = g.n
+        pert = [xs + sc * rng.standard_normal(n) / n for sc in (1e-3, 1e-6)] + [xs * (1 + 1e-4), xs * (1 - 3e-7)]
+        for x in pert:
+            err = np.abs(x - xs).sum()
+            c = cert_fn(g, x, s)
+            ok &= err <= c * (1 + 1e-9) + 1e-15
+            ok &= c <= err * (1 + A) / (1 - A) * (1 + 1e-9) + 1e-15
+    return bool(ok)
+
+
+_PPR_GRAPHS = [(tg.random_graph(120, 500, 11), 3), (tg.dangling_heavy(90, 5), 7)]
+
+
+def _ppr_holds():
+    return _cert_pins_hold(lambda g, x, s: opr.ppr_certificate(g, x, s), opr.ppr_dense, _PPR_GRAPHS)
+
+
+def _pr_holds():
+    graphs = [(tg.random_graph(120, 500, 11), 0), (tg.dangling_heavy(90, 5), 0)]
+    return _cert_pins_hold(lambda g, x, s: opr.certificate(g, x), lambda g, s: opr.pagerank_dense(g), graphs)
+
+
+def test_real_certificates_pass():
+    assert _ppr_holds()
+    assert _pr_holds()
+
+
+def _ppr_step(x, src, dst, deg, s, alpha, teleport=True, dangling_to="restart"):
+    n = x.shape[0]
+    c = np.where(deg > 0, x / np.maximum(deg, 1), 0.0)
+    out = alpha * np.bincount(dst, weights=c[src], minlength=n)
+    dang = float(x[deg == 0].sum())
+    if dangling_to == "restart":
+        out[s] += alpha * dang
+    else:
+        out += alpha * dang / n
+    if teleport:
+        out[s] += 1.0 - alpha
+    return out
+
+
+def _ppr_cert_mutant(kind):
+    def cert(g, x, s, alpha=A):
+        src, dst = opr.edge_list(g)
+        deg = opr.out_degree(g)
+        x = np.asarray(x, dtype=np.float64)
+        if kind == "no_factor":
+            return float(np.abs(opr.apply_ppr(x, src, dst, deg, s, alpha) - x).sum())
+        if kind == "zero":
+            return 0.0
+        if kind == "plus_alpha":
+            return float(np.abs(opr.apply_ppr(x, src, dst, deg, s, alpha) - x).sum()) / (1.0 + alpha)
+        if kind == "dangling_uniform":
+            y = _ppr_step(x, src, dst, deg, s, alpha, dangling_to="uniform")
+        elif kind == "no_teleport":
+            y = _ppr_step(x, src, dst, deg, s, alpha, teleport=False)
+        return float(np.abs(y - x).sum()) / (1.0 - alpha)
+    return cert
+
+
+@pytest.mark.parametrize("kind", ["no_factor", "zero", "plus_alpha", "dangling_uniform", "no_teleport"])
+def test_ppr_certificate_mutants_caught(monkeypatch, kind):
+    monkeypatch.setattr(opr, "ppr_certificate", _ppr_cert_mutant(kind))
+    assert not _ppr_holds()
+
+
+def _pr_cert_mutant(kind):
+    def cert(g, x, alpha=A):
+        src, dst = opr.edge_list(g)
+        deg = opr.out_degree(g)
+        x = np.asarray(x, dtype=np.float64)
+        r = float(np.abs(opr.apply_T(x, src, dst, deg, alpha) - x).sum())
+        return {"no_factor": r, "zero": 0.0, "plus_alpha": r / (1.0 + alpha)}[kind]
+    return cert
+
+
+@pytest.mark.parametrize("kind", ["no_factor", "zero", "plus_alpha"])
+def test_pr_certificate_mutants_caught(monkeypatch, kind):
+    monkeypatch.setattr(opr, "certificate", _pr_cert_mutant(kind))
+    assert not _pr_holds()

@@ -133,6 +133,42 @@ def test_pr_certificate_bounds_error():
         assert cert <= err * (1 + ALPHA) / (1 - ALPHA) * (1 + 1e-9) + 1e-15
 
 
+def _perturbations(xs, rng):
+    """Vectors around a fixed point x*: random signed noise at three scales,
+    a uniform rescale of x* (the direction in which the certificate is
+    tight) and mass moved between two vertices."""
+    n = xs.size
+    out = [xs + sc * rng.standard_normal(n) / n for sc in (1e-3, 1e-6, 1e-9)]
+    out += [xs * (1 + t) for t in (1e-4, -3e-7)]
+    y = xs.copy()
+    y[0] += 1e-5
+    y[n - 1] -= 1e-5
+    out.append(y)
+    return out
+
+
+@pytest.mark.parametrize("gname", ["random", "dangling"])
+def test_ppr_certificate_bounds_error(gname):
+    """||P_s(x) - x||/(1 - a) bounds ||x - x*_s|| from above, and by
+    contraction it is at most (1 + a)/(1 - a) times that error, for any x.
+    x*_s comes from the dense direct solve, not from the certificate's own
+    sweep.  On x = (1 + t) x*_s the bound is exact (P_s is affine and maps
+    (1 + t) x* to (1 + t) x* - t (1 - a) e_s), so a certificate that drops its
+    1/(1 - a) factor falls below the true error there."""
+    g = tg.random_graph(120, 500, 11) if gname == "random" else tg.dangling_heavy(90, 5)
+    s = int(gg.pick_sources(g, 1, seed=2)[0])
+    xs = opr.ppr_dense(g, s)
+    assert opr.ppr_certificate(g, xs, s) < 1e-13
+    rng = np.random.default_rng(9)
+    for x in _perturbations(xs, rng):
+        err = np.abs(x - xs).sum()
+        cert = opr.ppr_certificate(g, x, s)
+        assert err <= cert * (1 + 1e-9) + 1e-15
+        assert cert <= err * (1 + ALPHA) / (1 - ALPHA) * (1 + 1e-9) + 1e-15
+    for t in (1e-4, -3e-7):
+        assert abs(opr.ppr_certificate(g, xs * (1 + t), s) - abs(t)) < 1e-6 * abs(t) + 1e-14
+
+
 def test_pr_stopping_rule():
     """Stops at the first sweep whose L1 change is strictly below tol, and the
     returned count includes that sweep."""
