@@ -84,17 +84,41 @@ typedef enum { DG_F32 = 0, DG_F64 = 1 } dg_dtype;
 
 typedef struct dg_graph dg_graph;
 
-/* Per-call statistics. */
+/* Per-call statistics.  Every field is written by the call except
+ * `request`, which the caller sets (zero-initialise the struct otherwise).
+ *
+ * Commit granularity.  A worker computes the vertices of one tile (up to
+ * 1024 consecutive vertices) at once, after all of the tile's gathers, so a
+ * commit can only fall between tiles: in DG_DELAYED a worker commits at the
+ * end of the first tile that brings its staged count to >= d (and at the end
+ * of its block).  Any d up to the tile size therefore commits after every
+ * tile; `commit_interval` reports the interval that took effect. */
+#define DG_STATS_ERR_BOUND 1u
 typedef struct {
   uint32_t sweeps;          /* sweeps run, including the confirming one     */
   uint32_t workers;         /* persistent workgroups (contiguous blocks)    */
-  uint32_t tile_vertices;   /* vertices a worker computes concurrently      */
-  uint32_t commit_interval; /* effective d in vertices (0 = no staging)     */
+  uint32_t tile_vertices;   /* mean vertices per tile: n / tiles, rounded   */
+  uint32_t commit_interval; /* delayed modes: mean vertices per commit of a
+                               worker's staged values, n / commits, rounded
+                               (>= d up to the end of a block); 0 otherwise */
   double residual;          /* PageRank: L1 change of the last sweep        */
   double seconds;           /* time to convergence: first sweep launch to
                                the end of the sweep that met the stopping
                                rule, measured with events on the stream     */
   uint64_t edges_traversed; /* m * sweeps                                   */
+  double err_bound;         /* dg_pagerank and dg_ppr, when `request` holds
+                               DG_STATS_ERR_BOUND: ||T(x) - x||_1 / (1 -
+                               damping) for the returned scores x and the
+                               call's map T, computed on the device in
+                               float64 after the sweeps (one more pull
+                               sweep, not part of `seconds`).  T is an L1
+                               contraction with factor damping, so this
+                               bounds the L1 distance of x to the exact
+                               fixed point; it overstates it by at most
+                               (1 + damping) / (1 - damping).  0 otherwise. */
+  uint32_t request;         /* in: DG_STATS_ERR_BOUND, or 0                 */
+  uint32_t commits;         /* delayed modes: commits per sweep, over all
+                               workers; 0 otherwise                         */
 } dg_stats;
 
 /* Static facts about an uploaded graph. */
@@ -181,6 +205,8 @@ typedef struct {
   uint32_t hot_vertices;
   uint32_t resident_vertices;
   uint32_t sweep_variant;
+  uint32_t arrays_on_device; /* 1: ptr, idx and w of dg_graph_create are
+                                device memory (see there); 0: host memory */
 } dg_graph_opts;
 
 /* Upload a graph and build its in-edge form (pull sweeps need in-neighbours,
@@ -189,20 +215,26 @@ typedef struct {
  *              below 2^29 (DG_ERR_UNSUPPORTED otherwise)
  *   m          edges, m < 2^32 - 4096
  *   layout     DG_CSR or DG_CSC (see dg_layout)
- *   ptr        host array of n+1 uint64 offsets: ptr[0] = 0, non-decreasing,
+ *   ptr        array of n+1 uint64 offsets: ptr[0] = 0, non-decreasing,
  *              ptr[n] = m
- *   idx        host array of m uint32 vertex ids, each < n
- *   w          host array of m uint32 edge weights, or NULL (PageRank only).
+ *   idx        array of m uint32 vertex ids, each < n
+ *   w          array of m uint32 edge weights, or NULL (PageRank only).
  *              Path lengths saturate at DG_INF_DIST.  When every weight is
  *              <= 255 the device keeps them as bytes (dg_graph_info.
  *              weight_bytes), which shortens the sweeps' weight stream.
  *   opts       creation options, or NULL for the defaults
+ * The three arrays are host memory, or device memory of the current device
+ * when opts->arrays_on_device is 1 (then they are read on hip_stream after
+ * the work already queued on it; the in-edge form, tiles and partition are
+ * built on the host from a copy, so the call moves the arrays over PCIe
+ * once each way).  Device arrays are validated after that copy, with the
+ * same rules; a pointer that is not device memory is INVALID_ARGUMENT.
  * Duplicate edges are kept (PageRank counts multiplicity, SSSP takes the
  * minimum) and self-loops count in the out-degree.  The arrays are copied:
  * the caller keeps ownership and may free them when the call returns.  On
  * success *out owns device memory until dg_graph_destroy.
- * Errors: INVALID_ARGUMENT (malformed arrays, NULL pointers), OUT_OF_MEMORY,
- * DEVICE. */
+ * Errors: INVALID_ARGUMENT (malformed arrays, NULL pointers,
+ * arrays_on_device not 0 or 1), OUT_OF_MEMORY, DEVICE. */
 dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr,
                           const uint32_t* idx, const uint32_t* w, const dg_graph_opts* opts,
                           void* hip_stream, dg_graph** out);
@@ -221,7 +253,8 @@ dg_status dg_graph_info_get(const dg_graph* g, dg_graph_info* info);
  * the blocked worker partition balanced by in-edges (section III-A).  For
  * inspecting a layout before uploading it, and for testing it on machines
  * without a GPU.  Arguments and errors as dg_graph_create, except DEVICE,
- * which cannot occur; *out is owned by the caller until dg_plan_destroy. */
+ * which cannot occur, and opts->arrays_on_device, which must be 0 (a plan is
+ * built without a device); *out is owned by the caller until dg_plan_destroy. */
 typedef struct dg_plan dg_plan;
 typedef struct {
   uint32_t n;
@@ -352,9 +385,9 @@ dg_status dg_graph_repartition(dg_graph* g, uint32_t workers, void* hip_stream);
  *   1. a full run of every candidate (sync, async, delayed with d in
  *      {16, 64, 256, 1024, 4096, whole}) at the current partition gives its
  *      sweep count;
- *   2. for every partition size (2, 3, 4, 5, 6, 8 workers per compute unit,
- *      rounded down to a multiple of 8), a 6-sweep probe of every candidate
- *      gives its time per sweep (best of two);
+ *   2. for every partition size (1, 2, 3 and 4 sweep workgroups per compute
+ *      unit, rounded down to a multiple of 8), a 6-sweep probe of every
+ *      candidate gives its time per sweep (best of two);
  *   3. the candidate with the least predicted time to convergence is run
  *      twice more to measure it.
  * The graph is left partitioned with the chosen number of workers (unless
@@ -420,13 +453,12 @@ dg_status dg_access_matrix(dg_graph* g, uint32_t groups, uint64_t* out_counts, d
  *  - SSSP: every graph's Bellman-Ford starts from its own source; each
  *    graph's distances are exactly those of dg_sssp on it.
  *  - PageRank: the union's PageRank restricted to one graph and renormalised
- *    to sum 1 equals that graph's own (its teleport and dangling term is the
- *    same constant for all vertices, and the graph's mass balance rescales
- *    it to the graph's own).  The union stops when its L1 change is below
- *    tol (1 - damping) min_i n_i / N, which bounds every graph's own L1
- *    change by tol.
- * All graphs sweep until the last one stops: out_sweeps reports the set's
- * sweep count for every graph. */
+ *    to sum 1 equals that graph's own (each graph's dangling mass is spread
+ *    over its own vertices, so the graph keeps the mass it starts with and
+ *    iterates as it would alone).  Each graph stops on its own L1 change
+ *    (see dg_set_pagerank).
+ * A graph that met its stopping rule is no longer swept, while the others
+ * go on; out_sweeps reports each graph's own sweep count. */
 typedef struct dg_set dg_set;
 
 typedef struct {

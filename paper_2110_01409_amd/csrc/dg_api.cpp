@@ -134,6 +134,59 @@ using dg::host::dev_alloc;
 using dg::host::dev_free;
 using dg::host::topo;
 
+namespace dg {
+namespace host {
+
+// Staging for a commit interval d.  LDS holds d values plus one more tile
+// (each staged vertex keeps its value and the 4-byte slot it is committed
+// to) when that fits next to the resident table (res values) and the
+// kernel's static LDS in kLdsBudget (the compute unit's LDS, which one sweep
+// workgroup fills), and in at most 16 KB; larger intervals stage in a global
+// per-vertex shadow array.  Returns the LDS capacity (0 = global shadow) and the
+// effective interval.
+constexpr size_t kLdsStage = 16 * 1024;
+constexpr size_t kStaticLds = 14 * 1024;  // bound on the sweep kernels' static LDS
+void staging(const dg_graph* g, uint32_t d, size_t elem, uint32_t res, uint32_t& cap, uint32_t& d_eff,
+             bool& shadow) {
+  d_eff = std::min(d, g->max_block_v);
+  if (d_eff < 1) d_eff = 1;
+  const size_t need = ((size_t)d_eff + kTileV) * (elem + 4);
+  const size_t room = std::min(kLdsStage, kLdsBudget - kStaticLds - (size_t)res * elem - 16);
+  shadow = need > room;
+  cap = shadow ? 0u : d_eff + kTileV;
+}
+
+// Commits per sweep of a delayed single-query sweep, counted as the kernels
+// decide them: a worker commits at the end of the first tile that brings its
+// staged count to >= d, of a tile after which the next one would overflow
+// its LDS staging (cap, when not staging in the shadow), and of its last tile.
+uint32_t commits_per_sweep(const dg_graph* g, uint32_t d, uint32_t cap, bool shadow) {
+  uint32_t c = 0;
+  const std::vector<uint32_t>& tv = g->tile_v_h;
+  const std::vector<uint32_t>& wt = g->work_t_h;
+  for (size_t w = 0; w + 1 < wt.size(); ++w) {
+    uint32_t staged = 0;
+    for (uint32_t t = wt[w]; t < wt[w + 1]; ++t) {
+      const uint32_t nv = tv[t + 1] - tv[t];
+      const bool more = t + 1 < wt[w + 1];
+      const uint32_t nvn = more ? tv[t + 2] - tv[t + 1] : 0u;
+      const bool flush = !more || staged + nv >= d || (!shadow && staged + nv + nvn > cap);
+      staged += nv;
+      if (flush) {
+        ++c;
+        staged = 0;
+      }
+    }
+  }
+  return c;
+}
+
+}  // namespace host
+}  // namespace dg
+
+using dg::host::commits_per_sweep;
+using dg::host::staging;
+
 namespace {
 
 void release_all(dg_graph* g) {
@@ -235,23 +288,43 @@ uint32_t resident(const dg_graph* g, size_t elem) {
   return std::min<uint32_t>(g->R, kResBytes / (uint32_t)elem);
 }
 
-// Staging for a commit interval d.  LDS holds d values plus one more tile
-// (each staged vertex keeps its value and the 4-byte slot it is committed
-// to) when that fits next to the resident table (res values) and the
-// kernel's static LDS in kLdsBudget (the compute unit's LDS, which one sweep
-// workgroup fills), and in at most 16 KB; larger intervals stage in a global
-// per-vertex shadow array.  Returns the LDS capacity (0 = global shadow) and the
-// effective interval.
-constexpr size_t kLdsStage = 16 * 1024;
-constexpr size_t kStaticLds = 14 * 1024;  // bound on the sweep kernels' static LDS
-void staging(const dg_graph* g, uint32_t d, size_t elem, uint32_t res, uint32_t& cap, uint32_t& d_eff,
-             bool& shadow) {
-  d_eff = std::min(d, g->max_block_v);
-  if (d_eff < 1) d_eff = 1;
-  const size_t need = ((size_t)d_eff + kTileV) * (elem + 4);
-  const size_t room = std::min(kLdsStage, kLdsBudget - kStaticLds - (size_t)res * elem - 16);
-  shadow = need > room;
-  cap = shadow ? 0u : d_eff + kTileV;
+// Fields of dg_stats that describe the partition and the commits.
+void fill_shape(const dg_graph* g, bool delayed, uint32_t d_eff, uint32_t cap, bool shadow, dg_stats* st) {
+  st->workers = g->P;
+  st->tile_vertices = g->T ? (uint32_t)(((uint64_t)g->n + g->T / 2) / g->T) : 0u;
+  st->commits = delayed ? commits_per_sweep(g, d_eff, cap, shadow) : 0u;
+  st->commit_interval = st->commits ? (uint32_t)(((uint64_t)g->n + st->commits / 2) / st->commits) : 0u;
+}
+
+// err_bound of dg_pagerank: ||T(y) - y||_1 / (1 - damping) for the float64
+// scores y (device, vertex order), by one synchronous float64 sweep in the
+// graph's workspace (its three value arrays; y may be one of them, and is
+// read before any is written).  Synchronises the stream.
+dg_status certify(dg_graph* g, const double* y, double damping, const SweepState& sst, hipStream_t s,
+                  double& bound) {
+  double* x = static_cast<double*>(g->vals[0]);
+  double* c0 = static_cast<double*>(y == g->vals[1] ? g->vals[2] : g->vals[1]);
+  double* c1 = static_cast<double*>(c0 == g->vals[1] ? g->vals[2] : g->vals[1]);
+  DG_HIP(launch_bound_setup(y, x, c0, g->out_deg, g->cpos, g->n, sst, g->norm, s));
+  PrArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.g = topo(g);
+  a.st = sst;
+  a.st.hresid = nullptr;
+  a.st.hchanged = nullptr;
+  a.x = x;
+  a.cin = c0;
+  a.cout = c1;
+  a.alpha = damping;
+  a.tol = 0.0;
+  a.k = 0;
+  a.res = resident(g, sizeof(double));
+  DG_HIP(launch_pr_sweep(kSync, true, a, s));
+  double r = 0.0;
+  DG_HIP(hipMemcpyAsync(&r, sst.resid + 1, sizeof r, hipMemcpyDeviceToHost, s));
+  DG_HIP(hipStreamSynchronize(s));
+  bound = r / (1.0 - damping);
+  return DG_OK;
 }
 
 // Convergence loop shared by every entry point.  launch(k) enqueues sweep k,
@@ -413,7 +486,60 @@ dg_status dg_set_allocator(dg_alloc_fn alloc, dg_free_fn free_fn, void* ctx) {
 dg_status dg_graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
                           const uint32_t* w, const dg_graph_opts* opts, void* hip_stream, dg_graph** out) {
   g_last_error.clear();
-  return dg::host::graph_create(n, m, layout, ptr, idx, w, opts, nullptr, hip_stream, out);
+  if (!opts || opts->arrays_on_device == 0)
+    return dg::host::graph_create(n, m, layout, ptr, idx, w, opts, nullptr, hip_stream, out);
+  if (opts->arrays_on_device != 1)
+    return fail(DG_ERR_INVALID_ARGUMENT, "arrays_on_device = %u, expected 0 or 1", opts->arrays_on_device);
+  // Device arrays: checked for what can be checked without reading them,
+  // then copied to the host, where the layout is built as for host input.
+  if (!out) return fail(DG_ERR_INVALID_ARGUMENT, "out is NULL");
+  if (n == 0 || n > 0xFFFFFFFEu) return fail(DG_ERR_INVALID_ARGUMENT, "n = %u outside [1, 2^32-2]", n);
+  if (m >= (uint64_t)0xFFFFFFFFu - 2 * kEdgePad)
+    return fail(DG_ERR_INVALID_ARGUMENT, "m = %llu too large", (unsigned long long)m);
+  if (!ptr) return fail(DG_ERR_INVALID_ARGUMENT, "ptr is NULL");
+  if (m > 0 && !idx) return fail(DG_ERR_INVALID_ARGUMENT, "idx is NULL");
+  int dev = 0;
+  hipError_t he = hipGetDevice(&dev);
+  if (he != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(DG_ERR_DEVICE, "no usable HIP device: %s", hipGetErrorString(he));
+  }
+  struct Arr {
+    const void* p;
+    size_t bytes;
+    const char* name;
+  } arrs[] = {{ptr, ((size_t)n + 1) * sizeof(uint64_t), "ptr"},
+              {idx, (size_t)m * sizeof(uint32_t), "idx"},
+              {w, (size_t)m * sizeof(uint32_t), "w"}};
+  for (const Arr& a : arrs) {
+    if (!a.p || a.bytes == 0) continue;
+    hipPointerAttribute_t at;
+    std::memset(&at, 0, sizeof at);
+    he = hipPointerGetAttributes(&at, a.p);
+    if (he != hipSuccess || (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)) {
+      (void)hipGetLastError();
+      return fail(DG_ERR_INVALID_ARGUMENT, "%s is not device memory (arrays_on_device = 1)", a.name);
+    }
+  }
+  std::vector<uint64_t> hptr;
+  std::vector<uint32_t> hidx, hw;
+  try {
+    hptr.resize((size_t)n + 1);
+    hidx.resize((size_t)m);
+    if (w) hw.resize(m ? (size_t)m : 1u);  // non-empty, so that a weighted graph without edges keeps w != NULL
+  } catch (const std::bad_alloc&) {
+    return fail(DG_ERR_OUT_OF_MEMORY, "host copy of the device arrays failed");
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  DG_HIP(hipMemcpyAsync(hptr.data(), ptr, hptr.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  if (m) DG_HIP(hipMemcpyAsync(hidx.data(), idx, (size_t)m * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  if (w && m) DG_HIP(hipMemcpyAsync(hw.data(), w, (size_t)m * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  DG_HIP(hipStreamSynchronize(s));
+  dg_graph_opts host_opts = *opts;
+  host_opts.arrays_on_device = 0;
+  const uint32_t* wp = w ? hw.data() : nullptr;
+  return dg::host::graph_create(n, m, layout, hptr.data(), m ? hidx.data() : nullptr, wp, &host_opts, nullptr,
+                                hip_stream, out);
 }
 
 }  // extern "C"
@@ -490,6 +616,7 @@ dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
     build_workers(L.tile_v, L.tile_e0, P, work_t);
   }
   g->P = P;
+  g->work_t_h = work_t;
   for (uint32_t wk = 0; wk < P; ++wk)
     g->max_block_v = std::max(g->max_block_v, L.tile_v[work_t[wk + 1]] - L.tile_v[work_t[wk]]);
   std::vector<uint32_t> work_tb;
@@ -719,15 +846,18 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
   if (!out_on_device && mode != DG_SYNC) dst = static_cast<double*>(g->vals[2]);
   DG_HIP(launch_normalize(f64, x, g->n, dst, g->norm, s));
   if (!out_on_device) DG_HIP(hipMemcpyAsync(out_scores, dst, (size_t)g->n * 8, hipMemcpyDeviceToHost, s));
+  double bound = 0.0;
+  if (stats && (stats->request & DG_STATS_ERR_BOUND)) {
+    if ((st = certify(g, dst, damping, sst, s, bound)) != DG_OK) return st;
+  }
   DG_HIP(hipStreamSynchronize(s));
   if (stats) {
     stats->sweeps = sweeps;
-    stats->workers = g->P;
-    stats->tile_vertices = kTileV;
-    stats->commit_interval = delayed ? d_eff : 0;
+    fill_shape(g, delayed, d_eff, cap, use_shadow, stats);
     stats->residual = resid;
     stats->seconds = secs;
     stats->edges_traversed = g->m * (uint64_t)sweeps;
+    stats->err_bound = bound;
   }
   if (!conv) return fail(DG_ERR_NOT_CONVERGED, "no convergence within %u sweeps (last change %g)", max_sweeps, resid);
   return DG_OK;
@@ -817,12 +947,11 @@ dg_status sssp_run(dg_graph* g, uint32_t src, const uint32_t* more_src, uint32_t
   DG_HIP(hipStreamSynchronize(s));
   if (stats) {
     stats->sweeps = sweeps;
-    stats->workers = g->P;
-    stats->tile_vertices = kTileV;
-    stats->commit_interval = delayed ? d_eff : 0;
+    fill_shape(g, delayed, d_eff, cap, use_shadow, stats);
     stats->residual = 0.0;
     stats->seconds = secs;
     stats->edges_traversed = g->m * (uint64_t)sweeps;
+    stats->err_bound = 0.0;
   }
   if (!conv) return fail(DG_ERR_NOT_CONVERGED, "no convergence within %u sweeps", max_sweeps);
   return DG_OK;
@@ -949,8 +1078,10 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
     }
     stats->sweeps = sweeps;
     stats->workers = g->Pb;
-    stats->tile_vertices = kTileV;
+    stats->tile_vertices = g->T ? (uint32_t)(((uint64_t)g->n + g->T / 2) / g->T) : 0u;
     stats->commit_interval = mode == DG_DELAYED ? a.d : 0;
+    stats->commits = 0;
+    stats->err_bound = 0.0;
     stats->residual = 0.0;
     stats->seconds = secs;
     stats->edges_traversed = g->m * qe;
@@ -1068,8 +1199,10 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
     }
     stats->sweeps = sweeps;
     stats->workers = g->Pb;
-    stats->tile_vertices = kTileV;
+    stats->tile_vertices = g->T ? (uint32_t)(((uint64_t)g->n + g->T / 2) / g->T) : 0u;
     stats->commit_interval = mode == DG_DELAYED ? a.d : 0;
+    stats->commits = 0;
+    stats->err_bound = 0.0;
     stats->residual = last_r;
     stats->seconds = secs;
     stats->edges_traversed = g->m * qe;
@@ -1101,6 +1234,7 @@ dg_status dg_graph_repartition(dg_graph* g, uint32_t workers, void* hip_stream) 
   DG_HIP(hipStreamSynchronize(s));
   dev_free(g, g->work_t);
   g->work_t = wt;
+  g->work_t_h = work_t;
   if (g->part) {
     dev_free(g, g->part);
     g->part = part;

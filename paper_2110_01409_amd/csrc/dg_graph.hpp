@@ -58,6 +58,7 @@ struct dg_graph {
   // dg_ppr_batch, the server): Pb workers, most vertices per block.
   uint32_t Pb = 0, max_block_vb = 1;
   std::vector<uint32_t> tile_v_h, tile_e0_h;  // host copies: first vertex / first in-edge of each tile
+  std::vector<uint32_t> work_t_h;             // host copy of work_t: first tile of each worker
   uint64_t hash = 0;                         // content hash of the in-edge form (tuning cache key)
   // Graph sets: the union of G graphs, with worker blocks aligned to graph
   // boundaries (graph i's workers are wseg[i] .. wseg[i+1]-1); G = 0 otherwise.
@@ -118,6 +119,13 @@ Topology topo_batch(const dg_graph* g);
 dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
                        const uint32_t* w, const dg_graph_opts* opts, const std::vector<uint32_t>* seg_v,
                        void* hip_stream, dg_graph** out);
+// Staging of a delayed single-query sweep for commit interval d with elem-byte
+// values and res resident-table entries: LDS capacity cap (0 = the global
+// per-vertex shadow, shadow = true) and the effective interval d_eff.
+void staging(const dg_graph* g, uint32_t d, size_t elem, uint32_t res, uint32_t& cap, uint32_t& d_eff,
+             bool& shadow);
+// Commits per sweep of a delayed single-query sweep with that staging.
+uint32_t commits_per_sweep(const dg_graph* g, uint32_t d, uint32_t cap, bool shadow);
 // Bellman-Ford from src and, when n_more > 0, also from the n_more sources in
 // the device array more_src (distance to the nearest source); otherwise as
 // dg_sssp.

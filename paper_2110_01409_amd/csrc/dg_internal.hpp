@@ -222,6 +222,12 @@ hipError_t launch_by_vertex(bool f64, const void* c, const uint32_t* cpos, uint3
 // out[v] = x[v] / sum(x), sum in float64 with a fixed reduction order.
 hipError_t launch_normalize(bool f64, const void* x, uint32_t n, double* out, double* scratch, hipStream_t s);
 constexpr uint32_t kNormBlocks = 512;  // scratch needs kNormBlocks + 1 doubles
+// Inputs of a synchronous float64 sweep that evaluates T(y) for the float64
+// scores y (vertex order): x = y, c[cpos[v]] = y[v] / outdeg(v), and sweep
+// state row 0 set to run once spreading the dangling mass of y.  The sweep's
+// residual resid[1] is then ||T(y) - y||_1.  scratch: kNormBlocks + 1 doubles.
+hipError_t launch_bound_setup(const double* y, double* x, double* c, const uint32_t* out_deg, const uint32_t* cpos,
+                              uint32_t n, SweepState st, double* scratch, hipStream_t s);
 
 // Sets of graphs stored as one union graph (disjoint vertex ranges).
 // Distances 0 at k more sources (device array src of vertex ids), in both

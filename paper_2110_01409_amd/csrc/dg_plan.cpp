@@ -275,6 +275,8 @@ dg_status dg_plan_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_
   g_last_error.clear();
   if (!out) return fail(DG_ERR_INVALID_ARGUMENT, "out is NULL");
   if (compute_units == 0) return fail(DG_ERR_INVALID_ARGUMENT, "compute_units must be >= 1");
+  if (opts && opts->arrays_on_device != 0)
+    return fail(DG_ERR_INVALID_ARGUMENT, "a plan is built without a device: arrays_on_device must be 0");
   dg_status st = dg::host::validate_graph(n, m, layout, ptr, idx);
   if (st != DG_OK) return st;
   dg_plan* p = new (std::nothrow) dg_plan;

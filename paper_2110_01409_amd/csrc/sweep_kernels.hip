@@ -869,6 +869,42 @@ __global__ __launch_bounds__(kWG) void scale_kernel(const T* x, uint32_t n, cons
   if (i < n) out[i] = (double)x[i] / *total;
 }
 
+// Error certificate of a score vector y (float64, vertex order, sum 1): the
+// inputs of one synchronous float64 sweep, which then evaluates T(y) and
+// reports ||T(y) - y||_1 as its residual.  x[v] = y[v] (the sweep's old
+// score), c[cpos[v]] = y[v] / outdeg(v) (0 for a dangling v), and part[b] =
+// the dangling mass in block b's grid-stride share (summed in fixed order).
+__global__ __launch_bounds__(kWG) void bound_init_kernel(const double* y, double* x, double* c,
+                                                         const uint32_t* out_deg, const uint32_t* cpos, uint32_t n,
+                                                         double* part) {
+  __shared__ double s[kWG / 64];
+  double acc = 0.0;
+  for (uint32_t v = blockIdx.x * kWG + threadIdx.x; v < n; v += gridDim.x * kWG) {
+    const double yv = y[v];
+    const uint32_t dg = out_deg[v];
+    x[v] = yv;
+    c[cpos[v]] = dg ? yv / (double)dg : 0.0;
+    if (dg == 0) acc += yv;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63u) == 0) s[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0] + s[1] + s[2] + s[3];
+}
+
+// Sweep state of the certificate sweep (sweep 0 of a fresh row): it runs
+// (resid[0] = inf), spreads the dangling mass *dang (= D(y)), and starts its
+// worker count at 0.
+__global__ void bound_state_kernel(SweepState st, const double* dang) {
+  if (threadIdx.x == 0) {
+    st.resid[0] = __builtin_inf();
+    st.resid[1] = 0.0;
+    st.dang[0] = *dang;
+    st.count[0] = 0;
+    st.count[1] = 0;
+  }
+}
+
 // out[v] = c[cpos[v]]: committed values in vertex order (the local-read
 // variant starts its shadow from them).
 template <typename T>
@@ -936,6 +972,14 @@ hipError_t launch_pr_sweep(int mode, bool f64, const PrArgs& a, hipStream_t s) {
     else if (mode == kDelayedLocal) pr_sweep_variant<kDelayed, float, true>(a, s);
     else pr_sweep_variant<kDelayed, float, false>(a, s);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_bound_setup(const double* y, double* x, double* c, const uint32_t* out_deg, const uint32_t* cpos,
+                              uint32_t n, SweepState st, double* scratch, hipStream_t s) {
+  bound_init_kernel<<<kNormBlocks, kWG, 0, s>>>(y, x, c, out_deg, cpos, n, scratch);
+  sum_partials_kernel<<<1, kWG, 0, s>>>(scratch, kNormBlocks);
+  bound_state_kernel<<<1, 64, 0, s>>>(st, scratch + kNormBlocks);
   return hipGetLastError();
 }
 

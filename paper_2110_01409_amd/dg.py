@@ -36,8 +36,8 @@ EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_
            "dg_set_pagerank", "dg_set_sssp", "dg_graph_partition", "dg_access_matrix", "dg_graph_repartition",
            "dg_tune", "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_server_create",
            "dg_server_destroy", "dg_server_submit", "dg_server_step", "dg_server_fetch", "dg_server_status_get",
-           "dg_plan_create", "dg_plan_info_get", "dg_plan_arrays", "dg_plan_destroy", "dg_status_str",
-           "dg_last_error", "dg_version")
+           "dg_plan_create", "dg_plan_info_get", "dg_plan_arrays", "dg_plan_destroy",
+           "dg_status_str", "dg_last_error", "dg_version")
 DG_QUERY_SSSP, DG_QUERY_PPR = 0, 1
 QUERIES = {"sssp": DG_QUERY_SSSP, "ppr": DG_QUERY_PPR}
 DG_ALGO_PAGERANK, DG_ALGO_SSSP = 0, 1
@@ -48,7 +48,11 @@ MODE_NAMES = {0: "sync", 1: "async", 2: "delayed"}
 class dg_stats(C.Structure):
     _fields_ = [("sweeps", C.c_uint32), ("workers", C.c_uint32), ("tile_vertices", C.c_uint32),
                 ("commit_interval", C.c_uint32), ("residual", C.c_double), ("seconds", C.c_double),
-                ("edges_traversed", C.c_uint64)]
+                ("edges_traversed", C.c_uint64), ("err_bound", C.c_double), ("request", C.c_uint32),
+                ("commits", C.c_uint32)]
+
+
+DG_STATS_ERR_BOUND = 1
 
 
 class dg_graph_info(C.Structure):
@@ -68,7 +72,7 @@ class dg_plan_info(C.Structure):
 
 class dg_graph_opts(C.Structure):
     _fields_ = [("workers", C.c_uint32), ("hot_vertices", C.c_uint32), ("resident_vertices", C.c_uint32),
-                ("sweep_variant", C.c_uint32)]
+                ("sweep_variant", C.c_uint32), ("arrays_on_device", C.c_uint32)]
 
 
 DG_HOT_AUTO = 0xFFFFFFFF
@@ -415,6 +419,10 @@ def _np_ptr(a):
     return a.ctypes.data_as(C.c_void_p)
 
 
+def _is_device_tensor(a):
+    return hasattr(a, "is_cuda") and bool(a.is_cuda)
+
+
 @dataclasses.dataclass
 class Stats:
     sweeps: int
@@ -425,6 +433,8 @@ class Stats:
     seconds: float
     edges_traversed: int
     converged: bool
+    err_bound: float = 0.0
+    commits: int = 0
 
     @property
     def gteps(self) -> float:
@@ -433,7 +443,7 @@ class Stats:
 
 def _stats(s: dg_stats, converged: bool) -> Stats:
     return Stats(s.sweeps, s.workers, s.tile_vertices, s.commit_interval, s.residual, s.seconds,
-                 s.edges_traversed, converged)
+                 s.edges_traversed, converged, s.err_bound, s.commits)
 
 
 class Graph:
@@ -450,20 +460,32 @@ class Graph:
 
     def __init__(self, n, ptr, idx, w=None, layout="csr", stream=None, torch_allocator=True, workers=0,
                  hot_vertices=DG_HOT_AUTO, resident_vertices=DG_RESIDENT_AUTO, sweep_variant="auto"):
-        ptr = np.ascontiguousarray(ptr, dtype=np.uint64)
-        idx = np.ascontiguousarray(idx, dtype=np.uint32)
-        wa = None if w is None else np.ascontiguousarray(w, dtype=np.uint32)
+        dev = _is_device_tensor(ptr)
+        if dev:
+            # device arrays (torch tensors of the required dtypes, contiguous)
+            import torch
+            for a, want in ((ptr, torch.uint64), (idx, torch.uint32), (w, torch.uint32)):
+                if a is not None and (not _is_device_tensor(a) or a.dtype != want or not a.is_contiguous()):
+                    raise TypeError("device input needs contiguous device tensors: ptr uint64, idx and w uint32")
+            pp, ip = C.c_void_p(ptr.data_ptr()), C.c_void_p(idx.data_ptr())
+            wp = None if w is None else C.c_void_p(w.data_ptr())
+            m = int(idx.shape[0])
+        else:
+            ptr = np.ascontiguousarray(ptr, dtype=np.uint64)
+            idx = np.ascontiguousarray(idx, dtype=np.uint32)
+            wa = None if w is None else np.ascontiguousarray(w, dtype=np.uint32)
+            pp, ip, wp = _np_ptr(ptr), _np_ptr(idx), None if wa is None else _np_ptr(wa)
+            m = int(idx.shape[0])
         if torch_allocator:
             use_torch_allocator()
         h = C.c_void_p()
         lay = DG_CSR if layout == "csr" else DG_CSC
-        opts = dg_graph_opts(int(workers), int(hot_vertices), int(resident_vertices), SWEEP_VARIANTS[sweep_variant])
-        _check(dg_graph_create(int(n), int(idx.shape[0]), lay, _np_ptr(ptr), _np_ptr(idx),
-                               None if wa is None else _np_ptr(wa), C.byref(opts), _stream_handle(stream),
-                               C.byref(h)))
+        opts = dg_graph_opts(int(workers), int(hot_vertices), int(resident_vertices), SWEEP_VARIANTS[sweep_variant],
+                             1 if dev else 0)
+        _check(dg_graph_create(int(n), m, lay, pp, ip, wp, C.byref(opts), _stream_handle(stream), C.byref(h)))
         self._h = h
         self.n = int(n)
-        self.m = int(idx.shape[0])
+        self.m = m
         self._dependents = []  # objects holding device state allocated through this graph
 
     @classmethod
@@ -476,12 +498,15 @@ class Graph:
         return inf
 
     def pagerank(self, damping=0.85, tol=1e-6, mode="delayed", d=64, dtype="f32", max_sweeps=10_000,
-                 out=None, stream=None, allow_not_converged=False):
-        """Returns (scores float64 tensor on the device, Stats)."""
+                 out=None, stream=None, allow_not_converged=False, err_bound=False):
+        """Returns (scores float64 tensor on the device, Stats); with
+        err_bound=True, Stats.err_bound holds the device-computed certificate
+        ||T(x) - x||_1 / (1 - damping)."""
         import torch
         if out is None:
             out = torch.empty(self.n, dtype=torch.float64, device="cuda")
         st = dg_stats()
+        st.request = DG_STATS_ERR_BOUND if err_bound else 0
         s = _check(dg_pagerank(self._h, float(damping), float(tol), MODES[mode], int(d), DTYPES[dtype],
                                int(max_sweeps), C.c_void_p(out.data_ptr()), 1, C.byref(st),
                                _stream_handle(stream)),

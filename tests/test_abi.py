@@ -92,6 +92,56 @@ def test_valid_graph_without_device(dg):
         assert s == dg.DG_ERR_DEVICE and "device" in dg.last_error()
 
 
+@pytest.mark.parametrize("case", ["flag2", "null_ptr", "null_idx", "n0", "m_huge"])
+def test_create_device_arrays_validation(dg, case):
+    """arrays_on_device: the checks that need no read of the arrays come
+    before any device call, so they hold on a machine without a GPU."""
+    ptr = np.array([0, 1, 3, 3], np.uint64)
+    idx = np.array([1, 0, 2], np.uint32)
+    n, m = 3, 3
+    opts = dg.dg_graph_opts(0, dg.DG_HOT_AUTO, dg.DG_RESIDENT_AUTO, 0, 2 if case == "flag2" else 1)
+    pp, ip = dg._np_ptr(ptr), dg._np_ptr(idx)
+    if case == "null_ptr":
+        pp = None
+    elif case == "null_idx":
+        ip = None
+    elif case == "n0":
+        n = 0
+    elif case == "m_huge":
+        m = 0xFFFFFFFF
+    h = C.c_void_p()
+    s = dg.dg_graph_create(n, m, dg.DG_CSR, pp, ip, None, C.byref(opts), None, C.byref(h))
+    assert s == dg.DG_ERR_INVALID_ARGUMENT, dg.last_error()
+    assert dg.last_error() and not h.value
+
+
+def test_create_device_arrays_needs_device_memory(dg):
+    """Host pointers flagged as device arrays: DG_ERR_DEVICE without a GPU,
+    DG_ERR_INVALID_ARGUMENT (not device memory) with one."""
+    import torch
+    ptr = np.array([0, 1, 3, 3], np.uint64)
+    idx = np.array([1, 0, 2], np.uint32)
+    opts = dg.dg_graph_opts(0, dg.DG_HOT_AUTO, dg.DG_RESIDENT_AUTO, 0, 1)
+    h = C.c_void_p()
+    s = dg.dg_graph_create(3, 3, dg.DG_CSR, dg._np_ptr(ptr), dg._np_ptr(idx), None, C.byref(opts), None,
+                           C.byref(h))
+    if torch.cuda.is_available():
+        assert s == dg.DG_ERR_INVALID_ARGUMENT and "device memory" in dg.last_error()
+    else:
+        assert s == dg.DG_ERR_DEVICE
+    assert not h.value
+
+
+def test_plan_refuses_device_arrays(dg):
+    ptr = np.array([0, 1, 3, 3], np.uint64)
+    idx = np.array([1, 0, 2], np.uint32)
+    opts = dg.dg_graph_opts(0, dg.DG_HOT_AUTO, dg.DG_RESIDENT_AUTO, 0, 1)
+    h = C.c_void_p()
+    s = dg.dg_plan_create(3, 3, dg.DG_CSR, dg._np_ptr(ptr), dg._np_ptr(idx), None, C.byref(opts), 8, C.byref(h))
+    assert s == dg.DG_ERR_INVALID_ARGUMENT and "arrays_on_device" in dg.last_error()
+    assert not h.value
+
+
 def test_call_validation_null_graph(dg):
     out = np.zeros(4, np.float64)
     st = dg.dg_stats()

@@ -282,7 +282,7 @@ def test_validation(dg):
     assert dg.dg_plan_create(2, 2, 7, dg._np_ptr(ptr), dg._np_ptr(idx), None, None, 1, dg.C.byref(h)) == P
     assert dg.dg_plan_create(2, 2, 0, dg._np_ptr(ptr), dg._np_ptr(idx), None, None, 1, None) == P
     # an unknown sweep variant
-    bad = dg.dg_graph_opts(0, dg.DG_HOT_AUTO, dg.DG_RESIDENT_AUTO, 4)
+    bad = dg.dg_graph_opts(0, dg.DG_HOT_AUTO, dg.DG_RESIDENT_AUTO, 4, 0)
     assert dg.dg_plan_create(2, 2, 0, dg._np_ptr(ptr), dg._np_ptr(idx), None, dg.C.byref(bad), 1, dg.C.byref(h)) == P
     assert "sweep_variant" in dg.last_error()
     assert dg.dg_plan_info_get(None, None) == P
