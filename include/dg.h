@@ -585,6 +585,31 @@ dg_status dg_server_step(dg_server* s, uint64_t* out_finished, uint32_t cap, uin
 dg_status dg_server_fetch(dg_server* s, uint64_t id, void* out, int out_on_device, dg_request_info* info);
 dg_status dg_server_status_get(const dg_server* s, dg_server_status* status);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): dg_sssp on a resident
+ * graph with no allocation of any kind during the call.  The sweeps' value
+ * arrays, staging and per-sweep state live in one fixed device array of the
+ * library, DG_NOALLOC_SCRATCH_BYTES (96 MiB) per GPU, held from the first
+ * call on that GPU until the process ends.  Results, sweep counts and the
+ * kernels are those of dg_sssp (bit-identical distances in every mode).
+ *   mode        DG_SYNC, DG_ASYNC or DG_DELAYED (not DG_DELAYED_LOCAL)
+ *   max_sweeps  1 <= max_sweeps <= 65535
+ *   out_dist    as for dg_sssp (device or host memory)
+ *   stats       as for dg_sssp, except that `seconds` is host wall time from
+ *               the first sweep launch to the host seeing the stopping flag
+ *               (the call uses no events)
+ * Needs (n + K) x 4 bytes (twice in DG_SYNC), plus n x 4 for the delayed
+ * modes' shadow staging when d is large, plus n x 4 for host output, plus
+ * about 24 x max_sweeps + 24 x workers bytes, each part rounded up to 256:
+ * a call that needs more returns DG_ERR_UNSUPPORTED and does nothing.  K is
+ * dg_graph_info.hot_vertices.  Not for the union graph of a set
+ * (DG_ERR_UNSUPPORTED).  Every call on a GPU uses that GPU's one array:
+ * calls that overlap in time on the same GPU (from several threads, or on
+ * several streams) race and give undefined results; serialise them. */
+#define DG_NOALLOC_SCRATCH_BYTES 100663296u
+dg_status dg_sssp_noalloc(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t max_sweeps,
+                          uint32_t* out_dist, int out_on_device, dg_stats* stats, void* hip_stream);
+
 /* Static name of a status code. */
 const char* dg_status_str(dg_status s);
 

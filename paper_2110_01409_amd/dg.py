@@ -36,8 +36,9 @@ EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_
            "dg_set_pagerank", "dg_set_sssp", "dg_graph_partition", "dg_access_matrix", "dg_graph_repartition",
            "dg_tune", "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_server_create",
            "dg_server_destroy", "dg_server_submit", "dg_server_step", "dg_server_fetch", "dg_server_status_get",
-           "dg_plan_create", "dg_plan_info_get", "dg_plan_arrays", "dg_plan_destroy",
+           "dg_plan_create", "dg_plan_info_get", "dg_plan_arrays", "dg_plan_destroy", "dg_sssp_noalloc",
            "dg_status_str", "dg_last_error", "dg_version")
+DG_NOALLOC_SCRATCH_BYTES = 100663296
 DG_QUERY_SSSP, DG_QUERY_PPR = 0, 1
 QUERIES = {"sssp": DG_QUERY_SSSP, "ppr": DG_QUERY_PPR}
 DG_ALGO_PAGERANK, DG_ALGO_SSSP = 0, 1
@@ -160,6 +161,8 @@ def _load():
         "dg_pagerank": (C.c_int, [P, C.c_double, C.c_double, C.c_int, C.c_uint32, C.c_int, C.c_uint32, P, C.c_int,
                                   C.POINTER(dg_stats), P]),
         "dg_sssp": (C.c_int, [P, C.c_uint32, C.c_int, C.c_uint32, C.c_uint32, P, C.c_int, C.POINTER(dg_stats), P]),
+        "dg_sssp_noalloc": (C.c_int, [P, C.c_uint32, C.c_int, C.c_uint32, C.c_uint32, P, C.c_int,
+                                      C.POINTER(dg_stats), P]),
         "dg_sssp_batch": (C.c_int, [P, P, C.c_uint32, C.c_int, C.c_uint32, C.c_uint32, P, C.c_int,
                                     C.POINTER(dg_stats), P]),
         "dg_ppr_batch": (C.c_int, [P, P, C.c_uint32, C.c_double, C.c_double, C.c_int, C.c_uint32, C.c_int, C.c_uint32, P,
@@ -249,6 +252,10 @@ def dg_pagerank(g, damping, tol, mode, d, dtype, max_sweeps, out, out_on_device,
 
 def dg_sssp(g, src, mode, d, max_sweeps, out, out_on_device, stats, stream):
     return lib.dg_sssp(g, src, mode, d, max_sweeps, out, out_on_device, stats, stream)
+
+
+def dg_sssp_noalloc(g, src, mode, d, max_sweeps, out, out_on_device, stats, stream):
+    return lib.dg_sssp_noalloc(g, src, mode, d, max_sweeps, out, out_on_device, stats, stream)
 
 
 def dg_sssp_batch(g, sources, k, mode, d, max_sweeps, out, out_on_device, stats, stream):
@@ -523,6 +530,22 @@ class Graph:
         st = dg_stats()
         s = _check(dg_sssp(self._h, int(src), MODES[mode], int(d), int(max_sweeps), C.c_void_p(out.data_ptr()), 1,
                            C.byref(st), _stream_handle(stream)),
+                   allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+        return out, _stats(st, s == DG_OK)
+
+    def sssp_noalloc(self, src, mode="delayed", d=64, max_sweeps=None, out=None, stream=None,
+                     allow_not_converged=False):
+        """dg_sssp_noalloc: as sssp, with no allocation inside the call (the
+        library's fixed scratch array).  ``out`` (uint32 [n], device) is
+        allocated here when not given, before the call."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.uint32, device="cuda")
+        if max_sweeps is None:
+            max_sweeps = min(self.n + 1, 65535)
+        st = dg_stats()
+        s = _check(dg_sssp_noalloc(self._h, int(src), MODES[mode], int(d), int(max_sweeps),
+                                   C.c_void_p(out.data_ptr()), 1, C.byref(st), _stream_handle(stream)),
                    allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
         return out, _stats(st, s == DG_OK)
 
