@@ -585,6 +585,20 @@ dg_status dg_server_step(dg_server* s, uint64_t* out_finished, uint32_t cap, uin
 dg_status dg_server_fetch(dg_server* s, uint64_t id, void* out, int out_on_device, dg_request_info* info);
 dg_status dg_server_status_get(const dg_server* s, dg_server_status* status);
 
+/* Gather-rate probe (measurement support, not a sweep): the time of random
+ * 4-byte loads from a table of table_bytes (a power of two in [4 KiB,
+ * 4 GiB]), the access a single query's pull sweep makes once per in-edge
+ * (section III-A: every in-neighbour's value is read from the global array).
+ * workgroups x 256 threads each make per_thread (a multiple of 16, at most
+ * 4096) loads, 16 in flight, at indices uniform over the table; streamed = 1
+ * reads each index from a coalesced 4-byte index stream (as a sweep reads
+ * its in-edge stream), streamed = 0 computes it.  The call allocates its
+ * table and stream with hipMalloc, runs one warm-up launch, and returns the
+ * best of three timed launches in *out_seconds (events on hip_stream).
+ * Total loads per launch must stay below 2^32. */
+dg_status dg_probe_gather(uint64_t table_bytes, int streamed, uint32_t per_thread, uint32_t workgroups,
+                          double* out_seconds, void* hip_stream);
+
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid allocation): dg_sssp on a resident
  * graph with no allocation of any kind during the call.  The sweeps' value

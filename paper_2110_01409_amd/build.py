@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdg.so")
 
 SOURCES = ["sweep_kernels.hip", "batch_kernels.hip", "set_kernels.hip", "topo_kernels.hip", "dg_api.cpp", "dg_plan.cpp", "dg_set.cpp",
-           "dg_server.cpp", "dg_noalloc.hip"]
+           "dg_server.cpp", "probe_kernels.hip", "dg_noalloc.hip"]
 
 
 def hipcc() -> str:

@@ -36,7 +36,7 @@ EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_
            "dg_set_pagerank", "dg_set_sssp", "dg_graph_partition", "dg_access_matrix", "dg_graph_repartition",
            "dg_tune", "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_server_create",
            "dg_server_destroy", "dg_server_submit", "dg_server_step", "dg_server_fetch", "dg_server_status_get",
-           "dg_plan_create", "dg_plan_info_get", "dg_plan_arrays", "dg_plan_destroy", "dg_sssp_noalloc",
+           "dg_plan_create", "dg_plan_info_get", "dg_plan_arrays", "dg_plan_destroy", "dg_probe_gather", "dg_sssp_noalloc",
            "dg_status_str", "dg_last_error", "dg_version")
 DG_NOALLOC_SCRATCH_BYTES = 100663296
 DG_QUERY_SSSP, DG_QUERY_PPR = 0, 1
@@ -187,6 +187,7 @@ def _load():
         "dg_server_step": (C.c_int, [P, P, C.c_uint32, C.POINTER(C.c_uint32)]),
         "dg_server_fetch": (C.c_int, [P, C.c_uint64, P, C.c_int, C.POINTER(dg_request_info)]),
         "dg_server_status_get": (C.c_int, [P, C.POINTER(dg_server_status)]),
+        "dg_probe_gather": (C.c_int, [C.c_uint64, C.c_int, C.c_uint32, C.c_uint32, C.POINTER(C.c_double), P]),
         "dg_status_str": (C.c_char_p, [C.c_int]),
         "dg_last_error": (C.c_char_p, []),
         "dg_version": (C.c_char_p, []),
@@ -339,6 +340,19 @@ def dg_server_fetch(srv, rid, out, out_on_device, info):
 
 def dg_server_status_get(srv, status):
     return lib.dg_server_status_get(srv, status)
+
+
+def dg_probe_gather(table_bytes, streamed, per_thread, workgroups, out_seconds, stream):
+    return lib.dg_probe_gather(table_bytes, streamed, per_thread, workgroups, out_seconds, stream)
+
+
+def probe_gather(table_bytes, streamed=False, per_thread=256, workgroups=1024, stream=None):
+    """Seconds of one launch of workgroups x 256 x per_thread random 4-byte
+    loads from a table of table_bytes (best of three), and the load count."""
+    sec = C.c_double()
+    _check(dg_probe_gather(int(table_bytes), 1 if streamed else 0, int(per_thread), int(workgroups), C.byref(sec),
+                           _stream_handle(stream)))
+    return sec.value, int(workgroups) * 256 * int(per_thread)
 
 
 def tune_cache_save(path):

@@ -264,3 +264,12 @@ def test_server_call_validation_null(dg):
     assert dg.dg_server_step(None, None, 0, C.byref(cnt)) == dg.DG_ERR_INVALID_ARGUMENT
     assert dg.dg_server_fetch(None, 1, None, 0, None) == dg.DG_ERR_INVALID_ARGUMENT
     assert dg.dg_server_destroy(None) == dg.DG_OK
+
+
+@pytest.mark.parametrize("args", [(1000, 0, 256, 4), (3 << 20, 0, 256, 4), (1 << 33, 0, 256, 4), (1 << 20, 2, 256, 4),
+                                  (1 << 20, 0, 0, 4), (1 << 20, 0, 17, 4), (1 << 20, 0, 256, 0),
+                                  (1 << 20, 0, 4096, 65536)])
+def test_probe_gather_validation(dg, args):
+    sec = C.c_double(-1.0)
+    assert dg.dg_probe_gather(*args, C.byref(sec), None) == dg.DG_ERR_INVALID_ARGUMENT
+    assert sec.value == -1.0 and dg.last_error()
