@@ -313,6 +313,32 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
                       dg_dtype dtype, uint32_t max_sweeps, double* out_scores,
                       int out_on_device, dg_stats* stats, void* hip_stream);
 
+/* Personalised PageRank of one restart vertex by repeated pull sweeps: the
+ * single-query form of dg_ppr_batch, on the sweep kernels of dg_pagerank
+ * (same partition, commit modes, staging and resident table).  It computes
+ *   x = (1 - damping) e_s + damping (A x + D(x) e_s),  s = src,
+ * where D(x) is the mass on dangling vertices: teleport and dangling mass
+ * both return to the restart vertex (the reading used for batched queries).
+ * Scores start at e_s.  After every sweep the vector is rescaled to mass 1
+ * (a per-sweep float64 factor; stored values are never touched): the fixed
+ * point has mass 1, and the rescale removes the mass error that
+ * asynchronous and delayed commits leave.  The stopping rule, tol, dtype,
+ * d, max_sweeps and outputs are those of dg_pagerank (scores normalised to
+ * sum 1; stats.err_bound, when requested, is the certificate of this map).
+ * The stopping rule bounds a synchronous iterate's L1 error by
+ * damping / (1 - damping) x tol (5.7 tol at 0.85), so an error of 1e-6 needs
+ * tol <= 1.5e-7, which float32 storage reaches on R-MAT, banded and
+ * dangling-heavy graphs (measured).  Where float32 rounding keeps the change
+ * above tol (mass on a few vertices can settle into a period-2 cycle near
+ * 2e-7), DG_F32 also stops at the first sweep whose change is below 2 tol and
+ * more than 0.9 times the change two sweeps earlier (exact synchronous
+ * changes shrink by damping^2 over two sweeps); stats.residual then holds
+ * that change, >= tol.
+ *   src   restart vertex, < n
+ * Not for the union graph of a set (DG_ERR_UNSUPPORTED). */
+dg_status dg_ppr(dg_graph* g, uint32_t src, double damping, double tol, dg_mode mode, uint32_t d, dg_dtype dtype,
+                 uint32_t max_sweeps, double* out_scores, int out_on_device, dg_stats* stats, void* hip_stream);
+
 /* Bellman-Ford single-source shortest paths by repeated pull relaxation
  * sweeps (sections III and IV-D): d'(v) = min(d(v), min over in-edges
  * (u,v) of d(u) + w(u,v)), stored every sweep, stopping after the first
@@ -353,9 +379,13 @@ dg_status dg_sssp(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t 
  * its row is the iterate of that sweep (later sweeps of its batch leave it
  * untouched), so a row does not depend on the other queries of the call in
  * synchronous mode.  Float32 storage has a noise floor: the L1 change of a
- * sweep cannot settle much below the rounding of a vector of mass 1, about
- * 1e-7 with synchronous commits and 1e-7 to 3e-7 with asynchronous ones;
- * ask for tol >= 5e-7 with DG_F32, or use DG_F64.
+ * sweep cannot settle much below the rounding of a vector of mass 1 (about
+ * 1e-7).  The stopping rule bounds a synchronous row's L1 error by
+ * damping / (1 - damping) x tol, so 1e-6 needs tol <= 1.5e-7, which float32
+ * rows reach on R-MAT, banded and dangling-heavy graphs (measured).  A
+ * float32 query also stops at its rounding floor, by the rule of dg_ppr: a
+ * change below 2 tol that is more than 0.9 times its change two sweeps
+ * earlier.
  *   damping     0 <= damping < 1
  *   dtype       DG_F32 or DG_F64
  *   out_scores  k rows of n float64, each normalised to sum 1 */

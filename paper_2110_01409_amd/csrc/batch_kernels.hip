@@ -399,7 +399,15 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
     // single row, and asynchronous sweeps of that operator can diverge.
     a.dang[next] = live ? dm / ms : D;
     a.scale[next] = live ? S * ms : S;
-    if (live && !(r >= a.tol)) a.qdone[(size_t)b * kQ + lane] = k + 1;
+    if (live) {
+      bool stop = !(r >= a.tol);
+      if (!stop && a.rhist) {
+        // float32 stall rule: the change of sweep k-2 is in this ring slot
+        stop = r < kStallTols * a.tol && r > kStallRatio * a.rhist[ring];
+        a.rhist[ring] = r;
+      }
+      if (stop) a.qdone[(size_t)b * kQ + lane] = k + 1;
+    }
     // batch residual: the largest change among the queries still live
     double m = live ? r : 0.0;
 #pragma unroll
@@ -525,7 +533,7 @@ __global__ __launch_bounds__(kWG) void mppr_lane_init_kernel(T* x, T* c0, T* c1,
 // the dangling mass of x0 = e_s in both ring slots, running.
 __global__ __launch_bounds__(kWG) void mppr_lane_scalars_kernel(const uint32_t* lane_src, const uint32_t* out_deg,
                                                                 uint32_t NB, uint32_t* src, double* dang,
-                                                                double* scale, uint32_t* qdone) {
+                                                                double* scale, uint32_t* qdone, double* rhist) {
   const uint32_t i = blockIdx.x * kWG + threadIdx.x;
   if (i >= NB * kQ) return;
   const uint32_t s = lane_src[i];
@@ -537,6 +545,10 @@ __global__ __launch_bounds__(kWG) void mppr_lane_scalars_kernel(const uint32_t* 
   scale[i] = 1.0;
   scale[(size_t)NB * kQ + i] = 1.0;
   qdone[i] = 0;
+  if (rhist) {
+    rhist[i] = __builtin_inf();
+    rhist[(size_t)NB * kQ + i] = __builtin_inf();
+  }
 }
 
 // Row of one finished query: distances in vertex order.
@@ -668,7 +680,7 @@ hipError_t launch_mbf_lane_init(uint32_t* d0, uint32_t* d1, const uint32_t* cpos
 hipError_t launch_mppr_lane_init(bool f64, void* x, void* c0, void* c1, const uint32_t* out_deg, const uint32_t* cpos,
                                  uint32_t n, uint32_t K, uint32_t NB, const uint32_t* lane_src, const uint32_t* blist,
                                  uint32_t nb, uint32_t* src, double* dang, double* scale, uint32_t* qdone,
-                                 hipStream_t s) {
+                                 double* rhist, hipStream_t s) {
   if (!nb) return hipSuccess;
   const dim3 grid(nblocks((size_t)n * kQ), nb);
   if (f64)
@@ -677,7 +689,8 @@ hipError_t launch_mppr_lane_init(bool f64, void* x, void* c0, void* c1, const ui
   else
     mppr_lane_init_kernel<float><<<grid, kWG, 0, s>>>(static_cast<float*>(x), static_cast<float*>(c0),
                                                       static_cast<float*>(c1), out_deg, cpos, n, K, lane_src, blist);
-  mppr_lane_scalars_kernel<<<nblocks((size_t)NB * kQ), kWG, 0, s>>>(lane_src, out_deg, NB, src, dang, scale, qdone);
+  mppr_lane_scalars_kernel<<<nblocks((size_t)NB * kQ), kWG, 0, s>>>(lane_src, out_deg, NB, src, dang, scale, qdone,
+                                                                     rhist);
   return hipGetLastError();
 }
 

@@ -236,6 +236,7 @@ dg_status ensure_workspace(dg_graph* g, uint32_t S, hipStream_t s) {
   }
   if (g->ws_sweeps < S) {
     dev_free(g, g->resid);
+    dev_free(g, g->scale);
     dev_free(g, g->dang);
     dev_free(g, g->count);
     dev_free(g, g->changed);
@@ -244,10 +245,11 @@ dg_status ensure_workspace(dg_graph* g, uint32_t S, hipStream_t s) {
     g->host_poll_dev = nullptr;
     const size_t k = (size_t)S + 1;
     g->resid = static_cast<double*>(dev_alloc(g, k * sizeof(double), s));
+    g->scale = static_cast<double*>(dev_alloc(g, k * sizeof(double), s));
     g->dang = static_cast<double*>(dev_alloc(g, k * sizeof(double), s));
     g->count = static_cast<uint32_t*>(dev_alloc(g, k * sizeof(uint32_t), s));
     g->changed = static_cast<uint32_t*>(dev_alloc(g, k * sizeof(uint32_t), s));
-    if (!g->resid || !g->dang || !g->count || !g->changed) {
+    if (!g->resid || !g->scale || !g->dang || !g->count || !g->changed) {
       g->ws_sweeps = 0;
       return fail(DG_ERR_OUT_OF_MEMORY, "sweep state allocation failed");
     }
@@ -296,11 +298,13 @@ void fill_shape(const dg_graph* g, bool delayed, uint32_t d_eff, uint32_t cap, b
   st->commit_interval = st->commits ? (uint32_t)(((uint64_t)g->n + st->commits / 2) / st->commits) : 0u;
 }
 
-// err_bound of dg_pagerank: ||T(y) - y||_1 / (1 - damping) for the float64
-// scores y (device, vertex order), by one synchronous float64 sweep in the
+// err_bound of dg_pagerank / dg_ppr: ||T(y) - y||_1 / (1 - damping) for the
+// float64 scores y (device, vertex order, sum 1) and the map T of global
+// PageRank (psrc = kInf) or of personalised PageRank with restart vertex
+// psrc, by one synchronous float64 sweep in the
 // graph's workspace (its three value arrays; y may be one of them, and is
 // read before any is written).  Synchronises the stream.
-dg_status certify(dg_graph* g, const double* y, double damping, const SweepState& sst, hipStream_t s,
+dg_status certify(dg_graph* g, const double* y, double damping, uint32_t psrc, const SweepState& sst, hipStream_t s,
                   double& bound) {
   double* x = static_cast<double*>(g->vals[0]);
   double* c0 = static_cast<double*>(y == g->vals[1] ? g->vals[2] : g->vals[1]);
@@ -319,6 +323,7 @@ dg_status certify(dg_graph* g, const double* y, double damping, const SweepState
   a.tol = 0.0;
   a.k = 0;
   a.res = resident(g, sizeof(double));
+  a.psrc = psrc;
   DG_HIP(launch_pr_sweep(kSync, true, a, s));
   double r = 0.0;
   DG_HIP(hipMemcpyAsync(&r, sst.resid + 1, sizeof r, hipMemcpyDeviceToHost, s));
@@ -766,6 +771,27 @@ dg_status dg_access_matrix(dg_graph* g, uint32_t groups, uint64_t* out_counts, d
 dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uint32_t d, dg_dtype dtype,
                       uint32_t max_sweeps, double* out_scores, int out_on_device, dg_stats* stats,
                       void* hip_stream) {
+  return dg::host::pr_run(g, kInf, damping, tol, mode, d, dtype, max_sweeps, out_scores, out_on_device, stats,
+                          hip_stream);
+}
+
+dg_status dg_ppr(dg_graph* g, uint32_t src, double damping, double tol, dg_mode mode, uint32_t d, dg_dtype dtype,
+                 uint32_t max_sweeps, double* out_scores, int out_on_device, dg_stats* stats, void* hip_stream) {
+  g_last_error.clear();
+  if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (g->G) return fail(DG_ERR_UNSUPPORTED, "personalised PageRank is not supported on the union graph of a set");
+  if (src >= g->n) return fail(DG_ERR_INVALID_ARGUMENT, "restart vertex %u >= n = %u", src, g->n);
+  return dg::host::pr_run(g, src, damping, tol, mode, d, dtype, max_sweeps, out_scores, out_on_device, stats,
+                          hip_stream);
+}
+
+}  // extern "C"
+
+namespace dg {
+namespace host {
+
+dg_status pr_run(dg_graph* g, uint32_t psrc, double damping, double tol, dg_mode mode, uint32_t d, dg_dtype dtype,
+                 uint32_t max_sweeps, double* out_scores, int out_on_device, dg_stats* stats, void* hip_stream) {
   g_last_error.clear();
   if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
   if (!(damping >= 0.0 && damping < 1.0)) return fail(DG_ERR_INVALID_ARGUMENT, "damping must be in [0, 1)");
@@ -793,9 +819,17 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
   void* x = g->vals[0];
   void* c0 = g->vals[1];
   void* c1 = mode == DG_SYNC ? g->vals[2] : nullptr;
-  const double d0 = (double)g->n_dangling / (double)g->n;
   SweepState sst = state(g);
-  DG_HIP(launch_pr_init(f64, x, c0, c1, g->out_deg, g->cpos, g->n, sst, max_sweeps, d0, s));
+  double d0 = (double)g->n_dangling / (double)g->n;  // dangling mass of x = 1/n
+  if (psrc != kInf) {
+    // dangling mass of the one-hot start: 1 if the restart vertex is dangling
+    uint32_t deg = 0;
+    DG_HIP(hipMemcpyAsync(&deg, g->out_deg + psrc, sizeof deg, hipMemcpyDeviceToHost, s));
+    DG_HIP(hipStreamSynchronize(s));
+    d0 = deg ? 0.0 : 1.0;
+    sst.scale = g->scale;
+  }
+  DG_HIP(launch_pr_init(f64, x, c0, c1, g->out_deg, g->cpos, g->n, sst, max_sweeps, d0, psrc, s));
   if (mode == DG_DELAYED_LOCAL) DG_HIP(launch_by_vertex(f64, c0, g->cpos, g->n, g->vals[2], s));
 
   PrArgs a;
@@ -814,6 +848,7 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
   a.gsweeps = g->gsweeps;
   a.voff = g->segv_d;
   a.gdang = g->gdang;
+  a.psrc = psrc;
   if (g->G) {
     DG_HIP(launch_fill_u32(g->gsweeps, g->G, 0u, s));
     DG_HIP(hipMemcpyAsync(g->gdang, g->gdang0.data(), (size_t)g->G * sizeof(double), hipMemcpyHostToDevice, s));
@@ -841,6 +876,7 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
   if ((st = drive(g, max_sweeps, s, sizeof(double), poll, launch, done, sweeps, secs, conv)) != DG_OK)
     return st;
   std::memcpy(&resid, poll + (size_t)sweeps * sizeof(double), sizeof(double));
+  resid = std::fabs(resid);  // negative: a float32 personalised sweep stopped at its rounding floor
 
   double* dst = out_on_device ? out_scores : static_cast<double*>(g->vals[1]);
   if (!out_on_device && mode != DG_SYNC) dst = static_cast<double*>(g->vals[2]);
@@ -848,7 +884,7 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
   if (!out_on_device) DG_HIP(hipMemcpyAsync(out_scores, dst, (size_t)g->n * 8, hipMemcpyDeviceToHost, s));
   double bound = 0.0;
   if (stats && (stats->request & DG_STATS_ERR_BOUND)) {
-    if ((st = certify(g, dst, damping, sst, s, bound)) != DG_OK) return st;
+    if ((st = certify(g, dst, damping, psrc, sst, s, bound)) != DG_OK) return st;
   }
   DG_HIP(hipStreamSynchronize(s));
   if (stats) {
@@ -862,6 +898,11 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
   if (!conv) return fail(DG_ERR_NOT_CONVERGED, "no convergence within %u sweeps (last change %g)", max_sweeps, resid);
   return DG_OK;
 }
+
+}  // namespace host
+}  // namespace dg
+
+extern "C" {
 
 dg_status dg_sssp(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t max_sweeps, uint32_t* out_dist,
                   int out_on_device, dg_stats* stats, void* hip_stream) {
@@ -1118,13 +1159,14 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   uint32_t* count = static_cast<uint32_t*>(al.get(((size_t)max_sweeps + 1) * NB * 4, s));
   double* dang = static_cast<double*>(al.get((size_t)2 * NB * kBatchQ * 8, s));
   double* scale = static_cast<double*>(al.get((size_t)2 * NB * kBatchQ * 8, s));
+  double* rhist = f64 ? nullptr : static_cast<double*>(al.get((size_t)2 * NB * kBatchQ * 8, s));
   uint32_t* qdone = static_cast<uint32_t*>(al.get((size_t)NB * kBatchQ * 4, s));
   double* part = static_cast<double*>(al.get((size_t)g->Pb * NB * 3 * kBatchQ * 8, s));
   double* qsum = static_cast<double*>(al.get((size_t)NB * kBatchQ * 8, s));
   double* qpart = static_cast<double*>(al.get((size_t)NB * 256 * kBatchQ * 8, s));
   double* outd = out_on_device ? out_scores : static_cast<double*>(al.get((size_t)k * g->n * 8, s));
   if (!srcd || !x || !c0 || (mode == DG_SYNC && !c1) || (need_sh && !sh) || !resid || !count || !dang ||
-      !scale || !qdone || !part || !qsum || !qpart || !outd)
+      !scale || (!f64 && !rhist) || !qdone || !part || !qsum || !qpart || !outd)
     return fail(DG_ERR_OUT_OF_MEMORY, "batched PageRank workspace allocation failed");
   PinnedBuf poll;
   DG_HIP(alloc_mapped(&poll.p, &poll.dev, ((size_t)max_sweeps + 1) * NB * 8));
@@ -1134,6 +1176,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   DG_HIP(launch_fill_u32(count, ((size_t)max_sweeps + 1) * NB, 0u, s));
   DG_HIP(launch_fill_f64(dang, (size_t)2 * NB * kBatchQ, 0.0, s));
   DG_HIP(launch_fill_f64(scale, (size_t)2 * NB * kBatchQ, 1.0, s));
+  if (rhist) DG_HIP(launch_fill_f64(rhist, (size_t)2 * NB * kBatchQ, __builtin_inf(), s));
   // padding lanes of the last batch start frozen
   DG_HIP(launch_fill_u32(qdone, (size_t)k, 0u, s));
   if ((size_t)NB * kBatchQ > k) DG_HIP(launch_fill_u32(qdone + k, (size_t)NB * kBatchQ - k, 1u, s));
@@ -1148,6 +1191,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   a.hresid = static_cast<double*>(poll.dev);
   a.dang = dang;
   a.scale = scale;
+  a.rhist = rhist;
   a.qdone = qdone;
   a.count = count;
   a.part = part;

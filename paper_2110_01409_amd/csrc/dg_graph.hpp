@@ -93,6 +93,7 @@ struct dg_graph {
   double* norm = nullptr;                        // kNormBlocks + 1
   uint32_t ws_sweeps = 0;
   double *resid = nullptr, *dang = nullptr, *part = nullptr;
+  double* scale = nullptr;  // [S+1] storage scales of personalised PageRank sweeps
   uint32_t *count = nullptr, *changed = nullptr;
   void* host_poll = nullptr;      // mapped pinned [S+1] doubles: the sweeps' stopping values
   void* host_poll_dev = nullptr;  // its device address
@@ -126,6 +127,10 @@ void staging(const dg_graph* g, uint32_t d, size_t elem, uint32_t res, uint32_t&
              bool& shadow);
 // Commits per sweep of a delayed single-query sweep with that staging.
 uint32_t commits_per_sweep(const dg_graph* g, uint32_t d, uint32_t cap, bool shadow);
+// PageRank (psrc = 0xFFFFFFFF, as dg_pagerank) or personalised PageRank with
+// restart vertex psrc (as dg_ppr).
+dg_status pr_run(dg_graph* g, uint32_t psrc, double damping, double tol, dg_mode mode, uint32_t d, dg_dtype dtype,
+                 uint32_t max_sweeps, double* out_scores, int out_on_device, dg_stats* stats, void* hip_stream);
 // Bellman-Ford from src and, when n_more > 0, also from the n_more sources in
 // the device array more_src (distance to the nearest source); otherwise as
 // dg_sssp.

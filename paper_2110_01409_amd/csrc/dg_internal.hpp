@@ -92,6 +92,9 @@ struct SweepState {
   uint32_t* count;    // [S+1] workers finished in sweep k
   uint32_t* changed;  // [S+1] changed[k+1] != 0 iff sweep k decreased a distance
   double* part;       // [3P] per-worker partial sums (residual, non-dangling mass, total mass)
+  // Personalised PageRank only (PrArgs::psrc set): scale[k] is the storage
+  // scale of sweep k's values (stored = true value * scale[k]); null otherwise.
+  double* scale = nullptr;
   // Mapped host mirrors of resid and changed (device addresses of pinned
   // host memory the host polls; same row indices), or null.
   double* hresid = nullptr;
@@ -133,6 +136,12 @@ struct PrArgs {
   // refreshes one segment of it after every tile, a delayed sweep after
   // every tile that ends with a commit.
   uint32_t res;
+  // Personalised PageRank with restart vertex psrc (kInf: global PageRank).
+  // Teleport and dangling mass go to psrc; st.dang[k] is the dangling mass
+  // (true scale) of the previous iterate, and values are stored scaled by
+  // st.scale[k], which the sweep's last worker multiplies by the iterate's
+  // mass (a rescale to mass 1 without a pass over memory).  Not for sets.
+  uint32_t psrc = 0xFFFFFFFFu;
 };
 
 struct BfArgs {
@@ -153,6 +162,15 @@ struct BfArgs {
   uint32_t G;
   uint32_t* gsweeps;
 };
+
+// Float32 personalised PageRank stops at its rounding floor: a query whose
+// L1 change is below kStallTols x tol and no smaller than kStallRatio times
+// its change two sweeps earlier stops as if it had met tol.  In exact
+// arithmetic the change of a synchronous sweep contracts by at least
+// damping^2 over two sweeps, so a change that stops shrinking is rounding
+// noise (a float32 vector can settle into a period-2 cycle above tol).
+constexpr double kStallTols = 2.0;
+constexpr double kStallRatio = 0.9;
 
 // Batched queries: rows a wavefront stages in registers in delayed mode, and
 // the largest commit interval staged that way (four wavefronts per
@@ -184,6 +202,8 @@ struct MpprArgs {
   double* dang;         // [2][NB][64] dangling mass (true scale) returned to the restart vertex, by sweep parity
   double* scale;        // [2][NB][64] storage scale of each query's values, by sweep parity
   uint32_t* qdone;      // [NB][64] 0 while a query runs, else the sweep count that stopped it
+  double* rhist;        // [2][NB][64] float32 only: each query's change of sweep k-2 (slot k & 1), for
+                        // the stall rule; null = no stall rule
   const uint32_t* bactive;  // serving: [NB] nonzero for batches with running queries (count is then a
                             // [2][NB] ring and resid is unused), else null
   uint32_t* count;      // [(S+1)][NB] workers finished
@@ -209,8 +229,11 @@ hipError_t launch_mppr_out(bool f64, const void* x, double* qpart, double* qsum,
                            double* out, hipStream_t s);
 
 // Launchers (enqueue only; return the launch status).
+// x = 1/n (psrc = kInf) or the one-hot vector of psrc; c = x / outdeg in
+// slot order (both buffers when c1 is set); state rows 0..S: resid[0] = inf,
+// dang[0] = d0, scale = 1 (when st.scale is set), counters 0.
 hipError_t launch_pr_init(bool f64, void* x, void* c0, void* c1, const uint32_t* out_deg, const uint32_t* cpos,
-                          uint32_t n, SweepState st, uint32_t S, double d0, hipStream_t s);
+                          uint32_t n, SweepState st, uint32_t S, double d0, uint32_t psrc, hipStream_t s);
 hipError_t launch_pr_sweep(int mode, bool f64, const PrArgs& a, hipStream_t s);
 hipError_t launch_bf_init(uint32_t* d0, uint32_t* d1, const uint32_t* cpos, uint32_t n, uint32_t src,
                           SweepState st, uint32_t S, hipStream_t s);
@@ -251,7 +274,7 @@ hipError_t launch_mbf_lane_init(uint32_t* d0, uint32_t* d1, const uint32_t* cpos
 hipError_t launch_mppr_lane_init(bool f64, void* x, void* c0, void* c1, const uint32_t* out_deg, const uint32_t* cpos,
                                  uint32_t n, uint32_t K, uint32_t NB, const uint32_t* lane_src, const uint32_t* blist,
                                  uint32_t nb, uint32_t* src, double* dang, double* scale, uint32_t* qdone,
-                                 hipStream_t s);
+                                 double* rhist, hipStream_t s);
 hipError_t launch_mbf_lane_out(const uint32_t* d, const uint32_t* cpos, uint32_t n, uint32_t K, uint32_t b, uint32_t q,
                                uint32_t* out, hipStream_t s);
 // qpart: [256] float64 scratch

@@ -46,6 +46,7 @@ struct Pool {
   void *x = nullptr, *c0 = nullptr, *c1 = nullptr, *psh = nullptr;
   uint32_t *src = nullptr, *qdone = nullptr, *count = nullptr;
   double *dang = nullptr, *scale = nullptr, *part = nullptr;
+  double* rhist = nullptr;  // float32 storage: [2][NB][64] changes two sweeps back (stall rule)
   // both kinds
   uint32_t *bactive = nullptr, *lane_src = nullptr, *blist = nullptr;
   uint32_t* flags_h = nullptr;  // pinned [NB * 64] readback
@@ -98,13 +99,14 @@ size_t batch_bytes(const dg_server* s, const dg_graph* g, int kind) {
   if (kind == DG_QUERY_SSSP)
     return (slots * (sync ? 2 : 1) + (sssp_shadow(s, g) ? n : 0)) * kLanes * 4 + kLanes * 8 + 16;
   const size_t e = f64(s) ? 8 : 4;
-  return (n + slots * (sync ? 2 : 1) + (del ? n : 0)) * kLanes * e + kLanes * (4 + 4 + 4 * 8 + 4) +
+  return (n + slots * (sync ? 2 : 1) + (del ? n : 0)) * kLanes * e + kLanes * (4 + 4 + 6 * 8 + 4) +
          (size_t)g->Pb * 3 * kLanes * 8 + 16;
 }
 
 void free_pool(Pool& p) {
   for (void* q : {(void*)p.b0, (void*)p.b1, (void*)p.sh, (void*)p.lchg, p.x, p.c0, p.c1, p.psh, (void*)p.src,
-                  (void*)p.qdone, (void*)p.count, (void*)p.dang, (void*)p.scale, (void*)p.part, (void*)p.bactive,
+                  (void*)p.qdone, (void*)p.count, (void*)p.dang, (void*)p.scale, (void*)p.rhist, (void*)p.part,
+                  (void*)p.bactive,
                   (void*)p.lane_src, (void*)p.blist})
     dev_free(p.g, q);
   if (p.flags_h) (void)hipHostFree(p.flags_h);
@@ -183,6 +185,7 @@ dg_status resize(dg_server* s, Pool& p, uint32_t NBn) {
     if ((st = reshape(p, p.qdone, kLanes * 4, NBn, true)) != DG_OK) return st;
     if ((st = reshape_ring(p, p.dang, kLanes * 8, NBn)) != DG_OK) return st;
     if ((st = reshape_ring(p, p.scale, kLanes * 8, NBn)) != DG_OK) return st;
+    if (!f64(s) && (st = reshape_ring(p, p.rhist, kLanes * 8, NBn)) != DG_OK) return st;
     if ((st = reshape_ring(p, p.count, 4, NBn)) != DG_OK) return st;
     if ((st = reshape(p, p.part, (size_t)g->Pb * 3 * kLanes * 8, NBn, false)) != DG_OK) return st;
     // new batches: lanes frozen and unassigned
@@ -193,6 +196,10 @@ dg_status resize(dg_server* s, Pool& p, uint32_t NBn) {
       DG_HIP(launch_fill_f64(p.scale + (size_t)(NBn + b) * kLanes, kLanes, 1.0, p.st));
       DG_HIP(launch_fill_f64(p.dang + (size_t)b * kLanes, kLanes, 0.0, p.st));
       DG_HIP(launch_fill_f64(p.dang + (size_t)(NBn + b) * kLanes, kLanes, 0.0, p.st));
+      if (p.rhist) {
+        DG_HIP(launch_fill_f64(p.rhist + (size_t)b * kLanes, kLanes, __builtin_inf(), p.st));
+        DG_HIP(launch_fill_f64(p.rhist + (size_t)(NBn + b) * kLanes, kLanes, __builtin_inf(), p.st));
+      }
     }
   }
   if ((st = reshape(p, p.bactive, 4, NBn, false)) != DG_OK) return st;
@@ -275,7 +282,7 @@ dg_status pool_sweep(dg_server* s, Pool& p, bool& ran) {
       DG_HIP(launch_mbf_lane_init(p.b0, p.b1, g->cpos, g->n, g->K, p.lane_src, p.blist, (uint32_t)blist.size(), q));
     else
       DG_HIP(launch_mppr_lane_init(f64(s), p.x, p.c0, p.c1, g->out_deg, g->cpos, g->n, g->K, p.NB, p.lane_src,
-                                   p.blist, (uint32_t)blist.size(), p.src, p.dang, p.scale, p.qdone, q));
+                                   p.blist, (uint32_t)blist.size(), p.src, p.dang, p.scale, p.qdone, p.rhist, q));
   }
   DG_HIP(hipMemcpyAsync(p.bactive, active.data(), active.size() * 4, hipMemcpyHostToDevice, q));
   const bool sync = s->o.mode == DG_SYNC;
@@ -307,6 +314,7 @@ dg_status pool_sweep(dg_server* s, Pool& p, bool& ran) {
     a.dang = p.dang;
     a.scale = p.scale;
     a.qdone = p.qdone;
+    a.rhist = p.rhist;
     a.count = p.count;
     a.part = p.part;
     a.bactive = p.bactive;

@@ -283,6 +283,18 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
     const uint32_t gi = a.wgraph[w];
     base = (1.0 - alpha) * inv_n + alpha * a.gdang[(k & 1u) * a.G + gi] / (double)(a.voff[gi + 1] - a.voff[gi]);
   }
+  // Personalised PageRank: no uniform term; the restart vertex gets the
+  // teleport and the dangling mass; values are stored at scale S.  For
+  // global PageRank S = 1 and the extra term never applies, so the update
+  // below is exactly the global one.
+  const uint32_t psrc = a.psrc;
+  double S = 1.0, extra = 0.0;
+  if (psrc != kInf) {
+    S = a.st.scale[k];
+    extra = (1.0 - alpha) + alpha * a.st.dang[k];
+    base = 0.0;
+  }
+  const double invS = 1.0 / S;
   const T* cin = static_cast<const T*>(a.cin);
   T* cout = static_cast<T*>(a.cout);
   T* x = static_cast<T*>(a.x);
@@ -435,12 +447,12 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
     if (refresh) rt.issue(rc, tid);
     if (tid < nv) {
       const uint32_t v = v0 + tid;
-      const double xn = base + alpha * s_acc[tid];
-      x[v] = static_cast<T>(xn);
-      const T cn = dg ? static_cast<T>(xn / (double)dg) : static_cast<T>(0);
+      const double xn = base + alpha * s_acc[tid] * invS + (v == psrc ? extra : 0.0);
+      x[v] = static_cast<T>(xn * S);
+      const T cn = dg ? static_cast<T>(xn * S / (double)dg) : static_cast<T>(0);
       // Change of the score: new value before rounding to storage minus the
       // stored old value (in float64 both are the same value).
-      r_loc += fabs(xn - (double)xo);
+      r_loc += fabs(xn - (double)xo * invS);
       if (dg != 0) nd_loc += xn;
       m_loc += xn;
       if constexpr (M == kSync) {
@@ -511,9 +523,11 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
     auto part = [&](uint32_t i) {
       return __hip_atomic_load(a.st.part + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
-    double r = 0.0, dd = 0.0;
+    double r = 0.0, dd = 0.0, mm = 0.0;
     if (!a.wseg) {
       for (uint32_t i = tid; i < P; i += kSweepWG) r += part(i);
+      if (psrc != kInf)
+        for (uint32_t i = tid; i < P; i += kSweepWG) mm += part(2 * P + i);
     } else {
       // Graph sets: each graph's change relative to its own mass (its L1
       // change once normalised); the sweep's value is the largest of them.
@@ -553,21 +567,38 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
       }
     }
     dd = wave_sum(dd);
+    mm = wave_sum(mm);
     if (lane == 0) {
       s_red[wv] = r;
       s_red[NW + wv] = dd;
+      s_red[2 * NW + wv] = mm;
     }
     __syncthreads();
     if (tid == 0) {
-      double r_all = 0.0, r_max = 0.0, d_all = 0.0;
+      double r_all = 0.0, r_max = 0.0, d_all = 0.0, m_all = 0.0;
       for (uint32_t i = 0; i < NW; ++i) {
         r_all += s_red[i];
         r_max = fmax(r_max, s_red[i]);
         d_all += s_red[NW + i];
+        m_all += s_red[2 * NW + i];
       }
-      const double r_k = !a.wseg ? r_all : r_max;
+      double r_k = !a.wseg ? r_all : r_max;
+      // Float32 personalised PageRank: a change below kStallTols x tol that
+      // no longer shrinks over two sweeps is the rounding floor; it is
+      // recorded negated, which stops the call like a change below tol.
+      if constexpr (sizeof(T) == 4) {
+        if (psrc != kInf && r_k >= a.tol && r_k < kStallTols * a.tol && r_k > kStallRatio * a.st.resid[k - 1 + (k == 0)])
+          r_k = -r_k;
+      }
       a.st.resid[k + 1] = r_k;
-      a.st.dang[k + 1] = 1.0 - d_all;
+      if (psrc == kInf) {
+        a.st.dang[k + 1] = 1.0 - d_all;
+      } else {
+        // the dangling mass itself (not the deficit), then the rescale to
+        // mass 1: the new iterate's true values are its stored ones / (S m)
+        a.st.dang[k + 1] = (m_all - d_all) / m_all;
+        a.st.scale[k + 1] = S * m_all;
+      }
       if (a.st.hresid) st_host(a.st.hresid + k + 1, r_k);
     }
   }
@@ -576,9 +607,9 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
 template <typename T>
 __global__ __launch_bounds__(kWG) void pr_init_kernel(T* x, T* c0, T* c1, const uint32_t* out_deg,
                                                       const uint32_t* cpos, uint32_t n, SweepState st, uint32_t S,
-                                                      double d0) {
+                                                      double d0, uint32_t psrc) {
   const uint32_t i = blockIdx.x * kWG + threadIdx.x;
-  const double x0 = 1.0 / (double)n;
+  const double x0 = psrc == kInf ? 1.0 / (double)n : (i == psrc ? 1.0 : 0.0);
   if (i < n) {
     const uint32_t dg = out_deg[i];
     const T c = dg ? static_cast<T>(x0 / (double)dg) : static_cast<T>(0);
@@ -592,6 +623,7 @@ __global__ __launch_bounds__(kWG) void pr_init_kernel(T* x, T* c0, T* c1, const 
     st.dang[i] = (i == 0) ? d0 : 0.0;
     st.count[i] = 0;
     st.changed[i] = (i == 0) ? 1u : 0u;
+    if (st.scale) st.scale[i] = 1.0;
   }
 }
 
@@ -902,6 +934,7 @@ __global__ void bound_state_kernel(SweepState st, const double* dang) {
     st.dang[0] = *dang;
     st.count[0] = 0;
     st.count[1] = 0;
+    if (st.scale) st.scale[0] = 1.0;
   }
 }
 
@@ -923,14 +956,14 @@ size_t pr_dyn_lds(const PrArgs& a) {
 }  // namespace
 
 hipError_t launch_pr_init(bool f64, void* x, void* c0, void* c1, const uint32_t* out_deg, const uint32_t* cpos,
-                          uint32_t n, SweepState st, uint32_t S, double d0, hipStream_t s) {
+                          uint32_t n, SweepState st, uint32_t S, double d0, uint32_t psrc, hipStream_t s) {
   const uint32_t nb = blocks_for((uint64_t)(n > S + 1 ? n : S + 1));
   if (f64) {
     pr_init_kernel<double><<<nb, kWG, 0, s>>>(static_cast<double*>(x), static_cast<double*>(c0),
-                                              static_cast<double*>(c1), out_deg, cpos, n, st, S, d0);
+                                              static_cast<double*>(c1), out_deg, cpos, n, st, S, d0, psrc);
   } else {
     pr_init_kernel<float><<<nb, kWG, 0, s>>>(static_cast<float*>(x), static_cast<float*>(c0),
-                                             static_cast<float*>(c1), out_deg, cpos, n, st, S, d0);
+                                             static_cast<float*>(c1), out_deg, cpos, n, st, S, d0, psrc);
   }
   return hipGetLastError();
 }

@@ -31,7 +31,7 @@ MODES = {"sync": DG_SYNC, "async": DG_ASYNC, "delayed": DG_DELAYED, "delayed_loc
 DTYPES = {"f32": DG_F32, "f64": DG_F64}
 
 # Every symbol declared in include/dg.h.
-EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_info_get", "dg_pagerank",
+EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_info_get", "dg_pagerank", "dg_ppr",
            "dg_sssp", "dg_sssp_batch", "dg_ppr_batch", "dg_set_create", "dg_set_destroy", "dg_set_info_get",
            "dg_set_pagerank", "dg_set_sssp", "dg_graph_partition", "dg_access_matrix", "dg_graph_repartition",
            "dg_tune", "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_server_create",
@@ -160,6 +160,8 @@ def _load():
         "dg_graph_info_get": (C.c_int, [P, C.POINTER(dg_graph_info)]),
         "dg_pagerank": (C.c_int, [P, C.c_double, C.c_double, C.c_int, C.c_uint32, C.c_int, C.c_uint32, P, C.c_int,
                                   C.POINTER(dg_stats), P]),
+        "dg_ppr": (C.c_int, [P, C.c_uint32, C.c_double, C.c_double, C.c_int, C.c_uint32, C.c_int, C.c_uint32, P,
+                             C.c_int, C.POINTER(dg_stats), P]),
         "dg_sssp": (C.c_int, [P, C.c_uint32, C.c_int, C.c_uint32, C.c_uint32, P, C.c_int, C.POINTER(dg_stats), P]),
         "dg_sssp_noalloc": (C.c_int, [P, C.c_uint32, C.c_int, C.c_uint32, C.c_uint32, P, C.c_int,
                                       C.POINTER(dg_stats), P]),
@@ -249,6 +251,10 @@ def dg_graph_info_get(g, info):
 
 def dg_pagerank(g, damping, tol, mode, d, dtype, max_sweeps, out, out_on_device, stats, stream):
     return lib.dg_pagerank(g, damping, tol, mode, d, dtype, max_sweeps, out, out_on_device, stats, stream)
+
+
+def dg_ppr(g, src, damping, tol, mode, d, dtype, max_sweeps, out, out_on_device, stats, stream):
+    return lib.dg_ppr(g, src, damping, tol, mode, d, dtype, max_sweeps, out, out_on_device, stats, stream)
 
 
 def dg_sssp(g, src, mode, d, max_sweeps, out, out_on_device, stats, stream):
@@ -531,6 +537,20 @@ class Graph:
         s = _check(dg_pagerank(self._h, float(damping), float(tol), MODES[mode], int(d), DTYPES[dtype],
                                int(max_sweeps), C.c_void_p(out.data_ptr()), 1, C.byref(st),
                                _stream_handle(stream)),
+                   allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
+        return out, _stats(st, s == DG_OK)
+
+    def ppr(self, src, damping=0.85, tol=1e-6, mode="delayed", d=64, dtype="f32", max_sweeps=10_000, out=None,
+            stream=None, allow_not_converged=False, err_bound=False):
+        """Personalised PageRank of restart vertex src (dg_ppr): float64
+        scores on the device, Stats."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        st = dg_stats()
+        st.request = DG_STATS_ERR_BOUND if err_bound else 0
+        s = _check(dg_ppr(self._h, int(src), float(damping), float(tol), MODES[mode], int(d), DTYPES[dtype],
+                          int(max_sweeps), C.c_void_p(out.data_ptr()), 1, C.byref(st), _stream_handle(stream)),
                    allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
         return out, _stats(st, s == DG_OK)
 

@@ -8,10 +8,9 @@ compact hot region):
 * the diagonal-banded graph, 16,777,216 vertices, 16 out-edges within
   +-4096 plus 1% long-range (seed 24).
 
-PageRank on R-MAT 22 is compared with the oracle's float64 fixed point
-(Jacobi to an L1 change below 1e-12) directly: L1 <= 1e-6 in every mode and
-precision.  On the banded graph the oracle's error certificate
-||T(x) - x||_1 / (1 - alpha), an upper bound on ||x - x*||_1, must be <= 1e-6.
+PageRank is compared with the oracle's float64 fixed point (Jacobi to an L1
+change below 1e-12; the C oracle for the banded graph) directly: L1 <= 1e-6
+in every mode, d and precision.
 
 SSSP results are checked with the oracle's O(m) optimality certificate, which
 holds exactly when the distances are the true shortest paths (a bit-exact
@@ -48,7 +47,8 @@ def rmat22():
 
 @pytest.fixture(scope="module")
 def rmat22_xstar(rmat22):
-    x = opr.pagerank_fixed_point(rmat22, tol=1e-12)
+    from oracle import cpr
+    x = cpr.pagerank_fixed_point(rmat22, tol=1e-12)
     print("rmat22 fixed point ready", flush=True)
     return x
 
@@ -90,20 +90,60 @@ def test_rmat22_sssp_all_modes(dg, rmat22):
     G.close()
 
 
-def test_banded16m_pagerank_and_sssp(dg):
+@pytest.fixture(scope="module")
+def banded16m():
     g = gg.banded(1 << 24, 16, 4096, 0.01, seed=24)
     print(f"banded n={g.n} m={g.m}", flush=True)
+    return g
+
+
+@pytest.fixture(scope="module")
+def banded16m_xstar(banded16m):
+    from oracle import cpr
+    x = cpr.pagerank_fixed_point(banded16m, tol=1e-12)
+    print("banded fixed point ready", flush=True)
+    return x
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_banded16m_pagerank_all_modes(dg, banded16m, banded16m_xstar, dtype):
+    """The diagonal-clustered graph where delay should not help (section
+    IV-C), against the oracle's fixed point (the C oracle's Jacobi to 1e-12,
+    the numpy oracle's iterates computed in parallel): L1 <= 1e-6 in every
+    mode and d, in both precisions."""
+    g = banded16m
+    xs = banded16m_xstar
     G = dg.Graph.from_csr(g)
-    for mode, d in [("sync", 1), ("delayed", 64), ("async", 1)]:
-        x, st = G.pagerank(tol=1e-7, mode=mode, d=d, dtype="f32", max_sweeps=1000)
-        cert = opr.certificate(g, x.cpu().numpy())
-        print(f"banded f32 {mode} d={d}: sweeps={st.sweeps} certificate bound {cert:.2e}", flush=True)
-        assert cert <= 1e-6
-    src = int(gg.pick_sources(g, 1, seed=24)[0])
-    for mode, d in [("delayed", 1024), ("sync", 1)]:
+    for mode, d in MODES:
+        x, st = G.pagerank(tol=PR_TOL[dtype], mode=mode, d=d, dtype=dtype, max_sweeps=1000)
+        err = float(np.abs(x.cpu().numpy() - xs).sum())
+        print(f"banded {dtype} {mode} d={d}: sweeps={st.sweeps} L1 err={err:.2e} t={st.seconds*1e3:.2f} ms",
+              flush=True)
+        assert err <= 1e-6, (dtype, mode, d, err)
+    G.close()
+
+
+def test_banded16m_sssp_all_modes(dg, banded16m):
+    """One source against scipy's Dijkstra bit for bit in every mode and d;
+    two more by the oracle's optimality certificate."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import dijkstra as sp_dijkstra
+    g = banded16m
+    srcs = gg.pick_sources(g, 3, seed=24).tolist()
+    mat = csr_matrix((g.w.astype(np.float64), g.idx.astype(np.int64), g.ptr.astype(np.int64)), shape=(g.n, g.n))
+    ref = sp_dijkstra(mat, directed=True, indices=srcs[0])
+    del mat
+    ref = np.where(np.isinf(ref), osp.INF32, ref).astype(np.uint32)
+    print("banded Dijkstra ready", flush=True)
+    G = dg.Graph.from_csr(g)
+    for mode, d in MODES:
+        dist, st = G.sssp(srcs[0], mode=mode, d=d)
+        print(f"banded sssp {mode} d={d}: sweeps={st.sweeps}", flush=True)
+        np.testing.assert_array_equal(dist.cpu().numpy(), ref, err_msg=f"{mode} d={d}")
+    for src, (mode, d) in zip(srcs[1:], [("async", 1), ("delayed", 0xFFFFFFFF)]):
         dist, st = G.sssp(src, mode=mode, d=d)
         ok, msg = osp.certificate(g, src, dist.cpu().numpy())
-        print(f"banded sssp {mode} d={d}: sweeps={st.sweeps} certificate {msg}", flush=True)
+        print(f"banded sssp src={src} {mode} d={d}: sweeps={st.sweeps} certificate {msg}", flush=True)
         assert ok, msg
     G.close()
 

@@ -3,10 +3,10 @@ boundaries over resident graphs.
 
 Every SSSP result is bit-exact against the oracle, every PPR result is
 within tolerance of the oracle's fixed point (1e-8 with float64 storage at
-tol 1e-9; the stopping rule's bound alpha/(1-alpha) * tol with float32
-storage at tol 5e-7), and in synchronous mode each
-result is bit-identical whether its request ran alone or in a mix that
-joined and left the batches around it.
+tol 1e-9; 1e-6, the workload's accuracy, with float32 storage at tol 1.5e-7).
+In synchronous mode each result is bit-identical whether its request ran
+alone or in a mix that joined and left the batches around it; in the
+asynchronous modes SSSP rows are identical and PPR rows agree within 1e-6.
 """
 import numpy as np
 import pytest
@@ -17,6 +17,7 @@ from oracle import sssp as osp
 from tests import graphs as tg
 
 pytestmark = pytest.mark.gpu
+F32_TOL = 1.5e-7
 
 
 @pytest.fixture(scope="module")
@@ -113,7 +114,7 @@ def test_server_mix_sync_f64_and_alone(dg, graphs):
 @pytest.mark.parametrize("mode,d", [("async", 1), ("delayed", 64), ("delayed", 256)])
 def test_server_mix_modes_f32(dg, graphs, mode, d):
     G = [dg.Graph.from_csr(g) for g in graphs]
-    srv = dg.Server(G, mode=mode, d=d, dtype="f32", tol=5e-7)
+    srv = dg.Server(G, mode=mode, d=d, dtype="f32", tol=F32_TOL)
     reqs = _requests(graphs, 120, seed=3)
     ids = _drive(srv, reqs, waves=4, rng=np.random.default_rng(4))
     results, infos = [], []
@@ -121,11 +122,31 @@ def test_server_mix_modes_f32(dg, graphs, mode, d):
         out, inf = srv.fetch(rid)
         results.append(out.cpu().numpy())
         infos.append(inf)
-    # Float32 storage cannot reach the tol at which the stopping rule alone
-    # bounds the error by 1e-6 (1.76e-7 < its asynchronous rounding floor),
-    # so the check is the rule's own bound: alpha/(1-alpha) * tol, plus 10%
-    # for rounding.  The float64 test above checks 1e-8.
-    _check(graphs, reqs, results, infos, ppr_bound=1.1 * 0.85 / 0.15 * 5e-7)
+    # Float32 storage at tol 1.5e-7, where the stopping rule bounds a
+    # synchronous iterate's error by alpha/(1-alpha) tol = 8.5e-7: every
+    # served PPR row within L1 1e-6 of the oracle's fixed point, the
+    # workload's accuracy.  (At tol 5e-7 a row on the slowly mixing banded
+    # graph stopped 1.1e-6 away, which that bound allows.)
+    _check(graphs, reqs, results, infos, ppr_bound=1e-6)
+    # Alone against in the mix: asynchronous and delayed rows depend on the
+    # timing of the other lanes' commits, so a PPR row alone may differ from
+    # the same request in the mix, but both are within 1e-6 of x* and of each
+    # other; SSSP rows are the same bits.
+    for i in (0, 5, 17, 64, 119):
+        alone = dg.Server(G, mode=mode, d=d, dtype="f32", tol=F32_TOL)
+        rid = alone.submit(*reqs[i])
+        got = []
+        while not got:
+            got = alone.step()
+        out, inf = alone.fetch(rid)
+        out = out.cpu().numpy()
+        if reqs[i][1] == "sssp":
+            np.testing.assert_array_equal(out, results[i], err_msg=str(reqs[i]))
+        else:
+            diff = float(np.abs(out - results[i]).sum())
+            print(f"{mode} d={d} {reqs[i]}: alone vs mix L1 {diff:.2e}", flush=True)
+            assert diff <= 1e-6, (reqs[i], diff)
+        alone.close()
     srv.close()
     for g in G:
         g.close()
