@@ -69,7 +69,7 @@ def bf_bytes_per_sweep(n, m, weight_bytes=4):
     return m * (8 + weight_bytes) + n * 12
 
 
-def oracle_worker(scale, n_sources, ref_tol=1e-10):
+def oracle_worker(scale, n_sources, ref_tol=1e-10, ppr_sources=(), ppr_tol=1e-10):
     """Runs in a process of its own (spawned before the GPU legs, so the host
     work overlaps them) on the same seeded graph:
 
@@ -81,7 +81,9 @@ def oracle_worker(scale, n_sources, ref_tol=1e-10):
       alpha/(1 - alpha) ref_tol);
     * the oracle's synchronous Bellman-Ford and scipy's Dijkstra from the
       first n_sources of the workload's sources, timed, with the distances
-      (checked equal) for bit-exact checks of the GPU runs."""
+      (checked equal) for bit-exact checks of the GPU runs;
+    * the personalised PageRank fixed points of ppr_sources (the C oracle,
+      Jacobi to ppr_tol), references for sampled batched and single rows."""
     import graphgen as gg
     from oracle import pagerank as opr
     from oracle import sssp as osp
@@ -118,6 +120,9 @@ def oracle_worker(scale, n_sources, ref_tol=1e-10):
         tdj = time.perf_counter() - t
         ref = np.where(np.isinf(ref), osp.INF32, ref).astype(np.uint32)
         out["dijkstra"].append({"source": s, "seconds": tdj, "equal_to_bf": bool(np.array_equal(ref, d))})
+    if len(ppr_sources):
+        from oracle import cpr
+        out["ppr_xstar"] = {int(s): cpr.ppr_fixed_point(g, int(s), tol=ppr_tol) for s in ppr_sources}
     return out
 
 
@@ -211,8 +216,9 @@ def serve_bench(dg, gg, G22, g22, args):
 
     buf = torch.empty(max(x.n for x in graphs), dtype=torch.float64, device="cuda")
 
-    def run(reqs, arrivals):
+    def run(reqs, arrivals, certify=False):
         srv = dg.Server(handles, mode="async", tol=1e-6, dtype="f32", hbm_budget=args.serve_budget_gib << 30)
+        bounds = []
         t0 = time.perf_counter()
         i, pend, lat, fin_t, steps = 0, {}, [], [], 0
         max_b, max_state, max_q = 0, 0, 0
@@ -233,7 +239,10 @@ def serve_bench(dg, gg, G22, g22, args):
             for rid in fin:
                 lat.append(now - pend.pop(rid))
                 fin_t.append(now)
-                srv.fetch(rid, out=buf)
+                out, inf = srv.fetch(rid, out=buf)
+                if certify and inf["kind"] == "ppr":
+                    gi = inf["graph"]
+                    bounds.append(handles[gi].error_bound(buf[:graphs[gi].n], restart=inf["source"]))
         wall = time.perf_counter() - t0
         srv.close()
         lat = np.array(lat)
@@ -241,7 +250,10 @@ def serve_bench(dg, gg, G22, g22, args):
         # excluded); with every request queued at once, over the whole run
         span = float(arrivals[-1])
         qps = (np.sum(np.array(fin_t) <= span) / span) if span > 0 else len(reqs) / wall
-        return {"requests": len(reqs), "wall_s": round(wall, 3), "achieved_qps": round(float(qps), 1),
+        cert = {} if not certify else {
+            "ppr_results_certified": len(bounds), "ppr_err_bound_max": max(bounds),
+            "ppr_err_bound_median": float(np.median(bounds)), "ppr_err_bound_p99": float(np.percentile(bounds, 99))}
+        return {**cert, "requests": len(reqs), "wall_s": round(wall, 3), "achieved_qps": round(float(qps), 1),
                 "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
                 "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2), "steps": steps,
                 "max_batches": max_b, "max_state_gib": round(max_state / 2**30, 2), "max_queued": max_q}
@@ -249,6 +261,11 @@ def serve_bench(dg, gg, G22, g22, args):
     reqs = make(R)
     run(reqs[:64], np.zeros(64))  # warm-up
     peak = run(reqs, np.zeros(R))
+    # the same requests again, with the certificate of every served PPR result
+    # computed on the device after its fetch (outside the timed comparison)
+    acc = run(reqs, np.zeros(R), certify=True)
+    log(f"served PPR certificates ({acc['ppr_results_certified']} results, tol 1e-6, float32): median "
+        f"{acc['ppr_err_bound_median']:.2e}, p99 {acc['ppr_err_bound_p99']:.2e}, max {acc['ppr_err_bound_max']:.2e}")
     qps = peak["achieved_qps"]
     levels = []
     for load in (0.25, 0.5, 0.75, 0.9):
@@ -266,7 +283,8 @@ def serve_bench(dg, gg, G22, g22, args):
     return {"graphs": [f"rmat{s}" for s in scales] + [f"rmat{args.scale}"],
             "mix": "1/2 SSSP (random source), 1/2 PPR (float32, tol 1e-6), uniform over graphs; async commits",
             "hbm_budget_gib": args.serve_budget_gib,
-            "peak": peak, "levels": levels}
+            "peak": peak, "levels": levels,
+            "accuracy": {k: v for k, v in acc.items() if k.startswith("ppr_")}}
 
 
 def main():
@@ -306,7 +324,11 @@ def main():
         import multiprocessing as mp
         from concurrent.futures import ProcessPoolExecutor
         pool = ProcessPoolExecutor(1, mp_context=mp.get_context("spawn"))
-        orc_future = pool.submit(oracle_worker, args.scale, 2)
+        import graphgen as _gg
+        n_ppr_ref = 4
+        orc_future = pool.submit(oracle_worker, args.scale, 2, 1e-10,
+                                 _gg.pick_sources(_gg.rmat(args.scale, seed=args.scale), args.batch_queries,
+                                                  seed=args.scale + 1)[:n_ppr_ref].tolist())
 
     import torch
 
@@ -497,6 +519,7 @@ def main():
         GS.close()
 
     batched = {}
+    ppr_rows = {}  # mode -> (first 4 batched rows, first 4 single results), checked against the oracle
     if not args.no_batched:
         # Many queries on the same resident graph: batched launches against the
         # single-query entry point called once per source, same stopping rule.
@@ -520,9 +543,21 @@ def main():
             G.ppr_batch(bsrc[:64], tol=1e-6, mode=mode, d=args.d)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            _, sp = G.ppr_batch(bsrc, tol=1e-6, mode=mode, d=args.d, dtype="f32")
+            xb, sp = G.ppr_batch(bsrc, tol=1e-6, mode=mode, d=args.d, dtype="f32")
             torch.cuda.synchronize()
             tp = time.perf_counter() - t
+            # one query at a time through the single-query sweeps, same tol and storage
+            t = time.perf_counter()
+            e1p, singles = 0, []
+            for q, src in enumerate(bsrc.tolist()):
+                x1, s1 = G.ppr(src, tol=1e-6, mode=mode, d=args.d, dtype="f32")
+                e1p += s1.edges_traversed
+                if q < 4:
+                    singles.append(x1.clone())
+            torch.cuda.synchronize()
+            tp1 = time.perf_counter() - t
+            bounds = [G.error_bound(xb[q], restart=int(src)) for q, src in enumerate(bsrc.tolist())]
+            ppr_rows[mode] = (xb[:4].clone(), singles)
             batched[mode] = {
                 "sssp": {"queries": len(bsrc), "batched_ms": round(tb * 1e3, 2), "batched_sweeps": sb.sweeps,
                          "batched_gteps": round(sb.edges_traversed / tb / 1e9, 1),
@@ -530,10 +565,16 @@ def main():
                          "speedup": round(t1 / tb, 2), "rows_equal_to_one_at_a_time": f"{rows_equal}/{len(bsrc)}"},
                 "ppr_f32_tol1e-6": {"queries": len(bsrc), "batched_ms": round(tp * 1e3, 2),
                                     "batched_sweeps": sp.sweeps,
-                                    "batched_gteps": round(sp.edges_traversed / tp / 1e9, 1)}}
+                                    "batched_gteps": round(sp.edges_traversed / tp / 1e9, 1),
+                                    "one_at_a_time_ms": round(tp1 * 1e3, 2),
+                                    "one_at_a_time_gteps": round(e1p / tp1 / 1e9, 1),
+                                    "speedup": round(tp1 / tp, 2),
+                                    "batched_max_err_bound": max(bounds),
+                                    "batched_median_err_bound": float(np.median(bounds))}}
             log(f"batched {mode}: SSSP x{len(bsrc)} {tb * 1e3:.1f} ms vs one-at-a-time {t1 * 1e3:.1f} ms "
                 f"({t1 / tb:.1f}x, rows equal {equal}); PPR x{len(bsrc)} {tp * 1e3:.1f} ms "
-                f"({sp.edges_traversed / tp / 1e9:.0f} GTEPS)")
+                f"({sp.edges_traversed / tp / 1e9:.0f} GTEPS) vs one-at-a-time {tp1 * 1e3:.1f} ms "
+                f"({tp1 / tp:.1f}x); largest row certificate {max(bounds):.2e}")
 
     topology = {}
     if not args.no_topology:
@@ -644,6 +685,17 @@ def main():
             for (tname, key, src), dist in sssp_out.items():
                 if src == b["source"]:
                     parity["sssp_bit_exact"][f"{tname}/{key}/src{src}"] = bool(torch.equal(dist.to(torch.int64), ref))
+        ppr_err = {}
+        for mode, (rows, singles) in ppr_rows.items():
+            for q, (xs_q, src) in enumerate(zip(orc.get("ppr_xstar", {}).values(), orc.get("ppr_xstar", {}).keys())):
+                xq = torch.from_numpy(xs_q).to("cuda")
+                ppr_err[f"{mode}/batched/src{src}"] = float((rows[q] - xq).abs().sum())
+                ppr_err[f"{mode}/single/src{src}"] = float((singles[q] - xq).abs().sum())
+            batched[mode]["ppr_f32_tol1e-6"]["max_l1_err_vs_oracle_sampled"] = max(
+                v for k, v in ppr_err.items() if k.startswith(f"{mode}/batched"))
+            batched[mode]["ppr_f32_tol1e-6"]["one_at_a_time_max_l1_err_vs_oracle_sampled"] = max(
+                v for k, v in ppr_err.items() if k.startswith(f"{mode}/single"))
+        parity["ppr_l1_err_sampled"] = ppr_err
         worst = max(parity["pagerank_l1_err"].values(), default=float("nan"))
         worst7 = max((v for k, v in parity["pagerank_l1_err"].items() if k.endswith("tol1e-7")), default=float("nan"))
         parity["pagerank_max_l1_err_tol1e-6"] = worst

@@ -339,6 +339,21 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
 dg_status dg_ppr(dg_graph* g, uint32_t src, double damping, double tol, dg_mode mode, uint32_t d, dg_dtype dtype,
                  uint32_t max_sweeps, double* out_scores, int out_on_device, dg_stats* stats, void* hip_stream);
 
+/* Error certificate of any score vector x (n float64 values, normalised to
+ * sum 1 by the caller): ||T(x) - x||_1 / (1 - damping) for the PageRank map T
+ * of dg_pagerank (restart = DG_NO_RESTART) or the personalised map of dg_ppr
+ * with that restart vertex, computed on the device in float64 by one
+ * synchronous sweep.  T is an L1 contraction with factor damping, so the
+ * value bounds the L1 distance of x to the exact fixed point, and is at most
+ * (1 + damping) / (1 - damping) times that distance.  For the results of
+ * dg_ppr_batch and the server, which report no bound themselves.
+ *   scores       device memory when scores_on_device != 0, else host memory
+ *   out_bound    host double
+ * Uses the graph's workspace: not concurrently with another call on g. */
+#define DG_NO_RESTART 0xFFFFFFFFu
+dg_status dg_error_bound(dg_graph* g, double damping, uint32_t restart, const double* scores, int scores_on_device,
+                         double* out_bound, void* hip_stream);
+
 /* Bellman-Ford single-source shortest paths by repeated pull relaxation
  * sweeps (sections III and IV-D): d'(v) = min(d(v), min over in-edges
  * (u,v) of d(u) + w(u,v)), stored every sweep, stopping after the first

@@ -775,6 +775,31 @@ dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uin
                           hip_stream);
 }
 
+dg_status dg_error_bound(dg_graph* g, double damping, uint32_t restart, const double* scores, int scores_on_device,
+                         double* out_bound, void* hip_stream) {
+  g_last_error.clear();
+  if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (g->G) return fail(DG_ERR_UNSUPPORTED, "not supported on the union graph of a set");
+  if (!(damping >= 0.0 && damping < 1.0)) return fail(DG_ERR_INVALID_ARGUMENT, "damping must be in [0, 1)");
+  if (restart != DG_NO_RESTART && restart >= g->n)
+    return fail(DG_ERR_INVALID_ARGUMENT, "restart vertex %u >= n = %u", restart, g->n);
+  if (!scores || !out_bound) return fail(DG_ERR_INVALID_ARGUMENT, "NULL scores or out_bound");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  dg_status st = ensure_workspace(g, 1, s);
+  if (st != DG_OK) return st;
+  const double* y = scores;
+  if (!scores_on_device) {
+    DG_HIP(hipMemcpyAsync(g->vals[2], scores, (size_t)g->n * 8, hipMemcpyHostToDevice, s));
+    y = static_cast<const double*>(g->vals[2]);
+  }
+  SweepState sst = state(g);
+  sst.scale = g->scale;
+  double bound = 0.0;
+  if ((st = certify(g, y, damping, restart, sst, s, bound)) != DG_OK) return st;
+  *out_bound = bound;
+  return DG_OK;
+}
+
 dg_status dg_ppr(dg_graph* g, uint32_t src, double damping, double tol, dg_mode mode, uint32_t d, dg_dtype dtype,
                  uint32_t max_sweeps, double* out_scores, int out_on_device, dg_stats* stats, void* hip_stream) {
   g_last_error.clear();

@@ -32,6 +32,7 @@ DTYPES = {"f32": DG_F32, "f64": DG_F64}
 
 # Every symbol declared in include/dg.h.
 EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_info_get", "dg_pagerank", "dg_ppr",
+           "dg_error_bound",
            "dg_sssp", "dg_sssp_batch", "dg_ppr_batch", "dg_set_create", "dg_set_destroy", "dg_set_info_get",
            "dg_set_pagerank", "dg_set_sssp", "dg_graph_partition", "dg_access_matrix", "dg_graph_repartition",
            "dg_tune", "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_server_create",
@@ -162,6 +163,7 @@ def _load():
                                   C.POINTER(dg_stats), P]),
         "dg_ppr": (C.c_int, [P, C.c_uint32, C.c_double, C.c_double, C.c_int, C.c_uint32, C.c_int, C.c_uint32, P,
                              C.c_int, C.POINTER(dg_stats), P]),
+        "dg_error_bound": (C.c_int, [P, C.c_double, C.c_uint32, P, C.c_int, C.POINTER(C.c_double), P]),
         "dg_sssp": (C.c_int, [P, C.c_uint32, C.c_int, C.c_uint32, C.c_uint32, P, C.c_int, C.POINTER(dg_stats), P]),
         "dg_sssp_noalloc": (C.c_int, [P, C.c_uint32, C.c_int, C.c_uint32, C.c_uint32, P, C.c_int,
                                       C.POINTER(dg_stats), P]),
@@ -251,6 +253,13 @@ def dg_graph_info_get(g, info):
 
 def dg_pagerank(g, damping, tol, mode, d, dtype, max_sweeps, out, out_on_device, stats, stream):
     return lib.dg_pagerank(g, damping, tol, mode, d, dtype, max_sweeps, out, out_on_device, stats, stream)
+
+
+DG_NO_RESTART = 0xFFFFFFFF
+
+
+def dg_error_bound(g, damping, restart, scores, scores_on_device, out_bound, stream):
+    return lib.dg_error_bound(g, damping, restart, scores, scores_on_device, out_bound, stream)
 
 
 def dg_ppr(g, src, damping, tol, mode, d, dtype, max_sweeps, out, out_on_device, stats, stream):
@@ -539,6 +548,23 @@ class Graph:
                                _stream_handle(stream)),
                    allow=(DG_ERR_NOT_CONVERGED,) if allow_not_converged else ())
         return out, _stats(st, s == DG_OK)
+
+    def error_bound(self, scores, restart=None, damping=0.85, stream=None):
+        """dg_error_bound of a float64 score vector (device tensor or numpy
+        array): an upper bound on its L1 distance to the fixed point of
+        PageRank, or of personalised PageRank with this restart vertex."""
+        b = C.c_double()
+        rs = DG_NO_RESTART if restart is None else int(restart)
+        if _is_device_tensor(scores):
+            import torch
+            assert scores.dtype == torch.float64 and scores.is_contiguous() and scores.numel() == self.n
+            _check(dg_error_bound(self._h, float(damping), rs, C.c_void_p(scores.data_ptr()), 1, C.byref(b),
+                                  _stream_handle(stream)))
+        else:
+            a = np.ascontiguousarray(scores, dtype=np.float64)
+            assert a.size == self.n
+            _check(dg_error_bound(self._h, float(damping), rs, _np_ptr(a), 0, C.byref(b), _stream_handle(stream)))
+        return b.value
 
     def ppr(self, src, damping=0.85, tol=1e-6, mode="delayed", d=64, dtype="f32", max_sweeps=10_000, out=None,
             stream=None, allow_not_converged=False, err_bound=False):

@@ -118,3 +118,24 @@ def test_ppr_validation(dg):
     with pytest.raises(dg.DGError):
         G.ppr(0, damping=1.0)
     G.close()
+
+
+def test_error_bound_of_any_vector(dg):
+    """dg_error_bound equals the oracle's certificates (global and
+    personalised) on perturbed vectors, from device and host memory."""
+    import torch
+    g = _graph("dangling")
+    G = dg.Graph.from_csr(g)
+    rng = np.random.default_rng(4)
+    s = int(gg.pick_sources(g, 1, seed=8)[0])
+    for restart in (None, s):
+        xs = opr.pagerank_fixed_point(g) if restart is None else opr.ppr_fixed_point(g, s)
+        for sc in (1e-3, 1e-7):
+            y = np.abs(xs + sc * rng.standard_normal(g.n) / g.n)
+            y /= y.sum()
+            want = opr.certificate(g, y) if restart is None else opr.ppr_certificate(g, y, s)
+            got_h = G.error_bound(y, restart=restart)
+            got_d = G.error_bound(torch.from_numpy(y).cuda(), restart=restart)
+            assert abs(got_h - want) <= 1e-12 + 1e-9 * want and abs(got_d - want) <= 1e-12 + 1e-9 * want
+            assert got_h >= np.abs(y - xs).sum() - 1e-12
+    G.close()
