@@ -634,26 +634,44 @@ def main():
 
     tuning = {}
     if not args.no_tune:
-        # Autotuner: partition size and commit mode/interval chosen by the
-        # sweep-time x sweep-count model, against the default configuration.
+        # Autotuner: commit mode and d, partition size and mapping (sweep
+        # variant, resident table) by the sweep-time x sweep-count model and
+        # timed runs, on R-MAT scales 16, 20 and 22 (each on a handle of its
+        # own), against the creation-time default (delayed d=64) with the
+        # spread of three runs each; and the batched tuner on 64 of the
+        # workload's batched sources.
         dg.tune_cache_clear()
-        for algo, kw in (("pagerank", {"dtype": "f32", "tol": 1e-6}), ("sssp", {"src": int(sources[0])})):
-            t0 = time.perf_counter()
-            t = G.tune(algo, use_cache=False, **kw)
-            t["tuning_wall_s"] = round(time.perf_counter() - t0, 3)
-            G.repartition(0)
-            if algo == "pagerank":
-                dflt = min(G.pagerank(tol=1e-6, mode="delayed", d=args.d, dtype="f32")[1].seconds for _ in range(3))
-            else:
-                dflt = min(G.sssp(int(sources[0]), mode="delayed", d=args.d)[1].seconds for _ in range(3))
-            t["default_seconds"] = dflt
-            t["default"] = f"delayed d={args.d}, {info.workers} workers"
-            t["speedup_vs_default"] = round(dflt / t["seconds"], 3)
-            t.pop("graph_hash")
-            tuning[algo] = t
-            log(f"tuned {algo}: {t['mode']} d={t['d']} workers={t['workers']} -> {t['seconds'] * 1e3:.3f} ms "
-                f"(model {t['predicted_seconds'] * 1e3:.3f} ms; default {dflt * 1e3:.3f} ms; "
-                f"{t['candidates']} candidates in {t['tuning_wall_s']} s)")
+        for sc in (16, 20, args.scale):
+            gt = g if sc == args.scale else gg.rmat(sc, seed=sc)
+            GT = dg.Graph.from_csr(gt)
+            srcs_t = gg.pick_sources(gt, 1, seed=sc).tolist()
+            row = {}
+            for algo, kw in (("pagerank", {"dtype": "f32", "tol": 1e-6}), ("sssp", {"src": int(srcs_t[0])})):
+                t0 = time.perf_counter()
+                t = GT.tune(algo, use_cache=False, **kw)
+                t["tuning_wall_s"] = round(time.perf_counter() - t0, 3)
+                t["speedup_vs_default_median"] = round(t["default_seconds"] / t["seconds"], 3)
+                t.pop("graph_hash")
+                row[algo] = t
+                log(f"tuned rmat{sc} {algo}: {t['mode']} d={t['d']} workers={t['workers']} "
+                    f"{t['sweep_variant']} table={t['resident_vertices']} -> {t['seconds'] * 1e3:.3f} ms "
+                    f"[{t['seconds_min'] * 1e3:.3f}, {t['seconds_max'] * 1e3:.3f}] vs default "
+                    f"{t['default_seconds'] * 1e3:.3f} ms [{t['default_seconds_min'] * 1e3:.3f}, "
+                    f"{t['default_seconds_max'] * 1e3:.3f}] ({t['candidates']} candidates in {t['tuning_wall_s']} s)")
+            if sc == args.scale and not args.no_batched:
+                bs = gg.pick_sources(g, 64, seed=args.scale + 1)
+                for algo in ("sssp", "ppr"):
+                    t0 = time.perf_counter()
+                    t = GT.tune_batch(algo, bs, dtype="f32", tol=1e-6)
+                    t["tuning_wall_s"] = round(time.perf_counter() - t0, 3)
+                    t["speedup_vs_default_median"] = round(t["default_seconds"] / t["seconds"], 3)
+                    t.pop("graph_hash")
+                    row[f"{algo}_batch64"] = t
+                    log(f"tuned rmat{sc} batched {algo} x64: {t['mode']} d={t['d']} workers={t['workers']} -> "
+                        f"{t['seconds'] * 1e3:.2f} ms [{t['seconds_min'] * 1e3:.2f}, {t['seconds_max'] * 1e3:.2f}] "
+                        f"vs default {t['default_seconds'] * 1e3:.2f} ms ({t['candidates']} candidates)")
+            tuning[f"rmat{sc}"] = row
+            GT.close()
 
     graph_set = {}
     if not args.no_set:

@@ -423,22 +423,44 @@ dg_status dg_graph_partition(const dg_graph* g, uint32_t* out_first_vertex, void
  * Must not overlap a sweep call on the same graph. */
 dg_status dg_graph_repartition(dg_graph* g, uint32_t workers, void* hip_stream);
 
+/* Changes how the single-query sweeps map a resident graph onto the GPU,
+ * without re-uploading it (a form beyond the paper, for the autotuner):
+ *   sweep_variant      DG_SWEEP_WIDE, _WIDE_INFLIGHT or _NARROW, or
+ *                      DG_SWEEP_AUTO for the variant chosen at creation; a
+ *                      switch to or from DG_SWEEP_NARROW rebuilds the tiles
+ *                      (its tile cap differs) and both partitions over them
+ *   resident_vertices  at most this many resident-table entries are read
+ *                      from LDS (<= dg_graph_info.resident_vertices; 0 = no
+ *                      table; DG_RESIDENT_AUTO = all of them)
+ *   workers            as dg_graph_repartition (0 = the default)
+ * Results do not change beyond the reordering of floating-point sums and the
+ * timing-dependent commits of the asynchronous modes.  Not for the union
+ * graph of a set.  Must not overlap a sweep call on the same graph. */
+dg_status dg_graph_set_mapping(dg_graph* g, uint32_t sweep_variant, uint32_t resident_vertices, uint32_t workers,
+                               void* hip_stream);
+
 /* Autotuner (a form beyond the paper, which leaves the choice of delta to
  * future work and shows that it depends on topology, thread count and update
- * density: sections IV and V).  Chooses the partition size and the commit mode and interval
- * for one algorithm on one graph by a sweep-time x sweep-count model:
- *   1. a full run of every candidate (sync, async, delayed with d in
- *      {16, 64, 256, 1024, 4096, whole}) at the current partition gives its
- *      sweep count;
- *   2. for every partition size (1, 2, 3 and 4 sweep workgroups per compute
- *      unit, rounded down to a multiple of 8), a 6-sweep probe of every
- *      candidate gives its time per sweep (best of two);
- *   3. the candidate with the least predicted time to convergence is run
- *      twice more to measure it.
- * The graph is left partitioned with the chosen number of workers (unless
- * DG_TUNE_KEEP_WORKERS).  Results are cached in-process by the graph's
- * 64-bit content hash, the algorithm, dtype, tol and source; a cached entry
- * is returned at once (from_cache = 1) unless DG_TUNE_NO_CACHE.
+ * density: sections IV and V).  Chooses, for one algorithm on one graph:
+ *   1. the commit mode and interval: a full run of every candidate (sync,
+ *      async, delayed with d in {16, 64, 256, 1024, 4096, whole}) at the
+ *      current mapping gives its sweep count;
+ *   2. the partition size: for 1, 2, 3 and 4 sweep workgroups per compute
+ *      unit (rounded down to a multiple of 8), a 6-sweep probe of every
+ *      candidate gives its time per sweep (best of two); the least predicted
+ *      time to convergence (sweeps x time per sweep) wins;
+ *   3. the mapping, for that mode, d and partition: every sweep variant
+ *      (wide, wide with all gathers in flight, narrow) with the whole
+ *      resident table, half of it and none, each run to convergence three
+ *      times; the least median time wins.
+ * The choice and the default (the mapping and partition chosen at creation,
+ * delayed d = 64) are each run to convergence three times: their median,
+ * fastest and slowest times are reported.  The graph is left with the chosen
+ * partition and mapping (with DG_TUNE_KEEP_WORKERS neither changes and only
+ * stage 1 runs, at the current partition).  Results are cached in-process by
+ * the graph's 64-bit content hash, the algorithm, dtype, tol and source; a
+ * cached entry is applied and returned at once (from_cache = 1) unless
+ * DG_TUNE_NO_CACHE.
  *   algo   DG_ALGO_PAGERANK (damping 0.85, tol > 0, dtype) or DG_ALGO_SSSP
  *          (source src; tol and dtype ignored) */
 typedef enum { DG_ALGO_PAGERANK = 0, DG_ALGO_SSSP = 1 } dg_algo;
@@ -448,15 +470,35 @@ typedef struct {
   uint32_t workers;          /* chosen partition size (now the graph's) */
   dg_mode mode;              /* chosen commit mode */
   uint32_t d;                /* chosen commit interval (delayed) */
-  uint32_t sweeps;           /* sweeps of the measuring run */
-  double seconds;            /* time to convergence of the measuring run */
-  double predicted_seconds;  /* the model's estimate for the choice */
-  uint32_t candidates;       /* (partition, mode, d) triples evaluated */
+  uint32_t sweeps;           /* sweeps of the last measuring run */
+  double seconds;            /* median time to convergence of the choice */
+  double predicted_seconds;  /* the sweep-count x sweep-time model's estimate */
+  uint32_t candidates;       /* configurations evaluated */
   uint32_t from_cache;
   uint64_t graph_hash;       /* content hash of the graph */
+  uint32_t sweep_variant;    /* chosen sweep variant (now the graph's) */
+  uint32_t resident_vertices; /* chosen resident-table limit, or DG_RESIDENT_AUTO */
+  uint32_t repeats;          /* timed runs of the choice and of the default */
+  uint32_t reserved;
+  double seconds_min, seconds_max;                 /* fastest and slowest run of the choice */
+  double default_seconds;                          /* median of the default */
+  double default_seconds_min, default_seconds_max; /* fastest and slowest run of the default */
 } dg_tuning;
 dg_status dg_tune(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, uint32_t src, uint32_t flags,
                   dg_tuning* out, void* hip_stream);
+
+/* Autotuner of the batched calls (dg_sssp_batch, or dg_ppr_batch for
+ * DG_ALGO_PAGERANK with damping 0.85, tol and dtype): on the given sample of
+ * k (1..1024) sources, every commit mode and interval (sync, async, delayed
+ * d in {16, 64, 256, whole}) for 3, 5 and 8 batched workgroups per compute
+ * unit, each run three times; the least median time wins, and the graph's
+ * batched partition (used by dg_sssp_batch, dg_ppr_batch and the server) is
+ * left at the chosen size.  The default is delayed d = 64 with 5 workgroups
+ * per compute unit.  Fills dg_tuning as dg_tune (predicted_seconds = the
+ * measured median; sweep_variant and resident_vertices are unchanged);
+ * nothing is cached.  flags must be 0. */
+dg_status dg_tune_batch(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, const uint32_t* sources, uint32_t k,
+                        uint32_t flags, dg_tuning* out, void* hip_stream);
 /* The in-process cache of tuning results: cleared, written to and merged
  * from a text file (one result per line, comments start with '#'). */
 dg_status dg_tune_cache_clear(void);

@@ -69,6 +69,7 @@ using dg::host::topo_batch;
 using dg::host::build_layout;
 using dg::host::build_workers;
 using dg::host::build_workers_seg;
+using dg::host::build_tiles;
 using dg::host::plan_workers;
 using dg::host::Layout;
 using dg::host::validate_graph;
@@ -287,7 +288,7 @@ dg_status check_mode(dg_mode mode, uint32_t d, bool local = false) {
 // Resident-table entries a sweep reads from LDS: the graph's R leading
 // compact-region slots, as many as kResBytes holds at this element size.
 uint32_t resident(const dg_graph* g, size_t elem) {
-  return std::min<uint32_t>(g->R, kResBytes / (uint32_t)elem);
+  return std::min(std::min<uint32_t>(g->R, kResBytes / (uint32_t)elem), g->res_limit);
 }
 
 // Fields of dg_stats that describe the partition and the commits.
@@ -605,8 +606,10 @@ dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
   g->hash = L.hash;
   g->T = L.T();
   g->variant = L.variant;
+  g->variant0 = L.variant;
   g->tile_v_h = L.tile_v;
   g->tile_e0_h = L.tile_e0;
+  if (!seg_v) g->in_ptr_h = L.in_ptr;
   uint32_t P = plan_workers(L, opts ? opts->workers : 0u, g->cus, per_cu);
   std::vector<uint32_t> work_t;
   if (seg_v) {
@@ -1313,6 +1316,84 @@ dg_status dg_graph_repartition(dg_graph* g, uint32_t workers, void* hip_stream) 
   return DG_OK;
 }
 
+dg_status dg_graph_set_mapping(dg_graph* g, uint32_t sweep_variant, uint32_t resident_vertices, uint32_t workers,
+                               void* hip_stream) {
+  g_last_error.clear();
+  if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (g->G) return fail(DG_ERR_UNSUPPORTED, "a set's union graph keeps its own mapping");
+  if (sweep_variant > DG_SWEEP_NARROW)
+    return fail(DG_ERR_INVALID_ARGUMENT, "unknown sweep_variant %u", sweep_variant);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const uint32_t want = sweep_variant == DG_SWEEP_AUTO ? g->variant0 : sweep_variant;
+  const bool narrow_now = g->variant == kNarrow, narrow_want = want == kNarrow;
+  if (narrow_now != narrow_want) {
+    // The narrow variant has its own tile cap: rebuild the tiles, then both
+    // partitions over them (the batched kernels use the same tiles).
+    std::vector<uint32_t> tv, te0, wtb;
+    try {
+      build_tiles(g->in_ptr_h, g->n, tv, nullptr, narrow_want ? (uint32_t)kTileENarrow : (uint32_t)kTileE);
+      te0.resize(tv.size());
+      for (size_t t = 0; t < tv.size(); ++t) te0[t] = g->in_ptr_h[tv[t]];
+    } catch (const std::bad_alloc&) {
+      return fail(DG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+    const uint32_t T = (uint32_t)tv.size() - 1;
+    uint32_t Pb = std::max(1u, std::min(g->cus * kBatchWorkersPerCU, T));
+    if (Pb > 8) Pb &= ~7u;
+    build_workers(tv, te0, Pb, wtb);
+    DG_HIP(hipStreamSynchronize(s));
+    uint32_t* tvd = static_cast<uint32_t*>(dev_alloc(g, tv.size() * 4, s));
+    uint32_t* wtbd = static_cast<uint32_t*>(dev_alloc(g, wtb.size() * 4, s));
+    if (!tvd || !wtbd) {
+      dev_free(g, tvd);
+      dev_free(g, wtbd);
+      return fail(DG_ERR_OUT_OF_MEMORY, "re-tiling allocation failed");
+    }
+    DG_HIP(hipMemcpyAsync(tvd, tv.data(), tv.size() * 4, hipMemcpyHostToDevice, s));
+    DG_HIP(hipMemcpyAsync(wtbd, wtb.data(), wtb.size() * 4, hipMemcpyHostToDevice, s));
+    DG_HIP(hipStreamSynchronize(s));
+    dev_free(g, g->tile_v);
+    dev_free(g, g->work_tb);
+    g->tile_v = tvd;
+    g->work_tb = wtbd;
+    g->tile_v_h.swap(tv);
+    g->tile_e0_h.swap(te0);
+    g->T = T;
+    g->Pb = Pb;
+    g->max_block_vb = 1;
+    for (uint32_t w = 0; w < Pb; ++w)
+      g->max_block_vb = std::max(g->max_block_vb, g->tile_v_h[wtb[w + 1]] - g->tile_v_h[wtb[w]]);
+    g->P = 0;  // forces the repartition below
+  }
+  g->variant = want;
+  g->res_limit = resident_vertices == DG_RESIDENT_AUTO ? 0xFFFFFFFFu : resident_vertices;
+  return dg_graph_repartition(g, workers, hip_stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Median, min and max of a few timed runs.
+struct Spread {
+  double med = 0.0, lo = 0.0, hi = 0.0;
+};
+Spread spread_of(std::vector<double> v) {
+  std::sort(v.begin(), v.end());
+  Spread sp;
+  if (v.empty()) return sp;
+  sp.lo = v.front();
+  sp.hi = v.back();
+  sp.med = v.size() % 2 ? v[v.size() / 2] : 0.5 * (v[v.size() / 2 - 1] + v[v.size() / 2]);
+  return sp;
+}
+
+constexpr uint32_t kTuneRepeats = 3;
+
+}  // namespace
+
+extern "C" {
+
 dg_status dg_tune(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, uint32_t src, uint32_t flags,
                   dg_tuning* out, void* hip_stream) {
   g_last_error.clear();
@@ -1331,10 +1412,13 @@ dg_status dg_tune(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, uint32_
     tol = 0.0;
   }
   const bool keep = (flags & DG_TUNE_KEEP_WORKERS) != 0;
+  const bool can_map = g->G == 0 && !keep;  // sets keep their per-graph mapping
   dg_tuning cached;
   if (!(flags & DG_TUNE_NO_CACHE) && tune_find(g->hash, (int)algo, (int)dtype, tol, src, cached)) {
     if (!keep) {
-      dg_status st = dg_graph_repartition(g, cached.workers, hip_stream);
+      dg_status st = can_map ? dg_graph_set_mapping(g, cached.sweep_variant, cached.resident_vertices, cached.workers,
+                                                    hip_stream)
+                             : dg_graph_repartition(g, cached.workers, hip_stream);
       if (st != DG_OK) return st;
     }
     *out = cached;
@@ -1355,6 +1439,29 @@ dg_status dg_tune(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, uint32_
     if (r == DG_ERR_NOT_CONVERGED) r = DG_OK;
     return r;
   };
+  // kTuneRepeats full runs: the spread of their times to convergence
+  auto timed = [&](dg_mode mode, uint32_t d, Spread& sp, uint32_t& sweeps) -> dg_status {
+    std::vector<double> t;
+    for (uint32_t i = 0; i < kTuneRepeats; ++i) {
+      dg_stats x{};
+      dg_status r = run(mode, d, tol, full, x);
+      if (r != DG_OK) return r;
+      t.push_back(x.seconds);
+      sweeps = x.sweeps;
+    }
+    sp = spread_of(t);
+    return DG_OK;
+  };
+  dg_status st;
+  // The default the choice is compared with: the creation-time mapping and
+  // partition, delayed d = 64.
+  const uint32_t P0 = g->P, var0 = g->variant, res0 = g->res_limit;
+  Spread def{};
+  uint32_t def_sweeps = 0;
+  if (can_map && (st = dg_graph_set_mapping(g, DG_SWEEP_AUTO, DG_RESIDENT_AUTO, 0, hip_stream)) != DG_OK) return st;
+  if ((st = timed(DG_DELAYED, 64, def, def_sweeps)) != DG_OK) return st;
+  if (can_map && (st = dg_graph_set_mapping(g, var0, res0, P0, hip_stream)) != DG_OK) return st;
+
   struct Cand {
     dg_mode mode;
     uint32_t d;
@@ -1363,15 +1470,16 @@ dg_status dg_tune(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, uint32_
   std::vector<Cand> cands = {{DG_SYNC, 1, 0},      {DG_ASYNC, 1, 0},     {DG_DELAYED, 16, 0},
                              {DG_DELAYED, 64, 0},  {DG_DELAYED, 256, 0}, {DG_DELAYED, 1024, 0},
                              {DG_DELAYED, 4096, 0}, {DG_DELAYED, DG_D_WHOLE, 0}};
-  // Sweep counts: a full run of each candidate at the current partition.
-  dg_status st;
+  // Stage 1, commit mode and interval: sweep counts from a full run of each
+  // candidate at the current mapping.
   for (auto& c : cands) {
     dg_stats x{};
     if ((st = run(c.mode, c.d, tol, full, x)) != DG_OK) return st;
     c.sweeps = x.sweeps;
   }
-  // Time per sweep: short fixed-length probes (tol 0 for PageRank) for every
-  // partition size, best of two.
+  // Stage 2, partition size: time per sweep from short fixed-length probes
+  // (tol 0 for PageRank) of every candidate for every size, best of two; the
+  // least predicted time to convergence wins.
   std::vector<uint32_t> Ps;
   if (keep) {
     Ps.push_back(g->P);
@@ -1404,20 +1512,183 @@ dg_status dg_tune(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, uint32_
     }
   }
   if ((st = dg_graph_repartition(g, bestP, hip_stream)) != DG_OK) return st;
-  dg_stats v1{}, v2{};
-  if ((st = run(cands[bestc].mode, cands[bestc].d, tol, full, v1)) != DG_OK) return st;
-  if ((st = run(cands[bestc].mode, cands[bestc].d, tol, full, v2)) != DG_OK) return st;
+  const dg_mode mode = cands[bestc].mode;
+  const uint32_t d = cands[bestc].d;
+  // Stage 3, the mapping of edges onto the workgroup (sweep variant) and the
+  // size of the resident table, for the chosen mode, d and partition: each
+  // candidate timed kTuneRepeats times to convergence (their sweep counts
+  // depend on the mapping in the asynchronous modes), the least median wins.
+  uint32_t best_var = g->variant, best_res = g->res_limit, sweeps = 0;
+  Spread chosen{};
+  if ((st = timed(mode, d, chosen, sweeps)) != DG_OK) return st;
+  ++evaluated;
+  if (can_map) {
+    const uint32_t R = g->R;
+    std::vector<uint32_t> res_c = {DG_RESIDENT_AUTO};
+    if (R >= 2) res_c.push_back(R / 2);
+    if (R > 0) res_c.push_back(0);
+    for (uint32_t var : {DG_SWEEP_WIDE, DG_SWEEP_WIDE_INFLIGHT, DG_SWEEP_NARROW}) {
+      for (uint32_t res : res_c) {
+        const uint32_t res_l = res == DG_RESIDENT_AUTO ? 0xFFFFFFFFu : res;
+        if (var == best_var && res_l == best_res) continue;  // the current mapping, timed above
+        if ((st = dg_graph_set_mapping(g, var, res, bestP, hip_stream)) != DG_OK) return st;
+        Spread sp{};
+        uint32_t sw = 0;
+        if ((st = timed(mode, d, sp, sw)) != DG_OK) return st;
+        ++evaluated;
+        if (sp.med < chosen.med) {
+          chosen = sp;
+          sweeps = sw;
+          best_var = var;
+          best_res = res_l;
+        }
+      }
+    }
+    if ((st = dg_graph_set_mapping(g, best_var, best_res == 0xFFFFFFFFu ? DG_RESIDENT_AUTO : best_res, bestP,
+                                   hip_stream)) != DG_OK)
+      return st;
+  }
   dg_tuning t{};
   t.workers = g->P;
-  t.mode = cands[bestc].mode;
-  t.d = cands[bestc].d;
-  t.sweeps = v2.sweeps;
-  t.seconds = std::min(v1.seconds, v2.seconds);
+  t.mode = mode;
+  t.d = d;
+  t.sweeps = sweeps;
+  t.seconds = chosen.med;
+  t.seconds_min = chosen.lo;
+  t.seconds_max = chosen.hi;
   t.predicted_seconds = best;
   t.candidates = evaluated;
   t.from_cache = 0;
   t.graph_hash = g->hash;
+  t.sweep_variant = g->variant;
+  t.resident_vertices = best_res == 0xFFFFFFFFu ? DG_RESIDENT_AUTO : best_res;
+  t.repeats = kTuneRepeats;
+  t.default_seconds = def.med;
+  t.default_seconds_min = def.lo;
+  t.default_seconds_max = def.hi;
   tune_put(TuneEntry{g->hash, (int)algo, (int)dtype, tol, src, t});
+  *out = t;
+  return DG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Re-partitions the batched kernels' tiles over Pb workers.
+dg_status set_batch_workers(dg_graph* g, uint32_t Pb, hipStream_t s) {
+  Pb = std::max(1u, std::min(Pb, g->T));
+  if (Pb == g->Pb) return DG_OK;
+  std::vector<uint32_t> wtb;
+  build_workers(g->tile_v_h, g->tile_e0_h, Pb, wtb);
+  DG_HIP(hipStreamSynchronize(s));
+  uint32_t* d = static_cast<uint32_t*>(dev_alloc(g, wtb.size() * 4, s));
+  if (!d) return fail(DG_ERR_OUT_OF_MEMORY, "batched partition allocation failed");
+  DG_HIP(hipMemcpyAsync(d, wtb.data(), wtb.size() * 4, hipMemcpyHostToDevice, s));
+  DG_HIP(hipStreamSynchronize(s));
+  dev_free(g, g->work_tb);
+  g->work_tb = d;
+  g->Pb = Pb;
+  g->max_block_vb = 1;
+  for (uint32_t w = 0; w < Pb; ++w) g->max_block_vb = std::max(g->max_block_vb, g->tile_v_h[wtb[w + 1]] - g->tile_v_h[wtb[w]]);
+  return DG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dg_status dg_tune_batch(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, const uint32_t* sources, uint32_t k,
+                        uint32_t flags, dg_tuning* out, void* hip_stream) {
+  g_last_error.clear();
+  if (!g || !out || !sources) return fail(DG_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (algo != DG_ALGO_PAGERANK && algo != DG_ALGO_SSSP) return fail(DG_ERR_INVALID_ARGUMENT, "unknown algorithm");
+  if (k == 0 || k > 1024) return fail(DG_ERR_INVALID_ARGUMENT, "k = %u outside [1, 1024]", k);
+  if (flags != 0) return fail(DG_ERR_INVALID_ARGUMENT, "flags must be 0 (got 0x%x)", flags);
+  for (uint32_t i = 0; i < k; ++i)
+    if (sources[i] >= g->n) return fail(DG_ERR_INVALID_ARGUMENT, "sources[%u] = %u >= n", i, sources[i]);
+  if (algo == DG_ALGO_PAGERANK) {
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(DG_ERR_INVALID_ARGUMENT, "tol must be finite and > 0");
+    if (dtype != DG_F32 && dtype != DG_F64) return fail(DG_ERR_INVALID_ARGUMENT, "dtype must be DG_F32 or DG_F64");
+  } else if (!g->has_w) {
+    return fail(DG_ERR_INVALID_ARGUMENT, "the graph was created without weights");
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  CallAllocs al(g);
+  void* outd = al.get((size_t)k * g->n * (algo == DG_ALGO_PAGERANK ? 8 : 4), s);
+  if (!outd) return fail(DG_ERR_OUT_OF_MEMORY, "tuning output allocation failed");
+  auto timed = [&](dg_mode mode, uint32_t d, Spread& sp, uint32_t& sweeps) -> dg_status {
+    std::vector<double> t;
+    for (uint32_t i = 0; i < kTuneRepeats; ++i) {
+      dg_stats x{};
+      dg_status r = algo == DG_ALGO_PAGERANK
+                        ? dg_ppr_batch(g, sources, k, 0.85, tol, mode, d, dtype, 10000, static_cast<double*>(outd), 1,
+                                       &x, hip_stream)
+                        : dg_sssp_batch(g, sources, k, mode, d, std::min<uint32_t>(g->n + 1, 100000),
+                                        static_cast<uint32_t*>(outd), 1, &x, hip_stream);
+      if (r == DG_ERR_NOT_CONVERGED) r = DG_OK;
+      if (r != DG_OK) return r;
+      t.push_back(x.seconds);
+      sweeps = x.sweeps;
+    }
+    sp = spread_of(t);
+    return DG_OK;
+  };
+  dg_status st;
+  const uint32_t Pb_def = default_workers(g, kBatchWorkersPerCU);
+  Spread def{};
+  uint32_t sw_def = 0;
+  if ((st = set_batch_workers(g, Pb_def, s)) != DG_OK) return st;
+  if ((st = timed(DG_DELAYED, 64, def, sw_def)) != DG_OK) return st;
+  struct Cand {
+    dg_mode mode;
+    uint32_t d;
+  };
+  const Cand cands[] = {{DG_SYNC, 1},       {DG_ASYNC, 1},        {DG_DELAYED, 16},
+                        {DG_DELAYED, 64},   {DG_DELAYED, 256},    {DG_DELAYED, DG_D_WHOLE}};
+  Spread best{};
+  best.med = 1e300;
+  uint32_t bestP = Pb_def, best_sw = 0, evaluated = 0;
+  Cand bestc = {DG_DELAYED, 64};
+  for (uint32_t per_cu : {3u, 5u, 8u}) {
+    const uint32_t Pb = default_workers(g, per_cu);
+    if ((st = set_batch_workers(g, Pb, s)) != DG_OK) return st;
+    for (const Cand& c : cands) {
+      Spread sp{};
+      uint32_t sw = 0;
+      if (Pb == Pb_def && c.mode == DG_DELAYED && c.d == 64) {
+        sp = def;
+        sw = sw_def;
+      } else if ((st = timed(c.mode, c.d, sp, sw)) != DG_OK) {
+        return st;
+      }
+      ++evaluated;
+      if (sp.med < best.med) {
+        best = sp;
+        bestP = g->Pb;
+        bestc = c;
+        best_sw = sw;
+      }
+    }
+  }
+  if ((st = set_batch_workers(g, bestP, s)) != DG_OK) return st;
+  dg_tuning t{};
+  t.workers = g->Pb;
+  t.mode = bestc.mode;
+  t.d = bestc.d;
+  t.sweeps = best_sw;
+  t.seconds = best.med;
+  t.seconds_min = best.lo;
+  t.seconds_max = best.hi;
+  t.predicted_seconds = best.med;
+  t.candidates = evaluated;
+  t.graph_hash = g->hash;
+  t.sweep_variant = g->variant;
+  t.resident_vertices = DG_RESIDENT_AUTO;
+  t.repeats = kTuneRepeats;
+  t.default_seconds = def.med;
+  t.default_seconds_min = def.lo;
+  t.default_seconds_max = def.hi;
   *out = t;
   return DG_OK;
 }
@@ -1434,10 +1705,11 @@ dg_status dg_tune_cache_save(const char* path) {
   FILE* f = std::fopen(path, "w");
   if (!f) return fail(DG_ERR_INVALID_ARGUMENT, "cannot open %s for writing", path);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  std::fprintf(f, "# dg tuning cache: hash algo dtype tol src workers mode d sweeps seconds\n");
+  std::fprintf(f, "# dg tuning cache: hash algo dtype tol src workers mode d sweeps seconds variant resident\n");
   for (const auto& e : g_tune_cache)
-    std::fprintf(f, "%016llx %d %d %.17g %u %u %d %u %u %.9g\n", (unsigned long long)e.hash, e.algo, e.dtype, e.tol,
-                 e.src, e.t.workers, (int)e.t.mode, e.t.d, e.t.sweeps, e.t.seconds);
+    std::fprintf(f, "%016llx %d %d %.17g %u %u %d %u %u %.9g %u %u\n", (unsigned long long)e.hash, e.algo, e.dtype,
+                 e.tol, e.src, e.t.workers, (int)e.t.mode, e.t.d, e.t.sweeps, e.t.seconds, e.t.sweep_variant,
+                 e.t.resident_vertices);
   const bool ok = std::fclose(f) == 0;
   return ok ? DG_OK : fail(DG_ERR_INVALID_ARGUMENT, "writing %s failed", path);
 }
@@ -1454,9 +1726,10 @@ dg_status dg_tune_cache_load(const char* path) {
     unsigned long long h = 0;
     int algo = 0, dtype = 0, mode = 0;
     double tol = 0.0, secs = 0.0;
-    unsigned src = 0, workers = 0, d = 0, sweeps = 0;
-    if (std::sscanf(line, "%llx %d %d %lg %u %u %d %u %u %lg", &h, &algo, &dtype, &tol, &src, &workers, &mode, &d,
-                    &sweeps, &secs) != 10 ||
+    unsigned src = 0, workers = 0, d = 0, sweeps = 0, variant = DG_SWEEP_AUTO, res = DG_RESIDENT_AUTO;
+    const int got = std::sscanf(line, "%llx %d %d %lg %u %u %d %u %u %lg %u %u", &h, &algo, &dtype, &tol, &src,
+                                &workers, &mode, &d, &sweeps, &secs, &variant, &res);
+    if ((got != 10 && got != 12) || variant > DG_SWEEP_NARROW ||
         (algo != DG_ALGO_PAGERANK && algo != DG_ALGO_SSSP) || mode < DG_SYNC || mode > DG_DELAYED || workers == 0 ||
         (mode == DG_DELAYED && d == 0)) {
       ++bad;
@@ -1469,6 +1742,8 @@ dg_status dg_tune_cache_load(const char* path) {
     t.sweeps = sweeps;
     t.seconds = secs;
     t.graph_hash = h;
+    t.sweep_variant = variant;
+    t.resident_vertices = res;
     tune_put(TuneEntry{(uint64_t)h, algo, dtype, tol, src, t});
   }
   std::fclose(f);

@@ -52,6 +52,7 @@ struct dg_graph {
   bool has_w = false;
   uint32_t P = 0, T = 0, cus = 0, max_in_deg = 0, n_dangling = 0;
   uint32_t variant = 0;  // SweepVariant of the single-query sweeps
+  uint32_t variant0 = 0; // the variant chosen at creation
   uint32_t K = 0;          // sources stored in the compact region
   uint32_t max_block_v = 1;  // most vertices any worker owns
   // Partition of the same tiles for the batched kernels (dg_sssp_batch,
@@ -59,6 +60,8 @@ struct dg_graph {
   uint32_t Pb = 0, max_block_vb = 1;
   std::vector<uint32_t> tile_v_h, tile_e0_h;  // host copies: first vertex / first in-edge of each tile
   std::vector<uint32_t> work_t_h;             // host copy of work_t: first tile of each worker
+  std::vector<uint32_t> in_ptr_h;             // host copy of in_ptr (re-tiling by dg_graph_set_mapping)
+  uint32_t res_limit = 0xFFFFFFFFu;           // resident-table entries the sweeps may use (<= R)
   uint64_t hash = 0;                         // content hash of the in-edge form (tuning cache key)
   // Graph sets: the union of G graphs, with worker blocks aligned to graph
   // boundaries (graph i's workers are wseg[i] .. wseg[i+1]-1); G = 0 otherwise.

@@ -35,7 +35,7 @@ EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_
            "dg_error_bound",
            "dg_sssp", "dg_sssp_batch", "dg_ppr_batch", "dg_set_create", "dg_set_destroy", "dg_set_info_get",
            "dg_set_pagerank", "dg_set_sssp", "dg_graph_partition", "dg_access_matrix", "dg_graph_repartition",
-           "dg_tune", "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_server_create",
+           "dg_tune", "dg_tune_batch", "dg_graph_set_mapping", "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_server_create",
            "dg_server_destroy", "dg_server_submit", "dg_server_step", "dg_server_fetch", "dg_server_status_get",
            "dg_plan_create", "dg_plan_info_get", "dg_plan_arrays", "dg_plan_destroy", "dg_probe_gather", "dg_sssp_noalloc",
            "dg_status_str", "dg_last_error", "dg_version")
@@ -98,7 +98,10 @@ class dg_access_stats(C.Structure):
 class dg_tuning(C.Structure):
     _fields_ = [("workers", C.c_uint32), ("mode", C.c_int), ("d", C.c_uint32), ("sweeps", C.c_uint32),
                 ("seconds", C.c_double), ("predicted_seconds", C.c_double), ("candidates", C.c_uint32),
-                ("from_cache", C.c_uint32), ("graph_hash", C.c_uint64)]
+                ("from_cache", C.c_uint32), ("graph_hash", C.c_uint64), ("sweep_variant", C.c_uint32),
+                ("resident_vertices", C.c_uint32), ("repeats", C.c_uint32), ("reserved", C.c_uint32),
+                ("seconds_min", C.c_double), ("seconds_max", C.c_double), ("default_seconds", C.c_double),
+                ("default_seconds_min", C.c_double), ("default_seconds_max", C.c_double)]
 
 
 class dg_server_opts(C.Structure):
@@ -182,6 +185,9 @@ def _load():
         "dg_access_matrix": (C.c_int, [P, C.c_uint32, P, C.POINTER(dg_access_stats), P]),
         "dg_graph_repartition": (C.c_int, [P, C.c_uint32, P]),
         "dg_tune": (C.c_int, [P, C.c_int, C.c_int, C.c_double, C.c_uint32, C.c_uint32, C.POINTER(dg_tuning), P]),
+        "dg_tune_batch": (C.c_int, [P, C.c_int, C.c_int, C.c_double, P, C.c_uint32, C.c_uint32,
+                                    C.POINTER(dg_tuning), P]),
+        "dg_graph_set_mapping": (C.c_int, [P, C.c_uint32, C.c_uint32, C.c_uint32, P]),
         "dg_tune_cache_clear": (C.c_int, []),
         "dg_tune_cache_save": (C.c_int, [C.c_char_p]),
         "dg_tune_cache_load": (C.c_int, [C.c_char_p]),
@@ -370,6 +376,14 @@ def probe_gather(table_bytes, streamed=False, per_thread=256, workgroups=1024, s
     return sec.value, int(workgroups) * 256 * int(per_thread)
 
 
+def dg_tune_batch(g, algo, dtype, tol, sources, k, flags, out, stream):
+    return lib.dg_tune_batch(g, algo, dtype, tol, sources, k, flags, out, stream)
+
+
+def dg_graph_set_mapping(g, variant, resident, workers, stream):
+    return lib.dg_graph_set_mapping(g, variant, resident, workers, stream)
+
+
 def tune_cache_save(path):
     _check(dg_tune_cache_save(os.fsencode(path)))
 
@@ -480,6 +494,20 @@ class Stats:
 def _stats(s: dg_stats, converged: bool) -> Stats:
     return Stats(s.sweeps, s.workers, s.tile_vertices, s.commit_interval, s.residual, s.seconds,
                  s.edges_traversed, converged, s.err_bound, s.commits)
+
+
+VARIANT_NAMES = {1: "wide", 2: "wide_inflight", 3: "narrow"}
+
+
+def _tuning(t):
+    return {"workers": t.workers, "mode": MODE_NAMES[t.mode], "d": t.d, "sweeps": t.sweeps,
+            "seconds": t.seconds, "seconds_min": t.seconds_min, "seconds_max": t.seconds_max,
+            "predicted_seconds": t.predicted_seconds, "candidates": t.candidates,
+            "from_cache": bool(t.from_cache), "graph_hash": t.graph_hash,
+            "sweep_variant": VARIANT_NAMES.get(t.sweep_variant, "auto"),
+            "resident_vertices": t.resident_vertices, "repeats": t.repeats,
+            "default_seconds": t.default_seconds, "default_seconds_min": t.default_seconds_min,
+            "default_seconds_max": t.default_seconds_max}
 
 
 class Graph:
@@ -651,9 +679,21 @@ class Graph:
         flags = (0 if use_cache else DG_TUNE_NO_CACHE) | (DG_TUNE_KEEP_WORKERS if keep_workers else 0)
         _check(dg_tune(self._h, DG_ALGO_PAGERANK if algo == "pagerank" else DG_ALGO_SSSP, DTYPES[dtype],
                        float(tol), int(src), flags, C.byref(t), _stream_handle(stream)))
-        return {"workers": t.workers, "mode": MODE_NAMES[t.mode], "d": t.d, "sweeps": t.sweeps,
-                "seconds": t.seconds, "predicted_seconds": t.predicted_seconds, "candidates": t.candidates,
-                "from_cache": bool(t.from_cache), "graph_hash": t.graph_hash}
+        return _tuning(t)
+
+    def tune_batch(self, algo, sources, dtype="f32", tol=1e-6, stream=None):
+        """dg_tune_batch on a sample of sources ("sssp" or "ppr"); the graph
+        keeps the chosen batched partition.  Returns the choice as a dict."""
+        t = dg_tuning()
+        src = np.ascontiguousarray(sources, dtype=np.uint32)
+        _check(dg_tune_batch(self._h, DG_ALGO_PAGERANK if algo == "ppr" else DG_ALGO_SSSP, DTYPES[dtype], float(tol),
+                             _np_ptr(src), int(src.shape[0]), 0, C.byref(t), _stream_handle(stream)))
+        return _tuning(t)
+
+    def set_mapping(self, sweep_variant="auto", resident_vertices=DG_RESIDENT_AUTO, workers=0, stream=None):
+        """dg_graph_set_mapping: sweep variant, resident-table limit, workers."""
+        _check(dg_graph_set_mapping(self._h, SWEEP_VARIANTS[sweep_variant], int(resident_vertices), int(workers),
+                                    _stream_handle(stream)))
 
     def partition(self, stream=None):
         """First vertex of each worker's block: uint32 array [workers + 1]."""

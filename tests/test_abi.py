@@ -240,14 +240,18 @@ def test_tune_cache_roundtrip(dg, tmp_path):
     assert p.read_text().startswith("#")
     p.write_text("# comment\n"
                  "00000000deadbeef 0 0 1e-06 0 640 2 64 13 0.0065\n"
+                 "00000000deadbee0 1 0 0 5 256 1 1 12 0.0043 3 16384\n"
                  "not a valid line\n")
     assert dg.dg_tune_cache_load(os.fsencode(str(p))) == dg.DG_ERR_INVALID_ARGUMENT
     assert "1 malformed" in dg.last_error()
     q = tmp_path / "again.txt"
     dg.tune_cache_save(q)
-    lines = [ln for ln in q.read_text().splitlines() if not ln.startswith("#")]
-    assert len(lines) == 1 and lines[0].split()[:8] == ["00000000deadbeef", "0", "0", "9.9999999999999995e-07",
+    lines = sorted(ln for ln in q.read_text().splitlines() if not ln.startswith("#"))
+    assert len(lines) == 2 and lines[1].split()[:8] == ["00000000deadbeef", "0", "0", "9.9999999999999995e-07",
                                                         "0", "640", "2", "64"]
+    # a line without the mapping columns loads with the automatic mapping; one with them keeps it
+    assert lines[1].split()[10:] == ["0", str(0xFFFFFFFF)]
+    assert lines[0].split()[10:] == ["3", "16384"]
     dg.tune_cache_clear()
     dg.tune_cache_save(q)
     assert [ln for ln in q.read_text().splitlines() if not ln.startswith("#")] == []
