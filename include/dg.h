@@ -439,6 +439,33 @@ dg_status dg_graph_repartition(dg_graph* g, uint32_t workers, void* hip_stream);
 dg_status dg_graph_set_mapping(dg_graph* g, uint32_t sweep_variant, uint32_t resident_vertices, uint32_t workers,
                                void* hip_stream);
 
+/* Captured launches (a form beyond the paper, which runs one sweep after
+ * another on the CPU; here for graphs whose sweeps are short enough that
+ * launching them costs time).  chunk_sweeps = 0 (the default) launches every
+ * sweep on its own; 1..64 records chunks of that many consecutive sweeps into
+ * HIP graphs and replays them with one launch each.  It applies to every
+ * later dg_pagerank, dg_ppr, dg_sssp, dg_sssp_batch and dg_ppr_batch call on
+ * the graph (and to dg_set_* through dg_set_set_capture).
+ *  - Chunk j (sweeps j*chunk_sweeps ..) is recorded the first time a call of
+ *    the same shape reaches it and kept for later calls of that shape: same
+ *    entry point, mode, d, dtype, tol, damping, max_sweeps, restart vertex
+ *    and the same device buffers (the graph's own workspace, reused by the
+ *    single-query calls; the batched calls allocate theirs per call and are
+ *    recorded again when an address differs).  At most 256 chunks are kept
+ *    per shape; a call beyond them launches its later sweeps one by one.
+ *    A call of another shape replaces the recorded chunks.
+ *  - Results are those of the eager launches: the replayed kernels and
+ *    arguments are the same (bit for bit in synchronous mode).  Sweeps after
+ *    the converging one in its chunk exit at once on the device; stats.seconds
+ *    runs to the end of that chunk.
+ *  - The recorded graphs hold device memory until the shape changes, the
+ *    setting changes, dg_graph_set_mapping / dg_graph_repartition is called,
+ *    or the graph is destroyed.
+ * Errors: DG_ERR_INVALID_ARGUMENT for a NULL graph or chunk_sweeps > 64;
+ * recording failures surface as DG_ERR_DEVICE from the sweep call.  Must not
+ * overlap a sweep call on the same graph. */
+dg_status dg_graph_set_capture(dg_graph* g, uint32_t chunk_sweeps);
+
 /* Autotuner (a form beyond the paper, which leaves the choice of delta to
  * future work and shows that it depends on topology, thread count and update
  * density: sections IV and V).  Chooses, for one algorithm on one graph:
@@ -582,6 +609,10 @@ dg_status dg_set_create(uint32_t count, const dg_graph_desc* graphs, const dg_se
                         dg_set** out);
 dg_status dg_set_destroy(dg_set* s);
 dg_status dg_set_info_get(const dg_set* s, dg_set_info* info);
+/* dg_graph_set_capture for the set's union graph: later dg_set_pagerank and
+ * dg_set_sssp calls run as recorded chunks of chunk_sweeps sweeps (0 = one
+ * launch per sweep).  Errors as dg_graph_set_capture, or a NULL set. */
+dg_status dg_set_set_capture(dg_set* s, uint32_t chunk_sweeps);
 
 /* PageRank of every graph of the set (as dg_pagerank, per graph).  All
  * graphs are swept together; each graph's dangling mass is spread over its

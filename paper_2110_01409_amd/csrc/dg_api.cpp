@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -11,6 +12,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "dg.h"
@@ -191,6 +193,11 @@ using dg::host::staging;
 namespace {
 
 void release_all(dg_graph* g) {
+  dg::host::drop_captures(g);
+  if (g->cap_stream) {
+    (void)hipStreamDestroy(g->cap_stream);
+    g->cap_stream = nullptr;
+  }
   if (g->events) {
     (void)hipEventDestroy(g->ev_start);
     for (auto& e : g->ev_sweep) (void)hipEventDestroy(e);
@@ -333,61 +340,200 @@ dg_status certify(dg_graph* g, const double* y, double damping, uint32_t psrc, c
   return DG_OK;
 }
 
-// Convergence loop shared by every entry point.  launch(k) enqueues sweep k,
-// which writes the E stopping values of its row k+1 to the device state and,
-// with system-scope stores, to the same row (`row` bytes) of the mapped host
-// buffer `host`; rows are zeroed here before their sweep is enqueued, so a
-// value a sweep does not write reads as 0, as on the device.  done(row, k)
-// tells whether sweep k met the stopping rule.  The host waits for each
-// sweep's event in turn and keeps up to `lookahead` sweeps queued beyond it,
-// enough to cover its own reaction time at the measured sweep time, so the
-// device does not wait for the host and at most that many sweeps are queued
-// after the converging one (each exits at once on the device's own check).
+// Bytes that identify a call shape for captured launches: every value the
+// call's launch(k, stream) reads besides k and the stream.
+using CaptureKey = std::vector<unsigned char>;
+
+template <typename T>
+void key_add(CaptureKey& key, const T& v) {
+  const unsigned char* p = reinterpret_cast<const unsigned char*>(&v);
+  key.insert(key.end(), p, p + sizeof(T));
+}
+
+}  // namespace
+
+namespace dg {
+namespace host {
+
+void drop_captures(dg_graph* g) {
+  for (hipGraphExec_t& e : g->cap_exec)
+    if (e) (void)hipGraphExecDestroy(e);
+  g->cap_exec.clear();
+  g->cap_key.clear();
+}
+
+}  // namespace host
+}  // namespace dg
+
+namespace {
+
+using dg::host::drop_captures;
+using dg::host::kMaxCaptureChunk;
+using dg::host::kMaxCapturedChunks;
+
+// Records sweeps k0 .. k1-1, as launch(k, stream) issues them, into a HIP
+// graph on the graph's capture stream and instantiates it.
+template <typename Launch>
+dg_status record_chunk(dg_graph* g, uint32_t k0, uint32_t k1, Launch& launch, hipGraphExec_t* out) {
+  if (!g->cap_stream) DG_HIP(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+  DG_HIP(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeRelaxed));
+  hipError_t le = hipSuccess;
+  for (uint32_t k = k0; k < k1 && le == hipSuccess; ++k) le = launch(k, g->cap_stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t ce = hipStreamEndCapture(g->cap_stream, &graph);
+  if (le != hipSuccess || ce != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return fail(DG_ERR_DEVICE, "recording sweeps %u..%u failed: %s", k0, k1 - 1,
+                hipGetErrorString(le != hipSuccess ? le : ce));
+  }
+  const hipError_t ie = hipGraphInstantiateWithFlags(out, graph, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) {
+    *out = nullptr;
+    (void)hipGetLastError();
+    return fail(DG_ERR_DEVICE, "instantiating sweeps %u..%u failed: %s", k0, k1 - 1, hipGetErrorString(ie));
+  }
+  return DG_OK;
+}
+
+// Waits for the event after recorded chunk j (sweeps k0..k1-1).  A wait
+// longer than 20 s prints one line naming the chunk to stderr, then goes on
+// waiting: a chunk runs at most 64 sweeps, so this only shows on a stalled
+// device or runtime.
+dg_status wait_chunk(hipEvent_t e, uint32_t k0, uint32_t k1) {
+  const auto t0 = std::chrono::steady_clock::now();
+  bool warned = false;
+  for (;;) {
+    const hipError_t q = hipEventQuery(e);
+    if (q == hipSuccess) return DG_OK;
+    if (q != hipErrorNotReady) {
+      (void)hipGetLastError();
+      return fail(DG_ERR_DEVICE, "waiting for recorded sweeps %u..%u failed: %s", k0, k1 - 1, hipGetErrorString(q));
+    }
+    const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (!warned && el > 20.0) {
+      std::fprintf(stderr, "dg: recorded sweeps %u..%u not complete after %.0f s\n", k0, k1 - 1, el);
+      std::fflush(stderr);
+      warned = true;
+    }
+    if (el > 1e-3) std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+}
+
+// Convergence loop shared by every entry point.  launch(k, stream) enqueues
+// sweep k, which writes the E stopping values of its row k+1 to the device
+// state and, with system-scope stores, to the same row (`row` bytes) of the
+// mapped host buffer `host`; rows are zeroed here before their sweep is
+// enqueued, so a value a sweep does not write reads as 0, as on the device.
+// done(row, k) tells whether sweep k met the stopping rule; it is called for
+// k = 0, 1, ... in order until it says yes.
+//
+// Launched one by one (the default), the host waits for each sweep's event in
+// turn and keeps up to `lookahead` sweeps queued beyond it, enough to cover
+// its own reaction time at the measured sweep time, so the device does not
+// wait for the host and at most that many sweeps are queued after the
+// converging one (each exits at once on the device's own check).
+//
+// With captured launches (g->capture > 0 and a key), sweeps go in chunks of
+// g->capture: chunk j is recorded once per call shape, on first use, and
+// replayed with one hipGraphLaunch; two chunks are queued while the host
+// reads the rows of the older one.  The replayed kernels are the ones the
+// eager path launches, with the same arguments, so results do not change.
 template <typename Launch, typename Done>
 dg_status drive(dg_graph* g, uint32_t max_sweeps, hipStream_t s, size_t row, unsigned char* host, Launch launch,
-                Done done, uint32_t& sweeps, double& seconds, bool& converged) {
+                Done done, uint32_t& sweeps, double& seconds, bool& converged, const CaptureKey* key = nullptr) {
   static_assert(kMaxLookahead + 1 < kEventRing, "a queued sweep's event slot must not be reused before it is read");
-  DG_HIP(hipEventRecord(g->ev_start, s));
-  uint32_t look = std::max(1u, std::min(g->lookahead, kMaxLookahead));
-  uint32_t next = 0;  // next sweep to enqueue
-  auto enqueue = [&]() -> dg_status {
-    std::memset(host + (size_t)(next + 1) * row, 0, row);
-    const hipError_t e = launch(next);
-    if (e != hipSuccess) return fail(DG_ERR_DEVICE, "sweep launch failed: %s", hipGetErrorString(e));
-    DG_HIP(hipEventRecord(g->ev_sweep[next % kEventRing], s));
-    ++next;
-    return DG_OK;
-  };
   converged = false;
   sweeps = 0;
   dg_status st = DG_OK;
-  while (next < max_sweeps && next < 1 + look)
-    if ((st = enqueue()) != DG_OK) return st;
   int found = -1;
-  for (uint32_t k = 0; k < next; ++k) {
-    DG_HIP(hipEventSynchronize(g->ev_sweep[k % kEventRing]));
-    if (k == 0) {
-      // The first sweep's time (from the stream reaching it) sets how far
-      // ahead to queue, here and in the graph's next call.
-      float ms = 0.f;
-      DG_HIP(hipEventElapsedTime(&ms, g->ev_start, g->ev_sweep[0]));
-      const double us = std::max(1.0, (double)ms * 1e3);
-      look = (uint32_t)std::min<double>(kMaxLookahead, std::max(2.0, std::ceil(kHostReactUs / us) + 1.0));
-      g->lookahead = look;
+  uint32_t last_event = 0;  // event slot of the last sweep run (or of its chunk)
+  DG_HIP(hipEventRecord(g->ev_start, s));
+  if (key && g->capture) {
+    const uint32_t C = g->capture;
+    if (g->cap_key != *key) {
+      drop_captures(g);
+      g->cap_key = *key;
     }
-    if (done(host + (size_t)(k + 1) * row, k)) {
-      found = (int)k;
-      break;
-    }
-    while (next < max_sweeps && next < k + 2 + look)
+    const uint32_t nchunks = (uint32_t)(((uint64_t)max_sweeps + C - 1) / C);
+    uint32_t launched = 0;
+    auto enqueue = [&]() -> dg_status {
+      const uint32_t j = launched;
+      const uint32_t k0 = j * C, k1 = std::min(k0 + C, max_sweeps);
+      std::memset(host + (size_t)(k0 + 1) * row, 0, (size_t)(k1 - k0) * row);
+      if (j < kMaxCapturedChunks) {
+        if (g->cap_exec.size() <= j) g->cap_exec.resize(j + 1, nullptr);
+        if (!g->cap_exec[j]) {
+          const dg_status rs = record_chunk(g, k0, k1, launch, &g->cap_exec[j]);
+          if (rs != DG_OK) return rs;
+        }
+        DG_HIP(hipGraphLaunch(g->cap_exec[j], s));
+      } else {
+        for (uint32_t k = k0; k < k1; ++k) {
+          const hipError_t e = launch(k, s);
+          if (e != hipSuccess) return fail(DG_ERR_DEVICE, "sweep launch failed: %s", hipGetErrorString(e));
+        }
+      }
+      DG_HIP(hipEventRecord(g->ev_sweep[j % kEventRing], s));
+      ++launched;
+      return DG_OK;
+    };
+    while (launched < nchunks && launched < 2)
       if ((st = enqueue()) != DG_OK) return st;
+    for (uint32_t j = 0; j < launched && found < 0; ++j) {
+      const uint32_t k1 = std::min((j + 1) * C, max_sweeps);
+      if ((st = wait_chunk(g->ev_sweep[j % kEventRing], j * C, k1)) != DG_OK) return st;
+      last_event = j % kEventRing;
+      for (uint32_t k = j * C; k < k1; ++k)
+        if (done(host + (size_t)(k + 1) * row, k)) {
+          found = (int)k;
+          break;
+        }
+      if (found < 0 && launched < nchunks)
+        if ((st = enqueue()) != DG_OK) return st;
+    }
+  } else {
+    uint32_t look = std::max(1u, std::min(g->lookahead, kMaxLookahead));
+    uint32_t next = 0;  // next sweep to enqueue
+    auto enqueue = [&]() -> dg_status {
+      std::memset(host + (size_t)(next + 1) * row, 0, row);
+      const hipError_t e = launch(next, s);
+      if (e != hipSuccess) return fail(DG_ERR_DEVICE, "sweep launch failed: %s", hipGetErrorString(e));
+      DG_HIP(hipEventRecord(g->ev_sweep[next % kEventRing], s));
+      ++next;
+      return DG_OK;
+    };
+    while (next < max_sweeps && next < 1 + look)
+      if ((st = enqueue()) != DG_OK) return st;
+    for (uint32_t k = 0; k < next; ++k) {
+      DG_HIP(hipEventSynchronize(g->ev_sweep[k % kEventRing]));
+      last_event = k % kEventRing;
+      if (k == 0) {
+        // The first sweep's time (from the stream reaching it) sets how far
+        // ahead to queue, here and in the graph's next call.
+        float ms = 0.f;
+        DG_HIP(hipEventElapsedTime(&ms, g->ev_start, g->ev_sweep[0]));
+        const double us = std::max(1.0, (double)ms * 1e3);
+        look = (uint32_t)std::min<double>(kMaxLookahead, std::max(2.0, std::ceil(kHostReactUs / us) + 1.0));
+        g->lookahead = look;
+      }
+      if (done(host + (size_t)(k + 1) * row, k)) {
+        found = (int)k;
+        break;
+      }
+      while (next < max_sweeps && next < k + 2 + look)
+        if ((st = enqueue()) != DG_OK) return st;
+    }
   }
   DG_HIP(hipStreamSynchronize(s));
   const uint32_t last = found >= 0 ? (uint32_t)found : max_sweeps - 1;
   converged = found >= 0;
   sweeps = last + 1;
+  // Time to the event after the converging sweep (captured: after its chunk,
+  // whose later sweeps exit at once).
   float ms = 0.f;
-  DG_HIP(hipEventElapsedTime(&ms, g->ev_start, g->ev_sweep[last % kEventRing]));
+  DG_HIP(hipEventElapsedTime(&ms, g->ev_start, g->ev_sweep[last_event]));
   seconds = ms * 1e-3;
   return DG_OK;
 }
@@ -861,6 +1007,7 @@ dg_status pr_run(dg_graph* g, uint32_t psrc, double damping, double tol, dg_mode
   if (mode == DG_DELAYED_LOCAL) DG_HIP(launch_by_vertex(f64, c0, g->cpos, g->n, g->vals[2], s));
 
   PrArgs a;
+  std::memset(&a, 0, sizeof a);  // padding too: the bytes identify a captured call shape
   a.g = topo(g);
   a.st = sst;
   a.x = x;
@@ -881,7 +1028,15 @@ dg_status pr_run(dg_graph* g, uint32_t psrc, double damping, double tol, dg_mode
     DG_HIP(launch_fill_u32(g->gsweeps, g->G, 0u, s));
     DG_HIP(hipMemcpyAsync(g->gdang, g->gdang0.data(), (size_t)g->G * sizeof(double), hipMemcpyHostToDevice, s));
   }
-  auto launch = [&](uint32_t k) {
+  CaptureKey key;
+  key_add(key, 1);
+  key_add(key, (int)mode);
+  key_add(key, f64);
+  key_add(key, max_sweeps);
+  key_add(key, c0);
+  key_add(key, c1);
+  key_add(key, a);
+  auto launch = [&](uint32_t k, hipStream_t q) {
     if (mode == DG_SYNC) {
       a.cin = (k & 1) ? c1 : c0;
       a.cout = (k & 1) ? c0 : c1;
@@ -890,7 +1045,7 @@ dg_status pr_run(dg_graph* g, uint32_t psrc, double damping, double tol, dg_mode
       a.cout = c0;
     }
     a.k = k;
-    return launch_pr_sweep((int)mode, f64, a, s);
+    return launch_pr_sweep((int)mode, f64, a, q);
   };
   auto done = [&](const unsigned char* p, uint32_t) {
     double r;
@@ -901,7 +1056,7 @@ dg_status pr_run(dg_graph* g, uint32_t psrc, double damping, double tol, dg_mode
   double secs = 0.0, resid = 0.0;
   bool conv = false;
   unsigned char* poll = static_cast<unsigned char*>(g->host_poll);
-  if ((st = drive(g, max_sweeps, s, sizeof(double), poll, launch, done, sweeps, secs, conv)) != DG_OK)
+  if ((st = drive(g, max_sweeps, s, sizeof(double), poll, launch, done, sweeps, secs, conv, &key)) != DG_OK)
     return st;
   std::memcpy(&resid, poll + (size_t)sweeps * sizeof(double), sizeof(double));
   resid = std::fabs(resid);  // negative: a float32 personalised sweep stopped at its rounding floor
@@ -974,6 +1129,7 @@ dg_status sssp_run(dg_graph* g, uint32_t src, const uint32_t* more_src, uint32_t
     DG_HIP(launch_bf_gather(b0, g->cpos, g->n, static_cast<uint32_t*>(g->vals[2]), s));
 
   BfArgs a;
+  std::memset(&a, 0, sizeof a);  // padding too: the bytes identify a captured call shape
   a.g = topo(g);
   a.st = sst;
   a.d = d_eff;
@@ -985,7 +1141,14 @@ dg_status sssp_run(dg_graph* g, uint32_t src, const uint32_t* more_src, uint32_t
   a.G = g->G;
   a.gsweeps = g->gsweeps;
   if (g->G) DG_HIP(launch_fill_u32(g->gsweeps, g->G, 0u, s));
-  auto launch = [&](uint32_t k) {
+  CaptureKey key;
+  key_add(key, 2);
+  key_add(key, (int)mode);
+  key_add(key, max_sweeps);
+  key_add(key, b0);
+  key_add(key, b1);
+  key_add(key, a);
+  auto launch = [&](uint32_t k, hipStream_t q) {
     if (mode == DG_SYNC) {
       a.din = (k & 1) ? b1 : b0;
       a.dout = (k & 1) ? b0 : b1;
@@ -994,7 +1157,7 @@ dg_status sssp_run(dg_graph* g, uint32_t src, const uint32_t* more_src, uint32_t
       a.dout = b0;
     }
     a.k = k;
-    return launch_bf_sweep((int)mode, a, s);
+    return launch_bf_sweep((int)mode, a, q);
   };
   auto done = [&](const unsigned char* p, uint32_t) {
     uint32_t c;
@@ -1005,7 +1168,7 @@ dg_status sssp_run(dg_graph* g, uint32_t src, const uint32_t* more_src, uint32_t
   double secs = 0.0;
   bool conv = false;
   unsigned char* poll = static_cast<unsigned char*>(g->host_poll);
-  if ((st = drive(g, max_sweeps, s, sizeof(uint32_t), poll, launch, done, sweeps, secs, conv)) != DG_OK)
+  if ((st = drive(g, max_sweeps, s, sizeof(uint32_t), poll, launch, done, sweeps, secs, conv, &key)) != DG_OK)
     return st;
   // The last executed sweep k = sweeps-1 wrote buffer (k+1) % 2 in sync mode.
   const uint32_t* res = (mode == DG_SYNC && (sweeps & 1)) ? b1 : b0;
@@ -1092,7 +1255,14 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
   a.shadow = sh;
   a.d = d_eff;
   a.NB = NB;
-  auto launch = [&](uint32_t kk) {
+  CaptureKey key;
+  key_add(key, 3);
+  key_add(key, (int)mode);
+  key_add(key, max_sweeps);
+  key_add(key, b0);
+  key_add(key, b1);
+  key_add(key, a);
+  auto launch = [&](uint32_t kk, hipStream_t q) {
     if (mode == DG_SYNC) {
       a.din = (kk & 1) ? b1 : b0;
       a.dout = (kk & 1) ? b0 : b1;
@@ -1101,7 +1271,7 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
       a.dout = b0;
     }
     a.k = kk;
-    return launch_mbf_sweep((int)mode, a, s);
+    return launch_mbf_sweep((int)mode, a, q);
   };
   std::vector<uint32_t> bsweeps(NB, 0);
   auto done = [&](const unsigned char* p, uint32_t kk) {
@@ -1118,7 +1288,7 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
   double secs = 0.0;
   bool conv = false;
   if ((st = drive(g, max_sweeps, s, (size_t)NB * 4, static_cast<unsigned char*>(poll.p), launch, done, sweeps, secs,
-                  conv)) != DG_OK)
+                  conv, &key)) != DG_OK)
     return st;
   // The buffer sweep `sweeps-1` wrote holds every batch's final distances:
   // converged batches skip later sweeps, and sync sweeps alternate buffers.
@@ -1228,7 +1398,15 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   a.nq = k;
   a.d = d_eff;
   a.NB = NB;
-  auto launch = [&](uint32_t kk) {
+  CaptureKey key;
+  key_add(key, 4);
+  key_add(key, (int)mode);
+  key_add(key, f64);
+  key_add(key, max_sweeps);
+  key_add(key, c0);
+  key_add(key, c1);
+  key_add(key, a);
+  auto launch = [&](uint32_t kk, hipStream_t q) {
     if (mode == DG_SYNC) {
       a.cin = (kk & 1) ? c1 : c0;
       a.cout = (kk & 1) ? c0 : c1;
@@ -1237,7 +1415,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
       a.cout = c0;
     }
     a.k = kk;
-    return launch_mppr_sweep((int)mode, f64, a, s);
+    return launch_mppr_sweep((int)mode, f64, a, q);
   };
   std::vector<uint32_t> bsweeps(NB, 0);
   double last_r = 0.0;
@@ -1258,7 +1436,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   double secs = 0.0;
   bool conv = false;
   if ((st = drive(g, max_sweeps, s, (size_t)NB * 8, static_cast<unsigned char*>(poll.p), launch, done, sweeps, secs,
-                  conv)) != DG_OK)
+                  conv, &key)) != DG_OK)
     return st;
   DG_HIP(launch_mppr_out(f64, x, qpart, qsum, g->n, k, NB, outd, s));
   if (!out_on_device) DG_HIP(hipMemcpyAsync(out_scores, outd, (size_t)k * g->n * 8, hipMemcpyDeviceToHost, s));
@@ -1313,6 +1491,17 @@ dg_status dg_graph_repartition(dg_graph* g, uint32_t workers, void* hip_stream) 
   }
   g->P = P;
   g->max_block_v = mbv;
+  dg::host::drop_captures(g);
+  return DG_OK;
+}
+
+dg_status dg_graph_set_capture(dg_graph* g, uint32_t chunk_sweeps) {
+  g_last_error.clear();
+  if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (chunk_sweeps > kMaxCaptureChunk)
+    return fail(DG_ERR_INVALID_ARGUMENT, "chunk_sweeps = %u beyond %u", chunk_sweeps, kMaxCaptureChunk);
+  if (chunk_sweeps != g->capture) dg::host::drop_captures(g);
+  g->capture = chunk_sweeps;
   return DG_OK;
 }
 
@@ -1367,6 +1556,7 @@ dg_status dg_graph_set_mapping(dg_graph* g, uint32_t sweep_variant, uint32_t res
   }
   g->variant = want;
   g->res_limit = resident_vertices == DG_RESIDENT_AUTO ? 0xFFFFFFFFu : resident_vertices;
+  dg::host::drop_captures(g);
   return dg_graph_repartition(g, workers, hip_stream);
 }
 

@@ -42,6 +42,11 @@ constexpr uint32_t kSetWorkersPerCU = 5;
 // scale 22 (4680 tiles).
 constexpr uint64_t kNarrowBelow = 2;
 constexpr uint64_t kInFlightUpTo = 8;
+// Captured launches (dg_graph_set_capture): at most kMaxCaptureChunk sweeps
+// per recorded chunk, and at most kMaxCapturedChunks chunks recorded per call
+// shape; a call that runs longer launches its later sweeps one by one.
+constexpr uint32_t kMaxCaptureChunk = 64;
+constexpr uint32_t kMaxCapturedChunks = 256;
 
 }  // namespace host
 }  // namespace dg
@@ -104,11 +109,23 @@ struct dg_graph {
   hipEvent_t ev_start = nullptr;
   hipEvent_t ev_sweep[dg::host::kEventRing] = {};
   bool events = false;
+  // Captured launches: 0 = every sweep launched on its own; else chunks of
+  // `capture` consecutive sweeps, each recorded once into a HIP graph (on
+  // cap_stream, which holds no other work) and replayed on the call's stream.
+  // cap_exec[j] holds sweeps j*capture .. j*capture+capture-1 of calls whose
+  // launch arguments (pointers, sizes, mode, limits) are the bytes cap_key.
+  uint32_t capture = 0;
+  hipStream_t cap_stream = nullptr;
+  std::vector<unsigned char> cap_key;
+  std::vector<hipGraphExec_t> cap_exec;
 };
 
 namespace dg {
 namespace host {
 
+// Destroys the graph's recorded chunks (their key no longer matches, or the
+// capture length or the mapping changed).
+void drop_captures(dg_graph* g);
 // Device allocations through the graph's allocator hooks (tracked, freed with
 // the graph).
 void* dev_alloc(dg_graph* g, size_t bytes, hipStream_t s);

@@ -179,6 +179,12 @@ dg_status dg_set_info_get(const dg_set* s, dg_set_info* info) {
   return DG_OK;
 }
 
+dg_status dg_set_set_capture(dg_set* s, uint32_t chunk_sweeps) {
+  g_last_error.clear();
+  if (!s) return fail(DG_ERR_INVALID_ARGUMENT, "set is NULL");
+  return dg_graph_set_capture(s->g, chunk_sweeps);
+}
+
 dg_status dg_set_pagerank(dg_set* s, double damping, double tol, dg_mode mode, uint32_t d, dg_dtype dtype,
                           uint32_t max_sweeps, uint32_t flags, double* out_scores, int out_on_device,
                           uint32_t* out_sweeps, dg_stats* stats, void* hip_stream) {

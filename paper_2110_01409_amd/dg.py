@@ -35,7 +35,8 @@ EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_
            "dg_error_bound",
            "dg_sssp", "dg_sssp_batch", "dg_ppr_batch", "dg_set_create", "dg_set_destroy", "dg_set_info_get",
            "dg_set_pagerank", "dg_set_sssp", "dg_graph_partition", "dg_access_matrix", "dg_graph_repartition",
-           "dg_tune", "dg_tune_batch", "dg_graph_set_mapping", "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_server_create",
+           "dg_tune", "dg_tune_batch", "dg_graph_set_mapping", "dg_graph_set_capture", "dg_set_set_capture",
+           "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_server_create",
            "dg_server_destroy", "dg_server_submit", "dg_server_step", "dg_server_fetch", "dg_server_status_get",
            "dg_plan_create", "dg_plan_info_get", "dg_plan_arrays", "dg_plan_destroy", "dg_probe_gather", "dg_sssp_noalloc",
            "dg_status_str", "dg_last_error", "dg_version")
@@ -188,6 +189,8 @@ def _load():
         "dg_tune_batch": (C.c_int, [P, C.c_int, C.c_int, C.c_double, P, C.c_uint32, C.c_uint32,
                                     C.POINTER(dg_tuning), P]),
         "dg_graph_set_mapping": (C.c_int, [P, C.c_uint32, C.c_uint32, C.c_uint32, P]),
+        "dg_graph_set_capture": (C.c_int, [P, C.c_uint32]),
+        "dg_set_set_capture": (C.c_int, [P, C.c_uint32]),
         "dg_tune_cache_clear": (C.c_int, []),
         "dg_tune_cache_save": (C.c_int, [C.c_char_p]),
         "dg_tune_cache_load": (C.c_int, [C.c_char_p]),
@@ -382,6 +385,14 @@ def dg_tune_batch(g, algo, dtype, tol, sources, k, flags, out, stream):
 
 def dg_graph_set_mapping(g, variant, resident, workers, stream):
     return lib.dg_graph_set_mapping(g, variant, resident, workers, stream)
+
+
+def dg_graph_set_capture(g, chunk_sweeps):
+    return lib.dg_graph_set_capture(g, chunk_sweeps)
+
+
+def dg_set_set_capture(s, chunk_sweeps):
+    return lib.dg_set_set_capture(s, chunk_sweeps)
 
 
 def tune_cache_save(path):
@@ -695,6 +706,11 @@ class Graph:
         _check(dg_graph_set_mapping(self._h, SWEEP_VARIANTS[sweep_variant], int(resident_vertices), int(workers),
                                     _stream_handle(stream)))
 
+    def set_capture(self, chunk_sweeps):
+        """dg_graph_set_capture: replay recorded chunks of this many sweeps
+        (0: launch every sweep on its own)."""
+        _check(dg_graph_set_capture(self._h, int(chunk_sweeps)))
+
     def partition(self, stream=None):
         """First vertex of each worker's block: uint32 array [workers + 1]."""
         out = np.zeros(self.info().workers + 1, np.uint32)
@@ -771,6 +787,11 @@ class GraphSet:
 
     def split(self, t):
         return [t[self.offsets[i]:self.offsets[i + 1]] for i in range(len(self.sizes))]
+
+    def set_capture(self, chunk_sweeps):
+        """dg_set_set_capture: replay recorded chunks of this many sweeps
+        (0: launch every sweep on its own)."""
+        _check(dg_set_set_capture(self._h, int(chunk_sweeps)))
 
     def pagerank(self, damping=0.85, tol=1e-6, mode="delayed", d=64, dtype="f64", max_sweeps=10_000, stream=None,
                  allow_not_converged=False):
