@@ -189,6 +189,76 @@ def set_bench(dg, gg):
     return res
 
 
+def capture_bench(dg, gg, chunk=16, reps=5):
+    """Captured launches (chunks of `chunk` sweeps recorded into HIP graphs
+    and replayed) against one launch per sweep, on work whose sweeps are
+    short enough for launching to matter, and on one where they are not.
+    Each entry: best of `reps` calls after a warm-up call (which also records
+    the chunks), device milliseconds from the call's first sweep to the end
+    of the converging sweep's chunk (stats.seconds) and host wall
+    milliseconds per call."""
+    import torch
+
+    def timed(call):
+        call()
+        dev, wall = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = call()
+            torch.cuda.synchronize()
+            wall.append(time.perf_counter() - t0)
+            dev.append(st.seconds)
+        return min(dev), min(wall), st.sweeps
+
+    def compare(name, obj, call):
+        row = {}
+        for label, c in (("eager", 0), ("captured", chunk)):
+            obj.set_capture(c)
+            d, w, sw = timed(call)
+            row[label] = {"device_ms": round(d * 1e3, 4), "wall_ms": round(w * 1e3, 4), "sweeps": int(sw)}
+        obj.set_capture(0)
+        row["device_speedup"] = round(row["eager"]["device_ms"] / row["captured"]["device_ms"], 3)
+        row["wall_speedup"] = round(row["eager"]["wall_ms"] / row["captured"]["wall_ms"], 3)
+        log(f"captured launches, {name}: device {row['eager']['device_ms']:.3f} -> "
+            f"{row['captured']['device_ms']:.3f} ms, wall {row['eager']['wall_ms']:.3f} -> "
+            f"{row['captured']['wall_ms']:.3f} ms ({row['captured']['sweeps']} sweeps)")
+        return row
+
+    res = {"chunk_sweeps": chunk, "repeats": reps}
+    rng = np.random.default_rng(64)
+    small = []
+    for i in range(64):
+        if i % 2 == 0:
+            small.append(gg.rmat(int(rng.integers(8, 14)), seed=200 + i))
+        else:
+            small.append(gg.erdos_renyi(int(rng.integers(500, 5000)), float(rng.integers(8, 33)), seed=200 + i))
+    src = np.array([int(rng.integers(0, x.n)) for x in small], np.uint32)
+    S = dg.GraphSet(small)
+    res["set64_small"] = {
+        "mix": "32 R-MAT (scales 8-13) + 32 G(n, m) (n 500-5000, avg degree 8-32)",
+        "sssp_async": compare("64 small graphs, SSSP async", S, lambda: S.sssp(src, mode="async")[2]),
+        "pagerank_f64_delayed_d64_tol1e-8": compare(
+            "64 small graphs, PageRank f64", S,
+            lambda: S.pagerank(tol=1e-8, mode="delayed", d=64, dtype="f64")[2]),
+    }
+    S.close()
+    g16 = gg.rmat(16, seed=16)
+    bsrc = gg.pick_sources(g16, 256, seed=17)
+    s16 = int(gg.pick_sources(g16, 1, seed=16)[0])
+    G16 = dg.Graph.from_csr(g16)
+    res["rmat16"] = {
+        "pagerank_f32_delayed_d64_tol1e-6": compare(
+            "RMAT-16 PageRank f32", G16, lambda: G16.pagerank(tol=1e-6, mode="delayed", d=64, dtype="f32")[1]),
+        "sssp_delayed_d64": compare("RMAT-16 SSSP", G16, lambda: G16.sssp(s16, mode="delayed", d=64)[1]),
+        "ppr_batch256_f32_async": compare(
+            "RMAT-16 batched PPR x256", G16,
+            lambda: G16.ppr_batch(bsrc, tol=1e-6, mode="async", dtype="f32")[1]),
+    }
+    G16.close()
+    return res
+
+
 def serve_bench(dg, gg, G22, g22, args):
     """Serving loop under load: 8 resident R-MAT graphs (scales 16-21 plus the
     workload graph), requests half SSSP from a random source and half PPR
@@ -301,6 +371,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-set", action="store_true")
+    ap.add_argument("--no-capture", action="store_true", help="skip the captured-against-eager launch leg")
+    ap.add_argument("--capture-only", action="store_true", help="only run the captured-against-eager launch leg")
     ap.add_argument("--serve-requests", type=int, default=2048)
     ap.add_argument("--serve-budget-gib", type=int, default=12, help="batch-state budget of the serving leg")
     ap.add_argument("--batch-queries", type=int, default=256)
@@ -319,7 +391,8 @@ def main():
         sys.exit(2)
 
     orc_future = None
-    if not (args.no_cpu_baseline or args.copy_calibration or args.gather_ceiling or args.sweeps_only):
+    if not (args.no_cpu_baseline or args.copy_calibration or args.gather_ceiling or args.sweeps_only
+            or args.capture_only):
         # the oracle's reference run and CPU baseline overlap the GPU legs
         import multiprocessing as mp
         from concurrent.futures import ProcessPoolExecutor
@@ -370,6 +443,9 @@ def main():
 
     if args.gather_ceiling:
         print(json.dumps({"gather_ceiling": gather_ceiling()}), flush=True)
+        return
+    if args.capture_only:
+        print(json.dumps({"captured_launches": capture_bench(dg, gg)}), flush=True)
         return
 
     t = time.perf_counter()
@@ -677,6 +753,10 @@ def main():
     if not args.no_set:
         graph_set = set_bench(dg, gg)
 
+    captured = {}
+    if not args.no_capture:
+        captured = capture_bench(dg, gg)
+
     serving = {}
     if not args.no_serve:
         serving = serve_bench(dg, gg, G, g, args)
@@ -750,6 +830,7 @@ def main():
         "topology": topology,
         "tuning": tuning,
         "graph_set": graph_set,
+        "captured_launches": captured,
         "serving": serving,
     }
     G.close()
