@@ -18,7 +18,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdg.so")
+# DG_LIBRARY names another build of the same library (the host-sanitizer
+# build the CPU tests use); by default the in-tree libdg.so.
+LIB_PATH = os.environ.get("DG_LIBRARY") or os.path.join(_HERE, "libdg.so")
 
 DG_OK, DG_ERR_INVALID_ARGUMENT, DG_ERR_OUT_OF_MEMORY, DG_ERR_DEVICE, DG_ERR_NOT_CONVERGED, DG_ERR_UNSUPPORTED = range(6)
 DG_SYNC, DG_ASYNC, DG_DELAYED, DG_DELAYED_LOCAL = 0, 1, 2, 3
