@@ -169,6 +169,18 @@ def set_bench(dg, gg):
     _, _, sp = S.pagerank(tol=1e-6, mode="delayed", d=64, dtype="f64")
     t_pr = min(S.pagerank(tol=1e-6, mode="delayed", d=64, dtype="f64")[2].seconds for _ in range(3))
     info = S.info()
+    tuned = {}
+    for algo in ("pagerank", "sssp"):
+        t0 = time.perf_counter()
+        t = S.tune(algo, sources=sources if algo == "sssp" else None, dtype="f64", tol=1e-6)
+        t["tuning_wall_s"] = round(time.perf_counter() - t0, 3)
+        t["speedup_vs_default_median"] = round(t["default_seconds"] / t["seconds"], 3)
+        t.pop("graph_hash")
+        tuned[algo] = t
+        log(f"tuned set {algo}: {t['mode']} d={t['d']} workers={t['workers']} -> {t['seconds'] * 1e3:.3f} ms "
+            f"[{t['seconds_min'] * 1e3:.3f}, {t['seconds_max'] * 1e3:.3f}] vs default {t['default_seconds'] * 1e3:.3f} "
+            f"ms [{t['default_seconds_min'] * 1e3:.3f}, {t['default_seconds_max'] * 1e3:.3f}] "
+            f"({t['candidates']} candidates in {t['tuning_wall_s']} s)")
     S.close()
     alone_sssp, alone_pr = 0.0, 0.0
     for x, src in zip(graphs, sources.tolist()):
@@ -183,7 +195,8 @@ def set_bench(dg, gg):
                           "speedup": round(alone_sssp / t_sssp, 2)},
            "pagerank_f64_delayed_d64_tol1e-6": {"set_ms": round(t_pr * 1e3, 3), "set_sweeps": sp.sweeps,
                                                "one_graph_at_a_time_ms": round(alone_pr * 1e3, 3),
-                                               "speedup": round(alone_pr / t_pr, 2)}}
+                                               "speedup": round(alone_pr / t_pr, 2)},
+           "tuned": tuned}
     log(f"graph set (64 graphs, n={info.n}, m={info.m}): SSSP {t_sssp * 1e3:.2f} ms vs {alone_sssp * 1e3:.2f} ms "
         f"one at a time; PageRank f64 {t_pr * 1e3:.2f} ms ({sp.sweeps} sweeps) vs {alone_pr * 1e3:.2f} ms")
     return res

@@ -613,6 +613,26 @@ dg_status dg_set_info_get(const dg_set* s, dg_set_info* info);
  * dg_set_sssp calls run as recorded chunks of chunk_sweeps sweeps (0 = one
  * launch per sweep).  Errors as dg_graph_set_capture, or a NULL set. */
 dg_status dg_set_set_capture(dg_set* s, uint32_t chunk_sweeps);
+/* Rebuilds the set's worker blocks for `workers` sweep workgroups (0 = the
+ * default, five per compute unit rounded down to a multiple of 8; at least one
+ * per graph, the rest in proportion to each graph's cost), without
+ * re-uploading.  Must not overlap a sweep call on the set. */
+dg_status dg_set_repartition(dg_set* s, uint32_t workers, void* hip_stream);
+/* Autotuner for a set (as dg_tune, for the whole set): every commit mode and
+ * interval (sync, async, delayed d in {16, 64, 256, 1024, whole}) at every
+ * partition (the current one and 2, 3, 5 and 8 workgroups per compute unit),
+ * each run to convergence after a warm-up run, three times; the least median
+ * time wins and the set keeps its partition.  The current partition with
+ * delayed d = 64 is among the candidates and is reported as the default, so
+ * the choice is never slower than it in the same measurement.
+ *   algo     DG_ALGO_PAGERANK (damping 0.85, tol > 0 per graph, dtype; float32
+ *            needs tol >= 1e-7) or DG_ALGO_SSSP (sources: one local source
+ *            per graph, as dg_set_sssp)
+ *   flags    0
+ * Fills dg_tuning as dg_tune (predicted_seconds = seconds; from_cache = 0;
+ * sweep_variant and resident_vertices are the union graph's own).  Not cached. */
+dg_status dg_set_tune(dg_set* s, dg_algo algo, dg_dtype dtype, double tol, const uint32_t* sources, uint32_t flags,
+                      dg_tuning* out, void* hip_stream);
 
 /* PageRank of every graph of the set (as dg_pagerank, per graph).  All
  * graphs are swept together; each graph's dangling mass is spread over its

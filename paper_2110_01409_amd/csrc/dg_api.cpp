@@ -1464,23 +1464,39 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
 dg_status dg_graph_repartition(dg_graph* g, uint32_t workers, void* hip_stream) {
   g_last_error.clear();
   if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
-  if (g->G) return fail(DG_ERR_UNSUPPORTED, "a set's union graph keeps its per-graph worker blocks");
-  const uint32_t P = workers ? std::max(1u, std::min(workers, g->T)) : default_workers(g, kWorkersPerCU);
+  uint32_t P = workers ? std::max(1u, std::min(workers, g->T))
+                       : default_workers(g, g->G ? kSetWorkersPerCU : kWorkersPerCU);
+  std::vector<uint32_t> work_t, wseg, wgraph;
+  if (g->G) {
+    // a set's union graph: every graph keeps worker blocks of its own
+    build_workers_seg(g->tile_v_h, g->tile_e0_h, g->seg_v, std::max(P, g->G), work_t, wseg);
+    P = wseg.back();
+    wgraph.resize(P);
+    for (uint32_t gi = 0; gi < g->G; ++gi)
+      for (uint32_t wk = wseg[gi]; wk < wseg[gi + 1]; ++wk) wgraph[wk] = gi;
+  }
   if (P == g->P) return DG_OK;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  std::vector<uint32_t> work_t;
-  build_workers(g->tile_v_h, g->tile_e0_h, P, work_t);
+  if (!g->G) build_workers(g->tile_v_h, g->tile_e0_h, P, work_t);
   uint32_t mbv = 1;
   for (uint32_t w = 0; w < P; ++w) mbv = std::max(mbv, g->tile_v_h[work_t[w + 1]] - g->tile_v_h[work_t[w]]);
   DG_HIP(hipStreamSynchronize(s));
   uint32_t* wt = static_cast<uint32_t*>(dev_alloc(g, (size_t)(P + 1) * 4, s));
   double* part = g->part ? static_cast<double*>(dev_alloc(g, 3 * (size_t)P * sizeof(double), s)) : nullptr;
-  if (!wt || (g->part && !part)) {
+  uint32_t* wsd = g->G ? static_cast<uint32_t*>(dev_alloc(g, wseg.size() * 4, s)) : nullptr;
+  uint32_t* wgd = g->G ? static_cast<uint32_t*>(dev_alloc(g, (size_t)P * 4, s)) : nullptr;
+  if (!wt || (g->part && !part) || (g->G && (!wsd || !wgd))) {
     dev_free(g, wt);
     dev_free(g, part);
+    dev_free(g, wsd);
+    dev_free(g, wgd);
     return fail(DG_ERR_OUT_OF_MEMORY, "repartition allocation failed");
   }
   DG_HIP(hipMemcpyAsync(wt, work_t.data(), (size_t)(P + 1) * 4, hipMemcpyHostToDevice, s));
+  if (g->G) {
+    DG_HIP(hipMemcpyAsync(wsd, wseg.data(), wseg.size() * 4, hipMemcpyHostToDevice, s));
+    DG_HIP(hipMemcpyAsync(wgd, wgraph.data(), (size_t)P * 4, hipMemcpyHostToDevice, s));
+  }
   DG_HIP(hipStreamSynchronize(s));
   dev_free(g, g->work_t);
   g->work_t = wt;
@@ -1488,6 +1504,14 @@ dg_status dg_graph_repartition(dg_graph* g, uint32_t workers, void* hip_stream) 
   if (g->part) {
     dev_free(g, g->part);
     g->part = part;
+  }
+  if (g->G) {
+    dev_free(g, g->wseg);
+    dev_free(g, g->wgraph);
+    g->wseg = wsd;
+    g->wgraph = wgd;
+    g->wseg_h.swap(wseg);
+    g->wgraph_h.swap(wgraph);
   }
   g->P = P;
   g->max_block_v = mbv;

@@ -66,6 +66,22 @@ dg_status per_graph_sweeps(const dg_set* s, uint32_t* out_sweeps, hipStream_t q)
   return DG_OK;
 }
 
+struct Spread {
+  double med = 0.0, lo = 0.0, hi = 0.0;
+};
+
+Spread spread_of(std::vector<double> v) {
+  std::sort(v.begin(), v.end());
+  Spread sp;
+  if (v.empty()) return sp;
+  sp.lo = v.front();
+  sp.hi = v.back();
+  sp.med = v.size() % 2 ? v[v.size() / 2] : 0.5 * (v[v.size() / 2 - 1] + v[v.size() / 2]);
+  return sp;
+}
+
+constexpr uint32_t kSetTuneRepeats = 3;
+
 }  // namespace
 
 extern "C" {
@@ -176,6 +192,120 @@ dg_status dg_set_info_get(const dg_set* s, dg_set_info* info) {
   info->workers = gi.workers;
   info->has_weights = gi.has_weights;
   info->device_bytes = gi.device_bytes;
+  return DG_OK;
+}
+
+dg_status dg_set_repartition(dg_set* s, uint32_t workers, void* hip_stream) {
+  g_last_error.clear();
+  if (!s) return fail(DG_ERR_INVALID_ARGUMENT, "set is NULL");
+  return dg_graph_repartition(s->g, workers, hip_stream);
+}
+
+dg_status dg_set_tune(dg_set* s, dg_algo algo, dg_dtype dtype, double tol, const uint32_t* sources, uint32_t flags,
+                      dg_tuning* out, void* hip_stream) {
+  g_last_error.clear();
+  if (!s || !out) return fail(DG_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (algo != DG_ALGO_PAGERANK && algo != DG_ALGO_SSSP) return fail(DG_ERR_INVALID_ARGUMENT, "unknown algorithm");
+  if (flags != 0) return fail(DG_ERR_INVALID_ARGUMENT, "flags must be 0 (got 0x%x)", flags);
+  if (algo == DG_ALGO_PAGERANK) {
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(DG_ERR_INVALID_ARGUMENT, "tol must be finite and > 0");
+    if (dtype != DG_F32 && dtype != DG_F64) return fail(DG_ERR_INVALID_ARGUMENT, "dtype must be DG_F32 or DG_F64");
+    if (dtype == DG_F32 && tol < kF32Floor)
+      return fail(DG_ERR_UNSUPPORTED, "float32 scores cannot settle below an L1 change of %.0e", kF32Floor);
+  } else {
+    if (!s->g->has_w) return fail(DG_ERR_INVALID_ARGUMENT, "the set was created without weights");
+    if (!sources) return fail(DG_ERR_INVALID_ARGUMENT, "sources is NULL");
+    for (uint32_t i = 0; i < s->G; ++i)
+      if (sources[i] >= s->voff[i + 1] - s->voff[i])
+        return fail(DG_ERR_INVALID_ARGUMENT, "source %u of graph %u is not a vertex of it", sources[i], i);
+  }
+  hipStream_t q = static_cast<hipStream_t>(hip_stream);
+  const uint32_t N = s->voff.back();
+  void* outd = dev_alloc(s->g, (size_t)N * (algo == DG_ALGO_PAGERANK ? 8 : 4), q);
+  if (!outd) return fail(DG_ERR_OUT_OF_MEMORY, "tuning output allocation failed");
+  uint32_t n_max = 0;
+  for (uint32_t i = 0; i < s->G; ++i) n_max = std::max(n_max, s->voff[i + 1] - s->voff[i]);
+  const uint32_t max_sw = algo == DG_ALGO_PAGERANK ? 10000u : std::min<uint32_t>(n_max + 1, dg::host::kMaxSweeps);
+  auto timed = [&](dg_mode mode, uint32_t d, Spread& sp, uint32_t& sweeps) -> dg_status {
+    std::vector<double> t;
+    for (uint32_t i = 0; i <= kSetTuneRepeats; ++i) {  // the first run is a warm-up
+      dg_stats x{};
+      dg_status r = algo == DG_ALGO_PAGERANK
+                        ? dg_set_pagerank(s, 0.85, tol, mode, d, dtype, 10000, 0, static_cast<double*>(outd), 1,
+                                          nullptr, &x, hip_stream)
+                        : dg_set_sssp(s, sources, mode, d, max_sw, 0, static_cast<uint32_t*>(outd), 1, nullptr, &x,
+                                      hip_stream);
+      if (r == DG_ERR_NOT_CONVERGED) r = DG_OK;
+      if (r != DG_OK) return r;
+      if (i) t.push_back(x.seconds);
+      sweeps = x.sweeps;
+    }
+    sp = spread_of(t);
+    return DG_OK;
+  };
+  struct Cand {
+    dg_mode mode;
+    uint32_t d;
+  };
+  const Cand cands[] = {{DG_SYNC, 1},      {DG_ASYNC, 1},       {DG_DELAYED, 16},        {DG_DELAYED, 64},
+                        {DG_DELAYED, 256}, {DG_DELAYED, 1024}, {DG_DELAYED, DG_D_WHOLE}};
+  const uint32_t P0 = s->g->P;  // the partition chosen at creation (or the current one)
+  dg_status st = DG_OK;
+  Spread def{}, best{};
+  best.med = 1e300;
+  uint32_t sw_def = 0, best_sw = 0, bestP = P0, evaluated = 0;
+  Cand bestc = {DG_DELAYED, 64};
+  std::vector<uint32_t> parts = {P0};
+  for (uint32_t per_cu : {2u, 3u, 5u, 8u}) {
+    uint32_t P = std::max(1u, std::min(s->g->cus * per_cu, s->g->T));
+    if (P > 8) P &= ~7u;
+    if (std::find(parts.begin(), parts.end(), P) == parts.end()) parts.push_back(P);
+  }
+  for (uint32_t P : parts) {
+    if ((st = dg_graph_repartition(s->g, P, hip_stream)) != DG_OK) break;
+    for (const Cand& c : cands) {
+      Spread sp{};
+      uint32_t sw = 0;
+      if ((st = timed(c.mode, c.d, sp, sw)) != DG_OK) break;
+      ++evaluated;
+      if (P == parts[0] && c.mode == DG_DELAYED && c.d == 64) {
+        def = sp;
+        sw_def = sw;
+      }
+      if (sp.med < best.med) {
+        best = sp;
+        bestP = s->g->P;
+        bestc = c;
+        best_sw = sw;
+      }
+    }
+    if (st != DG_OK) break;
+  }
+  dev_free(s->g, outd);
+  if (st == DG_OK) st = dg_graph_repartition(s->g, bestP, hip_stream);
+  if (st != DG_OK) {
+    (void)dg_graph_repartition(s->g, P0, hip_stream);
+    return st;
+  }
+  dg_tuning t{};
+  t.workers = s->g->P;
+  t.mode = bestc.mode;
+  t.d = bestc.d;
+  t.sweeps = best_sw;
+  t.seconds = best.med;
+  t.seconds_min = best.lo;
+  t.seconds_max = best.hi;
+  t.predicted_seconds = best.med;
+  t.candidates = evaluated;
+  t.graph_hash = s->g->hash;
+  t.sweep_variant = s->g->variant;
+  t.resident_vertices = DG_RESIDENT_AUTO;
+  t.repeats = kSetTuneRepeats;
+  t.default_seconds = def.med;
+  t.default_seconds_min = def.lo;
+  t.default_seconds_max = def.hi;
+  (void)sw_def;
+  *out = t;
   return DG_OK;
 }
 

@@ -38,6 +38,7 @@ EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_
            "dg_sssp", "dg_sssp_batch", "dg_ppr_batch", "dg_set_create", "dg_set_destroy", "dg_set_info_get",
            "dg_set_pagerank", "dg_set_sssp", "dg_graph_partition", "dg_access_matrix", "dg_graph_repartition",
            "dg_tune", "dg_tune_batch", "dg_graph_set_mapping", "dg_graph_set_capture", "dg_set_set_capture",
+           "dg_set_repartition", "dg_set_tune",
            "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_server_create",
            "dg_server_destroy", "dg_server_submit", "dg_server_step", "dg_server_fetch", "dg_server_status_get",
            "dg_plan_create", "dg_plan_info_get", "dg_plan_arrays", "dg_plan_destroy", "dg_probe_gather", "dg_sssp_noalloc",
@@ -193,6 +194,8 @@ def _load():
         "dg_graph_set_mapping": (C.c_int, [P, C.c_uint32, C.c_uint32, C.c_uint32, P]),
         "dg_graph_set_capture": (C.c_int, [P, C.c_uint32]),
         "dg_set_set_capture": (C.c_int, [P, C.c_uint32]),
+        "dg_set_repartition": (C.c_int, [P, C.c_uint32, P]),
+        "dg_set_tune": (C.c_int, [P, C.c_int, C.c_int, C.c_double, P, C.c_uint32, C.POINTER(dg_tuning), P]),
         "dg_tune_cache_clear": (C.c_int, []),
         "dg_tune_cache_save": (C.c_int, [C.c_char_p]),
         "dg_tune_cache_load": (C.c_int, [C.c_char_p]),
@@ -395,6 +398,14 @@ def dg_graph_set_capture(g, chunk_sweeps):
 
 def dg_set_set_capture(s, chunk_sweeps):
     return lib.dg_set_set_capture(s, chunk_sweeps)
+
+
+def dg_set_repartition(s, workers, stream):
+    return lib.dg_set_repartition(s, workers, stream)
+
+
+def dg_set_tune(s, algo, dtype, tol, sources, flags, out, stream):
+    return lib.dg_set_tune(s, algo, dtype, tol, sources, flags, out, stream)
 
 
 def tune_cache_save(path):
@@ -794,6 +805,21 @@ class GraphSet:
         """dg_set_set_capture: replay recorded chunks of this many sweeps
         (0: launch every sweep on its own)."""
         _check(dg_set_set_capture(self._h, int(chunk_sweeps)))
+
+    def repartition(self, workers=0, stream=None):
+        """dg_set_repartition: per-graph worker blocks for `workers` workgroups."""
+        _check(dg_set_repartition(self._h, int(workers), _stream_handle(stream)))
+
+    def tune(self, algo="pagerank", sources=None, dtype="f64", tol=1e-6, stream=None):
+        """dg_set_tune ("pagerank" or "sssp" with one local source per graph);
+        the set keeps the chosen partition.  Returns the choice as a dict."""
+        t = dg_tuning()
+        src = None
+        if algo == "sssp":
+            src = np.ascontiguousarray(sources, dtype=np.uint32)
+        _check(dg_set_tune(self._h, DG_ALGO_SSSP if algo == "sssp" else DG_ALGO_PAGERANK, DTYPES[dtype], float(tol),
+                           None if src is None else _np_ptr(src), 0, C.byref(t), _stream_handle(stream)))
+        return _tuning(t)
 
     def pagerank(self, damping=0.85, tol=1e-6, mode="delayed", d=64, dtype="f64", max_sweeps=10_000, stream=None,
                  allow_not_converged=False):

@@ -152,3 +152,67 @@ def test_tune_batch(dg, algo):
         for q in (0, 19):
             assert float(np.abs(rows[q].cpu().numpy() - opr.ppr_fixed_point(g, int(srcs[q]))).sum()) <= 1e-8
     G.close()
+
+
+def _small_set(dg, count=16, seed=64):
+    rng = np.random.default_rng(seed)
+    graphs = []
+    for i in range(count):
+        if i % 2 == 0:
+            graphs.append(gg.rmat(int(rng.integers(6, 12)), seed=400 + i))
+        else:
+            graphs.append(gg.erdos_renyi(int(rng.integers(100, 3000)), float(rng.integers(4, 17)), seed=400 + i))
+    sources = np.array([int(rng.integers(0, g.n)) for g in graphs], np.uint32)
+    return graphs, sources
+
+
+def test_set_repartition_keeps_results(dg):
+    """A set's worker blocks rebuilt for other workgroup counts (fewer than
+    the graphs: one each) keep SSSP bit-exact with each graph's oracle sweep
+    counts in sync mode, and PageRank within the rule's bound."""
+    graphs, sources = _small_set(dg)
+    refs = [osp.bellman_ford_sync(g, int(s))[:2] for g, s in zip(graphs, sources)]
+    xs = [opr.pagerank_fixed_point(g) for g in graphs]
+    S = dg.GraphSet(graphs)
+    for workers in (1, 16, 100, 2048, 0):
+        print(f"set repartition {workers}", flush=True)
+        S.repartition(workers)
+        assert S.info().workers >= len(graphs)
+        out, sw, _ = S.sssp(sources, mode="sync")
+        for part, (ref, rs), s_g in zip(S.split(out.cpu().numpy()), refs, sw.tolist()):
+            np.testing.assert_array_equal(part, ref)
+            assert s_g == rs
+        out, _, st = S.pagerank(tol=1e-9, mode="delayed", d=64, dtype="f64")
+        assert st.converged
+        for part, x in zip(S.split(out.cpu().numpy()), xs):
+            assert float(np.abs(part - x).sum()) <= 1e-8
+    S.close()
+
+
+@pytest.mark.parametrize("algo", ["pagerank", "sssp"])
+def test_set_tune(dg, algo):
+    """dg_set_tune: the choice is a valid candidate, no slower than the
+    default in the same measurement, the set keeps the chosen partition, and
+    the chosen configuration is still exact (SSSP) or within the rule's bound
+    (PageRank)."""
+    graphs, sources = _small_set(dg, count=24, seed=65)
+    S = dg.GraphSet(graphs)
+    print(f"set tune {algo}", flush=True)
+    t = S.tune(algo, sources=sources if algo == "sssp" else None, dtype="f64", tol=1e-8)
+    assert t["repeats"] == 3 and t["candidates"] >= 7
+    assert t["seconds"] <= t["default_seconds"] * (1 + 1e-12)
+    assert t["seconds_min"] <= t["seconds"] <= t["seconds_max"]
+    assert S.info().workers == t["workers"]
+    mode = t["mode"]
+    if algo == "sssp":
+        out, _, _ = S.sssp(sources, mode=mode, d=t["d"])
+        for part, g, s in zip(S.split(out.cpu().numpy()), graphs, sources.tolist()):
+            np.testing.assert_array_equal(part, osp.bellman_ford_sync(g, s)[0])
+    else:
+        out, _, st = S.pagerank(tol=1e-8, mode=mode, d=t["d"], dtype="f64")
+        assert st.converged
+        for part, g in zip(S.split(out.cpu().numpy()), graphs):
+            assert float(np.abs(part - opr.pagerank_fixed_point(g)).sum()) <= 1e-6
+    print(f"set tune {algo}: {mode} d={t['d']} workers={t['workers']} {t['seconds'] * 1e3:.3f} ms "
+          f"vs default {t['default_seconds'] * 1e3:.3f} ms", flush=True)
+    S.close()
