@@ -577,7 +577,7 @@ def main():
             log(f"{name} {key:16s} PR f32 {p32['sweeps']} {p32['t_conv_ms']} ms ({p32['gteps']} GTEPS; tol 1e-7: "
                 f"{p32['sweeps_tol1e-7']} sweeps {p32['t_conv_ms_tol1e-7']} ms; tile {p32['tile_vertices_mean']}, "
                 f"{p32['commits_per_sweep']} commits/sweep = every {p32['commit_interval_effective']} vertices) | "
-                f"SSSP {row[f'sssp_{len(srcs)}_sources']['t_conv_ms_total']} ms total")
+                f"SSSP {row[f'sssp_{len(srcs)}_sources']['t_conv_ms_total']} ms total over {len(srcs)} sources")
         sync_pr = out["sync"]["pagerank_f32"]["t_conv_ms"]
         sync_bf = out["sync"][f"sssp_{len(srcs)}_sources"]["t_conv_ms_total"]
         async_pr = out["async"]["pagerank_f32"]["t_conv_ms"]
