@@ -18,11 +18,11 @@
 // gathers in flight.
 //
 // Commit modes are those of the single-query sweeps: synchronous (double
-// buffer), asynchronous (agent-scope store per vertex), delayed (SSSP with
-// d <= kRegStageMaxD: staged in registers and committed every d vertices of
-// the worker; otherwise staged in a per-batch shadow array and committed at
-// the end of the first tile that brings the staged count to d; always also
-// at the end of the block).
+// buffer), asynchronous (agent-scope store per vertex), delayed (with
+// d <= kRegStageMaxD staged per wavefront, SSSP in registers and PPR in LDS,
+// and committed every d vertices of the worker; otherwise staged in a
+// per-batch shadow array and committed at the end of the first tile that
+// brings the staged count to d; always also at the end of the block).
 #include "dg_device.hpp"
 #include "dg_internal.hpp"
 
@@ -54,9 +54,9 @@ __device__ __forceinline__ void st_q(T* p, T v) {
 // rows, once `per` rows are staged and at the end of its block.  Used
 // instead of the global shadow when d <= kStageRows * waves per workgroup,
 // so that a commit every d vertices of the worker costs no extra row
-// traffic.  Batched SSSP only: the PPR kernel's extra registers cost it more
+// traffic.  Batched SSSP only: in the PPR kernel the extra registers cost more
 // occupancy than the shadow's row traffic (measured 17 against 15.3 ms per
-// batch-sweep on RMAT-22).
+// batch-sweep on RMAT-22), so PPR stages in LDS (LdsStage).
 template <typename T>
 struct RegStage {
   T val[kStageRows];
@@ -76,6 +76,36 @@ struct RegStage {
     if (++cnt >= per) flush(out, lane);
   }
 };
+
+// Delayed commits of the PPR kernel staged in LDS: the same cadence as
+// RegStage (each wavefront commits its own rows once `per` are staged, and at
+// the end of its block), with the rows in the wavefront's part of the
+// dynamic LDS instead of registers, which the PPR kernel cannot spare.  Each
+// wavefront reads back only what it wrote itself, in order, so no barrier is
+// needed.  Every lane stages a value (cnt stays the same in all lanes); a
+// lane whose query is frozen does not store it.
+template <typename T>
+struct LdsStage {
+  T* rows;           // [kStageRows][64], this wavefront's
+  uint32_t* slot;    // [kStageRows], this wavefront's
+  uint32_t cnt = 0;  // the same in every lane
+  __device__ __forceinline__ void flush(T* out, uint32_t lane, bool store) {
+    for (uint32_t r = 0; r < cnt; ++r)
+      if (store) st_q(out + (size_t)slot[r] * kQ + lane, rows[r * kQ + lane]);
+    cnt = 0;
+  }
+  __device__ __forceinline__ void push(uint32_t p, T v, uint32_t per, T* out, uint32_t lane, bool store) {
+    rows[cnt * kQ + lane] = v;
+    if (lane == 0) slot[cnt] = p;
+    if (++cnt >= per) flush(out, lane, store);
+  }
+};
+
+// Dynamic LDS of a delayed PPR sweep that stages in LDS (0 otherwise).
+template <typename T>
+constexpr size_t lds_stage_bytes() {
+  return (size_t)(kWG / 64) * kStageRows * (kQ * sizeof(T) + sizeof(uint32_t));
+}
 
 __device__ __forceinline__ uint32_t sat_add_q(uint32_t a, uint32_t b) {
   const uint32_t s = a + b;
@@ -317,21 +347,34 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
   const uint32_t t0 = cst(a.g.work_t)[w], t1 = cst(a.g.work_t)[w + 1];
   double r_loc = 0.0, dm_loc = 0.0, m_loc = 0.0;
   uint32_t staged = 0, t_first = t0;  // t_first: first tile staged since the last commit
+  // Delayed mode without a shadow: stage in LDS, commit every per rows.
+  const bool lds = M == kDelayed && shadow == nullptr;
+  const uint32_t per = (a.d + kWG / 64 - 1) / (kWG / 64);
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  LdsStage<T> ls;
+  ls.rows = reinterpret_cast<T*>(s_dyn) + (size_t)wv * kStageRows * kQ;
+  ls.slot = reinterpret_cast<uint32_t*>(s_dyn + (size_t)(kWG / 64) * kStageRows * kQ * sizeof(T)) + wv * kStageRows;
 
+  // Called by every lane of the wavefront (frozen queries included).
   auto update = [&](uint32_t v, double acc) {
-    if (!live) return;
-    const double xn = alpha * acc * invS + (v == src ? restart : 0.0);
-    const double xo = (double)x[(size_t)v * kQ + lane] * invS;
-    x[(size_t)v * kQ + lane] = (T)(xn * S);
-    const uint32_t dg = a.g.out_deg[v];
-    const T cn = dg ? (T)(xn * S / (double)dg) : (T)0;
-    r_loc += fabs(xn - xo);
-    m_loc += xn;
-    if (dg == 0) dm_loc += xn;
     const uint32_t p = a.g.cpos[v];
-    if constexpr (M == kSync) cout[(size_t)p * kQ + lane] = cn;
-    else if constexpr (M == kAsync) st_q(cout + (size_t)p * kQ + lane, cn);
-    else shadow[(size_t)v * kQ + lane] = cn;
+    T cn = (T)0;
+    if (live) {
+      const double xn = alpha * acc * invS + (v == src ? restart : 0.0);
+      const double xo = (double)x[(size_t)v * kQ + lane] * invS;
+      x[(size_t)v * kQ + lane] = (T)(xn * S);
+      const uint32_t dg = a.g.out_deg[v];
+      cn = dg ? (T)(xn * S / (double)dg) : (T)0;
+      r_loc += fabs(xn - xo);
+      m_loc += xn;
+      if (dg == 0) dm_loc += xn;
+      if constexpr (M == kSync) cout[(size_t)p * kQ + lane] = cn;
+      else if constexpr (M == kAsync) st_q(cout + (size_t)p * kQ + lane, cn);
+      else if (!lds) shadow[(size_t)v * kQ + lane] = cn;
+    }
+    // outside the branch, so that the slot (written by lane 0) and the count
+    // are the same for the whole wavefront; a frozen lane stores nothing
+    if (lds) ls.push(p, cn, per, cout, lane, live);
   };
 
   for (uint32_t t = t0; t < t1; ++t) {
@@ -346,7 +389,9 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
       for (uint32_t v = v0 + wv; v < v1; v += kWG / 64)
         update(v, pull_edges<M, T>(a.g.in_src, cin, in_ptr[v], in_ptr[v + 1], 0, 1, lane));
     }
-    if constexpr (M == kDelayed) {
+    if (lds) {
+      if (t + 1 == t1) ls.flush(cout, lane, live);  // the end of the block
+    } else if constexpr (M == kDelayed) {
       staged += nv;
       if (t + 1 == t1 || staged >= a.d) {
         // each wavefront commits the rows it staged itself (as in the SSSP kernel)
@@ -651,7 +696,7 @@ static void mppr_sweep_dispatch(int mode, const MpprArgs& a, hipStream_t s) {
   const dim3 grid(a.g.P, a.NB);
   if (mode == kSync) mppr_sweep_kernel<kSync, T><<<grid, kWG, 0, s>>>(a);
   else if (mode == kAsync) mppr_sweep_kernel<kAsync, T><<<grid, kWG, 0, s>>>(a);
-  else mppr_sweep_kernel<kDelayed, T><<<grid, kWG, 0, s>>>(a);
+  else mppr_sweep_kernel<kDelayed, T><<<grid, kWG, a.shadow ? 0 : lds_stage_bytes<T>(), s>>>(a);
 }
 
 hipError_t launch_mppr_sweep(int mode, bool f64, const MpprArgs& a, hipStream_t s) {

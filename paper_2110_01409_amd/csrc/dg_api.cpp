@@ -1351,7 +1351,8 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   void* c0 = al.get(vals * esz, s);
   void* c1 = mode == DG_SYNC ? al.get(vals * esz, s) : nullptr;
   const uint32_t d_eff = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_vb)) : 0u;
-  const bool need_sh = mode == DG_DELAYED;
+  // Delayed commits stage in LDS up to kRegStageMaxD, beyond in a shadow.
+  const bool need_sh = mode == DG_DELAYED && d_eff > kRegStageMaxD;
   void* sh = need_sh ? al.get(xs * esz, s) : nullptr;
   double* resid = static_cast<double*>(al.get(((size_t)max_sweeps + 1) * NB * 8, s));
   uint32_t* count = static_cast<uint32_t*>(al.get(((size_t)max_sweeps + 1) * NB * 4, s));
