@@ -87,19 +87,19 @@ namespace {
 
 bool f64(const dg_server* s) { return s->o.dtype == DG_F64; }
 
-// Delayed SSSP stages its commits in registers up to kRegStageMaxD, and
-// needs the per-batch shadow array only beyond.
-bool sssp_shadow(const dg_server* s, const dg_graph* g) {
+// Delayed commits stage per wavefront (SSSP in registers, PPR in LDS) up to
+// kRegStageMaxD, and need the per-batch shadow array only beyond.
+bool delayed_shadow(const dg_server* s, const dg_graph* g) {
   return s->o.mode == DG_DELAYED && std::max(1u, std::min(s->o.d, g->max_block_vb)) > kRegStageMaxD;
 }
 
 size_t batch_bytes(const dg_server* s, const dg_graph* g, int kind) {
   const size_t n = g->n, slots = (size_t)g->n + g->K;
-  const bool sync = s->o.mode == DG_SYNC, del = s->o.mode == DG_DELAYED;
+  const bool sync = s->o.mode == DG_SYNC;
   if (kind == DG_QUERY_SSSP)
-    return (slots * (sync ? 2 : 1) + (sssp_shadow(s, g) ? n : 0)) * kLanes * 4 + kLanes * 8 + 16;
+    return (slots * (sync ? 2 : 1) + (delayed_shadow(s, g) ? n : 0)) * kLanes * 4 + kLanes * 8 + 16;
   const size_t e = f64(s) ? 8 : 4;
-  return (n + slots * (sync ? 2 : 1) + (del ? n : 0)) * kLanes * e + kLanes * (4 + 4 + 6 * 8 + 4) +
+  return (n + slots * (sync ? 2 : 1) + (delayed_shadow(s, g) ? n : 0)) * kLanes * e + kLanes * (4 + 4 + 6 * 8 + 4) +
          (size_t)g->Pb * 3 * kLanes * 8 + 16;
 }
 
@@ -162,7 +162,7 @@ dg_status reshape_ring(Pool& p, T*& arr, size_t stride_bytes, uint32_t NBn) {
 dg_status resize(dg_server* s, Pool& p, uint32_t NBn) {
   dg_graph* g = p.g;
   const size_t n = g->n, slots = (size_t)g->n + g->K;
-  const bool sync = s->o.mode == DG_SYNC, del = s->o.mode == DG_DELAYED;
+  const bool sync = s->o.mode == DG_SYNC;
   dg_status st;
   if (!p.st) {
     DG_HIP(hipStreamCreateWithFlags(&p.st, hipStreamNonBlocking));
@@ -173,14 +173,14 @@ dg_status resize(dg_server* s, Pool& p, uint32_t NBn) {
   if (p.kind == DG_QUERY_SSSP) {
     if ((st = reshape(p, p.b0, slots * kLanes * 4, NBn, true)) != DG_OK) return st;
     if (sync && (st = reshape(p, p.b1, slots * kLanes * 4, NBn, true)) != DG_OK) return st;
-    if (sssp_shadow(s, g) && (st = reshape(p, p.sh, n * kLanes * 4, NBn, false)) != DG_OK) return st;
+    if (delayed_shadow(s, g) && (st = reshape(p, p.sh, n * kLanes * 4, NBn, false)) != DG_OK) return st;
     if ((st = reshape(p, p.lchg, kLanes * 4, NBn, false)) != DG_OK) return st;
   } else {
     const size_t e = f64(s) ? 8 : 4;
     if ((st = reshape(p, p.x, n * kLanes * e, NBn, true)) != DG_OK) return st;
     if ((st = reshape(p, p.c0, slots * kLanes * e, NBn, true)) != DG_OK) return st;
     if (sync && (st = reshape(p, p.c1, slots * kLanes * e, NBn, true)) != DG_OK) return st;
-    if (del && (st = reshape(p, p.psh, n * kLanes * e, NBn, false)) != DG_OK) return st;
+    if (delayed_shadow(s, g) && (st = reshape(p, p.psh, n * kLanes * e, NBn, false)) != DG_OK) return st;
     if ((st = reshape(p, p.src, kLanes * 4, NBn, true)) != DG_OK) return st;
     if ((st = reshape(p, p.qdone, kLanes * 4, NBn, true)) != DG_OK) return st;
     if ((st = reshape_ring(p, p.dang, kLanes * 8, NBn)) != DG_OK) return st;
