@@ -706,20 +706,34 @@ def main():
             res["self_share"] = round(st.self_share, 4)
             return res
 
+        def predicted(GG, modes):
+            # the static predictor against the measured modes of the same graph
+            p = GG.predict_mode()
+            key = "async" if p["mode"] == "async" else f"delayed_d{p['d']}"
+            cand = [k for k in modes if isinstance(modes[k], dict)]
+            out = {"mode": p["mode"], "d": p["d"], "lift_groups8": round(p["lift"], 2)}
+            for what in ("pagerank_f32_ms", "sssp_ms"):
+                best = min(cand, key=lambda k: modes[k][what])
+                out[f"{what[:-3]}_best"] = best
+                out[f"{what[:-3]}_predicted_over_best"] = round(modes[key][what] / modes[best][what], 3)
+            return out
+
         topology[f"rmat{args.scale}"] = {"access": access(G), "modes": mode_times(G, sources[:4]),
                                           "local_reads_d_whole": local_reads(G, sources[:4])}
+        topology[f"rmat{args.scale}"]["prediction"] = predicted(G, topology[f"rmat{args.scale}"]["modes"])
         gb = gg.banded(n, 16, 4096, 0.01, seed=args.scale)
         GB = dg.Graph.from_csr(gb)
         topology[gb.name] = {"n": gb.n, "m": gb.m, "access": access(GB),
                              "modes": mode_times(GB, gg.pick_sources(gb, 4, seed=1).tolist()),
                              "local_reads_d_whole": local_reads(GB, gg.pick_sources(gb, 4, seed=1).tolist())}
+        topology[gb.name]["prediction"] = predicted(GB, topology[gb.name]["modes"])
         GB.close()
         del gb
         for k, v in topology.items():
             log(f"topology {k}: diagonal share (32 groups) {v['access']['groups32']['diagonal_share']} "
                 f"(lift {v['access']['groups32']['lift']}), self share {v['access']['self_share']}; "
                 f"delay gain PR {v['modes']['delay_gain_pagerank']}x, SSSP {v['modes']['delay_gain_sssp']}x; "
-                f"local reads (d whole): {v['local_reads_d_whole']}")
+                f"predicted {v['prediction']}; local reads (d whole): {v['local_reads_d_whole']}")
 
     tuning = {}
     if not args.no_tune:

@@ -558,6 +558,31 @@ typedef struct {
 dg_status dg_access_matrix(dg_graph* g, uint32_t groups, uint64_t* out_counts, dg_access_stats* stats,
                            void* hip_stream);
 
+/* Commit-mode predictor (sections IV-C and V: when reads cluster, so that a
+ * worker mostly reads values written within its own part of the machine,
+ * buffering its commits only delays what it reads itself; when reads are
+ * spread, delaying commits cuts the contention on shared lines).  From the
+ * access matrix with one group per XCD (8 groups, or one per worker when
+ * there are fewer), without running a sweep:
+ *   lift = diagonal_share / uniform_diagonal
+ *   lift >= DG_PREDICT_CLUSTER_LIFT: DG_ASYNC (commits unbuffered);
+ *   otherwise: DG_DELAYED with d = 64 (one commit per tile, the finest
+ *   interval the sweeps have).
+ * The same choice serves PageRank and SSSP.  Costs one access-matrix pass
+ * (about one sweep).  Errors as dg_access_matrix. */
+#define DG_PREDICT_CLUSTER_LIFT 2.0
+typedef struct {
+  dg_mode mode;            /* predicted commit mode */
+  uint32_t d;              /* commit interval for DG_DELAYED, else 0 */
+  uint32_t groups;         /* groups of the access matrix used */
+  uint32_t reserved;
+  double diagonal_share;   /* as dg_access_stats */
+  double uniform_diagonal;
+  double lift;             /* diagonal_share / uniform_diagonal */
+  double self_share;
+} dg_prediction;
+dg_status dg_predict_mode(dg_graph* g, dg_prediction* out, void* hip_stream);
+
 /* Graph sets (a form beyond the paper's single graph: many graphs, of uneven
  * sizes, resident together and swept in one launch per sweep).  The graphs
  * are stored as one union graph (graph i's vertices follow those of graphs

@@ -917,6 +917,30 @@ dg_status dg_access_matrix(dg_graph* g, uint32_t groups, uint64_t* out_counts, d
   return DG_OK;
 }
 
+dg_status dg_predict_mode(dg_graph* g, dg_prediction* out, void* hip_stream) {
+  g_last_error.clear();
+  if (!g || !out) return fail(DG_ERR_INVALID_ARGUMENT, "NULL argument");
+  dg_access_stats st{};
+  const uint32_t groups = std::min(8u, g->P);
+  const dg_status r = dg_access_matrix(g, groups, nullptr, &st, hip_stream);
+  if (r != DG_OK) return r;
+  dg_prediction p{};
+  p.groups = groups;
+  p.diagonal_share = st.diagonal_share;
+  p.uniform_diagonal = st.uniform_diagonal;
+  p.lift = st.uniform_diagonal > 0.0 ? st.diagonal_share / st.uniform_diagonal : 1.0;
+  p.self_share = st.self_share;
+  if (p.lift >= DG_PREDICT_CLUSTER_LIFT) {
+    p.mode = DG_ASYNC;
+    p.d = 0;
+  } else {
+    p.mode = DG_DELAYED;
+    p.d = 64;
+  }
+  *out = p;
+  return DG_OK;
+}
+
 dg_status dg_pagerank(dg_graph* g, double damping, double tol, dg_mode mode, uint32_t d, dg_dtype dtype,
                       uint32_t max_sweeps, double* out_scores, int out_on_device, dg_stats* stats,
                       void* hip_stream) {

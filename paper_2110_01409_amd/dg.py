@@ -38,7 +38,7 @@ EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_
            "dg_sssp", "dg_sssp_batch", "dg_ppr_batch", "dg_set_create", "dg_set_destroy", "dg_set_info_get",
            "dg_set_pagerank", "dg_set_sssp", "dg_graph_partition", "dg_access_matrix", "dg_graph_repartition",
            "dg_tune", "dg_tune_batch", "dg_graph_set_mapping", "dg_graph_set_capture", "dg_set_set_capture",
-           "dg_set_repartition", "dg_set_tune",
+           "dg_set_repartition", "dg_set_tune", "dg_predict_mode",
            "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_server_create",
            "dg_server_destroy", "dg_server_submit", "dg_server_step", "dg_server_fetch", "dg_server_status_get",
            "dg_plan_create", "dg_plan_info_get", "dg_plan_arrays", "dg_plan_destroy", "dg_probe_gather", "dg_sssp_noalloc",
@@ -97,6 +97,12 @@ class dg_access_stats(C.Structure):
     _fields_ = [("reads", C.c_uint64), ("same_worker", C.c_uint64), ("diagonal", C.c_uint64),
                 ("groups", C.c_uint32), ("workers", C.c_uint32), ("self_share", C.c_double),
                 ("diagonal_share", C.c_double), ("uniform_diagonal", C.c_double)]
+
+
+class dg_prediction(C.Structure):
+    _fields_ = [("mode", C.c_int), ("d", C.c_uint32), ("groups", C.c_uint32), ("reserved", C.c_uint32),
+                ("diagonal_share", C.c_double), ("uniform_diagonal", C.c_double), ("lift", C.c_double),
+                ("self_share", C.c_double)]
 
 
 class dg_tuning(C.Structure):
@@ -196,6 +202,7 @@ def _load():
         "dg_set_set_capture": (C.c_int, [P, C.c_uint32]),
         "dg_set_repartition": (C.c_int, [P, C.c_uint32, P]),
         "dg_set_tune": (C.c_int, [P, C.c_int, C.c_int, C.c_double, P, C.c_uint32, C.POINTER(dg_tuning), P]),
+        "dg_predict_mode": (C.c_int, [P, C.POINTER(dg_prediction), P]),
         "dg_tune_cache_clear": (C.c_int, []),
         "dg_tune_cache_save": (C.c_int, [C.c_char_p]),
         "dg_tune_cache_load": (C.c_int, [C.c_char_p]),
@@ -398,6 +405,10 @@ def dg_graph_set_capture(g, chunk_sweeps):
 
 def dg_set_set_capture(s, chunk_sweeps):
     return lib.dg_set_set_capture(s, chunk_sweeps)
+
+
+def dg_predict_mode(g, out, stream):
+    return lib.dg_predict_mode(g, out, stream)
 
 
 def dg_set_repartition(s, workers, stream):
@@ -723,6 +734,13 @@ class Graph:
         """dg_graph_set_capture: replay recorded chunks of this many sweeps
         (0: launch every sweep on its own)."""
         _check(dg_graph_set_capture(self._h, int(chunk_sweeps)))
+
+    def predict_mode(self, stream=None):
+        """dg_predict_mode: the commit mode the access matrix suggests, as a dict."""
+        p = dg_prediction()
+        _check(dg_predict_mode(self._h, C.byref(p), _stream_handle(stream)))
+        return {"mode": MODE_NAMES[p.mode], "d": p.d, "groups": p.groups, "diagonal_share": p.diagonal_share,
+                "uniform_diagonal": p.uniform_diagonal, "lift": p.lift, "self_share": p.self_share}
 
     def partition(self, stream=None):
         """First vertex of each worker's block: uint32 array [workers + 1]."""

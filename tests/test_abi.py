@@ -232,6 +232,8 @@ def test_tune_call_validation_null(dg):
     assert dg.dg_graph_set_capture(None, 8) == dg.DG_ERR_INVALID_ARGUMENT
     assert dg.dg_set_set_capture(None, 8) == dg.DG_ERR_INVALID_ARGUMENT
     assert dg.dg_set_repartition(None, 8, None) == dg.DG_ERR_INVALID_ARGUMENT
+    pr = dg.dg_prediction()
+    assert dg.dg_predict_mode(None, C.byref(pr), None) == dg.DG_ERR_INVALID_ARGUMENT
     assert dg.dg_set_tune(None, 0, 0, 1e-6, None, 0, C.byref(t), None) == dg.DG_ERR_INVALID_ARGUMENT
 
 

@@ -61,3 +61,29 @@ def test_access_matrix_validation(dg):
         assert dg.dg_access_matrix(G._h, groups, None, C.byref(st), None) == dg.DG_ERR_INVALID_ARGUMENT
     assert dg.dg_access_matrix(G._h, 4, None, None, None) == dg.DG_ERR_INVALID_ARGUMENT
     G.close()
+
+
+@pytest.mark.parametrize("name,want", [("banded", "async"), ("rmat14", "delayed"), ("few_workers", "delayed")])
+def test_predict_mode(dg, name, want):
+    """dg_predict_mode reads the 8-group access matrix (the oracle's shares of
+    the same partition) and leaves commits unbuffered exactly when the lift
+    of the diagonal reaches DG_PREDICT_CLUSTER_LIFT."""
+    kw = {}
+    if name == "banded":
+        g = gg.banded(200_000, 8, 1024, 0.01, seed=6)
+    elif name == "rmat14":
+        g = gg.rmat(14, seed=14)
+    else:
+        g = gg.rmat(12, seed=3)
+        kw = {"workers": 5}
+    G = dg.Graph.from_csr(g, **kw)
+    p = G.predict_mode()
+    groups = min(8, G.info().workers)
+    ref, same = otop.access_matrix(g, G.partition(), groups)
+    d, u = otop.shares(ref)
+    assert p["groups"] == groups
+    assert abs(p["diagonal_share"] - d) < 1e-12 and abs(p["uniform_diagonal"] - u) < 1e-12
+    assert abs(p["lift"] - d / u) < 1e-9 and abs(p["self_share"] - same / g.m) < 1e-12
+    assert (p["lift"] >= 2.0) == (p["mode"] == "async")
+    assert p["mode"] == want and p["d"] == (64 if want == "delayed" else 0)
+    G.close()
