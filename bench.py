@@ -757,7 +757,7 @@ def main():
                 t.pop("graph_hash")
                 row[algo] = t
                 log(f"tuned rmat{sc} {algo}: {t['mode']} d={t['d']} workers={t['workers']} "
-                    f"{t['sweep_variant']} table={t['resident_vertices']} -> {t['seconds'] * 1e3:.3f} ms "
+                    f"{t['sweep_variant']} table={t['resident_vertices']} capture={t['capture_chunk']} -> {t['seconds'] * 1e3:.3f} ms "
                     f"[{t['seconds_min'] * 1e3:.3f}, {t['seconds_max'] * 1e3:.3f}] vs default "
                     f"{t['default_seconds'] * 1e3:.3f} ms [{t['default_seconds_min'] * 1e3:.3f}, "
                     f"{t['default_seconds_max'] * 1e3:.3f}] ({t['candidates']} candidates in {t['tuning_wall_s']} s)")

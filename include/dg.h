@@ -479,7 +479,11 @@ dg_status dg_graph_set_capture(dg_graph* g, uint32_t chunk_sweeps);
  *   3. the mapping, for that mode, d and partition: every sweep variant
  *      (wide, wide with all gathers in flight, narrow) with the whole
  *      resident table, half of it and none, each run to convergence three
- *      times; the least median time wins.
+ *      times; the least median time wins;
+ *   4. the launch: one launch per sweep against chunks of 16 captured sweeps
+ *      (dg_graph_set_capture), three runs each; the lesser median wins and
+ *      the graph keeps that setting (stages 1-3 and the default run with one
+ *      launch per sweep).
  * The choice and the default (the mapping and partition chosen at creation,
  * delayed d = 64) are each run to convergence three times: their median,
  * fastest and slowest times are reported.  The graph is left with the chosen
@@ -506,7 +510,7 @@ typedef struct {
   uint32_t sweep_variant;    /* chosen sweep variant (now the graph's) */
   uint32_t resident_vertices; /* chosen resident-table limit, or DG_RESIDENT_AUTO */
   uint32_t repeats;          /* timed runs of the choice and of the default */
-  uint32_t reserved;
+  uint32_t capture_chunk;    /* chosen captured-launch chunk (dg_graph_set_capture), 0 = one launch per sweep */
   double seconds_min, seconds_max;                 /* fastest and slowest run of the choice */
   double default_seconds;                          /* median of the default */
   double default_seconds_min, default_seconds_max; /* fastest and slowest run of the default */

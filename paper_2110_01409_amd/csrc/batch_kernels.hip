@@ -197,7 +197,8 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
   uint32_t any = 0, staged = 0, t_first = t0;  // t_first: first tile staged since the last commit
   // Delayed mode without a shadow: stage in registers, commit every per rows.
   const bool regs = M == kDelayed && shadow == nullptr;
-  const uint32_t per = (a.d + kWG / 64 - 1) / (kWG / 64);
+  // rows per wavefront between commits (the host stages here only for d <= kRegStageMaxD)
+  const uint32_t per = min((a.d + kWG / 64 - 1) / (kWG / 64), kStageRows);
   RegStage<uint32_t> rs;
   rs.slot = s_slot[wv];
 
@@ -349,7 +350,8 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
   uint32_t staged = 0, t_first = t0;  // t_first: first tile staged since the last commit
   // Delayed mode without a shadow: stage in LDS, commit every per rows.
   const bool lds = M == kDelayed && shadow == nullptr;
-  const uint32_t per = (a.d + kWG / 64 - 1) / (kWG / 64);
+  // rows per wavefront between commits (the host stages here only for d <= kRegStageMaxD)
+  const uint32_t per = min((a.d + kWG / 64 - 1) / (kWG / 64), kStageRows);
   extern __shared__ __align__(16) unsigned char s_dyn[];
   LdsStage<T> ls;
   ls.rows = reinterpret_cast<T*>(s_dyn) + (size_t)wv * kStageRows * kQ;

@@ -109,7 +109,7 @@ class dg_tuning(C.Structure):
     _fields_ = [("workers", C.c_uint32), ("mode", C.c_int), ("d", C.c_uint32), ("sweeps", C.c_uint32),
                 ("seconds", C.c_double), ("predicted_seconds", C.c_double), ("candidates", C.c_uint32),
                 ("from_cache", C.c_uint32), ("graph_hash", C.c_uint64), ("sweep_variant", C.c_uint32),
-                ("resident_vertices", C.c_uint32), ("repeats", C.c_uint32), ("reserved", C.c_uint32),
+                ("resident_vertices", C.c_uint32), ("repeats", C.c_uint32), ("capture_chunk", C.c_uint32),
                 ("seconds_min", C.c_double), ("seconds_max", C.c_double), ("default_seconds", C.c_double),
                 ("default_seconds_min", C.c_double), ("default_seconds_max", C.c_double)]
 
@@ -540,7 +540,7 @@ def _tuning(t):
             "predicted_seconds": t.predicted_seconds, "candidates": t.candidates,
             "from_cache": bool(t.from_cache), "graph_hash": t.graph_hash,
             "sweep_variant": VARIANT_NAMES.get(t.sweep_variant, "auto"),
-            "resident_vertices": t.resident_vertices, "repeats": t.repeats,
+            "resident_vertices": t.resident_vertices, "repeats": t.repeats, "capture_chunk": t.capture_chunk,
             "default_seconds": t.default_seconds, "default_seconds_min": t.default_seconds_min,
             "default_seconds_max": t.default_seconds_max}
 

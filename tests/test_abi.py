@@ -247,17 +247,21 @@ def test_tune_cache_roundtrip(dg, tmp_path):
     p.write_text("# comment\n"
                  "00000000deadbeef 0 0 1e-06 0 640 2 64 13 0.0065\n"
                  "00000000deadbee0 1 0 0 5 256 1 1 12 0.0043 3 16384\n"
+                 "00000000deadbee1 0 1 1e-08 0 120 0 1 21 0.0004 3 4096 16\n"
+                 "00000000deadbee2 0 1 1e-08 0 120 0 1 21 0.0004 3 4096 65\n"
                  "not a valid line\n")
     assert dg.dg_tune_cache_load(os.fsencode(str(p))) == dg.DG_ERR_INVALID_ARGUMENT
-    assert "1 malformed" in dg.last_error()
+    assert "2 malformed" in dg.last_error()  # the text line, and a capture chunk beyond 64
     q = tmp_path / "again.txt"
     dg.tune_cache_save(q)
     lines = sorted(ln for ln in q.read_text().splitlines() if not ln.startswith("#"))
-    assert len(lines) == 2 and lines[1].split()[:8] == ["00000000deadbeef", "0", "0", "9.9999999999999995e-07",
+    assert len(lines) == 3 and lines[2].split()[:8] == ["00000000deadbeef", "0", "0", "9.9999999999999995e-07",
                                                         "0", "640", "2", "64"]
-    # a line without the mapping columns loads with the automatic mapping; one with them keeps it
-    assert lines[1].split()[10:] == ["0", str(0xFFFFFFFF)]
-    assert lines[0].split()[10:] == ["3", "16384"]
+    # a line without the mapping columns loads with the automatic mapping and one launch per sweep; one with
+    # them keeps them
+    assert lines[2].split()[10:] == ["0", str(0xFFFFFFFF), "0"]
+    assert lines[0].split()[10:] == ["3", "16384", "0"]
+    assert lines[1].split()[10:] == ["3", "4096", "16"]
     dg.tune_cache_clear()
     dg.tune_cache_save(q)
     assert [ln for ln in q.read_text().splitlines() if not ln.startswith("#")] == []

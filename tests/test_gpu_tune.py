@@ -65,7 +65,8 @@ def test_tune_pagerank_and_cache(dg, tmp_path):
     assert 0 < t["default_seconds_min"] <= t["default_seconds"] <= t["default_seconds_max"]
     assert t["sweep_variant"] in ("wide", "wide_inflight", "narrow")
     assert dg.VARIANT_NAMES[G.info().sweep_variant] == t["sweep_variant"]
-    # the chosen configuration converges to the fixed point
+    assert t["capture_chunk"] in (0, 16)  # stage 4: one launch per sweep or captured chunks of 16
+    # the chosen configuration (launch setting included) converges to the fixed point
     x, st = G.pagerank(tol=1e-7, mode=t["mode"], d=max(t["d"], 1), dtype="f32")
     assert float(np.abs(x.cpu().numpy() - opr.pagerank_fixed_point(g)).sum()) <= 1e-6
     # and is not slower than the untuned defaults by more than timing noise
@@ -85,6 +86,7 @@ def test_tune_pagerank_and_cache(dg, tmp_path):
     dg.tune_cache_load(path)
     third = G3.tune("pagerank", dtype="f32", tol=1e-6)
     assert third["from_cache"] and (third["mode"], third["d"]) == (t["mode"], t["d"])
+    assert third["capture_chunk"] == t["capture_chunk"]
     assert G3.info().workers == t["workers"]
     # the cached mapping is applied too
     assert dg.VARIANT_NAMES[G3.info().sweep_variant] == t["sweep_variant"]
