@@ -373,7 +373,11 @@ dg_status dg_sssp(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t 
  * batch of a call runs in the same sweep launches; values are stored
  * vertex-major so one gather serves the 64 queries of a batch.  Each batch
  * stops when all its queries met the stopping rule; the call returns when
- * every batch has.  Commit modes and d are as for the single-query calls.
+ * every batch has.  Commit modes are those of the single-query calls.  A
+ * batched worker's four wavefronts take its vertices in turn, one at a time
+ * (not a tile at once), so DG_DELAYED commits every d vertices of the worker
+ * within a tile too: each wavefront commits its own staged rows every
+ * ceil(d/4) of its vertices, and at the end of the block.
  *   sources     host array of k vertex ids (< n); k >= 1
  *   max_sweeps  1 <= max_sweeps <= 100000
  *   stats       sweeps = sweeps until every batch converged;

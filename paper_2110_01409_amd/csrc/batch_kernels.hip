@@ -18,11 +18,11 @@
 // gathers in flight.
 //
 // Commit modes are those of the single-query sweeps: synchronous (double
-// buffer), asynchronous (agent-scope store per vertex), delayed (with
-// d <= kRegStageMaxD staged per wavefront, SSSP in registers and PPR in LDS,
-// and committed every d vertices of the worker; otherwise staged in a
-// per-batch shadow array and committed at the end of the first tile that
-// brings the staged count to d; always also at the end of the block).
+// buffer), asynchronous (agent-scope store per vertex), delayed (staged per
+// wavefront and committed every d vertices of the worker, i.e. every
+// ceil(d/4) rows of each wavefront, and at the end of the block: with
+// d <= kRegStageMaxD in registers (SSSP) or LDS (PPR), beyond in a per-batch
+// shadow array).
 #include "dg_device.hpp"
 #include "dg_internal.hpp"
 
@@ -119,6 +119,52 @@ __device__ __forceinline__ uint32_t bcast(uint32_t v, uint32_t j) {
 typedef const __attribute__((address_space(4))) uint32_t* cu32p;
 __device__ __forceinline__ cu32p cst(const uint32_t* p) { return (cu32p)(p); }
 
+// Delayed commits through the per-batch shadow array, for d beyond what a
+// wavefront stages itself: the same cadence (each wavefront commits its own
+// rows once `per` are staged, mid-tile, and at the end of its block), with
+// the rows in the shadow.  The rows of a commit are the wavefront's vertices
+// since its previous commit, walked again in the order it updated them:
+// tile by tile, vertices v0 + wv, v0 + wv + 4, ... of a tile, a single-vertex
+// tile being wavefront 0's.  (ft, fv) is the first of them; pend their number
+// (the same in every lane).  The wavefront reads back only rows it wrote
+// itself, so no barrier is needed.
+struct ShadowWalk {
+  uint32_t ft, fv, pend = 0;
+  __device__ __forceinline__ ShadowWalk(uint32_t t0, uint32_t first_v, uint32_t wv) : ft(t0), fv(first_v + wv) {}
+  // Commits the rows through vertex vl of tile tl (inclusive).
+  template <typename T>
+  __device__ __forceinline__ void commit(cu32p tile_v, const uint32_t* cpos, const T* shadow, T* out, uint32_t tl,
+                                        uint32_t vl, uint32_t wv, uint32_t lane, bool store) {
+    for (uint32_t tt = ft; tt <= tl; ++tt) {
+      const uint32_t a0 = tile_v[tt], a1 = tile_v[tt + 1];
+      const bool hub = a1 - a0 == 1;
+      if (hub && wv != 0) continue;
+      const uint32_t step = hub ? 1u : kWG / 64;
+      const uint32_t end = tt == tl ? vl + 1 : a1;
+      for (uint32_t v = tt == ft ? fv : (hub ? a0 : a0 + wv); v < end; v += step)
+        if (store) st_q(out + (size_t)cpos[v] * kQ + lane, shadow[(size_t)v * kQ + lane]);
+    }
+    pend = 0;
+  }
+  // After the wavefront staged the row of vertex v in tile t (hub: a
+  // single-vertex tile).
+  template <typename T>
+  __device__ __forceinline__ void staged(cu32p tile_v, const uint32_t* cpos, const T* shadow, T* out, uint32_t t,
+                                         uint32_t v, bool hub, uint32_t per, uint32_t wv, uint32_t lane, bool store) {
+    if (++pend < per) return;
+    commit(tile_v, cpos, shadow, out, t, v, wv, lane, store);
+    ft = t;
+    fv = v + (hub ? 1u : kWG / 64);
+  }
+  // At the end of the worker's block (tiles t0 .. t1-1).
+  template <typename T>
+  __device__ __forceinline__ void finish(cu32p tile_v, const uint32_t* cpos, const T* shadow, T* out, uint32_t t1,
+                                         uint32_t wv, uint32_t lane, bool store) {
+    if (pend) commit(tile_v, cpos, shadow, out, t1 - 1, tile_v[t1] - 1, wv, lane, store);
+  }
+};
+
+
 // min over in-edges [e0, e1) of d[src] + w, taking every `step`-th group of
 // 64 edges starting at group `first`.  Lane q handles query q.
 template <int M>
@@ -194,13 +240,15 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
   if (tid == 0) s_any = 0;
   if (tid < kQ) s_lane[tid] = 0;
   __syncthreads();
-  uint32_t any = 0, staged = 0, t_first = t0;  // t_first: first tile staged since the last commit
+  uint32_t any = 0;
   // Delayed mode without a shadow: stage in registers, commit every per rows.
   const bool regs = M == kDelayed && shadow == nullptr;
-  // rows per wavefront between commits (the host stages here only for d <= kRegStageMaxD)
-  const uint32_t per = min((a.d + kWG / 64 - 1) / (kWG / 64), kStageRows);
+  // rows per wavefront between commits (the host stages in registers only for d <= kRegStageMaxD)
+  const uint32_t per_rows = (uint32_t)(((uint64_t)a.d + kWG / 64 - 1) / (kWG / 64));
+  const uint32_t per = min(per_rows, kStageRows);
   RegStage<uint32_t> rs;
   rs.slot = s_slot[wv];
+  ShadowWalk sw(t0, t0 < t1 ? tile_v[t0] : 0u, wv);
 
   for (uint32_t t = t0; t < t1; ++t) {
     const uint32_t v0 = tile_v[t], v1 = tile_v[t + 1], nv = v1 - v0;
@@ -219,7 +267,10 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
         if constexpr (M == kSync) dout[(size_t)p * kQ + lane] = nw;
         else if constexpr (M == kAsync) st_q(dout + (size_t)p * kQ + lane, nw);
         else if (regs) rs.push(p, nw, per, dout, lane);
-        else shadow[(size_t)v0 * kQ + lane] = nw;
+        else {
+          shadow[(size_t)v0 * kQ + lane] = nw;
+          sw.staged(tile_v, a.g.cpos, shadow, dout, t, v0, true, per_rows, wv, lane, true);
+        }
       }
       __syncthreads();
     } else {
@@ -232,26 +283,15 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
         if constexpr (M == kSync) dout[(size_t)p * kQ + lane] = nw;
         else if constexpr (M == kAsync) st_q(dout + (size_t)p * kQ + lane, nw);
         else if (regs) rs.push(p, nw, per, dout, lane);
-        else shadow[(size_t)v * kQ + lane] = nw;
+        else {
+          shadow[(size_t)v * kQ + lane] = nw;
+          sw.staged(tile_v, a.g.cpos, shadow, dout, t, v, false, per_rows, wv, lane, true);
+        }
       }
     }
-    if (regs) {
-      if (t + 1 == t1) rs.flush(dout, lane);  // the end of the block
-    } else if constexpr (M == kDelayed) {
-      staged += nv;
-      if (t + 1 == t1 || staged >= a.d) {
-        // Each wavefront commits the rows it staged itself (a tile's vertex v
-        // is wavefront (v - v0) % 4's, a hub wavefront 0's): its own stores
-        // precede its loads, so no workgroup barrier is needed.
-        for (uint32_t tt = t_first; tt <= t; ++tt) {
-          const uint32_t a0 = tile_v[tt], a1 = tile_v[tt + 1];
-          const uint32_t first = a1 - a0 == 1 ? (wv == 0 ? a0 : a1) : a0 + wv;
-          for (uint32_t v = first; v < a1; v += kWG / 64)
-            st_q(dout + (size_t)a.g.cpos[v] * kQ + lane, shadow[(size_t)v * kQ + lane]);
-        }
-        staged = 0;
-        t_first = t + 1;
-      }
+    if (M == kDelayed && t + 1 == t1) {  // the end of the block
+      if (regs) rs.flush(dout, lane);
+      else sw.finish(tile_v, a.g.cpos, shadow, dout, t1, wv, lane, true);
     }
   }
   if (a.lchg) {
@@ -347,11 +387,13 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
   const cu32p in_ptr = cst(a.g.in_ptr);
   const uint32_t t0 = cst(a.g.work_t)[w], t1 = cst(a.g.work_t)[w + 1];
   double r_loc = 0.0, dm_loc = 0.0, m_loc = 0.0;
-  uint32_t staged = 0, t_first = t0;  // t_first: first tile staged since the last commit
   // Delayed mode without a shadow: stage in LDS, commit every per rows.
   const bool lds = M == kDelayed && shadow == nullptr;
-  // rows per wavefront between commits (the host stages here only for d <= kRegStageMaxD)
-  const uint32_t per = min((a.d + kWG / 64 - 1) / (kWG / 64), kStageRows);
+  // rows per wavefront between commits (the host stages in LDS only for d <= kRegStageMaxD)
+  const uint32_t per_rows = (uint32_t)(((uint64_t)a.d + kWG / 64 - 1) / (kWG / 64));
+  const uint32_t per = min(per_rows, kStageRows);
+  ShadowWalk sw(t0, t0 < t1 ? tile_v[t0] : 0u, wv);
+  uint32_t cur_t = t0;  // the tile being updated (for the shadow's commits)
   extern __shared__ __align__(16) unsigned char s_dyn[];
   LdsStage<T> ls;
   ls.rows = reinterpret_cast<T*>(s_dyn) + (size_t)wv * kStageRows * kQ;
@@ -377,10 +419,14 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
     // outside the branch, so that the slot (written by lane 0) and the count
     // are the same for the whole wavefront; a frozen lane stores nothing
     if (lds) ls.push(p, cn, per, cout, lane, live);
+    else if (M == kDelayed)
+      sw.staged(tile_v, a.g.cpos, shadow, cout, cur_t, v, tile_v[cur_t + 1] - tile_v[cur_t] == 1, per_rows, wv,
+                lane, live);
   };
 
   for (uint32_t t = t0; t < t1; ++t) {
     const uint32_t v0 = tile_v[t], v1 = tile_v[t + 1], nv = v1 - v0;
+    cur_t = t;
     if (nv == 1) {
       const uint32_t e0 = in_ptr[v0], e1 = in_ptr[v1];
       s_hub[wv][lane] = pull_edges<M, T>(a.g.in_src, cin, e0, e1, wv, kWG / 64, lane);
@@ -391,23 +437,9 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
       for (uint32_t v = v0 + wv; v < v1; v += kWG / 64)
         update(v, pull_edges<M, T>(a.g.in_src, cin, in_ptr[v], in_ptr[v + 1], 0, 1, lane));
     }
-    if (lds) {
-      if (t + 1 == t1) ls.flush(cout, lane, live);  // the end of the block
-    } else if constexpr (M == kDelayed) {
-      staged += nv;
-      if (t + 1 == t1 || staged >= a.d) {
-        // each wavefront commits the rows it staged itself (as in the SSSP kernel)
-        if (live) {
-          for (uint32_t tt = t_first; tt <= t; ++tt) {
-            const uint32_t a0 = tile_v[tt], a1 = tile_v[tt + 1];
-            const uint32_t first = a1 - a0 == 1 ? (wv == 0 ? a0 : a1) : a0 + wv;
-            for (uint32_t v = first; v < a1; v += kWG / 64)
-              st_q(cout + (size_t)a.g.cpos[v] * kQ + lane, shadow[(size_t)v * kQ + lane]);
-          }
-        }
-        staged = 0;
-        t_first = t + 1;
-      }
+    if (M == kDelayed && t + 1 == t1) {  // the end of the block
+      if (lds) ls.flush(cout, lane, live);
+      else sw.finish(tile_v, a.g.cpos, shadow, cout, t1, wv, lane, live);
     }
   }
 
