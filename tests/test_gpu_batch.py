@@ -9,6 +9,10 @@
   above its rounding floor (about 1e-7 synchronous, 1-3e-7 under
   asynchronous commits, where each sweep reads a timing-dependent mix of
   values that differ by rounding).
+* Edge cases: synchronous batches stopped after k sweeps return the k-th
+  Jacobi iterate; 1025 queries (17 launches, a one-lane tail); a batch of
+  one query against the single-query entry points; one-vertex, self-loop
+  and edgeless graphs.
 """
 import ctypes as C
 
@@ -133,4 +137,106 @@ def test_batch_validation(dg):
     assert dg.dg_ppr_batch(G._h, dg._np_ptr(s2), 2, 0.85, 1e-9, dg.DG_ASYNC, 1, dg.DG_F64, 5000, dg._np_ptr(outp),
                            0, C.byref(st), None) == dg.DG_OK
     assert np.abs(outp[:g.n] - opr.ppr_fixed_point(g, 3)).sum() < 1e-6
+    G.close()
+
+
+def test_batch_sync_per_sweep_iterates(dg):
+    """Synchronous batched sweeps stopped after k sweeps return the oracle's
+    k-th Jacobi iterate of every query: Bellman-Ford bit-exact, personalised
+    PageRank (float64, normalised like every finished row) within 1e-13
+    relative L1."""
+    g = gg.rmat(12, seed=21)
+    srcs = gg.pick_sources(g, 5, seed=8)
+    G = dg.Graph.from_csr(g)
+    iters = {int(s): osp.bellman_ford_sync(g, int(s), keep_iterates=True)[2] for s in srcs}
+    for k in (1, 2, 3, 5):
+        out, st = G.sssp_batch(srcs, mode="sync", max_sweeps=k, allow_not_converged=True)
+        got = out.cpu().numpy()
+        for q, s in enumerate(srcs.tolist()):
+            its = iters[s]
+            np.testing.assert_array_equal(got[q], its[min(k, len(its)) - 1], err_msg=f"k={k} query {q}")
+        assert st.sweeps == k and not st.converged
+    for k in (1, 2, 4):
+        out, st = G.ppr_batch(srcs, tol=0.0, mode="sync", dtype="f64", max_sweeps=k, allow_not_converged=True)
+        got = out.cpu().numpy()
+        for q, s in enumerate(srcs.tolist()):
+            ref, n_sw = opr.ppr_jacobi(g, s, tol=0.0, max_sweeps=k)
+            assert n_sw == k
+            ref = ref / ref.sum()
+            assert np.abs(got[q] - ref).sum() <= 1e-13, (k, q)
+        assert st.sweeps == k and not st.converged
+    G.close()
+
+
+def test_batch_many_batches_one_lane_tail(dg):
+    """1025 queries: 17 launches of 64 lanes, the last holding one query.
+    Sampled rows in every batch, the tail included, bit-exact (SSSP) or
+    within the rule's bound (PPR)."""
+    g = gg.rmat(10, seed=30)
+    rng = np.random.default_rng(30)
+    k = 1025
+    srcs = rng.integers(0, g.n, size=k).astype(np.uint32)
+    G = dg.Graph.from_csr(g)
+    sample = list(range(0, k, 61)) + [63, 64, 1023, 1024]
+    for mode, d in (("sync", 1), ("async", 1), ("delayed", 64)):
+        out, st = G.sssp_batch(srcs, mode=mode, d=d)
+        got = out.cpu().numpy()
+        assert got.shape == (k, g.n) and st.converged
+        for q in sample:
+            np.testing.assert_array_equal(got[q], osp.bellman_ford_sync(g, int(srcs[q]))[0], err_msg=f"{mode} {q}")
+    out, st = G.ppr_batch(srcs, tol=1e-9, mode="delayed", d=64, dtype="f64", max_sweeps=5000)
+    got = out.cpu().numpy()
+    assert st.converged and np.abs(got.sum(axis=1) - 1.0).max() < 1e-9
+    for q in sample:
+        assert np.abs(got[q] - opr.ppr_fixed_point(g, int(srcs[q]))).sum() <= 1e-8, q
+    G.close()
+
+
+def test_batch_single_query_matches_single_entry_point(dg):
+    """A batch of one query equals the single-query entry points: SSSP bit
+    for bit, PPR within the rule's bound of the same fixed point; a batch of
+    one source repeated gives identical rows in synchronous mode."""
+    g = gg.rmat(12, seed=33)
+    s = int(gg.pick_sources(g, 1, seed=9)[0])
+    G = dg.Graph.from_csr(g)
+    for mode, d in MODES:
+        one, _ = G.sssp_batch(np.array([s], np.uint32), mode=mode, d=d)
+        single, _ = G.sssp(s, mode=mode, d=d)
+        np.testing.assert_array_equal(one[0].cpu().numpy(), single.cpu().numpy(), err_msg=f"{mode} d={d}")
+        p, _ = G.ppr_batch(np.array([s], np.uint32), tol=1e-9, mode=mode, d=d, dtype="f64", max_sweeps=5000)
+        x, _ = G.ppr(s, tol=1e-9, mode=mode, d=d, dtype="f64", max_sweeps=5000)
+        assert np.abs(p[0].cpu().numpy() - x.cpu().numpy()).sum() <= 2e-8, (mode, d)
+    rep = np.full(130, s, np.uint32)
+    out, _ = G.ppr_batch(rep, tol=1e-9, mode="sync", dtype="f64")
+    got = out.cpu().numpy()
+    assert (got == got[0]).all()
+    G.close()
+
+
+def test_batch_degenerate_graphs(dg):
+    """One vertex without edges, a self-loop only, and an edgeless graph:
+    distance 0 at the source and unreachable elsewhere, PPR all mass at the
+    restart vertex (a dangling vertex returns its mass there)."""
+    G = dg.Graph(1, np.array([0, 0], np.uint64), np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    for mode, d in MODES:
+        dist, _ = G.sssp_batch(np.zeros(3, np.uint32), mode=mode, d=d)
+        assert (dist.cpu().numpy() == 0).all()
+        p, _ = G.ppr_batch(np.zeros(2, np.uint32), tol=1e-12, mode=mode, d=d, dtype="f64")
+        assert np.abs(p.cpu().numpy() - 1.0).max() < 1e-15
+    G.close()
+    G = dg.Graph(1, np.array([0, 1], np.uint64), np.zeros(1, np.uint32), np.array([9], np.uint32))
+    p, _ = G.ppr_batch(np.zeros(1, np.uint32), tol=1e-12, mode="async", dtype="f64")
+    assert abs(p.cpu().numpy()[0, 0] - 1.0) < 1e-15
+    G.close()
+    n = 777
+    G = dg.Graph(n, np.zeros(n + 1, np.uint64), np.zeros(0, np.uint32), np.zeros(0, np.uint32))
+    srcs = np.array([0, 5, 776], np.uint32)
+    for mode, d in MODES:
+        dist, _ = G.sssp_batch(srcs, mode=mode, d=d)
+        dv = dist.cpu().numpy()
+        p, _ = G.ppr_batch(srcs, tol=1e-12, mode=mode, d=d, dtype="f64")
+        pv = p.cpu().numpy()
+        for q, s in enumerate(srcs.tolist()):
+            assert dv[q, s] == 0 and (np.delete(dv[q], s) == dg.DG_INF_DIST).all()
+            assert abs(pv[q, s] - 1.0) < 1e-15 and np.abs(np.delete(pv[q], s)).max() == 0.0
     G.close()
