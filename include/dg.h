@@ -381,7 +381,10 @@ dg_status dg_sssp(dg_graph* g, uint32_t src, dg_mode mode, uint32_t d, uint32_t 
  *   sources     host array of k vertex ids (< n); k >= 1
  *   max_sweeps  1 <= max_sweeps <= 100000
  *   stats       sweeps = sweeps until every batch converged;
- *               edges_traversed = m * sum over queries of their batch's sweeps
+ *               edges_traversed = m * sum over queries of their batch's sweeps;
+ *               workers = the batched partition's workers; in DG_DELAYED,
+ *               commits = commits per sweep of one batch, over every
+ *               wavefront of every worker, and commit_interval = n / commits
  *
  * dg_sssp_batch: Bellman-Ford from each source (as dg_sssp).
  *   out_dist    k rows of n uint32: row q holds the distances from sources[q]

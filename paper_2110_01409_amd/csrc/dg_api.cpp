@@ -184,6 +184,30 @@ uint32_t commits_per_sweep(const dg_graph* g, uint32_t d, uint32_t cap, bool sha
   return c;
 }
 
+// Commits per sweep of one batch (64 queries) of a delayed batched sweep,
+// counted as the kernels decide them: each of a batched worker's kWG / 64
+// wavefronts stages the rows it updates (vertices v0 + wv, v0 + wv + kWG / 64,
+// ... of each tile; wavefront 0 alone the row of a single-vertex tile) and
+// commits them once ceil(d / (kWG / 64)) are staged, and at the end of the
+// worker's block.
+uint32_t batch_commits_per_sweep(const dg_graph* g, uint32_t d) {
+  constexpr uint32_t waves = kWG / 64;
+  const uint64_t per = ((uint64_t)d + waves - 1) / waves;
+  const std::vector<uint32_t>& tv = g->tile_v_h;
+  const std::vector<uint32_t>& wt = g->work_tb_h;
+  uint64_t c = 0;
+  for (size_t w = 0; w + 1 < wt.size(); ++w)
+    for (uint32_t wv = 0; wv < waves; ++wv) {
+      uint64_t rows = 0;
+      for (uint32_t t = wt[w]; t < wt[w + 1]; ++t) {
+        const uint32_t nv = tv[t + 1] - tv[t];
+        rows += nv == 1 ? (wv == 0 ? 1u : 0u) : (nv > wv ? (nv - wv + waves - 1) / waves : 0u);
+      }
+      c += (rows + per - 1) / per;
+    }
+  return (uint32_t)std::min<uint64_t>(c, 0xFFFFFFFFu);
+}
+
 }  // namespace host
 }  // namespace dg
 
@@ -778,6 +802,7 @@ dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
   build_workers(L.tile_v, L.tile_e0, g->Pb, work_tb);
   for (uint32_t wk = 0; wk < g->Pb; ++wk)
     g->max_block_vb = std::max(g->max_block_vb, L.tile_v[work_tb[wk + 1]] - L.tile_v[work_tb[wk]]);
+  g->work_tb_h = work_tb;
 
   uint32_t* w8_words = nullptr;
   struct Up {
@@ -1342,8 +1367,8 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
     stats->sweeps = sweeps;
     stats->workers = g->Pb;
     stats->tile_vertices = g->T ? (uint32_t)(((uint64_t)g->n + g->T / 2) / g->T) : 0u;
-    stats->commit_interval = mode == DG_DELAYED ? a.d : 0;
-    stats->commits = 0;
+    stats->commits = mode == DG_DELAYED ? dg::host::batch_commits_per_sweep(g, a.d) : 0u;
+    stats->commit_interval = stats->commits ? (uint32_t)(((uint64_t)g->n + stats->commits / 2) / stats->commits) : 0u;
     stats->err_bound = 0.0;
     stats->residual = 0.0;
     stats->seconds = secs;
@@ -1475,8 +1500,8 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
     stats->sweeps = sweeps;
     stats->workers = g->Pb;
     stats->tile_vertices = g->T ? (uint32_t)(((uint64_t)g->n + g->T / 2) / g->T) : 0u;
-    stats->commit_interval = mode == DG_DELAYED ? a.d : 0;
-    stats->commits = 0;
+    stats->commits = mode == DG_DELAYED ? dg::host::batch_commits_per_sweep(g, a.d) : 0u;
+    stats->commit_interval = stats->commits ? (uint32_t)(((uint64_t)g->n + stats->commits / 2) / stats->commits) : 0u;
     stats->err_bound = 0.0;
     stats->residual = last_r;
     stats->seconds = secs;
@@ -1594,6 +1619,7 @@ dg_status dg_graph_set_mapping(dg_graph* g, uint32_t sweep_variant, uint32_t res
     dev_free(g, g->work_tb);
     g->tile_v = tvd;
     g->work_tb = wtbd;
+    g->work_tb_h = wtb;
     g->tile_v_h.swap(tv);
     g->tile_e0_h.swap(te0);
     g->T = T;
@@ -1859,6 +1885,7 @@ dg_status set_batch_workers(dg_graph* g, uint32_t Pb, hipStream_t s) {
   DG_HIP(hipStreamSynchronize(s));
   dev_free(g, g->work_tb);
   g->work_tb = d;
+  g->work_tb_h = wtb;
   g->Pb = Pb;
   g->max_block_vb = 1;
   for (uint32_t w = 0; w < Pb; ++w) g->max_block_vb = std::max(g->max_block_vb, g->tile_v_h[wtb[w + 1]] - g->tile_v_h[wtb[w]]);

@@ -65,6 +65,7 @@ struct dg_graph {
   uint32_t Pb = 0, max_block_vb = 1;
   std::vector<uint32_t> tile_v_h, tile_e0_h;  // host copies: first vertex / first in-edge of each tile
   std::vector<uint32_t> work_t_h;             // host copy of work_t: first tile of each worker
+  std::vector<uint32_t> work_tb_h;            // host copy of work_tb: first tile of each batched worker
   std::vector<uint32_t> in_ptr_h;             // host copy of in_ptr (re-tiling by dg_graph_set_mapping)
   uint32_t res_limit = 0xFFFFFFFFu;           // resident-table entries the sweeps may use (<= R)
   uint64_t hash = 0;                         // content hash of the in-edge form (tuning cache key)

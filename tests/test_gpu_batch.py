@@ -240,3 +240,32 @@ def test_batch_degenerate_graphs(dg):
             assert dv[q, s] == 0 and (np.delete(dv[q], s) == dg.DG_INF_DIST).all()
             assert abs(pv[q, s] - 1.0) < 1e-15 and np.abs(np.delete(pv[q], s)).max() == 0.0
     G.close()
+
+
+def test_batch_commit_counts(dg):
+    """dg_stats.commits of a delayed batched call: each wavefront commits
+    every ceil(d/4) of its rows and at the end of its block, so d = 1 commits
+    every row on its own (n per batch-sweep), d = 64 about n/16, and a whole
+    block at most once per wavefront; sync and async report 0.  The
+    interval is n / commits."""
+    g = gg.rmat(12, seed=40)
+    srcs = gg.pick_sources(g, 3, seed=1)
+    G = dg.Graph.from_csr(g)
+    for call in ("sssp", "ppr"):
+        def run(mode, d):
+            if call == "sssp":
+                return G.sssp_batch(srcs, mode=mode, d=d)[1]
+            return G.ppr_batch(srcs, tol=1e-9, mode=mode, d=d, dtype="f64")[1]
+        for mode in ("sync", "async"):
+            st = run(mode, 1)
+            assert st.commits == 0 and st.commit_interval == 0
+        st = run("delayed", 1)
+        assert st.commits == g.n and st.commit_interval == 1, (call, st.commits)
+        st = run("delayed", 64)
+        waves = 4 * st.workers
+        assert g.n / 16 <= st.commits <= g.n / 16 + waves, (call, st.commits)
+        assert abs(st.commit_interval - g.n / st.commits) <= 0.5
+        st = run("delayed", dg.DG_D_WHOLE)
+        assert st.workers <= st.commits <= waves, (call, st.commits)
+        print(f"{call}: whole-block commits {st.commits} for {st.workers} workers", flush=True)
+    G.close()
