@@ -116,6 +116,29 @@ __device__ __forceinline__ uint32_t owner_of(const uint32_t* s_ptr, uint32_t nv,
   return lo;
 }
 
+// Owner walk of a thread's window: slot e has just reached `bound` =
+// s_ptr[i + 1], so the owner moves to the last vertex whose first slot is e.
+// The next two bounds wait in registers (b2 = s_ptr[i + 2], b3 = s_ptr[i + 3],
+// read one crossing ahead), so a crossing costs no LDS round trip unless it
+// skips two or more vertices without in-edges; then they are read again for
+// the next crossing.  Every index read is <= nv: a step is taken only while
+// e >= s_ptr[i + 1] and e < s_ptr[nv], i.e. i + 1 < nv.
+__device__ __forceinline__ void next_owner(const uint32_t* s_ptr, uint32_t nv, uint32_t e, uint32_t& i,
+                                           uint32_t& bound, uint32_t& b2, uint32_t& b3) {
+  ++i;
+  bound = b2;
+  if (e >= bound) {
+    ++i;
+    bound = b3;
+    while (e >= bound) {
+      ++i;
+      bound = s_ptr[i + 1];
+    }
+  }
+  b2 = s_ptr[min(i + 2, nv)];
+  b3 = s_ptr[min(i + 3, nv)];
+}
+
 // Buffer resources (raw, stride 0).  A lane whose byte offset lies outside
 // [0, bytes) reads 0 and makes no memory access, which masks lanes without
 // branches.  dword3 is the raw-buffer format word for this target.
@@ -421,7 +444,7 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
         const uint32_t es = e0 > eb ? e0 : eb;
         const uint32_t en = (e0 + EPT < ee) ? e0 + EPT : ee;
         uint32_t i = owner_of(s_ptr, nv, es);
-        uint32_t bound = s_ptr[i + 1];
+        uint32_t bound = s_ptr[i + 1], b2 = s_ptr[min(i + 2, nv)], b3 = s_ptr[min(i + 3, nv)];
         double part = 0.0;
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
@@ -430,7 +453,7 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
             if (e >= bound) {
               atomicAdd(&s_acc[i], part);
               part = 0.0;
-              do { ++i; bound = s_ptr[i + 1]; } while (e >= bound);
+              next_owner(s_ptr, nv, e, i, bound, b2, b3);
             }
             part += val[j];
           }
@@ -745,7 +768,7 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
         const uint32_t es = e0 > eb ? e0 : eb;
         const uint32_t en = (e0 + EPT < ee) ? e0 + EPT : ee;
         uint32_t i = owner_of(s_ptr, nv, es);
-        uint32_t bound = s_ptr[i + 1];
+        uint32_t bound = s_ptr[i + 1], b2 = s_ptr[min(i + 2, nv)], b3 = s_ptr[min(i + 3, nv)];
         uint32_t part = kInf;
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
@@ -754,7 +777,7 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
             if (e >= bound) {
               if (part != kInf) atomicMin(&s_acc[i], part);
               part = kInf;
-              do { ++i; bound = s_ptr[i + 1]; } while (e >= bound);
+              next_owner(s_ptr, nv, e, i, bound, b2, b3);
             }
             part = cand[j] < part ? cand[j] : part;
           }
