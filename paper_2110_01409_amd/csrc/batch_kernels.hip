@@ -21,8 +21,7 @@
 // buffer), asynchronous (agent-scope store per vertex), delayed (staged per
 // wavefront and committed every d vertices of the worker, i.e. every
 // ceil(d/4) rows of each wavefront, and at the end of the block: with
-// d <= kRegStageMaxD in registers (SSSP) or LDS (PPR), beyond in a per-batch
-// shadow array).
+// d <= kLdsStageMaxD in LDS, beyond in a per-batch shadow array).
 #include "dg_device.hpp"
 #include "dg_internal.hpp"
 
@@ -47,43 +46,16 @@ __device__ __forceinline__ void st_q(T* p, T v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Delayed commits staged in registers: each wavefront keeps up to kStageRows
-// rows it computed (its lane's value in a register; the vertex's slot, the
-// same in every lane, in the wavefront's own LDS array, which it reads back
-// in order, so no barrier is needed) and commits them, as coalesced 64-lane
-// rows, once `per` rows are staged and at the end of its block.  Used
-// instead of the global shadow when d <= kStageRows * waves per workgroup,
-// so that a commit every d vertices of the worker costs no extra row
-// traffic.  Batched SSSP only: in the PPR kernel the extra registers cost more
-// occupancy than the shadow's row traffic (measured 17 against 15.3 ms per
-// batch-sweep on RMAT-22), so PPR stages in LDS (LdsStage).
-template <typename T>
-struct RegStage {
-  T val[kStageRows];
-  uint32_t* slot;    // [kStageRows] in LDS, this wavefront's
-  uint32_t cnt = 0;  // the same in every lane
-  __device__ __forceinline__ void flush(T* out, uint32_t lane) {
-#pragma unroll
-    for (uint32_t r = 0; r < kStageRows; ++r)
-      if (r < cnt) st_q(out + (size_t)slot[r] * kQ + lane, val[r]);
-    cnt = 0;
-  }
-  __device__ __forceinline__ void push(uint32_t p, T v, uint32_t per, T* out, uint32_t lane) {
-#pragma unroll
-    for (uint32_t r = 0; r < kStageRows; ++r)
-      if (r == cnt) val[r] = v;
-    if (lane == 0) slot[cnt] = p;
-    if (++cnt >= per) flush(out, lane);
-  }
-};
-
-// Delayed commits of the PPR kernel staged in LDS: the same cadence as
-// RegStage (each wavefront commits its own rows once `per` are staged, and at
-// the end of its block), with the rows in the wavefront's part of the
-// dynamic LDS instead of registers, which the PPR kernel cannot spare.  Each
-// wavefront reads back only what it wrote itself, in order, so no barrier is
-// needed.  Every lane stages a value (cnt stays the same in all lanes); a
-// lane whose query is frozen does not store it.
+// Delayed commits staged in LDS: each wavefront keeps up to kStageRows rows
+// it computed, with their slots, in its own part of the dynamic LDS and
+// commits them, as coalesced 64-lane rows, once `per` are staged and at the
+// end of its block.  Used instead of the global shadow when d <= kStageRows *
+// waves per workgroup, so that a commit every d vertices of the worker costs
+// no extra row traffic.  Each wavefront reads back only what it wrote itself,
+// in order, so no barrier is needed.  Every lane stages a value (cnt stays
+// the same in all lanes); a lane whose query is frozen does not store it.
+// (Rows held in registers instead cost the SSSP kernel 73 VGPRs and two
+// waves per SIMD: 14.3 against 12.1 ms per batch-sweep on RMAT-22.)
 template <typename T>
 struct LdsStage {
   T* rows;           // [kStageRows][64], this wavefront's
@@ -101,10 +73,19 @@ struct LdsStage {
   }
 };
 
-// Dynamic LDS of a delayed PPR sweep that stages in LDS (0 otherwise).
+// Dynamic LDS of a batched PPR sweep: the staged rows and their slots when
+// a delayed sweep stages in LDS, and in every sweep each wavefront's three
+// per-query partials (double) for the workgroup's fold at the end, which a
+// staging wavefront writes over its own rows once it has flushed them.
 template <typename T>
 constexpr size_t lds_stage_bytes() {
   return (size_t)(kWG / 64) * kStageRows * (kQ * sizeof(T) + sizeof(uint32_t));
+}
+constexpr size_t kRedBytes = 3 * kQ * sizeof(double);  // one wavefront's partials
+static_assert(kStageRows * kQ * sizeof(float) >= kRedBytes, "a wavefront's staged rows hold its partials");
+template <typename T, bool STAGE>
+constexpr size_t mppr_dyn_bytes() {
+  return STAGE ? lds_stage_bytes<T>() : (size_t)(kWG / 64) * kRedBytes;
 }
 
 __device__ __forceinline__ uint32_t sat_add_q(uint32_t a, uint32_t b) {
@@ -218,12 +199,13 @@ __device__ __forceinline__ double pull_edges(const uint32_t* __restrict__ in_src
 
 // ------------------------------------------------------ multi-source SSSP --
 
-template <int M>
+// SH: delayed commits through the shadow, compiled apart from the kernel
+// that stages in LDS (as the PPR kernel).
+template <int M, bool SH>
 __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
   __shared__ uint32_t s_hub[kWG / 64][kQ];
   __shared__ int s_any;
   __shared__ uint32_t s_lane[kQ];
-  __shared__ uint32_t s_slot[kWG / 64][kStageRows];
   const uint32_t b = blockIdx.y, NB = a.NB, k = a.k;
   // batch already converged (call mode) or without running queries (serving)
   if (a.bactive ? a.bactive[b] == 0 : a.changed[k * NB + b] == 0) return;
@@ -241,13 +223,15 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
   if (tid < kQ) s_lane[tid] = 0;
   __syncthreads();
   uint32_t any = 0;
-  // Delayed mode without a shadow: stage in registers, commit every per rows.
-  const bool regs = M == kDelayed && shadow == nullptr;
-  // rows per wavefront between commits (the host stages in registers only for d <= kRegStageMaxD)
+  // Delayed mode without a shadow: stage in LDS, commit every per rows.
+  constexpr bool lds = M == kDelayed && !SH;
+  // rows per wavefront between commits (the host stages in LDS only for d <= kLdsStageMaxD)
   const uint32_t per_rows = (uint32_t)(((uint64_t)a.d + kWG / 64 - 1) / (kWG / 64));
   const uint32_t per = min(per_rows, kStageRows);
-  RegStage<uint32_t> rs;
-  rs.slot = s_slot[wv];
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  LdsStage<uint32_t> ls;
+  ls.rows = reinterpret_cast<uint32_t*>(s_dyn) + (size_t)wv * kStageRows * kQ;
+  ls.slot = reinterpret_cast<uint32_t*>(s_dyn + (size_t)(kWG / 64) * kStageRows * kQ * sizeof(uint32_t)) + wv * kStageRows;
   ShadowWalk sw(t0, t0 < t1 ? tile_v[t0] : 0u, wv);
 
   for (uint32_t t = t0; t < t1; ++t) {
@@ -266,7 +250,7 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
         any |= nw < old;
         if constexpr (M == kSync) dout[(size_t)p * kQ + lane] = nw;
         else if constexpr (M == kAsync) st_q(dout + (size_t)p * kQ + lane, nw);
-        else if (regs) rs.push(p, nw, per, dout, lane);
+        else if constexpr (lds) ls.push(p, nw, per, dout, lane, true);
         else {
           shadow[(size_t)v0 * kQ + lane] = nw;
           sw.staged(tile_v, a.g.cpos, shadow, dout, t, v0, true, per_rows, wv, lane, true);
@@ -282,7 +266,7 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
         any |= nw < old;
         if constexpr (M == kSync) dout[(size_t)p * kQ + lane] = nw;
         else if constexpr (M == kAsync) st_q(dout + (size_t)p * kQ + lane, nw);
-        else if (regs) rs.push(p, nw, per, dout, lane);
+        else if constexpr (lds) ls.push(p, nw, per, dout, lane, true);
         else {
           shadow[(size_t)v * kQ + lane] = nw;
           sw.staged(tile_v, a.g.cpos, shadow, dout, t, v, false, per_rows, wv, lane, true);
@@ -290,7 +274,7 @@ __global__ __launch_bounds__(kWG) void mbf_sweep_kernel(MbfArgs a) {
       }
     }
     if (M == kDelayed && t + 1 == t1) {  // the end of the block
-      if (regs) rs.flush(dout, lane);
+      if constexpr (lds) ls.flush(dout, lane, true);
       else sw.finish(tile_v, a.g.cpos, shadow, dout, t1, wv, lane, true);
     }
   }
@@ -355,10 +339,12 @@ __global__ __launch_bounds__(kWG) void mbf_out_kernel(const uint32_t* d, const u
 // delayed) sweeps create, which synchronous sweeps do not have because they
 // conserve mass exactly.
 
-template <int M, typename T>
+// SH: delayed commits through the shadow (d beyond what a wavefront stages
+// in LDS); compiled apart from the LDS-staging kernel so that neither carries
+// the other's state.
+template <int M, typename T, bool SH>
 __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
   __shared__ double s_hub[kWG / 64][kQ];
-  __shared__ double s_red[3][kWG / 64][kQ];
   __shared__ int s_last;
   const uint32_t b = blockIdx.y, NB = a.NB, k = a.k;
   // batch already converged (call mode) or without running queries (serving)
@@ -388,8 +374,8 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
   const uint32_t t0 = cst(a.g.work_t)[w], t1 = cst(a.g.work_t)[w + 1];
   double r_loc = 0.0, dm_loc = 0.0, m_loc = 0.0;
   // Delayed mode without a shadow: stage in LDS, commit every per rows.
-  const bool lds = M == kDelayed && shadow == nullptr;
-  // rows per wavefront between commits (the host stages in LDS only for d <= kRegStageMaxD)
+  constexpr bool lds = M == kDelayed && !SH;
+  // rows per wavefront between commits (the host stages in LDS only for d <= kLdsStageMaxD)
   const uint32_t per_rows = (uint32_t)(((uint64_t)a.d + kWG / 64 - 1) / (kWG / 64));
   const uint32_t per = min(per_rows, kStageRows);
   ShadowWalk sw(t0, t0 < t1 ? tile_v[t0] : 0u, wv);
@@ -398,6 +384,12 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
   LdsStage<T> ls;
   ls.rows = reinterpret_cast<T*>(s_dyn) + (size_t)wv * kStageRows * kQ;
   ls.slot = reinterpret_cast<uint32_t*>(s_dyn + (size_t)(kWG / 64) * kStageRows * kQ * sizeof(T)) + wv * kStageRows;
+  // This wavefront's partials [3][kQ]: over its own staged rows when staging
+  // (free after its last flush), else in a region of their own.
+  constexpr size_t red_stride = lds ? kStageRows * kQ * sizeof(T) : kRedBytes;
+  auto red = [&](uint32_t j, uint32_t wave) -> double& {
+    return reinterpret_cast<double*>(s_dyn + (size_t)wave * red_stride)[j * kQ + lane];
+  };
 
   // Called by every lane of the wavefront (frozen queries included).
   auto update = [&](uint32_t v, double acc) {
@@ -414,12 +406,12 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
       if (dg == 0) dm_loc += xn;
       if constexpr (M == kSync) cout[(size_t)p * kQ + lane] = cn;
       else if constexpr (M == kAsync) st_q(cout + (size_t)p * kQ + lane, cn);
-      else if (!lds) shadow[(size_t)v * kQ + lane] = cn;
+      else if constexpr (SH) shadow[(size_t)v * kQ + lane] = cn;
     }
     // outside the branch, so that the slot (written by lane 0) and the count
     // are the same for the whole wavefront; a frozen lane stores nothing
-    if (lds) ls.push(p, cn, per, cout, lane, live);
-    else if (M == kDelayed)
+    if constexpr (lds) ls.push(p, cn, per, cout, lane, live);
+    else if constexpr (SH)
       sw.staged(tile_v, a.g.cpos, shadow, cout, cur_t, v, tile_v[cur_t + 1] - tile_v[cur_t] == 1, per_rows, wv,
                 lane, live);
   };
@@ -438,22 +430,21 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
         update(v, pull_edges<M, T>(a.g.in_src, cin, in_ptr[v], in_ptr[v + 1], 0, 1, lane));
     }
     if (M == kDelayed && t + 1 == t1) {  // the end of the block
-      if (lds) ls.flush(cout, lane, live);
+      if constexpr (lds) ls.flush(cout, lane, live);
       else sw.finish(tile_v, a.g.cpos, shadow, cout, t1, wv, lane, live);
     }
   }
 
   // Per-query partials of this worker, then the last worker of the batch
   // folds them in worker order.
-  s_red[0][wv][lane] = r_loc;
-  s_red[1][wv][lane] = dm_loc;
-  s_red[2][wv][lane] = m_loc;
+  red(0, wv) = r_loc;
+  red(1, wv) = dm_loc;
+  red(2, wv) = m_loc;
   __syncthreads();
   double* part = a.part + ((size_t)w * NB + b) * 3 * kQ;
   if (wv == 0) {
 #pragma unroll
-    for (int j = 0; j < 3; ++j)
-      part[j * kQ + lane] = s_red[j][0][lane] + s_red[j][1][lane] + s_red[j][2][lane] + s_red[j][3][lane];
+    for (int j = 0; j < 3; ++j) part[j * kQ + lane] = red(j, 0) + red(j, 1) + red(j, 2) + red(j, 3);
   }
   __threadfence();
   __syncthreads();
@@ -700,9 +691,10 @@ hipError_t launch_mbf_init(uint32_t* d0, uint32_t* d1, const uint32_t* cpos, con
 
 hipError_t launch_mbf_sweep(int mode, const MbfArgs& a, hipStream_t s) {
   const dim3 grid(a.g.P, a.NB);
-  if (mode == kSync) mbf_sweep_kernel<kSync><<<grid, kWG, 0, s>>>(a);
-  else if (mode == kAsync) mbf_sweep_kernel<kAsync><<<grid, kWG, 0, s>>>(a);
-  else mbf_sweep_kernel<kDelayed><<<grid, kWG, 0, s>>>(a);
+  if (mode == kSync) mbf_sweep_kernel<kSync, false><<<grid, kWG, 0, s>>>(a);
+  else if (mode == kAsync) mbf_sweep_kernel<kAsync, false><<<grid, kWG, 0, s>>>(a);
+  else if (a.shadow) mbf_sweep_kernel<kDelayed, true><<<grid, kWG, 0, s>>>(a);
+  else mbf_sweep_kernel<kDelayed, false><<<grid, kWG, lds_stage_bytes<uint32_t>(), s>>>(a);
   return hipGetLastError();
 }
 
@@ -728,9 +720,10 @@ hipError_t launch_mppr_init(bool f64, void* x, void* c0, void* c1, const uint32_
 template <typename T>
 static void mppr_sweep_dispatch(int mode, const MpprArgs& a, hipStream_t s) {
   const dim3 grid(a.g.P, a.NB);
-  if (mode == kSync) mppr_sweep_kernel<kSync, T><<<grid, kWG, 0, s>>>(a);
-  else if (mode == kAsync) mppr_sweep_kernel<kAsync, T><<<grid, kWG, 0, s>>>(a);
-  else mppr_sweep_kernel<kDelayed, T><<<grid, kWG, a.shadow ? 0 : lds_stage_bytes<T>(), s>>>(a);
+  if (mode == kSync) mppr_sweep_kernel<kSync, T, false><<<grid, kWG, mppr_dyn_bytes<T, false>(), s>>>(a);
+  else if (mode == kAsync) mppr_sweep_kernel<kAsync, T, false><<<grid, kWG, mppr_dyn_bytes<T, false>(), s>>>(a);
+  else if (a.shadow) mppr_sweep_kernel<kDelayed, T, true><<<grid, kWG, mppr_dyn_bytes<T, false>(), s>>>(a);
+  else mppr_sweep_kernel<kDelayed, T, false><<<grid, kWG, mppr_dyn_bytes<T, true>(), s>>>(a);
 }
 
 hipError_t launch_mppr_sweep(int mode, bool f64, const MpprArgs& a, hipStream_t s) {

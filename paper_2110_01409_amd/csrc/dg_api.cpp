@@ -1282,9 +1282,9 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
   uint32_t* srcd = static_cast<uint32_t*>(al.get((size_t)k * 4, s));
   uint32_t* b0 = static_cast<uint32_t*>(al.get(vals * 4, s));
   uint32_t* b1 = mode == DG_SYNC ? static_cast<uint32_t*>(al.get(vals * 4, s)) : nullptr;
-  // Delayed commits stage in registers up to kRegStageMaxD, beyond in a shadow.
+  // Delayed commits stage in LDS up to kLdsStageMaxD, beyond in a shadow.
   const uint32_t d_eff = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_vb)) : 0u;
-  const bool need_sh = mode == DG_DELAYED && d_eff > kRegStageMaxD;
+  const bool need_sh = mode == DG_DELAYED && d_eff > kLdsStageMaxD;
   uint32_t* sh = need_sh ? static_cast<uint32_t*>(al.get((size_t)NB * g->n * kBatchQ * 4, s)) : nullptr;
   uint32_t* changed = static_cast<uint32_t*>(al.get(((size_t)max_sweeps + 1) * NB * 4, s));
   uint32_t* outd = out_on_device ? out_dist : static_cast<uint32_t*>(al.get((size_t)k * g->n * 4, s));
@@ -1400,8 +1400,8 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   void* c0 = al.get(vals * esz, s);
   void* c1 = mode == DG_SYNC ? al.get(vals * esz, s) : nullptr;
   const uint32_t d_eff = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_vb)) : 0u;
-  // Delayed commits stage in LDS up to kRegStageMaxD, beyond in a shadow.
-  const bool need_sh = mode == DG_DELAYED && d_eff > kRegStageMaxD;
+  // Delayed commits stage in LDS up to kLdsStageMaxD, beyond in a shadow.
+  const bool need_sh = mode == DG_DELAYED && d_eff > kLdsStageMaxD;
   void* sh = need_sh ? al.get(xs * esz, s) : nullptr;
   double* resid = static_cast<double*>(al.get(((size_t)max_sweeps + 1) * NB * 8, s));
   uint32_t* count = static_cast<uint32_t*>(al.get(((size_t)max_sweeps + 1) * NB * 4, s));

@@ -172,11 +172,11 @@ struct BfArgs {
 constexpr double kStallTols = 2.0;
 constexpr double kStallRatio = 0.9;
 
-// Batched queries: rows a wavefront stages in registers in delayed mode, and
-// the largest commit interval staged that way (four wavefronts per
-// workgroup); larger intervals stage in a global shadow array.
+// Batched queries: rows a wavefront stages in LDS in delayed mode, and the
+// largest commit interval staged that way (four wavefronts per workgroup);
+// larger intervals stage in a global shadow array.
 constexpr uint32_t kStageRows = 16;
-constexpr uint32_t kRegStageMaxD = kStageRows * (kWG / 64);
+constexpr uint32_t kLdsStageMaxD = kStageRows * (kWG / 64);
 
 // Batched queries (64 per batch, vertex-major [slot][64] values).
 struct MbfArgs {

@@ -87,10 +87,10 @@ namespace {
 
 bool f64(const dg_server* s) { return s->o.dtype == DG_F64; }
 
-// Delayed commits stage per wavefront (SSSP in registers, PPR in LDS) up to
-// kRegStageMaxD, and need the per-batch shadow array only beyond.
+// Delayed commits stage per wavefront in LDS up to kLdsStageMaxD, and need
+// the per-batch shadow array only beyond.
 bool delayed_shadow(const dg_server* s, const dg_graph* g) {
-  return s->o.mode == DG_DELAYED && std::max(1u, std::min(s->o.d, g->max_block_vb)) > kRegStageMaxD;
+  return s->o.mode == DG_DELAYED && std::max(1u, std::min(s->o.d, g->max_block_vb)) > kLdsStageMaxD;
 }
 
 size_t batch_bytes(const dg_server* s, const dg_graph* g, int kind) {
