@@ -106,12 +106,17 @@ __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
 }
 
 // Largest i in [0, nv) with s_ptr[i] <= e, given s_ptr[0] <= e < s_ptr[nv]:
-// the tile-local vertex that owns edge slot e.
+// the tile-local vertex that owns edge slot e.  A fixed number of halvings
+// over s_ptr[min(i, nv)] (which exceeds e from nv on), without branches, so
+// that the compiler can interleave its LDS reads with other work; every read
+// index is <= nv <= kTileV.
+static_assert((kTileV & (kTileV - 1)) == 0, "the owner search halves a power-of-two range");
 __device__ __forceinline__ uint32_t owner_of(const uint32_t* s_ptr, uint32_t nv, uint32_t e) {
-  uint32_t lo = 0, hi = nv;
-  while (hi - lo > 1) {
-    const uint32_t mid = (lo + hi) >> 1;
-    if (s_ptr[mid] <= e) lo = mid; else hi = mid;
+  uint32_t lo = 0;
+#pragma unroll
+  for (uint32_t step = kTileV / 2; step > 0; step >>= 1) {
+    const uint32_t c = lo + step;
+    lo = s_ptr[min(c, nv)] <= e ? c : lo;
   }
   return lo;
 }
@@ -423,6 +428,10 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
           }
         }
       }
+      // The owner of the window's first slot, searched while the gathers are
+      // in flight.
+      const uint32_t es = e0 > eb ? e0 : eb;
+      const uint32_t i0 = (nv > 1 && active) ? owner_of(s_ptr, nv, es) : 0u;
       // Prefetch the next chunk's indices: the next chunk of this tile, else
       // the first chunk of the next tile (its window starts at this tile's
       // last edge rounded down), else nothing.
@@ -441,9 +450,8 @@ __global__ __launch_bounds__(kSweepWG) void pr_sweep_kernel(PrArgs a) {
         q = wave_sum(q);
         if (lane == 0) atomicAdd(&s_acc[0], q);
       } else if (active) {
-        const uint32_t es = e0 > eb ? e0 : eb;
         const uint32_t en = (e0 + EPT < ee) ? e0 + EPT : ee;
-        uint32_t i = owner_of(s_ptr, nv, es);
+        uint32_t i = i0;
         uint32_t bound = s_ptr[i + 1], b2 = s_ptr[min(i + 2, nv)], b3 = s_ptr[min(i + 3, nv)];
         double part = 0.0;
 #pragma unroll
@@ -749,6 +757,10 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
           }
         }
       }
+      // The owner of the window's first slot, searched while the gathers are
+      // in flight.
+      const uint32_t es = e0 > eb ? e0 : eb;
+      const uint32_t i0 = (nv > 1 && active) ? owner_of(s_ptr, nv, es) : 0u;
       const bool last = cb + CH >= ee;
       const uint32_t nb = !last ? cb + CH : (more ? (ee & ~3u) : cb);
       const uint32_t lim = !last ? ee : (more ? ee_next : cb);
@@ -765,9 +777,8 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
         q = wave_min(q);
         if (lane == 0 && q != kInf) atomicMin(&s_acc[0], q);
       } else if (active) {
-        const uint32_t es = e0 > eb ? e0 : eb;
         const uint32_t en = (e0 + EPT < ee) ? e0 + EPT : ee;
-        uint32_t i = owner_of(s_ptr, nv, es);
+        uint32_t i = i0;
         uint32_t bound = s_ptr[i + 1], b2 = s_ptr[min(i + 2, nv)], b3 = s_ptr[min(i + 3, nv)];
         uint32_t part = kInf;
 #pragma unroll
