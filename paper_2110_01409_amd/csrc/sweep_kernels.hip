@@ -173,40 +173,44 @@ __device__ __forceinline__ void load_win(const uint32_t* stream, uint32_t nb, ui
   }
 }
 
-// The same for a stream of one-byte weights: EPT bytes per thread in one
-// load (4-byte aligned, as buffer loads need), widened to uint32.
+// A thread's window of EPT edge weights for one chunk, from whichever stream
+// the graph keeps.  One-byte weights (W8) stay packed four to a register, as
+// one EPT-byte load brought them, and are unpacked where they are used; the
+// widened form would hold EPT registers per window, two windows at a time.
+template <int EPT, bool W8>
+struct WeightWin;
+
 template <int EPT>
-__device__ __forceinline__ void load_win_u8(const uint8_t* stream, uint32_t nb, uint32_t lim, uint32_t tid,
-                                            uint32_t (&u)[EPT]) {
+struct WeightWin<EPT, true> {
   static_assert(EPT == 8 || EPT == 16, "one 8- or 16-byte load per thread");
-  const uint32_t end = (lim + (EPT - 1)) & ~(uint32_t)(EPT - 1);
-  const rsrc_t r = make_rsrc(stream + nb, end > nb ? end - nb : 0u);
-  if constexpr (EPT == 16) {
-    const v4u q = __builtin_amdgcn_raw_buffer_load_b128(r, tid * 16u, 0, 0);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      u[j] = (q.x >> (8 * j)) & 255u;
-      u[4 + j] = (q.y >> (8 * j)) & 255u;
-      u[8 + j] = (q.z >> (8 * j)) & 255u;
-      u[12 + j] = (q.w >> (8 * j)) & 255u;
-    }
-  } else {
-    const v2u q = __builtin_amdgcn_raw_buffer_load_b64(r, tid * 8u, 0, 0);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      u[j] = (q.x >> (8 * j)) & 255u;
-      u[4 + j] = (q.y >> (8 * j)) & 255u;
+  uint32_t q[EPT / 4] = {};
+  __device__ __forceinline__ void load(const Topology& g, uint32_t nb, uint32_t lim, uint32_t tid) {
+    // window [nb + EPT tid, ...) of the byte stream; nb is 4-byte aligned, as buffer loads need
+    const uint32_t end = (lim + (EPT - 1)) & ~(uint32_t)(EPT - 1);
+    const rsrc_t r = make_rsrc(g.in_w8 + nb, end > nb ? end - nb : 0u);
+    if constexpr (EPT == 16) {
+      const v4u v = __builtin_amdgcn_raw_buffer_load_b128(r, tid * 16u, 0, 0);
+      q[0] = v.x;
+      q[1] = v.y;
+      q[2] = v.z;
+      q[3] = v.w;
+    } else {
+      const v2u v = __builtin_amdgcn_raw_buffer_load_b64(r, tid * 8u, 0, 0);
+      q[0] = v.x;
+      q[1] = v.y;
     }
   }
-}
+  __device__ __forceinline__ uint32_t at(int j) const { return (q[j >> 2] >> (8 * (j & 3))) & 255u; }
+};
 
-// Weights of the next chunk, from whichever stream the graph keeps.
 template <int EPT>
-__device__ __forceinline__ void load_weights(const Topology& g, uint32_t nb, uint32_t lim, uint32_t tid,
-                                             uint32_t (&u)[EPT]) {
-  if (g.in_w8) load_win_u8<EPT>(g.in_w8, nb, lim, tid, u);
-  else load_win<EPT>(g.in_w, nb, lim, tid, u);
-}
+struct WeightWin<EPT, false> {
+  uint32_t w[EPT] = {};
+  __device__ __forceinline__ void load(const Topology& g, uint32_t nb, uint32_t lim, uint32_t tid) {
+    load_win<EPT>(g.in_w, nb, lim, tid, w);
+  }
+  __device__ __forceinline__ uint32_t at(int j) const { return w[j]; }
+};
 
 // Gather of a published value; out-of-range offsets read 0.  Asynchronous
 // and delayed sweeps read with the agent-scope coherence bit (sc1), the
@@ -662,7 +666,8 @@ __global__ __launch_bounds__(kWG) void pr_init_kernel(T* x, T* c0, T* c1, const 
 
 // LOCAL: as for pr_sweep_kernel, reads of this worker's own vertices come
 // from its shadow (delayed mode with the per-vertex shadow only).
-template <int M, bool LOCAL, int V>
+// W8: the graph keeps its weights as bytes (in_w8), else as 4-byte words.
+template <int M, bool LOCAL, int V, bool W8>
 __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
   constexpr int EPT = ept_of(V);
   constexpr uint32_t CH = kSweepWG * EPT;  // edge slots per chunk
@@ -696,7 +701,8 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
   const uint32_t bv0 = tile_v[t0], bv1 = tile_v[t1];  // this worker's vertex block
 
   uint32_t v0 = tile_v[t0];
-  uint32_t u[EPT], wt[EPT];  // next chunk's indices and weights, loaded one chunk ahead
+  uint32_t u[EPT];  // next chunk's indices and weights, loaded one chunk ahead
+  WeightWin<EPT, W8> wt;
   uint32_t p_n = 0, nxt = 0, nxt_end = 0;
   if (t0 < t1) {
     const uint32_t nv0 = tile_v[t0 + 1] - v0;
@@ -705,7 +711,7 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
     const uint32_t b0 = as_const(a.g.in_ptr)[v0] & ~3u;
     const uint32_t l0 = as_const(a.g.in_ptr)[tile_v[t0 + 1]];
     load_win<EPT>(a.g.in_src, b0, l0, tid, u);
-    load_weights<EPT>(a.g, b0, l0, tid, wt);
+    wt.load(a.g, b0, l0, tid);
     p_n = a.g.cpos[min(v0 + tid, n - 1)];
   }
   for (uint32_t t = t0; t < t1; ++t) {
@@ -728,7 +734,8 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
       const uint32_t e0 = cb + tid * EPT;
       const bool active = (e0 < ee) && (e0 + EPT > eb);
       bool ok[EPT];
-      uint32_t du[EPT], wc[EPT];
+      uint32_t du[EPT];
+      const WeightWin<EPT, W8> wc = wt;
 #pragma unroll
       for (int j = 0; j < EPT; ++j) {
         ok[j] = (e0 + j >= eb) & (e0 + j < ee);
@@ -744,7 +751,6 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
         if constexpr (!all_in_flight(V)) {
           if (inres) du[j] = rt.lds[ri];
         }
-        wc[j] = wt[j];
       }
       if constexpr (all_in_flight(V)) {
         if (rt.res) {
@@ -765,11 +771,11 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
       const uint32_t nb = !last ? cb + CH : (more ? (ee & ~3u) : cb);
       const uint32_t lim = !last ? ee : (more ? ee_next : cb);
       load_win<EPT>(a.g.in_src, nb, lim, tid, u);
-      load_weights<EPT>(a.g, nb, lim, tid, wt);
+      wt.load(a.g, nb, lim, tid);
       if (last) prefetch_next();
       uint32_t cand[EPT];
 #pragma unroll
-      for (int j = 0; j < EPT; ++j) cand[j] = ok[j] ? sat_add(du[j], wc[j]) : kInf;
+      for (int j = 0; j < EPT; ++j) cand[j] = ok[j] ? sat_add(du[j], wc.at(j)) : kInf;
       if (nv == 1) {
         uint32_t q = kInf;
 #pragma unroll
@@ -799,7 +805,7 @@ __global__ __launch_bounds__(kSweepWG) void bf_sweep_kernel(BfArgs a) {
     if (eb >= ee) {
       if (more) {
         load_win<EPT>(a.g.in_src, ee & ~3u, ee_next, tid, u);
-        load_weights<EPT>(a.g, ee & ~3u, ee_next, tid, wt);
+        wt.load(a.g, ee & ~3u, ee_next, tid);
       }
       prefetch_next();
     }
@@ -1074,8 +1080,13 @@ hipError_t launch_bf_gather(const uint32_t* d, const uint32_t* cpos, uint32_t n,
 
 template <int M, bool LOCAL, int V>
 static void bf_sweep_go(const BfArgs& a, size_t lds, hipStream_t s) {
-  allow_dyn_lds<bf_sweep_kernel<M, LOCAL, V>>();
-  bf_sweep_kernel<M, LOCAL, V><<<a.g.P, kSweepWG, lds, s>>>(a);
+  if (a.g.in_w8) {
+    allow_dyn_lds<bf_sweep_kernel<M, LOCAL, V, true>>();
+    bf_sweep_kernel<M, LOCAL, V, true><<<a.g.P, kSweepWG, lds, s>>>(a);
+  } else {
+    allow_dyn_lds<bf_sweep_kernel<M, LOCAL, V, false>>();
+    bf_sweep_kernel<M, LOCAL, V, false><<<a.g.P, kSweepWG, lds, s>>>(a);
+  }
 }
 
 template <int M, bool LOCAL>
