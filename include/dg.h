@@ -154,8 +154,11 @@ dg_status dg_set_allocator(dg_alloc_fn alloc, dg_free_fn free_fn, void* ctx);
  *   workers       persistent workgroups that own the contiguous vertex blocks
  *                 of the single-query sweeps; 0 = automatic (one 1024-thread
  *                 workgroup per compute unit, at most one per tile).  The
- *                 batched calls use a partition of their own (five 256-thread
- *                 workgroups per compute unit).
+ *                 batched calls use partitions of their own, one per
+ *                 algorithm: 256-thread workgroups, eight per compute unit
+ *                 for SSSP (dg_sssp_batch, the server's SSSP pools) and
+ *                 five for personalised PageRank (dg_ppr_batch, its PPR
+ *                 pools).
  *   hot_vertices  at most this many sources with the largest out-degree (and
  *                 above-average out-degree) get their published value stored
  *                 in a compact region after the n regular slots, so gathers
@@ -530,13 +533,24 @@ dg_status dg_tune(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, uint32_
  * k (1..1024) sources, every commit mode and interval (sync, async, delayed
  * d in {16, 64, 256, whole}) for 3, 5 and 8 batched workgroups per compute
  * unit, each run three times; the least median time wins, and the graph's
- * batched partition (used by dg_sssp_batch, dg_ppr_batch and the server) is
- * left at the chosen size.  The default is delayed d = 64 with 5 workgroups
- * per compute unit.  Fills dg_tuning as dg_tune (predicted_seconds = the
+ * batched partition for that algorithm (SSSP: dg_sssp_batch and the server's
+ * SSSP pools; PageRank: dg_ppr_batch and its PPR pools) is left at the
+ * chosen size.  The default is delayed d = 64 with 8 (SSSP) or 5 (PageRank)
+ * workgroups per compute unit.  A live server's PPR pools resize their
+ * per-worker partials at their next sweep.  Fills dg_tuning as dg_tune (predicted_seconds = the
  * measured median; sweep_variant and resident_vertices are unchanged);
  * nothing is cached.  flags must be 0. */
 dg_status dg_tune_batch(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, const uint32_t* sources, uint32_t k,
                         uint32_t flags, dg_tuning* out, void* hip_stream);
+
+/* Re-partitions the batched calls of one algorithm (DG_ALGO_SSSP:
+ * dg_sssp_batch and the server's SSSP pools; DG_ALGO_PAGERANK: dg_ppr_batch
+ * and its PPR pools) over `workers` 256-thread workgroups per batch (0 = the
+ * default: 8 per compute unit for SSSP, 5 for PageRank, rounded down to a
+ * multiple of 8), at most one per tile, as dg_tune_batch leaves it after
+ * tuning.  A live server's PPR pools resize their per-worker partials at
+ * their next sweep.  Must not overlap a sweep call on the same graph. */
+dg_status dg_graph_repartition_batch(dg_graph* g, dg_algo algo, uint32_t workers, void* hip_stream);
 /* The in-process cache of tuning results: cleared, written to and merged
  * from a text file (one result per line, comments start with '#'). */
 dg_status dg_tune_cache_clear(void);

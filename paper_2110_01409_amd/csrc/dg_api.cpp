@@ -65,7 +65,11 @@ using dg::host::kEventRing;
 using dg::host::kHostReactUs;
 using dg::host::kMaxLookahead;
 using dg::host::kWorkersPerCU;
-using dg::host::kBatchWorkersPerCU;
+using dg::host::kBatchSsspWorkersPerCU;
+using dg::host::kBatchPprWorkersPerCU;
+using dg::host::kBatchSssp;
+using dg::host::kBatchPpr;
+using dg::host::BatchPart;
 using dg::host::kSetWorkersPerCU;
 using dg::host::topo_batch;
 using dg::host::build_layout;
@@ -123,10 +127,10 @@ Topology topo(const dg_graph* g) {
   return t;
 }
 
-Topology topo_batch(const dg_graph* g) {
+Topology topo_batch(const dg_graph* g, int which) {
   Topology t = topo(g);
-  t.work_t = g->work_tb;
-  t.P = g->Pb;
+  t.work_t = g->bp[which].work_t;
+  t.P = g->bp[which].P;
   return t;
 }
 
@@ -190,11 +194,19 @@ uint32_t commits_per_sweep(const dg_graph* g, uint32_t d, uint32_t cap, bool sha
 // ... of each tile; wavefront 0 alone the row of a single-vertex tile) and
 // commits them once ceil(d / (kWG / 64)) are staged, and at the end of the
 // worker's block.
-uint32_t batch_commits_per_sweep(const dg_graph* g, uint32_t d) {
+// Splits the tiles tv (first in-edges te0) into P batched workers (host side).
+void plan_batch_part(const std::vector<uint32_t>& tv, const std::vector<uint32_t>& te0, uint32_t P, BatchPart& bp) {
+  bp.P = P;
+  build_workers(tv, te0, P, bp.work_t_h);
+  bp.max_block_v = 1;
+  for (uint32_t w = 0; w < P; ++w) bp.max_block_v = std::max(bp.max_block_v, tv[bp.work_t_h[w + 1]] - tv[bp.work_t_h[w]]);
+}
+
+uint32_t batch_commits_per_sweep(const dg_graph* g, int which, uint32_t d) {
   constexpr uint32_t waves = kWG / 64;
   const uint64_t per = ((uint64_t)d + waves - 1) / waves;
   const std::vector<uint32_t>& tv = g->tile_v_h;
-  const std::vector<uint32_t>& wt = g->work_tb_h;
+  const std::vector<uint32_t>& wt = g->bp[which].work_t_h;
   uint64_t c = 0;
   for (size_t w = 0; w + 1 < wt.size(); ++w)
     for (uint32_t wv = 0; wv < waves; ++wv) {
@@ -797,12 +809,10 @@ dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
   g->work_t_h = work_t;
   for (uint32_t wk = 0; wk < P; ++wk)
     g->max_block_v = std::max(g->max_block_v, L.tile_v[work_t[wk + 1]] - L.tile_v[work_t[wk]]);
-  std::vector<uint32_t> work_tb;
-  g->Pb = plan_workers(L, 0u, g->cus, kBatchWorkersPerCU);
-  build_workers(L.tile_v, L.tile_e0, g->Pb, work_tb);
-  for (uint32_t wk = 0; wk < g->Pb; ++wk)
-    g->max_block_vb = std::max(g->max_block_vb, L.tile_v[work_tb[wk + 1]] - L.tile_v[work_tb[wk]]);
-  g->work_tb_h = work_tb;
+  dg::host::plan_batch_part(L.tile_v, L.tile_e0, plan_workers(L, 0u, g->cus, kBatchSsspWorkersPerCU),
+                            g->bp[kBatchSssp]);
+  dg::host::plan_batch_part(L.tile_v, L.tile_e0, plan_workers(L, 0u, g->cus, kBatchPprWorkersPerCU),
+                            g->bp[kBatchPpr]);
 
   uint32_t* w8_words = nullptr;
   struct Up {
@@ -810,8 +820,9 @@ dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
     const std::vector<uint32_t>* src;
   } ups[] = {{&g->in_ptr, &L.in_ptr}, {&g->in_src, &L.in_src}, {&g->in_w, &L.in_w}, {&w8_words, &L.w8pack},
              {&g->out_deg, &L.out_deg}, {&g->cpos, &L.cpos}, {&g->tile_v, &L.tile_v}, {&g->work_t, &work_t},
-             {&g->wseg, &g->wseg_h}, {&g->wgraph, &g->wgraph_h}, {&g->work_tb, &work_tb},
-             {&g->segv_d, &g->seg_v}};
+             {&g->wseg, &g->wseg_h}, {&g->wgraph, &g->wgraph_h},
+             {&g->bp[kBatchSssp].work_t, &g->bp[kBatchSssp].work_t_h},
+             {&g->bp[kBatchPpr].work_t, &g->bp[kBatchPpr].work_t_h}, {&g->segv_d, &g->seg_v}};
   for (auto& u : ups) {
     if (u.src->empty()) continue;
     const size_t bytes = u.src->size() * sizeof(uint32_t);
@@ -1283,7 +1294,7 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
   uint32_t* b0 = static_cast<uint32_t*>(al.get(vals * 4, s));
   uint32_t* b1 = mode == DG_SYNC ? static_cast<uint32_t*>(al.get(vals * 4, s)) : nullptr;
   // Delayed commits stage in LDS up to kLdsStageMaxD, beyond in a shadow.
-  const uint32_t d_eff = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_vb)) : 0u;
+  const uint32_t d_eff = mode == DG_DELAYED ? std::max(1u, std::min(d, g->bp[kBatchSssp].max_block_v)) : 0u;
   const bool need_sh = mode == DG_DELAYED && d_eff > kLdsStageMaxD;
   uint32_t* sh = need_sh ? static_cast<uint32_t*>(al.get((size_t)NB * g->n * kBatchQ * 4, s)) : nullptr;
   uint32_t* changed = static_cast<uint32_t*>(al.get(((size_t)max_sweeps + 1) * NB * 4, s));
@@ -1298,7 +1309,7 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
   DG_HIP(launch_mbf_init(b0, b1, g->cpos, srcd, k, g->n, g->K, NB, s));
   MbfArgs a;
   std::memset(&a, 0, sizeof a);  // call mode: no serving fields
-  a.g = topo_batch(g);
+  a.g = topo_batch(g, kBatchSssp);
   a.changed = changed;
   a.hchanged = static_cast<uint32_t*>(poll.dev);
   a.shadow = sh;
@@ -1365,9 +1376,9 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
       qe += (uint64_t)(bsweeps[b] ? bsweeps[b] : sweeps) * nq;
     }
     stats->sweeps = sweeps;
-    stats->workers = g->Pb;
+    stats->workers = g->bp[kBatchSssp].P;
     stats->tile_vertices = g->T ? (uint32_t)(((uint64_t)g->n + g->T / 2) / g->T) : 0u;
-    stats->commits = mode == DG_DELAYED ? dg::host::batch_commits_per_sweep(g, a.d) : 0u;
+    stats->commits = mode == DG_DELAYED ? dg::host::batch_commits_per_sweep(g, kBatchSssp, a.d) : 0u;
     stats->commit_interval = stats->commits ? (uint32_t)(((uint64_t)g->n + stats->commits / 2) / stats->commits) : 0u;
     stats->err_bound = 0.0;
     stats->residual = 0.0;
@@ -1399,7 +1410,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   void* x = al.get(xs * esz, s);
   void* c0 = al.get(vals * esz, s);
   void* c1 = mode == DG_SYNC ? al.get(vals * esz, s) : nullptr;
-  const uint32_t d_eff = mode == DG_DELAYED ? std::max(1u, std::min(d, g->max_block_vb)) : 0u;
+  const uint32_t d_eff = mode == DG_DELAYED ? std::max(1u, std::min(d, g->bp[kBatchPpr].max_block_v)) : 0u;
   // Delayed commits stage in LDS up to kLdsStageMaxD, beyond in a shadow.
   const bool need_sh = mode == DG_DELAYED && d_eff > kLdsStageMaxD;
   void* sh = need_sh ? al.get(xs * esz, s) : nullptr;
@@ -1409,7 +1420,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   double* scale = static_cast<double*>(al.get((size_t)2 * NB * kBatchQ * 8, s));
   double* rhist = f64 ? nullptr : static_cast<double*>(al.get((size_t)2 * NB * kBatchQ * 8, s));
   uint32_t* qdone = static_cast<uint32_t*>(al.get((size_t)NB * kBatchQ * 4, s));
-  double* part = static_cast<double*>(al.get((size_t)g->Pb * NB * 3 * kBatchQ * 8, s));
+  double* part = static_cast<double*>(al.get((size_t)g->bp[kBatchPpr].P * NB * 3 * kBatchQ * 8, s));
   double* qsum = static_cast<double*>(al.get((size_t)NB * kBatchQ * 8, s));
   double* qpart = static_cast<double*>(al.get((size_t)NB * 256 * kBatchQ * 8, s));
   double* outd = out_on_device ? out_scores : static_cast<double*>(al.get((size_t)k * g->n * 8, s));
@@ -1431,7 +1442,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
   DG_HIP(launch_mppr_init(f64, x, c0, c1, g->out_deg, g->cpos, srcd, k, g->n, g->K, NB, dang, s));
   MpprArgs a;
   std::memset(&a, 0, sizeof a);  // call mode: no serving fields
-  a.g = topo_batch(g);
+  a.g = topo_batch(g, kBatchPpr);
   a.x = x;
   a.shadow = sh;
   a.src = srcd;
@@ -1498,9 +1509,9 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
       qe += (uint64_t)(bsweeps[b] ? bsweeps[b] : sweeps) * nq;
     }
     stats->sweeps = sweeps;
-    stats->workers = g->Pb;
+    stats->workers = g->bp[kBatchPpr].P;
     stats->tile_vertices = g->T ? (uint32_t)(((uint64_t)g->n + g->T / 2) / g->T) : 0u;
-    stats->commits = mode == DG_DELAYED ? dg::host::batch_commits_per_sweep(g, a.d) : 0u;
+    stats->commits = mode == DG_DELAYED ? dg::host::batch_commits_per_sweep(g, kBatchPpr, a.d) : 0u;
     stats->commit_interval = stats->commits ? (uint32_t)(((uint64_t)g->n + stats->commits / 2) / stats->commits) : 0u;
     stats->err_bound = 0.0;
     stats->residual = last_r;
@@ -1590,9 +1601,10 @@ dg_status dg_graph_set_mapping(dg_graph* g, uint32_t sweep_variant, uint32_t res
   const uint32_t want = sweep_variant == DG_SWEEP_AUTO ? g->variant0 : sweep_variant;
   const bool narrow_now = g->variant == kNarrow, narrow_want = want == kNarrow;
   if (narrow_now != narrow_want) {
-    // The narrow variant has its own tile cap: rebuild the tiles, then both
-    // partitions over them (the batched kernels use the same tiles).
-    std::vector<uint32_t> tv, te0, wtb;
+    // The narrow variant has its own tile cap: rebuild the tiles, then every
+    // partition over them (the batched kernels use the same tiles).
+    std::vector<uint32_t> tv, te0;
+    BatchPart nb[2];
     try {
       build_tiles(g->in_ptr_h, g->n, tv, nullptr, narrow_want ? (uint32_t)kTileENarrow : (uint32_t)kTileE);
       te0.resize(tv.size());
@@ -1601,32 +1613,32 @@ dg_status dg_graph_set_mapping(dg_graph* g, uint32_t sweep_variant, uint32_t res
       return fail(DG_ERR_OUT_OF_MEMORY, "host allocation failed");
     }
     const uint32_t T = (uint32_t)tv.size() - 1;
-    uint32_t Pb = std::max(1u, std::min(g->cus * kBatchWorkersPerCU, T));
-    if (Pb > 8) Pb &= ~7u;
-    build_workers(tv, te0, Pb, wtb);
+    for (int b : {kBatchSssp, kBatchPpr}) {
+      uint32_t Pb = std::max(1u, std::min(g->cus * (b == kBatchSssp ? kBatchSsspWorkersPerCU : kBatchPprWorkersPerCU), T));
+      if (Pb > 8) Pb &= ~7u;
+      dg::host::plan_batch_part(tv, te0, Pb, nb[b]);
+    }
     DG_HIP(hipStreamSynchronize(s));
     uint32_t* tvd = static_cast<uint32_t*>(dev_alloc(g, tv.size() * 4, s));
-    uint32_t* wtbd = static_cast<uint32_t*>(dev_alloc(g, wtb.size() * 4, s));
-    if (!tvd || !wtbd) {
+    for (BatchPart& b : nb) b.work_t = static_cast<uint32_t*>(dev_alloc(g, b.work_t_h.size() * 4, s));
+    if (!tvd || !nb[0].work_t || !nb[1].work_t) {
       dev_free(g, tvd);
-      dev_free(g, wtbd);
+      for (BatchPart& b : nb) dev_free(g, b.work_t);
       return fail(DG_ERR_OUT_OF_MEMORY, "re-tiling allocation failed");
     }
     DG_HIP(hipMemcpyAsync(tvd, tv.data(), tv.size() * 4, hipMemcpyHostToDevice, s));
-    DG_HIP(hipMemcpyAsync(wtbd, wtb.data(), wtb.size() * 4, hipMemcpyHostToDevice, s));
+    for (BatchPart& b : nb)
+      DG_HIP(hipMemcpyAsync(b.work_t, b.work_t_h.data(), b.work_t_h.size() * 4, hipMemcpyHostToDevice, s));
     DG_HIP(hipStreamSynchronize(s));
     dev_free(g, g->tile_v);
-    dev_free(g, g->work_tb);
     g->tile_v = tvd;
-    g->work_tb = wtbd;
-    g->work_tb_h = wtb;
+    for (int b : {kBatchSssp, kBatchPpr}) {
+      dev_free(g, g->bp[b].work_t);
+      g->bp[b] = std::move(nb[b]);
+    }
     g->tile_v_h.swap(tv);
     g->tile_e0_h.swap(te0);
     g->T = T;
-    g->Pb = Pb;
-    g->max_block_vb = 1;
-    for (uint32_t w = 0; w < Pb; ++w)
-      g->max_block_vb = std::max(g->max_block_vb, g->tile_v_h[wtb[w + 1]] - g->tile_v_h[wtb[w]]);
     g->P = 0;  // forces the repartition below
   }
   g->variant = want;
@@ -1872,29 +1884,35 @@ dg_status dg_tune(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, uint32_
 
 namespace {
 
-// Re-partitions the batched kernels' tiles over Pb workers.
-dg_status set_batch_workers(dg_graph* g, uint32_t Pb, hipStream_t s) {
+// Re-partitions the tiles of batched partition `which` over Pb workers.
+dg_status set_batch_workers(dg_graph* g, int which, uint32_t Pb, hipStream_t s) {
   Pb = std::max(1u, std::min(Pb, g->T));
-  if (Pb == g->Pb) return DG_OK;
-  std::vector<uint32_t> wtb;
-  build_workers(g->tile_v_h, g->tile_e0_h, Pb, wtb);
+  if (Pb == g->bp[which].P) return DG_OK;
+  BatchPart nb;
+  dg::host::plan_batch_part(g->tile_v_h, g->tile_e0_h, Pb, nb);
   DG_HIP(hipStreamSynchronize(s));
-  uint32_t* d = static_cast<uint32_t*>(dev_alloc(g, wtb.size() * 4, s));
-  if (!d) return fail(DG_ERR_OUT_OF_MEMORY, "batched partition allocation failed");
-  DG_HIP(hipMemcpyAsync(d, wtb.data(), wtb.size() * 4, hipMemcpyHostToDevice, s));
+  nb.work_t = static_cast<uint32_t*>(dev_alloc(g, nb.work_t_h.size() * 4, s));
+  if (!nb.work_t) return fail(DG_ERR_OUT_OF_MEMORY, "batched partition allocation failed");
+  DG_HIP(hipMemcpyAsync(nb.work_t, nb.work_t_h.data(), nb.work_t_h.size() * 4, hipMemcpyHostToDevice, s));
   DG_HIP(hipStreamSynchronize(s));
-  dev_free(g, g->work_tb);
-  g->work_tb = d;
-  g->work_tb_h = wtb;
-  g->Pb = Pb;
-  g->max_block_vb = 1;
-  for (uint32_t w = 0; w < Pb; ++w) g->max_block_vb = std::max(g->max_block_vb, g->tile_v_h[wtb[w + 1]] - g->tile_v_h[wtb[w]]);
+  dev_free(g, g->bp[which].work_t);
+  g->bp[which] = std::move(nb);
   return DG_OK;
 }
 
 }  // namespace
 
 extern "C" {
+
+dg_status dg_graph_repartition_batch(dg_graph* g, dg_algo algo, uint32_t workers, void* hip_stream) {
+  g_last_error.clear();
+  if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (algo != DG_ALGO_PAGERANK && algo != DG_ALGO_SSSP) return fail(DG_ERR_INVALID_ARGUMENT, "unknown algorithm");
+  const int which = algo == DG_ALGO_SSSP ? kBatchSssp : kBatchPpr;
+  const uint32_t P =
+      workers ? workers : default_workers(g, which == kBatchSssp ? kBatchSsspWorkersPerCU : kBatchPprWorkersPerCU);
+  return set_batch_workers(g, which, P, static_cast<hipStream_t>(hip_stream));
+}
 
 dg_status dg_tune_batch(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, const uint32_t* sources, uint32_t k,
                         uint32_t flags, dg_tuning* out, void* hip_stream) {
@@ -1933,10 +1951,11 @@ dg_status dg_tune_batch(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, c
     return DG_OK;
   };
   dg_status st;
-  const uint32_t Pb_def = default_workers(g, kBatchWorkersPerCU);
+  const int which = algo == DG_ALGO_SSSP ? kBatchSssp : kBatchPpr;
+  const uint32_t Pb_def = default_workers(g, which == kBatchSssp ? kBatchSsspWorkersPerCU : kBatchPprWorkersPerCU);
   Spread def{};
   uint32_t sw_def = 0;
-  if ((st = set_batch_workers(g, Pb_def, s)) != DG_OK) return st;
+  if ((st = set_batch_workers(g, which, Pb_def, s)) != DG_OK) return st;
   if ((st = timed(DG_DELAYED, 64, def, sw_def)) != DG_OK) return st;
   struct Cand {
     dg_mode mode;
@@ -1950,7 +1969,7 @@ dg_status dg_tune_batch(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, c
   Cand bestc = {DG_DELAYED, 64};
   for (uint32_t per_cu : {3u, 5u, 8u}) {
     const uint32_t Pb = default_workers(g, per_cu);
-    if ((st = set_batch_workers(g, Pb, s)) != DG_OK) return st;
+    if ((st = set_batch_workers(g, which, Pb, s)) != DG_OK) return st;
     for (const Cand& c : cands) {
       Spread sp{};
       uint32_t sw = 0;
@@ -1963,15 +1982,15 @@ dg_status dg_tune_batch(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, c
       ++evaluated;
       if (sp.med < best.med) {
         best = sp;
-        bestP = g->Pb;
+        bestP = g->bp[which].P;
         bestc = c;
         best_sw = sw;
       }
     }
   }
-  if ((st = set_batch_workers(g, bestP, s)) != DG_OK) return st;
+  if ((st = set_batch_workers(g, which, bestP, s)) != DG_OK) return st;
   dg_tuning t{};
-  t.workers = g->Pb;
+  t.workers = g->bp[which].P;
   t.mode = bestc.mode;
   t.d = bestc.d;
   t.sweeps = best_sw;

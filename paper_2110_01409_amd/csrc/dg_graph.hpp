@@ -26,9 +26,21 @@ constexpr uint32_t kMaxSweeps = 1000000;
 // Default persistent workgroups per compute unit of the single-query sweeps:
 // one 1024-thread workgroup, whose LDS holds the resident table.
 constexpr uint32_t kWorkersPerCU = 1;
-// The same for the batched kernels (256 threads, no table).  Five measured
-// faster than eight on RMAT and banded graphs.
-constexpr uint32_t kBatchWorkersPerCU = 5;
+// The same for the batched kernels (256 threads, no table), one partition
+// per algorithm: on RMAT-22 the SSSP kernel runs 5-8% faster per batch-sweep
+// with eight than with five, the PPR kernel 2-5% slower.
+constexpr uint32_t kBatchSsspWorkersPerCU = 8;
+constexpr uint32_t kBatchPprWorkersPerCU = 5;
+// Which batched partition: SSSP (dg_sssp_batch, the server's SSSP pools) or
+// personalised PageRank (dg_ppr_batch, the server's PPR pools).
+enum BatchAlgo : int { kBatchSssp = 0, kBatchPpr = 1 };
+// A partition of the tiles into batched workers (the grid's x dimension).
+struct BatchPart {
+  uint32_t P = 0;                  // workers
+  uint32_t max_block_v = 1;        // most vertices any worker owns
+  uint32_t* work_t = nullptr;      // device [P + 1]: first tile of each worker
+  std::vector<uint32_t> work_t_h;  // host copy
+};
 // The same for the union graph of a set: smaller blocks, several sweep
 // workgroups per compute unit in turn, so that the last graphs to converge
 // (the others' workers exit at once) still spread over the whole GPU.
@@ -60,12 +72,11 @@ struct dg_graph {
   uint32_t variant0 = 0; // the variant chosen at creation
   uint32_t K = 0;          // sources stored in the compact region
   uint32_t max_block_v = 1;  // most vertices any worker owns
-  // Partition of the same tiles for the batched kernels (dg_sssp_batch,
-  // dg_ppr_batch, the server): Pb workers, most vertices per block.
-  uint32_t Pb = 0, max_block_vb = 1;
+  // Partitions of the same tiles for the batched kernels, one per algorithm
+  // (indexed by BatchAlgo).
+  dg::host::BatchPart bp[2];
   std::vector<uint32_t> tile_v_h, tile_e0_h;  // host copies: first vertex / first in-edge of each tile
   std::vector<uint32_t> work_t_h;             // host copy of work_t: first tile of each worker
-  std::vector<uint32_t> work_tb_h;            // host copy of work_tb: first tile of each batched worker
   std::vector<uint32_t> in_ptr_h;             // host copy of in_ptr (re-tiling by dg_graph_set_mapping)
   uint32_t res_limit = 0xFFFFFFFFu;           // resident-table entries the sweeps may use (<= R)
   uint64_t hash = 0;                         // content hash of the in-edge form (tuning cache key)
@@ -96,7 +107,6 @@ struct dg_graph {
   uint32_t *in_ptr = nullptr, *in_src = nullptr, *in_w = nullptr, *out_deg = nullptr, *cpos = nullptr;
   uint8_t* in_w8 = nullptr;  // weights as bytes when all are <= 255 (then in_w is null)
   uint32_t *tile_v = nullptr, *work_t = nullptr;
-  uint32_t* work_tb = nullptr;  // [Pb+1] first tile of each batched worker
   // workspace (grown on demand)
   void* vals[3] = {nullptr, nullptr, nullptr};  // 8(n+K) bytes each
   double* norm = nullptr;                        // kNormBlocks + 1
@@ -132,9 +142,9 @@ void drop_captures(dg_graph* g);
 void* dev_alloc(dg_graph* g, size_t bytes, hipStream_t s);
 void dev_free(dg_graph* g, void* p);
 // Device arrays of the resident graph as passed to the single-query sweep
-// kernels (P workers), and to the batched kernels (Pb workers).
+// kernels (P workers), and to the batched kernels (the partition `which`).
 Topology topo(const dg_graph* g);
-Topology topo_batch(const dg_graph* g);
+Topology topo_batch(const dg_graph* g, int which);
 // dg_graph_create for the union graph of a set: seg_v[G+1] are the first
 // vertices of the G graphs.  Tiles never cross a graph boundary and every
 // graph gets its own worker blocks (at least one).

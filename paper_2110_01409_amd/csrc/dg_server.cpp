@@ -28,6 +28,8 @@ using dg::host::fail;
 using dg::host::g_last_error;
 using dg::host::topo;
 using dg::host::topo_batch;
+using dg::host::kBatchSssp;
+using dg::host::kBatchPpr;
 
 namespace {
 
@@ -46,6 +48,7 @@ struct Pool {
   void *x = nullptr, *c0 = nullptr, *c1 = nullptr, *psh = nullptr;
   uint32_t *src = nullptr, *qdone = nullptr, *count = nullptr;
   double *dang = nullptr, *scale = nullptr, *part = nullptr;
+  uint32_t part_P = 0;      // batched workers `part` was sized for
   double* rhist = nullptr;  // float32 storage: [2][NB][64] changes two sweeps back (stall rule)
   // both kinds
   uint32_t *bactive = nullptr, *lane_src = nullptr, *blist = nullptr;
@@ -87,20 +90,28 @@ namespace {
 
 bool f64(const dg_server* s) { return s->o.dtype == DG_F64; }
 
+// The graph's batched partition for a pool of this kind.
+int batch_part(int kind) { return kind == DG_QUERY_SSSP ? kBatchSssp : kBatchPpr; }
+
+// Commit interval of a pool's delayed sweeps: d, at most a worker's block.
+uint32_t pool_d(const dg_server* s, const dg_graph* g, int kind) {
+  return std::max(1u, std::min(s->o.d, g->bp[batch_part(kind)].max_block_v));
+}
+
 // Delayed commits stage per wavefront in LDS up to kLdsStageMaxD, and need
 // the per-batch shadow array only beyond.
-bool delayed_shadow(const dg_server* s, const dg_graph* g) {
-  return s->o.mode == DG_DELAYED && std::max(1u, std::min(s->o.d, g->max_block_vb)) > kLdsStageMaxD;
+bool delayed_shadow(const dg_server* s, const dg_graph* g, int kind) {
+  return s->o.mode == DG_DELAYED && pool_d(s, g, kind) > kLdsStageMaxD;
 }
 
 size_t batch_bytes(const dg_server* s, const dg_graph* g, int kind) {
   const size_t n = g->n, slots = (size_t)g->n + g->K;
   const bool sync = s->o.mode == DG_SYNC;
   if (kind == DG_QUERY_SSSP)
-    return (slots * (sync ? 2 : 1) + (delayed_shadow(s, g) ? n : 0)) * kLanes * 4 + kLanes * 8 + 16;
+    return (slots * (sync ? 2 : 1) + (delayed_shadow(s, g, kind) ? n : 0)) * kLanes * 4 + kLanes * 8 + 16;
   const size_t e = f64(s) ? 8 : 4;
-  return (n + slots * (sync ? 2 : 1) + (delayed_shadow(s, g) ? n : 0)) * kLanes * e + kLanes * (4 + 4 + 6 * 8 + 4) +
-         (size_t)g->Pb * 3 * kLanes * 8 + 16;
+  return (n + slots * (sync ? 2 : 1) + (delayed_shadow(s, g, kind) ? n : 0)) * kLanes * e + kLanes * (4 + 4 + 6 * 8 + 4) +
+         (size_t)g->bp[kBatchPpr].P * 3 * kLanes * 8 + 16;
 }
 
 void free_pool(Pool& p) {
@@ -173,21 +184,22 @@ dg_status resize(dg_server* s, Pool& p, uint32_t NBn) {
   if (p.kind == DG_QUERY_SSSP) {
     if ((st = reshape(p, p.b0, slots * kLanes * 4, NBn, true)) != DG_OK) return st;
     if (sync && (st = reshape(p, p.b1, slots * kLanes * 4, NBn, true)) != DG_OK) return st;
-    if (delayed_shadow(s, g) && (st = reshape(p, p.sh, n * kLanes * 4, NBn, false)) != DG_OK) return st;
+    if (delayed_shadow(s, g, p.kind) && (st = reshape(p, p.sh, n * kLanes * 4, NBn, false)) != DG_OK) return st;
     if ((st = reshape(p, p.lchg, kLanes * 4, NBn, false)) != DG_OK) return st;
   } else {
     const size_t e = f64(s) ? 8 : 4;
     if ((st = reshape(p, p.x, n * kLanes * e, NBn, true)) != DG_OK) return st;
     if ((st = reshape(p, p.c0, slots * kLanes * e, NBn, true)) != DG_OK) return st;
     if (sync && (st = reshape(p, p.c1, slots * kLanes * e, NBn, true)) != DG_OK) return st;
-    if (delayed_shadow(s, g) && (st = reshape(p, p.psh, n * kLanes * e, NBn, false)) != DG_OK) return st;
+    if (delayed_shadow(s, g, p.kind) && (st = reshape(p, p.psh, n * kLanes * e, NBn, false)) != DG_OK) return st;
     if ((st = reshape(p, p.src, kLanes * 4, NBn, true)) != DG_OK) return st;
     if ((st = reshape(p, p.qdone, kLanes * 4, NBn, true)) != DG_OK) return st;
     if ((st = reshape_ring(p, p.dang, kLanes * 8, NBn)) != DG_OK) return st;
     if ((st = reshape_ring(p, p.scale, kLanes * 8, NBn)) != DG_OK) return st;
     if (!f64(s) && (st = reshape_ring(p, p.rhist, kLanes * 8, NBn)) != DG_OK) return st;
     if ((st = reshape_ring(p, p.count, 4, NBn)) != DG_OK) return st;
-    if ((st = reshape(p, p.part, (size_t)g->Pb * 3 * kLanes * 8, NBn, false)) != DG_OK) return st;
+    p.part_P = g->bp[kBatchPpr].P;
+    if ((st = reshape(p, p.part, (size_t)p.part_P * 3 * kLanes * 8, NBn, false)) != DG_OK) return st;
     // new batches: lanes frozen and unassigned
     for (uint32_t b = p.NB; b < NBn; ++b) {
       DG_HIP(launch_fill_u32(p.qdone + (size_t)b * kLanes, kLanes, 1u, p.st));
@@ -273,7 +285,7 @@ dg_status pool_sweep(dg_server* s, Pool& p, bool& ran) {
     if (p.lane_req[i] >= 0) active[i / kLanes] = 1, any = true;
   if (!any) return DG_OK;
   hipStream_t q = p.st;
-  const Topology t = topo_batch(g);
+  const Topology t = topo_batch(g, batch_part(p.kind));
   if (!blist.empty()) {
     lane_src.resize((size_t)p.NB * kLanes, kNone);
     DG_HIP(hipMemcpyAsync(p.lane_src, lane_src.data(), lane_src.size() * 4, hipMemcpyHostToDevice, q));
@@ -297,11 +309,17 @@ dg_status pool_sweep(dg_server* s, Pool& p, bool& ran) {
     a.lchg = p.lchg;
     a.bactive = p.bactive;
     a.k = p.k;
-    a.d = s->o.mode == DG_DELAYED ? std::max(1u, std::min(s->o.d, g->max_block_vb)) : 0u;
+    a.d = s->o.mode == DG_DELAYED ? pool_d(s, g, p.kind) : 0u;
     a.NB = p.NB;
     DG_HIP(launch_mbf_sweep((int)s->o.mode, a, q));
     DG_HIP(hipMemcpyAsync(p.flags_h, p.lchg, (size_t)p.NB * kLanes * 4, hipMemcpyDeviceToHost, q));
   } else {
+    if (p.part_P != t.P) {
+      // the graph was re-partitioned (dg_tune_batch) since the partials were sized
+      dg_status rs = reshape(p, p.part, (size_t)t.P * 3 * kLanes * 8, p.NB, false);
+      if (rs != DG_OK) return rs;
+      p.part_P = t.P;
+    }
     DG_HIP(launch_fill_u32(p.count, 2 * (size_t)p.NB, 0u, q));
     MpprArgs a;
     std::memset(&a, 0, sizeof a);
@@ -322,7 +340,7 @@ dg_status pool_sweep(dg_server* s, Pool& p, bool& ran) {
     a.tol = s->o.tol;
     a.nq = p.NB * kLanes;
     a.k = p.k;
-    a.d = s->o.mode == DG_DELAYED ? std::max(1u, std::min(s->o.d, g->max_block_vb)) : 0u;
+    a.d = s->o.mode == DG_DELAYED ? pool_d(s, g, p.kind) : 0u;
     a.NB = p.NB;
     DG_HIP(launch_mppr_sweep((int)s->o.mode, f64(s), a, q));
     DG_HIP(hipMemcpyAsync(p.flags_h, p.qdone, (size_t)p.NB * kLanes * 4, hipMemcpyDeviceToHost, q));

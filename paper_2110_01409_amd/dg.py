@@ -37,6 +37,7 @@ EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_
            "dg_error_bound",
            "dg_sssp", "dg_sssp_batch", "dg_ppr_batch", "dg_set_create", "dg_set_destroy", "dg_set_info_get",
            "dg_set_pagerank", "dg_set_sssp", "dg_graph_partition", "dg_access_matrix", "dg_graph_repartition",
+           "dg_graph_repartition_batch",
            "dg_tune", "dg_tune_batch", "dg_graph_set_mapping", "dg_graph_set_capture", "dg_set_set_capture",
            "dg_set_repartition", "dg_set_tune", "dg_predict_mode",
            "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_server_create",
@@ -194,6 +195,7 @@ def _load():
         "dg_graph_partition": (C.c_int, [P, P, P]),
         "dg_access_matrix": (C.c_int, [P, C.c_uint32, P, C.POINTER(dg_access_stats), P]),
         "dg_graph_repartition": (C.c_int, [P, C.c_uint32, P]),
+        "dg_graph_repartition_batch": (C.c_int, [P, C.c_int, C.c_uint32, P]),
         "dg_tune": (C.c_int, [P, C.c_int, C.c_int, C.c_double, C.c_uint32, C.c_uint32, C.POINTER(dg_tuning), P]),
         "dg_tune_batch": (C.c_int, [P, C.c_int, C.c_int, C.c_double, P, C.c_uint32, C.c_uint32,
                                     C.POINTER(dg_tuning), P]),
@@ -336,6 +338,10 @@ def dg_access_matrix(g, groups, out_counts, stats, stream):
 
 def dg_graph_repartition(g, workers, stream):
     return lib.dg_graph_repartition(g, workers, stream)
+
+
+def dg_graph_repartition_batch(g, algo, workers, stream):
+    return lib.dg_graph_repartition_batch(g, algo, workers, stream)
 
 
 def dg_tune(g, algo, dtype, tol, src, flags, out, stream):
@@ -706,6 +712,12 @@ class Graph:
     def repartition(self, workers=0, stream=None):
         """Rebuild the blocked partition over `workers` workers (0 = default)."""
         _check(dg_graph_repartition(self._h, int(workers), _stream_handle(stream)))
+
+    def repartition_batch(self, algo, workers=0, stream=None):
+        """Rebuild the batched partition of algo ("sssp" or "ppr") over
+        `workers` workgroups per batch (0 = default)."""
+        _check(dg_graph_repartition_batch(self._h, DG_ALGO_SSSP if algo == "sssp" else DG_ALGO_PAGERANK, int(workers),
+                                          _stream_handle(stream)))
 
     def tune(self, algo="pagerank", dtype="f32", tol=1e-6, src=0, use_cache=True, keep_workers=False, stream=None):
         """Choose workers, mode and d (the graph keeps the chosen partition).

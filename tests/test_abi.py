@@ -229,6 +229,7 @@ def test_tune_call_validation_null(dg):
     t = dg.dg_tuning()
     assert dg.dg_tune(None, 0, 0, 1e-6, 0, 0, C.byref(t), None) == dg.DG_ERR_INVALID_ARGUMENT
     assert dg.dg_graph_repartition(None, 8, None) == dg.DG_ERR_INVALID_ARGUMENT
+    assert dg.dg_graph_repartition_batch(None, dg.DG_ALGO_SSSP, 8, None) == dg.DG_ERR_INVALID_ARGUMENT
     assert dg.dg_graph_set_capture(None, 8) == dg.DG_ERR_INVALID_ARGUMENT
     assert dg.dg_set_set_capture(None, 8) == dg.DG_ERR_INVALID_ARGUMENT
     assert dg.dg_set_repartition(None, 8, None) == dg.DG_ERR_INVALID_ARGUMENT

@@ -299,3 +299,47 @@ def test_server_validation(dg, graphs):
         srv.fetch(99)
     srv.close()
     G.close()
+
+
+def test_server_after_batched_retune(dg):
+    """A live server keeps serving correct results after its graph gets
+    another batched partition (dg_graph_repartition_batch, dg_tune_batch):
+    PPR pools resize their per-worker partials at their next sweep.  The graph has enough tiles (about 2900)
+    that 3, 5 and 8 workgroups per CU are three different partitions; PPR
+    rows are checked by the oracle's certificate, which bounds their L1
+    error, SSSP rows bit-exact."""
+    g = gg.erdos_renyi(3_000_000, 2.0, seed=31)
+    G = dg.Graph.from_csr(g)
+    assert G.info().tiles > 2048
+    srv = dg.Server([G], mode="async", dtype="f64", tol=1e-10)
+    rng = np.random.default_rng(7)
+    srcs = [int(s) for s in rng.integers(0, g.n, size=5)]
+
+    def serve(kind, batch):
+        ids = [srv.submit(0, kind, s) for s in batch]
+        done = set()
+        guard = 0
+        while len(done) < len(ids):
+            done.update(srv.step())
+            guard += 1
+            assert guard < 100_000
+        return [srv.fetch(i)[0].cpu().numpy() for i in ids]
+
+    def check(batch, outs):
+        for s, x in zip(batch, outs):
+            assert abs(x.sum() - 1.0) < 1e-9
+            assert opr.ppr_certificate(g, x, s) <= 1e-8, s
+
+    check(srcs[:1], serve("ppr", srcs[:1]))
+    one = np.array(srcs[:1], np.uint32)
+    for i, workers in enumerate((2048, 768)):  # more workers than the pool's partials hold, then fewer
+        G.repartition_batch("ppr", workers)
+        assert G.ppr_batch(one, tol=1e-9, dtype="f64")[1].workers == workers
+        check(srcs[1 + i:2 + i], serve("ppr", srcs[1 + i:2 + i]))
+    t = G.tune_batch("ppr", np.array(srcs, np.uint32), dtype="f64", tol=1e-9)
+    print("ppr batched partition after tuning:", t["workers"], "workers", flush=True)
+    check(srcs[2:3], serve("ppr", srcs[2:3]))
+    for s, d in zip(srcs[3:], serve("sssp", srcs[3:])):
+        np.testing.assert_array_equal(d, osp.bellman_ford_sync(g, s)[0])
+    srv.close()
+    G.close()

@@ -133,16 +133,33 @@ def test_set_mapping_keeps_results(dg, variant, res):
     G.close()
 
 
+def _cus():
+    import torch
+    return torch.cuda.get_device_properties(0).multi_processor_count
+
+
 @pytest.mark.parametrize("algo", ["sssp", "ppr"])
 def test_tune_batch(dg, algo):
     g = gg.rmat(13, seed=9)
     G = dg.Graph.from_csr(g)
     srcs = gg.pick_sources(g, 20, seed=4)
+    # one batched partition per algorithm: 8 workgroups per CU for SSSP, 5 for
+    # PPR (rounded down to a multiple of 8, at most one per tile)
+    T = G.info().tiles
+    want = {a: max(1, min(_cus() * per, T)) for a, per in (("sssp", 8), ("ppr", 5))}
+    want = {a: (p & ~7 if p > 8 else p) for a, p in want.items()}
+    w_sssp = G.sssp_batch(srcs[:1], mode="async")[1].workers
+    w_ppr = G.ppr_batch(srcs[:1], tol=1e-9, mode="async", dtype="f64")[1].workers
+    assert (w_sssp, w_ppr) == (want["sssp"], want["ppr"])
     t = G.tune_batch(algo, srcs, dtype="f64", tol=1e-9)
     print("tuned batch", algo, t, flush=True)
     assert t["mode"] in MODES and t["candidates"] == 18 and t["repeats"] == 3
     assert 0 < t["seconds_min"] <= t["seconds"] <= t["seconds_max"] and t["seconds"] <= t["default_seconds"]
-    # the graph keeps the chosen batched partition, and results stay exact
+    # the graph keeps the chosen batched partition for this algorithm only,
+    # and results stay exact
+    other = G.ppr_batch(srcs[:1], tol=1e-9, mode="async", dtype="f64")[1].workers if algo == "sssp" else \
+        G.sssp_batch(srcs[:1], mode="async")[1].workers
+    assert other == (w_ppr if algo == "sssp" else w_sssp)
     if algo == "sssp":
         rows, st = G.sssp_batch(srcs, mode=t["mode"], d=max(t["d"], 1))
         assert st.workers == t["workers"]
