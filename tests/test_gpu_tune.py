@@ -235,3 +235,33 @@ def test_set_tune(dg, algo):
     print(f"set tune {algo}: {mode} d={t['d']} workers={t['workers']} {t['seconds'] * 1e3:.3f} ms "
           f"vs default {t['default_seconds'] * 1e3:.3f} ms", flush=True)
     S.close()
+
+
+def test_repartition_batch(dg):
+    """dg_graph_repartition_batch: sets one algorithm's batched partition
+    (clamped to one worker per tile), leaves the other's alone, 0 restores the
+    default, an unknown algorithm is refused; results stay exact."""
+    g = gg.rmat(14, seed=12)
+    G = dg.Graph.from_csr(g)
+    srcs = gg.pick_sources(g, 3, seed=5)
+    T = G.info().tiles
+    def workers(algo):
+        if algo == "sssp":
+            return G.sssp_batch(srcs, mode="async")[1].workers
+        return G.ppr_batch(srcs, tol=1e-9, mode="async", dtype="f64")[1].workers
+    d_sssp, d_ppr = workers("sssp"), workers("ppr")
+    G.repartition_batch("sssp", 3)
+    assert workers("sssp") == 3 and workers("ppr") == d_ppr
+    G.repartition_batch("ppr", 10 ** 6)
+    assert workers("ppr") == T and workers("sssp") == 3
+    rows, _ = G.sssp_batch(srcs, mode="delayed", d=64)
+    for q, s in enumerate(srcs.tolist()):
+        np.testing.assert_array_equal(rows[q].cpu().numpy(), osp.bellman_ford_sync(g, s)[0])
+    p, _ = G.ppr_batch(srcs, tol=1e-9, mode="delayed", d=64, dtype="f64")
+    for q, s in enumerate(srcs.tolist()):
+        assert float(np.abs(p[q].cpu().numpy() - opr.ppr_fixed_point(g, s)).sum()) <= 1e-8
+    G.repartition_batch("sssp", 0)
+    G.repartition_batch("ppr", 0)
+    assert (workers("sssp"), workers("ppr")) == (d_sssp, d_ppr)
+    assert dg.dg_graph_repartition_batch(G._h, 7, 8, None) == dg.DG_ERR_INVALID_ARGUMENT
+    G.close()
