@@ -262,6 +262,66 @@ def families_bench(dg, gg, scale):
     return out
 
 
+def batched_rmat20(dg, gg, queries=256):
+    """Batched queries on R-MAT scale 20 (256 sources): one query at a time
+    through the single-query entry points, against batched calls at the
+    default (delayed d = 64) and at what dg_tune_batch picks on the same
+    sources (mode, d and batched workgroups).  SSSP rows are compared with
+    the one-at-a-time rows; every PPR row carries its device certificate
+    (bound on its L1 error) and its largest difference from the one-at-a-time
+    row."""
+    import torch
+    g = gg.rmat(20, seed=20)
+    G = dg.Graph.from_csr(g)
+    src = gg.pick_sources(g, queries, seed=21)
+
+    def timed(fn):
+        fn()  # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t
+
+    res = {"graph": f"rmat20 (n={g.n}, m={int(g.ptr[-1])})", "queries": queries}
+    # one at a time
+    def sssp_one():
+        return [G.sssp(int(s), mode="delayed", d=64)[0] for s in src.tolist()]
+    ones, t1 = timed(sssp_one)
+    def ppr_one():
+        return [G.ppr(int(s), tol=1e-6, mode="delayed", d=64, dtype="f32")[0] for s in src.tolist()]
+    onep, tp1 = timed(ppr_one)
+    res["one_at_a_time_ms"] = {"sssp": round(t1 * 1e3, 2), "ppr_f32_tol1e-6": round(tp1 * 1e3, 2)}
+    for label, tune in (("default", False), ("tuned", True)):
+        row = {}
+        for algo in ("sssp", "ppr"):
+            mode, d = "delayed", 64
+            if tune:
+                t = G.tune_batch(algo, src, dtype="f32", tol=1e-6)
+                mode, d = t["mode"], max(t["d"], 1)
+                choice = {"mode": mode, "d": t["d"], "batched_workers": t["workers"]}
+            if algo == "sssp":
+                (out, st), tb = timed(lambda: G.sssp_batch(src, mode=mode, d=d))
+                equal = sum(int(torch.equal(out[q], ones[q])) for q in range(queries))
+                r = {"batched_ms": round(tb * 1e3, 2), "speedup": round(t1 / tb, 2),
+                     "gteps": round(st.edges_traversed / tb / 1e9, 1), "rows_equal_to_one_at_a_time": f"{equal}/{queries}"}
+            else:
+                (out, st), tb = timed(lambda: G.ppr_batch(src, tol=1e-6, mode=mode, d=d, dtype="f32"))
+                bounds = [G.error_bound(out[q], restart=int(s)) for q, s in enumerate(src.tolist())]
+                diff = max(float((out[q] - onep[q]).abs().sum()) for q in range(queries))
+                r = {"batched_ms": round(tb * 1e3, 2), "speedup": round(tp1 / tb, 2),
+                     "gteps": round(st.edges_traversed / tb / 1e9, 1), "max_err_bound": max(bounds),
+                     "median_err_bound": float(np.median(bounds)), "max_l1_diff_to_one_at_a_time": diff}
+            if tune:
+                r.update(choice)
+            row["sssp" if algo == "sssp" else "ppr_f32_tol1e-6"] = r
+        res[label] = row
+        log(f"batched rmat20 x{queries} {label}: SSSP {row['sssp']['batched_ms']} ms ({row['sssp']['speedup']}x one at a "
+            f"time), PPR {row['ppr_f32_tol1e-6']['batched_ms']} ms ({row['ppr_f32_tol1e-6']['speedup']}x)")
+    G.close()
+    return res
+
+
 def capture_bench(dg, gg, chunk=16, reps=5):
     """Captured launches (chunks of `chunk` sweeps recorded into HIP graphs
     and replayed) against one launch per sweep, on work whose sweeps are
@@ -838,6 +898,8 @@ def main():
             tuning[f"rmat{sc}"] = row
             GT.close()
 
+    batched20 = {} if args.no_batched else batched_rmat20(dg, gg)
+
     graph_set = {}
     if not args.no_set:
         graph_set = set_bench(dg, gg)
@@ -922,6 +984,7 @@ def main():
         "batched": batched,
         "topology": topology,
         "tuning": tuning,
+        "batched_rmat20": batched20,
         "graph_set": graph_set,
         "captured_launches": captured,
         "graph_families": families,
