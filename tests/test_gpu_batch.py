@@ -245,8 +245,9 @@ def test_batch_degenerate_graphs(dg):
 def test_batch_commit_counts(dg):
     """dg_stats.commits of a delayed batched call: each wavefront commits
     every ceil(d/4) of its rows and at the end of its block, so d = 1 commits
-    every row on its own (n per batch-sweep), d = 64 about n/16, and a whole
-    block at most once per wavefront; sync and async report 0.  The
+    every row on its own (n per batch-sweep), d = 64 about n/16 (staged in
+    LDS), d = 256 about n/64 (staged in the shadow), and a whole block at
+    most once per wavefront; sync and async report 0.  The
     interval is n / commits."""
     g = gg.rmat(12, seed=40)
     srcs = gg.pick_sources(g, 3, seed=1)
@@ -265,6 +266,8 @@ def test_batch_commit_counts(dg):
         waves = 4 * st.workers
         assert g.n / 16 <= st.commits <= g.n / 16 + waves, (call, st.commits)
         assert abs(st.commit_interval - g.n / st.commits) <= 0.5
+        st = run("delayed", 256)  # staged in the shadow, a commit every 64 rows per wavefront
+        assert g.n / 64 <= st.commits <= g.n / 64 + 4 * st.workers, (call, st.commits)
         st = run("delayed", dg.DG_D_WHOLE)
         assert st.workers <= st.commits <= waves, (call, st.commits)
         print(f"{call}: whole-block commits {st.commits} for {st.workers} workers", flush=True)
