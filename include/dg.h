@@ -537,9 +537,9 @@ dg_status dg_tune(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, uint32_
  * SSSP pools; PageRank: dg_ppr_batch and its PPR pools) is left at the
  * chosen size.  The default is delayed d = 64 with 8 (SSSP) or 5 (PageRank)
  * workgroups per compute unit.  A live server's PPR pools resize their
- * per-worker partials at their next sweep.  Fills dg_tuning as dg_tune (predicted_seconds = the
- * measured median; sweep_variant and resident_vertices are unchanged);
- * nothing is cached.  flags must be 0. */
+ * per-worker partials at their next sweep.  Fills dg_tuning as dg_tune
+ * (predicted_seconds = the measured median; sweep_variant and
+ * resident_vertices are unchanged); nothing is cached.  flags must be 0. */
 dg_status dg_tune_batch(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, const uint32_t* sources, uint32_t k,
                         uint32_t flags, dg_tuning* out, void* hip_stream);
 
@@ -551,6 +551,7 @@ dg_status dg_tune_batch(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, c
  * tuning.  A live server's PPR pools resize their per-worker partials at
  * their next sweep.  Must not overlap a sweep call on the same graph. */
 dg_status dg_graph_repartition_batch(dg_graph* g, dg_algo algo, uint32_t workers, void* hip_stream);
+
 /* The in-process cache of tuning results: cleared, written to and merged
  * from a text file (one result per line, comments start with '#'). */
 dg_status dg_tune_cache_clear(void);
