@@ -454,14 +454,41 @@ __global__ __launch_bounds__(kWG) void mppr_sweep_kernel(MpprArgs a) {
   __syncthreads();
   if (!s_last) return;
   __threadfence();
-  if (wv == 0) {
-    double r = 0.0, dm = 0.0, ms = 0.0;
-    for (uint32_t i = 0; i < P; ++i) {
-      const double* pp = a.part + ((size_t)i * NB + b) * 3 * kQ;
-      r += __hip_atomic_load(pp + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      dm += __hip_atomic_load(pp + kQ + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      ms += __hip_atomic_load(pp + 2 * kQ + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  {
+    // The batch's last worker folds the P workers' partials: wavefront wv
+    // takes workers wv, wv + 4, ... in order, kFoldU at a time so that their
+    // loads are in flight together (one at a time, the fold was P round trips
+    // long), and wavefront 0 adds the four sums in wavefront order.  The
+    // order is fixed, so the sums do not depend on which worker came last.
+    constexpr uint32_t W = kWG / 64, kFoldU = 4;
+    auto part_at = [&](uint32_t i, uint32_t j) {
+      return __hip_atomic_load(a.part + ((size_t)i * NB + b) * 3 * kQ + j * kQ + lane, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    };
+    double f[3] = {0.0, 0.0, 0.0};
+    uint32_t i = wv;
+    for (; i + (kFoldU - 1) * W < P; i += kFoldU * W) {
+      double v[3][kFoldU];
+#pragma unroll
+      for (uint32_t u = 0; u < kFoldU; ++u)
+#pragma unroll
+        for (uint32_t j = 0; j < 3; ++j) v[j][u] = part_at(i + u * W, j);
+#pragma unroll
+      for (uint32_t u = 0; u < kFoldU; ++u)
+#pragma unroll
+        for (uint32_t j = 0; j < 3; ++j) f[j] += v[j][u];
     }
+    for (; i < P; i += W)
+#pragma unroll
+      for (uint32_t j = 0; j < 3; ++j) f[j] += part_at(i, j);
+#pragma unroll
+    for (uint32_t j = 0; j < 3; ++j) red(j, wv) = f[j];
+  }
+  __syncthreads();
+  if (wv == 0) {
+    const double r = red(0, 0) + red(0, 1) + red(0, 2) + red(0, 3);
+    const double dm = red(1, 0) + red(1, 1) + red(1, 2) + red(1, 3);
+    const double ms = red(2, 0) + red(2, 1) + red(2, 2) + red(2, 3);
     // A live query's mass is at least 1 - alpha > 0 (the restart term).
     const size_t next = ((size_t)((k + 1) & 1u) * NB + b) * kQ + lane;
     // The dangling mass itself, not the deficit 1 - (non-dangling mass): with
