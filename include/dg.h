@@ -97,7 +97,8 @@ typedef struct dg_graph dg_graph;
 typedef struct {
   uint32_t sweeps;          /* sweeps run, including the confirming one     */
   uint32_t workers;         /* persistent workgroups (contiguous blocks)    */
-  uint32_t tile_vertices;   /* mean vertices per tile: n / tiles, rounded   */
+  uint32_t tile_vertices;   /* mean vertices per tile: n / tiles, rounded
+                               (batched calls: per batched tile)            */
   uint32_t commit_interval; /* delayed modes: mean vertices per commit of a
                                worker's staged values, n / commits, rounded
                                (>= d up to the end of a block); 0 otherwise */
@@ -139,6 +140,10 @@ typedef struct {
                                  <= 255, 4 otherwise, 0 without weights        */
   uint64_t device_bytes; /* device memory held by the graph (not workspace) */
   uint32_t sweep_variant; /* DG_SWEEP_WIDE, _WIDE_INFLIGHT or _NARROW          */
+  uint32_t batch_tiles;   /* tiles of the batched calls: each tile split into
+                             runs of at most 4096 in-edges (a vertex with more
+                             is a run of its own), at most one batched worker
+                             per run                                        */
 } dg_graph_info;
 
 /* Device memory hooks.  alloc(bytes, stream, ctx) returns device memory or
@@ -273,6 +278,7 @@ typedef struct {
   uint32_t weight_bytes;      /* 1, 4, or 0 without weights                     */
   uint64_t content_hash;      /* hash of the in-edge form (the tuning cache key) */
   uint32_t sweep_variant;     /* DG_SWEEP_WIDE, _WIDE_INFLIGHT or _NARROW        */
+  uint32_t batch_tiles;       /* tiles of the batched calls (as dg_graph_info)  */
 } dg_plan_info;
 dg_status dg_plan_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
                          const uint32_t* w, const dg_graph_opts* opts, uint32_t compute_units, dg_plan** out);
@@ -289,6 +295,10 @@ dg_status dg_plan_info_get(const dg_plan* p, dg_plan_info* info);
  *   work_t [workers+1] first tile of each worker */
 dg_status dg_plan_arrays(const dg_plan* p, uint32_t* in_ptr, uint32_t* in_src, uint32_t* in_w, uint32_t* cpos,
                          uint32_t* tile_v, uint32_t* work_t);
+/* Copies the first vertex of each tile of the batched calls into the caller's
+ * btile_v [batch_tiles+1] (host memory).  INVALID_ARGUMENT if either pointer
+ * is NULL. */
+dg_status dg_plan_batch_tiles(const dg_plan* p, uint32_t* btile_v);
 dg_status dg_plan_destroy(dg_plan* p);
 
 /* PageRank by repeated pull sweeps (sections III and IV-A).

@@ -129,6 +129,7 @@ Topology topo(const dg_graph* g) {
 
 Topology topo_batch(const dg_graph* g, int which) {
   Topology t = topo(g);
+  t.tile_v = g->btile_v;
   t.work_t = g->bp[which].work_t;
   t.P = g->bp[which].P;
   return t;
@@ -191,10 +192,12 @@ uint32_t commits_per_sweep(const dg_graph* g, uint32_t d, uint32_t cap, bool sha
 // Commits per sweep of one batch (64 queries) of a delayed batched sweep,
 // counted as the kernels decide them: each of a batched worker's kWG / 64
 // wavefronts stages the rows it updates (vertices v0 + wv, v0 + wv + kWG / 64,
-// ... of each tile; wavefront 0 alone the row of a single-vertex tile) and
+// ... of each batched tile; wavefront 0 alone the row of a single-vertex
+// tile) and
 // commits them once ceil(d / (kWG / 64)) are staged, and at the end of the
 // worker's block.
-// Splits the tiles tv (first in-edges te0) into P batched workers (host side).
+// Splits the batched tiles tv (first in-edges te0) into P batched workers
+// (host side).
 void plan_batch_part(const std::vector<uint32_t>& tv, const std::vector<uint32_t>& te0, uint32_t P, BatchPart& bp) {
   bp.P = P;
   build_workers(tv, te0, P, bp.work_t_h);
@@ -202,10 +205,24 @@ void plan_batch_part(const std::vector<uint32_t>& tv, const std::vector<uint32_t
   for (uint32_t w = 0; w < P; ++w) bp.max_block_v = std::max(bp.max_block_v, tv[bp.work_t_h[w + 1]] - tv[bp.work_t_h[w]]);
 }
 
+// Default batched workers: per_cu 256-thread workgroups per compute unit,
+// rounded down to a multiple of 8, at most one per batched tile.
+uint32_t batch_workers(const dg_graph* g, uint32_t per_cu) {
+  uint32_t P = std::max(1u, std::min(g->cus * per_cu, (uint32_t)g->btile_v_h.size() - 1));
+  if (P > 8) P &= ~7u;
+  return P;
+}
+
+// Mean vertices per batched tile, rounded.
+uint32_t batch_tile_vertices(const dg_graph* g) {
+  const uint64_t Tb = g->btile_v_h.size() - 1;
+  return (uint32_t)(((uint64_t)g->n + Tb / 2) / Tb);
+}
+
 uint32_t batch_commits_per_sweep(const dg_graph* g, int which, uint32_t d) {
   constexpr uint32_t waves = kWG / 64;
   const uint64_t per = ((uint64_t)d + waves - 1) / waves;
-  const std::vector<uint32_t>& tv = g->tile_v_h;
+  const std::vector<uint32_t>& tv = g->btile_v_h;
   const std::vector<uint32_t>& wt = g->bp[which].work_t_h;
   uint64_t c = 0;
   for (size_t w = 0; w + 1 < wt.size(); ++w)
@@ -809,9 +826,10 @@ dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
   g->work_t_h = work_t;
   for (uint32_t wk = 0; wk < P; ++wk)
     g->max_block_v = std::max(g->max_block_v, L.tile_v[work_t[wk + 1]] - L.tile_v[work_t[wk]]);
-  dg::host::plan_batch_part(L.tile_v, L.tile_e0, plan_workers(L, 0u, g->cus, kBatchSsspWorkersPerCU),
+  dg::host::build_batch_tiles(L.tile_v, L.in_ptr, dg::host::kBatchTileE, g->btile_v_h, g->btile_e0_h);
+  dg::host::plan_batch_part(g->btile_v_h, g->btile_e0_h, dg::host::batch_workers(g, kBatchSsspWorkersPerCU),
                             g->bp[kBatchSssp]);
-  dg::host::plan_batch_part(L.tile_v, L.tile_e0, plan_workers(L, 0u, g->cus, kBatchPprWorkersPerCU),
+  dg::host::plan_batch_part(g->btile_v_h, g->btile_e0_h, dg::host::batch_workers(g, kBatchPprWorkersPerCU),
                             g->bp[kBatchPpr]);
 
   uint32_t* w8_words = nullptr;
@@ -820,7 +838,7 @@ dg_status graph_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
     const std::vector<uint32_t>* src;
   } ups[] = {{&g->in_ptr, &L.in_ptr}, {&g->in_src, &L.in_src}, {&g->in_w, &L.in_w}, {&w8_words, &L.w8pack},
              {&g->out_deg, &L.out_deg}, {&g->cpos, &L.cpos}, {&g->tile_v, &L.tile_v}, {&g->work_t, &work_t},
-             {&g->wseg, &g->wseg_h}, {&g->wgraph, &g->wgraph_h},
+             {&g->wseg, &g->wseg_h}, {&g->wgraph, &g->wgraph_h}, {&g->btile_v, &g->btile_v_h},
              {&g->bp[kBatchSssp].work_t, &g->bp[kBatchSssp].work_t_h},
              {&g->bp[kBatchPpr].work_t, &g->bp[kBatchPpr].work_t_h}, {&g->segv_d, &g->seg_v}};
   for (auto& u : ups) {
@@ -894,6 +912,7 @@ dg_status dg_graph_info_get(const dg_graph* g, dg_graph_info* info) {
   info->weight_bytes = g->in_w8 ? 1u : (g->in_w ? 4u : 0u);
   info->device_bytes = g->graph_bytes;
   info->sweep_variant = g->variant;
+  info->batch_tiles = (uint32_t)g->btile_v_h.size() - 1;
   return DG_OK;
 }
 
@@ -1377,7 +1396,7 @@ dg_status dg_sssp_batch(dg_graph* g, const uint32_t* sources, uint32_t k, dg_mod
     }
     stats->sweeps = sweeps;
     stats->workers = g->bp[kBatchSssp].P;
-    stats->tile_vertices = g->T ? (uint32_t)(((uint64_t)g->n + g->T / 2) / g->T) : 0u;
+    stats->tile_vertices = dg::host::batch_tile_vertices(g);
     stats->commits = mode == DG_DELAYED ? dg::host::batch_commits_per_sweep(g, kBatchSssp, a.d) : 0u;
     stats->commit_interval = stats->commits ? (uint32_t)(((uint64_t)g->n + stats->commits / 2) / stats->commits) : 0u;
     stats->err_bound = 0.0;
@@ -1510,7 +1529,7 @@ dg_status dg_ppr_batch(dg_graph* g, const uint32_t* sources, uint32_t k, double 
     }
     stats->sweeps = sweeps;
     stats->workers = g->bp[kBatchPpr].P;
-    stats->tile_vertices = g->T ? (uint32_t)(((uint64_t)g->n + g->T / 2) / g->T) : 0u;
+    stats->tile_vertices = dg::host::batch_tile_vertices(g);
     stats->commits = mode == DG_DELAYED ? dg::host::batch_commits_per_sweep(g, kBatchPpr, a.d) : 0u;
     stats->commit_interval = stats->commits ? (uint32_t)(((uint64_t)g->n + stats->commits / 2) / stats->commits) : 0u;
     stats->err_bound = 0.0;
@@ -1601,43 +1620,51 @@ dg_status dg_graph_set_mapping(dg_graph* g, uint32_t sweep_variant, uint32_t res
   const uint32_t want = sweep_variant == DG_SWEEP_AUTO ? g->variant0 : sweep_variant;
   const bool narrow_now = g->variant == kNarrow, narrow_want = want == kNarrow;
   if (narrow_now != narrow_want) {
-    // The narrow variant has its own tile cap: rebuild the tiles, then every
-    // partition over them (the batched kernels use the same tiles).
-    std::vector<uint32_t> tv, te0;
+    // The narrow variant has its own tile cap: rebuild the tiles, the batched
+    // tiles split from them, and every partition over either.
+    std::vector<uint32_t> tv, te0, btv, bte0;
     BatchPart nb[2];
     try {
       build_tiles(g->in_ptr_h, g->n, tv, nullptr, narrow_want ? (uint32_t)kTileENarrow : (uint32_t)kTileE);
       te0.resize(tv.size());
       for (size_t t = 0; t < tv.size(); ++t) te0[t] = g->in_ptr_h[tv[t]];
+      dg::host::build_batch_tiles(tv, g->in_ptr_h, dg::host::kBatchTileE, btv, bte0);
     } catch (const std::bad_alloc&) {
       return fail(DG_ERR_OUT_OF_MEMORY, "host allocation failed");
     }
-    const uint32_t T = (uint32_t)tv.size() - 1;
+    const uint32_t T = (uint32_t)tv.size() - 1, Tb = (uint32_t)btv.size() - 1;
     for (int b : {kBatchSssp, kBatchPpr}) {
-      uint32_t Pb = std::max(1u, std::min(g->cus * (b == kBatchSssp ? kBatchSsspWorkersPerCU : kBatchPprWorkersPerCU), T));
+      uint32_t Pb = std::max(1u, std::min(g->cus * (b == kBatchSssp ? kBatchSsspWorkersPerCU : kBatchPprWorkersPerCU), Tb));
       if (Pb > 8) Pb &= ~7u;
-      dg::host::plan_batch_part(tv, te0, Pb, nb[b]);
+      dg::host::plan_batch_part(btv, bte0, Pb, nb[b]);
     }
     DG_HIP(hipStreamSynchronize(s));
     uint32_t* tvd = static_cast<uint32_t*>(dev_alloc(g, tv.size() * 4, s));
+    uint32_t* btvd = static_cast<uint32_t*>(dev_alloc(g, btv.size() * 4, s));
     for (BatchPart& b : nb) b.work_t = static_cast<uint32_t*>(dev_alloc(g, b.work_t_h.size() * 4, s));
-    if (!tvd || !nb[0].work_t || !nb[1].work_t) {
+    if (!tvd || !btvd || !nb[0].work_t || !nb[1].work_t) {
       dev_free(g, tvd);
+      dev_free(g, btvd);
       for (BatchPart& b : nb) dev_free(g, b.work_t);
       return fail(DG_ERR_OUT_OF_MEMORY, "re-tiling allocation failed");
     }
     DG_HIP(hipMemcpyAsync(tvd, tv.data(), tv.size() * 4, hipMemcpyHostToDevice, s));
+    DG_HIP(hipMemcpyAsync(btvd, btv.data(), btv.size() * 4, hipMemcpyHostToDevice, s));
     for (BatchPart& b : nb)
       DG_HIP(hipMemcpyAsync(b.work_t, b.work_t_h.data(), b.work_t_h.size() * 4, hipMemcpyHostToDevice, s));
     DG_HIP(hipStreamSynchronize(s));
     dev_free(g, g->tile_v);
     g->tile_v = tvd;
+    dev_free(g, g->btile_v);
+    g->btile_v = btvd;
     for (int b : {kBatchSssp, kBatchPpr}) {
       dev_free(g, g->bp[b].work_t);
       g->bp[b] = std::move(nb[b]);
     }
     g->tile_v_h.swap(tv);
     g->tile_e0_h.swap(te0);
+    g->btile_v_h.swap(btv);
+    g->btile_e0_h.swap(bte0);
     g->T = T;
     g->P = 0;  // forces the repartition below
   }
@@ -1884,12 +1911,13 @@ dg_status dg_tune(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, uint32_
 
 namespace {
 
-// Re-partitions the tiles of batched partition `which` over Pb workers.
+// Re-partitions the batched tiles of batched partition `which` over Pb
+// workers.
 dg_status set_batch_workers(dg_graph* g, int which, uint32_t Pb, hipStream_t s) {
-  Pb = std::max(1u, std::min(Pb, g->T));
+  Pb = std::max(1u, std::min(Pb, (uint32_t)g->btile_v_h.size() - 1));
   if (Pb == g->bp[which].P) return DG_OK;
   BatchPart nb;
-  dg::host::plan_batch_part(g->tile_v_h, g->tile_e0_h, Pb, nb);
+  dg::host::plan_batch_part(g->btile_v_h, g->btile_e0_h, Pb, nb);
   DG_HIP(hipStreamSynchronize(s));
   nb.work_t = static_cast<uint32_t*>(dev_alloc(g, nb.work_t_h.size() * 4, s));
   if (!nb.work_t) return fail(DG_ERR_OUT_OF_MEMORY, "batched partition allocation failed");
@@ -1909,8 +1937,9 @@ dg_status dg_graph_repartition_batch(dg_graph* g, dg_algo algo, uint32_t workers
   if (!g) return fail(DG_ERR_INVALID_ARGUMENT, "graph is NULL");
   if (algo != DG_ALGO_PAGERANK && algo != DG_ALGO_SSSP) return fail(DG_ERR_INVALID_ARGUMENT, "unknown algorithm");
   const int which = algo == DG_ALGO_SSSP ? kBatchSssp : kBatchPpr;
-  const uint32_t P =
-      workers ? workers : default_workers(g, which == kBatchSssp ? kBatchSsspWorkersPerCU : kBatchPprWorkersPerCU);
+  const uint32_t P = workers ? workers
+                             : dg::host::batch_workers(g, which == kBatchSssp ? kBatchSsspWorkersPerCU
+                                                                              : kBatchPprWorkersPerCU);
   return set_batch_workers(g, which, P, static_cast<hipStream_t>(hip_stream));
 }
 
@@ -1952,7 +1981,8 @@ dg_status dg_tune_batch(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, c
   };
   dg_status st;
   const int which = algo == DG_ALGO_SSSP ? kBatchSssp : kBatchPpr;
-  const uint32_t Pb_def = default_workers(g, which == kBatchSssp ? kBatchSsspWorkersPerCU : kBatchPprWorkersPerCU);
+  const uint32_t Pb_def =
+      dg::host::batch_workers(g, which == kBatchSssp ? kBatchSsspWorkersPerCU : kBatchPprWorkersPerCU);
   Spread def{};
   uint32_t sw_def = 0;
   if ((st = set_batch_workers(g, which, Pb_def, s)) != DG_OK) return st;
@@ -1968,7 +1998,7 @@ dg_status dg_tune_batch(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, c
   uint32_t bestP = Pb_def, best_sw = 0, evaluated = 0;
   Cand bestc = {DG_DELAYED, 64};
   for (uint32_t per_cu : {3u, 5u, 8u}) {
-    const uint32_t Pb = default_workers(g, per_cu);
+    const uint32_t Pb = dg::host::batch_workers(g, per_cu);
     if ((st = set_batch_workers(g, which, Pb, s)) != DG_OK) return st;
     for (const Cand& c : cands) {
       Spread sp{};

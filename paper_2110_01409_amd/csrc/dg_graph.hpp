@@ -34,11 +34,12 @@ constexpr uint32_t kBatchPprWorkersPerCU = 5;
 // Which batched partition: SSSP (dg_sssp_batch, the server's SSSP pools) or
 // personalised PageRank (dg_ppr_batch, the server's PPR pools).
 enum BatchAlgo : int { kBatchSssp = 0, kBatchPpr = 1 };
-// A partition of the tiles into batched workers (the grid's x dimension).
+// A partition of the batched tiles (dg_graph::btile_v) into batched workers
+// (the grid's x dimension).
 struct BatchPart {
   uint32_t P = 0;                  // workers
   uint32_t max_block_v = 1;        // most vertices any worker owns
-  uint32_t* work_t = nullptr;      // device [P + 1]: first tile of each worker
+  uint32_t* work_t = nullptr;      // device [P + 1]: first batched tile of each worker
   std::vector<uint32_t> work_t_h;  // host copy
 };
 // The same for the union graph of a set: smaller blocks, several sweep
@@ -72,8 +73,11 @@ struct dg_graph {
   uint32_t variant0 = 0; // the variant chosen at creation
   uint32_t K = 0;          // sources stored in the compact region
   uint32_t max_block_v = 1;  // most vertices any worker owns
-  // Partitions of the same tiles for the batched kernels, one per algorithm
-  // (indexed by BatchAlgo).
+  // Tiles of the batched kernels (the tiles split by build_batch_tiles), and
+  // their partitions into batched workers, one per algorithm (indexed by
+  // BatchAlgo).
+  std::vector<uint32_t> btile_v_h, btile_e0_h;  // host: first vertex / first in-edge of each batched tile
+  uint32_t* btile_v = nullptr;                  // device copy of btile_v_h
   dg::host::BatchPart bp[2];
   std::vector<uint32_t> tile_v_h, tile_e0_h;  // host copies: first vertex / first in-edge of each tile
   std::vector<uint32_t> work_t_h;             // host copy of work_t: first tile of each worker

@@ -28,6 +28,20 @@ void current_allocator(dg_alloc_fn& alloc, dg_free_fn& free_fn, void*& ctx);
 void build_tiles(const std::vector<uint32_t>& in_ptr, uint32_t n, std::vector<uint32_t>& tile_v,
                  const std::vector<uint32_t>* seg_v, uint32_t max_e);
 
+// In-edges per tile of the batched kernels.  Their workers gather a 256-byte
+// row per edge, so a single-query tile (up to 16380 in-edges) is a coarse
+// unit for them: a graph with a thousand tiles could not give eight
+// 256-thread workgroups to each compute unit.
+constexpr uint32_t kBatchTileE = 4096;
+
+// Tiles of the batched kernels: each tile of tile_v split greedily into runs
+// of consecutive vertices with at most max_e in-edges, a vertex with more
+// being a run of its own; a single-vertex tile stays whole.  Runs never
+// cross a tile boundary (nor, therefore, a graph of a set).  btile_e0[t] is
+// the first in-edge of run t.
+void build_batch_tiles(const std::vector<uint32_t>& tile_v, const std::vector<uint32_t>& in_ptr, uint32_t max_e,
+                       std::vector<uint32_t>& btile_v, std::vector<uint32_t>& btile_e0);
+
 }  // namespace host
 }  // namespace dg
 

@@ -53,6 +53,27 @@ void build_tiles(const std::vector<uint32_t>& in_ptr, uint32_t n, std::vector<ui
   if (tile_v.back() != n) tile_v.push_back(n);
 }
 
+void build_batch_tiles(const std::vector<uint32_t>& tile_v, const std::vector<uint32_t>& in_ptr, uint32_t max_e,
+                       std::vector<uint32_t>& btile_v, std::vector<uint32_t>& btile_e0) {
+  btile_v.clear();
+  btile_v.push_back(0);
+  for (size_t t = 0; t + 1 < tile_v.size(); ++t) {
+    const uint32_t a = tile_v[t], b = tile_v[t + 1];
+    uint64_t ne = 0;
+    for (uint32_t v = a; v < b; ++v) {
+      const uint64_t deg = in_ptr[v + 1] - in_ptr[v];
+      if (v > btile_v.back() && ne + deg > (uint64_t)max_e) {
+        btile_v.push_back(v);
+        ne = 0;
+      }
+      ne += deg;
+    }
+    btile_v.push_back(b);
+  }
+  btile_e0.resize(btile_v.size());
+  for (size_t t = 0; t < btile_v.size(); ++t) btile_e0[t] = in_ptr[btile_v[t]];
+}
+
 void build_workers(const std::vector<uint32_t>& tile_v, const std::vector<uint32_t>& tile_e0, uint32_t P,
                    std::vector<uint32_t>& work_t) {
   const uint32_t T = (uint32_t)tile_v.size() - 1;
@@ -266,6 +287,7 @@ struct dg_plan {
   dg::host::Layout L;
   uint32_t P = 0;
   std::vector<uint32_t> work_t;
+  std::vector<uint32_t> btile_v, btile_e0;  // tiles of the batched kernels
 };
 
 extern "C" {
@@ -289,6 +311,7 @@ dg_status dg_plan_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_
   p->P = dg::host::plan_workers(p->L, opts ? opts->workers : 0u, compute_units, dg::host::kWorkersPerCU);
   try {
     dg::host::build_workers(p->L.tile_v, p->L.tile_e0, p->P, p->work_t);
+    dg::host::build_batch_tiles(p->L.tile_v, p->L.in_ptr, dg::host::kBatchTileE, p->btile_v, p->btile_e0);
   } catch (const std::bad_alloc&) {
     delete p;
     return fail(DG_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -313,6 +336,13 @@ dg_status dg_plan_info_get(const dg_plan* p, dg_plan_info* info) {
   info->weight_bytes = !L.has_w ? 0u : (L.w8pack.empty() ? 4u : 1u);
   info->content_hash = L.hash;
   info->sweep_variant = L.variant;
+  info->batch_tiles = (uint32_t)p->btile_v.size() - 1;
+  return DG_OK;
+}
+
+dg_status dg_plan_batch_tiles(const dg_plan* p, uint32_t* btile_v) {
+  if (!p || !btile_v) return fail(DG_ERR_INVALID_ARGUMENT, "NULL argument");
+  std::copy(p->btile_v.begin(), p->btile_v.end(), btile_v);
   return DG_OK;
 }
 

@@ -42,7 +42,7 @@ EXPORTS = ("dg_set_allocator", "dg_graph_create", "dg_graph_destroy", "dg_graph_
            "dg_set_repartition", "dg_set_tune", "dg_predict_mode",
            "dg_tune_cache_clear", "dg_tune_cache_save", "dg_tune_cache_load", "dg_server_create",
            "dg_server_destroy", "dg_server_submit", "dg_server_step", "dg_server_fetch", "dg_server_status_get",
-           "dg_plan_create", "dg_plan_info_get", "dg_plan_arrays", "dg_plan_destroy", "dg_probe_gather", "dg_sssp_noalloc",
+           "dg_plan_create", "dg_plan_info_get", "dg_plan_arrays", "dg_plan_batch_tiles", "dg_plan_destroy", "dg_probe_gather", "dg_sssp_noalloc",
            "dg_status_str", "dg_last_error", "dg_version")
 DG_NOALLOC_SCRATCH_BYTES = 100663296
 DG_QUERY_SSSP, DG_QUERY_PPR = 0, 1
@@ -67,14 +67,15 @@ class dg_graph_info(C.Structure):
                 ("max_in_degree", C.c_uint32), ("dangling", C.c_uint32), ("has_weights", C.c_uint32),
                 ("compute_units", C.c_uint32), ("hot_vertices", C.c_uint32), ("hot_edges", C.c_uint64),
                 ("resident_vertices", C.c_uint32), ("resident_edges", C.c_uint64), ("weight_bytes", C.c_uint32),
-                ("device_bytes", C.c_uint64), ("sweep_variant", C.c_uint32)]
+                ("device_bytes", C.c_uint64), ("sweep_variant", C.c_uint32), ("batch_tiles", C.c_uint32)]
 
 
 class dg_plan_info(C.Structure):
     _fields_ = [("n", C.c_uint32), ("m", C.c_uint64), ("workers", C.c_uint32), ("tiles", C.c_uint32),
                 ("max_in_degree", C.c_uint32), ("dangling", C.c_uint32), ("hot_vertices", C.c_uint32),
                 ("hot_edges", C.c_uint64), ("resident_vertices", C.c_uint32), ("resident_edges", C.c_uint64),
-                ("weight_bytes", C.c_uint32), ("content_hash", C.c_uint64), ("sweep_variant", C.c_uint32)]
+                ("weight_bytes", C.c_uint32), ("content_hash", C.c_uint64), ("sweep_variant", C.c_uint32),
+                ("batch_tiles", C.c_uint32)]
 
 
 class dg_graph_opts(C.Structure):
@@ -171,6 +172,7 @@ def _load():
                                      C.POINTER(C.c_void_p)]),
         "dg_plan_info_get": (C.c_int, [P, C.POINTER(dg_plan_info)]),
         "dg_plan_arrays": (C.c_int, [P, P, P, P, P, P, P]),
+        "dg_plan_batch_tiles": (C.c_int, [P, P]),
         "dg_plan_destroy": (C.c_int, [P]),
         "dg_graph_info_get": (C.c_int, [P, C.POINTER(dg_graph_info)]),
         "dg_pagerank": (C.c_int, [P, C.c_double, C.c_double, C.c_int, C.c_uint32, C.c_int, C.c_uint32, P, C.c_int,
@@ -264,6 +266,10 @@ def dg_plan_info_get(p, info):
 
 def dg_plan_arrays(p, in_ptr, in_src, in_w, cpos, tile_v, work_t):
     return lib.dg_plan_arrays(p, in_ptr, in_src, in_w, cpos, tile_v, work_t)
+
+
+def dg_plan_batch_tiles(p, btile_v):
+    return lib.dg_plan_batch_tiles(p, btile_v)
 
 
 def dg_plan_destroy(p):
@@ -452,7 +458,8 @@ def plan(n, ptr, idx, w=None, layout="csr", compute_units=256, workers=0, hot_ve
          resident_vertices=DG_RESIDENT_AUTO, sweep_variant="auto"):
     """The layout dg_graph_create would upload, built on the host only
     (dg_plan_*): a dict of the plan's facts and its arrays as numpy arrays
-    (in_ptr, in_src, in_w or None, cpos, tile_v, work_t)."""
+    (in_ptr, in_src, in_w or None, cpos, tile_v, work_t, btile_v: the tiles
+    of the batched calls)."""
     ptr = np.ascontiguousarray(ptr, dtype=np.uint64)
     idx = np.ascontiguousarray(idx, dtype=np.uint32)
     wa = None if w is None else np.ascontiguousarray(w, dtype=np.uint32)
@@ -470,6 +477,8 @@ def plan(n, ptr, idx, w=None, layout="csr", compute_units=256, workers=0, hot_ve
                "cpos": np.empty(info.n, np.uint32), "tile_v": np.empty(info.tiles + 1, np.uint32),
                "work_t": np.empty(info.workers + 1, np.uint32)}
         _check(dg_plan_arrays(h, *[None if a is None else _np_ptr(a) for a in arr.values()]))
+        arr["btile_v"] = np.empty(info.batch_tiles + 1, np.uint32)
+        _check(dg_plan_batch_tiles(h, _np_ptr(arr["btile_v"])))
         out.update(arr)
         return out
     finally:

@@ -262,6 +262,8 @@ def test_batch_commit_counts(dg):
             assert st.commits == 0 and st.commit_interval == 0
         st = run("delayed", 1)
         assert st.commits == g.n and st.commit_interval == 1, (call, st.commits)
+        Tb = G.info().batch_tiles  # the batched calls' own tiles
+        assert st.tile_vertices == (g.n + Tb // 2) // Tb
         st = run("delayed", 64)
         waves = 4 * st.workers
         assert g.n / 16 <= st.commits <= g.n / 16 + waves, (call, st.commits)

@@ -304,13 +304,13 @@ def test_server_validation(dg, graphs):
 def test_server_after_batched_retune(dg):
     """A live server keeps serving correct results after its graph gets
     another batched partition (dg_graph_repartition_batch, dg_tune_batch):
-    PPR pools resize their per-worker partials at their next sweep.  The graph has enough tiles (about 2900)
-    that 3, 5 and 8 workgroups per CU are three different partitions; PPR
+    PPR pools resize their per-worker partials at their next sweep.  The graph has enough batched tiles (about
+    2900) that 3, 5 and 8 workgroups per CU are three different partitions; PPR
     rows are checked by the oracle's certificate, which bounds their L1
     error, SSSP rows bit-exact."""
     g = gg.erdos_renyi(3_000_000, 2.0, seed=31)
     G = dg.Graph.from_csr(g)
-    assert G.info().tiles > 2048
+    assert G.info().batch_tiles > 2048
     srv = dg.Server([G], mode="async", dtype="f64", tol=1e-10)
     rng = np.random.default_rng(7)
     srcs = [int(s) for s in rng.integers(0, g.n, size=5)]

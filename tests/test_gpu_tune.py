@@ -121,6 +121,9 @@ def test_set_mapping_keeps_results(dg, variant, res):
     info = G.info()
     if variant != "auto":
         assert dg.VARIANT_NAMES[info.sweep_variant] == variant
+    # the re-tiled graph's tiles and batched tiles are the host plan's
+    p = dg.plan(g.n, g.ptr, g.idx, g.w, compute_units=_cus(), sweep_variant=dg.VARIANT_NAMES[info.sweep_variant])
+    assert (info.tiles, info.batch_tiles) == (p["tiles"], p["batch_tiles"]), variant
     for mode in MODES:
         x, _ = G.pagerank(tol=1e-7, mode=mode, d=64, dtype="f32")
         assert float(np.abs(x.cpu().numpy() - xs).sum()) <= 1e-6, (variant, res, mode)
@@ -144,8 +147,9 @@ def test_tune_batch(dg, algo):
     G = dg.Graph.from_csr(g)
     srcs = gg.pick_sources(g, 20, seed=4)
     # one batched partition per algorithm: 8 workgroups per CU for SSSP, 5 for
-    # PPR (rounded down to a multiple of 8, at most one per tile)
-    T = G.info().tiles
+    # PPR (rounded down to a multiple of 8, at most one per batched tile)
+    T = G.info().batch_tiles
+    assert T > G.info().tiles  # RMAT-13's tiles are split for the batched calls
     want = {a: max(1, min(_cus() * per, T)) for a, per in (("sssp", 8), ("ppr", 5))}
     want = {a: (p & ~7 if p > 8 else p) for a, p in want.items()}
     w_sssp = G.sssp_batch(srcs[:1], mode="async")[1].workers
@@ -239,12 +243,13 @@ def test_set_tune(dg, algo):
 
 def test_repartition_batch(dg):
     """dg_graph_repartition_batch: sets one algorithm's batched partition
-    (clamped to one worker per tile), leaves the other's alone, 0 restores the
-    default, an unknown algorithm is refused; results stay exact."""
+    (clamped to one worker per batched tile), leaves the other's alone, 0
+    restores the default, an unknown algorithm is refused; results stay
+    exact."""
     g = gg.rmat(14, seed=12)
     G = dg.Graph.from_csr(g)
     srcs = gg.pick_sources(g, 3, seed=5)
-    T = G.info().tiles
+    T = G.info().batch_tiles
     def workers(algo):
         if algo == "sssp":
             return G.sssp_batch(srcs, mode="async")[1].workers

@@ -14,6 +14,8 @@ with numpy:
   worker (narrow < 2 <= wide with all gathers in flight <= 8 < wide);
 * the blocked partition (section III-A: contiguous blocks balanced by
   in-edges): P contiguous tile ranges split at the cost quantiles;
+* the tiles of the batched calls: each tile cut greedily into runs of at
+  most 4096 in-edges, a larger vertex alone, never across a tile;
 * byte weights exactly when every weight fits a byte;
 * CSC input gives the same plan as the equivalent CSR input;
 * argument validation.
@@ -158,6 +160,44 @@ def test_tiles_and_partition(dg, graph):
         cum = np.concatenate([[0.0], np.cumsum(cost)])
         per = cum[work[1:]] - cum[work[:-1]]
         assert per.max() <= cum[-1] / P + cost.max() + 1e-6
+
+
+BATCH_TILE_E = 4096
+
+
+def test_batch_tiles(dg, graph):
+    """The batched tiles refine the tiles: every tile boundary is one of
+    theirs, each run holds at most 4096 in-edges unless it is one vertex,
+    and the cut is greedy (a run ends only where its next vertex would take
+    it past 4096 in-edges, or at a tile's end)."""
+    g = graph
+    for variant in ("wide", "narrow"):
+        p = dg.plan(g.n, g.ptr, g.idx, g.w, sweep_variant=variant)
+        tv = p["tile_v"].astype(np.int64)
+        bt = p["btile_v"].astype(np.int64)
+        assert p["batch_tiles"] == bt.size - 1 >= p["tiles"]
+        assert bt[0] == 0 and bt[-1] == g.n and (np.diff(bt) >= 1).all()
+        assert np.isin(tv, bt).all()
+        deg = np.diff(p["in_ptr"].astype(np.int64))
+        e = np.concatenate([[0], np.cumsum(deg)])
+        ne, nv = np.diff(e[bt]), np.diff(bt)
+        assert ((ne <= BATCH_TILE_E) | (nv == 1)).all()
+        tile_ends = set(tv.tolist())
+        for t in range(bt.size - 2):
+            end = int(bt[t + 1])
+            if end in tile_ends:
+                continue
+            # an inner cut: the next vertex would not have fitted
+            assert ne[t] + deg[end] > BATCH_TILE_E, (variant, t)
+    # a hub with more in-edges than a run stays a run of its own
+    g = tg.in_star(20_000)
+    p = dg.plan(g.n, g.ptr, g.idx, g.w)
+    hub = int(np.argmax(np.diff(p["in_ptr"].astype(np.int64))))
+    t = int(np.searchsorted(p["btile_v"], hub, side="right")) - 1
+    assert p["btile_v"][t] == hub and p["btile_v"][t + 1] == hub + 1
+    # no edges: the tiles themselves
+    p = dg.plan(3000, np.zeros(3001, np.uint64), np.zeros(0, np.uint32))
+    np.testing.assert_array_equal(p["btile_v"], [0, 1024, 2048, 3000])
 
 
 @pytest.mark.parametrize("hot,res", [(0, AUTO), (50, AUTO), (1000, 100), (AUTO, 0), (AUTO, 1), (AUTO, 2049),
