@@ -159,11 +159,13 @@ dg_status dg_set_allocator(dg_alloc_fn alloc, dg_free_fn free_fn, void* ctx);
  *   workers       persistent workgroups that own the contiguous vertex blocks
  *                 of the single-query sweeps; 0 = automatic (one 1024-thread
  *                 workgroup per compute unit, at most one per tile).  The
- *                 batched calls use partitions of their own, one per
- *                 algorithm: 256-thread workgroups, eight per compute unit
- *                 for SSSP (dg_sssp_batch, the server's SSSP pools) and
- *                 five for personalised PageRank (dg_ppr_batch, its PPR
- *                 pools).
+ *                 batched calls use tiles and partitions of their own: the
+ *                 tiles cut into runs of at most 4096 in-edges
+ *                 (dg_graph_info.batch_tiles), split per algorithm over
+ *                 256-thread workgroups, eight per compute unit for SSSP
+ *                 (dg_sssp_batch, the server's SSSP pools) and five for
+ *                 personalised PageRank (dg_ppr_batch, its PPR pools), at
+ *                 most one per run.
  *   hot_vertices  at most this many sources with the largest out-degree (and
  *                 above-average out-degree) get their published value stored
  *                 in a compact region after the n regular slots, so gathers
@@ -448,7 +450,8 @@ dg_status dg_graph_repartition(dg_graph* g, uint32_t workers, void* hip_stream);
  *   sweep_variant      DG_SWEEP_WIDE, _WIDE_INFLIGHT or _NARROW, or
  *                      DG_SWEEP_AUTO for the variant chosen at creation; a
  *                      switch to or from DG_SWEEP_NARROW rebuilds the tiles
- *                      (its tile cap differs) and both partitions over them
+ *                      (its tile cap differs), the batched calls' runs cut
+ *                      from them, and every partition over either
  *   resident_vertices  at most this many resident-table entries are read
  *                      from LDS (<= dg_graph_info.resident_vertices; 0 = no
  *                      table; DG_RESIDENT_AUTO = all of them)
@@ -557,9 +560,10 @@ dg_status dg_tune_batch(dg_graph* g, dg_algo algo, dg_dtype dtype, double tol, c
  * dg_sssp_batch and the server's SSSP pools; DG_ALGO_PAGERANK: dg_ppr_batch
  * and its PPR pools) over `workers` 256-thread workgroups per batch (0 = the
  * default: 8 per compute unit for SSSP, 5 for PageRank, rounded down to a
- * multiple of 8), at most one per tile, as dg_tune_batch leaves it after
- * tuning.  A live server's PPR pools resize their per-worker partials at
- * their next sweep.  Must not overlap a sweep call on the same graph. */
+ * multiple of 8), at most one per batched tile (dg_graph_info.batch_tiles),
+ * as dg_tune_batch leaves it after tuning.  A live server's PPR pools resize
+ * their per-worker partials at their next sweep.  Must not overlap a sweep
+ * call on the same graph. */
 dg_status dg_graph_repartition_batch(dg_graph* g, dg_algo algo, uint32_t workers, void* hip_stream);
 
 /* The in-process cache of tuning results: cleared, written to and merged
