@@ -43,6 +43,25 @@ def in_star(n):
     return gg.from_edges(n, leaves, np.zeros(n - 1, dtype=np.int64), weight_seed=2, name=f"instar{n}")
 
 
+def hubs_at_run_limit(seed, n=40_000, m=160_000):
+    """Random edges plus hubs around the batched calls' run limit of 4096
+    in-edges: vertex 1000 has exactly 4096 in-edges, 1001 has 4097, 1002 one,
+    1003 6000 and 25000 4096 (each from distinct sources).  The cut of the
+    batched tiles then makes 1000, 1001, 1002 and 1003 single-vertex runs,
+    1002 a low-degree one stranded between two hubs."""
+    rng = np.random.default_rng(seed)
+    hubs = {1000: 4096, 1001: 4097, 1002: 1, 1003: 6000, 25000: 4096}
+    dst = rng.integers(0, n, size=m)
+    dst = dst[~np.isin(dst, list(hubs))]
+    src = rng.integers(0, n, size=dst.size)
+    srcs, dsts = [src], [dst]
+    for h, deg in hubs.items():
+        srcs.append(rng.choice(n, size=deg, replace=False))
+        dsts.append(np.full(deg, h))
+    return gg.from_edges(n, np.concatenate(srcs), np.concatenate(dsts), weight_seed=seed, dedup=True,
+                         name=f"runlimit{n}")
+
+
 def out_star(n):
     """Hub 0 points to leaves 1..n-1; every leaf is dangling."""
     leaves = np.arange(1, n)

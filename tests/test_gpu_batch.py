@@ -38,18 +38,22 @@ def dg():
     return _dg
 
 
-@pytest.mark.parametrize("name", ["rmat13", "instar", "banded"])
+@pytest.mark.parametrize("name", ["rmat13", "instar", "banded", "runlimit"])
 def test_sssp_batch_all_modes(dg, name):
     if name == "rmat13":
         g = gg.rmat(13, seed=13)
     elif name == "instar":
         g = tg.in_star(20_000)  # one hub beyond a tile (16380 in-edges): the wavefront split
+    elif name == "runlimit":
+        g = tg.hubs_at_run_limit(5)  # single-vertex batched runs at and above 4096 in-edges
     else:
         g = gg.banded(20_000, 16, 512, 0.01, seed=4)
     k = 70  # two batches, the second ragged
     rng = np.random.default_rng(1)
     sources = rng.integers(0, g.n, size=k).astype(np.uint32)
     sources[5] = sources[6]  # a duplicate query
+    if name == "runlimit":
+        sources[:5] = [1000, 1001, 1002, 1003, 25000]
     refs = {int(s): osp.bellman_ford_sync(g, int(s))[0] for s in set(sources.tolist())}
     G = dg.Graph.from_csr(g)
     # d <= 64 stages in registers (16 rows per wavefront, a commit every
@@ -69,12 +73,14 @@ def test_sssp_batch_all_modes(dg, name):
 
 
 @pytest.mark.parametrize("dtype,tol", [("f64", 1e-9), ("f32", 5e-7)])
-@pytest.mark.parametrize("name", ["rmat12", "dangling", "instar"])
+@pytest.mark.parametrize("name", ["rmat12", "dangling", "instar", "runlimit"])
 def test_ppr_batch_all_modes(dg, name, dtype, tol):
     if name == "rmat12":
         g = gg.rmat(12, seed=12)
     elif name == "dangling":
         g = tg.dangling_heavy(3000, 5)
+    elif name == "runlimit":
+        g = tg.hubs_at_run_limit(5)
     else:
         g = tg.in_star(20_000)
     k = 67
@@ -82,6 +88,8 @@ def test_ppr_batch_all_modes(dg, name, dtype, tol):
     sources = rng.integers(0, g.n, size=k).astype(np.uint32)
     deg = np.diff(g.ptr.astype(np.int64))
     sources[0] = int(np.flatnonzero(deg == 0)[0])  # a dangling restart vertex
+    if name == "runlimit":
+        sources[1:6] = [1000, 1001, 1002, 1003, 25000]
     refs = {int(s): opr.ppr_fixed_point(g, int(s)) for s in set(sources.tolist())}
     G = dg.Graph.from_csr(g)
     for mode, d in MODES:

@@ -102,6 +102,7 @@ GRAPHS = {
     "instar": lambda: tg.in_star(20_000),
     "dangling": lambda: tg.dangling_heavy(3000, 23),
     "multi": lambda: tg.random_graph(3001, 20_000, 7, dedup=False),
+    "runlimit": lambda: tg.hubs_at_run_limit(5),
 }
 
 
@@ -195,6 +196,15 @@ def test_batch_tiles(dg, graph):
     hub = int(np.argmax(np.diff(p["in_ptr"].astype(np.int64))))
     t = int(np.searchsorted(p["btile_v"], hub, side="right")) - 1
     assert p["btile_v"][t] == hub and p["btile_v"][t + 1] == hub + 1
+    # in-degrees at the limit: 4096 fits a run, 4097 and 6000 are runs of
+    # their own, and the one-edge vertex between them is left alone
+    g = tg.hubs_at_run_limit(5)
+    p = dg.plan(g.n, g.ptr, g.idx, g.w)
+    deg = np.diff(p["in_ptr"].astype(np.int64))
+    assert [int(deg[v]) for v in (1000, 1001, 1002, 1003, 25000)] == [4096, 4097, 1, 6000, 4096]
+    bt = p["btile_v"].tolist()
+    for v in (1000, 1001, 1002, 1003):
+        assert v in bt and v + 1 in bt, v
     # no edges: the tiles themselves
     p = dg.plan(3000, np.zeros(3001, np.uint64), np.zeros(0, np.uint32))
     np.testing.assert_array_equal(p["btile_v"], [0, 1024, 2048, 3000])
