@@ -12,7 +12,8 @@
 * Edge cases: synchronous batches stopped after k sweeps return the k-th
   Jacobi iterate; 1025 queries (17 launches, a one-lane tail); a batch of
   one query against the single-query entry points; one-vertex, self-loop
-  and edgeless graphs.
+  and edgeless graphs; hubs at the batched tiles' limit of 4096 in-edges
+  (single-vertex runs, one of them a one-edge vertex between two hubs).
 """
 import ctypes as C
 
