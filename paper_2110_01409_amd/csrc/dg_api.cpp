@@ -1578,6 +1578,8 @@ dg_status dg_graph_repartition(dg_graph* g, uint32_t workers, void* hip_stream) 
     DG_HIP(hipMemcpyAsync(wgd, wgraph.data(), (size_t)P * 4, hipMemcpyHostToDevice, s));
   }
   DG_HIP(hipStreamSynchronize(s));
+  g->graph_bytes += 4 * ((uint64_t)work_t.size() + wseg.size() + wgraph.size());
+  g->graph_bytes -= 4 * ((uint64_t)g->work_t_h.size() + (g->G ? g->wseg_h.size() + g->wgraph_h.size() : 0u));
   dev_free(g, g->work_t);
   g->work_t = wt;
   g->work_t_h = work_t;
@@ -1653,6 +1655,9 @@ dg_status dg_graph_set_mapping(dg_graph* g, uint32_t sweep_variant, uint32_t res
     for (BatchPart& b : nb)
       DG_HIP(hipMemcpyAsync(b.work_t, b.work_t_h.data(), b.work_t_h.size() * 4, hipMemcpyHostToDevice, s));
     DG_HIP(hipStreamSynchronize(s));
+    g->graph_bytes += 4 * ((uint64_t)tv.size() + btv.size() + nb[0].work_t_h.size() + nb[1].work_t_h.size());
+    g->graph_bytes -= 4 * ((uint64_t)g->tile_v_h.size() + g->btile_v_h.size() + g->bp[0].work_t_h.size() +
+                           g->bp[1].work_t_h.size());
     dev_free(g, g->tile_v);
     g->tile_v = tvd;
     dev_free(g, g->btile_v);
@@ -1923,6 +1928,8 @@ dg_status set_batch_workers(dg_graph* g, int which, uint32_t Pb, hipStream_t s) 
   if (!nb.work_t) return fail(DG_ERR_OUT_OF_MEMORY, "batched partition allocation failed");
   DG_HIP(hipMemcpyAsync(nb.work_t, nb.work_t_h.data(), nb.work_t_h.size() * 4, hipMemcpyHostToDevice, s));
   DG_HIP(hipStreamSynchronize(s));
+  g->graph_bytes += 4 * (uint64_t)nb.work_t_h.size();
+  g->graph_bytes -= 4 * (uint64_t)g->bp[which].work_t_h.size();
   dev_free(g, g->bp[which].work_t);
   g->bp[which] = std::move(nb);
   return DG_OK;

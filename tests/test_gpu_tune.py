@@ -33,11 +33,13 @@ def test_repartition_keeps_results(dg):
     ref, _, _ = osp.bellman_ford_sync(g, 7)
     G = dg.Graph.from_csr(g)
     T = G.info().tiles
+    base = G.info().device_bytes - 4 * (G.info().workers + 1)  # all but the worker array
     for workers in (8, 40, 333, T, 0):
         G.repartition(workers)
         info = G.info()
         if workers:
             assert info.workers == min(workers, T)
+        assert info.device_bytes == base + 4 * (info.workers + 1)
         first = G.partition()
         assert first[0] == 0 and first[-1] == g.n and first.shape[0] == info.workers + 1
         for mode in MODES:
@@ -117,8 +119,17 @@ def test_set_mapping_keeps_results(dg, variant, res):
     src = int(gg.pick_sources(g, 1, seed=3)[0])
     ref, _, _ = osp.bellman_ford_sync(g, src)
     G = dg.Graph.from_csr(g)
+    one = np.array([src], np.uint32)
+
+    def arrays():  # entries of the tile, run and worker arrays (single-query and both batched partitions)
+        i = G.info()
+        wb = G.sssp_batch(one, mode="async")[1].workers + G.ppr_batch(one, tol=1e-9, mode="async", dtype="f64")[1].workers
+        return i.tiles + i.batch_tiles + i.workers + wb
+    b0, a0 = G.info().device_bytes, arrays()
     G.set_mapping(variant, dg.DG_RESIDENT_AUTO if res is None else res)
     info = G.info()
+    # re-tiling replaces those arrays, and device_bytes follows them
+    assert info.device_bytes - b0 == 4 * (arrays() - a0), variant
     if variant != "auto":
         assert dg.VARIANT_NAMES[info.sweep_variant] == variant
     # the re-tiled graph's tiles and batched tiles are the host plan's
@@ -255,8 +266,10 @@ def test_repartition_batch(dg):
             return G.sssp_batch(srcs, mode="async")[1].workers
         return G.ppr_batch(srcs, tol=1e-9, mode="async", dtype="f64")[1].workers
     d_sssp, d_ppr = workers("sssp"), workers("ppr")
+    b0 = G.info().device_bytes
     G.repartition_batch("sssp", 3)
     assert workers("sssp") == 3 and workers("ppr") == d_ppr
+    assert G.info().device_bytes == b0 + 4 * (3 - d_sssp)  # the worker array is all that changed
     G.repartition_batch("ppr", 10 ** 6)
     assert workers("ppr") == T and workers("sssp") == 3
     rows, _ = G.sssp_batch(srcs, mode="delayed", d=64)
