@@ -283,7 +283,8 @@ def batched_rmat20(dg, gg, queries=256):
         torch.cuda.synchronize()
         return out, time.perf_counter() - t
 
-    res = {"graph": f"rmat20 (n={g.n}, m={int(g.ptr[-1])})", "queries": queries}
+    res = {"graph": f"rmat20 (n={g.n}, m={int(g.ptr[-1])})", "queries": queries,
+           "tiles": G.info().tiles, "batch_tiles": G.info().batch_tiles}
     # one at a time
     def sssp_one():
         return [G.sssp(int(s), mode="delayed", d=64)[0] for s in src.tolist()]
@@ -771,11 +772,12 @@ def main():
             ppr_rows[mode] = (xb[:4].clone(), singles)
             batched[mode] = {
                 "sssp": {"queries": len(bsrc), "batched_ms": round(tb * 1e3, 2), "batched_sweeps": sb.sweeps,
+                         "batched_workers": sb.workers, "batch_tiles": G.info().batch_tiles,
                          "batched_gteps": round(sb.edges_traversed / tb / 1e9, 1),
                          "one_at_a_time_ms": round(t1 * 1e3, 2), "one_at_a_time_gteps": round(e1 / t1 / 1e9, 1),
                          "speedup": round(t1 / tb, 2), "rows_equal_to_one_at_a_time": f"{rows_equal}/{len(bsrc)}"},
                 "ppr_f32_tol1e-6": {"queries": len(bsrc), "batched_ms": round(tp * 1e3, 2),
-                                    "batched_sweeps": sp.sweeps,
+                                    "batched_sweeps": sp.sweeps, "batched_workers": sp.workers,
                                     "batched_gteps": round(sp.edges_traversed / tp / 1e9, 1),
                                     "one_at_a_time_ms": round(tp1 * 1e3, 2),
                                     "one_at_a_time_gteps": round(e1p / tp1 / 1e9, 1),
