@@ -8,11 +8,13 @@
 // batch instead of once per query.  Batches are the y dimension of the
 // launch; a batch whose queries have all met the stopping rule exits at once.
 //
-// Work mapping: the tiles of the single-query sweeps, in contiguous blocks of
-// a partition of their own (five 256-thread workgroups per compute unit),
-// each walked in ascending order.  Within a tile the four
-// wavefronts of the workgroup take vertices round-robin; a single-vertex tile
-// (a hub) is split over the four wavefronts and combined in LDS.  For each
+// Work mapping: tiles of their own (the single-query tiles cut into runs of
+// at most 4096 in-edges, a vertex with more being a run of its own), in
+// contiguous blocks of a partition per algorithm (by default eight 256-thread
+// workgroups per compute unit for SSSP, five for PPR), each walked in
+// ascending order.  Within a tile the four wavefronts of the workgroup take
+// vertices round-robin; a single-vertex tile (a hub) is split over the four
+// wavefronts and combined in LDS.  For each
 // vertex a wavefront reads 64 in-edges with one coalesced load, broadcasts
 // each edge's source slot and weight with readlane, and keeps eight row
 // gathers in flight.
