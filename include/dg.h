@@ -281,6 +281,8 @@ typedef struct {
   uint64_t content_hash;      /* hash of the in-edge form (the tuning cache key) */
   uint32_t sweep_variant;     /* DG_SWEEP_WIDE, _WIDE_INFLIGHT or _NARROW        */
   uint32_t batch_tiles;       /* tiles of the batched calls (as dg_graph_info)  */
+  uint32_t batch_workers_sssp; /* default batched partitions on compute_units:  */
+  uint32_t batch_workers_ppr;  /* SSSP and personalised PageRank workers        */
 } dg_plan_info;
 dg_status dg_plan_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_t* ptr, const uint32_t* idx,
                          const uint32_t* w, const dg_graph_opts* opts, uint32_t compute_units, dg_plan** out);
@@ -297,10 +299,12 @@ dg_status dg_plan_info_get(const dg_plan* p, dg_plan_info* info);
  *   work_t [workers+1] first tile of each worker */
 dg_status dg_plan_arrays(const dg_plan* p, uint32_t* in_ptr, uint32_t* in_src, uint32_t* in_w, uint32_t* cpos,
                          uint32_t* tile_v, uint32_t* work_t);
-/* Copies the first vertex of each tile of the batched calls into the caller's
- * btile_v [batch_tiles+1] (host memory).  INVALID_ARGUMENT if either pointer
- * is NULL. */
-dg_status dg_plan_batch_tiles(const dg_plan* p, uint32_t* btile_v);
+/* Copies the batched calls' layout into caller arrays (host memory); any
+ * array pointer may be NULL to skip it.
+ *   btile_v   [batch_tiles+1]        first vertex of each tile of the batched calls
+ *   work_sssp [batch_workers_sssp+1] first batched tile of each worker of the
+ *   work_ppr  [batch_workers_ppr+1]  default SSSP and PPR partitions */
+dg_status dg_plan_batch_tiles(const dg_plan* p, uint32_t* btile_v, uint32_t* work_sssp, uint32_t* work_ppr);
 dg_status dg_plan_destroy(dg_plan* p);
 
 /* PageRank by repeated pull sweeps (sections III and IV-A).

@@ -208,9 +208,7 @@ void plan_batch_part(const std::vector<uint32_t>& tv, const std::vector<uint32_t
 // Default batched workers: per_cu 256-thread workgroups per compute unit,
 // rounded down to a multiple of 8, at most one per batched tile.
 uint32_t batch_workers(const dg_graph* g, uint32_t per_cu) {
-  uint32_t P = std::max(1u, std::min(g->cus * per_cu, (uint32_t)g->btile_v_h.size() - 1));
-  if (P > 8) P &= ~7u;
-  return P;
+  return batch_workers_for(g->cus, per_cu, (uint32_t)g->btile_v_h.size() - 1);
 }
 
 // Mean vertices per batched tile, rounded.
@@ -1636,8 +1634,8 @@ dg_status dg_graph_set_mapping(dg_graph* g, uint32_t sweep_variant, uint32_t res
     }
     const uint32_t T = (uint32_t)tv.size() - 1, Tb = (uint32_t)btv.size() - 1;
     for (int b : {kBatchSssp, kBatchPpr}) {
-      uint32_t Pb = std::max(1u, std::min(g->cus * (b == kBatchSssp ? kBatchSsspWorkersPerCU : kBatchPprWorkersPerCU), Tb));
-      if (Pb > 8) Pb &= ~7u;
+      const uint32_t Pb =
+          dg::host::batch_workers_for(g->cus, b == kBatchSssp ? kBatchSsspWorkersPerCU : kBatchPprWorkersPerCU, Tb);
       dg::host::plan_batch_part(btv, bte0, Pb, nb[b]);
     }
     DG_HIP(hipStreamSynchronize(s));

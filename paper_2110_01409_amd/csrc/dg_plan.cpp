@@ -270,6 +270,12 @@ dg_status build_layout(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
   return DG_OK;
 }
 
+uint32_t batch_workers_for(uint32_t cus, uint32_t per_cu, uint32_t batch_tiles) {
+  uint32_t P = std::max(1u, std::min(cus * per_cu, batch_tiles));
+  if (P > 8) P &= ~7u;
+  return P;
+}
+
 uint32_t plan_workers(const Layout& L, uint32_t want_workers, uint32_t cus, uint32_t per_cu) {
   uint32_t P = want_workers ? want_workers : cus * per_cu;
   P = std::max(1u, std::min(P, L.T()));
@@ -288,6 +294,7 @@ struct dg_plan {
   uint32_t P = 0;
   std::vector<uint32_t> work_t;
   std::vector<uint32_t> btile_v, btile_e0;  // tiles of the batched kernels
+  std::vector<uint32_t> bwork[2];           // their default partitions: SSSP, PPR (first batched tile of each worker)
 };
 
 extern "C" {
@@ -312,6 +319,11 @@ dg_status dg_plan_create(uint32_t n, uint64_t m, dg_layout layout, const uint64_
   try {
     dg::host::build_workers(p->L.tile_v, p->L.tile_e0, p->P, p->work_t);
     dg::host::build_batch_tiles(p->L.tile_v, p->L.in_ptr, dg::host::kBatchTileE, p->btile_v, p->btile_e0);
+    const uint32_t Tb = (uint32_t)p->btile_v.size() - 1;
+    const uint32_t per[2] = {dg::host::kBatchSsspWorkersPerCU, dg::host::kBatchPprWorkersPerCU};
+    for (int a = 0; a < 2; ++a)
+      dg::host::build_workers(p->btile_v, p->btile_e0, dg::host::batch_workers_for(compute_units, per[a], Tb),
+                              p->bwork[a]);
   } catch (const std::bad_alloc&) {
     delete p;
     return fail(DG_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -337,12 +349,16 @@ dg_status dg_plan_info_get(const dg_plan* p, dg_plan_info* info) {
   info->content_hash = L.hash;
   info->sweep_variant = L.variant;
   info->batch_tiles = (uint32_t)p->btile_v.size() - 1;
+  info->batch_workers_sssp = (uint32_t)p->bwork[0].size() - 1;
+  info->batch_workers_ppr = (uint32_t)p->bwork[1].size() - 1;
   return DG_OK;
 }
 
-dg_status dg_plan_batch_tiles(const dg_plan* p, uint32_t* btile_v) {
-  if (!p || !btile_v) return fail(DG_ERR_INVALID_ARGUMENT, "NULL argument");
-  std::copy(p->btile_v.begin(), p->btile_v.end(), btile_v);
+dg_status dg_plan_batch_tiles(const dg_plan* p, uint32_t* btile_v, uint32_t* work_sssp, uint32_t* work_ppr) {
+  if (!p) return fail(DG_ERR_INVALID_ARGUMENT, "plan is NULL");
+  if (btile_v) std::copy(p->btile_v.begin(), p->btile_v.end(), btile_v);
+  if (work_sssp) std::copy(p->bwork[0].begin(), p->bwork[0].end(), work_sssp);
+  if (work_ppr) std::copy(p->bwork[1].begin(), p->bwork[1].end(), work_ppr);
   return DG_OK;
 }
 

@@ -55,6 +55,10 @@ dg_status build_layout(uint32_t n, uint64_t m, dg_layout layout, const uint64_t*
 // than the tiles.
 uint32_t plan_workers(const Layout& L, uint32_t want_workers, uint32_t cus, uint32_t per_cu);
 
+// Default workers of a batched partition: per_cu per compute unit, rounded
+// down to a multiple of 8, at most one per batched tile, at least one.
+uint32_t batch_workers_for(uint32_t cus, uint32_t per_cu, uint32_t batch_tiles);
+
 // Contiguous tile ranges of P workers balanced by 256 + in-edges + 4 x
 // vertices per tile; work_t[P+1].
 void build_workers(const std::vector<uint32_t>& tile_v, const std::vector<uint32_t>& tile_e0, uint32_t P,

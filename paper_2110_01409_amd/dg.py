@@ -75,7 +75,7 @@ class dg_plan_info(C.Structure):
                 ("max_in_degree", C.c_uint32), ("dangling", C.c_uint32), ("hot_vertices", C.c_uint32),
                 ("hot_edges", C.c_uint64), ("resident_vertices", C.c_uint32), ("resident_edges", C.c_uint64),
                 ("weight_bytes", C.c_uint32), ("content_hash", C.c_uint64), ("sweep_variant", C.c_uint32),
-                ("batch_tiles", C.c_uint32)]
+                ("batch_tiles", C.c_uint32), ("batch_workers_sssp", C.c_uint32), ("batch_workers_ppr", C.c_uint32)]
 
 
 class dg_graph_opts(C.Structure):
@@ -172,7 +172,7 @@ def _load():
                                      C.POINTER(C.c_void_p)]),
         "dg_plan_info_get": (C.c_int, [P, C.POINTER(dg_plan_info)]),
         "dg_plan_arrays": (C.c_int, [P, P, P, P, P, P, P]),
-        "dg_plan_batch_tiles": (C.c_int, [P, P]),
+        "dg_plan_batch_tiles": (C.c_int, [P, P, P, P]),
         "dg_plan_destroy": (C.c_int, [P]),
         "dg_graph_info_get": (C.c_int, [P, C.POINTER(dg_graph_info)]),
         "dg_pagerank": (C.c_int, [P, C.c_double, C.c_double, C.c_int, C.c_uint32, C.c_int, C.c_uint32, P, C.c_int,
@@ -268,8 +268,8 @@ def dg_plan_arrays(p, in_ptr, in_src, in_w, cpos, tile_v, work_t):
     return lib.dg_plan_arrays(p, in_ptr, in_src, in_w, cpos, tile_v, work_t)
 
 
-def dg_plan_batch_tiles(p, btile_v):
-    return lib.dg_plan_batch_tiles(p, btile_v)
+def dg_plan_batch_tiles(p, btile_v, work_sssp, work_ppr):
+    return lib.dg_plan_batch_tiles(p, btile_v, work_sssp, work_ppr)
 
 
 def dg_plan_destroy(p):
@@ -458,8 +458,9 @@ def plan(n, ptr, idx, w=None, layout="csr", compute_units=256, workers=0, hot_ve
          resident_vertices=DG_RESIDENT_AUTO, sweep_variant="auto"):
     """The layout dg_graph_create would upload, built on the host only
     (dg_plan_*): a dict of the plan's facts and its arrays as numpy arrays
-    (in_ptr, in_src, in_w or None, cpos, tile_v, work_t, btile_v: the tiles
-    of the batched calls)."""
+    (in_ptr, in_src, in_w or None, cpos, tile_v, work_t; btile_v, the tiles
+    of the batched calls, and work_sssp / work_ppr, their default batched
+    partitions)."""
     ptr = np.ascontiguousarray(ptr, dtype=np.uint64)
     idx = np.ascontiguousarray(idx, dtype=np.uint32)
     wa = None if w is None else np.ascontiguousarray(w, dtype=np.uint32)
@@ -478,7 +479,9 @@ def plan(n, ptr, idx, w=None, layout="csr", compute_units=256, workers=0, hot_ve
                "work_t": np.empty(info.workers + 1, np.uint32)}
         _check(dg_plan_arrays(h, *[None if a is None else _np_ptr(a) for a in arr.values()]))
         arr["btile_v"] = np.empty(info.batch_tiles + 1, np.uint32)
-        _check(dg_plan_batch_tiles(h, _np_ptr(arr["btile_v"])))
+        arr["work_sssp"] = np.empty(info.batch_workers_sssp + 1, np.uint32)
+        arr["work_ppr"] = np.empty(info.batch_workers_ppr + 1, np.uint32)
+        _check(dg_plan_batch_tiles(h, _np_ptr(arr["btile_v"]), _np_ptr(arr["work_sssp"]), _np_ptr(arr["work_ppr"])))
         out.update(arr)
         return out
     finally:

@@ -15,7 +15,8 @@ with numpy:
 * the blocked partition (section III-A: contiguous blocks balanced by
   in-edges): P contiguous tile ranges split at the cost quantiles;
 * the tiles of the batched calls: each tile cut greedily into runs of at
-  most 4096 in-edges, a larger vertex alone, never across a tile;
+  most 4096 in-edges, a larger vertex alone, never across a tile; their
+  default partitions (8 and 5 workgroups per compute unit);
 * byte weights exactly when every weight fits a byte;
 * CSC input gives the same plan as the equivalent CSR input;
 * argument validation.
@@ -208,6 +209,28 @@ def test_batch_tiles(dg, graph):
     # no edges: the tiles themselves
     p = dg.plan(3000, np.zeros(3001, np.uint64), np.zeros(0, np.uint32))
     np.testing.assert_array_equal(p["btile_v"], [0, 1024, 2048, 3000])
+
+
+BATCH_PER_CU = {"sssp": 8, "ppr": 5}  # default batched workgroups per compute unit
+
+
+def test_batch_partitions(dg, graph):
+    """The default batched partitions: per algorithm, its workgroups per
+    compute unit rounded down to a multiple of 8, at most one per batched
+    tile, split over the batched tiles with the blocked partition's cost
+    quantiles."""
+    g = graph
+    for cus in (256, 4, 1):
+        p = dg.plan(g.n, g.ptr, g.idx, g.w, compute_units=cus)
+        bt = p["btile_v"].astype(np.int64)
+        Tb = bt.size - 1
+        for algo, per in BATCH_PER_CU.items():
+            P = max(1, min(cus * per, Tb))
+            if P > 8:
+                P &= ~7
+            assert p[f"batch_workers_{algo}"] == P, (algo, cus)
+            work, _ = _ref_workers(bt, p["in_ptr"], P)
+            np.testing.assert_array_equal(p[f"work_{algo}"], work, err_msg=f"{algo} cus={cus}")
 
 
 @pytest.mark.parametrize("hot,res", [(0, AUTO), (50, AUTO), (1000, 100), (AUTO, 0), (AUTO, 1), (AUTO, 2049),
