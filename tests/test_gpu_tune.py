@@ -166,6 +166,8 @@ def test_tune_batch(dg, algo):
     w_sssp = G.sssp_batch(srcs[:1], mode="async")[1].workers
     w_ppr = G.ppr_batch(srcs[:1], tol=1e-9, mode="async", dtype="f64")[1].workers
     assert (w_sssp, w_ppr) == (want["sssp"], want["ppr"])
+    p = dg.plan(g.n, g.ptr, g.idx, g.w, compute_units=_cus())  # the host plan agrees
+    assert (p["batch_tiles"], p["batch_workers_sssp"], p["batch_workers_ppr"]) == (T, w_sssp, w_ppr)
     t = G.tune_batch(algo, srcs, dtype="f64", tol=1e-9)
     print("tuned batch", algo, t, flush=True)
     assert t["mode"] in MODES and t["candidates"] == 18 and t["repeats"] == 3
